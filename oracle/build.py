@@ -1,0 +1,22 @@
+"""Builds the C oracle (test infrastructure) into oracle/liboracle.so."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRCS = [os.path.join(HERE, "oracle.c")]
+FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall", "-shared", "-fPIC"]
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB) and all(
+            os.path.getmtime(LIB) >= os.path.getmtime(s) for s in SRCS + [os.path.join(HERE, "oracle.h")]):
+        return LIB
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", *FLAGS, "-o", tmp, *SRCS, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())
