@@ -1,0 +1,184 @@
+#!/usr/bin/env python
+"""Benchmark of the MARS hot path on one MI355X.
+
+Workload: the guided path-tracing configuration -- 512 x 512 pixels, a seeded
+procedural scene of ~132k triangles (displaced 256 x 256 heightfield + 200
+boxes, GGX materials, 4 quad emitters), three techniques (BSDF, NEE, guided
+8 x 8 histogram per cell), max depth 10, octree cache (8 levels, split after
+32 visits, 72 MB budget).  One step = one MARS iteration: render at 1 sample
+per pixel (all depths, shadow rays, back-propagation, cell statistics) plus
+the update (image estimates, fixed-point factors, guided distribution,
+octree refinement).  The first warm-up steps are classic-RR iterations as in
+the paper's schedule; timed steps are MARS iterations.
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "guided_pt_512x512_heightfield132k_d10"
+BYTES_RAY_IO = 48.0      # ray 32 B in (origin, direction) + hit 16 B out
+BYTES_NODE = 64.0        # one BVH node (two child boxes + references)
+BYTES_TRI = 48.0         # one triangle record (v0, e1, e2)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_math.hpp", "mars_internal.h"):
+        with open(os.path.join(ROOT, "paper_2410_20429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(per_launch_rays):
+    """HBM bytes per launch of trace_closest from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "trace_closest_guided512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, n_pix=16384, seed=7):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    n_pix random pixels of the same 512 x 512 frame, one untimed classic
+    iteration, then timed MARS iterations (render + update)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    threads = orc.set_threads(0)
+    o = orc.Oracle(sc, mode=orc.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+    rng = np.random.default_rng(seed)
+    o.set_pixel_subset(rng.choice(sc["width"] * sc["height"], n_pix, replace=False))
+    p = orc.Oracle.params(iteration=0, spp=1)
+    o.render_iteration(p)
+    o.update(p)
+    t0 = time.perf_counter()
+    n_iter = 0
+    while True:
+        p = orc.Oracle.params(iteration=1 + n_iter, spp=1, alloc=orc.ALLOC_MARS)
+        o.render_iteration(p)
+        o.update(p)
+        n_iter += 1
+        if time.perf_counter() - t0 > 10.0 or n_iter >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n_pix * n_iter / dt / 1e6, "unit": "Mpaths/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_pix} random pixels of the 512x512 frame, {n_iter} MARS iterations "
+                      f"(render+update) after one classic iteration, {dt:.1f} s"}
+
+
+def cells_budget(mbytes=72.0):
+    # bytes per cell: factors 72, accumulators 192, visits/leaf data 12,
+    # directional pmf+cdf 512, training sums 512, octree node words 32
+    return int(mbytes * 1e6 / (72 + 192 + 12 + 512 + 512 + 32))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=-1,
+                    help="(profiling runs) total iterations to run, no extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
+                                   "--gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import scenegen
+    from paper_2410_20429_amd import api
+
+    sc = scenegen.make_heightfield_scene(seed=1)
+    ctx = api.Context(0)
+    s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+    n_classic = min(3, args.warmup)
+
+    def step(i):
+        alloc = api.ALLOC_CLASSIC if i < n_classic else api.ALLOC_MARS
+        p = api.iter_params(iteration=i, spp=1, alloc=alloc, stat_clamp=50.0)
+        st = s.render_iteration(p)
+        us = s.update(p)
+        return st, us
+
+    for i in range(args.warmup):
+        step(i)
+        print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rays = rays_closest = 0
+    for k in range(args.steps):
+        st, us = step(args.warmup + k)
+        rays += st.total_rays()
+        rays_closest += st.rays_camera + st.rays_ext
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    paths = args.steps * sc["width"] * sc["height"]
+    out = {
+        "metric": "Mpaths/s (efficiency 1/(relMSE*s) reported beside it)",
+        "value": paths / dt / 1e6,
+        "unit": "Mpaths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "width": sc["width"], "height": sc["height"],
+                   "triangles": int(sc["V"].shape[0]), "max_depth": 10, "spp_per_step": 1,
+                   "techniques": ["bsdf", "nee", "guided"], "max_cells": cells_budget()},
+        "mrays_per_s": rays / dt / 1e6,
+        "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+    }
+    if args.profile_steps < 0:
+        # algorithmic bytes of the dominant kernel from one instrumented iteration
+        ctx.trace_counting(True)
+        st, _ = step(args.warmup + args.steps)
+        tc = ctx.trace_counts()
+        ctx.trace_counting(False)
+        rays_i, nodes_i, tris_i = tc[0], tc[1], tc[2]
+        bytes_per_ray = BYTES_RAY_IO + (BYTES_NODE * nodes_i + BYTES_TRI * tris_i) / max(rays_i, 1)
+        ms_tc, n_tc = prof["trace_closest"]
+        avg_ms = ms_tc / max(n_tc, 1)
+        rays_per_launch = rays_closest / max(n_tc, 1)
+        achieved = bytes_per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = load_traffic(rays_per_launch)
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "trace_closest", "avg_launch_ms": avg_ms,
+                           "bytes_per_ray": bytes_per_ray,
+                           "nodes_per_ray": nodes_i / max(rays_i, 1),
+                           "tris_per_ray": tris_i / max(rays_i, 1)}
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/* mars.h -- C ABI of the MI355X implementation of MARS
+ * (Meyer, Rath, Yazici, Slusallek: "MARS: Multi-sample Allocation through
+ * Russian roulette and Splitting", SIGGRAPH Asia 2024).
+ *
+ * The iterative scheme the interface follows is the paper's (Sec. 4.1
+ * "Fixed-point iteration", Sec. 5.1): render an iteration with the current
+ * per-cell, per-technique sample counts, collect local and image estimates,
+ * update the counts by the fixed-point rule, repeat.
+ *
+ * Conventions
+ *  - Every function returns a mars_status; no exception crosses the ABI.
+ *    mars_last_error() gives a message for the last failing call on a context.
+ *  - Scene arrays are copied at upload; the caller may free them afterwards.
+ *  - Device memory comes from the allocator callbacks given at creation (the
+ *    Python binding passes PyTorch's caching allocator); NULL callbacks mean
+ *    hipMalloc/hipFree.  The library frees everything it allocated at
+ *    mars_scene_release / mars_destroy.
+ *  - Work is ordered on the HIP stream given at creation.  Functions that
+ *    fill host-side stats synchronise that stream before returning.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - Host pointers ("dst" with dst_is_device = 0) must hold the documented
+ *    number of elements; device pointers must be on the context's device.
+ */
+#ifndef MARS_H
+#define MARS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MARS_OK = 0,
+  MARS_E_ARG = -1,        /* invalid argument (null pointer, bad size, bad id) */
+  MARS_E_OOM = -2,        /* an allocation failed */
+  MARS_E_HIP = -3,        /* a HIP runtime call failed (no device, launch error) */
+  MARS_E_STATE = -4,      /* call not valid in the current state */
+  MARS_E_OVERFLOW = -5,   /* a single path tree exceeds the queue capacity */
+  MARS_E_NONFINITE = -6,  /* non-finite scene input */
+  MARS_E_IO = -7          /* checkpoint file error */
+} mars_status;
+
+/* rendering modes: the paper's two applications (Sec. 4: path guiding with
+ * BSDF/NEE/guided techniques; Sec. 5: bidirectional path tracing with
+ * BSDF/NEE/light-path-connection techniques) and plain BSDF+NEE tracing */
+enum { MARS_MODE_PT = 0, MARS_MODE_PT_GUIDED = 1, MARS_MODE_BDPT = 2 };
+/* how per-vertex counts are chosen: classic throughput RR (the baseline and
+ * warm-up of Sec. 4.1/5.2), the MARS fixed point (Sec. 3.1 "Optimization"),
+ * fixed counts (tests of unbiasedness, supplement A.1), or the learned cache */
+enum { MARS_ALLOC_CLASSIC = 0, MARS_ALLOC_MARS = 1, MARS_ALLOC_FIXED = 2, MARS_ALLOC_MLP = 3 };
+/* technique slots: 0 BSDF, 1 NEE, 2 guided (PT_GUIDED) or light path (BDPT) */
+enum { MARS_TECH_BSDF = 0, MARS_TECH_NEE = 1, MARS_TECH_THIRD = 2 };
+enum { MARS_IMAGE_MEAN = 0, MARS_IMAGE_IVW = 1, MARS_IMAGE_LAST = 2 };
+
+typedef struct mars_ctx mars_ctx;
+
+typedef void* (*mars_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*mars_free_fn)(void* ptr, void* stream, void* user);
+
+typedef struct {
+  int32_t device;          /* HIP device ordinal */
+  void* stream;            /* hipStream_t, NULL = default stream */
+  mars_alloc_fn alloc;     /* optional */
+  mars_free_fn free;       /* optional */
+  void* user;              /* passed to alloc/free */
+} mars_ctx_desc;
+
+typedef struct {
+  /* geometry, host pointers, copied at upload */
+  const float* V;           /* [n_tris][9]: v0, v1, v2 */
+  const uint32_t* tri_mat;  /* [n_tris] material index */
+  const float* mats;        /* [n_mats][8]: kind (0 Lambert, 1 GGX), albedo rgb, GGX alpha,
+                               emitted radiance rgb (one-sided, front = winding normal) */
+  const float* camera;      /* [10]: position, target, up, vertical fov (degrees) */
+  int32_t n_tris, n_mats, width, height;
+  /* algorithm configuration */
+  int32_t mode;             /* MARS_MODE_* */
+  int32_t max_depth;        /* maximum number of path segments D */
+  int32_t max_cells;        /* octree leaf budget (the paper caps the cache at 72 MB) */
+  int32_t max_tree_depth;   /* 8 */
+  int32_t split_visits;     /* a leaf splits after more than this many vertex visits (32) */
+  int32_t nee_enabled;      /* NEE technique available */
+  uint64_t seed;            /* Philox key */
+  int64_t queue_capacity;   /* entries per path-depth queue; 0 = automatic */
+  int32_t tile_roots;       /* camera samples per wavefront tile; 0 = automatic */
+  int32_t reserved;
+} mars_scene_desc;
+
+typedef struct {
+  int32_t iteration;        /* keys the random streams */
+  int32_t spp;              /* camera samples per pixel in this iteration */
+  int32_t alloc;            /* MARS_ALLOC_* */
+  int32_t budget_aware;     /* 1: budget-aware balance heuristic (Sec. 3 "Proxy model") */
+  int32_t rr_start;         /* classic RR from this depth on (5 in Sec. 4.2) */
+  int32_t fixed_scale;      /* FIXED: multiply the counts by |T / I~| */
+  float clamp_lo, clamp_hi; /* count clamp, [0.05, 20] in Sec. 4.1 */
+  float stat_clamp;         /* outlier clamp of statistics (50 in Sec. 4.1; 0 = off) */
+  int32_t center_jitter;    /* 1: pixel-centre camera rays */
+  int32_t debug_depth;      /* record per-vertex decisions up to this depth */
+  int32_t lp_stride;        /* BDPT: pool stride for extra light paths */
+} mars_iter_params;
+
+typedef struct {
+  uint64_t rays_camera, rays_ext, rays_shadow, rays_light, rays_conn;
+  uint64_t vertices, samples;
+  int32_t tiles, overflow_retries;
+  double ms;                /* wall time of the call */
+} mars_iter_stats;
+
+typedef struct {
+  double V_I, C_I;          /* image relative variance and cost (Sec. 4.1 "Image estimates") */
+  int32_t n_cells_before, n_cells_after, n_excluded;
+  int32_t reserved;
+} mars_update_stats;
+
+/* per-vertex decision record (parity tests): the vertex's random stream
+ * identifies its position in the path tree */
+typedef struct {
+  uint32_t root, depth, stream_lo, stream_hi, cell;
+  float beta[3];
+  uint32_t gamma[3];
+  float T[3];
+} mars_vertex_rec;
+
+/* ---- lifetime ---------------------------------------------------------- */
+/* Creates a context on desc->device.  MARS_E_HIP if no device is usable. */
+mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out);
+mars_status mars_destroy(mars_ctx* ctx);
+const char* mars_last_error(const mars_ctx* ctx);
+const char* mars_version(void);
+
+/* ---- scenes ------------------------------------------------------------ */
+/* Builds the BVH on the host, uploads geometry, emitter table and camera,
+ * and initialises the cache (one root cell, classic counts until data, a
+ * uniform directional distribution).  MARS_E_NONFINITE for non-finite
+ * vertices/materials, MARS_E_ARG for bad sizes or indices. */
+mars_status mars_scene_upload(mars_ctx* ctx, const mars_scene_desc* desc, int32_t* scene_id);
+mars_status mars_scene_release(mars_ctx* ctx, int32_t scene_id);
+
+/* ---- the iteration ----------------------------------------------------- */
+/* Renders one iteration: camera rays, per-depth closest-hit traversal,
+ * shading with per-vertex counts (Sec. 3.1 "Optimization"; colour rule of
+ * Sec. 4.1), low-discrepancy rounding (supplement Alg. 1), multi-sample MIS
+ * (Sec. 3 "The model"), shadow traversal, back-propagation of the secondary
+ * estimates, per-cell moment/cost accumulation (Sec. 4.1 "Local
+ * estimates") and the per-pixel sums.  stats is filled (host pointer). */
+mars_status mars_render_iteration(mars_ctx* ctx, int32_t scene_id, const mars_iter_params* p,
+                                  mars_iter_stats* stats);
+/* Renders one iteration of n scenes in one batched launch sequence. */
+mars_status mars_render_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                              const mars_iter_params* p, mars_iter_stats* stats);
+/* Image estimates (I~, V_I, C_I), the fixed-point update of every cell's
+ * factors, the directional distribution of the guided technique, octree
+ * refinement and the inverse-variance weighted image (Sec. 4.1, 5.1). */
+mars_status mars_update_counts(mars_ctx* ctx, int32_t scene_id, const mars_iter_params* p,
+                               mars_update_stats* stats);
+
+/* ---- inputs for tests and fixed allocations ---------------------------- */
+/* beta: host [n][3]; n = 1 (global) or the current number of cells. */
+mars_status mars_set_fixed_counts(mars_ctx* ctx, int32_t scene_id, const float* beta, int32_t n);
+/* Itilde: host [H*W][3] pixel estimates used by the next iteration. */
+mars_status mars_set_itilde(mars_ctx* ctx, int32_t scene_id, const float* itilde);
+/* pm, cdf: host [n][64] directional distributions of the first n cells. */
+mars_status mars_set_hist(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* pm,
+                          const float* cdf);
+/* factors [n][2][3][3] (float), acc [n][3][8] (double), visits [n]; any may
+ * be NULL.  n must equal the current number of cells. */
+mars_status mars_write_cells(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* factors,
+                             const double* acc, const uint32_t* visits);
+/* Runs only the fixed-point update of the cells with the given V_I, C_I. */
+mars_status mars_update_cells_only(mars_ctx* ctx, int32_t scene_id, double V_I, double C_I);
+/* Runs only the octree refinement from the current visit counts. */
+mars_status mars_refine_only(mars_ctx* ctx, int32_t scene_id, int32_t* n_split);
+
+/* ---- outputs ----------------------------------------------------------- */
+/* which = MARS_IMAGE_*; dst [H*W][3] */
+mars_status mars_read_image(mars_ctx* ctx, int32_t scene_id, int32_t which, float* dst,
+                            int32_t dst_is_device);
+/* dst [H*W][3]: mean count per technique at the first hit of the last iteration */
+mars_status mars_read_count_map(mars_ctx* ctx, int32_t scene_id, float* dst,
+                                int32_t dst_is_device);
+/* dst [H*W*spp][3]: radiance of every camera sample of the last iteration,
+ * sample s of pixel i at i*spp+s */
+mars_status mars_read_sample_radiance(mars_ctx* ctx, int32_t scene_id, float* dst,
+                                      int32_t dst_is_device);
+mars_status mars_read_itilde(mars_ctx* ctx, int32_t scene_id, float* dst, int32_t dst_is_device);
+mars_status mars_num_cells(mars_ctx* ctx, int32_t scene_id, int32_t* n_cells, int32_t* n_nodes);
+/* host arrays sized by mars_num_cells; any may be NULL */
+mars_status mars_read_cells(mars_ctx* ctx, int32_t scene_id, float* factors, double* acc,
+                            uint32_t* visits, uint32_t* leaf_depth);
+mars_status mars_read_nodes(mars_ctx* ctx, int32_t scene_id, uint32_t* nodes);
+mars_status mars_read_hist(mars_ctx* ctx, int32_t scene_id, float* pm, float* cdf);
+/* per-vertex decisions of the last iteration up to params.debug_depth;
+ * writes at most cap records, returns the total in *n */
+mars_status mars_debug_vertices(mars_ctx* ctx, int32_t scene_id, mars_vertex_rec* dst,
+                                int32_t cap, int32_t* n);
+
+/* ---- checkpoint --------------------------------------------------------- */
+/* Cache (nodes, cells, distributions), images and iteration state. */
+mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* path);
+mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* path);
+
+/* ---- measurement ------------------------------------------------------- */
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch.  Enabling resets the totals. */
+mars_status mars_profile_enable(mars_ctx* ctx, int32_t on);
+/* ms[k], launches[k] for kernel k < n; *n_kernels receives the kernel count */
+mars_status mars_profile_read(mars_ctx* ctx, double* ms, uint64_t* launches, int32_t n,
+                              int32_t* n_kernels);
+const char* mars_profile_kernel_name(int32_t id);
+/* Instrumented traversal (slower; for the algorithmic byte count per ray):
+ * out[0..2] = closest-hit rays, BVH nodes visited, triangles tested;
+ * out[3..5] = the same for shadow rays.  Enabling resets the counters. */
+mars_status mars_trace_counting(mars_ctx* ctx, int32_t on);
+mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[6]);
+
+/* ---- device probes (tests): evaluates a building block on the GPU ------ */
+/* kind 0: Philox4x32-10, in [n][6] u32 (key0, key1, ctr0..3), out [n][4] u32
+ * kind 1: sin/cos of 2 pi u, in [n] f32, out [n][2] f32
+ * kind 2: Alg. 1 rounding, in [n][4] f32 (beta x3, u), out [n][3] u32
+ * host buffers */
+mars_status mars_probe(mars_ctx* ctx, int32_t kind, int32_t n, const void* in, void* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -241,6 +241,7 @@ struct oracle {
   uint64_t rays_last;
   /* debug */
   orc_vertex_rec* dbg; int32_t ndbg;
+  unsigned char* pix_mask; /* optional: render only these pixels */
 };
 
 /* ---- median-split BVH over triangle indices (oracle's own, simple) ---- */
@@ -737,7 +738,7 @@ void orc_destroy(oracle* o) {
   free(o->nodes); free(o->leaf_node); free(o->leaf_depth); free(o->visits); free(o->fac);
   free(o->acc); free(o->pm); free(o->cdf); free(o->hacc); free(o->fixed_beta); free(o->Ls);
   free(o->iter_sum); free(o->accum); free(o->Itilde); free(o->ivw_acc); free(o->count_map);
-  free(o->beta1); free(o->dbg);
+  free(o->beta1); free(o->dbg); free(o->pix_mask);
   free(o);
 }
 
@@ -1060,6 +1061,7 @@ int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats
     o->spp_last = spp;
   }
   memset(o->beta1, 0, nroots * 3 * sizeof(float));
+  memset(o->Ls, 0, nroots * 3 * sizeof(float));
   memset(o->visits, 0, sizeof(uint32_t) * o->ncells);
   memset(o->acc, 0, sizeof(double) * 24 * o->ncells);
   memset(o->hacc, 0, sizeof(double) * 64 * o->ncells);
@@ -1072,6 +1074,7 @@ int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats
     c.o = o; c.p = p; c.key = key; c.L = &logs[py];
     for (int32_t px = 0; px < W; ++px) {
       uint32_t pix = (uint32_t)(py * W + px);
+      if (o->pix_mask && !o->pix_mask[pix]) continue;
       c.pix = pix;
       c.It[0] = o->Itilde[3 * pix]; c.It[1] = o->Itilde[3 * pix + 1]; c.It[2] = o->Itilde[3 * pix + 2];
       for (int32_t s = 0; s < spp; ++s) {
@@ -1210,12 +1213,13 @@ int32_t orc_refine_only(oracle* o) {
     if (n0 + 7 * (r + 1) > o->maxc) continue;
     uint32_t node = o->leaf_node[l];
     uint32_t base = (uint32_t)(nn0 + 8 * r);
+    uint32_t child_depth = o->leaf_depth[l] + 1; /* all eight children sit one level below */
     o->nodes[node] = base;
     for (int ch = 0; ch < 8; ++ch) {
       uint32_t id = ch == 0 ? (uint32_t)l : (uint32_t)(n0 + 7 * r + (ch - 1));
       o->nodes[base + ch] = LEAF_BIT | id;
       o->leaf_node[id] = base + ch;
-      o->leaf_depth[id] = o->leaf_depth[l] + 1;
+      o->leaf_depth[id] = child_depth;
       if (ch) {
         memcpy(o->fac + 18 * (size_t)id, o->fac + 18 * (size_t)l, 18 * sizeof(float));
         memcpy(o->pm + 64 * (size_t)id, o->pm + 64 * (size_t)l, 64 * sizeof(float));
@@ -1374,6 +1378,14 @@ void orc_write_cells(oracle* o, int32_t n, const float* factors, const double* a
   if (factors) memcpy(o->fac, factors, sizeof(float) * 18 * n);
   if (acc) memcpy(o->acc, acc, sizeof(double) * 24 * n);
   if (visits) memcpy(o->visits, visits, sizeof(uint32_t) * n);
+}
+void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n) {
+  free(o->pix_mask);
+  o->pix_mask = NULL;
+  if (!pix || n <= 0) return;
+  o->pix_mask = calloc((size_t)o->W * o->H, 1);
+  for (int32_t i = 0; i < n; ++i)
+    if (pix[i] >= 0 && pix[i] < o->W * o->H) o->pix_mask[pix[i]] = 1;
 }
 void orc_set_Itilde(oracle* o, const float* src) {
   memcpy(o->Itilde, src, sizeof(float) * 3 * o->W * o->H);

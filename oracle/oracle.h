@@ -97,6 +97,8 @@ int32_t orc_read_debug(const oracle* o, orc_vertex_rec* dst, int32_t cap);
 void orc_write_cells(oracle* o, int32_t n, const float* factors, const double* acc,
                      const uint32_t* visits);
 void orc_set_Itilde(oracle* o, const float* src);
+/* render only the listed pixels (NULL / 0: all); others get zero radiance */
+void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n);
 void orc_set_fixed_beta(oracle* o, const float* beta, int32_t n);
 void orc_set_hist(oracle* o, int32_t n, const float* pm, const float* cdf);
 int32_t orc_update_cells_only(oracle* o, double V_I, double C_I);

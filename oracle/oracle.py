@@ -84,6 +84,7 @@ def lib():
         L.orc_read_debug.restype = C.c_int32
         L.orc_write_cells.argtypes = [P, C.c_int32, P, P, P]
         L.orc_set_Itilde.argtypes = [P, P]
+        L.orc_set_pixel_subset.argtypes = [P, P, C.c_int32]
         L.orc_set_fixed_beta.argtypes = [P, P, C.c_int32]
         L.orc_set_hist.argtypes = [P, C.c_int32, P, P]
         L.orc_update_cells_only.argtypes = [P, C.c_double, C.c_double]
@@ -240,6 +241,13 @@ class Oracle:
     def set_itilde(self, it):
         it = np.ascontiguousarray(it, np.float32).reshape(self.H, self.W, 3)
         lib().orc_set_Itilde(self.h, _p(it))
+
+    def set_pixel_subset(self, pix):
+        if pix is None:
+            lib().orc_set_pixel_subset(self.h, None, 0)
+            return
+        a = np.ascontiguousarray(pix, np.int32)
+        lib().orc_set_pixel_subset(self.h, _p(a), a.shape[0])
 
     def set_fixed_beta(self, beta):
         b = np.ascontiguousarray(beta, np.float32).reshape(-1, 3)

@@ -1,0 +1,1090 @@
+// C ABI of the MARS library: context and scene management, the per-iteration
+// wavefront schedule, the update step, read-back, checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mars.h"
+#include "bvh_build.h"
+#include "mars_internal.h"
+
+using namespace mars;
+
+namespace {
+
+struct Status : std::exception {
+  mars_status code;
+  std::string msg;
+  Status(mars_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw Status(MARS_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+struct Ctx;
+
+struct Scene {
+  Ctx* ctx = nullptr;
+  std::vector<void*> owned;
+  // configuration
+  int W = 0, H = 0, mode = 0, max_depth = 0, max_cells = 0, max_tree_depth = 8, split_visits = 32;
+  int nee = 1;
+  uint64_t seed = 1;
+  size_t cap = 0;
+  int tile_roots = 0;
+  int n_tris = 0, n_mats = 0;
+  // host copies kept for checkpoints and re-validation
+  std::vector<float> mats;
+  // device views
+  SceneDev sd{};
+  CacheDev cd{};
+  QueuesDev qd{};
+  ImageDev img{};
+  Counters* cnt = nullptr;
+  DebugRec* dbg = nullptr;
+  uint32_t dbg_cap = 0;
+  int32_t* n_cells_dev = nullptr;  // [2]: cells, nodes
+  uint32_t* scratch = nullptr;     // [max_cells + 1]
+  float* fixed = nullptr;
+  int n_fixed = 0;
+  size_t roots_cap = 0;            // Ls / beta1 capacity in roots
+  // host mirrors
+  int n_cells = 1, n_nodes = 1;
+  double total_spp = 0.0;
+  int spp_last = 0;
+  uint64_t rays_last = 0;
+  int bvh_depth = 0;
+  int n_bvh_nodes = 0;
+  uint32_t dbg_last = 0;
+};
+
+// per-kernel HIP-event timing on the context's stream
+enum KernelId {
+  KID_RAYGEN, KID_TRACE_CLOSEST, KID_SHADE, KID_TRACE_ANY, KID_BACKPROP, KID_PIXEL_SUMS,
+  KID_UPDATE_IMAGE, KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_COUNT
+};
+const char* kKernelNames[KID_COUNT] = {
+    "raygen", "trace_closest", "shade", "trace_any", "backprop", "pixel_sums",
+    "update_image", "fixed_point", "hist_normalize", "refine", "ivw"};
+
+struct Profiler {
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[KID_COUNT] = {0};
+  uint64_t n[KID_COUNT] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  // call only after the stream has been synchronised
+  void flush() {
+    for (auto& p : pending) {
+      float t = 0.0f;
+      HIPCHK(hipEventElapsedTime(&t, p.second.first, p.second.second));
+      ms[p.first] += t;
+      n[p.first] += 1;
+      pool.push_back(p.second.first);
+      pool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int k = 0; k < KID_COUNT; ++k) { ms[k] = 0.0; n[k] = 0; }
+  }
+  ~Profiler() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct Ctx {
+  int device = 0;
+  Profiler prof;
+  unsigned long long* tcount = nullptr;  // traversal counters (instrumented runs)
+  bool counting = false;
+  hipStream_t stream = nullptr;
+  mars_alloc_fn alloc = nullptr;
+  mars_free_fn free_ = nullptr;
+  void* user = nullptr;
+  int cu = 256;
+  std::string err;
+  std::vector<std::unique_ptr<Scene>> scenes;
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, (void*)stream, user);
+      if (!p) throw Status(MARS_E_OOM, "allocator callback returned NULL");
+    } else {
+      if (hipMalloc(&p, bytes) != hipSuccess) throw Status(MARS_E_OOM, "hipMalloc failed");
+    }
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (free_) free_(p, (void*)stream, user);
+    else (void)hipFree(p);
+  }
+  Scene* scene(int id) {
+    if (id < 0 || id >= (int)scenes.size() || !scenes[id])
+      throw Status(MARS_E_ARG, "invalid scene id");
+    return scenes[id].get();
+  }
+};
+
+template <typename F>
+void timed(Ctx* c, int kid, F&& launch) {
+  if (!c->prof.on) {
+    launch();
+    return;
+  }
+  hipEvent_t a = c->prof.get(), b = c->prof.get();
+  HIPCHK(hipEventRecord(a, c->stream));
+  launch();
+  HIPCHK(hipEventRecord(b, c->stream));
+  c->prof.pending.push_back({kid, {a, b}});
+}
+
+template <typename T>
+T* salloc(Scene* s, size_t n) {
+  void* p = s->ctx->dalloc(n * sizeof(T));
+  s->owned.push_back(p);
+  return (T*)p;
+}
+
+void release_scene(Scene* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->ctx->stream);
+  for (void* p : s->owned) s->ctx->dfree(p);
+  s->owned.clear();
+}
+
+template <typename F>
+mars_status guard(Ctx* c, F&& f) {
+  try {
+    if (c) c->err.clear();
+    f();
+    return MARS_OK;
+  } catch (const Status& st) {
+    if (c) c->err = st.msg;
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return MARS_E_OOM;
+  } catch (...) {
+    if (c) c->err = "unknown error";
+    return MARS_E_STATE;
+  }
+}
+
+void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+}
+
+IterDev to_dev(const mars_iter_params* p) {
+  IterDev it;
+  it.iteration = p->iteration;
+  it.spp = p->spp;
+  it.alloc = p->alloc;
+  it.aware = p->budget_aware;
+  it.rr_start = p->rr_start;
+  it.fixed_scale = p->fixed_scale;
+  it.clamp_lo = p->clamp_lo;
+  it.clamp_hi = p->clamp_hi;
+  it.stat_clamp = p->stat_clamp;
+  it.center_jitter = p->center_jitter;
+  it.debug_depth = p->debug_depth;
+  it.lp_stride = p->lp_stride;
+  return it;
+}
+
+void check_params(Scene* s, const mars_iter_params* p) {
+  if (!p) throw Status(MARS_E_ARG, "null params");
+  if (p->spp <= 0 || p->spp > 4096) throw Status(MARS_E_ARG, "spp out of range");
+  if (p->alloc < 0 || p->alloc > 3) throw Status(MARS_E_ARG, "bad alloc mode");
+  if (p->alloc == MARS_ALLOC_FIXED && !s->fixed) throw Status(MARS_E_STATE, "no fixed counts set");
+  if (p->alloc == MARS_ALLOC_MLP) throw Status(MARS_E_ARG, "learned cache not enabled for scene");
+  if (!(p->clamp_lo > 0.0f) || !(p->clamp_hi >= p->clamp_lo) || !(p->clamp_hi <= 64.0f))
+    throw Status(MARS_E_ARG, "count clamp must satisfy 0 < lo <= hi <= 64");
+  if (!(p->stat_clamp >= 0.0f)) throw Status(MARS_E_ARG, "stat_clamp must be >= 0");
+}
+
+void ensure_roots(Scene* s, size_t roots) {
+  if (roots <= s->roots_cap) return;
+  s->img.Ls = salloc<float>(s, roots * 3);
+  s->img.beta1 = salloc<float>(s, roots * 3);
+  s->roots_cap = roots;
+}
+
+// one wavefront tile: returns false on queue overflow
+bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t dbg0,
+              Counters* hc) {
+  hipStream_t st = s->ctx->stream;
+  const int grid_trace = s->ctx->cu * 8, grid = s->ctx->cu * 8;
+  Ctx* c = s->ctx;
+  unsigned long long* tc = c->counting ? c->tcount : nullptr;
+  k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
+  if (dbg0) h2d(&s->cnt->n_debug, &dbg0, 4, st);  // debug records accumulate across tiles
+  timed(c, KID_RAYGEN, [&] { k_raygen(s->sd, s->qd, s->cnt, it, root0, n, st); });
+  for (int d = 1; d <= s->max_depth; ++d) {
+    timed(c, KID_TRACE_CLOSEST, [&] { k_trace_closest(s->sd, s->qd, s->cnt, d, grid_trace, st, tc); });
+    timed(c, KID_SHADE, [&] {
+      k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
+    });
+    timed(c, KID_TRACE_ANY, [&] { k_trace_any(s->sd, s->qd, s->cnt, d, grid_trace, st, tc); });
+  }
+  d2h(hc, s->cnt, sizeof(Counters), st);
+  HIPCHK(hipStreamSynchronize(st));
+  if (hc->overflow) return false;
+  for (int d = s->max_depth; d >= 1; --d)
+    timed(c, KID_BACKPROP, [&] { k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st); });
+  return true;
+}
+
+void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out) {
+  check_params(s, p);
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = s->ctx->stream;
+  const size_t roots = (size_t)s->W * s->H * p->spp;
+  if (roots > 0x7FFFFFFFull) throw Status(MARS_E_ARG, "too many camera samples");
+  ensure_roots(s, roots);
+  IterDev it = to_dev(p);
+  if (s->mode == MARS_MODE_BDPT) throw Status(MARS_E_ARG, "bidirectional mode not available");
+  // per-iteration statistics start at zero (Sec. 4.1: estimates per iteration)
+  k_fill_f64(s->cd.acc, 0.0, (size_t)s->n_cells * 24, st);
+  k_fill_f64(s->cd.hacc, 0.0, (size_t)s->n_cells * 64, st);
+  k_fill_u32(s->cd.visits, 0u, (size_t)s->n_cells, st);
+  k_fill_f32(s->img.beta1, 0.0f, roots * 3, st);
+  mars_iter_stats S{};
+  S.rays_camera = roots;
+  const uint32_t tile = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
+  std::vector<std::pair<uint32_t, uint32_t>> work;
+  for (size_t r = roots; r > 0;) {
+    const uint32_t n = (uint32_t)std::min<size_t>(tile, r);
+    r -= n;
+    work.emplace_back((uint32_t)r, n);  // processed back to front: ascending roots
+  }
+  uint32_t dbg_total = 0;
+  while (!work.empty()) {
+    auto [r0, n] = work.back();
+    work.pop_back();
+    Counters hc;
+    const bool ok = run_tile(s, it, r0, n, dbg_total, &hc);
+    S.tiles++;
+    if (!ok) {
+      if (n == 1) throw Status(MARS_E_OVERFLOW, "a single path tree exceeds the queue capacity");
+      S.overflow_retries++;
+      const uint32_t h = n / 2;
+      work.emplace_back(r0 + h, n - h);
+      work.emplace_back(r0, h);
+      continue;
+    }
+    dbg_total = hc.n_debug;
+    S.rays_ext += hc.rays_ext;
+    S.rays_shadow += hc.rays_shadow;
+    S.vertices += hc.vertices;
+    S.samples += hc.samples;
+  }
+  timed(s->ctx, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, p->spp, st); });
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  s->ctx->prof.flush();
+  s->spp_last = p->spp;
+  s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
+  s->dbg_last = dbg_total;
+  S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = S;
+}
+
+
+// ---------------------------------------------------------------------------
+// scene upload: validation, derived quantities in binary64 stored as binary32
+// (normals, emitter selection by area x luminance, octree root cube, camera
+// basis), BVH, device buffers
+// ---------------------------------------------------------------------------
+int upload_scene(Ctx* c, const mars_scene_desc* d) {
+  if (!d || !d->V || !d->tri_mat || !d->mats || !d->camera) throw Status(MARS_E_ARG, "null scene array");
+  if (d->n_tris <= 0 || d->n_mats <= 0 || d->width <= 0 || d->height <= 0)
+    throw Status(MARS_E_ARG, "bad scene sizes");
+  if (d->mode < 0 || d->mode > 2) throw Status(MARS_E_ARG, "bad mode");
+  if (d->max_depth < 1 || d->max_depth > kMaxDepth) throw Status(MARS_E_ARG, "max_depth out of range");
+  if (d->max_cells < 8 || d->max_cells > (1 << 24)) throw Status(MARS_E_ARG, "max_cells out of range");
+  if (d->max_tree_depth < 0 || d->max_tree_depth > 20) throw Status(MARS_E_ARG, "bad max_tree_depth");
+  if ((int64_t)d->width * d->height > (1 << 26)) throw Status(MARS_E_ARG, "image too large");
+  const int nt = d->n_tris, nm = d->n_mats;
+  for (size_t i = 0; i < (size_t)nt * 9; ++i)
+    if (!std::isfinite(d->V[i])) throw Status(MARS_E_NONFINITE, "non-finite vertex");
+  for (size_t i = 0; i < (size_t)nm * 8; ++i)
+    if (!std::isfinite(d->mats[i])) throw Status(MARS_E_NONFINITE, "non-finite material");
+  for (int i = 0; i < 10; ++i)
+    if (!std::isfinite(d->camera[i])) throw Status(MARS_E_NONFINITE, "non-finite camera");
+  for (int i = 0; i < nt; ++i)
+    if (d->tri_mat[i] >= (uint32_t)nm) throw Status(MARS_E_ARG, "material index out of range");
+  for (int i = 0; i < nm; ++i) {
+    const float* m = d->mats + 8 * i;
+    if (m[0] != 0.0f && m[0] != 1.0f) throw Status(MARS_E_ARG, "unknown material kind");
+    if (m[0] == 1.0f && !(m[4] > 0.0f)) throw Status(MARS_E_ARG, "GGX alpha must be positive");
+    for (int k = 5; k < 8; ++k)
+      if (m[k] < 0.0f) throw Status(MARS_E_ARG, "negative emission");
+  }
+
+  auto sp = std::make_unique<Scene>();
+  Scene* s = sp.get();
+  s->ctx = c;
+  s->W = d->width;
+  s->H = d->height;
+  s->mode = d->mode;
+  s->max_depth = d->max_depth;
+  s->max_cells = d->max_cells;
+  s->max_tree_depth = d->max_tree_depth;
+  s->split_visits = d->split_visits;
+  s->nee = d->nee_enabled;
+  s->seed = d->seed;
+  s->n_tris = nt;
+  s->n_mats = nm;
+  s->mats.assign(d->mats, d->mats + 8 * (size_t)nm);
+  hipStream_t st = c->stream;
+  try {
+    // per-triangle normals, areas; bounding box
+    std::vector<float> ng(4 * (size_t)nt), geo(12 * (size_t)nt);
+    std::vector<double> area(nt);
+    float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < nt; ++i) {
+      const float* p = d->V + 9 * (size_t)i;
+      for (int k = 0; k < 9; ++k) {
+        bmin[k % 3] = std::min(bmin[k % 3], p[k]);
+        bmax[k % 3] = std::max(bmax[k % 3], p[k]);
+      }
+      const float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+      const float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
+      float* g = &geo[12 * (size_t)i];
+      g[0] = p[0]; g[1] = p[1]; g[2] = p[2]; g[3] = 0.0f;
+      g[4] = e1[0]; g[5] = e1[1]; g[6] = e1[2]; g[7] = 0.0f;
+      g[8] = e2[0]; g[9] = e2[1]; g[10] = e2[2]; g[11] = 0.0f;
+      const double a[3] = {e1[0], e1[1], e1[2]}, b[3] = {e2[0], e2[1], e2[2]};
+      const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
+                            a[0] * b[1] - a[1] * b[0]};
+      const double l = std::sqrt((cr[0] * cr[0] + cr[1] * cr[1]) + cr[2] * cr[2]);
+      area[i] = 0.5 * l;
+      float* n = &ng[4 * (size_t)i];
+      if (l > 0.0) {
+        n[0] = (float)(cr[0] / l); n[1] = (float)(cr[1] / l); n[2] = (float)(cr[2] / l);
+      } else {
+        n[0] = 0.0f; n[1] = 0.0f; n[2] = 1.0f;
+      }
+      n[3] = 0.0f;
+    }
+    // emitters, selected proportionally to area x luminance
+    std::vector<int32_t> ltri;
+    std::vector<double> lw;
+    for (int i = 0; i < nt; ++i) {
+      const float* m = d->mats + 8 * (size_t)d->tri_mat[i];
+      if (std::max(std::max(m[5], m[6]), m[7]) > 0.0f && area[i] > 0.0) {
+        const double L = (0.2126 * (double)m[5] + 0.7152 * (double)m[6]) + 0.0722 * (double)m[7];
+        lw.push_back(area[i] * L);
+        ltri.push_back(i);
+      }
+    }
+    double wsum = 0.0;
+    for (double w : lw) wsum += w;
+    std::vector<float> lcdf(ltri.size());
+    double run = 0.0;
+    for (size_t k = 0; k < ltri.size(); ++k) {
+      run += lw[k];
+      lcdf[k] = (k + 1 == ltri.size()) ? 1.0f : (float)(run / wsum);
+      ng[4 * (size_t)ltri[k] + 3] = (float)((lw[k] / wsum) / area[ltri[k]]);
+    }
+    const double ext = std::max(std::max((double)bmax[0] - bmin[0], (double)bmax[1] - bmin[1]),
+                                (double)bmax[2] - bmin[2]);
+    SceneDev& sd = s->sd;
+    sd.eps = (float)(1e-4 * ext);
+    const double side = ext * (1.0 + 2e-4);
+    for (int k = 0; k < 3; ++k) {
+      const double ctr = 0.5 * ((double)bmin[k] + (double)bmax[k]);
+      sd.oct_lo[k] = (float)(ctr - 0.5 * side);
+    }
+    sd.oct_inv = (float)(1.0 / side);
+    {
+      const float* cam = d->camera;
+      const double P[3] = {cam[0], cam[1], cam[2]}, Tg[3] = {cam[3], cam[4], cam[5]},
+                   U[3] = {cam[6], cam[7], cam[8]};
+      double f[3] = {Tg[0] - P[0], Tg[1] - P[1], Tg[2] - P[2]};
+      const double fl = std::sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+      if (!(fl > 0.0)) throw Status(MARS_E_ARG, "camera target equals position");
+      for (int k = 0; k < 3; ++k) f[k] /= fl;
+      double r[3] = {f[1] * U[2] - f[2] * U[1], f[2] * U[0] - f[0] * U[2], f[0] * U[1] - f[1] * U[0]};
+      const double rl = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+      if (!(rl > 0.0)) throw Status(MARS_E_ARG, "camera up parallel to view direction");
+      for (int k = 0; k < 3; ++k) r[k] /= rl;
+      const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2],
+                           r[0] * f[1] - r[1] * f[0]};
+      const double th = std::tan(0.5 * (double)cam[9] * 3.14159265358979323846 / 180.0);
+      const double asp = (double)d->width / (double)d->height;
+      for (int k = 0; k < 3; ++k) {
+        sd.cam_o[k] = cam[k];
+        sd.cam_f[k] = (float)f[k];
+        sd.cam_r[k] = (float)(r[k] * th * asp);
+        sd.cam_u[k] = (float)(u[k] * th);
+      }
+    }
+    // BVH
+    BvhResult bvh = build_bvh(d->V, nt, (float)(1e-5 * ext) + 1e-7f);
+    s->bvh_depth = bvh.max_depth;
+    s->n_bvh_nodes = (int)(bvh.nodes.size() / 16);
+    if (bvh.max_depth >= kStackDepth) throw Status(MARS_E_STATE, "BVH deeper than the traversal stack");
+    float4* dbvh = salloc<float4>(s, bvh.nodes.size() / 4);
+    float4* dtri = salloc<float4>(s, bvh.tris.size() / 4);
+    float4* dgeo = salloc<float4>(s, geo.size() / 4);
+    float4* dng = salloc<float4>(s, ng.size() / 4);
+    uint32_t* dmat = salloc<uint32_t>(s, nt);
+    float* dmats = salloc<float>(s, 8 * (size_t)nm);
+    int32_t* dlt = salloc<int32_t>(s, std::max<size_t>(1, ltri.size()));
+    float* dlc = salloc<float>(s, std::max<size_t>(1, lcdf.size()));
+    h2d(dbvh, bvh.nodes.data(), bvh.nodes.size() * 4, st);
+    h2d(dtri, bvh.tris.data(), bvh.tris.size() * 4, st);
+    h2d(dgeo, geo.data(), geo.size() * 4, st);
+    h2d(dng, ng.data(), ng.size() * 4, st);
+    h2d(dmat, d->tri_mat, (size_t)nt * 4, st);
+    h2d(dmats, d->mats, (size_t)nm * 32, st);
+    h2d(dlt, ltri.data(), ltri.size() * 4, st);
+    h2d(dlc, lcdf.data(), lcdf.size() * 4, st);
+    sd.bvh = dbvh;
+    sd.tri_bvh = dtri;
+    sd.tri_geo = dgeo;
+    sd.tri_ng = dng;
+    sd.tri_mat = dmat;
+    sd.mats = dmats;
+    sd.light_tri = dlt;
+    sd.light_cdf = dlc;
+    sd.n_lights = (int)ltri.size();
+    sd.n_tris = nt;
+    sd.W = d->width;
+    sd.H = d->height;
+    sd.mode = d->mode;
+    sd.max_depth = d->max_depth;
+    sd.nee = d->nee_enabled;
+    sd.key0 = (uint32_t)d->seed;
+    sd.key1 = (uint32_t)(d->seed >> 32);
+    // cache: one root leaf, no data (classic counts), uniform distribution
+    const size_t mc = (size_t)d->max_cells;
+    CacheDev& cd = s->cd;
+    cd.nodes = salloc<uint32_t>(s, 1 + 8 * mc);
+    cd.leaf_node = salloc<uint32_t>(s, mc);
+    cd.leaf_depth = salloc<uint32_t>(s, mc);
+    cd.visits = salloc<uint32_t>(s, mc);
+    cd.fac = salloc<float>(s, mc * 18);
+    cd.acc = salloc<double>(s, mc * 24);
+    cd.pm = salloc<float>(s, mc * 64);
+    cd.cdf = salloc<float>(s, mc * 64);
+    cd.hacc = salloc<double>(s, mc * 64);
+    cd.fixed = nullptr;
+    cd.n_fixed = 0;
+    cd.max_cells = d->max_cells;
+    s->n_cells_dev = salloc<int32_t>(s, 4);
+    s->scratch = salloc<uint32_t>(s, mc + 1);
+    {
+      const uint32_t root = kLeafBit;
+      const int32_t nc[4] = {1, 1, 0, 0};
+      std::vector<float> f0(18, -1.0f), pm0(64), cdf0(64);
+      for (int b = 0; b < 64; ++b) {
+        pm0[b] = (float)(1.0 / 64.0);
+        cdf0[b] = (float)((double)(b + 1) / 64.0);
+      }
+      cdf0[63] = 1.0f;
+      const uint32_t z = 0;
+      h2d(cd.nodes, &root, 4, st);
+      h2d(cd.leaf_node, &z, 4, st);
+      h2d(cd.leaf_depth, &z, 4, st);
+      h2d(cd.fac, f0.data(), 18 * 4, st);
+      h2d(cd.pm, pm0.data(), 256, st);
+      h2d(cd.cdf, cdf0.data(), 256, st);
+      h2d(s->n_cells_dev, nc, 16, st);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    // queues
+    const size_t px = (size_t)d->width * d->height;
+    s->tile_roots = d->tile_roots > 0 ? d->tile_roots : (int)std::min<size_t>(px * 16, 1u << 20);
+    size_t cap = d->queue_capacity > 0 ? (size_t)d->queue_capacity
+                                       : std::max<size_t>(65536, 4 * (size_t)s->tile_roots);
+    if (cap > 0xFFFF0000ull) cap = 0xFFFF0000ull;
+    s->cap = cap;
+    const size_t lv = (size_t)(d->max_depth + 2) * cap;
+    QueuesDev& q = s->qd;
+    q.cap = cap;
+    q.R0 = salloc<float4>(s, lv); q.R1 = salloc<float4>(s, lv);
+    q.S0 = salloc<float4>(s, lv); q.S1 = salloc<float4>(s, lv);
+    q.S2 = salloc<float4>(s, lv); q.S3 = salloc<uint4>(s, lv);
+    q.H = salloc<uint2>(s, lv);
+    q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
+    q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
+    q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
+    s->cnt = salloc<Counters>(s, 1);
+    s->dbg_cap = 1u << 20;
+    s->dbg = salloc<DebugRec>(s, s->dbg_cap);
+    // images
+    ImageDev& im = s->img;
+    im.iter_sum = salloc<float>(s, px * 3);
+    im.accum = salloc<float>(s, px * 3);
+    im.mean = salloc<float>(s, px * 3);
+    im.itilde = salloc<float>(s, px * 3);
+    im.excl = salloc<uint8_t>(s, px);
+    im.ivw_acc = salloc<double>(s, px * 3);
+    im.count_map = salloc<float>(s, px * 3);
+    im.red = salloc<double>(s, 8);
+    k_fill_f32(im.iter_sum, 0.0f, px * 3, st);
+    k_fill_f32(im.accum, 0.0f, px * 3, st);
+    k_fill_f32(im.itilde, INFINITY, px * 3, st);
+    k_fill_f64(im.ivw_acc, 0.0, px * 3, st);
+    k_fill_f32(im.count_map, 0.0f, px * 3, st);
+    k_fill_f64(im.red, 0.0, 8, st);
+    ensure_roots(s, px);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+  } catch (...) {
+    release_scene(s);
+    throw;
+  }
+  c->scenes.push_back(std::move(sp));
+  return (int)c->scenes.size() - 1;
+}
+
+void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) {
+  if (s->spp_last <= 0) throw Status(MARS_E_STATE, "no iteration rendered");
+  hipStream_t st = s->ctx->stream;
+  const int npx = s->W * s->H, spp = s->spp_last;
+  s->total_spp += (double)spp;
+  const float kc = p ? p->stat_clamp : 0.0f;
+  Ctx* c = s->ctx;
+  timed(c, KID_UPDATE_IMAGE, [&] {
+    k_update_image(s->img, s->W, s->H, spp, (float)s->total_spp, s->mode == MARS_MODE_BDPT, kc, st);
+  });
+  const double C_I = (double)s->rays_last / ((double)npx * (double)spp);
+  const int nb = s->n_cells;
+  timed(c, KID_FIXED_POINT, [&] {
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, 1, 0.0, s->max_cells, st);
+  });
+  if (s->mode == MARS_MODE_PT_GUIDED)
+    timed(c, KID_HIST, [&] { k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, st); });
+  timed(c, KID_REFINE, [&] {
+    k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
+             s->max_tree_depth, s->max_cells, st);
+  });
+  timed(c, KID_IVW, [&] { k_ivw(s->img, npx, spp, st); });
+  double red[8];
+  int32_t nc[4];
+  d2h(red, s->img.red, sizeof(red), st);
+  d2h(nc, s->n_cells_dev, sizeof(nc), st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  c->prof.flush();
+  s->n_cells = nc[0];
+  s->n_nodes = nc[1];
+  if (out) {
+    out->V_I = red[4] > 0.0 ? red[3] / red[4] : 0.0;
+    out->C_I = C_I;
+    out->n_cells_before = nb;
+    out->n_cells_after = s->n_cells;
+    out->n_excluded = npx - (int)red[4];
+  }
+}
+
+struct CkptHeader {
+  char magic[8];
+  int32_t version, W, H, max_cells, n_cells, n_nodes, mode, spp_last;
+  double total_spp, ivw_w;
+};
+
+}  // namespace
+
+namespace {
+void out_copy(Ctx* c, float* dst, const float* host, size_t n, int dst_is_device) {
+  if (dst_is_device) {
+    HIPCHK(hipMemcpyAsync(dst, host, n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } else {
+    std::memcpy(dst, host, n * 4);
+  }
+}
+void dev_out(Ctx* c, float* dst, const float* src, size_t n, int dst_is_device) {
+  HIPCHK(hipMemcpyAsync(dst, src, n * 4, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+}  // namespace
+
+struct mars_ctx : Ctx {};
+
+extern "C" {
+
+const char* mars_version(void) { return "mars-mi355x 0.1"; }
+
+const char* mars_last_error(const mars_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
+  if (!desc || !out) return MARS_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MARS_E_HIP;
+  if (desc->device < 0 || desc->device >= n) return MARS_E_ARG;
+  if (hipSetDevice(desc->device) != hipSuccess) return MARS_E_HIP;
+  auto* c = new (std::nothrow) mars_ctx();
+  if (!c) return MARS_E_OOM;
+  c->device = desc->device;
+  c->stream = (hipStream_t)desc->stream;
+  c->alloc = desc->alloc;
+  c->free_ = desc->free;
+  c->user = desc->user;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess &&
+      cu > 0)
+    c->cu = cu;
+  *out = c;
+  return MARS_OK;
+}
+
+mars_status mars_destroy(mars_ctx* ctx) {
+  if (!ctx) return MARS_E_ARG;
+  for (auto& s : ctx->scenes) release_scene(s.get());
+  if (ctx->tcount) ctx->dfree(ctx->tcount);
+  delete ctx;
+  return MARS_OK;
+}
+
+mars_status mars_profile_enable(mars_ctx* ctx, int32_t on) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->prof.flush();
+    ctx->prof.reset();
+    ctx->prof.on = on != 0;
+  });
+}
+
+mars_status mars_profile_read(mars_ctx* ctx, double* ms, uint64_t* launches, int32_t n,
+                              int32_t* n_kernels) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->prof.flush();
+    if (n_kernels) *n_kernels = KID_COUNT;
+    for (int k = 0; k < n && k < KID_COUNT; ++k) {
+      if (ms) ms[k] = ctx->prof.ms[k];
+      if (launches) launches[k] = ctx->prof.n[k];
+    }
+  });
+}
+
+const char* mars_profile_kernel_name(int32_t id) {
+  return (id >= 0 && id < KID_COUNT) ? kKernelNames[id] : "";
+}
+
+mars_status mars_trace_counting(mars_ctx* ctx, int32_t on) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    if (!ctx->tcount) ctx->tcount = (unsigned long long*)ctx->dalloc(8 * 8);
+    k_fill_u32((uint32_t*)ctx->tcount, 0u, 16, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->counting = on != 0;
+  });
+}
+
+mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[6]) {
+  if (!ctx || !out) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    if (!ctx->tcount) throw Status(MARS_E_STATE, "trace counting never enabled");
+    d2h(out, ctx->tcount, 48, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_scene_upload(mars_ctx* ctx, const mars_scene_desc* desc, int32_t* scene_id) {
+  if (!ctx || !scene_id) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    HIPCHK(hipSetDevice(ctx->device));
+    *scene_id = upload_scene(ctx, desc);
+  });
+}
+
+mars_status mars_scene_release(mars_ctx* ctx, int32_t scene_id) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    release_scene(s);
+    ctx->scenes[scene_id].reset();
+  });
+}
+
+mars_status mars_render_iteration(mars_ctx* ctx, int32_t scene_id, const mars_iter_params* p,
+                                  mars_iter_stats* stats) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] { render_iteration(ctx->scene(scene_id), p, stats); });
+}
+
+mars_status mars_render_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                              const mars_iter_params* p, mars_iter_stats* stats) {
+  if (!ctx || !scene_ids || n <= 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    mars_iter_stats tot{};
+    for (int i = 0; i < n; ++i) {
+      mars_iter_stats one{};
+      render_iteration(ctx->scene(scene_ids[i]), p, &one);
+      tot.rays_camera += one.rays_camera; tot.rays_ext += one.rays_ext;
+      tot.rays_shadow += one.rays_shadow; tot.rays_light += one.rays_light;
+      tot.rays_conn += one.rays_conn; tot.vertices += one.vertices; tot.samples += one.samples;
+      tot.tiles += one.tiles; tot.overflow_retries += one.overflow_retries; tot.ms += one.ms;
+    }
+    if (stats) *stats = tot;
+  });
+}
+
+mars_status mars_update_counts(mars_ctx* ctx, int32_t scene_id, const mars_iter_params* p,
+                               mars_update_stats* stats) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] { update_counts(ctx->scene(scene_id), p, stats); });
+}
+
+mars_status mars_set_fixed_counts(mars_ctx* ctx, int32_t scene_id, const float* beta, int32_t n) {
+  if (!ctx || !beta) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (n != 1 && n != s->n_cells) throw Status(MARS_E_ARG, "n must be 1 or the number of cells");
+    for (int i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(beta[i]) || beta[i] < 0.0f) throw Status(MARS_E_ARG, "bad fixed count");
+    if (n > s->n_fixed) s->fixed = salloc<float>(s, 3 * (size_t)s->max_cells);
+    h2d(s->fixed, beta, 12 * (size_t)n, ctx->stream);
+    s->n_fixed = n;
+    s->cd.fixed = s->fixed;
+    s->cd.n_fixed = n;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_set_itilde(mars_ctx* ctx, int32_t scene_id, const float* itilde) {
+  if (!ctx || !itilde) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    h2d(s->img.itilde, itilde, 12 * (size_t)s->W * s->H, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_set_hist(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* pm,
+                          const float* cdf) {
+  if (!ctx || !pm || !cdf) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (n <= 0 || n > s->n_cells) throw Status(MARS_E_ARG, "bad cell count");
+    h2d(s->cd.pm, pm, 256 * (size_t)n, ctx->stream);
+    h2d(s->cd.cdf, cdf, 256 * (size_t)n, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_write_cells(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* factors,
+                             const double* acc, const uint32_t* visits) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (n != s->n_cells) throw Status(MARS_E_ARG, "n must equal the number of cells");
+    if (factors) h2d(s->cd.fac, factors, 72 * (size_t)n, ctx->stream);
+    if (acc) h2d(s->cd.acc, acc, 192 * (size_t)n, ctx->stream);
+    if (visits) h2d(s->cd.visits, visits, 4 * (size_t)n, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_update_cells_only(mars_ctx* ctx, int32_t scene_id, double V_I, double C_I) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, 0, V_I, s->max_cells, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+mars_status mars_refine_only(mars_ctx* ctx, int32_t scene_id, int32_t* n_split) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    const int before = s->n_cells;
+    k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
+             s->max_tree_depth, s->max_cells, ctx->stream);
+    int32_t nc[4];
+    d2h(nc, s->n_cells_dev, sizeof(nc), ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    s->n_cells = nc[0];
+    s->n_nodes = nc[1];
+    if (n_split) *n_split = (s->n_cells - before) / 7;
+  });
+}
+
+
+mars_status mars_read_image(mars_ctx* ctx, int32_t scene_id, int32_t which, float* dst,
+                            int32_t dst_is_device) {
+  if (!ctx || !dst) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    const size_t n = 3 * (size_t)s->W * s->H;
+    std::vector<float> out(n, 0.0f);
+    if (which == MARS_IMAGE_MEAN) {
+      std::vector<float> a(n);
+      d2h(a.data(), s->img.accum, n * 4, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (s->total_spp > 0)
+        for (size_t i = 0; i < n; ++i) out[i] = a[i] / (float)s->total_spp;
+    } else if (which == MARS_IMAGE_IVW) {
+      std::vector<double> a(n), red(8);
+      d2h(a.data(), s->img.ivw_acc, n * 8, ctx->stream);
+      d2h(red.data(), s->img.red, 64, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (red[5] > 0)
+        for (size_t i = 0; i < n; ++i) out[i] = (float)(a[i] / red[5]);
+    } else if (which == MARS_IMAGE_LAST) {
+      std::vector<float> a(n);
+      d2h(a.data(), s->img.iter_sum, n * 4, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (s->spp_last > 0)
+        for (size_t i = 0; i < n; ++i) out[i] = a[i] / (float)s->spp_last;
+    } else {
+      throw Status(MARS_E_ARG, "bad image kind");
+    }
+    out_copy(ctx, dst, out.data(), n, dst_is_device);
+  });
+}
+
+mars_status mars_read_count_map(mars_ctx* ctx, int32_t scene_id, float* dst,
+                                int32_t dst_is_device) {
+  if (!ctx || !dst) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    dev_out(ctx, dst, s->img.count_map, 3 * (size_t)s->W * s->H, dst_is_device);
+  });
+}
+
+mars_status mars_read_sample_radiance(mars_ctx* ctx, int32_t scene_id, float* dst,
+                                      int32_t dst_is_device) {
+  if (!ctx || !dst) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (s->spp_last <= 0) throw Status(MARS_E_STATE, "no iteration rendered");
+    dev_out(ctx, dst, s->img.Ls, 3 * (size_t)s->W * s->H * s->spp_last, dst_is_device);
+  });
+}
+
+mars_status mars_read_itilde(mars_ctx* ctx, int32_t scene_id, float* dst, int32_t dst_is_device) {
+  if (!ctx || !dst) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    dev_out(ctx, dst, s->img.itilde, 3 * (size_t)s->W * s->H, dst_is_device);
+  });
+}
+
+mars_status mars_num_cells(mars_ctx* ctx, int32_t scene_id, int32_t* n_cells, int32_t* n_nodes) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (n_cells) *n_cells = s->n_cells;
+    if (n_nodes) *n_nodes = s->n_nodes;
+  });
+}
+
+mars_status mars_read_cells(mars_ctx* ctx, int32_t scene_id, float* factors, double* acc,
+                            uint32_t* visits, uint32_t* leaf_depth) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    const size_t n = (size_t)s->n_cells;
+    if (factors) d2h(factors, s->cd.fac, 72 * n, ctx->stream);
+    if (acc) d2h(acc, s->cd.acc, 192 * n, ctx->stream);
+    if (visits) d2h(visits, s->cd.visits, 4 * n, ctx->stream);
+    if (leaf_depth) d2h(leaf_depth, s->cd.leaf_depth, 4 * n, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_read_nodes(mars_ctx* ctx, int32_t scene_id, uint32_t* nodes) {
+  if (!ctx || !nodes) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    d2h(nodes, s->cd.nodes, 4 * (size_t)s->n_nodes, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_read_hist(mars_ctx* ctx, int32_t scene_id, float* pm, float* cdf) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (pm) d2h(pm, s->cd.pm, 256 * (size_t)s->n_cells, ctx->stream);
+    if (cdf) d2h(cdf, s->cd.cdf, 256 * (size_t)s->n_cells, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_debug_vertices(mars_ctx* ctx, int32_t scene_id, mars_vertex_rec* dst, int32_t cap,
+                                int32_t* n) {
+  if (!ctx || !n) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    static_assert(sizeof(mars_vertex_rec) == sizeof(DebugRec), "record layout");
+    const uint32_t total = std::min(s->dbg_last, s->dbg_cap);
+    *n = (int32_t)total;
+    const uint32_t m = std::min<uint32_t>(total, cap > 0 ? (uint32_t)cap : 0u);
+    if (dst && m) {
+      d2h(dst, s->dbg, sizeof(DebugRec) * m, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+  });
+}
+
+mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* path) {
+  if (!ctx || !path) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    hipStream_t st = ctx->stream;
+    const size_t nc = (size_t)s->n_cells, nn = (size_t)s->n_nodes, px = (size_t)s->W * s->H;
+    std::vector<uint32_t> nodes(nn), lnode(nc), ldep(nc);
+    std::vector<float> fac(nc * 18), pm(nc * 64), cdf(nc * 64), accum(px * 3), it(px * 3);
+    std::vector<double> ivw(px * 3), red(8);
+    d2h(nodes.data(), s->cd.nodes, nn * 4, st);
+    d2h(lnode.data(), s->cd.leaf_node, nc * 4, st);
+    d2h(ldep.data(), s->cd.leaf_depth, nc * 4, st);
+    d2h(fac.data(), s->cd.fac, nc * 72, st);
+    d2h(pm.data(), s->cd.pm, nc * 256, st);
+    d2h(cdf.data(), s->cd.cdf, nc * 256, st);
+    d2h(accum.data(), s->img.accum, px * 12, st);
+    d2h(it.data(), s->img.itilde, px * 12, st);
+    d2h(ivw.data(), s->img.ivw_acc, px * 24, st);
+    d2h(red.data(), s->img.red, 64, st);
+    HIPCHK(hipStreamSynchronize(st));
+    CkptHeader h{};
+    std::memcpy(h.magic, "MARSCKP1", 8);
+    h.version = 1; h.W = s->W; h.H = s->H; h.max_cells = s->max_cells;
+    h.n_cells = s->n_cells; h.n_nodes = s->n_nodes; h.mode = s->mode; h.spp_last = s->spp_last;
+    h.total_spp = s->total_spp; h.ivw_w = red[5];
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw Status(MARS_E_IO, "cannot open checkpoint for writing");
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+    auto w = [&](const void* p, size_t b) { ok = ok && (b == 0 || std::fwrite(p, b, 1, f) == 1); };
+    w(nodes.data(), nn * 4); w(lnode.data(), nc * 4); w(ldep.data(), nc * 4);
+    w(fac.data(), nc * 72); w(pm.data(), nc * 256); w(cdf.data(), nc * 256);
+    w(accum.data(), px * 12); w(it.data(), px * 12); w(ivw.data(), px * 24);
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw Status(MARS_E_IO, "checkpoint write failed");
+  });
+}
+
+mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* path) {
+  if (!ctx || !path) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw Status(MARS_E_IO, "cannot open checkpoint");
+    CkptHeader h{};
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+    if (!ok || std::memcmp(h.magic, "MARSCKP1", 8) != 0 || h.version != 1) {
+      std::fclose(f);
+      throw Status(MARS_E_IO, "not a checkpoint");
+    }
+    if (h.W != s->W || h.H != s->H || h.max_cells != s->max_cells || h.mode != s->mode ||
+        h.n_cells <= 0 || h.n_cells > s->max_cells || h.n_nodes <= 0 ||
+        h.n_nodes > 1 + 8 * s->max_cells) {
+      std::fclose(f);
+      throw Status(MARS_E_ARG, "checkpoint does not match the scene");
+    }
+    const size_t nc = (size_t)h.n_cells, nn = (size_t)h.n_nodes, px = (size_t)s->W * s->H;
+    std::vector<uint32_t> nodes(nn), lnode(nc), ldep(nc);
+    std::vector<float> fac(nc * 18), pm(nc * 64), cdf(nc * 64), accum(px * 3), it(px * 3);
+    std::vector<double> ivw(px * 3);
+    auto r = [&](void* p, size_t b) { ok = ok && (b == 0 || std::fread(p, b, 1, f) == 1); };
+    r(nodes.data(), nn * 4); r(lnode.data(), nc * 4); r(ldep.data(), nc * 4);
+    r(fac.data(), nc * 72); r(pm.data(), nc * 256); r(cdf.data(), nc * 256);
+    r(accum.data(), px * 12); r(it.data(), px * 12); r(ivw.data(), px * 24);
+    std::fclose(f);
+    if (!ok) throw Status(MARS_E_IO, "truncated checkpoint");
+    // structural validation: every reference stays inside the arrays
+    for (size_t i = 0; i < nn; ++i) {
+      const uint32_t v = nodes[i];
+      if (v & kLeafBit) {
+        if ((v & ~kLeafBit) >= nc) throw Status(MARS_E_IO, "corrupt checkpoint (leaf id)");
+      } else if ((size_t)v + 8 > nn || v == 0) {
+        throw Status(MARS_E_IO, "corrupt checkpoint (child index)");
+      }
+    }
+    for (size_t l = 0; l < nc; ++l)
+      if (lnode[l] >= nn || ldep[l] > 30) throw Status(MARS_E_IO, "corrupt checkpoint (leaf)");
+    hipStream_t st = ctx->stream;
+    h2d(s->cd.nodes, nodes.data(), nn * 4, st);
+    h2d(s->cd.leaf_node, lnode.data(), nc * 4, st);
+    h2d(s->cd.leaf_depth, ldep.data(), nc * 4, st);
+    h2d(s->cd.fac, fac.data(), nc * 72, st);
+    h2d(s->cd.pm, pm.data(), nc * 256, st);
+    h2d(s->cd.cdf, cdf.data(), nc * 256, st);
+    h2d(s->img.accum, accum.data(), px * 12, st);
+    h2d(s->img.itilde, it.data(), px * 12, st);
+    h2d(s->img.ivw_acc, ivw.data(), px * 24, st);
+    const int32_t ncv[4] = {h.n_cells, h.n_nodes, 0, 0};
+    h2d(s->n_cells_dev, ncv, 16, st);
+    std::vector<double> red(8, 0.0);
+    red[5] = h.ivw_w;
+    h2d(s->img.red, red.data(), 64, st);
+    HIPCHK(hipStreamSynchronize(st));
+    s->n_cells = h.n_cells;
+    s->n_nodes = h.n_nodes;
+    s->total_spp = h.total_spp;
+    s->spp_last = 0;
+  });
+}
+
+mars_status mars_probe(mars_ctx* ctx, int32_t kind, int32_t n, const void* in, void* out) {
+  if (!ctx || !in || !out || n <= 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    size_t ib, ob;
+    if (kind == 0) { ib = 24; ob = 16; }
+    else if (kind == 1) { ib = 4; ob = 8; }
+    else if (kind == 2) { ib = 16; ob = 12; }
+    else throw Status(MARS_E_ARG, "bad probe kind");
+    void* din = ctx->dalloc(ib * n);
+    void* dout = nullptr;
+    try {
+      dout = ctx->dalloc(ob * n);
+      h2d(din, in, ib * n, ctx->stream);
+      k_probe(kind, n, din, dout, ctx->stream);
+      d2h(out, dout, ob * n, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipGetLastError());
+    } catch (...) {
+      ctx->dfree(din);
+      ctx->dfree(dout);
+      throw;
+    }
+    ctx->dfree(din);
+    ctx->dfree(dout);
+  });
+}
+
+}  // extern "C"

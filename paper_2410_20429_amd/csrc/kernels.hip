@@ -1,0 +1,986 @@
+// Wavefront kernels of the MARS hot path for gfx950 (CDNA4).
+//
+// One iteration (Sec. 4.1 "Fixed-point iteration") is a sequence of
+// per-depth stages over SoA queues:
+//   raygen -> [trace_closest -> shade -> trace_any] x D -> backprop (D..1)
+//   -> pixel sums
+// and the update between iterations:
+//   image estimates (I~, V_I) -> fixed-point factors -> guided distribution
+//   -> octree refinement -> inverse-variance image.
+// Splitting turns a camera path into a tree; every child sample is written
+// to the next depth's queue at an offset from a wave-level prefix sum (one
+// global atomic per wave), and the tree is reduced bottom-up afterwards by a
+// pull over each vertex's contiguous child range, so per-pixel radiance does
+// not depend on queue order.
+#include <hip/hip_runtime.h>
+
+#include "device_math.hpp"
+#include "mars_internal.h"
+
+namespace mars {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float fbits(uint32_t u) { return __uint_as_float(u); }
+__device__ __forceinline__ uint32_t ubits(float f) { return __float_as_uint(f); }
+__device__ __forceinline__ Mat load_mat(const float* m) {
+  return Mat{m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]};
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n) fill_kernel<uint32_t><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
+}
+void k_fill_f64(double* p, double v, size_t n, hipStream_t s) {
+  if (n) fill_kernel<double><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
+}
+void k_fill_f32(float* p, float v, size_t n, hipStream_t s) {
+  if (n) fill_kernel<float><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
+}
+
+// ---------------------------------------------------------------------------
+// camera rays: pinhole, W/p = 1, jitter from block 1 of the root stream
+// ---------------------------------------------------------------------------
+__global__ void raygen_kernel(SceneDev sc, QueuesDev q, Counters* cnt, IterDev it, uint32_t root0,
+                              uint32_t n) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) cnt->n_ray[1] = n;
+  if (j >= n) return;
+  const Key key{sc.key0, sc.key1};
+  const uint32_t root = root0 + j;
+  const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
+  const int px = (int)(pix % (uint32_t)sc.W), py = (int)(pix / (uint32_t)sc.W);
+  const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagCam);
+  const float4 u = draw4(key, st, 1);
+  const float jx = it.center_jitter ? 0.5f : u.x, jy = it.center_jitter ? 0.5f : u.y;
+  const float sx = (((float)px + jx) / (float)sc.W) * 2.0f - 1.0f;
+  const float sy = 1.0f - (((float)py + jy) / (float)sc.H) * 2.0f;
+  const f3 d = norm3(mk3((sc.cam_f[0] + sx * sc.cam_r[0]) + sy * sc.cam_u[0],
+                         (sc.cam_f[1] + sx * sc.cam_r[1]) + sy * sc.cam_u[1],
+                         (sc.cam_f[2] + sx * sc.cam_r[2]) + sy * sc.cam_u[2]));
+  const size_t e = q.cap + j;  // depth 1
+  q.R0[e] = make_float4(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2], 1.0f);
+  q.R1[e] = make_float4(d.x, d.y, d.z, fbits(pix));
+  q.S0[e] = make_float4(1.0f, 1.0f, 1.0f, fbits(0xFFFFFFFFu));
+  q.S1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  q.S3[e] = make_uint4(st.x, st.y, 0u, root);
+}
+void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterDev& it,
+              uint32_t root0, uint32_t n_roots, hipStream_t s) {
+  raygen_kernel<<<(n_roots + 255) / 256, 256, 0, s>>>(sc, q, cnt, it, root0, n_roots);
+}
+
+// ---------------------------------------------------------------------------
+// BVH traversal.  Node: two child boxes + two child references (>= 0 inner
+// node, < 0 leaf = -1 - (first << 4 | count)).  Per-lane stack in LDS,
+// column-major so that lanes of a wave hit distinct banks.  Leaf children
+// are intersected as soon as their box is hit; the nearer inner child is
+// visited first.
+// ---------------------------------------------------------------------------
+struct RayInv {
+  float ix, iy, iz, ox, oy, oz;
+};
+__device__ __forceinline__ RayInv ray_inv(f3 o, f3 d) {
+  const float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
+  const float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
+  const float dz = fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z);
+  RayInv r;
+  r.ix = 1.0f / dx; r.iy = 1.0f / dy; r.iz = 1.0f / dz;
+  r.ox = o.x * r.ix; r.oy = o.y * r.iy; r.oz = o.z * r.iz;
+  return r;
+}
+__device__ __forceinline__ float box_near(const RayInv& r, float lx, float ly, float lz, float hx,
+                                          float hy, float hz, float tmax) {
+  const float ax = __builtin_fmaf(lx, r.ix, -r.ox), bx = __builtin_fmaf(hx, r.ix, -r.ox);
+  const float ay = __builtin_fmaf(ly, r.iy, -r.oy), by = __builtin_fmaf(hy, r.iy, -r.oy);
+  const float az = __builtin_fmaf(lz, r.iz, -r.oz), bz = __builtin_fmaf(hz, r.iz, -r.oz);
+  const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+  const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+  return (tn <= tf && tf >= 0.0f && tn <= tmax) ? tn : INFINITY;
+}
+
+// Moller-Trumbore, two-sided, fixed operation order
+__device__ __forceinline__ bool tri_hit(f3 o, f3 d, float4 A, float4 B, float4 Cc, float* t) {
+  const f3 v0 = xyz(A), e1 = xyz(B), e2 = xyz(Cc);
+  const f3 p = cross3(d, e2);
+  const float det = dot3(e1, p);
+  if (det == 0.0f) return false;
+  const float inv = 1.0f / det;
+  const f3 s = sub3(o, v0);
+  const float u = dot3(s, p) * inv;
+  if (u < 0.0f || u > 1.0f) return false;
+  const f3 qv = cross3(s, e1);
+  const float v = dot3(d, qv) * inv;
+  if (v < 0.0f || u + v > 1.0f) return false;
+  *t = dot3(e2, qv) * inv;
+  return true;
+}
+
+template <bool kAny, bool kCount>
+__device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
+                                         float* bt_out, uint32_t* bp_out, uint32_t* n_nodes,
+                                         uint32_t* n_tris) {
+  const RayInv ri = ray_inv(o, d);
+  float bt = tmax;
+  uint32_t bp = kMiss;
+  int sp = 0;
+  int node = 0;
+  const int lane = threadIdx.x;
+  while (true) {
+    const float4* N = sc.bvh + (size_t)node * 4;
+    if (kCount) ++*n_nodes;
+    const float4 a = N[0], b = N[1], c = N[2];
+    const float4 rr = N[3];
+    const int c0 = (int)ubits(rr.x), c1 = (int)ubits(rr.y);
+    float t0 = box_near(ri, a.x, a.y, a.z, a.w, b.x, b.y, bt);
+    float t1 = box_near(ri, b.z, b.w, c.x, c.y, c.z, c.w, bt);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int ch = side ? c1 : c0;
+      const float tn = side ? t1 : t0;
+      if (ch < 0 && tn != INFINITY) {
+        const uint32_t code = (uint32_t)(-1 - ch);
+        const uint32_t first = code >> 4, count = code & 15u;
+        for (uint32_t k = first; k < first + count; ++k) {
+          const float4* T = sc.tri_bvh + (size_t)k * 3;
+          if (kCount) ++*n_tris;
+          const float4 A = T[0];
+          float t;
+          if (!tri_hit(o, d, A, T[1], T[2], &t)) continue;
+          if (!(t > 0.0f && t < tmax)) continue;
+          const uint32_t prim = ubits(A.w);
+          if (kAny) {
+            *bt_out = t;
+            *bp_out = prim;
+            return true;
+          }
+          if (t < bt || (t == bt && prim < bp)) {
+            bt = t;
+            bp = prim;
+          }
+        }
+        if (side) t1 = INFINITY; else t0 = INFINITY;
+      }
+    }
+    const bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
+    if (h0 && h1) {
+      int nearc = c0, farc = c1;
+      if (t1 < t0) { nearc = c1; farc = c0; }
+      stk[sp * kTraceBlock + lane] = farc;
+      ++sp;
+      node = nearc;
+    } else if (h0) {
+      node = c0;
+    } else if (h1) {
+      node = c1;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = stk[sp * kTraceBlock + lane];
+    }
+  }
+  *bt_out = bt;
+  *bp_out = bp;
+  return bp != kMiss;
+}
+
+__device__ __forceinline__ void add_counts(unsigned long long* tc, uint32_t rays, uint32_t nodes,
+                                           uint32_t tris) {
+  const uint32_t a = wave_sum(rays), b = wave_sum(nodes), c = wave_sum(tris);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(tc + 0, (unsigned long long)a);
+    atomicAdd(tc + 1, (unsigned long long)b);
+    atomicAdd(tc + 2, (unsigned long long)c);
+  }
+}
+
+template <bool kCount>
+__global__ __launch_bounds__(kTraceBlock) void trace_closest_kernel(SceneDev sc, QueuesDev q,
+                                                                    const Counters* cnt, int d,
+                                                                    unsigned long long* tc) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  if (cnt->overflow) return;  // the tile is re-run; queue contents past capacity are not valid
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap;
+  uint32_t nr = 0, nn = 0, nt = 0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const float4 r0 = q.R0[L + j];
+    uint2 h = make_uint2(ubits(INFINITY), kMiss);
+    if (r0.w != 0.0f) {
+      const float4 r1 = q.R1[L + j];
+      float t;
+      uint32_t p;
+      if (kCount) ++nr;
+      if (traverse<false, kCount>(sc, xyz(r0), xyz(r1), INFINITY, stk, &t, &p, &nn, &nt))
+        h = make_uint2(ubits(t), p);
+    }
+    q.H[L + j] = h;
+  }
+  if (kCount) add_counts(tc, nr, nn, nt);
+}
+void k_trace_closest(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
+                     hipStream_t s, unsigned long long* tc) {
+  if (tc) trace_closest_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, tc);
+  else trace_closest_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, nullptr);
+}
+
+template <bool kCount>
+__global__ __launch_bounds__(kTraceBlock) void trace_any_kernel(SceneDev sc, QueuesDev q,
+                                                                const Counters* cnt, int d,
+                                                                unsigned long long* tc) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  if (cnt->overflow) return;
+  const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap;
+  uint32_t nr = 0, nn = 0, nt = 0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const float4 v = q.SH2[L + j];
+    if (v.w == 0.0f) continue;
+    const float4 a = q.SH0[L + j], b = q.SH1[L + j];
+    float t;
+    uint32_t p;
+    if (kCount) ++nr;
+    if (traverse<true, kCount>(sc, xyz(a), xyz(b), a.w, stk, &t, &p, &nn, &nt))
+      q.SH2[L + j] = make_float4(0.0f, 0.0f, 0.0f, v.w);
+  }
+  if (kCount) add_counts(tc + 3, nr, nn, nt);
+}
+void k_trace_any(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
+                 hipStream_t s, unsigned long long* tc) {
+  if (tc) trace_any_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, tc);
+  else trace_any_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// per-vertex sample counts (Sec. 3.1 "Optimization", colour rule Sec. 4.1):
+//   beta^X_t = sqrt((1/3) sum_ch (T_ch / I~_ch)^2 a^X_{t,ch}),
+//   beta = beta^RR if < 1, else beta^S if > 1, else 1; clamped.
+// classic throughput RR: q = min(1, max T) from rr_start on (baseline and
+// warm-up of Sec. 4.1 / 5.2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c, const IterDev& it,
+                                          uint32_t cell, f3 T, const float* It, int depth,
+                                          float beta[3]) {
+  const float q = (depth >= it.rr_start) ? fminf(1.0f, fmaxf(fmaxf(T.x, T.y), T.z)) : 1.0f;
+  float cb[3];
+  if (sc.mode == 1) { cb[0] = q * 0.5f; cb[1] = 1.0f; cb[2] = q * 0.5f; }
+  else if (sc.mode == 2) { cb[0] = q; cb[1] = 1.0f; cb[2] = 1.0f; }
+  else { cb[0] = q; cb[1] = 1.0f; cb[2] = 0.0f; }
+  const bool en[3] = {true, sc.nee != 0 && sc.n_lights > 0, sc.mode != 0};
+  const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!en[t]) { beta[t] = 0.0f; continue; }
+    if (it.alloc == 0) { beta[t] = cb[t]; continue; }
+    float b;
+    if (it.alloc == 2) {
+      const int idx = c.n_fixed > 1 ? (int)cell : 0;
+      b = c.fixed[idx * 3 + t];
+      if (it.fixed_scale) {
+        const float s = ((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f);
+        b = b * sqrtf(s);
+      }
+    } else {
+      const float* aRR = c.fac + (size_t)cell * 18 + (0 * 3 + t) * 3;
+      const float* aS = c.fac + (size_t)cell * 18 + (1 * 3 + t) * 3;
+      if (aRR[0] < 0.0f) {
+        b = cb[t];
+      } else {
+        const float sr = ((z0 * z0) * aRR[0] + (z1 * z1) * aRR[1]) + (z2 * z2) * aRR[2];
+        const float ss = ((z0 * z0) * aS[0] + (z1 * z1) * aS[1]) + (z2 * z2) * aS[2];
+        const float bRR = sqrtf(sr * (1.0f / 3.0f));
+        const float bS = sqrtf(ss * (1.0f / 3.0f));
+        b = bRR < 1.0f ? bRR : (bS > 1.0f ? bS : 1.0f);
+      }
+    }
+    beta[t] = fminf(fmaxf(b, it.clamp_lo), it.clamp_hi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// shading of unidirectional paths (Sec. 3.1, Sec. 4): emission with its
+// direct-light MIS weight, cell lookup, counts, Alg. 1 rounding, and the
+// samples of every technique: NEE (shadow queue), BSDF and guided
+// (continuation queue).  Balance heuristic over {B,N,G} for direct light and
+// {B,G} for indirect light; budget-aware multiplies every density by beta.
+// Child throughput T' = T B|cos| / p_t * w_ind,t / beta_t (Sec. 3.1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+                                                       Counters* cnt, IterDev it, ImageDev img,
+                                                       DebugRec* dbg, uint32_t dbg_cap, int d) {
+  if (cnt->overflow) return;
+  const Key key{sc.key0, sc.key1};
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const int lane = threadIdx.x & 63;
+  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
+  const bool guided = sc.mode == 1;
+  uint32_t my_vert = 0, my_samp = 0, my_ext = 0, my_sh = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t j = base + threadIdx.x;
+    const bool active = j < n;
+    bool vert = false;
+    f3 Ew = mk3(0.0f, 0.0f, 0.0f);
+    uint32_t cell = kNoCell;
+    float beta[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t gam[3] = {0u, 0u, 0u};
+    f3 x = mk3(0, 0, 0), n_s = mk3(0, 0, 0), wo = mk3(0, 0, 0), T = mk3(0, 0, 0), ov = mk3(0, 0, 0);
+    uint32_t prim = kMiss, pix = 0, root = 0;
+    uint2 strm = make_uint2(0, 0);
+    float It[3] = {1.0f, 1.0f, 1.0f};
+    if (active) {
+      const uint2 h = q.H[L + j];
+      prim = h.y;
+      const float4 r1 = q.R1[L + j];
+      pix = ubits(r1.w);
+      const uint4 s3 = q.S3[L + j];
+      root = s3.w;
+      if (prim != kMiss) {
+        const float t = fbits(h.x);
+        const float4 r0 = q.R0[L + j];
+        const f3 dir = xyz(r1);
+        const float4 ngl = sc.tri_ng[prim];
+        const f3 ng = xyz(ngl);
+        const float* m = sc.mats + 8 * (size_t)sc.tri_mat[prim];
+        x = mk3(r0.x + t * dir.x, r0.y + t * dir.y, r0.z + t * dir.z);
+        const float cosl = -dot3(dir, ng);
+        if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
+          if (d == 1) {
+            Ew = mk3(m[5], m[6], m[7]);
+          } else {
+            const float4 s2 = q.S2[L + j];
+            const float pN = (ngl.w * (t * t)) / cosl;
+            const float w = s2.x / (s2.y + s2.z * pN);
+            Ew = mk3(w * m[5], w * m[6], w * m[7]);
+          }
+        }
+        if (d < sc.max_depth) {
+          vert = true;
+          n_s = dot3(ng, dir) < 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+          wo = mk3(-dir.x, -dir.y, -dir.z);
+          ov = mk3(x.x + n_s.x * sc.eps, x.y + n_s.y * sc.eps, x.z + n_s.z * sc.eps);
+          cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
+          const float4 s0 = q.S0[L + j];
+          T = xyz(s0);
+          It[0] = img.itilde[3 * (size_t)pix];
+          It[1] = img.itilde[3 * (size_t)pix + 1];
+          It[2] = img.itilde[3 * (size_t)pix + 2];
+          counts_at(sc, c, it, cell, T, It, d, beta);
+          strm = make_uint2(s3.x, s3.y);
+          const float4 u = draw4(key, strm, 0);
+          round_counts(beta, u.x, gam);
+        }
+      }
+    }
+    const uint32_t ncont = vert ? gam[0] + gam[2] : 0u, nnee = vert ? gam[1] : 0u;
+    // wave-level allocation in the next-depth and shadow queues
+    const uint32_t packed = ncont | (nnee << 16);
+    const uint32_t incl = wave_scan_incl(packed);
+    const uint32_t excl = incl - packed;
+    const uint32_t tot = __shfl(incl, 63, 64);
+    uint32_t bc = 0, bs = 0;
+    if (lane == 63) {
+      if (tot & 0xFFFFu) bc = atomicAdd(&cnt->n_ray[d + 1], tot & 0xFFFFu);
+      if (tot >> 16) bs = atomicAdd(&cnt->n_shadow[d], tot >> 16);
+    }
+    bc = __shfl(bc, 63, 64);
+    bs = __shfl(bs, 63, 64);
+    const uint32_t cfirst = bc + (excl & 0xFFFFu), sfirst = bs + (excl >> 16);
+    bool ovf = false;
+    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.cap)) {
+      ovf = true;
+      atomicMax(&cnt->overflow, 1u);
+    }
+    if (!active) continue;
+    q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
+    q.V1[L + j] = make_float4(beta[0], beta[1], beta[2], 0.0f);
+    q.V2[L + j] = ovf ? make_uint4(0, 0, 0, 0) : make_uint4(sfirst, nnee, cfirst, ncont);
+    if (d == 1) {
+      img.beta1[3 * (size_t)root] = beta[0];
+      img.beta1[3 * (size_t)root + 1] = beta[1];
+      img.beta1[3 * (size_t)root + 2] = beta[2];
+    }
+    if (!vert || ovf) continue;
+    ++my_vert;
+    my_samp += gam[0] + gam[1] + gam[2];
+    if (d <= it.debug_depth && dbg) {
+      const uint32_t k = atomicAdd(&cnt->n_debug, 1u);
+      if (k < dbg_cap) {
+        DebugRec r;
+        r.root = root; r.depth = (uint32_t)d; r.stream_lo = strm.x; r.stream_hi = strm.y;
+        r.cell = cell;
+        for (int t = 0; t < 3; ++t) { r.beta[t] = beta[t]; r.gamma[t] = gam[t]; }
+        r.T[0] = T.x; r.T[1] = T.y; r.T[2] = T.z;
+        dbg[k] = r;
+      }
+    }
+    const float* m = sc.mats + 8 * (size_t)sc.tri_mat[prim];
+    const Mat mat = load_mat(m);
+    const float* pmf = c.pm + 64 * (size_t)cell;
+    const float* cdf = c.cdf + 64 * (size_t)cell;
+    const float bB = it.aware ? beta[0] : (beta[0] > 0.0f ? 1.0f : 0.0f);
+    const float bN = it.aware ? beta[1] : (beta[1] > 0.0f ? 1.0f : 0.0f);
+    const float bG = it.aware ? beta[2] : (beta[2] > 0.0f ? 1.0f : 0.0f);
+    // NEE: light by power, uniform point on the triangle
+    for (uint32_t k = 0; k < gam[1]; ++k) {
+      const uint2 ss = stream_child(key, strm, 1u, k, (uint32_t)d);
+      const float4 u = draw4(key, ss, 1);
+      int lo = 0, hi = sc.n_lights - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u.x < sc.light_cdf[mid]) hi = mid; else lo = mid + 1;
+      }
+      const int lt = sc.light_tri[lo];
+      const float4* G = sc.tri_geo + (size_t)lt * 3;
+      const f3 v0 = xyz(G[0]), e1 = xyz(G[1]), e2 = xyz(G[2]);
+      const float su = sqrtf(u.y);
+      const float a = su * (1.0f - u.z), b = su * u.z;
+      const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
+                       (v0.z + a * e1.z) + b * e2.z);
+      const f3 dv = sub3(y, ov);
+      const float d2 = dot3(dv, dv);
+      const float dist = sqrtf(d2);
+      const f3 w = scl3(dv, 1.0f / dist);
+      const float4 lng = sc.tri_ng[lt];
+      const float cl = -dot3(w, xyz(lng));
+      f3 fc;
+      float pB;
+      eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+      float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+        const float pN = (lng.w * d2) / cl;
+        const float pG = guided ? guided_density(pmf, w) : 0.0f;
+        const float nb = bB * pB, nn = bN * pN, ngd = bG * pG;
+        const float ddir = (nb + ngd) + nn;
+        const float wN = ddir > 0.0f ? nn / ddir : 0.0f;
+        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[lt] + 5;
+        sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
+                          (fc.z / pN) * (wN * Le[2]), 1.0f);
+        ++my_sh;
+      }
+      const size_t e = L + sfirst + k;
+      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
+      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      q.SH2[e] = sh2;
+    }
+    // continuation: BSDF samples then guided samples
+    uint32_t slot = 0;
+    for (int tech = 0; tech < 3; tech += 2) {
+      for (uint32_t k = 0; k < gam[tech]; ++k, ++slot) {
+        const uint2 ss = stream_child(key, strm, (uint32_t)tech, k, (uint32_t)d);
+        const float4 u = draw4(key, ss, 1);
+        f3 w;
+        bool ok;
+        if (tech == 0) {
+          ok = sample_bsdf(mat, n_s, wo, u.x, u.y, &w);
+        } else {
+          w = guided_direction(cdf, u.x, u.y, u.z);
+          ok = dot3(n_s, w) > 0.0f;
+        }
+        f3 fc = mk3(0.0f, 0.0f, 0.0f);
+        float pB = 0.0f, pG = 0.0f, pt = 0.0f;
+        if (ok) {
+          eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+          pG = guided ? guided_density(pmf, w) : 0.0f;
+          pt = tech == 0 ? pB : pG;
+          ok = (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f) && pt > 0.0f;
+        }
+        const size_t e = Ln + cfirst + slot;
+        if (ok) {
+          const float nb = bB * pB, ngd = bG * pG;
+          const float dind = nb + ngd;
+          const float wind = dind > 0.0f ? (tech == 0 ? nb : ngd) / dind : 0.0f;
+          const float dsum = bB * pB + bG * pG;
+          const float bt = beta[tech];
+          const float c0 = fc.x / pt, c1 = fc.y / pt, c2 = fc.z / pt;
+          const f3 Tc = mk3(T.x * ((c0 * wind) / bt), T.y * ((c1 * wind) / bt),
+                            T.z * ((c2 * wind) / bt));
+          q.R0[e] = make_float4(ov.x, ov.y, ov.z, 1.0f);
+          q.R1[e] = make_float4(w.x, w.y, w.z, fbits(pix));
+          q.S0[e] = make_float4(Tc.x, Tc.y, Tc.z, fbits(j));
+          q.S1[e] = make_float4(c0, c1, c2, wind);
+          q.S2[e] = make_float4((tech == 0 ? bB : bG) * pt, dsum, bN, bt);
+          ++my_ext;
+        } else {
+          q.R0[e] = make_float4(ov.x, ov.y, ov.z, 0.0f);
+          q.R1[e] = make_float4(w.x, w.y, w.z, fbits(pix));
+          q.S0[e] = make_float4(0.0f, 0.0f, 0.0f, fbits(j));
+          q.S1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, beta[tech]);
+        }
+        q.S3[e] = make_uint4(ss.x, ss.y, ((uint32_t)tech << 16) | k, root);
+      }
+    }
+  }
+  // one atomic per wave for the iteration counters
+  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext),
+                 sh = wave_sum(my_sh);
+  if (lane == 0) {
+    if (sv) atomicAdd(&cnt->vertices, (unsigned long long)sv);
+    if (ss) atomicAdd(&cnt->samples, (unsigned long long)ss);
+    if (se) atomicAdd(&cnt->rays_ext, (unsigned long long)se);
+    if (sh) atomicAdd(&cnt->rays_shadow, (unsigned long long)sh);
+  }
+}
+void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
+                const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
+                int grid, hipStream_t s) {
+  shade_pt_kernel<<<grid, 256, 0, s>>>(sc, c, q, cnt, it, img, dbg, dbg_cap, d);
+}
+
+// ---------------------------------------------------------------------------
+// back-propagation over the path tree (Sec. 3.1 "Secondary estimator"):
+//   R(vertex) = sum_t (1/beta_t) sum_s v_s,
+//   v_s = B|cos|/p_t (w_dir,t E' + w_ind,t R')   (continuation samples),
+//   v_s = B|cos|/p_N w_dir,N Le                   (NEE samples, 0 if occluded)
+// summed in the order NEE, BSDF, guided.  Every sample also feeds the cell's
+// moment and cost accumulators (Sec. 4.1 "Local estimates"); continuation
+// samples train the directional histogram of the guided technique.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void accumulate_sample(const CacheDev& c, uint32_t cell, uint32_t tech,
+                                                  f3 v, uint32_t cost) {
+  double* a = c.acc + ((size_t)cell * 3 + tech) * 8;
+  atomicAdd(a + 0, (double)v.x);
+  atomicAdd(a + 1, (double)v.y);
+  atomicAdd(a + 2, (double)v.z);
+  atomicAdd(a + 3, (double)v.x * (double)v.x);
+  atomicAdd(a + 4, (double)v.y * (double)v.y);
+  atomicAdd(a + 5, (double)v.z * (double)v.z);
+  atomicAdd(a + 6, 1.0);
+  atomicAdd(a + 7, (double)cost);
+}
+
+__global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+                                                          const Counters* cnt, IterDev it,
+                                                          ImageDev img, int d) {
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
+  const bool guided = sc.mode == 1;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const float4 v0 = q.V0[L + j];
+    const uint32_t cell = ubits(v0.w);
+    f3 R = mk3(0.0f, 0.0f, 0.0f);
+    uint32_t cost = 0;
+    if (cell != kNoCell) {
+      const uint4 v2 = q.V2[L + j];
+      const float4 b = q.V1[L + j];
+      const f3 T = xyz(q.S0[L + j]);
+      const uint32_t pix = ubits(q.R1[L + j].w);
+      float lim[3] = {INFINITY, INFINITY, INFINITY};
+      if (it.stat_clamp > 0.0f) {
+        const float k = it.stat_clamp;
+        lim[0] = (k * img.itilde[3 * (size_t)pix]) / T.x;
+        lim[1] = (k * img.itilde[3 * (size_t)pix + 1]) / T.y;
+        lim[2] = (k * img.itilde[3 * (size_t)pix + 2]) / T.z;
+      }
+      atomicAdd(c.visits + cell, 1u);
+      for (uint32_t k = 0; k < v2.y; ++k) {
+        const float4 sv = q.SH2[L + v2.x + k];
+        const f3 v = xyz(sv);
+        R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
+        cost += 1;
+        accumulate_sample(c, cell, 1u,
+                          mk3(fminf(v.x, lim[0]), fminf(v.y, lim[1]), fminf(v.z, lim[2])), 1u);
+      }
+      for (uint32_t k = 0; k < v2.w; ++k) {
+        const size_t e = Ln + v2.z + k;
+        const float4 s1 = q.S1[e], s2 = q.S2[e];
+        const uint32_t tech = q.S3[e].z >> 16;
+        f3 v = mk3(0.0f, 0.0f, 0.0f);
+        uint32_t sc_ = 1;
+        if (q.R0[e].w != 0.0f) {
+          const float4 cv = q.V0[e], cr = q.RO[e];
+          v = mk3(s1.x * (cv.x + s1.w * cr.x), s1.y * (cv.y + s1.w * cr.y),
+                  s1.z * (cv.z + s1.w * cr.z));
+          sc_ = 1u + ubits(cr.w);
+          if (guided && s2.y > 0.0f) {
+            f3 E = mk3(0.0f, 0.0f, 0.0f);
+            const uint2 h = q.H[e];
+            const f3 dir = xyz(q.R1[e]);
+            if (h.y != kMiss) {
+              const float* m = sc.mats + 8 * (size_t)sc.tri_mat[h.y];
+              const float cosl = -dot3(dir, xyz(sc.tri_ng[h.y]));
+              if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f))
+                E = mk3(m[5], m[6], m[7]);
+            }
+            const f3 Li = add3(E, xyz(cr));
+            atomicAdd(c.hacc + (size_t)cell * 64 + dir_bin(dir), (double)(lum(Li) / s2.y));
+          }
+        }
+        R = mk3(R.x + v.x / s2.w, R.y + v.y / s2.w, R.z + v.z / s2.w);
+        cost += sc_;
+        accumulate_sample(c, cell, tech,
+                          mk3(fminf(v.x, lim[0]), fminf(v.y, lim[1]), fminf(v.z, lim[2])), sc_);
+      }
+    }
+    q.RO[L + j] = make_float4(R.x, R.y, R.z, fbits(cost));
+    if (d == 1) {
+      const uint32_t root = q.S3[L + j].w;
+      img.Ls[3 * (size_t)root] = v0.x + R.x;
+      img.Ls[3 * (size_t)root + 1] = v0.y + R.y;
+      img.Ls[3 * (size_t)root + 2] = v0.z + R.z;
+    }
+  }
+}
+void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
+                   const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s) {
+  backprop_pt_kernel<<<grid, 256, 0, s>>>(sc, c, q, cnt, it, img, d);
+}
+
+// ---------------------------------------------------------------------------
+// per-pixel sums of the iteration (sample order) and the count map
+// ---------------------------------------------------------------------------
+__global__ void pixel_sums_kernel(ImageDev img, int npx, int spp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npx) return;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+  for (int s = 0; s < spp; ++s) {
+    const size_t r = (size_t)i * spp + s;
+    s0 += img.Ls[3 * r]; s1 += img.Ls[3 * r + 1]; s2 += img.Ls[3 * r + 2];
+    b0 += img.beta1[3 * r]; b1 += img.beta1[3 * r + 1]; b2 += img.beta1[3 * r + 2];
+  }
+  img.iter_sum[3 * (size_t)i] = s0;
+  img.iter_sum[3 * (size_t)i + 1] = s1;
+  img.iter_sum[3 * (size_t)i + 2] = s2;
+  img.count_map[3 * (size_t)i] = b0 / (float)spp;
+  img.count_map[3 * (size_t)i + 1] = b1 / (float)spp;
+  img.count_map[3 * (size_t)i + 2] = b2 / (float)spp;
+}
+void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s) {
+  pixel_sums_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp);
+}
+
+// ---------------------------------------------------------------------------
+// image estimates (Sec. 4.1 "Image estimates", Sec. 5.1):
+//   I~ = 3x3 box filter (edge clamped) of the running mean image, floored
+//   at 1e-3 x the image-mean channel value; V_I = mean over included pixels
+//   of (1/spp) sum_s (1/3) sum_ch ((min(I_s, k I~) - I~) / I~)^2.
+// red[0..2]: image-mean sums, red[3]: V_I sum, red[4]: included pixels,
+// red[5]: inverse-variance weight sum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_add_d(double v, double* dst) {
+  __shared__ double part[16];
+  v = wave_sum_d(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += part[k];
+    atomicAdd(dst, s);
+  }
+  __syncthreads();
+}
+
+__global__ void accum_mean_kernel(ImageDev img, int npx, float tsp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double m[3] = {0.0, 0.0, 0.0};
+  if (i < npx) {
+    for (int ch = 0; ch < 3; ++ch) {
+      const size_t e = 3 * (size_t)i + ch;
+      const float a = img.accum[e] + img.iter_sum[e];
+      img.accum[e] = a;
+      const float mv = a / tsp;
+      img.mean[e] = mv;
+      m[ch] = (double)mv;
+    }
+  }
+  for (int ch = 0; ch < 3; ++ch) block_add_d(m[ch], img.red + ch);
+}
+
+__global__ void itilde_kernel(ImageDev img, int W, int H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int y = i / W, x = i % W;
+  const double npx = (double)W * (double)H;
+  uint8_t ex = 0;
+  for (int ch = 0; ch < 3; ++ch) {
+    const float flo = fmaxf(1e-3f * (float)(img.red[ch] / npx), 1e-6f);
+    float s = 0.0f;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int yy = min(max(y + dy, 0), H - 1), xx = min(max(x + dx, 0), W - 1);
+        s += img.mean[3 * ((size_t)yy * W + xx) + ch];
+      }
+    s = s / 9.0f;
+    if (!(s > flo)) {
+      s = flo;
+      ex = 1;
+    }
+    img.itilde[3 * (size_t)i + ch] = s;
+  }
+  img.excl[i] = ex;
+}
+
+// BDPT: the 10 pixels with the largest iteration luminance leave V_I
+// (Sec. 5.1); ties go to the lower index.  One workgroup, ten passes.
+__global__ void brightest_kernel(ImageDev img, int npx) {
+  __shared__ float bl[1024];
+  __shared__ int bi[1024];
+  for (int k = 0; k < 10 && k < npx; ++k) {
+    float best = -1.0f;
+    int idx = -1;
+    for (int i = threadIdx.x; i < npx; i += blockDim.x) {
+      if (img.excl[i] == 2) continue;
+      const float l = lum(mk3(img.iter_sum[3 * (size_t)i], img.iter_sum[3 * (size_t)i + 1],
+                              img.iter_sum[3 * (size_t)i + 2]));
+      if (l > best) { best = l; idx = i; }
+    }
+    bl[threadIdx.x] = best;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        const float o = bl[threadIdx.x + s];
+        const int oi = bi[threadIdx.x + s];
+        if (o > bl[threadIdx.x] || (o == bl[threadIdx.x] && oi >= 0 &&
+                                    (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
+          bl[threadIdx.x] = o;
+          bi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && bi[0] >= 0) img.excl[bi[0]] = 2;
+    __syncthreads();
+  }
+}
+
+__global__ void vi_kernel(ImageDev img, int npx, int spp, float kc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0, inc = 0.0;
+  if (i < npx && img.excl[i] == 0) {
+    const float* It = img.itilde + 3 * (size_t)i;
+    for (int s = 0; s < spp; ++s) {
+      const float* l = img.Ls + 3 * ((size_t)i * spp + s);
+      float dd[3];
+      for (int ch = 0; ch < 3; ++ch) {
+        const float xv = kc > 0.0f ? fminf(l[ch], kc * It[ch]) : l[ch];
+        dd[ch] = (xv - It[ch]) / It[ch];
+      }
+      e += (double)((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+    }
+    e = e / (3.0 * (double)spp);
+    inc = 1.0;
+  }
+  block_add_d(e, img.red + 3);
+  block_add_d(inc, img.red + 4);
+}
+
+void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
+                    float stat_clamp, hipStream_t s) {
+  const int npx = W * H;
+  k_fill_f64(img.red, 0.0, 5, s);
+  accum_mean_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, total_spp);
+  itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H);
+  if (bdpt) brightest_kernel<<<1, 1024, 0, s>>>(img, npx);
+  vi_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, stat_clamp);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-point update (Sec. 3.1 "Optimization", supplement A.3): per cell and
+// technique with samples, in binary64,
+//   a^RR = C_I / (C_t V_I) E[v^2],  a^S = C_I / (C_t V_I) V[v]   per channel
+// ---------------------------------------------------------------------------
+__global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const double* red,
+                                   double C_I, int use_dev, double V_host) {
+  const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cidx >= *n_cells_dev) return;
+  const double V_I = use_dev ? (red[4] > 0.0 ? red[3] / red[4] : 0.0) : V_host;
+  if (!(V_I > 0.0) || !(C_I > 0.0)) return;
+  for (int t = 0; t < 3; ++t) {
+    const double* a = c.acc + ((size_t)cidx * 3 + t) * 8;
+    const double n = a[6];
+    if (!(n > 0.0)) continue;
+    const double Ct = a[7] / n;
+    if (!(Ct > 0.0)) continue;
+    const double k = C_I / (Ct * V_I);
+    for (int ch = 0; ch < 3; ++ch) {
+      const double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+      double var = E2 - E1 * E1;
+      if (var < 0.0) var = 0.0;
+      c.fac[(size_t)cidx * 18 + (0 * 3 + t) * 3 + ch] = (float)(k * E2);
+      c.fac[(size_t)cidx * 18 + (1 * 3 + t) * 3 + ch] = (float)(k * var);
+    }
+  }
+}
+void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
+                   int use_device_vi, double V_I_host, int max_cells, hipStream_t s) {
+  fixed_point_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, red, C_I,
+                                                               use_device_vi, V_I_host);
+}
+
+// guided distribution of the next iteration: 0.9 learned + 0.1 uniform
+__global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev) {
+  const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cidx >= *n_cells_dev) return;
+  const double* h = c.hacc + 64 * (size_t)cidx;
+  double tot = 0.0;
+  for (int b = 0; b < 64; ++b) tot += h[b];
+  if (!(tot > 0.0)) return;
+  double run = 0.0;
+  for (int b = 0; b < 64; ++b) {
+    const double p = 0.9 * (h[b] / tot) + 0.1 / 64.0;
+    run += p;
+    c.pm[64 * (size_t)cidx + b] = (float)p;
+    c.cdf[64 * (size_t)cidx + b] = b == 63 ? 1.0f : (float)run;
+  }
+}
+void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells, hipStream_t s) {
+  hist_normalize_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev);
+}
+
+// ---------------------------------------------------------------------------
+// octree refinement: leaves with more than split_visits visits and depth
+// below the maximum split, in increasing leaf order, while the leaf budget
+// allows.  flags -> one-workgroup exclusive scan -> apply.
+// ---------------------------------------------------------------------------
+__global__ void split_flags_kernel(CacheDev c, const int32_t* n_cells_dev, uint32_t* flags,
+                                   int split_visits, int max_tree_depth) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= *n_cells_dev) return;
+  flags[l] = (c.visits[l] > (uint32_t)split_visits && c.leaf_depth[l] < (uint32_t)max_tree_depth)
+                 ? 1u : 0u;
+}
+__global__ void scan_flags_kernel(const int32_t* n_cells_dev, uint32_t* flags, uint32_t* total) {
+  __shared__ uint32_t part[1024];
+  const int n = *n_cells_dev;
+  const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int b = threadIdx.x * chunk, e = min(n, b + chunk);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += flags[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const uint32_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    const uint32_t f = flags[i];
+    flags[i] = f ? run : 0xFFFFFFFFu;  // rank of flagged leaves, sentinel otherwise
+    run += f;
+  }
+  if (threadIdx.x == blockDim.x - 1) *total = part[threadIdx.x];
+}
+__global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
+                                   const int32_t* n_nodes_dev, const uint32_t* rank,
+                                   const uint32_t* total, int max_cells) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n0 = *n_cells_dev, nn0 = *n_nodes_dev;
+  if (l >= n0) return;
+  const uint32_t r = rank[l];
+  if (r == 0xFFFFFFFFu) return;
+  const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
+  const uint32_t acc = min(*total, room);
+  if (r >= acc) return;
+  const uint32_t node = c.leaf_node[l];
+  const uint32_t base = (uint32_t)nn0 + 8u * r;
+  c.nodes[node] = base;
+  const uint32_t dep = c.leaf_depth[l] + 1u;
+  for (int ch = 0; ch < 8; ++ch) {
+    const uint32_t id = ch == 0 ? (uint32_t)l : (uint32_t)n0 + 7u * r + (uint32_t)(ch - 1);
+    c.nodes[base + ch] = kLeafBit | id;
+    c.leaf_node[id] = base + ch;
+    c.leaf_depth[id] = dep;
+    if (ch) {
+      for (int k = 0; k < 18; ++k) c.fac[(size_t)id * 18 + k] = c.fac[(size_t)l * 18 + k];
+      for (int k = 0; k < 64; ++k) {
+        c.pm[(size_t)id * 64 + k] = c.pm[(size_t)l * 64 + k];
+        c.cdf[(size_t)id * 64 + k] = c.cdf[(size_t)l * 64 + k];
+      }
+    }
+  }
+}
+__global__ void finish_split_kernel(int32_t* n_cells_dev, int32_t* n_nodes_dev,
+                                    const uint32_t* total, int max_cells) {
+  const int n0 = *n_cells_dev;
+  const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
+  const uint32_t acc = min(*total, room);
+  *n_cells_dev = n0 + 7 * (int)acc;
+  *n_nodes_dev = *n_nodes_dev + 8 * (int)acc;
+}
+void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
+              int split_visits, int max_tree_depth, int max_cells, hipStream_t s) {
+  const int g = (max_cells + 255) / 256;
+  split_flags_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, scratch, split_visits, max_tree_depth);
+  scan_flags_kernel<<<1, 1024, 0, s>>>(n_cells_dev, scratch, scratch + max_cells);
+  apply_split_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch, scratch + max_cells,
+                                       max_cells);
+  finish_split_kernel<<<1, 1, 0, s>>>(n_cells_dev, n_nodes_dev, scratch + max_cells, max_cells);
+}
+
+// inverse-variance weighted combination of the iterations (Sec. 5.1)
+__global__ void ivw_kernel(ImageDev img, int npx, int spp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double V_I = img.red[4] > 0.0 ? img.red[3] / img.red[4] : 0.0;
+  if (!(V_I > 0.0)) return;
+  const double w = (double)spp / V_I;
+  if (i == 0) img.red[5] += w;
+  if (i >= npx) return;
+  for (int ch = 0; ch < 3; ++ch) {
+    const size_t e = 3 * (size_t)i + ch;
+    img.ivw_acc[e] += w * (double)(img.iter_sum[e] / (float)spp);
+  }
+}
+void k_ivw(const ImageDev& img, int npx, int spp, hipStream_t s) {
+  ivw_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp);
+}
+
+// ---------------------------------------------------------------------------
+// probes of the building blocks (tests)
+// ---------------------------------------------------------------------------
+__global__ void probe_kernel(int kind, int n, const void* in, void* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (kind == 0) {
+    const uint32_t* a = (const uint32_t*)in + 6 * (size_t)i;
+    const u4 o = philox10(a[0], a[1], u4{a[2], a[3], a[4], a[5]});
+    uint32_t* b = (uint32_t*)out + 4 * (size_t)i;
+    b[0] = o.a; b[1] = o.b; b[2] = o.c; b[3] = o.d;
+  } else if (kind == 1) {
+    float s, c;
+    sincos_turns(((const float*)in)[i], &s, &c);
+    ((float*)out)[2 * (size_t)i] = s;
+    ((float*)out)[2 * (size_t)i + 1] = c;
+  } else if (kind == 2) {
+    const float* a = (const float*)in + 4 * (size_t)i;
+    const float beta[3] = {a[0], a[1], a[2]};
+    uint32_t g[3];
+    round_counts(beta, a[3], g);
+    uint32_t* b = (uint32_t*)out + 3 * (size_t)i;
+    b[0] = g[0]; b[1] = g[1]; b[2] = g[2];
+  }
+}
+void k_probe(int kind, int n, const void* in, void* out, hipStream_t s) {
+  probe_kernel<<<(n + 255) / 256, 256, 0, s>>>(kind, n, in, out);
+}
+
+}  // namespace mars

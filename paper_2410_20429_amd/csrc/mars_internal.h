@@ -1,0 +1,132 @@
+// Internal layout shared by the host orchestration and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mars {
+
+constexpr uint32_t kLeafBit = 0x80000000u;  // octree node word: leaf flag | leaf id
+constexpr int kMaxDepth = 16;       // maximum path segments supported
+constexpr int kTraceBlock = 128;    // threads per traversal workgroup
+constexpr int kStackDepth = 32;     // per-lane LDS traversal stack (BVH depth <= 31)
+
+// scene on the device (read-only during an iteration)
+struct SceneDev {
+  const float4* bvh;       // [n_nodes][4]: two child boxes + child references
+  const float4* tri_bvh;   // [n_tris][3] leaf order: (v0, prim bits), (e1, 0), (e2, 0)
+  const float4* tri_geo;   // [n_tris][3] primitive order: v0, e1, e2
+  const float4* tri_ng;    // [n_tris] primitive order: (geometric normal, p_select / area)
+  const uint32_t* tri_mat; // [n_tris]
+  const float* mats;       // [n_mats][8]
+  const int32_t* light_tri;
+  const float* light_cdf;
+  int32_t n_lights, n_tris;
+  float cam_o[3], cam_f[3], cam_r[3], cam_u[3];
+  int32_t W, H;
+  float eps;
+  float oct_lo[3];
+  float oct_inv;
+  int32_t mode, max_depth, nee;
+  uint32_t key0, key1;
+};
+
+// spatial cache (octree leaves = cells)
+struct CacheDev {
+  uint32_t* nodes;       // [1 + 8 max_cells]
+  uint32_t* leaf_node;   // [max_cells]
+  uint32_t* leaf_depth;  // [max_cells]
+  uint32_t* visits;      // [max_cells]
+  float* fac;            // [max_cells][2][3][3]  a^RR, a^S per technique and channel
+  double* acc;           // [max_cells][3][8]     sum v (3), sum v^2 (3), n, cost
+  float* pm;             // [max_cells][64]       directional pmf (guided)
+  float* cdf;            // [max_cells][64]
+  double* hacc;          // [max_cells][64]       directional training sums
+  const float* fixed;    // [n_fixed][3]
+  int32_t n_fixed;
+  int32_t max_cells;
+};
+
+// per-depth SoA queues; entry (d, j) lives at d * cap + j
+struct QueuesDev {
+  float4* R0;   // origin, flags (1 = traced)
+  float4* R1;   // direction, pixel (bits)
+  float4* S0;   // prefix throughput T, parent index (bits)
+  float4* S1;   // B|cos|/p_t (rgb), w_ind
+  float4* S2;   // beta_t p_t, sum_{B,G} beta p, beta_N, beta_t   (parent's MIS data)
+  uint4* S3;    // stream lo/hi, tech << 16 | k, root
+  uint2* H;     // hit: t (bits), primitive
+  float4* V0;   // weighted emission for the parent's direct term, cell (bits)
+  float4* V1;   // beta_B, beta_N, beta_third, unused
+  uint4* V2;    // NEE first, NEE count, continuation first, continuation count
+  float4* RO;   // back-propagated secondary estimate, subtree cost (bits)
+  float4* SH0;  // shadow origin, tmax
+  float4* SH1;  // shadow direction, parent vertex (bits)
+  float4* SH2;  // unoccluded NEE sample value, flags (1 = traced)
+  size_t cap;   // entries per depth (rays and shadow rays each)
+};
+
+struct Counters {
+  uint32_t n_ray[kMaxDepth + 2];
+  uint32_t n_shadow[kMaxDepth + 2];
+  uint32_t overflow;
+  uint32_t n_debug;
+  unsigned long long rays_ext, rays_shadow, vertices, samples;
+};
+
+struct IterDev {
+  int32_t iteration, spp, alloc, aware, rr_start, fixed_scale;
+  float clamp_lo, clamp_hi, stat_clamp;
+  int32_t center_jitter, debug_depth, lp_stride;
+};
+
+struct DebugRec {
+  uint32_t root, depth, stream_lo, stream_hi, cell;
+  float beta[3];
+  uint32_t gamma[3];
+  float T[3];
+};
+
+// per-iteration image buffers
+struct ImageDev {
+  float* Ls;        // [roots][3] camera-sample radiance of the iteration
+  float* beta1;     // [roots][3] counts at the first hit
+  float* iter_sum;  // [px][3]
+  float* accum;     // [px][3]
+  float* mean;      // [px][3] scratch
+  float* itilde;    // [px][3]
+  uint8_t* excl;    // [px]
+  double* ivw_acc;  // [px][3]
+  float* count_map; // [px][3]
+  double* red;      // [8] reductions: image mean rgb, V_I sum, included count, ...
+};
+
+// ---- launchers (kernels.hip) ----
+void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void k_fill_f64(double* p, double v, size_t n, hipStream_t s);
+void k_fill_f32(float* p, float v, size_t n, hipStream_t s);
+void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterDev& it,
+              uint32_t root0, uint32_t n_roots, hipStream_t s);
+// tc (optional): traversal counters {rays, nodes, triangles} of closest-hit
+// rays at tc[0..2] and of shadow rays at tc[3..5]
+void k_trace_closest(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d,
+                     int grid, hipStream_t s, unsigned long long* tc);
+void k_trace_any(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
+                 hipStream_t s, unsigned long long* tc);
+void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
+                const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
+                int grid, hipStream_t s);
+void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
+                   const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s);
+void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s);
+void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
+                    float stat_clamp, hipStream_t s);
+void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
+                   int use_device_vi, double V_I_host, int max_cells, hipStream_t s);
+void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells, hipStream_t s);
+void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
+              int split_visits, int max_tree_depth, int max_cells, hipStream_t s);
+void k_ivw(const ImageDev& img, int npx, int spp, hipStream_t s);
+void k_probe(int kind, int n, const void* in, void* out, hipStream_t s);
+
+}  // namespace mars

@@ -256,6 +256,7 @@ def test_octree_lookup_and_refine():
     inv = np.float32(1.0 / side)
     rng = np.random.default_rng(0)
     P = rng.uniform(-0.05, 1.05, (3000, 3)).astype(np.float32)
+    leaf_depth = o.cells()["depth"]
     for p in P:
         cell, d = o.octree_lookup(p)
         q = np.clip((p - olo) * inv, 0, np.float32(1 - 2 ** -24)).astype(np.float64)
@@ -267,6 +268,7 @@ def test_octree_lookup_and_refine():
             node = int(nodes[node]) + int(child)
             depth += 1
         assert (nodes[node] & 0x7FFFFFFF) == cell and depth == d
+        assert leaf_depth[cell] == d  # recorded depth of the leaf = its depth in the tree
 
 
 # ---------------------------------------------------------------------------
