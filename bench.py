@@ -94,7 +94,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=-1,
-                    help="(profiling runs) total iterations to run, no extras")
+                    help="(profiling runs) skip the instrumented iteration and the CPU leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
@@ -118,6 +120,14 @@ def main():
         us = s.update(p)
         return st, us
 
+    if args.copy_calib:
+        # plain copy of known size: 1 GiB read + 1 GiB written
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        torch.cuda.synchronize()
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
     for i in range(args.warmup):
         step(i)
         print(f"[bench] warmup {i}", file=sys.stderr, flush=True)

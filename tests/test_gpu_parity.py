@@ -369,7 +369,8 @@ def test_edge_cases(ctx):
     s.render_iteration(api.iter_params(spp=2))
     assert np.all(s.sample_radiance() == 0)
     # single triangle (the BVH is one leaf)
-    tri = {"V": np.array([[-1, -1, 2, 1, -1, 2, 0, 1, 2]], np.float32),
+    # winding normal (v1-v0)x(v2-v0) points at the camera, so the emitter is seen
+    tri = {"V": np.array([[-1, -1, 2, 0, 1, 2, 1, -1, 2]], np.float32),
            "tri_mat": np.array([0], np.uint32),
            "mats": np.array([[0, .5, .5, .5, 0, 2, 2, 2]], np.float32),
            "camera": np.array([0, 0, 0, 0, 0, 1, 0, 1, 0, 60], np.float32),
