@@ -562,31 +562,72 @@ void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Count
 // moment and cost accumulators (Sec. 4.1 "Local estimates"); continuation
 // samples train the directional histogram of the guided technique.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void accumulate_sample(const CacheDev& c, uint32_t cell, uint32_t tech,
-                                                  f3 v, uint32_t cost) {
-  double* a = c.acc + ((size_t)cell * 3 + tech) * 8;
-  atomicAdd(a + 0, (double)v.x);
-  atomicAdd(a + 1, (double)v.y);
-  atomicAdd(a + 2, (double)v.z);
-  atomicAdd(a + 3, (double)v.x * (double)v.x);
-  atomicAdd(a + 4, (double)v.y * (double)v.y);
-  atomicAdd(a + 5, (double)v.z * (double)v.z);
-  atomicAdd(a + 6, 1.0);
-  atomicAdd(a + 7, (double)cost);
+// Cell statistics are first summed per vertex (all samples of a vertex fall
+// in its cell), then merged per workgroup in an LDS hash table keyed by
+// (cell, technique), and flushed with one set of global binary64 atomics per
+// table slot.  A workgroup walks a contiguous range of the queue, so
+// neighbouring vertices (often in the same cell) share slots; keys that find
+// no slot within a few probes go straight to global memory.
+constexpr int kAggSlots = 128;
+constexpr int kAggVals = 9;  // sum v (3), sum v^2 (3), n, cost, visits
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+
+struct AggTable {
+  uint32_t key[kAggSlots];
+  double val[kAggSlots][kAggVals];
+};
+
+__device__ __forceinline__ void global_add_stats(const CacheDev& c, uint32_t key, const double* v) {
+  const uint32_t cell = key >> 2, t = key & 3u;
+  double* a = c.acc + ((size_t)cell * 3 + t) * 8;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (v[i] != 0.0) atomicAdd(a + i, v[i]);
+  if (v[8] != 0.0) atomicAdd(c.visits + cell, (uint32_t)v[8]);
+}
+
+__device__ __forceinline__ void agg_add(AggTable& A, const CacheDev& c, uint32_t key,
+                                        const double* v) {
+  uint32_t h = (key * 2654435761u) >> 25;  // 7 bits
+#pragma unroll 1
+  for (int probe = 0; probe < 8; ++probe) {
+    const uint32_t prev = atomicCAS(&A.key[h], kAggEmpty, key);
+    if (prev == kAggEmpty || prev == key) {
+#pragma unroll
+      for (int i = 0; i < kAggVals; ++i)
+        if (v[i] != 0.0) atomicAdd(&A.val[h][i], v[i]);
+      return;
+    }
+    h = (h + 1) & (kAggSlots - 1);
+  }
+  global_add_stats(c, key, v);
 }
 
 __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                           const Counters* cnt, IterDev it,
                                                           ImageDev img, int d) {
+  __shared__ AggTable A;
+  for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
+    A.key[k] = kAggEmpty;
+    for (int i = 0; i < kAggVals; ++i) A.val[k][i] = 0.0;
+  }
+  __syncthreads();
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
   const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
   const bool guided = sc.mode == 1;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+  const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t j0 = blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     const float4 v0 = q.V0[L + j];
     const uint32_t cell = ubits(v0.w);
     f3 R = mk3(0.0f, 0.0f, 0.0f);
     uint32_t cost = 0;
     if (cell != kNoCell) {
+      double st[3][8];
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) st[t][i] = 0.0;
       const uint4 v2 = q.V2[L + j];
       const float4 b = q.V1[L + j];
       const f3 T = xyz(q.S0[L + j]);
@@ -598,14 +639,18 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
         lim[1] = (k * img.itilde[3 * (size_t)pix + 1]) / T.y;
         lim[2] = (k * img.itilde[3 * (size_t)pix + 2]) / T.z;
       }
-      atomicAdd(c.visits + cell, 1u);
+      auto record = [&](int t, f3 v, uint32_t cst) {
+        const double x0 = (double)fminf(v.x, lim[0]), x1 = (double)fminf(v.y, lim[1]),
+                     x2 = (double)fminf(v.z, lim[2]);
+        st[t][0] += x0; st[t][1] += x1; st[t][2] += x2;
+        st[t][3] += x0 * x0; st[t][4] += x1 * x1; st[t][5] += x2 * x2;
+        st[t][6] += 1.0; st[t][7] += (double)cst;
+      };
       for (uint32_t k = 0; k < v2.y; ++k) {
-        const float4 sv = q.SH2[L + v2.x + k];
-        const f3 v = xyz(sv);
+        const f3 v = xyz(q.SH2[L + v2.x + k]);
         R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
         cost += 1;
-        accumulate_sample(c, cell, 1u,
-                          mk3(fminf(v.x, lim[0]), fminf(v.y, lim[1]), fminf(v.z, lim[2])), 1u);
+        record(1, v, 1u);
       }
       for (uint32_t k = 0; k < v2.w; ++k) {
         const size_t e = Ln + v2.z + k;
@@ -634,8 +679,16 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
         }
         R = mk3(R.x + v.x / s2.w, R.y + v.y / s2.w, R.z + v.z / s2.w);
         cost += sc_;
-        accumulate_sample(c, cell, tech,
-                          mk3(fminf(v.x, lim[0]), fminf(v.y, lim[1]), fminf(v.z, lim[2])), sc_);
+        record(tech == 0 ? 0 : 2, v, sc_);
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t != 0 && st[t][6] == 0.0) continue;
+        double vals[kAggVals];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vals[i] = st[t][i];
+        vals[8] = t == 0 ? 1.0 : 0.0;
+        agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
       }
     }
     q.RO[L + j] = make_float4(R.x, R.y, R.z, fbits(cost));
@@ -645,6 +698,13 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
       img.Ls[3 * (size_t)root + 1] = v0.y + R.y;
       img.Ls[3 * (size_t)root + 2] = v0.z + R.z;
     }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
+    if (A.key[k] == kAggEmpty) continue;
+    double vals[kAggVals];
+    for (int i = 0; i < kAggVals; ++i) vals[i] = A.val[k][i];
+    global_add_stats(c, A.key[k], vals);
   }
 }
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
