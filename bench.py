@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "guided_pt_512x512_heightfield132k_d10"
 BYTES_RAY_IO = 48.0      # ray 32 B in (origin, direction) + hit 16 B out
+BYTES_SHADOW_IO = 36.0   # shadow ray 32 B in (origin + tmax, direction) + 4 B visibility out
 BYTES_NODE = 64.0        # one BVH node (two child boxes + references)
 BYTES_TRI = 48.0         # one triangle record (v0, e1, e2)
 
@@ -38,10 +39,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(per_launch_rays):
-    """HBM bytes per launch of trace_closest from the committed rocprofv3
+def load_traffic(bytes_per_launch):
+    """HBM bytes per launch of the traversal kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "trace_closest_guided512_traffic.json")
+    path = os.path.join(ROOT, "profiles", "trace_guided512_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -135,11 +136,12 @@ def main():
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rays = rays_closest = 0
+    rays = rays_closest = rays_shadow = 0
     for k in range(args.steps):
         st, us = step(args.warmup + k)
         rays += st.total_rays()
         rays_closest += st.rays_camera + st.rays_ext
+        rays_shadow += st.rays_shadow
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_read()
@@ -171,19 +173,22 @@ def main():
         st, _ = step(args.warmup + args.steps)
         tc = ctx.trace_counts()
         ctx.trace_counting(False)
-        rays_i, nodes_i, tris_i = tc[0], tc[1], tc[2]
-        bytes_per_ray = BYTES_RAY_IO + (BYTES_NODE * nodes_i + BYTES_TRI * tris_i) / max(rays_i, 1)
-        ms_tc, n_tc = prof["trace_closest"]
-        avg_ms = ms_tc / max(n_tc, 1)
-        rays_per_launch = rays_closest / max(n_tc, 1)
-        achieved = bytes_per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(rays_per_launch)
+        # per ray: I/O plus one 64 B node per visited node and 48 B per tested triangle
+        bpr_c = BYTES_RAY_IO + (BYTES_NODE * tc[1] + BYTES_TRI * tc[2]) / max(tc[0], 1)
+        bpr_s = BYTES_SHADOW_IO + (BYTES_NODE * tc[4] + BYTES_TRI * tc[5]) / max(tc[3], 1)
+        ms_tr, n_tr = prof["trace"]
+        avg_ms = ms_tr / max(n_tr, 1)
+        bytes_per_launch = (bpr_c * rays_closest + bpr_s * rays_shadow) / max(n_tr, 1)
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = load_traffic(bytes_per_launch)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "trace_closest", "avg_launch_ms": avg_ms,
-                           "bytes_per_ray": bytes_per_ray,
-                           "nodes_per_ray": nodes_i / max(rays_i, 1),
-                           "tris_per_ray": tris_i / max(rays_i, 1)}
+                           "kernel": "trace", "avg_launch_ms": avg_ms,
+                           "algorithmic_bytes_per_launch": bytes_per_launch,
+                           "bytes_per_closest_ray": bpr_c, "bytes_per_shadow_ray": bpr_s,
+                           "nodes_per_closest_ray": tc[1] / max(tc[0], 1),
+                           "tris_per_closest_ray": tc[2] / max(tc[0], 1),
+                           "nodes_per_shadow_ray": tc[4] / max(tc[3], 1)}
         if not args.no_cpu_baseline:
             print("[bench] cpu baseline", file=sys.stderr, flush=True)
             out["cpu_baseline"] = cpu_baseline(sc)

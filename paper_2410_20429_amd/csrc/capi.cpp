@@ -72,12 +72,12 @@ struct Scene {
 
 // per-kernel HIP-event timing on the context's stream
 enum KernelId {
-  KID_RAYGEN, KID_TRACE_CLOSEST, KID_SHADE, KID_TRACE_ANY, KID_BACKPROP, KID_PIXEL_SUMS,
-  KID_UPDATE_IMAGE, KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_COUNT
+  KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
+  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
-    "raygen", "trace_closest", "shade", "trace_any", "backprop", "pixel_sums",
-    "update_image", "fixed_point", "hist_normalize", "refine", "ivw"};
+    "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
+    "fixed_point", "hist_normalize", "refine", "ivw"};
 
 struct Profiler {
   bool on = false;
@@ -243,18 +243,21 @@ void ensure_roots(Scene* s, size_t roots) {
 bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t dbg0,
               Counters* hc) {
   hipStream_t st = s->ctx->stream;
-  const int grid_trace = s->ctx->cu * 8, grid = s->ctx->cu * 8;
+  // traversal: 128-thread groups, LDS-limited to 10 per CU; others 256-thread groups
+  const int grid_trace = s->ctx->cu * 10, grid = s->ctx->cu * 8;
   Ctx* c = s->ctx;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   if (dbg0) h2d(&s->cnt->n_debug, &dbg0, 4, st);  // debug records accumulate across tiles
   timed(c, KID_RAYGEN, [&] { k_raygen(s->sd, s->qd, s->cnt, it, root0, n, st); });
+  timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc); });
   for (int d = 1; d <= s->max_depth; ++d) {
-    timed(c, KID_TRACE_CLOSEST, [&] { k_trace_closest(s->sd, s->qd, s->cnt, d, grid_trace, st, tc); });
     timed(c, KID_SHADE, [&] {
       k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
     });
-    timed(c, KID_TRACE_ANY, [&] { k_trace_any(s->sd, s->qd, s->cnt, d, grid_trace, st, tc); });
+    // shadow rays of depth d with the continuation rays of depth d + 1
+    const int dc = d < s->max_depth ? d + 1 : 0;
+    timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc); });
   }
   d2h(hc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));

@@ -220,61 +220,52 @@ __device__ __forceinline__ void add_counts(unsigned long long* tc, uint32_t rays
   }
 }
 
+// Shadow rays of depth d and continuation rays of depth d+1 both come out of
+// shade(d) and are independent, so one launch traverses both queues (closest
+// hits first, then any hits); this halves the number of tail-bound launches.
 template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void trace_closest_kernel(SceneDev sc, QueuesDev q,
-                                                                    const Counters* cnt, int d,
-                                                                    unsigned long long* tc) {
-  __shared__ int stk[kStackDepth * kTraceBlock];
-  if (cnt->overflow) return;  // the tile is re-run; queue contents past capacity are not valid
-  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
-  const size_t L = (size_t)d * q.cap;
-  uint32_t nr = 0, nn = 0, nt = 0;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const float4 r0 = q.R0[L + j];
-    uint2 h = make_uint2(ubits(INFINITY), kMiss);
-    if (r0.w != 0.0f) {
-      const float4 r1 = q.R1[L + j];
-      float t;
-      uint32_t p;
-      if (kCount) ++nr;
-      if (traverse<false, kCount>(sc, xyz(r0), xyz(r1), INFINITY, stk, &t, &p, &nn, &nt))
-        h = make_uint2(ubits(t), p);
-    }
-    q.H[L + j] = h;
-  }
-  if (kCount) add_counts(tc, nr, nn, nt);
-}
-void k_trace_closest(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
-                     hipStream_t s, unsigned long long* tc) {
-  if (tc) trace_closest_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, tc);
-  else trace_closest_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, nullptr);
-}
-
-template <bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void trace_any_kernel(SceneDev sc, QueuesDev q,
-                                                                const Counters* cnt, int d,
-                                                                unsigned long long* tc) {
+__global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, QueuesDev q,
+                                                                 const Counters* cnt, int dc,
+                                                                 int ds, unsigned long long* tc) {
   __shared__ int stk[kStackDepth * kTraceBlock];
   if (cnt->overflow) return;
-  const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
-  const size_t L = (size_t)d * q.cap;
-  uint32_t nr = 0, nn = 0, nt = 0;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const float4 v = q.SH2[L + j];
-    if (v.w == 0.0f) continue;
-    const float4 a = q.SH0[L + j], b = q.SH1[L + j];
+  const uint32_t nc = dc > 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
+  const size_t Lc = (size_t)dc * q.cap, Ls = (size_t)ds * q.cap;
+  uint32_t cr = 0, cn = 0, ct = 0, sr = 0, sn = 0, st = 0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nc + ns;
+       j += gridDim.x * blockDim.x) {
     float t;
     uint32_t p;
-    if (kCount) ++nr;
-    if (traverse<true, kCount>(sc, xyz(a), xyz(b), a.w, stk, &t, &p, &nn, &nt))
-      q.SH2[L + j] = make_float4(0.0f, 0.0f, 0.0f, v.w);
+    if (j < nc) {
+      const float4 r0 = q.R0[Lc + j];
+      uint2 h = make_uint2(ubits(INFINITY), kMiss);
+      if (r0.w != 0.0f) {
+        const float4 r1 = q.R1[Lc + j];
+        if (kCount) ++cr;
+        if (traverse<false, kCount>(sc, xyz(r0), xyz(r1), INFINITY, stk, &t, &p, &cn, &ct))
+          h = make_uint2(ubits(t), p);
+      }
+      q.H[Lc + j] = h;
+    } else {
+      const uint32_t k = j - nc;
+      const float4 v = q.SH2[Ls + k];
+      if (v.w == 0.0f) continue;
+      const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
+      if (kCount) ++sr;
+      if (traverse<true, kCount>(sc, xyz(a), xyz(b), a.w, stk, &t, &p, &sn, &st))
+        q.SH2[Ls + k] = make_float4(0.0f, 0.0f, 0.0f, v.w);
+    }
   }
-  if (kCount) add_counts(tc + 3, nr, nn, nt);
+  if (kCount) {
+    add_counts(tc, cr, cn, ct);
+    add_counts(tc + 3, sr, sn, st);
+  }
 }
-void k_trace_any(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
-                 hipStream_t s, unsigned long long* tc) {
-  if (tc) trace_any_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, tc);
-  else trace_any_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, d, nullptr);
+void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
+                  int grid, hipStream_t s, unsigned long long* tc) {
+  if (tc) trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
+  else trace_pair_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -107,12 +107,11 @@ void k_fill_f64(double* p, double v, size_t n, hipStream_t s);
 void k_fill_f32(float* p, float v, size_t n, hipStream_t s);
 void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterDev& it,
               uint32_t root0, uint32_t n_roots, hipStream_t s);
-// tc (optional): traversal counters {rays, nodes, triangles} of closest-hit
-// rays at tc[0..2] and of shadow rays at tc[3..5]
-void k_trace_closest(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d,
-                     int grid, hipStream_t s, unsigned long long* tc);
-void k_trace_any(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int d, int grid,
-                 hipStream_t s, unsigned long long* tc);
+// traverses the closest-hit queue of depth dc and the shadow queue of depth
+// ds in one launch (0 = none).  tc (optional): traversal counters {rays,
+// nodes, triangles} of closest-hit rays at tc[0..2], shadow rays at tc[3..5]
+void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
+                  int grid, hipStream_t s, unsigned long long* tc);
 void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s);
