@@ -242,6 +242,8 @@ struct oracle {
   /* debug */
   orc_vertex_rec* dbg; int32_t ndbg;
   unsigned char* pix_mask; /* optional: render only these pixels */
+  /* BDPT light subpaths of the current iteration (one per camera sample) */
+  struct lightpath* lpaths; size_t nlpaths;
 };
 
 /* ---- median-split BVH over triangle indices (oracle's own, simple) ---- */
@@ -738,7 +740,7 @@ void orc_destroy(oracle* o) {
   free(o->nodes); free(o->leaf_node); free(o->leaf_depth); free(o->visits); free(o->fac);
   free(o->acc); free(o->pm); free(o->cdf); free(o->hacc); free(o->fixed_beta); free(o->Ls);
   free(o->iter_sum); free(o->accum); free(o->Itilde); free(o->ivw_acc); free(o->count_map);
-  free(o->beta1); free(o->dbg); free(o->pix_mask);
+  free(o->beta1); free(o->dbg); free(o->pix_mask); free(o->lpaths);
   free(o);
 }
 
@@ -1041,7 +1043,9 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
 }
 
 /* bidirectional variant (Sec. 5): defined further below */
+typedef struct lightpath lightpath;
 static void bdpt_root(tctx* c, v3* I);
+static void build_light_paths(oracle* o, const orc_iter_params* p, key_t2 key, rowlog* logs);
 
 /* ------------------------------------------------------------------------ */
 /* one rendering iteration over all pixels (Sec. 4.1 "Fixed-point          */
@@ -1068,6 +1072,7 @@ int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats
   rowlog* logs = calloc(H, sizeof(rowlog));
   key_t2 key = {(uint32_t)o->cfg.seed, (uint32_t)(o->cfg.seed >> 32)};
   int bdpt = o->cfg.mode == ORC_MODE_BDPT;
+  if (bdpt) build_light_paths(o, p, key, logs);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t py = 0; py < H; ++py) {
     tctx c;
@@ -1403,9 +1408,411 @@ void orc_set_hist(oracle* o, int32_t n, const float* pm, const float* cdf) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* BDPT (Sec. 5) -- placeholder until the bidirectional oracle is written   */
+/* Bidirectional path tracing (Sec. 5).  Techniques at every camera vertex: */
+/* BSDF continuation, NEE, and light-path connections (LP), each with its   */
+/* own count.  One light subpath per camera sample, throughput RR only     */
+/* (Sec. 5: no splitting on the light side).  LP sample j connects to the  */
+/* light subpath (root + j * stride) mod N and to every light vertex y_i,  */
+/* i >= 1, with total path length <= D.  MIS: balance heuristic over the   */
+/* strategies (s, t), t >= 2, of the full path; the budget-aware form     */
+/* weights strategy (s, t) by the expected number of its samples,          */
+/* n = prod_{j<=t-2} beta_B(z_j) * beta_tech(s)(z_{t-1}).  The weight is a  */
+/* function of the path's vertices only: every vertex's counts (also those */
+/* on the light side) come from the same formula with the throughput of    */
+/* the camera prefix computed from vertex positions.                       */
 /* ------------------------------------------------------------------------ */
+#define BD_MAXK 34
+typedef struct {
+  v3 P, ng;
+  const float* m;
+  float lpdf;
+} pvert;
+
+struct lightpath {
+  int len;            /* number of vertices y_1..y_len stored (y_0 separately) */
+  int rays;           /* rays traced for this light subpath */
+  pvert y0;
+  pvert y[BD_MAXK];
+  v3 wo[BD_MAXK];     /* direction from y_i towards y_{i-1} */
+  v3 alpha[BD_MAXK];  /* light-subpath throughput arriving at y_i */
+};
+
+static inline v3 dir_between(v3 a, v3 b, float* d2) {
+  v3 dv = vsub(b, a);
+  *d2 = vdot(dv, dv);
+  float dist = sqrtf(*d2);
+  return vscale(dv, 1.0f / dist);
+}
+
+/* BSDF value and sampling density with the shading normal facing wo */
+static void eval_facing(const float* m, v3 ng, v3 wo, v3 wi, v3* fc, float* pdf) {
+  v3 n = vdot(ng, wo) > 0.0f ? ng : mk(-ng.x, -ng.y, -ng.z);
+  bsdf_eval(m, n, wo, wi, fc, pdf);
+}
+
+/* counts of a vertex at depth `depth` used as camera vertex */
+static void counts_for(const tctx* c, v3 P, v3 T, int depth, float beta[3]) {
+  uint32_t cell = octree_lookup(c->o, P, NULL);
+  vertex_beta(c, cell, T, depth, beta);
+}
+
+/* Balance-heuristic weight of strategy t (t camera vertices z_0..z_{t-1})
+ * for the path z[0] (camera), z[1..k] (z[k] on an emitter). */
+static float bdpt_weight(const tctx* c, const pvert* z, int k, int t) {
+  if (k <= 1) return 1.0f;
+  float pF[BD_MAXK + 2], pR[BD_MAXK + 2], nB[BD_MAXK + 2], nN[BD_MAXK + 2], nL[BD_MAXK + 2];
+  float d2;
+  /* area densities of z_i sampled from the camera side (i >= 2) */
+  for (int i = 2; i <= k; ++i) {
+    v3 wo = dir_between(z[i - 1].P, z[i - 2].P, &d2);
+    v3 wi = dir_between(z[i - 1].P, z[i].P, &d2);
+    v3 fc;
+    float p;
+    eval_facing(z[i - 1].m, z[i - 1].ng, wo, wi, &fc, &p);
+    pF[i] = (p * fabsf(vdot(z[i].ng, wi))) / d2;
+  }
+  /* area densities of z_i sampled from the light side */
+  pR[k] = z[k].lpdf;
+  {
+    v3 w = dir_between(z[k].P, z[k - 1].P, &d2);
+    float cl = vdot(z[k].ng, w);
+    float pe = cl > 0.0f ? cl * INV_PI_F : 0.0f;
+    pR[k - 1] = (pe * fabsf(vdot(z[k - 1].ng, w))) / d2;
+  }
+  for (int i = k - 2; i >= 1; --i) {
+    v3 wo = dir_between(z[i + 1].P, z[i + 2].P, &d2);
+    v3 wi = dir_between(z[i + 1].P, z[i].P, &d2);
+    v3 fc;
+    float p;
+    eval_facing(z[i + 1].m, z[i + 1].ng, wo, wi, &fc, &p);
+    pR[i] = (p * fabsf(vdot(z[i].ng, wi))) / d2;
+  }
+  /* counts of z_1..z_{k-1} as camera vertices, throughput from positions */
+  v3 T = mk(1.0f, 1.0f, 1.0f);
+  int aware = c->p->budget_aware;
+  for (int i = 1; i <= k - 1; ++i) {
+    float b[3];
+    counts_for(c, z[i].P, T, i, b);
+    nB[i] = aware ? b[0] : (b[0] > 0.0f ? 1.0f : 0.0f);
+    nN[i] = aware ? b[1] : (b[1] > 0.0f ? 1.0f : 0.0f);
+    nL[i] = aware ? b[2] : (b[2] > 0.0f ? 1.0f : 0.0f);
+    if (i < k - 1) {
+      v3 wo = dir_between(z[i].P, z[i - 1].P, &d2);
+      v3 wi = dir_between(z[i].P, z[i + 1].P, &d2);
+      v3 fc;
+      float p;
+      eval_facing(z[i].m, z[i].ng, wo, wi, &fc, &p);
+      if (p > 0.0f && b[0] > 0.0f)
+        T = mk(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
+               T.z * (((fc.z / p) * 1.0f) / b[0]));
+      else
+        T = mk(0.0f, 0.0f, 0.0f);
+    }
+  }
+#define TF(tt) ((tt) == k + 1 ? 1.0f : ((tt) == k ? nN[k - 1] : nL[(tt) - 1]))
+  float tft = TF(t);
+  if (!(tft > 0.0f)) return 0.0f;
+  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
+  for (int tt = t + 1; tt <= k + 1; ++tt) {
+    rp = rp * (pF[tt - 1] / pR[tt - 1]);
+    rb = rb * nB[tt - 2];
+    sum = sum + (rp * rb) * (TF(tt) / tft);
+  }
+  rp = 1.0f;
+  rb = 1.0f;
+  for (int tt = t - 1; tt >= 2; --tt) {
+    rp = rp * (pR[tt] / pF[tt]);
+    rb = rb * nB[tt - 1];
+    sum = sum + rp * (TF(tt) / (rb * tft));
+  }
+#undef TF
+  if (!(sum < INFINITY)) return 0.0f; /* also NaN */
+  return 1.0f / sum;
+}
+
+/* light subpath of a camera sample: emission point by power, cosine
+ * direction, then BSDF sampling with throughput RR q = min(1, max_ch prod
+ * B|cos|/p); vertices y_1.. up to max_depth - 2 */
+static void trace_light(const tctx* c, uint32_t pix, uint32_t s, lightpath* lp) {
+  const oracle* o = c->o;
+  lp->len = 0;
+  lp->rays = 0;
+  if (o->nlights == 0) return;
+  stream_t st = root_stream(c->key, pix, s, (uint32_t)c->p->iteration, TAG_LIGHT);
+  float u[4], u2[4];
+  draw4(c->key, st, 0, u);
+  draw4(c->key, st, 1, u2);
+  int li = 0;
+  while (li < o->nlights - 1 && !(u[0] < o->light_cdf[li])) ++li;
+  int32_t lt = o->light_tri[li];
+  float su = sqrtf(u[1]);
+  float a = su * (1.0f - u[2]), b = su * u[2];
+  v3 y0 = mk((o->v0[lt].x + a * o->e1[lt].x) + b * o->e2[lt].x,
+             (o->v0[lt].y + a * o->e1[lt].y) + b * o->e2[lt].y,
+             (o->v0[lt].z + a * o->e1[lt].z) + b * o->e2[lt].z);
+  v3 nl = o->ng[lt];
+  const float* ml = o->mats + 8 * o->tmat[lt];
+  lp->y0.P = y0; lp->y0.ng = nl; lp->y0.m = ml; lp->y0.lpdf = o->lpdf[lt];
+  int maxv = o->cfg.max_depth - 2;
+  if (maxv <= 0) return;
+  /* cosine-weighted emission direction about the emitting side */
+  v3 tt, bb;
+  onb(nl, &tt, &bb);
+  float sn, cs;
+  float r = sqrtf(u2[0]);
+  orc_sincos2pi(u2[1], &sn, &cs);
+  v3 w = to_world(mk(r * cs, r * sn, sqrtf(fmaxf(0.0f, 1.0f - u2[0]))), tt, bb, nl);
+  v3 alpha = mk((ml[5] * PI_F) / lp->y0.lpdf, (ml[6] * PI_F) / lp->y0.lpdf,
+                (ml[7] * PI_F) / lp->y0.lpdf);
+  v3 org = mk(y0.x + nl.x * o->eps, y0.y + nl.y * o->eps, y0.z + nl.z * o->eps);
+  v3 rr = mk(1.0f, 1.0f, 1.0f);
+  for (int i = 1; i <= maxv; ++i) {
+    float t;
+    uint32_t prim;
+    lp->rays++;
+    if (!closest_hit(o, org, w, INFINITY, &t, &prim)) return;
+    v3 x = mk(org.x + t * w.x, org.y + t * w.y, org.z + t * w.z);
+    pvert* y = &lp->y[i - 1];
+    y->P = x; y->ng = o->ng[prim]; y->m = o->mats + 8 * o->tmat[prim]; y->lpdf = o->lpdf[prim];
+    v3 wo = mk(-w.x, -w.y, -w.z);
+    lp->wo[i - 1] = wo;
+    lp->alpha[i - 1] = alpha;
+    lp->len = i;
+    if (i == maxv) return;
+    float uu[4];
+    draw4(c->key, st, (uint32_t)(1 + i), uu);
+    float q = fminf(1.0f, maxc3(rr));
+    if (!(uu[0] < q)) return;
+    v3 n = vdot(y->ng, wo) > 0.0f ? y->ng : mk(-y->ng.x, -y->ng.y, -y->ng.z);
+    v3 wn;
+    if (!bsdf_sample(y->m, n, wo, uu[1], uu[2], &wn)) return;
+    v3 fc;
+    float p;
+    bsdf_eval(y->m, n, wo, wn, &fc, &p);
+    if (!(p > 0.0f) || !(fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) return;
+    alpha = mk(alpha.x * ((fc.x / p) / q), alpha.y * ((fc.y / p) / q), alpha.z * ((fc.z / p) / q));
+    rr = mk(rr.x * (fc.x / p), rr.y * (fc.y / p), rr.z * (fc.z / p));
+    org = mk(x.x + n.x * o->eps, x.y + n.y * o->eps, x.z + n.z * o->eps);
+    w = wn;
+  }
+}
+
+/* camera-side recursion of BDPT: z[1..depth-1] is the prefix, z[0] the camera */
+static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t strm, pvert* z) {
+  const oracle* o = c->o;
+  const orc_iter_params* p = c->p;
+  trace_out out;
+  memset(&out, 0, sizeof(out));
+  float t;
+  uint32_t prim;
+  if (!closest_hit(o, org, dir, INFINITY, &t, &prim)) return out;
+  out.hit = 1;
+  const float* m = o->mats + 8 * o->tmat[prim];
+  v3 ngeo = o->ng[prim];
+  v3 x = mk(org.x + t * dir.x, org.y + t * dir.y, org.z + t * dir.z);
+  z[depth].P = x; z[depth].ng = ngeo; z[depth].m = m; z[depth].lpdf = o->lpdf[prim];
+  float cosl = -vdot(dir, ngeo);
+  if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
+    out.E = mk(m[5], m[6], m[7]);
+    float w = depth == 1 ? 1.0f : bdpt_weight(c, z, depth, depth + 1);
+    out.Ew = mk(w * out.E.x, w * out.E.y, w * out.E.z);
+  }
+  if (depth >= o->cfg.max_depth) return out;
+  v3 n = vdot(ngeo, dir) < 0.0f ? ngeo : mk(-ngeo.x, -ngeo.y, -ngeo.z);
+  v3 wo = mk(-dir.x, -dir.y, -dir.z);
+  v3 ov = mk(x.x + n.x * o->eps, x.y + n.y * o->eps, x.z + n.z * o->eps);
+  uint32_t cell = octree_lookup(o, x, NULL);
+  float beta[3];
+  vertex_beta(c, cell, T, depth, beta);
+  float ur[4];
+  draw4(c->key, strm, 0, ur);
+  uint32_t gam[3];
+  alg1(beta, ur[0], gam);
+  c->L->vertices++;
+  { stat_rec s = {REC_VISIT, cell, 0, 0, {0, 0, 0}, 0, 0}; log_push(c->L, s); }
+  if (depth == 1) {
+    float* b1 = o->beta1 + 3 * (size_t)c->root;
+    b1[0] = beta[0]; b1[1] = beta[1]; b1[2] = beta[2];
+  }
+  if (depth <= p->debug_depth) {
+    orc_vertex_rec d;
+    d.root = c->root; d.depth = depth; d.stream_lo = strm.lo; d.stream_hi = strm.hi; d.cell = cell;
+    for (int k = 0; k < 3; ++k) { d.beta[k] = beta[k]; d.gamma[k] = gam[k]; }
+    d.T[0] = T.x; d.T[1] = T.y; d.T[2] = T.z;
+    dbg_push(c->L, d);
+  }
+  v3 R = mk(0, 0, 0);
+  uint32_t cost = 0;
+  /* NEE */
+  for (uint32_t k = 0; k < gam[1]; ++k) {
+    stream_t ss = child_stream(c->key, strm, ORC_TECH_N, k, depth);
+    float u[4];
+    draw4(c->key, ss, 1, u);
+    c->L->samples++;
+    int li = 0;
+    while (li < o->nlights - 1 && !(u[0] < o->light_cdf[li])) ++li;
+    int32_t lt = o->light_tri[li];
+    float su = sqrtf(u[1]);
+    float a = su * (1.0f - u[2]), b = su * u[2];
+    v3 y = mk((o->v0[lt].x + a * o->e1[lt].x) + b * o->e2[lt].x,
+              (o->v0[lt].y + a * o->e1[lt].y) + b * o->e2[lt].y,
+              (o->v0[lt].z + a * o->e1[lt].z) + b * o->e2[lt].z);
+    v3 dv = vsub(y, ov);
+    float d2 = vdot(dv, dv);
+    float dist = sqrtf(d2);
+    v3 w = vscale(dv, 1.0f / dist);
+    float cl = -vdot(w, o->ng[lt]);
+    v3 fc;
+    float pB;
+    bsdf_eval(m, n, wo, w, &fc, &pB);
+    v3 v = mk(0, 0, 0);
+    if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+      float pN = (o->lpdf[lt] * d2) / cl;
+      z[depth + 1].P = y; z[depth + 1].ng = o->ng[lt]; z[depth + 1].m = o->mats + 8 * o->tmat[lt];
+      z[depth + 1].lpdf = o->lpdf[lt];
+      float wN = bdpt_weight(c, z, depth + 1, depth + 1);
+      c->L->rays_shadow++;
+      if (!occluded(o, ov, w, dist * (1.0f - 1e-3f))) {
+        const float* Le = o->mats + 8 * o->tmat[lt] + 5;
+        v = mk((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]), (fc.z / pN) * (wN * Le[2]));
+      }
+    }
+    R = mk(R.x + v.x / beta[1], R.y + v.y / beta[1], R.z + v.z / beta[1]);
+    cost += 1;
+    stat_rec s = {REC_SAMPLE, cell, ORC_TECH_N, 0, {v.x, v.y, v.z}, 1, 0};
+    log_push(c->L, s);
+  }
+  /* BSDF continuation */
+  for (uint32_t k = 0; k < gam[0]; ++k) {
+    stream_t ss = child_stream(c->key, strm, ORC_TECH_B, k, depth);
+    float u[4];
+    draw4(c->key, ss, 1, u);
+    c->L->samples++;
+    v3 w;
+    int ok = bsdf_sample(m, n, wo, u[0], u[1], &w);
+    v3 fc = mk(0, 0, 0);
+    float pB = 0.0f;
+    if (ok) {
+      bsdf_eval(m, n, wo, w, &fc, &pB);
+      ok = (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f) && pB > 0.0f;
+    }
+    v3 v = mk(0, 0, 0);
+    uint32_t scost = 1;
+    if (ok) {
+      float c0 = fc.x / pB, c1 = fc.y / pB, c2 = fc.z / pB;
+      v3 Tc = mk(T.x * ((c0 * 1.0f) / beta[0]), T.y * ((c1 * 1.0f) / beta[0]),
+                 T.z * ((c2 * 1.0f) / beta[0]));
+      c->L->rays_ext++;
+      trace_out ch = trace_bdpt(c, ov, w, Tc, depth + 1, ss, z);
+      v = mk(c0 * (ch.Ew.x + 1.0f * ch.R.x), c1 * (ch.Ew.y + 1.0f * ch.R.y),
+             c2 * (ch.Ew.z + 1.0f * ch.R.z));
+      scost = 1 + ch.cost;
+    }
+    R = mk(R.x + v.x / beta[0], R.y + v.y / beta[0], R.z + v.z / beta[0]);
+    cost += scost;
+    stat_rec s = {REC_SAMPLE, cell, ORC_TECH_B, 0, {v.x, v.y, v.z}, scost, 0};
+    log_push(c->L, s);
+  }
+  /* light-path connections */
+  uint32_t npool = (uint32_t)(o->W * o->H * p->spp);
+  for (uint32_t k = 0; k < gam[2]; ++k) {
+    c->L->samples++;
+    uint32_t lpi = (uint32_t)(((uint64_t)c->root + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
+    const lightpath* lp = &o->lpaths[lpi];
+    v3 v = mk(0, 0, 0);
+    uint32_t scost = (uint32_t)lp->rays;
+    int imax = o->cfg.max_depth - depth - 1;
+    if (imax > lp->len) imax = lp->len;
+    for (int i = 1; i <= imax; ++i) {
+      const pvert* y = &lp->y[i - 1];
+      float d2;
+      v3 w = dir_between(x, y->P, &d2);
+      v3 fcC, fcL;
+      float pc, pl;
+      bsdf_eval(m, n, wo, w, &fcC, &pc);
+      eval_facing(y->m, y->ng, lp->wo[i - 1], mk(-w.x, -w.y, -w.z), &fcL, &pl);
+      if (!(fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f)) continue;
+      if (!(fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) continue;
+      /* the full path: z_1..z_depth, y_i, .., y_1, y_0 */
+      for (int j = 1; j <= i; ++j) z[depth + j] = lp->y[i - j];
+      z[depth + i + 1] = lp->y0;
+      float wc = bdpt_weight(c, z, depth + 1 + i, depth + 1);
+      v3 a = lp->alpha[i - 1];
+      v3 ny = vdot(y->ng, lp->wo[i - 1]) > 0.0f ? y->ng : mk(-y->ng.x, -y->ng.y, -y->ng.z);
+      v3 yo = mk(y->P.x + ny.x * o->eps, y->P.y + ny.y * o->eps, y->P.z + ny.z * o->eps);
+      float sd2;
+      v3 sw = dir_between(ov, yo, &sd2);
+      c->L->rays_conn++;
+      scost += 1;
+      if (!occluded(o, ov, sw, sqrtf(sd2) * (1.0f - 1e-3f))) {
+        v = mk(v.x + wc * (((a.x * fcL.x) * fcC.x) / d2), v.y + wc * (((a.y * fcL.y) * fcC.y) / d2),
+               v.z + wc * (((a.z * fcL.z) * fcC.z) / d2));
+      }
+    }
+    R = mk(R.x + v.x / beta[2], R.y + v.y / beta[2], R.z + v.z / beta[2]);
+    cost += scost;
+    stat_rec s = {REC_SAMPLE, cell, ORC_TECH_G, 0, {v.x, v.y, v.z}, scost, 0};
+    log_push(c->L, s);
+  }
+  out.R = R;
+  out.cost = cost;
+  return out;
+}
+
 static void bdpt_root(tctx* c, v3* I) {
-  (void)c;
-  *I = mk(0.0f, 0.0f, 0.0f);
+  const oracle* o = c->o;
+  uint32_t pix = c->pix, s = c->root % (uint32_t)c->p->spp;
+  stream_t rs = root_stream(c->key, pix, s, (uint32_t)c->p->iteration, TAG_CAM);
+  float u[4];
+  draw4(c->key, rs, 1, u);
+  float jx = c->p->center_jitter ? 0.5f : u[0], jy = c->p->center_jitter ? 0.5f : u[1];
+  v3 org, dir;
+  camera_ray(o, (int32_t)(pix % (uint32_t)o->W), (int32_t)(pix / (uint32_t)o->W), jx, jy, &org, &dir);
+  pvert z[2 * BD_MAXK + 4];
+  memset(z, 0, sizeof(z));
+  z[0].P = o->cam_o;
+  z[0].ng = dir;
+  trace_out r = trace_bdpt(c, org, dir, mk(1.0f, 1.0f, 1.0f), 1, rs, z);
+  *I = mk(r.Ew.x + r.R.x, r.Ew.y + r.R.y, r.Ew.z + r.R.z);
+}
+
+static void build_light_paths(oracle* o, const orc_iter_params* p, key_t2 key, rowlog* logs) {
+  size_t n = (size_t)o->W * o->H * p->spp;
+  if (o->nlpaths < n) {
+    free(o->lpaths);
+    o->lpaths = calloc(n, sizeof(lightpath));
+    o->nlpaths = n;
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t r = 0; r < (int64_t)n; ++r) {
+    tctx c;
+    memset(&c, 0, sizeof(c));
+    c.o = o; c.p = p; c.key = key;
+    trace_light(&c, (uint32_t)(r / p->spp), (uint32_t)(r % p->spp), &o->lpaths[r]);
+  }
+  uint64_t rays = 0;
+  for (size_t r = 0; r < n; ++r) rays += (uint64_t)o->lpaths[r].rays;
+  logs[0].rays_light += rays;
+}
+
+/* weights of every strategy t = 2..k+1 of an explicit path (tests):
+ * P [k+1][3] (camera position first), prims [k+1] (prims[0] unused),
+ * It [3] pixel estimate; out [k] */
+void orc_bdpt_weights(const oracle* o, const orc_iter_params* p, const float* P,
+                      const uint32_t* prims, int32_t k, const float* It, float* out) {
+  tctx c;
+  memset(&c, 0, sizeof(c));
+  c.o = o; c.p = p;
+  c.It[0] = It[0]; c.It[1] = It[1]; c.It[2] = It[2];
+  pvert z[BD_MAXK + 2];
+  memset(z, 0, sizeof(z));
+  for (int i = 0; i <= k; ++i) {
+    z[i].P = mk(P[3 * i], P[3 * i + 1], P[3 * i + 2]);
+    if (i > 0) {
+      z[i].ng = o->ng[prims[i]];
+      z[i].m = o->mats + 8 * o->tmat[prims[i]];
+      z[i].lpdf = o->lpdf[prims[i]];
+    }
+  }
+  for (int t = 2; t <= k + 1; ++t) out[t - 2] = bdpt_weight(&c, z, k, t);
 }

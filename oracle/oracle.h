@@ -123,6 +123,8 @@ void orc_mis(int32_t aware, const float beta[3], const float p[3], float wdir[3]
 uint32_t orc_octree_lookup(const oracle* o, const float p[3], uint32_t* depth);
 int32_t orc_intersect(const oracle* o, const float orig[3], const float dir[3], float tmax,
                       float* t, uint32_t* prim);
+void orc_bdpt_weights(const oracle* o, const orc_iter_params* p, const float* P,
+                      const uint32_t* prims, int32_t k, const float* It, float* out);
 void orc_camera_ray(const oracle* o, int32_t px, int32_t py, float jx, float jy, float orig[3],
                     float dir[3]);
 

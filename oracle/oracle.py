@@ -107,6 +107,7 @@ def lib():
         L.orc_octree_lookup.restype = C.c_uint32
         L.orc_intersect.argtypes = [P, P, P, C.c_float, fp, C.POINTER(C.c_uint32)]
         L.orc_intersect.restype = C.c_int32
+        L.orc_bdpt_weights.argtypes = [P, C.POINTER(IterParams), P, P, C.c_int32, P, P]
         L.orc_camera_ray.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P]
         _lib = L
     return _lib
@@ -285,6 +286,15 @@ class Oracle:
         pr = C.c_uint32()
         hit = lib().orc_intersect(self.h, _p(o), _p(d), float(tmax), C.byref(t), C.byref(pr))
         return (t.value, pr.value) if hit else (None, None)
+
+    def bdpt_weights(self, p, P, prims, It):
+        P = np.ascontiguousarray(P, np.float32)
+        prims = np.ascontiguousarray(prims, np.uint32)
+        It = np.ascontiguousarray(It, np.float32)
+        k = P.shape[0] - 1
+        out = np.zeros(k, np.float32)
+        lib().orc_bdpt_weights(self.h, C.byref(p), _p(P), _p(prims), k, _p(It), _p(out))
+        return out
 
     def camera_ray(self, px, py, jx=0.5, jy=0.5):
         o = np.zeros(3, np.float32)

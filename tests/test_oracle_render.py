@@ -333,3 +333,102 @@ def test_intersection_matches_brute_force():
         if t is None or abs(t - tt[k]) > 1e-4 * max(1, tt[k]):
             bad += 1
     assert bad <= 1
+
+
+# ---------------------------------------------------------------------------
+# BDPT (Sec. 5): the full-path balance heuristic sums to one over the
+# strategies of any path; the estimator matches the furnace closed form and
+# the unidirectional mean under classic, MARS and random fixed counts.
+# ---------------------------------------------------------------------------
+def _random_paths(o, sc, rng, n, kmax):
+    V = sc["V"].reshape(-1, 3, 3).astype(np.float64)
+    light = [i for i in range(len(sc["tri_mat"])) if sc["mats"][sc["tri_mat"][i]][5] > 0]
+    out = []
+    while len(out) < n:
+        k = int(rng.integers(1, kmax + 1))
+        cam = np.asarray(sc["camera"][:3], np.float64)
+        P, prims = [cam], [0]
+        org, d = o.camera_ray(int(rng.integers(0, sc["width"])), int(rng.integers(0, sc["height"])),
+                              *rng.random(2))
+        ok = True
+        for _ in range(k - 1):
+            t, pr = o.intersect(org, d)
+            if t is None:
+                ok = False
+                break
+            x = org + t * d
+            P.append(x)
+            prims.append(pr)
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            org = (x + 1e-4 * d).astype(np.float32)
+        if not ok:
+            continue
+        lt = light[int(rng.integers(0, len(light)))]
+        a, b = sorted(rng.random(2))
+        y = V[lt, 0] * a + V[lt, 1] * (b - a) + V[lt, 2] * (1 - b)
+        P.append(y)
+        prims.append(lt)
+        out.append((np.array(P), np.array(prims)))
+    return out
+
+
+@pytest.mark.parametrize("aware", [True, False])
+def test_bdpt_weights_partition_of_unity(aware):
+    sc = scenegen.make_cornell(16, 16)
+    o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=8)
+    for i in range(2):  # build a non-trivial cache so that counts vary per vertex
+        p = orc.Oracle.params(iteration=i, spp=4, alloc=orc.ALLOC_CLASSIC if i == 0 else orc.ALLOC_MARS,
+                              stat_clamp=0)
+        o.render_iteration(p)
+        o.update(p)
+    p = orc.Oracle.params(alloc=orc.ALLOC_MARS, budget_aware=aware, stat_clamp=0)
+    rng = np.random.default_rng(3)
+    checked = 0
+    for P, prims in _random_paths(o, sc, rng, 300, 7):
+        w = o.bdpt_weights(p, P, prims, [0.2, 0.2, 0.2])
+        s = float(np.sum(w.astype(np.float64)))
+        if s == 0.0:
+            continue  # the emitter faces away: no strategy generates this path
+        assert abs(s - 1.0) < 2e-5, (s, w)
+        assert np.all(w >= 0)
+        checked += 1
+    assert checked > 100
+
+
+def test_furnace_bdpt():
+    sc = scenegen.make_furnace(24, 24)
+    for D in (3, 5):
+        o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=D)
+        Ls = []
+        for i in range(6):
+            p = orc.Oracle.params(iteration=i, spp=4, stat_clamp=0,
+                                  alloc=orc.ALLOC_CLASSIC if i < 2 else orc.ALLOC_MARS)
+            o.render_iteration(p)
+            Ls.append(o.sample_radiance()[:, 0].copy())
+            o.update(p)
+        L = np.concatenate(Ls)
+        assert abs(_zscore(L, (1 - 0.5 ** D) / 0.5)) < 4.0, D
+
+
+@pytest.mark.parametrize("aware", [True, False])
+def test_bdpt_unbiased_against_pt(aware):
+    sc = scenegen.make_cornell(24, 24)
+    ref = orc.Oracle(sc, mode=orc.MODE_PT, max_depth=4)
+    mref = _image_means(ref, [orc.Oracle.params(iteration=i, spp=32, stat_clamp=0) for i in range(12)])
+    o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=4)
+    for i in range(2):
+        p = orc.Oracle.params(iteration=50 + i, spp=4, stat_clamp=0)
+        o.render_iteration(p)
+        o.update(p)
+    rng = np.random.default_rng(21)
+    n = o.ncells
+    o.set_fixed_beta(np.stack([rng.uniform(0.05, 2.0, n), rng.uniform(0.05, 6, n),
+                               rng.uniform(0.05, 4, n)], 1))
+    m = _image_means(o, [orc.Oracle.params(iteration=200 + i, spp=16, alloc=orc.ALLOC_FIXED,
+                                           budget_aware=aware, stat_clamp=0, fixed_scale=bool(i % 2))
+                         for i in range(12)])
+    for ch in range(3):
+        a, b = mref[:, ch], m[:, ch]
+        z = (a.mean() - b.mean()) / math.sqrt(a.var() / len(a) + b.var() / len(b))
+        assert abs(z) < 4.0, (ch, a.mean(), b.mean(), z)
