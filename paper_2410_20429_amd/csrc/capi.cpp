@@ -52,6 +52,7 @@ struct Scene {
   CacheDev cd{};
   QueuesDev qd{};
   ImageDev img{};
+  LightDev lt{};
   Counters* cnt = nullptr;
   DebugRec* dbg = nullptr;
   uint32_t dbg_cap = 0;
@@ -73,11 +74,11 @@ struct Scene {
 // per-kernel HIP-event timing on the context's stream
 enum KernelId {
   KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
-  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_COUNT
+  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
     "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
-    "fixed_point", "hist_normalize", "refine", "ivw"};
+    "fixed_point", "hist_normalize", "refine", "ivw", "light"};
 
 struct Profiler {
   bool on = false;
@@ -236,12 +237,43 @@ void ensure_roots(Scene* s, size_t roots) {
   if (roots <= s->roots_cap) return;
   s->img.Ls = salloc<float>(s, roots * 3);
   s->img.beta1 = salloc<float>(s, roots * 3);
+  if (s->mode == MARS_MODE_BDPT) {
+    const size_t lm = (size_t)std::max(1, s->lt.lmax);
+    s->lt.V0 = salloc<float4>(s, roots * lm);
+    s->lt.V1 = salloc<float4>(s, roots * lm);
+    s->lt.V2 = salloc<float4>(s, roots * lm);
+    s->lt.Y0 = salloc<float4>(s, roots);
+    s->lt.len = salloc<uint2>(s, roots);
+  }
   s->roots_cap = roots;
+}
+
+// BDPT: one light subpath per camera sample of the iteration, before any
+// camera tile (connections may use any sample's subpath)
+uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
+  hipStream_t st = s->ctx->stream;
+  Ctx* c = s->ctx;
+  const int grid_trace = c->cu * 10, grid = c->cu * 8;
+  unsigned long long* tc = c->counting ? c->tcount : nullptr;
+  k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
+  for (size_t r0 = 0; r0 < roots; r0 += s->cap) {
+    const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
+    timed(c, KID_LIGHT, [&] { k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st); });
+    for (int i = 1; i <= s->lt.lmax; ++i) {
+      timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc); });
+      timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st); });
+    }
+  }
+  Counters hc;
+  d2h(&hc, s->cnt, sizeof(Counters), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return hc.rays_light;
 }
 
 // one wavefront tile: returns false on queue overflow
 bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t dbg0,
-              Counters* hc) {
+              uint32_t npool, Counters* hc) {
+  const bool bdpt = s->mode == MARS_MODE_BDPT;
   hipStream_t st = s->ctx->stream;
   // traversal: 128-thread groups, LDS-limited to 10 per CU; others 256-thread groups
   const int grid_trace = s->ctx->cu * 10, grid = s->ctx->cu * 8;
@@ -253,17 +285,26 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
   timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc); });
   for (int d = 1; d <= s->max_depth; ++d) {
     timed(c, KID_SHADE, [&] {
-      k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
+      if (bdpt)
+        k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, npool,
+                     grid, st);
+      else
+        k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
     });
     // shadow rays of depth d with the continuation rays of depth d + 1
-    const int dc = d < s->max_depth ? d + 1 : 0;
+    const int dc = d < s->max_depth ? d + 1 : -1;
     timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc); });
   }
   d2h(hc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));
   if (hc->overflow) return false;
   for (int d = s->max_depth; d >= 1; --d)
-    timed(c, KID_BACKPROP, [&] { k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st); });
+    timed(c, KID_BACKPROP, [&] {
+      if (bdpt)
+        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, npool, grid, st);
+      else
+        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
+    });
   return true;
 }
 
@@ -275,14 +316,22 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   if (roots > 0x7FFFFFFFull) throw Status(MARS_E_ARG, "too many camera samples");
   ensure_roots(s, roots);
   IterDev it = to_dev(p);
-  if (s->mode == MARS_MODE_BDPT) throw Status(MARS_E_ARG, "bidirectional mode not available");
   // per-iteration statistics start at zero (Sec. 4.1: estimates per iteration)
   k_fill_f64(s->cd.acc, 0.0, (size_t)s->n_cells * 24, st);
   k_fill_f64(s->cd.hacc, 0.0, (size_t)s->n_cells * 64, st);
   k_fill_u32(s->cd.visits, 0u, (size_t)s->n_cells, st);
   k_fill_f32(s->img.beta1, 0.0f, roots * 3, st);
+  if (p->debug_depth > 0) {
+    // room for every vertex up to debug_depth with splitting headroom
+    const size_t want = std::min<size_t>(roots * (size_t)p->debug_depth * 4 + 1024, 1u << 25);
+    if (want > s->dbg_cap) {
+      s->dbg = salloc<DebugRec>(s, want);
+      s->dbg_cap = (uint32_t)want;
+    }
+  }
   mars_iter_stats S{};
   S.rays_camera = roots;
+  if (s->mode == MARS_MODE_BDPT) S.rays_light = trace_light_paths(s, it, roots);
   const uint32_t tile = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
   std::vector<std::pair<uint32_t, uint32_t>> work;
   for (size_t r = roots; r > 0;) {
@@ -295,7 +344,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     auto [r0, n] = work.back();
     work.pop_back();
     Counters hc;
-    const bool ok = run_tile(s, it, r0, n, dbg_total, &hc);
+    const bool ok = run_tile(s, it, r0, n, dbg_total, (uint32_t)roots, &hc);
     S.tiles++;
     if (!ok) {
       if (n == 1) throw Status(MARS_E_OVERFLOW, "a single path tree exceeds the queue capacity");
@@ -310,6 +359,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     S.rays_shadow += hc.rays_shadow;
     S.vertices += hc.vertices;
     S.samples += hc.samples;
+    S.rays_conn += hc.rays_conn;
   }
   timed(s->ctx, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, p->spp, st); });
   HIPCHK(hipStreamSynchronize(st));
@@ -545,8 +595,9 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
     q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
     s->cnt = salloc<Counters>(s, 1);
-    s->dbg_cap = 1u << 20;
-    s->dbg = salloc<DebugRec>(s, s->dbg_cap);
+    s->lt.lmax = d->max_depth - 2;
+    s->dbg_cap = 0;  // allocated on the first iteration that asks for records
+    s->dbg = nullptr;
     // images
     ImageDev& im = s->img;
     im.iter_sum = salloc<float>(s, px * 3);

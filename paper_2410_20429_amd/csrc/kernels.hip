@@ -229,9 +229,9 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
                                                                  int ds, unsigned long long* tc) {
   __shared__ int stk[kStackDepth * kTraceBlock];
   if (cnt->overflow) return;
-  const uint32_t nc = dc > 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
+  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
   const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
-  const size_t Lc = (size_t)dc * q.cap, Ls = (size_t)ds * q.cap;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
   uint32_t cr = 0, cn = 0, ct = 0, sr = 0, sn = 0, st = 0;
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nc + ns;
        j += gridDim.x * blockDim.x) {
@@ -701,6 +701,603 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
                    const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s) {
   backprop_pt_kernel<<<grid, 256, 0, s>>>(sc, c, q, cnt, it, img, d);
+}
+
+// ---------------------------------------------------------------------------
+// Bidirectional path tracing (Sec. 5).  Techniques per camera vertex: BSDF
+// continuation, NEE, light-path connections (LP), each with its own count.
+// One light subpath per camera sample with throughput RR only (no splitting
+// on the light side).  LP sample j connects to light subpath
+// (root + j * stride) mod N, to every vertex y_i (i >= 1) that keeps the path
+// length within D.  MIS is the full-path balance heuristic over strategies
+// (s, t), t >= 2; the budget-aware form weights strategy (s, t) by
+// prod_{j <= t-2} beta_B(z_j) * beta_tech(s)(z_{t-1}).  The weight is a
+// function of the path vertices only: counts of every vertex, also of those
+// on the light side, come from the camera-prefix throughput computed from
+// vertex positions.
+// ---------------------------------------------------------------------------
+struct PV {
+  f3 P, ng;
+  uint32_t mat;
+  float lpdf;
+};
+
+__device__ __forceinline__ f3 dir_between(f3 a, f3 b, float* d2) {
+  const f3 dv = sub3(b, a);
+  *d2 = dot3(dv, dv);
+  const float dist = sqrtf(*d2);
+  return scl3(dv, 1.0f / dist);
+}
+
+__device__ __forceinline__ void eval_facing(const Mat& m, f3 ng, f3 wo, f3 wi, f3* fc, float* pdf) {
+  const f3 n = dot3(ng, wo) > 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+  eval_bsdf(m, n, wo, wi, fc, pdf);
+}
+
+__device__ __forceinline__ PV prim_vertex(const SceneDev& sc, f3 P, uint32_t prim) {
+  const float4 ng = sc.tri_ng[prim];
+  return PV{P, xyz(ng), sc.tri_mat[prim], ng.w};
+}
+
+__device__ float bdpt_weight(const SceneDev& sc, const CacheDev& c, const IterDev& it,
+                             const PV* z, int k, int t, const float* It) {
+  if (k <= 1) return 1.0f;
+  float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
+      nL[kMaxDepth + 2];
+  float d2;
+  for (int i = 2; i <= k; ++i) {
+    const f3 wo = dir_between(z[i - 1].P, z[i - 2].P, &d2);
+    const f3 wi = dir_between(z[i - 1].P, z[i].P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)z[i - 1].mat), z[i - 1].ng, wo, wi, &fc, &p);
+    pF[i] = (p * fabsf(dot3(z[i].ng, wi))) / d2;
+  }
+  pR[k] = z[k].lpdf;
+  {
+    const f3 w = dir_between(z[k].P, z[k - 1].P, &d2);
+    const float cl = dot3(z[k].ng, w);
+    const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+    pR[k - 1] = (pe * fabsf(dot3(z[k - 1].ng, w))) / d2;
+  }
+  for (int i = k - 2; i >= 1; --i) {
+    const f3 wo = dir_between(z[i + 1].P, z[i + 2].P, &d2);
+    const f3 wi = dir_between(z[i + 1].P, z[i].P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)z[i + 1].mat), z[i + 1].ng, wo, wi, &fc, &p);
+    pR[i] = (p * fabsf(dot3(z[i].ng, wi))) / d2;
+  }
+  f3 T = mk3(1.0f, 1.0f, 1.0f);
+  const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
+  for (int i = 1; i <= k - 1; ++i) {
+    float b[3];
+    const uint32_t cell = cell_of(c.nodes, olo, sc.oct_inv, z[i].P);
+    counts_at(sc, c, it, cell, T, It, i, b);
+    nB[i] = it.aware ? b[0] : (b[0] > 0.0f ? 1.0f : 0.0f);
+    nN[i] = it.aware ? b[1] : (b[1] > 0.0f ? 1.0f : 0.0f);
+    nL[i] = it.aware ? b[2] : (b[2] > 0.0f ? 1.0f : 0.0f);
+    if (i < k - 1) {
+      const f3 wo = dir_between(z[i].P, z[i - 1].P, &d2);
+      const f3 wi = dir_between(z[i].P, z[i + 1].P, &d2);
+      f3 fc;
+      float p;
+      eval_facing(load_mat(sc.mats + 8 * (size_t)z[i].mat), z[i].ng, wo, wi, &fc, &p);
+      if (p > 0.0f && b[0] > 0.0f)
+        T = mk3(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
+                T.z * (((fc.z / p) * 1.0f) / b[0]));
+      else
+        T = mk3(0.0f, 0.0f, 0.0f);
+    }
+  }
+  auto tf = [&](int tt) -> float {
+    return tt == k + 1 ? 1.0f : (tt == k ? nN[k - 1] : nL[tt - 1]);
+  };
+  const float tft = tf(t);
+  if (!(tft > 0.0f)) return 0.0f;
+  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
+  for (int tt = t + 1; tt <= k + 1; ++tt) {
+    rp = rp * (pF[tt - 1] / pR[tt - 1]);
+    rb = rb * nB[tt - 2];
+    sum = sum + (rp * rb) * (tf(tt) / tft);
+  }
+  rp = 1.0f;
+  rb = 1.0f;
+  for (int tt = t - 1; tt >= 2; --tt) {
+    rp = rp * (pR[tt] / pF[tt]);
+    rb = rb * nB[tt - 1];
+    sum = sum + rp * (tf(tt) / (rb * tft));
+  }
+  if (!(sum < INFINITY)) return 0.0f;
+  return 1.0f / sum;
+}
+
+// light subpaths: emission point by power, cosine direction; the light
+// queue lives at depth 0 of the queues: R0 origin/flag, R1 direction/root,
+// S0 alpha, S1 RR throughput
+__global__ void light_start_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counters* cnt,
+                                   IterDev it, uint32_t root0, uint32_t n) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) cnt->n_ray[0] = n;
+  if (j >= n) return;
+  const Key key{sc.key0, sc.key1};
+  const uint32_t root = root0 + j;
+  lt.len[root] = make_uint2(0u, 0u);
+  q.R0[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  q.R1[j] = make_float4(0.0f, 0.0f, 0.0f, fbits(root));
+  if (sc.n_lights == 0) return;
+  const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
+  const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagLight);
+  const float4 u = draw4(key, st, 0), u2 = draw4(key, st, 1);
+  int lo = 0, hi = sc.n_lights - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (u.x < sc.light_cdf[mid]) hi = mid; else lo = mid + 1;
+  }
+  const int li = sc.light_tri[lo];
+  const float4* G = sc.tri_geo + (size_t)li * 3;
+  const f3 v0 = xyz(G[0]), e1 = xyz(G[1]), e2 = xyz(G[2]);
+  const float su = sqrtf(u.y);
+  const float a = su * (1.0f - u.z), b = su * u.z;
+  const f3 y0 = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
+                    (v0.z + a * e1.z) + b * e2.z);
+  lt.Y0[root] = make_float4(y0.x, y0.y, y0.z, fbits((uint32_t)li));
+  if (lt.lmax <= 0) return;
+  const float4 ngl = sc.tri_ng[li];
+  const f3 nl = xyz(ngl);
+  const float* ml = sc.mats + 8 * (size_t)sc.tri_mat[li];
+  f3 tt, bb;
+  frame(nl, &tt, &bb);
+  float sn, cs;
+  const float r = sqrtf(u2.x);
+  sincos_turns(u2.y, &sn, &cs);
+  const f3 w = local_to_world(mk3(r * cs, r * sn, sqrtf(fmaxf(0.0f, 1.0f - u2.x))), tt, bb, nl);
+  q.R0[j] = make_float4(y0.x + nl.x * sc.eps, y0.y + nl.y * sc.eps, y0.z + nl.z * sc.eps, 1.0f);
+  q.R1[j] = make_float4(w.x, w.y, w.z, fbits(root));
+  q.S0[j] = make_float4((ml[5] * kPi) / ngl.w, (ml[6] * kPi) / ngl.w, (ml[7] * kPi) / ngl.w, 0.0f);
+  q.S1[j] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+}
+void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
+                   const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s) {
+  light_start_kernel<<<(n + 255) / 256, 256, 0, s>>>(sc, q, lt, cnt, it, root0, n);
+}
+
+// stores light vertex y_i and continues with throughput RR and BSDF sampling
+__global__ void light_shade_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counters* cnt,
+                                   IterDev it, int i) {
+  const uint32_t n = min(cnt->n_ray[0], (uint32_t)q.cap);
+  const Key key{sc.key0, sc.key1};
+  uint32_t my_rays = 0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const float4 r0 = q.R0[j];
+    if (r0.w == 0.0f) continue;
+    ++my_rays;
+    const float4 r1 = q.R1[j];
+    const uint32_t root = ubits(r1.w);
+    const uint2 h = q.H[j];
+    if (h.y == kMiss) {
+      q.R0[j] = make_float4(r0.x, r0.y, r0.z, 0.0f);
+      lt.len[root] = make_uint2(lt.len[root].x, lt.len[root].y + 1u);
+      continue;
+    }
+    const float t = fbits(h.x);
+    const f3 w = xyz(r1);
+    const f3 x = mk3(r0.x + t * w.x, r0.y + t * w.y, r0.z + t * w.z);
+    const f3 wo = mk3(-w.x, -w.y, -w.z);
+    const float4 al = q.S0[j];
+    const size_t e = (size_t)root * lt.lmax + (i - 1);
+    lt.V0[e] = make_float4(x.x, x.y, x.z, fbits(h.y));
+    lt.V1[e] = make_float4(wo.x, wo.y, wo.z, al.x);
+    lt.V2[e] = make_float4(al.y, al.z, 0.0f, 0.0f);
+    lt.len[root] = make_uint2((uint32_t)i, lt.len[root].y + 1u);
+    bool alive = false;
+    if (i < lt.lmax) {
+      const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
+      const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagLight);
+      const float4 u = draw4(key, st, (uint32_t)(1 + i));
+      const float4 rr = q.S1[j];
+      const float qv = fminf(1.0f, fmaxf(fmaxf(rr.x, rr.y), rr.z));
+      if (u.x < qv) {
+        const float4 ngl = sc.tri_ng[h.y];
+        const f3 ng = xyz(ngl);
+        const f3 nn = dot3(ng, wo) > 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+        const Mat mat = load_mat(sc.mats + 8 * (size_t)sc.tri_mat[h.y]);
+        f3 wn;
+        if (sample_bsdf(mat, nn, wo, u.y, u.z, &wn)) {
+          f3 fc;
+          float p;
+          eval_bsdf(mat, nn, wo, wn, &fc, &p);
+          if (p > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+            alive = true;
+            q.S0[j] = make_float4(al.x * ((fc.x / p) / qv), al.y * ((fc.y / p) / qv),
+                                  al.z * ((fc.z / p) / qv), 0.0f);
+            q.S1[j] = make_float4(rr.x * (fc.x / p), rr.y * (fc.y / p), rr.z * (fc.z / p), 0.0f);
+            q.R0[j] = make_float4(x.x + nn.x * sc.eps, x.y + nn.y * sc.eps, x.z + nn.z * sc.eps, 1.0f);
+            q.R1[j] = make_float4(wn.x, wn.y, wn.z, r1.w);
+          }
+        }
+      }
+    }
+    if (!alive) q.R0[j] = make_float4(r0.x, r0.y, r0.z, 0.0f);
+  }
+  const uint32_t sr = wave_sum(my_rays);
+  if ((threadIdx.x & 63) == 0 && sr) atomicAdd(&cnt->rays_light, (unsigned long long)sr);
+}
+void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
+                   const IterDev& it, int bounce, int grid, hipStream_t s) {
+  light_shade_kernel<<<grid, 256, 0, s>>>(sc, q, lt, cnt, it, bounce);
+}
+
+__device__ __forceinline__ uint32_t lp_index(uint32_t root, uint32_t j, int32_t stride,
+                                             uint32_t npool) {
+  return (uint32_t)(((unsigned long long)root + (unsigned long long)j * (uint32_t)stride) % npool);
+}
+
+__global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+                                                         LightDev lt, Counters* cnt, IterDev it,
+                                                         ImageDev img, DebugRec* dbg,
+                                                         uint32_t dbg_cap, int d, uint32_t npool) {
+  if (cnt->overflow) return;
+  const Key key{sc.key0, sc.key1};
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const int lane = threadIdx.x & 63;
+  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
+  uint32_t my_vert = 0, my_samp = 0, my_ext = 0, my_sh = 0, my_conn = 0;
+  PV z[2 * kMaxDepth + 4];
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t j = base + threadIdx.x;
+    const bool active = j < n;
+    bool vert = false;
+    f3 Ew = mk3(0.0f, 0.0f, 0.0f);
+    uint32_t cell = kNoCell;
+    float beta[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t gam[3] = {0u, 0u, 0u};
+    f3 x = mk3(0, 0, 0), n_s = mk3(0, 0, 0), wo = mk3(0, 0, 0), T = mk3(0, 0, 0),
+       ov = mk3(0, 0, 0);
+    uint32_t prim = kMiss, pix = 0, root = 0, nconn = 0;
+    uint2 strm = make_uint2(0, 0);
+    float It[3] = {1.0f, 1.0f, 1.0f};
+    if (active) {
+      const uint2 h = q.H[L + j];
+      prim = h.y;
+      const float4 r1 = q.R1[L + j];
+      pix = ubits(r1.w);
+      const uint4 s3 = q.S3[L + j];
+      root = s3.w;
+      if (prim != kMiss) {
+        const float t = fbits(h.x);
+        const float4 r0 = q.R0[L + j];
+        const f3 dir = xyz(r1);
+        const float4 ngl = sc.tri_ng[prim];
+        const f3 ng = xyz(ngl);
+        const float* m = sc.mats + 8 * (size_t)sc.tri_mat[prim];
+        x = mk3(r0.x + t * dir.x, r0.y + t * dir.y, r0.z + t * dir.z);
+        It[0] = img.itilde[3 * (size_t)pix];
+        It[1] = img.itilde[3 * (size_t)pix + 1];
+        It[2] = img.itilde[3 * (size_t)pix + 2];
+        // camera prefix z_1..z_d from the parent chain
+        z[0].P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
+        z[0].ng = dir;
+        z[0].mat = 0;
+        z[0].lpdf = 0.0f;
+        z[d] = PV{x, ng, sc.tri_mat[prim], ngl.w};
+        uint32_t e = ubits(q.S0[L + j].w);
+        for (int l = d - 1; l >= 1; --l) {
+          const size_t ee = (size_t)l * q.cap + e;
+          const float4 a0 = q.R0[ee], a1 = q.R1[ee];
+          const uint2 ah = q.H[ee];
+          const float at = fbits(ah.x);
+          z[l] = prim_vertex(sc, mk3(a0.x + at * a1.x, a0.y + at * a1.y, a0.z + at * a1.z), ah.y);
+          e = ubits(q.S0[ee].w);
+        }
+        const float cosl = -dot3(dir, ng);
+        if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
+          const float w = d == 1 ? 1.0f : bdpt_weight(sc, c, it, z, d, d + 1, It);
+          Ew = mk3(w * m[5], w * m[6], w * m[7]);
+        }
+        if (d < sc.max_depth) {
+          vert = true;
+          n_s = dot3(ng, dir) < 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+          wo = mk3(-dir.x, -dir.y, -dir.z);
+          ov = mk3(x.x + n_s.x * sc.eps, x.y + n_s.y * sc.eps, x.z + n_s.z * sc.eps);
+          cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
+          T = xyz(q.S0[L + j]);
+          counts_at(sc, c, it, cell, T, It, d, beta);
+          strm = make_uint2(s3.x, s3.y);
+          const float4 u = draw4(key, strm, 0);
+          round_counts(beta, u.x, gam);
+          const int imax0 = sc.max_depth - d - 1;
+          for (uint32_t k = 0; k < gam[2]; ++k) {
+            const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+            nconn += (uint32_t)max(0, min(imax0, (int)lt.len[lpi].x));
+          }
+        }
+      }
+    }
+    const uint32_t ncont = vert ? gam[0] : 0u, nsh = vert ? gam[1] + nconn : 0u;
+    const uint32_t packed = ncont | (nsh << 16);
+    const uint32_t incl = wave_scan_incl(packed);
+    const uint32_t excl = incl - packed;
+    const uint32_t tot = __shfl(incl, 63, 64);
+    uint32_t bc = 0, bs = 0;
+    if (lane == 63) {
+      if (tot & 0xFFFFu) bc = atomicAdd(&cnt->n_ray[d + 1], tot & 0xFFFFu);
+      if (tot >> 16) bs = atomicAdd(&cnt->n_shadow[d], tot >> 16);
+    }
+    bc = __shfl(bc, 63, 64);
+    bs = __shfl(bs, 63, 64);
+    const uint32_t cfirst = bc + (excl & 0xFFFFu), sfirst = bs + (excl >> 16);
+    bool ovf = false;
+    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nsh > q.cap)) {
+      ovf = true;
+      atomicMax(&cnt->overflow, 1u);
+    }
+    if (!active) continue;
+    q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
+    q.V1[L + j] = make_float4(beta[0], beta[1], beta[2], fbits(vert ? gam[2] : 0u));
+    q.V2[L + j] = ovf ? make_uint4(0, 0, 0, 0)
+                      : make_uint4(sfirst, (vert ? gam[1] : 0u) | (nconn << 16), cfirst, ncont);
+    if (d == 1) {
+      img.beta1[3 * (size_t)root] = beta[0];
+      img.beta1[3 * (size_t)root + 1] = beta[1];
+      img.beta1[3 * (size_t)root + 2] = beta[2];
+    }
+    if (!vert || ovf) continue;
+    ++my_vert;
+    my_samp += gam[0] + gam[1] + gam[2];
+    if (d <= it.debug_depth && dbg) {
+      const uint32_t k = atomicAdd(&cnt->n_debug, 1u);
+      if (k < dbg_cap) {
+        DebugRec r;
+        r.root = root; r.depth = (uint32_t)d; r.stream_lo = strm.x; r.stream_hi = strm.y;
+        r.cell = cell;
+        for (int t = 0; t < 3; ++t) { r.beta[t] = beta[t]; r.gamma[t] = gam[t]; }
+        r.T[0] = T.x; r.T[1] = T.y; r.T[2] = T.z;
+        dbg[k] = r;
+      }
+    }
+    const Mat mat = load_mat(sc.mats + 8 * (size_t)sc.tri_mat[prim]);
+    // NEE
+    for (uint32_t k = 0; k < gam[1]; ++k) {
+      const uint2 ss = stream_child(key, strm, 1u, k, (uint32_t)d);
+      const float4 u = draw4(key, ss, 1);
+      int lo = 0, hi = sc.n_lights - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u.x < sc.light_cdf[mid]) hi = mid; else lo = mid + 1;
+      }
+      const int li = sc.light_tri[lo];
+      const float4* G = sc.tri_geo + (size_t)li * 3;
+      const f3 v0 = xyz(G[0]), e1 = xyz(G[1]), e2 = xyz(G[2]);
+      const float su = sqrtf(u.y);
+      const float a = su * (1.0f - u.z), b = su * u.z;
+      const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
+                       (v0.z + a * e1.z) + b * e2.z);
+      const f3 dv = sub3(y, ov);
+      const float d2 = dot3(dv, dv);
+      const float dist = sqrtf(d2);
+      const f3 w = scl3(dv, 1.0f / dist);
+      const float4 lng = sc.tri_ng[li];
+      const float cl = -dot3(w, xyz(lng));
+      f3 fc;
+      float pB;
+      eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+      float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+        const float pN = (lng.w * d2) / cl;
+        z[d + 1] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
+        const float wN = bdpt_weight(sc, c, it, z, d + 1, d + 1, It);
+        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
+        sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
+                          (fc.z / pN) * (wN * Le[2]), 1.0f);
+        ++my_sh;
+      }
+      const size_t e = L + sfirst + k;
+      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
+      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      q.SH2[e] = sh2;
+    }
+    // BSDF continuation (the only continuing technique: w_ind = 1)
+    for (uint32_t k = 0; k < gam[0]; ++k) {
+      const uint2 ss = stream_child(key, strm, 0u, k, (uint32_t)d);
+      const float4 u = draw4(key, ss, 1);
+      f3 w;
+      bool ok = sample_bsdf(mat, n_s, wo, u.x, u.y, &w);
+      f3 fc = mk3(0.0f, 0.0f, 0.0f);
+      float pB = 0.0f;
+      if (ok) {
+        eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+        ok = (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f) && pB > 0.0f;
+      }
+      const size_t e = Ln + cfirst + k;
+      if (ok) {
+        const float c0 = fc.x / pB, c1 = fc.y / pB, c2 = fc.z / pB;
+        const f3 Tc = mk3(T.x * ((c0 * 1.0f) / beta[0]), T.y * ((c1 * 1.0f) / beta[0]),
+                          T.z * ((c2 * 1.0f) / beta[0]));
+        q.R0[e] = make_float4(ov.x, ov.y, ov.z, 1.0f);
+        q.S0[e] = make_float4(Tc.x, Tc.y, Tc.z, fbits(j));
+        q.S1[e] = make_float4(c0, c1, c2, 1.0f);
+        ++my_ext;
+      } else {
+        q.R0[e] = make_float4(ov.x, ov.y, ov.z, 0.0f);
+        q.S0[e] = make_float4(0.0f, 0.0f, 0.0f, fbits(j));
+        q.S1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+      q.R1[e] = make_float4(w.x, w.y, w.z, fbits(pix));
+      q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, beta[0]);
+      q.S3[e] = make_uint4(ss.x, ss.y, k, root);
+    }
+    // light-path connections
+    uint32_t slot = sfirst + gam[1];
+    const int imax0 = sc.max_depth - d - 1;
+    for (uint32_t k = 0; k < gam[2]; ++k) {
+      const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+      const int imax = max(0, min(imax0, (int)lt.len[lpi].x));
+      for (int i = 1; i <= imax; ++i, ++slot) {
+        const size_t ye = (size_t)lpi * lt.lmax + (i - 1);
+        const float4 y0v = lt.V0[ye], y1v = lt.V1[ye], y2v = lt.V2[ye];
+        const f3 yP = xyz(y0v);
+        const uint32_t yprim = ubits(y0v.w);
+        const PV yv = prim_vertex(sc, yP, yprim);
+        float d2;
+        const f3 w = dir_between(x, yP, &d2);
+        f3 fcC, fcL;
+        float pc, pl;
+        eval_bsdf(mat, n_s, wo, w, &fcC, &pc);
+        const Mat ym = load_mat(sc.mats + 8 * (size_t)yv.mat);
+        const f3 ywo = xyz(y1v);
+        eval_facing(ym, yv.ng, ywo, mk3(-w.x, -w.y, -w.z), &fcL, &pl);
+        float4 sh0 = make_float4(ov.x, ov.y, ov.z, 0.0f), sh1 = make_float4(w.x, w.y, w.z, fbits(j));
+        float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
+            (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
+          for (int jj = 1; jj <= i; ++jj) {
+            const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
+            z[d + jj] = prim_vertex(sc, xyz(pv), ubits(pv.w));
+          }
+          const float4 y0r = lt.Y0[lpi];
+          z[d + i + 1] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
+          const float wc = bdpt_weight(sc, c, it, z, d + 1 + i, d + 1, It);
+          const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
+          const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
+          float sd2;
+          const f3 sw = dir_between(ov, yo, &sd2);
+          const f3 al = mk3(y1v.w, y2v.x, y2v.y);
+          sh0 = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
+          sh1 = make_float4(sw.x, sw.y, sw.z, fbits(j));
+          sh2 = make_float4(wc * (((al.x * fcL.x) * fcC.x) / d2), wc * (((al.y * fcL.y) * fcC.y) / d2),
+                            wc * (((al.z * fcL.z) * fcC.z) / d2), 1.0f);
+          ++my_conn;
+        }
+        const size_t e = L + slot;
+        q.SH0[e] = sh0;
+        q.SH1[e] = sh1;
+        q.SH2[e] = sh2;
+      }
+    }
+  }
+  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext),
+                 sh = wave_sum(my_sh), sn = wave_sum(my_conn);
+  if (lane == 0) {
+    if (sv) atomicAdd(&cnt->vertices, (unsigned long long)sv);
+    if (ss) atomicAdd(&cnt->samples, (unsigned long long)ss);
+    if (se) atomicAdd(&cnt->rays_ext, (unsigned long long)se);
+    if (sh) atomicAdd(&cnt->rays_shadow, (unsigned long long)sh);
+    if (sn) atomicAdd(&cnt->rays_conn, (unsigned long long)sn);
+  }
+}
+void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                  Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
+                  uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s) {
+  shade_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
+}
+
+// back-propagation for BDPT: NEE, BSDF and LP samples in that order
+__global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+                                                            LightDev lt, const Counters* cnt,
+                                                            IterDev it, ImageDev img, int d,
+                                                            uint32_t npool) {
+  __shared__ AggTable A;
+  for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
+    A.key[k] = kAggEmpty;
+    for (int i = 0; i < kAggVals; ++i) A.val[k][i] = 0.0;
+  }
+  __syncthreads();
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
+  const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t j0 = blockIdx.x * chunk, j1 = min(n, j0 + chunk);
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const float4 v0 = q.V0[L + j];
+    const uint32_t cell = ubits(v0.w);
+    f3 R = mk3(0.0f, 0.0f, 0.0f);
+    uint32_t cost = 0;
+    if (cell != kNoCell) {
+      double st[3][8];
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) st[t][i] = 0.0;
+      const uint4 v2 = q.V2[L + j];
+      const float4 b = q.V1[L + j];
+      const uint32_t nnee = v2.y & 0xFFFFu, glp = ubits(b.w);
+      const uint32_t root = q.S3[L + j].w;
+      auto record = [&](int t, f3 v, uint32_t cst) {
+        const double x0 = (double)v.x, x1 = (double)v.y, x2 = (double)v.z;
+        st[t][0] += x0; st[t][1] += x1; st[t][2] += x2;
+        st[t][3] += x0 * x0; st[t][4] += x1 * x1; st[t][5] += x2 * x2;
+        st[t][6] += 1.0; st[t][7] += (double)cst;
+      };
+      for (uint32_t k = 0; k < nnee; ++k) {
+        const f3 v = xyz(q.SH2[L + v2.x + k]);
+        R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
+        cost += 1;
+        record(1, v, 1u);
+      }
+      for (uint32_t k = 0; k < v2.w; ++k) {
+        const size_t e = Ln + v2.z + k;
+        const float4 s1 = q.S1[e], s2 = q.S2[e];
+        f3 v = mk3(0.0f, 0.0f, 0.0f);
+        uint32_t sc_ = 1;
+        if (q.R0[e].w != 0.0f) {
+          const float4 cv = q.V0[e], cr = q.RO[e];
+          v = mk3(s1.x * (cv.x + s1.w * cr.x), s1.y * (cv.y + s1.w * cr.y),
+                  s1.z * (cv.z + s1.w * cr.z));
+          sc_ = 1u + ubits(cr.w);
+        }
+        R = mk3(R.x + v.x / s2.w, R.y + v.y / s2.w, R.z + v.z / s2.w);
+        cost += sc_;
+        record(0, v, sc_);
+      }
+      uint32_t slot = v2.x + nnee;
+      const int imax0 = sc.max_depth - d - 1;
+      for (uint32_t k = 0; k < glp; ++k) {
+        const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+        const uint2 ll = lt.len[lpi];
+        const int imax = max(0, min(imax0, (int)ll.x));
+        f3 v = mk3(0.0f, 0.0f, 0.0f);
+        uint32_t sc_ = ll.y;
+        for (int i = 1; i <= imax; ++i, ++slot) {
+          const float4 r = q.SH2[L + slot];
+          if (r.w != 0.0f) {
+            sc_ += 1;
+            v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
+          }
+        }
+        R = mk3(R.x + v.x / b.z, R.y + v.y / b.z, R.z + v.z / b.z);
+        cost += sc_;
+        record(2, v, sc_);
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t != 0 && st[t][6] == 0.0) continue;
+        double vals[kAggVals];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vals[i] = st[t][i];
+        vals[8] = t == 0 ? 1.0 : 0.0;
+        agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
+      }
+    }
+    q.RO[L + j] = make_float4(R.x, R.y, R.z, fbits(cost));
+    if (d == 1) {
+      const uint32_t root = q.S3[L + j].w;
+      img.Ls[3 * (size_t)root] = v0.x + R.x;
+      img.Ls[3 * (size_t)root + 1] = v0.y + R.y;
+      img.Ls[3 * (size_t)root + 2] = v0.z + R.z;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
+    if (A.key[k] == kAggEmpty) continue;
+    double vals[kAggVals];
+    for (int i = 0; i < kAggVals; ++i) vals[i] = A.val[k][i];
+    global_add_stats(c, A.key[k], vals);
+  }
+}
+void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
+                     const LightDev& lt, const Counters* cnt, const IterDev& it,
+                     const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s) {
+  backprop_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,7 +71,17 @@ struct Counters {
   uint32_t n_shadow[kMaxDepth + 2];
   uint32_t overflow;
   uint32_t n_debug;
-  unsigned long long rays_ext, rays_shadow, vertices, samples;
+  unsigned long long rays_ext, rays_shadow, vertices, samples, rays_light, rays_conn;
+};
+
+// BDPT light subpaths of an iteration, one per camera sample (root)
+struct LightDev {
+  float4* V0;     // [root][lmax]: position y_i, primitive (bits)
+  float4* V1;     // [root][lmax]: direction towards y_{i-1}, alpha.r
+  float4* V2;     // [root][lmax]: alpha.g, alpha.b, -, -
+  float4* Y0;     // [root]: point on the emitter, emitter primitive (bits)
+  uint2* len;     // [root]: vertices stored, rays traced
+  int32_t lmax;   // max_depth - 2
 };
 
 struct IterDev {
@@ -107,8 +117,8 @@ void k_fill_f64(double* p, double v, size_t n, hipStream_t s);
 void k_fill_f32(float* p, float v, size_t n, hipStream_t s);
 void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterDev& it,
               uint32_t root0, uint32_t n_roots, hipStream_t s);
-// traverses the closest-hit queue of depth dc and the shadow queue of depth
-// ds in one launch (0 = none).  tc (optional): traversal counters {rays,
+// traverses the closest-hit queue of depth dc (-1 = none; 0 is the light
+// queue) and the shadow queue of depth ds (0 = none) in one launch.  tc (optional): traversal counters {rays,
 // nodes, triangles} of closest-hit rays at tc[0..2], shadow rays at tc[3..5]
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
                   int grid, hipStream_t s, unsigned long long* tc);
@@ -117,6 +127,16 @@ void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Count
                 int grid, hipStream_t s);
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
                    const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s);
+void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
+                   const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s);
+void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
+                   const IterDev& it, int bounce, int grid, hipStream_t s);
+void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                  Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
+                  uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s);
+void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
+                     const LightDev& lt, const Counters* cnt, const IterDev& it,
+                     const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s);
 void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s);
 void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
                     float stat_clamp, hipStream_t s);

@@ -232,3 +232,78 @@ def scaled(scene, width, height):
     sc["width"] = int(width)
     sc["height"] = int(height)
     return sc
+
+
+# --------------------------------------------------------------------------
+# Bidirectional workload: a closed 10 x 3 x 8 room filled with instanced
+# furniture (unions of 3-6 boxes whose faces are tessellated into 3 x 3
+# grids, ~500 triangles per piece), lit by one small 0.1 x 0.1 emitter
+# (Le = 2000) hidden above an occluder panel, so that most light reaches the
+# scene indirectly and connections to light subpaths matter.
+# --------------------------------------------------------------------------
+def _tess_box(lo, hi, n):
+    """Outward-wound box with every face split into n x n quads."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    d = hi - lo
+    faces = [
+        (lo, np.array([0, 0, d[2]]), np.array([d[0], 0, 0])),
+        (np.array([lo[0], hi[1], lo[2]]), np.array([d[0], 0, 0]), np.array([0, 0, d[2]])),
+        (lo, np.array([d[0], 0, 0]), np.array([0, d[1], 0])),
+        (np.array([lo[0], lo[1], hi[2]]), np.array([0, d[1], 0]), np.array([d[0], 0, 0])),
+        (lo, np.array([0, d[1], 0]), np.array([0, 0, d[2]])),
+        (np.array([hi[0], lo[1], lo[2]]), np.array([0, 0, d[2]]), np.array([0, d[1], 0])),
+    ]
+    tris = []
+    for p, e1, e2 in faces:
+        for i in range(n):
+            for j in range(n):
+                tris += _quad(p + e1 * (i / n) + e2 * (j / n), e1 / n, e2 / n)
+    return np.array(tris)
+
+
+def make_interior(seed=1, width=1280, height=720, n_pieces=2000, n_proto=16, tess=3):
+    rng = np.random.default_rng(seed)
+    mats, chunks, tm = [], [], []
+    mats.append(_mat(LAMBERT, 0.6))                                   # 0 room
+    room = np.array(_box((-5.0, 0.0, -4.0), (5.0, 3.0, 4.0), inward=True))
+    chunks.append(room)
+    tm += [0] * len(room)
+    protos = []
+    for _ in range(n_proto):
+        boxes = []
+        for _ in range(int(rng.integers(3, 7))):
+            c = rng.uniform([-0.4, 0.0, -0.4], [0.4, 0.8, 0.4])
+            s = rng.uniform([0.05, 0.05, 0.05], [0.5, 0.6, 0.5])
+            lo = np.array([c[0] - s[0] / 2, c[1], c[2] - s[2] / 2])
+            boxes.append(_tess_box(lo, lo + s, tess))
+        protos.append(np.concatenate(boxes))
+        if rng.random() < 0.5:
+            mats.append(_mat(LAMBERT, rng.uniform(0.2, 0.8, 3)))
+        else:
+            mats.append(_mat(GGX, rng.uniform(0.2, 0.8, 3), alpha=rng.uniform(0.05, 0.5)))
+    for _ in range(n_pieces):
+        k = int(rng.integers(0, n_proto))
+        scale = rng.uniform(0.4, 1.2)
+        yaw = rng.uniform(0, 2 * math.pi)
+        px, pz = rng.uniform([-4.5, -3.5], [4.5, 3.5])
+        t = protos[k].reshape(-1, 3, 3) * scale
+        cs, sn = math.cos(yaw), math.sin(yaw)
+        x, z = t[..., 0].copy(), t[..., 2].copy()
+        t[..., 0] = cs * x - sn * z + px
+        t[..., 2] = sn * x + cs * z + pz
+        chunks.append(t.reshape(-1, 9))
+        tm += [1 + k] * t.shape[0]
+    # hidden emitter near the ceiling, occluder panel below it
+    mats.append(_mat(LAMBERT, 0.0, le=(2000.0, 2000.0, 2000.0)))
+    le_id = len(mats) - 1
+    mats.append(_mat(LAMBERT, 0.7))
+    occ_id = len(mats) - 1
+    light = np.array(_quad((3.9, 2.95, 2.9), (0.1, 0, 0), (0, 0, 0.1)))   # faces -y
+    chunks.append(light)
+    tm += [le_id] * len(light)
+    panel = np.array(_box((3.55, 2.55, 2.55), (4.45, 2.6, 3.45)))
+    chunks.append(panel)
+    tm += [occ_id] * len(panel)
+    cam = [-4.3, 1.6, -3.4, 1.0, 0.9, 1.5, 0.0, 1.0, 0.0, 60.0]
+    return _finish(np.concatenate(chunks), tm, mats, cam, width, height, f"interior_s{seed}")

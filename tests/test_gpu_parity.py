@@ -429,3 +429,77 @@ def test_full_size_sampled_pixels(ctx):
     dg = g.debug_vertices()
     dg = dg[np.isin(dg["root"], roots)]
     _cmp_vertices(dg, o.debug_vertices())
+
+
+# ---------------------------------------------------------------------------
+# bidirectional mode (Sec. 5): light subpaths, NEE, light-path connections
+# with the full-path budget-aware balance heuristic
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scene", ["cornell", "interior"])
+def test_bdpt_schedule_parity(ctx, scene):
+    if scene == "cornell":
+        sc, D = scenegen.make_cornell(40, 36), 5
+    else:
+        sc, D = scenegen.make_interior(seed=2, n_pieces=40, tess=2, width=48, height=27), 6
+    g, o = _pair(ctx, sc, mode=orc.MODE_BDPT, max_depth=D)
+    for it in range(5):
+        say("bdpt", scene, "iteration", it)
+        alloc = orc.ALLOC_CLASSIC if it < 2 else orc.ALLOC_MARS
+        pg, po = _params(iteration=it, spp=2, alloc=alloc, stat_clamp=0.0, debug_depth=D)
+        sg = g.render_iteration(pg)
+        so = o.render_iteration(po)
+        assert (sg.rays_light, sg.rays_conn, sg.rays_shadow, sg.rays_ext) == \
+               (so.rays_light, so.rays_conn, so.rays_shadow, so.rays_ext)
+        _cmp_radiance(g.sample_radiance(), o.sample_radiance())
+        _cmp_vertices(g.debug_vertices(), o.debug_vertices())
+        _cmp_cells(g, o)
+        ug, uo = g.update(pg), o.update(po)
+        assert abs(ug.V_I - uo.V_I) <= 1e-9 * max(uo.V_I, 1e-30)
+        assert ug.n_excluded == uo.n_excluded
+        assert np.array_equal(g.nodes(), o.nodes())
+        _cmp_cells(g, o)
+
+
+def test_bdpt_furnace_gpu(ctx):
+    api = _api()
+    sc = scenegen.make_furnace(48, 48)
+    g = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=5)
+    L = []
+    for it in range(6):
+        p = api.iter_params(iteration=it, spp=4, stat_clamp=0.0,
+                            alloc=api.ALLOC_CLASSIC if it < 2 else api.ALLOC_MARS)
+        g.render_iteration(p)
+        L.append(g.sample_radiance()[:, 0].copy())
+        g.update(p)
+    L = np.concatenate(L)
+    z = (L.mean() - 1.9375) / (L.std() / math.sqrt(len(L)))
+    assert abs(z) < 4.0, (L.mean(), z)
+
+
+def test_bdpt_full_size_sampled_pixels(ctx):
+    """1280 x 720 interior, ~1M triangles, max path length 12: sampled
+    pixels of a classic iteration and of a MARS iteration with seeded
+    factors, against the oracle (which traces every light subpath)."""
+    api = _api()
+    sc = scenegen.make_interior(seed=1)
+    say("bdpt full size upload", sc["V"].shape[0], "tris")
+    g = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12)
+    o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=12)
+    rng = np.random.default_rng(23)
+    pix = rng.choice(sc["width"] * sc["height"], 200, replace=False)
+    o.set_pixel_subset(pix)
+    for it, alloc in ((0, orc.ALLOC_CLASSIC), (1, orc.ALLOC_MARS)):
+        if alloc == orc.ALLOC_MARS:
+            itl = rng.uniform(0.05, 2.0, (sc["height"], sc["width"], 3)).astype(np.float32)
+            fac = rng.uniform(0.0, 3.0, (1, 2, 3, 3)).astype(np.float32)
+            for x in (g, o):
+                x.set_itilde(itl)
+                x.write_cells(factors=fac)
+        pg, po = _params(iteration=it, spp=1, alloc=alloc, stat_clamp=0.0, debug_depth=3)
+        say("bdpt full size iteration", it)
+        g.render_iteration(pg)
+        o.render_iteration(po)
+        _cmp_radiance(g.sample_radiance()[pix], o.sample_radiance()[pix])
+        dg = g.debug_vertices()
+        dg = dg[np.isin(dg["root"], pix)]
+        _cmp_vertices(dg, o.debug_vertices())
