@@ -85,8 +85,12 @@ typedef struct {
   uint64_t seed;            /* Philox key */
   int64_t queue_capacity;   /* entries per path-depth queue; 0 = automatic */
   int32_t tile_roots;       /* camera samples per wavefront tile; 0 = automatic */
-  int32_t reserved;
+  int32_t flags;            /* MARS_SCENE_* bits */
 } mars_scene_desc;
+
+/* scene flags: MARS_SCENE_MLP allocates the learned cache (counts predicted
+ * by a small network trained online on the octree's estimates) */
+enum { MARS_SCENE_MLP = 1 };
 
 typedef struct {
   int32_t iteration;        /* keys the random streams */
@@ -201,6 +205,40 @@ mars_status mars_debug_vertices(mars_ctx* ctx, int32_t scene_id, mars_vertex_rec
 /* Cache (nodes, cells, distributions), images and iteration state. */
 mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* path);
 mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* path);
+
+/* ---- learned cache (scenes uploaded with MARS_SCENE_MLP) -----------------
+ * A network maps a vertex (position normalised to the octree box, shading
+ * normal) to the log count of every technique relative to |T / I~|; render
+ * iterations with alloc = MARS_ALLOC_MLP use beta_t = |T / I~| exp(y_t)
+ * (clamped; the octree count where the output is not finite).  Training
+ * data: a random subset of the iteration's vertices, recorded while shading;
+ * mars_update_counts turns them into targets from the cells' updated
+ * factors (log of the resolved octree count, weight min(n, 64)/64 for cells
+ * with at least 4 samples of the technique).  The counts of the MIS weights
+ * keep using the octree (a function of the path only).
+ * The network: sin/cos(2^k pi x), k < 6, of the 6 inputs (72 features,
+ * padded to 80), 3 hidden layers of 64 ReLU units, 3 outputs; bfloat16
+ * matrix-core products with binary32 accumulation; Adam (0.9, 0.99, 1e-8)
+ * on binary32 master weights.  Parameter layout (binary32): W1 [64][80],
+ * b1 [64], W2 [64][64], b2, W3 [64][64], b3, W4 [16][64] (rows 3..15 zero),
+ * b4 [16]. */
+int32_t mars_mlp_num_params(void);
+/* steps Adam steps over the current training set, batch samples each;
+ * *loss (host, optional) receives the loss of the last step */
+mars_status mars_mlp_train(mars_ctx* ctx, int32_t scene_id, int32_t steps, int32_t batch, float lr,
+                           float* loss, int32_t* n_train);
+mars_status mars_mlp_read_params(mars_ctx* ctx, int32_t scene_id, float* params);
+/* sets the master weights, re-quantises, resets the Adam state */
+mars_status mars_mlp_write_params(mars_ctx* ctx, int32_t scene_id, const float* params);
+/* host buffers: x6 [n][6] (q.xyz, n.xyz) -> y3 [n][3] */
+mars_status mars_mlp_forward(mars_ctx* ctx, int32_t scene_id, const float* x6, int32_t n,
+                             float* y3);
+/* gradient of the weighted squared loss over one batch (no update):
+ * x6 [n][6], target [n][3], weight [n][3] -> grad [num_params], *loss */
+mars_status mars_mlp_grad(mars_ctx* ctx, int32_t scene_id, const float* x6, const float* target,
+                          const float* weight, int32_t n, float* grad, float* loss);
+/* one Adam step with the given gradient (host [num_params]) */
+mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* grad, float lr);
 
 /* ---- measurement ------------------------------------------------------- */
 /* Per-kernel timing with HIP events recorded on the context's stream around

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "MARS_OK", -1: "MARS_E_ARG", -2: "MARS_E_OOM", -3: "MARS_E_HI
 MODE_PT, MODE_PT_GUIDED, MODE_BDPT = 0, 1, 2
 ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_MLP = 0, 1, 2, 3
 IMAGE_MEAN, IMAGE_IVW, IMAGE_LAST = 0, 1, 2
+SCENE_MLP = 1
 
 alloc_fn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 free_fn = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -34,7 +35,7 @@ class mars_scene_desc(C.Structure):
                 ("width", C.c_int32), ("height", C.c_int32), ("mode", C.c_int32),
                 ("max_depth", C.c_int32), ("max_cells", C.c_int32), ("max_tree_depth", C.c_int32),
                 ("split_visits", C.c_int32), ("nee_enabled", C.c_int32), ("seed", C.c_uint64),
-                ("queue_capacity", C.c_int64), ("tile_roots", C.c_int32), ("reserved", C.c_int32)]
+                ("queue_capacity", C.c_int64), ("tile_roots", C.c_int32), ("flags", C.c_int32)]
 
 
 class mars_iter_params(C.Structure):
@@ -101,6 +102,12 @@ SIGNATURES = {
     "mars_profile_read": [P, P, P, I32, PI32],
     "mars_trace_counting": [P, I32],
     "mars_read_trace_counts": [P, P],
+    "mars_mlp_train": [P, I32, I32, I32, C.c_float, P, PI32],
+    "mars_mlp_read_params": [P, I32, P],
+    "mars_mlp_write_params": [P, I32, P],
+    "mars_mlp_forward": [P, I32, P, I32, P],
+    "mars_mlp_grad": [P, I32, P, P, P, I32, P, P],
+    "mars_mlp_apply_grad": [P, I32, P, C.c_float],
 }
 
 _lib = None
@@ -121,6 +128,8 @@ def lib():
         L.mars_last_error.restype = C.c_char_p
         L.mars_profile_kernel_name.argtypes = [I32]
         L.mars_profile_kernel_name.restype = C.c_char_p
+        L.mars_mlp_num_params.argtypes = []
+        L.mars_mlp_num_params.restype = C.c_int32
         L.mars_version.argtypes = []
         L.mars_version.restype = C.c_char_p
         _lib = L
@@ -291,6 +300,39 @@ def mars_read_trace_counts(ctx):
     out = (C.c_uint64 * 6)()
     _call("mars_read_trace_counts", ctx, C.cast(out, C.c_void_p))
     return list(out)
+
+
+def mars_mlp_num_params():
+    return lib().mars_mlp_num_params()
+
+
+def mars_mlp_train(ctx, sid, steps, batch, lr):
+    loss = C.c_float()
+    n = C.c_int32()
+    _call("mars_mlp_train", ctx, sid, steps, batch, float(lr), C.byref(loss), C.byref(n))
+    return loss.value, n.value
+
+
+def mars_mlp_read_params(ctx, sid, ptr):
+    _call("mars_mlp_read_params", ctx, sid, ptr)
+
+
+def mars_mlp_write_params(ctx, sid, ptr):
+    _call("mars_mlp_write_params", ctx, sid, ptr)
+
+
+def mars_mlp_forward(ctx, sid, x_ptr, n, y_ptr):
+    _call("mars_mlp_forward", ctx, sid, x_ptr, n, y_ptr)
+
+
+def mars_mlp_grad(ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr):
+    loss = C.c_float()
+    _call("mars_mlp_grad", ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr, C.byref(loss))
+    return loss.value
+
+
+def mars_mlp_apply_grad(ctx, sid, g_ptr, lr):
+    _call("mars_mlp_apply_grad", ctx, sid, g_ptr, float(lr))
 
 
 def mars_version():

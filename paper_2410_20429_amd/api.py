@@ -8,8 +8,8 @@ import ctypes as C
 import numpy as np
 
 from . import _capi as capi
-from ._capi import (ALLOC_CLASSIC, ALLOC_FIXED, ALLOC_MARS, IMAGE_IVW, IMAGE_LAST,  # noqa: F401
-                    IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, MarsError)
+from ._capi import (ALLOC_CLASSIC, ALLOC_FIXED, ALLOC_MARS, ALLOC_MLP, IMAGE_IVW,  # noqa: F401
+                    IMAGE_LAST, IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, SCENE_MLP, MarsError)
 
 VERTEX_DTYPE = np.dtype([("root", "<u4"), ("depth", "<u4"), ("stream_lo", "<u4"),
                          ("stream_hi", "<u4"), ("cell", "<u4"), ("beta", "<f4", 3),
@@ -90,7 +90,7 @@ class Scene:
 
     def __init__(self, ctx: Context, scene: dict, mode=MODE_PT, max_depth=5, max_cells=65536,
                  max_tree_depth=8, split_visits=32, nee=True, seed=1, queue_capacity=0,
-                 tile_roots=0):
+                 tile_roots=0, mlp=False):
         self.ctx = ctx
         self.V = np.ascontiguousarray(scene["V"], np.float32)
         self.tm = np.ascontiguousarray(scene["tri_mat"], np.uint32)
@@ -101,7 +101,8 @@ class Scene:
         d = capi.mars_scene_desc(_p(self.V), _p(self.tm), _p(self.mats), _p(self.cam),
                                  self.V.shape[0], self.mats.shape[0], self.W, self.H, mode,
                                  max_depth, max_cells, max_tree_depth, split_visits, int(bool(nee)),
-                                 seed, int(queue_capacity), int(tile_roots), 0)
+                                 seed, int(queue_capacity), int(tile_roots),
+                                 SCENE_MLP if mlp else 0)
         self.id = capi.mars_scene_upload(ctx.h, d)
         self.spp = 0
         self._last = None
@@ -200,6 +201,38 @@ class Scene:
         if n:
             capi.mars_debug_vertices(self.ctx.h, self.id, _p(a), n)
         return a
+
+    # ---- learned cache ----
+    def mlp_train(self, steps=8, batch=32768, lr=1e-3):
+        return capi.mars_mlp_train(self.ctx.h, self.id, steps, batch, lr)
+
+    def mlp_params(self):
+        a = np.zeros(capi.mars_mlp_num_params(), np.float32)
+        capi.mars_mlp_read_params(self.ctx.h, self.id, _p(a))
+        return a
+
+    def set_mlp_params(self, params):
+        a = np.ascontiguousarray(params, np.float32)
+        assert a.shape[0] == capi.mars_mlp_num_params()
+        capi.mars_mlp_write_params(self.ctx.h, self.id, _p(a))
+
+    def mlp_forward(self, x6):
+        x = np.ascontiguousarray(x6, np.float32).reshape(-1, 6)
+        y = np.zeros((x.shape[0], 3), np.float32)
+        capi.mars_mlp_forward(self.ctx.h, self.id, _p(x), x.shape[0], _p(y))
+        return y
+
+    def mlp_grad(self, x6, target, weight):
+        x = np.ascontiguousarray(x6, np.float32).reshape(-1, 6)
+        t = np.ascontiguousarray(target, np.float32).reshape(-1, 3)
+        w = np.ascontiguousarray(weight, np.float32).reshape(-1, 3)
+        g = np.zeros(capi.mars_mlp_num_params(), np.float32)
+        loss = capi.mars_mlp_grad(self.ctx.h, self.id, _p(x), _p(t), _p(w), x.shape[0], _p(g))
+        return loss, g
+
+    def mlp_apply_grad(self, grad, lr=1e-3):
+        g = np.ascontiguousarray(grad, np.float32)
+        capi.mars_mlp_apply_grad(self.ctx.h, self.id, _p(g), lr)
 
     def checkpoint_save(self, path):
         capi.mars_checkpoint_save(self.ctx.h, self.id, str(path))

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmars.so")
-SOURCES = ["kernels.hip", "capi.cpp", "bvh_build.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "capi.cpp", "bvh_build.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -69,16 +69,22 @@ struct Scene {
   int bvh_depth = 0;
   int n_bvh_nodes = 0;
   uint32_t dbg_last = 0;
+  // learned cache
+  bool mlp_on = false;
+  MlpDev mlp{};
+  uint32_t mlp_n_train = 0;
+  int mlp_step = 0;
+  uint64_t vertices_last = 0;
 };
 
 // per-kernel HIP-event timing on the context's stream
 enum KernelId {
   KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
-  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_COUNT
+  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
     "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
-    "fixed_point", "hist_normalize", "refine", "ivw", "light"};
+    "fixed_point", "hist_normalize", "refine", "ivw", "light", "mlp_infer", "mlp_train"};
 
 struct Profiler {
   bool on = false;
@@ -227,7 +233,8 @@ void check_params(Scene* s, const mars_iter_params* p) {
   if (p->spp <= 0 || p->spp > 4096) throw Status(MARS_E_ARG, "spp out of range");
   if (p->alloc < 0 || p->alloc > 3) throw Status(MARS_E_ARG, "bad alloc mode");
   if (p->alloc == MARS_ALLOC_FIXED && !s->fixed) throw Status(MARS_E_STATE, "no fixed counts set");
-  if (p->alloc == MARS_ALLOC_MLP) throw Status(MARS_E_ARG, "learned cache not enabled for scene");
+  if (p->alloc == MARS_ALLOC_MLP && !s->mlp_on)
+    throw Status(MARS_E_ARG, "learned cache not enabled for scene");
   if (!(p->clamp_lo > 0.0f) || !(p->clamp_hi >= p->clamp_lo) || !(p->clamp_hi <= 64.0f))
     throw Status(MARS_E_ARG, "count clamp must satisfy 0 < lo <= hi <= 64");
   if (!(p->stat_clamp >= 0.0f)) throw Status(MARS_E_ARG, "stat_clamp must be >= 0");
@@ -284,6 +291,8 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
   timed(c, KID_RAYGEN, [&] { k_raygen(s->sd, s->qd, s->cnt, it, root0, n, st); });
   timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc); });
   for (int d = 1; d <= s->max_depth; ++d) {
+    if (it.alloc == MARS_ALLOC_MLP && d < s->max_depth)
+      timed(c, KID_MLP, [&] { k_mlp_infer_queue(s->sd, s->qd, s->mlp, s->cnt, d, grid * 4, st); });
     timed(c, KID_SHADE, [&] {
       if (bdpt)
         k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, npool,
@@ -329,6 +338,20 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
       s->dbg_cap = (uint32_t)want;
     }
   }
+  // learned cache: outputs for MLP iterations, training vertices always
+  s->cd.mlp_y = nullptr;
+  s->cd.mlp_rec = nullptr;
+  if (s->mlp_on) {
+    if (p->alloc == MARS_ALLOC_MLP) s->cd.mlp_y = s->mlp.y;
+    const double expect = (double)std::max<uint64_t>(s->vertices_last, 1);
+    s->mlp.keep = (uint32_t)std::min(16777216.0, 16777216.0 * (double)s->mlp.rec_cap / expect);
+    if (s->mlp.keep == 0) s->mlp.keep = 1;
+    s->cd.mlp_rec = s->mlp.rec;
+    s->cd.mlp_n_rec = s->mlp.n_rec;
+    s->cd.mlp_rec_cap = s->mlp.rec_cap;
+    s->cd.mlp_keep = s->mlp.keep;
+    k_fill_u32(s->mlp.n_rec, 0u, 4, st);
+  }
   mars_iter_stats S{};
   S.rays_camera = roots;
   if (s->mode == MARS_MODE_BDPT) S.rays_light = trace_light_paths(s, it, roots);
@@ -366,12 +389,47 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   HIPCHK(hipGetLastError());
   s->ctx->prof.flush();
   s->spp_last = p->spp;
+  s->vertices_last = S.vertices;
   s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
   s->dbg_last = dbg_total;
   S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = S;
 }
 
+
+// learned cache initial weights: He-uniform, zero biases, output layer scaled
+// by 0.1, output padding zero (deterministic in the seed)
+void mlp_write_master(Scene* s, const float* params) {
+  hipStream_t st = s->ctx->stream;
+  h2d(s->mlp.master, params, 4 * (size_t)kMlpParams, st);
+  k_fill_f32(s->mlp.m, 0.0f, kMlpParams, st);
+  k_fill_f32(s->mlp.v, 0.0f, kMlpParams, st);
+  k_mlp_quantize(s->mlp, st);
+  HIPCHK(hipStreamSynchronize(st));
+  s->mlp_step = 0;
+}
+void mlp_init(Scene* s, uint64_t seed) {
+  std::vector<float> p(kMlpParams, 0.0f);
+  uint64_t x = seed ^ 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {  // splitmix64 -> uniform in [0, 1)
+    x += 0x9E3779B97F4A7C15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  struct L { int w, rows, cols; double scale; };
+  const L layers[4] = {{kMlpW1, 64, 80, 1.0}, {kMlpW2, 64, 64, 1.0}, {kMlpW3, 64, 64, 1.0},
+                       {kMlpW4, 16, 64, 0.1}};
+  for (const L& l : layers) {
+    const double bound = std::sqrt(6.0 / l.cols) * l.scale;
+    for (int r = 0; r < l.rows; ++r)
+      for (int c = 0; c < l.cols; ++c)
+        p[l.w + r * l.cols + c] = (l.w == kMlpW4 && r >= 3) ? 0.0f : (float)((2.0 * next() - 1.0) * bound);
+  }
+  mlp_write_master(s, p.data());
+}
 
 // ---------------------------------------------------------------------------
 // scene upload: validation, derived quantities in binary64 stored as binary32
@@ -615,6 +673,25 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     k_fill_f32(im.count_map, 0.0f, px * 3, st);
     k_fill_f64(im.red, 0.0, 8, st);
     ensure_roots(s, px);
+    if (d->flags & MARS_SCENE_MLP) {
+      s->mlp_on = true;
+      MlpDev& m = s->mlp;
+      m.master = salloc<float>(s, kMlpParams);
+      m.wq = salloc<uint16_t>(s, kMlpParams);
+      m.m = salloc<float>(s, kMlpParams);
+      m.v = salloc<float>(s, kMlpParams);
+      m.partial = salloc<float>(s, (size_t)kMlpMaxBlocks * (kMlpParams + 1));
+      m.y = salloc<float>(s, lv * 4);
+      m.rec_cap = 1u << 18;
+      m.rec = salloc<float4>(s, 3 * (size_t)m.rec_cap);
+      m.n_rec = salloc<uint32_t>(s, 4);
+      m.x6 = salloc<float>(s, 6 * (size_t)m.rec_cap);
+      m.tgt = salloc<float>(s, 3 * (size_t)m.rec_cap);
+      m.wt = salloc<float>(s, 3 * (size_t)m.rec_cap);
+      m.keep = 1u << 24;
+      mlp_init(s, d->seed);
+      k_fill_u32(m.n_rec, 0u, 4, st);
+    }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
   } catch (...) {
@@ -642,6 +719,12 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   });
   if (s->mode == MARS_MODE_PT_GUIDED)
     timed(c, KID_HIST, [&] { k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, st); });
+  if (s->mlp_on) {
+    IterDev itd = p ? to_dev(p) : IterDev{};
+    timed(c, KID_MLP, [&] {
+      k_mlp_targets(s->sd, s->cd, s->mlp, s->img, itd, s->mlp.rec_cap, st);
+    });
+  }
   timed(c, KID_REFINE, [&] {
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
              s->max_tree_depth, s->max_cells, st);
@@ -649,13 +732,16 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   timed(c, KID_IVW, [&] { k_ivw(s->img, npx, spp, st); });
   double red[8];
   int32_t nc[4];
+  uint32_t nrec = 0;
   d2h(red, s->img.red, sizeof(red), st);
   d2h(nc, s->n_cells_dev, sizeof(nc), st);
+  if (s->mlp_on) d2h(&nrec, s->mlp.n_rec, 4, st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   c->prof.flush();
   s->n_cells = nc[0];
   s->n_nodes = nc[1];
+  if (s->mlp_on) s->mlp_n_train = std::min(nrec, s->mlp.rec_cap);
   if (out) {
     out->V_I = red[4] > 0.0 ? red[3] / red[4] : 0.0;
     out->C_I = C_I;
@@ -686,6 +772,40 @@ void dev_out(Ctx* c, float* dst, const float* src, size_t n, int dst_is_device) 
   HIPCHK(hipMemcpyAsync(dst, src, n * 4, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+}
+}  // namespace
+
+namespace {
+Scene* mlp_scene(Ctx* ctx, int32_t id) {
+  Scene* s = ctx->scene(id);
+  if (!s->mlp_on) throw Status(MARS_E_STATE, "learned cache not enabled for scene");
+  return s;
+}
+// one Adam step over `batch` samples of (x6, tgt, wt) starting at offset
+void mlp_step_once(Scene* s, const float* x6, const float* tgt, const float* wt, int n_set,
+                   int offset, int batch, float lr, float* loss_dev) {
+  hipStream_t st = s->ctx->stream;
+  int nb = 0;
+  k_mlp_train_pass(s->mlp, x6, tgt, wt, n_set, offset, batch, &nb, st);
+  s->mlp_step += 1;
+  const float bc1 = (float)(1.0 - std::pow(0.9, s->mlp_step));
+  const float bc2 = (float)(1.0 - std::pow(0.99, s->mlp_step));
+  k_mlp_adam(s->mlp, nb, nullptr, lr, bc1, bc2, loss_dev, st);
+}
+}  // namespace
+
+namespace {
+template <typename F>
+void with_device_buffers(Ctx* c, std::initializer_list<size_t> sizes, F&& f) {
+  std::vector<void*> bufs;
+  try {
+    for (size_t b : sizes) bufs.push_back(c->dalloc(b));
+    f(bufs);
+  } catch (...) {
+    for (void* p : bufs) c->dfree(p);
+    throw;
+  }
+  for (void* p : bufs) c->dfree(p);
 }
 }  // namespace
 
@@ -1114,10 +1234,134 @@ mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* pa
   });
 }
 
+int32_t mars_mlp_num_params(void) { return kMlpParams; }
+
+
+mars_status mars_mlp_train(mars_ctx* ctx, int32_t scene_id, int32_t steps, int32_t batch, float lr,
+                           float* loss, int32_t* n_train) {
+  if (!ctx || steps < 0 || batch <= 0 || !(lr > 0.0f)) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    const int n = (int)s->mlp_n_train;
+    if (n_train) *n_train = n;
+    if (n == 0 || steps == 0) {
+      if (loss) *loss = 0.0f;
+      return;
+    }
+    const int b = std::min(batch, std::min(n, kMlpMaxBlocks * 16 * 64));
+    float* ld = (float*)ctx->dalloc(16);
+    try {
+      for (int k = 0; k < steps; ++k) {
+        const int off = (int)(((int64_t)(s->mlp_step) * b) % n);
+        timed(ctx, KID_MLP_TRAIN, [&] {
+          mlp_step_once(s, s->mlp.x6, s->mlp.tgt, s->mlp.wt, n, off, b, lr, ld);
+        });
+      }
+      float l = 0.0f;
+      d2h(&l, ld, 4, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      ctx->prof.flush();
+      if (loss) *loss = l;
+    } catch (...) {
+      ctx->dfree(ld);
+      throw;
+    }
+    ctx->dfree(ld);
+  });
+}
+
+mars_status mars_mlp_read_params(mars_ctx* ctx, int32_t scene_id, float* params) {
+  if (!ctx || !params) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    d2h(params, s->mlp.master, 4 * (size_t)kMlpParams, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_mlp_write_params(mars_ctx* ctx, int32_t scene_id, const float* params) {
+  if (!ctx || !params) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    for (int i = 0; i < kMlpParams; ++i)
+      if (!std::isfinite(params[i])) throw Status(MARS_E_NONFINITE, "non-finite parameter");
+    mlp_write_master(s, params);
+  });
+}
+
+
+mars_status mars_mlp_forward(mars_ctx* ctx, int32_t scene_id, const float* x6, int32_t n,
+                             float* y3) {
+  if (!ctx || !x6 || !y3 || n <= 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    with_device_buffers(ctx, {24 * (size_t)n, 12 * (size_t)n}, [&](std::vector<void*>& b) {
+      h2d(b[0], x6, 24 * (size_t)n, ctx->stream);
+      k_mlp_forward(s->mlp, (const float*)b[0], n, (float*)b[1], ctx->stream);
+      d2h(y3, b[1], 12 * (size_t)n, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipGetLastError());
+    });
+  });
+}
+
+mars_status mars_mlp_grad(mars_ctx* ctx, int32_t scene_id, const float* x6, const float* target,
+                          const float* weight, int32_t n, float* grad, float* loss) {
+  if (!ctx || !x6 || !target || !weight || !grad || n <= 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    if (n > kMlpMaxBlocks * 16 * 64) throw Status(MARS_E_ARG, "batch too large");
+    with_device_buffers(ctx, {24 * (size_t)n, 12 * (size_t)n, 12 * (size_t)n, 4 * (size_t)kMlpParams + 4},
+                        [&](std::vector<void*>& b) {
+      h2d(b[0], x6, 24 * (size_t)n, ctx->stream);
+      h2d(b[1], target, 12 * (size_t)n, ctx->stream);
+      h2d(b[2], weight, 12 * (size_t)n, ctx->stream);
+      int nb = 0;
+      k_mlp_train_pass(s->mlp, (const float*)b[0], (const float*)b[1], (const float*)b[2], n, 0, n,
+                       &nb, ctx->stream);
+      float* g = (float*)b[3];
+      k_mlp_sum_partials(s->mlp, nb, g, g + kMlpParams, ctx->stream);
+      d2h(grad, g, 4 * (size_t)kMlpParams, ctx->stream);
+      float l = 0.0f;
+      d2h(&l, g + kMlpParams, 4, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipGetLastError());
+      if (loss) *loss = l;
+    });
+  });
+}
+
+mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* grad, float lr) {
+  if (!ctx || !grad || !(lr > 0.0f)) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    with_device_buffers(ctx, {4 * (size_t)kMlpParams}, [&](std::vector<void*>& b) {
+      h2d(b[0], grad, 4 * (size_t)kMlpParams, ctx->stream);
+      s->mlp_step += 1;
+      const float bc1 = (float)(1.0 - std::pow(0.9, s->mlp_step));
+      const float bc2 = (float)(1.0 - std::pow(0.99, s->mlp_step));
+      k_mlp_adam(s->mlp, 0, (const float*)b[0], lr, bc1, bc2, nullptr, ctx->stream);
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipGetLastError());
+    });
+  });
+}
+
 mars_status mars_probe(mars_ctx* ctx, int32_t kind, int32_t n, const void* in, void* out) {
   if (!ctx || !in || !out || n <= 0) return MARS_E_ARG;
   return guard(ctx, [&] {
     size_t ib, ob;
+    if (kind == 3) {  // one 16x16x16 bfloat16 matrix-core product: in = A, B (u16), out = D
+      if (n != 1) throw Status(MARS_E_ARG, "mfma probe takes n = 1");
+      with_device_buffers(ctx, {1024, 1024}, [&](std::vector<void*>& b) {
+        h2d(b[0], in, 1024, ctx->stream);
+        k_mfma_probe((const uint16_t*)b[0], (const uint16_t*)b[0] + 256, (float*)b[1], ctx->stream);
+        d2h(out, b[1], 1024, ctx->stream);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+      });
+      return;
+    }
     if (kind == 0) { ib = 24; ob = 16; }
     else if (kind == 1) { ib = 4; ob = 8; }
     else if (kind == 2) { ib = 16; ob = 12; }

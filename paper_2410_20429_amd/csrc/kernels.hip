@@ -314,6 +314,33 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
   }
 }
 
+// learned cache (alloc mode 3): beta_t = |T / I~| exp(y_t), clamped; the
+// octree count stays where the network output is not finite
+__device__ __forceinline__ void mlp_counts(const CacheDev& c, const IterDev& it, size_t e, f3 T,
+                                           const float* It, float beta[3]) {
+  if (it.alloc != 3 || !c.mlp_y) return;
+  const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
+  const float sm = sqrtf(((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f));
+  const float* y = c.mlp_y + e * 4;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!(beta[t] > 0.0f)) continue;
+    const float b = sm * expf(y[t]);
+    if (isfinite(b)) beta[t] = fminf(fmaxf(b, it.clamp_lo), it.clamp_hi);
+  }
+}
+
+// training vertices for the learned cache: a seeded random subset
+__device__ __forceinline__ void mlp_record(const CacheDev& c, uint2 strm, f3 x, uint32_t pix, f3 n,
+                                           f3 T) {
+  if (!c.mlp_rec || (strm.x >> 8) >= c.mlp_keep) return;
+  const uint32_t k = atomicAdd(c.mlp_n_rec, 1u);
+  if (k >= c.mlp_rec_cap) return;
+  c.mlp_rec[3 * (size_t)k] = make_float4(x.x, x.y, x.z, __uint_as_float(pix));
+  c.mlp_rec[3 * (size_t)k + 1] = make_float4(n.x, n.y, n.z, 0.0f);
+  c.mlp_rec[3 * (size_t)k + 2] = make_float4(T.x, T.y, T.z, 0.0f);
+}
+
 // ---------------------------------------------------------------------------
 // shading of unidirectional paths (Sec. 3.1, Sec. 4): emission with its
 // direct-light MIS weight, cell lookup, counts, Alg. 1 rounding, and the
@@ -382,9 +409,11 @@ __global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, 
           It[1] = img.itilde[3 * (size_t)pix + 1];
           It[2] = img.itilde[3 * (size_t)pix + 2];
           counts_at(sc, c, it, cell, T, It, d, beta);
+          mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
           round_counts(beta, u.x, gam);
+          mlp_record(c, strm, x, pix, n_s, T);
         }
       }
     }
@@ -1003,9 +1032,11 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
           cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
           T = xyz(q.S0[L + j]);
           counts_at(sc, c, it, cell, T, It, d, beta);
+          mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
           round_counts(beta, u.x, gam);
+          mlp_record(c, strm, x, pix, n_s, T);
           const int imax0 = sc.max_depth - d - 1;
           for (uint32_t k = 0; k < gam[2]; ++k) {
             const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
@@ -1298,6 +1329,55 @@ void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s) {
   backprop_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
+}
+
+// ---------------------------------------------------------------------------
+// training targets of the learned cache, from the cells' updated factors:
+//   y*_t = log(beta^_t) - log|T / I~|, beta^_t the resolved, unclamped
+//   octree count of the vertex; weight min(n_t,c, 64) / 64 if the cell had at
+//   least 4 samples of technique t in the iteration, else 0
+// ---------------------------------------------------------------------------
+__global__ void mlp_targets_kernel(SceneDev sc, CacheDev c, MlpDev m, ImageDev img, IterDev it,
+                                   uint32_t cap) {
+  const uint32_t n = min(*m.n_rec, cap);
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const float4 a = m.rec[3 * (size_t)r], b = m.rec[3 * (size_t)r + 1], tt = m.rec[3 * (size_t)r + 2];
+  const f3 P = xyz(a);
+  const uint32_t pix = __float_as_uint(a.w);
+  float* x = m.x6 + 6 * (size_t)r;
+  x[0] = fminf(fmaxf((P.x - sc.oct_lo[0]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[1] = fminf(fmaxf((P.y - sc.oct_lo[1]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[2] = fminf(fmaxf((P.z - sc.oct_lo[2]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[3] = b.x; x[4] = b.y; x[5] = b.z;
+  const float z0 = tt.x / img.itilde[3 * (size_t)pix], z1 = tt.y / img.itilde[3 * (size_t)pix + 1],
+              z2 = tt.z / img.itilde[3 * (size_t)pix + 2];
+  const float sm = sqrtf(((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f));
+  const uint32_t cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, P);
+  const bool en[3] = {true, sc.nee != 0 && sc.n_lights > 0, sc.mode != 0};
+  for (int t = 0; t < 3; ++t) {
+    float y = 0.0f, w = 0.0f;
+    const double cnt = c.acc[((size_t)cell * 3 + t) * 8 + 6];
+    const float* aRR = c.fac + (size_t)cell * 18 + (0 * 3 + t) * 3;
+    const float* aS = c.fac + (size_t)cell * 18 + (1 * 3 + t) * 3;
+    if (en[t] && cnt >= 4.0 && aRR[0] >= 0.0f && sm > 0.0f) {
+      const float sr = ((z0 * z0) * aRR[0] + (z1 * z1) * aRR[1]) + (z2 * z2) * aRR[2];
+      const float ss = ((z0 * z0) * aS[0] + (z1 * z1) * aS[1]) + (z2 * z2) * aS[2];
+      const float bRR = sqrtf(sr * (1.0f / 3.0f)), bS = sqrtf(ss * (1.0f / 3.0f));
+      const float bh = bRR < 1.0f ? bRR : (bS > 1.0f ? bS : 1.0f);
+      if (bh > 0.0f && isfinite(bh)) {
+        y = logf(bh) - logf(sm);
+        w = (float)(fmin(cnt, 64.0) / 64.0);
+      }
+    }
+    m.tgt[3 * (size_t)r + t] = y;
+    m.wt[3 * (size_t)r + t] = isfinite(y) ? w : 0.0f;
+    if (!isfinite(y)) m.tgt[3 * (size_t)r + t] = 0.0f;
+  }
+}
+void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const ImageDev& img,
+                   const IterDev& it, uint32_t n, hipStream_t s) {
+  if (n) mlp_targets_kernel<<<(n + 255) / 256, 256, 0, s>>>(sc, c, m, img, it, n);
 }
 
 // ---------------------------------------------------------------------------

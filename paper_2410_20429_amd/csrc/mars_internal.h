@@ -45,6 +45,10 @@ struct CacheDev {
   const float* fixed;    // [n_fixed][3]
   int32_t n_fixed;
   int32_t max_cells;
+  const float* mlp_y;    // learned-cache outputs per queue entry ([d * cap + j][4]), or null
+  float4* mlp_rec;       // training vertex records, or null
+  uint32_t* mlp_n_rec;
+  uint32_t mlp_rec_cap, mlp_keep;
 };
 
 // per-depth SoA queues; entry (d, j) lives at d * cap + j
@@ -111,6 +115,28 @@ struct ImageDev {
   double* red;      // [8] reductions: image mean rgb, V_I sum, included count, ...
 };
 
+// learned cache: parameter layout (binary32 master) -- W1 [64][80], b1 [64],
+// W2 [64][64], b2, W3 [64][64], b3, W4 [16][64] (rows 3..15 zero), b4 [16]
+constexpr int kMlpW1 = 0, kMlpB1 = 5120, kMlpW2 = 5184, kMlpB2 = 9280, kMlpW3 = 9344,
+              kMlpB3 = 13440, kMlpW4 = 13504, kMlpB4 = 14528, kMlpParams = 14544;
+constexpr int kMlpMaxBlocks = 256;  // workgroups of one training pass
+
+struct MlpDev {
+  float* master;    // [kMlpParams]
+  uint16_t* wq;     // bfloat16 weights
+  float* m;         // Adam first moments
+  float* v;         // Adam second moments
+  float* partial;   // [kMlpMaxBlocks][kMlpParams + 1] gradient partials + loss
+  float* y;         // [levels * cap][4] outputs at the queue vertices
+  float4* rec;      // [rec_cap][3] training vertices: (P, pixel), (n, -), (T, -)
+  uint32_t* n_rec;  // number of records written
+  uint32_t rec_cap;
+  uint32_t keep;    // a vertex is recorded if (stream.lo >> 8) < keep
+  float* x6;        // [rec_cap][6] training inputs
+  float* tgt;       // [rec_cap][3] targets (log counts relative to |T / I~|)
+  float* wt;        // [rec_cap][3] loss weights
+};
+
 // ---- launchers (kernels.hip) ----
 void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void k_fill_f64(double* p, double v, size_t n, hipStream_t s);
@@ -137,6 +163,19 @@ void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, con
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s);
+void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const ImageDev& img,
+                   const IterDev& it, uint32_t n, hipStream_t s);
+// ---- launchers (mlp.hip) ----
+void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream_t s);
+void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
+                       int d, int grid, hipStream_t s);
+void k_mlp_train_pass(const MlpDev& m, const float* x6, const float* tgt, const float* wt, int n_set,
+                      int offset, int batch, int* nblocks_out, hipStream_t s);
+void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, float bc1, float bc2,
+                float* loss_out, hipStream_t s);
+void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, hipStream_t s);
+void k_mlp_quantize(const MlpDev& m, hipStream_t s);
+void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s);
 void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s);
 void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
                     float stat_clamp, hipStream_t s);

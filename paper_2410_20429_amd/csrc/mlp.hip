@@ -1,0 +1,384 @@
+// Learned cache: a small MLP that predicts the log sample count of every
+// technique from a vertex's normalised position and shading normal
+// (sin/cos encoding with 6 frequencies -> 72 features, padded to 80; three
+// hidden layers of 64 ReLU units; 3 linear outputs).  Forward and backward
+// run as bfloat16 matrix-core products with binary32 accumulation
+// (v_mfma_f32_16x16x16_bf16), one 16-sample tile per wave.  Master weights,
+// biases and Adam moments are binary32.
+//
+// MFMA 16x16x16 operand layout (lane l = 0..63, element r = 0..3):
+//   A (16 x 16, M x K): A[l % 16][4 (l / 16) + r]
+//   B (16 x 16, K x N): B[4 (l / 16) + r][l % 16]
+//   D (16 x 16, M x N): D[4 (l / 16) + r][l % 16]
+#include <hip/hip_runtime.h>
+
+#include "device_math.hpp"
+#include "mars_internal.h"
+
+namespace mars {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0;  // NaN stays NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ v4f mma(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// bfloat16 copy of the weights (biases are read in binary32 from the master)
+constexpr int qW1 = 0, qW2 = 5120, qW3 = 9216, qW4 = 13312, kQW = 14336;
+__host__ __device__ constexpr int qindex(int p) {
+  return p < kMlpB1 ? p
+       : (p >= kMlpW2 && p < kMlpB2) ? qW2 + (p - kMlpW2)
+       : (p >= kMlpW3 && p < kMlpB3) ? qW3 + (p - kMlpW3)
+       : (p >= kMlpW4 && p < kMlpB4) ? qW4 + (p - kMlpW4) : -1;
+}
+
+// features of one vertex: x = (q.xyz, n.xyz); f[(d*6+k)*2 + s] = sin/cos(2^k pi x_d)
+__device__ __forceinline__ float feature(const float* x, int k) {
+  if (k >= 72) return 0.0f;
+  const int d = k / 12, kk = (k % 12) >> 1;
+  const float a = ldexpf(x[d], kk);
+  return (k & 1) ? cospif(a) : sinpif(a);
+}
+
+// Forward pass of one 16-sample tile by one wave.  x: this lane's sample
+// inputs (sample = lane % 16).  Hidden activations go to hs[l][16][64]
+// (bfloat16), features to xs[16][80] when xs != nullptr.  Returns the output
+// tile in D layout (rows = samples, columns = outputs).
+__device__ v4f mlp_forward_tile(const float* __restrict__ master, const uint16_t* __restrict__ wq,
+                                const float* x, uint16_t (*hs)[16][64], uint16_t (*xs)[80]) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  v4f acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 5; ++ks) {
+    v4s a;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 16 * ks + 4 * lg + r;
+      const uint16_t h = to_bf16(feature(x, k));
+      a[r] = (short)h;
+      if (xs) xs[lr][k] = h;
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const uint16_t* w = wq + qW1 + (16 * nt + lr) * 80 + 16 * ks + 4 * lg;
+      const v4s b = {(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+      acc[nt] = mma(a, b, acc[nt]);
+    }
+  }
+  int boff[3] = {kMlpB1, kMlpB2, kMlpB3};
+  int woff[3] = {qW2, qW3, qW4};
+  for (int l = 0; l < 3; ++l) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * nt + lr;
+        const float z = acc[nt][r] + master[boff[l] + j];
+        hs[l][4 * lg + r][j] = to_bf16(fmaxf(z, 0.0f));
+      }
+    __syncthreads();
+    const int ntn = l < 2 ? 4 : 1;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const uint16_t* hr = &hs[l][lr][16 * ks + 4 * lg];
+      const v4s a = {(short)hr[0], (short)hr[1], (short)hr[2], (short)hr[3]};
+      for (int nt = 0; nt < ntn; ++nt) {
+        const uint16_t* w = wq + woff[l] + (16 * nt + lr) * 64 + 16 * ks + 4 * lg;
+        const v4s b = {(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+        acc[nt] = mma(a, b, acc[nt]);
+      }
+    }
+  }
+  v4f y = acc[0];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] += master[kMlpB4 + lr];
+  return y;
+}
+
+// inference over a list of vertices given as (q, n); 64-thread workgroups
+__global__ __launch_bounds__(64) void mlp_infer_inputs_kernel(MlpDev m, const float* x6, int n,
+                                                              float* y3) {
+  __shared__ uint16_t hs[3][16][64];
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  for (int tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
+    const int s = tile * 16 + lr;
+    float x[6] = {0, 0, 0, 0, 0, 0};
+    if (s < n)
+      for (int k = 0; k < 6; ++k) x[k] = x6[6 * (size_t)s + k];
+    const v4f y = mlp_forward_tile(m.master, m.wq, x, hs, nullptr);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int si = tile * 16 + 4 * lg + r;
+      if (si < n && lr < 3) y3[3 * (size_t)si + lr] = y[r];
+    }
+    __syncthreads();
+  }
+}
+void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream_t s) {
+  const int tiles = (n + 15) / 16;
+  mlp_infer_inputs_kernel<<<std::min(tiles, 8192), 64, 0, s>>>(m, x6, n, y3);
+}
+
+// inference at the vertices of one depth's queue (hits with d < D): inputs
+// from the hit point and the shading normal, outputs to m.y[d * cap + j]
+__global__ __launch_bounds__(64) void mlp_infer_queue_kernel(SceneDev sc, QueuesDev q, MlpDev m,
+                                                             const Counters* cnt, int d) {
+  __shared__ uint16_t hs[3][16][64];
+  if (cnt->overflow) return;
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap;
+  for (uint32_t tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
+    const uint32_t s = tile * 16 + lr;
+    float x[6] = {0, 0, 0, 0, 0, 0};
+    if (s < n) {
+      const uint2 h = q.H[L + s];
+      if (h.y != kMiss) {
+        const float4 r0 = q.R0[L + s], r1 = q.R1[L + s];
+        const float t = __uint_as_float(h.x);
+        const f3 ng = xyz(sc.tri_ng[h.y]);
+        const f3 p = mk3(r0.x + t * r1.x, r0.y + t * r1.y, r0.z + t * r1.z);
+        const f3 ns = dot3(ng, xyz(r1)) < 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+        x[0] = fminf(fmaxf((p.x - sc.oct_lo[0]) * sc.oct_inv, 0.0f), kOneMinus);
+        x[1] = fminf(fmaxf((p.y - sc.oct_lo[1]) * sc.oct_inv, 0.0f), kOneMinus);
+        x[2] = fminf(fmaxf((p.z - sc.oct_lo[2]) * sc.oct_inv, 0.0f), kOneMinus);
+        x[3] = ns.x; x[4] = ns.y; x[5] = ns.z;
+      }
+    }
+    const v4f y = mlp_forward_tile(m.master, m.wq, x, hs, nullptr);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t si = tile * 16 + 4 * lg + r;
+      if (si < n && lr < 3) m.y[(L + si) * 4 + lr] = y[r];
+    }
+    __syncthreads();
+  }
+}
+void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
+                       int d, int grid, hipStream_t s) {
+  mlp_infer_queue_kernel<<<grid, 64, 0, s>>>(sc, q, m, cnt, d);
+}
+
+// ---------------------------------------------------------------------------
+// training: loss L = (1/N) sum_i sum_t w_it (y_it - y*_it)^2 over a batch of
+// N samples taken cyclically from the training set starting at `offset`.
+// One wave per workgroup walks a contiguous chunk of tiles and accumulates
+// the gradient in LDS (binary32, fixed order); each workgroup writes its
+// partial gradient; the Adam kernel sums the partials in workgroup order.
+// ---------------------------------------------------------------------------
+struct TrainLds {
+  uint16_t xs[16][80];
+  uint16_t hs[3][16][64];
+  uint16_t dz[16][64];
+  float g[kMlpParams];
+  float loss;
+};
+
+__device__ __forceinline__ void dense_backward(const uint16_t* __restrict__ wq, int qoff, int nout,
+                                               int nin, const uint16_t* hprev, int hstride,
+                                               float* gW, float* gb, v4f* dz_in,
+                                               uint16_t (*dzs)[64], v4f* dprev, bool want_prev) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int nto = nout / 16, nti = nin / 16;
+  // dZ to LDS (bfloat16) and the bias gradient
+  for (int nt = 0; nt < nto; ++nt) {
+    float sacc = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      dzs[4 * lg + r][16 * nt + lr] = to_bf16(dz_in[nt][r]);
+      sacc += dz_in[nt][r];
+    }
+    sacc += __shfl_xor(sacc, 16, 64);
+    sacc += __shfl_xor(sacc, 32, 64);
+    if (lg == 0) gb[16 * nt + lr] += sacc;
+  }
+  __syncthreads();
+  // weight gradient: dW[o][i] += sum_samples dZ[s][o] Hprev[s][i]
+  for (int mt = 0; mt < nto; ++mt)
+    for (int nt = 0; nt < nti; ++nt) {
+      v4s a, b;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[r] = (short)dzs[4 * lg + r][16 * mt + lr];
+        b[r] = (short)hprev[(4 * lg + r) * hstride + 16 * nt + lr];
+      }
+      const v4f d = mma(a, b, v4f{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gW[(16 * mt + 4 * lg + r) * nin + 16 * nt + lr] += d[r];
+    }
+  if (!want_prev) return;
+  // dHprev[s][i] = sum_o dZ[s][o] W[o][i], then the ReLU mask of Hprev
+  for (int nt = 0; nt < nti; ++nt) {
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ks = 0; ks < nto; ++ks) {
+      v4s a, b;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[r] = (short)dzs[lr][16 * ks + 4 * lg + r];
+        b[r] = (short)wq[qoff + (16 * ks + 4 * lg + r) * nin + 16 * nt + lr];
+      }
+      acc = mma(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float hp = from_bf16(hprev[(4 * lg + r) * hstride + 16 * nt + lr]);
+      acc[r] = hp > 0.0f ? acc[r] : 0.0f;
+    }
+    dprev[nt] = acc;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6, const float* tgt,
+                                                       const float* wt, int n_set, int offset,
+                                                       int batch, int tiles_per_block) {
+  __shared__ TrainLds S;
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  for (int p = lane; p < kMlpParams; p += 64) S.g[p] = 0.0f;
+  if (lane == 0) S.loss = 0.0f;
+  __syncthreads();
+  const int ntiles = (batch + 15) / 16;
+  const int t0 = blockIdx.x * tiles_per_block, t1 = min(ntiles, t0 + tiles_per_block);
+  const float inv_n = 1.0f / (float)batch;
+  float lsum = 0.0f;
+  for (int tile = t0; tile < t1; ++tile) {
+    const int bi = tile * 16 + lr;
+    float x[6] = {0, 0, 0, 0, 0, 0};
+    if (bi < batch) {
+      const size_t s = (size_t)((offset + bi) % n_set);
+      for (int k = 0; k < 6; ++k) x[k] = x6[6 * s + k];
+    }
+    const v4f y = mlp_forward_tile(m.master, m.wq, x, S.hs, S.xs);
+    v4f dz[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int bs = tile * 16 + 4 * lg + r;
+      float g = 0.0f;
+      if (bs < batch && lr < 3) {
+        const size_t s = (size_t)((offset + bs) % n_set);
+        const float w = wt[3 * s + lr];
+        const float df = y[r] - tgt[3 * s + lr];
+        g = (2.0f * w * df) * inv_n;
+        lsum += (w * df * df) * inv_n;
+      }
+      dz[0][r] = g;
+    }
+    v4f dp[5];
+    dense_backward(m.wq, qW4, 16, 64, &S.hs[2][0][0], 64, S.g + kMlpW4, S.g + kMlpB4, dz, S.dz, dp,
+                   true);
+    dense_backward(m.wq, qW3, 64, 64, &S.hs[1][0][0], 64, S.g + kMlpW3, S.g + kMlpB3, dp, S.dz, dz,
+                   true);
+    dense_backward(m.wq, qW2, 64, 64, &S.hs[0][0][0], 64, S.g + kMlpW2, S.g + kMlpB2, dz, S.dz, dp,
+                   true);
+    dense_backward(m.wq, qW1, 64, 80, &S.xs[0][0], 80, S.g + kMlpW1, S.g + kMlpB1, dp, S.dz, dz,
+                   false);
+    __syncthreads();
+  }
+  lsum += __shfl_xor(lsum, 1, 64);
+  lsum += __shfl_xor(lsum, 2, 64);
+  lsum += __shfl_xor(lsum, 4, 64);
+  lsum += __shfl_xor(lsum, 8, 64);
+  lsum += __shfl_xor(lsum, 16, 64);
+  lsum += __shfl_xor(lsum, 32, 64);
+  float* out = m.partial + (size_t)blockIdx.x * (kMlpParams + 1);
+  for (int p = lane; p < kMlpParams; p += 64) out[p] = S.g[p];
+  if (lane == 0) out[kMlpParams] = lsum;
+}
+
+// Adam (binary32): the gradient is the sum of the workgroup partials in
+// workgroup order
+__global__ void mlp_adam_kernel(MlpDev m, int nblocks, const float* ext_grad, float lr, float bc1,
+                                float bc2, float* loss_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0 && loss_out) {
+    float l = 0.0f;
+    for (int b = 0; b < nblocks; ++b) l += m.partial[(size_t)b * (kMlpParams + 1) + kMlpParams];
+    *loss_out = l;
+  }
+  if (p >= kMlpParams) return;
+  float g = 0.0f;
+  if (ext_grad) {
+    g = ext_grad[p];
+  } else {
+    for (int b = 0; b < nblocks; ++b) g += m.partial[(size_t)b * (kMlpParams + 1) + p];
+  }
+  const float b1 = 0.9f, b2 = 0.99f, c1 = (float)(1.0 - 0.9), c2 = (float)(1.0 - 0.99);
+  const float mm = b1 * m.m[p] + c1 * g;
+  const float vv = b2 * m.v[p] + c2 * g * g;
+  m.m[p] = mm;
+  m.v[p] = vv;
+  const float mh = mm / bc1, vh = vv / bc2;
+  const float w = m.master[p] - (lr * mh) / (sqrtf(vh) + 1e-8f);
+  m.master[p] = w;
+  const int qi = qindex(p);
+  if (qi >= 0) m.wq[qi] = to_bf16(w);
+}
+
+// gradient only (tests): the partials summed in workgroup order
+__global__ void mlp_sum_partials_kernel(MlpDev m, int nblocks, float* grad, float* loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kMlpParams) return;
+  float g = 0.0f;
+  for (int b = 0; b < nblocks; ++b) g += m.partial[(size_t)b * (kMlpParams + 1) + p];
+  if (p < kMlpParams) grad[p] = g;
+  else *loss = g;
+}
+
+void k_mlp_train_pass(const MlpDev& m, const float* x6, const float* tgt, const float* wt, int n_set,
+                      int offset, int batch, int* nblocks_out, hipStream_t s) {
+  const int ntiles = (batch + 15) / 16;
+  const int tpb = std::max(1, (ntiles + kMlpMaxBlocks - 1) / kMlpMaxBlocks);
+  const int nb = (ntiles + tpb - 1) / tpb;
+  mlp_train_kernel<<<nb, 64, 0, s>>>(m, x6, tgt, wt, n_set, offset, batch, tpb);
+  *nblocks_out = nb;
+}
+void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, float bc1, float bc2,
+                float* loss_out, hipStream_t s) {
+  mlp_adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, s>>>(m, nblocks, ext_grad, lr, bc1, bc2,
+                                                           loss_out);
+}
+void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, hipStream_t s) {
+  mlp_sum_partials_kernel<<<(kMlpParams + 256) / 256, 256, 0, s>>>(m, nblocks, grad, loss);
+}
+
+// bfloat16 copy of freshly written master weights
+__global__ void mlp_quantize_kernel(MlpDev m) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpParams) return;
+  const int qi = qindex(p);
+  if (qi >= 0) m.wq[qi] = to_bf16(m.master[p]);
+}
+void k_mlp_quantize(const MlpDev& m, hipStream_t s) {
+  mlp_quantize_kernel<<<(kMlpParams + 255) / 256, 256, 0, s>>>(m);
+}
+
+// probe of the matrix-core lane layout: D = A B for one 16 x 16 x 16 tile
+// (A, B given as bfloat16 bit patterns, row-major)
+__global__ void mfma_probe_kernel(const uint16_t* A, const uint16_t* B, float* D) {
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  v4s a, b;
+  for (int r = 0; r < 4; ++r) {
+    a[r] = (short)A[lr * 16 + 4 * lg + r];
+    b[r] = (short)B[(4 * lg + r) * 16 + lr];
+  }
+  const v4f d = mma(a, b, v4f{0.0f, 0.0f, 0.0f, 0.0f});
+  for (int r = 0; r < 4; ++r) D[(4 * lg + r) * 16 + lr] = d[r];
+}
+void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s) {
+  mfma_probe_kernel<<<1, 64, 0, s>>>(A, B, D);
+}
+
+}  // namespace mars
