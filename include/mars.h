@@ -152,9 +152,60 @@ mars_status mars_scene_release(mars_ctx* ctx, int32_t scene_id);
  * estimates") and the per-pixel sums.  stats is filled (host pointer). */
 mars_status mars_render_iteration(mars_ctx* ctx, int32_t scene_id, const mars_iter_params* p,
                                   mars_iter_stats* stats);
-/* Renders one iteration of n scenes in one batched launch sequence. */
+/* Renders one iteration of n distinct scenes as one batch (the workload of
+ * many independent requests of uneven size).  Equivalent to calling
+ * mars_render_iteration on each scene; stats (optional) receives the totals.
+ * Batches of scenes without the learned cache and without debug records run
+ * as one captured launch graph (see mars_iterate_batch); others one scene
+ * after another. */
 mars_status mars_render_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
                               const mars_iter_params* p, mars_iter_stats* stats);
+
+/* Batched iteration: the render iteration of each of n distinct scenes and,
+ * with MARS_BATCH_UPDATE, its update (as mars_update_counts), every scene's
+ * work enqueued without host synchronisation on one stream of a pool
+ * (scenes assigned longest-first to the least loaded stream), the whole
+ * batch captured once as a HIP graph and replayed by later calls with the
+ * same scenes and parameters apart from the iteration index.  The device
+ * reads the iteration index, the image cost C_I and the number of cells
+ * itself.  A scene whose queues overflowed skips its update inside the graph
+ * and is rendered (and updated) again on its own with tile halving, so the
+ * result always equals the per-scene calls.  Scenes with the learned cache
+ * and debug records (p->debug_depth > 0) are refused (MARS_E_ARG).
+ * iter_stats / upd_stats: optional host arrays of n.  The graph keeps device
+ * pointers of the scenes: mars_scene_configure, mars_set_fixed_counts,
+ * releases and a change of parameters rebuild it on the next call.
+ * MARS_BATCH_NO_GRAPH enqueues the same work on the stream pool directly. */
+enum { MARS_BATCH_UPDATE = 1, MARS_BATCH_NO_GRAPH = 2 };
+mars_status mars_iterate_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                               const mars_iter_params* p, int32_t flags,
+                               mars_iter_stats* iter_stats, mars_update_stats* upd_stats);
+
+/* Re-sizes a scene's path queues: queue_capacity entries per depth level,
+ * camera samples per wavefront tile (<= queue_capacity; 0 = keep).  Queue
+ * memory is about 216 bytes x (max_depth + 2) x queue_capacity. */
+mars_status mars_scene_configure(mars_ctx* ctx, int32_t scene_id, int64_t queue_capacity,
+                                 int32_t tile_roots);
+/* queue size and tile size of a scene, the peak queue occupancy per camera
+ * sample seen by the last eager render iteration */
+mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_capacity,
+                             int32_t* tile_roots, double* peak_per_root);
+
+/* Autotuner of queue and tile sizes.  For each scene: one probe render
+ * iteration with p (no update; the last-iteration image and sample radiance
+ * then hold the probe's) measures the peak queue occupancy per camera sample
+ * e; tiles of up to all camera samples are planned under mem_budget bytes of
+ * queue memory for the n scenes together (capacity = tile x e x 1.25,
+ * largest scenes halved first); then up to three tile sizes (plan, plan/2,
+ * plan/4; at least 65536 samples) are timed with one render iteration each
+ * and the fastest kept.  cache_path (optional): a text file of lines
+ * "<class> <capacity> <tile> <e> <ms>" keyed by the scene class (resolution,
+ * spp, mode, depth, triangles, allocation mode); classes found there are
+ * applied without probing and new ones appended.  out (optional, n entries
+ * each): chosen capacity, tile, measured e. */
+mars_status mars_autotune(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                          const mars_iter_params* p, int64_t mem_budget, const char* cache_path,
+                          int64_t* out_capacity, int32_t* out_tile, double* out_peak);
 /* Image estimates (I~, V_I, C_I), the fixed-point update of every cell's
  * factors, the directional distribution of the guided technique, octree
  * refinement and the inverse-variance weighted image (Sec. 4.1, 5.1). */

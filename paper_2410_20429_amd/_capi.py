@@ -19,6 +19,7 @@ MODE_PT, MODE_PT_GUIDED, MODE_BDPT = 0, 1, 2
 ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_MLP = 0, 1, 2, 3
 IMAGE_MEAN, IMAGE_IVW, IMAGE_LAST = 0, 1, 2
 SCENE_MLP = 1
+BATCH_UPDATE, BATCH_NO_GRAPH = 1, 2
 
 alloc_fn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 free_fn = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -79,6 +80,10 @@ SIGNATURES = {
     "mars_scene_release": [P, I32],
     "mars_render_iteration": [P, I32, C.POINTER(mars_iter_params), C.POINTER(mars_iter_stats)],
     "mars_render_batch": [P, P, I32, C.POINTER(mars_iter_params), C.POINTER(mars_iter_stats)],
+    "mars_iterate_batch": [P, P, I32, C.POINTER(mars_iter_params), I32, P, P],
+    "mars_scene_configure": [P, I32, C.c_int64, I32],
+    "mars_scene_query": [P, I32, C.POINTER(C.c_int64), PI32, C.POINTER(C.c_double)],
+    "mars_autotune": [P, P, I32, C.POINTER(mars_iter_params), C.c_int64, C.c_char_p, P, P, P],
     "mars_update_counts": [P, I32, C.POINTER(mars_iter_params), C.POINTER(mars_update_stats)],
     "mars_set_fixed_counts": [P, I32, P, I32],
     "mars_set_itilde": [P, I32, P],
@@ -186,6 +191,36 @@ def mars_render_batch(ctx, sids, params):
     _call("mars_render_batch", ctx, C.cast(arr, C.c_void_p), len(sids), C.byref(params),
           C.byref(st))
     return st
+
+
+def mars_iterate_batch(ctx, sids, params, flags):
+    n = len(sids)
+    arr = (C.c_int32 * n)(*sids)
+    its = (mars_iter_stats * n)()
+    ups = (mars_update_stats * n)()
+    _call("mars_iterate_batch", ctx, C.cast(arr, C.c_void_p), n, C.byref(params), flags,
+          C.cast(its, C.c_void_p), C.cast(ups, C.c_void_p))
+    return list(its), list(ups)
+
+
+def mars_scene_configure(ctx, sid, queue_capacity=0, tile_roots=0):
+    _call("mars_scene_configure", ctx, sid, queue_capacity, tile_roots)
+
+
+def mars_scene_query(ctx, sid):
+    cap, tile, peak = C.c_int64(), C.c_int32(), C.c_double()
+    _call("mars_scene_query", ctx, sid, C.byref(cap), C.byref(tile), C.byref(peak))
+    return cap.value, tile.value, peak.value
+
+
+def mars_autotune(ctx, sids, params, mem_budget=0, cache_path=None):
+    n = len(sids)
+    arr = (C.c_int32 * n)(*sids)
+    cap, tile, peak = (C.c_int64 * n)(), (C.c_int32 * n)(), (C.c_double * n)()
+    _call("mars_autotune", ctx, C.cast(arr, C.c_void_p), n, C.byref(params), mem_budget,
+          cache_path.encode() if cache_path else None, C.cast(cap, C.c_void_p),
+          C.cast(tile, C.c_void_p), C.cast(peak, C.c_void_p))
+    return list(cap), list(tile), list(peak)
 
 
 def mars_update_counts(ctx, sid, params):

@@ -9,7 +9,8 @@ import numpy as np
 
 from . import _capi as capi
 from ._capi import (ALLOC_CLASSIC, ALLOC_FIXED, ALLOC_MARS, ALLOC_MLP, IMAGE_IVW,  # noqa: F401
-                    IMAGE_LAST, IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, SCENE_MLP, MarsError)
+                    IMAGE_LAST, IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, SCENE_MLP, MarsError,
+                    BATCH_NO_GRAPH, BATCH_UPDATE)
 
 VERTEX_DTYPE = np.dtype([("root", "<u4"), ("depth", "<u4"), ("stream_lo", "<u4"),
                          ("stream_hi", "<u4"), ("cell", "<u4"), ("beta", "<f4", 3),
@@ -98,6 +99,7 @@ class Scene:
         self.cam = np.ascontiguousarray(scene["camera"], np.float32)
         self.W, self.H = int(scene["width"]), int(scene["height"])
         self.mode = mode
+        self.max_depth = int(max_depth)
         d = capi.mars_scene_desc(_p(self.V), _p(self.tm), _p(self.mats), _p(self.cam),
                                  self.V.shape[0], self.mats.shape[0], self.W, self.H, mode,
                                  max_depth, max_cells, max_tree_depth, split_visits, int(bool(nee)),
@@ -234,11 +236,45 @@ class Scene:
         g = np.ascontiguousarray(grad, np.float32)
         capi.mars_mlp_apply_grad(self.ctx.h, self.id, _p(g), lr)
 
+    # ---- queue sizing ----
+    def configure(self, queue_capacity=0, tile_roots=0):
+        capi.mars_scene_configure(self.ctx.h, self.id, int(queue_capacity), int(tile_roots))
+
+    def query(self):
+        """(queue capacity, tile size, peak queue level per camera sample of
+        the last eager iteration)"""
+        return capi.mars_scene_query(self.ctx.h, self.id)
+
     def checkpoint_save(self, path):
         capi.mars_checkpoint_save(self.ctx.h, self.id, str(path))
 
     def checkpoint_load(self, path):
         capi.mars_checkpoint_load(self.ctx.h, self.id, str(path))
+
+
+def render_batch(scenes, params):
+    """One render iteration of every scene as one batch; returns the totals."""
+    st = capi.mars_render_batch(scenes[0].ctx.h, [s.id for s in scenes], params)
+    for s in scenes:
+        s.spp, s._last = params.spp, params
+    return st
+
+
+def iterate_batch(scenes, params, update=True, graph=True):
+    """Render (and update) iteration of every scene in one captured launch
+    graph; returns per-scene iteration and update statistics."""
+    flags = (BATCH_UPDATE if update else 0) | (0 if graph else BATCH_NO_GRAPH)
+    its, ups = capi.mars_iterate_batch(scenes[0].ctx.h, [s.id for s in scenes], params, flags)
+    for s in scenes:
+        s.spp, s._last = params.spp, params
+    return its, ups
+
+
+def autotune(scenes, params, mem_budget=0, cache_path=None):
+    """Queue capacity and tile size per scene: [(capacity, tile, peak per sample)]."""
+    cap, tile, peak = capi.mars_autotune(scenes[0].ctx.h, [s.id for s in scenes], params,
+                                         int(mem_budget), cache_path)
+    return list(zip(cap, tile, peak))
 
 
 def run_schedule(scene: Scene, n_iter, warmup=1, spp=1, budget_aware=True, stat_clamp=None,

@@ -38,6 +38,8 @@ struct Ctx;
 struct Scene {
   Ctx* ctx = nullptr;
   std::vector<void*> owned;
+  uint64_t uid = 0;    // unique per context: keys captured graphs
+  uint64_t epoch = 0;  // bumped whenever a device buffer captured by a graph moves
   // configuration
   int W = 0, H = 0, mode = 0, max_depth = 0, max_cells = 0, max_tree_depth = 8, split_visits = 32;
   int nee = 1;
@@ -75,16 +77,20 @@ struct Scene {
   uint32_t mlp_n_train = 0;
   int mlp_step = 0;
   uint64_t vertices_last = 0;
+  // largest queue level per camera sample over the tiles of the last eager iteration
+  double peak_per_root = 0.0;
 };
 
 // per-kernel HIP-event timing on the context's stream
 enum KernelId {
   KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
-  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_COUNT
+  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_BATCH,
+  KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
     "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
-    "fixed_point", "hist_normalize", "refine", "ivw", "light", "mlp_infer", "mlp_train"};
+    "fixed_point", "hist_normalize", "refine", "ivw", "light", "mlp_infer", "mlp_train",
+    "batch"};
 
 struct Profiler {
   bool on = false;
@@ -123,8 +129,22 @@ struct Profiler {
   }
 };
 
+// a captured batch: the key lists everything the launches bake in
+struct BatchGraph {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+  int32_t* iter = nullptr;    // device: iteration index read by the kernels
+  double* summary = nullptr;  // device: [n][kSumWords]
+};
+
 struct Ctx {
   int device = 0;
+  uint64_t next_uid = 1;
+  // batched iterations: a pool of default-priority streams and the graph cache
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> pool;
+  std::vector<hipEvent_t> pool_ev;
+  std::vector<BatchGraph> graphs;
   Profiler prof;
   unsigned long long* tcount = nullptr;  // traversal counters (instrumented runs)
   bool counting = false;
@@ -151,6 +171,12 @@ struct Ctx {
     if (!p) return;
     if (free_) free_(p, (void*)stream, user);
     else (void)hipFree(p);
+  }
+  void drop_graph(BatchGraph& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    dfree(g.iter);
+    dfree(g.summary);
+    g = BatchGraph{};
   }
   Scene* scene(int id) {
     if (id < 0 || id >= (int)scenes.size() || !scenes[id])
@@ -184,6 +210,15 @@ void release_scene(Scene* s) {
   (void)hipStreamSynchronize(s->ctx->stream);
   for (void* p : s->owned) s->ctx->dfree(p);
   s->owned.clear();
+  s->epoch++;
+}
+
+// frees one buffer of the scene (the context's stream must be idle)
+void sfree(Scene* s, void* p) {
+  if (!p) return;
+  auto it = std::find(s->owned.begin(), s->owned.end(), p);
+  if (it != s->owned.end()) s->owned.erase(it);
+  s->ctx->dfree(p);
 }
 
 template <typename F>
@@ -212,7 +247,7 @@ void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 IterDev to_dev(const mars_iter_params* p) {
-  IterDev it;
+  IterDev it{};  // iter_dev null: the iteration index is the field
   it.iteration = p->iteration;
   it.spp = p->spp;
   it.alloc = p->alloc;
@@ -242,6 +277,12 @@ void check_params(Scene* s, const mars_iter_params* p) {
 
 void ensure_roots(Scene* s, size_t roots) {
   if (roots <= s->roots_cap) return;
+  if (s->roots_cap) {
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    for (void* p : {(void*)s->img.Ls, (void*)s->img.beta1, (void*)s->lt.V0, (void*)s->lt.V1,
+                    (void*)s->lt.V2, (void*)s->lt.Y0, (void*)s->lt.len})
+      sfree(s, p);
+  }
   s->img.Ls = salloc<float>(s, roots * 3);
   s->img.beta1 = salloc<float>(s, roots * 3);
   if (s->mode == MARS_MODE_BDPT) {
@@ -253,7 +294,38 @@ void ensure_roots(Scene* s, size_t roots) {
     s->lt.len = salloc<uint2>(s, roots);
   }
   s->roots_cap = roots;
+  s->epoch++;
 }
+
+// per-depth path queues of `cap` entries per level (levels 0 .. max_depth + 1)
+void alloc_queues(Scene* s, size_t cap) {
+  if (cap == 0 || cap > 0xFFFF0000ull) throw Status(MARS_E_ARG, "queue capacity out of range");
+  QueuesDev& q = s->qd;
+  if (q.R0) {
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    for (void* p : {(void*)q.R0, (void*)q.R1, (void*)q.S0, (void*)q.S1, (void*)q.S2, (void*)q.S3,
+                    (void*)q.H, (void*)q.V0, (void*)q.V1, (void*)q.V2, (void*)q.RO, (void*)q.SH0,
+                    (void*)q.SH1, (void*)q.SH2, (void*)s->mlp.y})
+      sfree(s, p);
+    q = QueuesDev{};
+    s->mlp.y = nullptr;
+  }
+  const size_t lv = (size_t)(s->max_depth + 2) * cap;
+  q.R0 = salloc<float4>(s, lv); q.R1 = salloc<float4>(s, lv);
+  q.S0 = salloc<float4>(s, lv); q.S1 = salloc<float4>(s, lv);
+  q.S2 = salloc<float4>(s, lv); q.S3 = salloc<uint4>(s, lv);
+  q.H = salloc<uint2>(s, lv);
+  q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
+  q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
+  q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
+  q.cap = cap;
+  if (s->mlp_on) s->mlp.y = salloc<float>(s, lv * 4);
+  s->cap = cap;
+  s->epoch++;
+}
+
+// bytes of queue memory per entry of one level
+constexpr size_t kQueueEntryBytes = 13 * 16 + 8;
 
 // BDPT: one light subpath per camera sample of the iteration, before any
 // camera tile (connections may use any sample's subpath)
@@ -363,12 +435,15 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     work.emplace_back((uint32_t)r, n);  // processed back to front: ascending roots
   }
   uint32_t dbg_total = 0;
+  double peak = 0.0;
   while (!work.empty()) {
     auto [r0, n] = work.back();
     work.pop_back();
     Counters hc;
     const bool ok = run_tile(s, it, r0, n, dbg_total, (uint32_t)roots, &hc);
     S.tiles++;
+    for (int d = 1; d <= s->max_depth + 1; ++d)
+      peak = std::max(peak, (double)std::max(hc.n_ray[d], hc.n_shadow[d]) / (double)n);
     if (!ok) {
       if (n == 1) throw Status(MARS_E_OVERFLOW, "a single path tree exceeds the queue capacity");
       S.overflow_retries++;
@@ -392,6 +467,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   s->vertices_last = S.vertices;
   s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
   s->dbg_last = dbg_total;
+  s->peak_per_root = peak;
   S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = S;
 }
@@ -641,17 +717,8 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     size_t cap = d->queue_capacity > 0 ? (size_t)d->queue_capacity
                                        : std::max<size_t>(65536, 4 * (size_t)s->tile_roots);
     if (cap > 0xFFFF0000ull) cap = 0xFFFF0000ull;
-    s->cap = cap;
-    const size_t lv = (size_t)(d->max_depth + 2) * cap;
-    QueuesDev& q = s->qd;
-    q.cap = cap;
-    q.R0 = salloc<float4>(s, lv); q.R1 = salloc<float4>(s, lv);
-    q.S0 = salloc<float4>(s, lv); q.S1 = salloc<float4>(s, lv);
-    q.S2 = salloc<float4>(s, lv); q.S3 = salloc<uint4>(s, lv);
-    q.H = salloc<uint2>(s, lv);
-    q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
-    q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
-    q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
+    s->mlp_on = (d->flags & MARS_SCENE_MLP) != 0;
+    alloc_queues(s, cap);
     s->cnt = salloc<Counters>(s, 1);
     s->lt.lmax = d->max_depth - 2;
     s->dbg_cap = 0;  // allocated on the first iteration that asks for records
@@ -673,15 +740,13 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     k_fill_f32(im.count_map, 0.0f, px * 3, st);
     k_fill_f64(im.red, 0.0, 8, st);
     ensure_roots(s, px);
-    if (d->flags & MARS_SCENE_MLP) {
-      s->mlp_on = true;
+    if (s->mlp_on) {
       MlpDev& m = s->mlp;
       m.master = salloc<float>(s, kMlpParams);
       m.wq = salloc<uint16_t>(s, kMlpParams);
       m.m = salloc<float>(s, kMlpParams);
       m.v = salloc<float>(s, kMlpParams);
       m.partial = salloc<float>(s, (size_t)kMlpMaxBlocks * (kMlpParams + 1));
-      m.y = salloc<float>(s, lv * 4);
       m.rec_cap = 1u << 18;
       m.rec = salloc<float4>(s, 3 * (size_t)m.rec_cap);
       m.n_rec = salloc<uint32_t>(s, 4);
@@ -698,6 +763,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     release_scene(s);
     throw;
   }
+  s->uid = c->next_uid++;
   c->scenes.push_back(std::move(sp));
   return (int)c->scenes.size() - 1;
 }
@@ -706,30 +772,34 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   if (s->spp_last <= 0) throw Status(MARS_E_STATE, "no iteration rendered");
   hipStream_t st = s->ctx->stream;
   const int npx = s->W * s->H, spp = s->spp_last;
-  s->total_spp += (double)spp;
   const float kc = p ? p->stat_clamp : 0.0f;
   Ctx* c = s->ctx;
+  // the running sample count lives on the device (red[6]) so that captured
+  // iterations can advance it
   timed(c, KID_UPDATE_IMAGE, [&] {
-    k_update_image(s->img, s->W, s->H, spp, (float)s->total_spp, s->mode == MARS_MODE_BDPT, kc, st);
+    k_add_spp(s->img.red + 6, spp, nullptr, st);
+    k_update_image(s->img, s->W, s->H, spp, s->img.red + 6, s->mode == MARS_MODE_BDPT, kc,
+                   nullptr, st);
   });
   const double C_I = (double)s->rays_last / ((double)npx * (double)spp);
   const int nb = s->n_cells;
   timed(c, KID_FIXED_POINT, [&] {
-    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, 1, 0.0, s->max_cells, st);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 1, 0.0, s->max_cells,
+                  nullptr, st);
   });
   if (s->mode == MARS_MODE_PT_GUIDED)
-    timed(c, KID_HIST, [&] { k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, st); });
+    timed(c, KID_HIST, [&] { k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, nullptr, st); });
   if (s->mlp_on) {
     IterDev itd = p ? to_dev(p) : IterDev{};
     timed(c, KID_MLP, [&] {
-      k_mlp_targets(s->sd, s->cd, s->mlp, s->img, itd, s->mlp.rec_cap, st);
+      k_mlp_targets(s->sd, s->cd, s->mlp, s->img, itd, s->mlp.rec_cap, nullptr, st);
     });
   }
   timed(c, KID_REFINE, [&] {
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
-             s->max_tree_depth, s->max_cells, st);
+             s->max_tree_depth, s->max_cells, nullptr, st);
   });
-  timed(c, KID_IVW, [&] { k_ivw(s->img, npx, spp, st); });
+  timed(c, KID_IVW, [&] { k_ivw(s->img, npx, spp, nullptr, st); });
   double red[8];
   int32_t nc[4];
   uint32_t nrec = 0;
@@ -741,6 +811,7 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   c->prof.flush();
   s->n_cells = nc[0];
   s->n_nodes = nc[1];
+  s->total_spp = red[6];
   if (s->mlp_on) s->mlp_n_train = std::min(nrec, s->mlp.rec_cap);
   if (out) {
     out->V_I = red[4] > 0.0 ? red[3] / red[4] : 0.0;
@@ -748,6 +819,403 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
     out->n_cells_before = nb;
     out->n_cells_after = s->n_cells;
     out->n_excluded = npx - (int)red[4];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched iterations: each scene's iteration enqueued with no host
+// synchronisation on one stream of a pool; the batch captured once as a graph
+// ---------------------------------------------------------------------------
+constexpr int kBatchStreams = 4;  // the hardware queues a process gets by default
+constexpr int kGraphCache = 4;
+
+size_t roots_of(const Scene* s, int spp) { return (size_t)s->W * s->H * (size_t)spp; }
+
+// One scene's whole iteration: the tile plan of an eager iteration, queue
+// counters of a tile reset on the device, iteration totals accumulated over
+// the tiles; the update takes C_I and the cell count from device memory and
+// becomes a no-op if any tile overflowed (the scene is then rendered again).
+void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, float stat_clamp,
+                       hipStream_t st, double* summary) {
+  Ctx* c = s->ctx;
+  const bool bdpt = s->mode == MARS_MODE_BDPT;
+  const size_t roots = roots_of(s, spp), mc = (size_t)s->max_cells;
+  const int grid_trace = c->cu * 10, grid = c->cu * 8;
+  unsigned long long* tc = c->counting ? c->tcount : nullptr;
+  k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
+  k_fill_f64_dev(s->cd.acc, 0.0, s->n_cells_dev, 24, mc * 24, st);
+  k_fill_f64_dev(s->cd.hacc, 0.0, s->n_cells_dev, 64, mc * 64, st);
+  k_fill_u32_dev(s->cd.visits, 0u, s->n_cells_dev, 1, mc, st);
+  k_fill_f32(s->img.beta1, 0.0f, roots * 3, st);
+  if (bdpt) {
+    for (size_t r0 = 0; r0 < roots; r0 += s->cap) {
+      const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
+      k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st);
+      for (int i = 1; i <= s->lt.lmax; ++i) {
+        k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc);
+        k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st);
+      }
+    }
+  }
+  const size_t tile = std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
+  for (size_t r0 = 0; r0 < roots; r0 += tile) {
+    const uint32_t n = (uint32_t)std::min(tile, roots - r0);
+    k_fill_u32((uint32_t*)s->cnt, 0u, kTileWords, st);
+    k_raygen(s->sd, s->qd, s->cnt, it, (uint32_t)r0, n, st);
+    k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc);
+    for (int d = 1; d <= s->max_depth; ++d) {
+      if (bdpt)
+        k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, nullptr, 0, d, (uint32_t)roots,
+                     grid, st);
+      else
+        k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, nullptr, 0, d, grid, st);
+      k_trace_pair(s->sd, s->qd, s->cnt, d < s->max_depth ? d + 1 : -1, d, grid_trace, st, tc);
+    }
+    for (int d = s->max_depth; d >= 1; --d) {
+      if (bdpt)
+        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, (uint32_t)roots, grid, st);
+      else
+        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
+    }
+  }
+  k_pixel_sums(s->img, s->W * s->H, spp, st);
+  if (with_update) {
+    const uint32_t* skip = &s->cnt->overflow_any;
+    k_add_spp(s->img.red + 6, spp, skip, st);
+    k_update_image(s->img, s->W, s->H, spp, s->img.red + 6, bdpt, stat_clamp, skip, st);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, 0.0, s->cnt, (double)roots, 1, 0.0,
+                  s->max_cells, skip, st);
+    if (s->mode == MARS_MODE_PT_GUIDED) k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, skip, st);
+    k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
+             s->max_tree_depth, s->max_cells, skip, st);
+    k_ivw(s->img, s->W * s->H, spp, skip, st);
+  }
+  k_batch_summary(s->cnt, s->img.red, s->n_cells_dev, summary, st);
+}
+
+void ensure_pool(Ctx* c) {
+  if (!c->origin) HIPCHK(hipStreamCreateWithFlags(&c->origin, hipStreamNonBlocking));
+  while ((int)c->pool.size() < kBatchStreams) {
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    c->pool.push_back(s);
+  }
+  while ((int)c->pool_ev.size() < kBatchStreams + 1) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->pool_ev.push_back(e);
+  }
+}
+
+uint64_t fbits64(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int flags,
+                   mars_iter_stats* its, mars_update_stats* ups) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!ids || n <= 0 || !p) throw Status(MARS_E_ARG, "empty batch or null params");
+  if (flags & ~(MARS_BATCH_UPDATE | MARS_BATCH_NO_GRAPH)) throw Status(MARS_E_ARG, "unknown batch flags");
+  const bool with_update = (flags & MARS_BATCH_UPDATE) != 0;
+  const bool use_graph = (flags & MARS_BATCH_NO_GRAPH) == 0;
+  if (p->debug_depth > 0) throw Status(MARS_E_ARG, "debug records are not batched");
+  std::vector<Scene*> sc(n);
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) {
+    sc[i] = c->scene(ids[i]);
+    for (int j = 0; j < i; ++j)
+      if (sc[j] == sc[i]) throw Status(MARS_E_ARG, "a scene appears twice in the batch");
+    check_params(sc[i], p);
+    if (sc[i]->mlp_on) throw Status(MARS_E_ARG, "learned-cache scenes are not batched");
+    if (roots_of(sc[i], p->spp) > 0x7FFFFFFFull) throw Status(MARS_E_ARG, "too many camera samples");
+    work[i] = (double)roots_of(sc[i], p->spp) * sc[i]->max_depth *
+              (sc[i]->mode == MARS_MODE_BDPT ? 2.0 : 1.0);
+  }
+  for (Scene* s : sc) ensure_roots(s, roots_of(s, p->spp));
+  ensure_pool(c);
+  // longest first onto the least loaded stream
+  std::vector<int> order(n), lane(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int K = std::min(n, kBatchStreams);
+  std::vector<double> load(K, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lane[i] = k;
+    load[k] += work[i];
+  }
+  std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)flags, (uint64_t)c->counting,
+                               (uint64_t)p->spp, (uint64_t)p->alloc, (uint64_t)p->budget_aware,
+                               (uint64_t)p->rr_start, (uint64_t)p->fixed_scale,
+                               fbits64(p->clamp_lo), fbits64(p->clamp_hi), fbits64(p->stat_clamp),
+                               (uint64_t)p->center_jitter, (uint64_t)p->lp_stride, (uint64_t)c->cu};
+  for (int i = 0; i < n; ++i) {
+    key.push_back(sc[i]->uid);
+    key.push_back(sc[i]->epoch);
+    key.push_back((uint64_t)lane[i]);
+  }
+  BatchGraph* g = nullptr;
+  for (auto& e : c->graphs)
+    if (e.key == key) g = &e;
+  if (!g) {
+    if ((int)c->graphs.size() >= kGraphCache) {
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->drop_graph(c->graphs.front());
+      c->graphs.erase(c->graphs.begin());
+    }
+    BatchGraph ng;
+    ng.key = key;
+    try {
+      ng.iter = (int32_t*)c->dalloc(sizeof(int32_t));
+      ng.summary = (double*)c->dalloc((size_t)n * kSumWords * sizeof(double));
+      if (use_graph) {
+        IterDev it = to_dev(p);
+        it.iter_dev = ng.iter;
+        HIPCHK(hipStreamBeginCapture(c->origin, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+          HIPCHK(hipEventRecord(c->pool_ev[0], c->origin));
+          for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
+          for (int i : order)
+            enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, c->pool[lane[i]],
+                              ng.summary + (size_t)i * kSumWords);
+          for (int k = 0; k < K; ++k) {
+            HIPCHK(hipEventRecord(c->pool_ev[1 + k], c->pool[k]));
+            HIPCHK(hipStreamWaitEvent(c->origin, c->pool_ev[1 + k], 0));
+          }
+        } catch (...) {
+          (void)hipStreamEndCapture(c->origin, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(c->origin, &graph));
+        const hipError_t e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) throw Status(MARS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    } catch (...) {
+      c->drop_graph(ng);
+      throw;
+    }
+    c->graphs.push_back(ng);
+    g = &c->graphs.back();
+  }
+  hipStream_t st = c->stream;
+  k_set_i32(g->iter, p->iteration, st);
+  timed(c, KID_BATCH, [&] {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(g->exec, st));
+    } else {
+      IterDev it = to_dev(p);
+      it.iter_dev = g->iter;
+      HIPCHK(hipEventRecord(c->pool_ev[0], st));
+      for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
+      for (int i : order)
+        enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, c->pool[lane[i]],
+                          g->summary + (size_t)i * kSumWords);
+      for (int k = 0; k < K; ++k) {
+        HIPCHK(hipEventRecord(c->pool_ev[1 + k], c->pool[k]));
+        HIPCHK(hipStreamWaitEvent(st, c->pool_ev[1 + k], 0));
+      }
+    }
+  });
+  std::vector<double> hs((size_t)n * kSumWords);
+  d2h(hs.data(), g->summary, hs.size() * sizeof(double), st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  c->prof.flush();
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < n; ++i) {
+    Scene* s = sc[i];
+    const double* h = &hs[(size_t)i * kSumWords];
+    if (h[0] != 0.0) {
+      // a queue overflowed: this scene again on its own, with tile halving
+      mars_iter_stats S{};
+      render_iteration(s, p, &S);
+      if (its) its[i] = S;
+      if (with_update) {
+        mars_update_stats U{};
+        update_counts(s, p, &U);
+        if (ups) ups[i] = U;
+      }
+      continue;
+    }
+    const size_t roots = roots_of(s, p->spp);
+    const size_t tile = std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
+    mars_iter_stats S{};
+    S.rays_camera = roots;
+    S.rays_ext = (uint64_t)h[1];
+    S.rays_shadow = (uint64_t)h[2];
+    S.rays_light = (uint64_t)h[3];
+    S.rays_conn = (uint64_t)h[4];
+    S.vertices = (uint64_t)h[5];
+    S.samples = (uint64_t)h[6];
+    S.tiles = (int32_t)((roots + tile - 1) / tile);
+    S.ms = ms;
+    s->spp_last = p->spp;
+    s->vertices_last = S.vertices;
+    s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
+    s->dbg_last = 0;
+    if (its) its[i] = S;
+    if (with_update) {
+      const double* red = h + 7;
+      mars_update_stats U{};
+      U.V_I = red[4] > 0.0 ? red[3] / red[4] : 0.0;
+      U.C_I = (double)s->rays_last / (double)roots;
+      U.n_cells_before = s->n_cells;
+      s->n_cells = (int)h[15];
+      s->n_nodes = (int)h[16];
+      s->total_spp = red[6];
+      U.n_cells_after = s->n_cells;
+      U.n_excluded = s->W * s->H - (int)red[4];
+      if (ups) ups[i] = U;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// queue / tile autotuner
+// ---------------------------------------------------------------------------
+size_t tuned_capacity(size_t tile, double e) {
+  const double want = std::ceil((double)tile * std::max(1.0, e) * 1.25);
+  size_t cap = (size_t)want;
+  cap = (cap + 4095) / 4096 * 4096;
+  return std::min<size_t>(std::max<size_t>(cap, 4096), 0xFFFF0000ull);
+}
+
+size_t queue_bytes(const Scene* s, size_t cap) {
+  return cap * (size_t)(s->max_depth + 2) * (kQueueEntryBytes + (s->mlp_on ? 16 : 0));
+}
+
+void configure(Scene* s, size_t cap, int tile) {
+  if (cap && cap != s->cap) alloc_queues(s, cap);
+  if (tile > 0 && tile != s->tile_roots) {
+    s->tile_roots = tile;
+    s->epoch++;
+  }
+}
+
+std::string scene_class(const Scene* s, const mars_iter_params* p) {
+  char b[192];
+  std::snprintf(b, sizeof(b), "%dx%d/spp%d/mode%d/depth%d/tris%d/alloc%d", s->W, s->H, p->spp,
+                s->mode, s->max_depth, s->n_tris, p->alloc);
+  return b;
+}
+
+struct TuneEntry {
+  size_t cap = 0;
+  int tile = 0;
+  double e = 0.0, ms = 0.0;
+};
+
+void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int64_t budget,
+              const char* path, int64_t* ocap, int32_t* otile, double* opeak) {
+  if (!ids || n <= 0 || !p) throw Status(MARS_E_ARG, "empty batch or null params");
+  if (budget <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    budget = (int64_t)(fr / 4);
+  }
+  std::vector<Scene*> sc(n);
+  for (int i = 0; i < n; ++i) {
+    sc[i] = c->scene(ids[i]);
+    check_params(sc[i], p);
+  }
+  std::vector<std::pair<std::string, TuneEntry>> cache;
+  if (path) {
+    if (FILE* f = std::fopen(path, "r")) {
+      char cls[192];
+      unsigned long long cap;
+      int tile;
+      double e, ms;
+      while (std::fscanf(f, "%191s %llu %d %lf %lf", cls, &cap, &tile, &e, &ms) == 5)
+        if (cap > 0 && cap <= 0xFFFF0000ull && tile > 0 && (size_t)tile <= cap)
+          cache.push_back({cls, TuneEntry{(size_t)cap, tile, e, ms}});
+      std::fclose(f);
+    }
+  }
+  auto find = [&](const std::string& k) -> TuneEntry* {
+    for (auto& e : cache)
+      if (e.first == k) return &e.second;
+    return nullptr;
+  };
+  std::vector<TuneEntry> res(n);
+  std::vector<int> todo;
+  for (int i = 0; i < n; ++i) {
+    if (TuneEntry* t = find(scene_class(sc[i], p))) {
+      configure(sc[i], t->cap, t->tile);
+      res[i] = *t;
+    } else {
+      todo.push_back(i);
+    }
+  }
+  // probe: peak queue level per camera sample at the current sizes
+  for (int i : todo) {
+    render_iteration(sc[i], p, nullptr);
+    res[i].e = std::max(1.0, sc[i]->peak_per_root);
+  }
+  // plan: whole-iteration tiles, the largest scenes halved until the queues fit
+  std::vector<size_t> T(n);
+  double used = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const bool tuned = std::find(todo.begin(), todo.end(), i) != todo.end();
+    T[i] = tuned ? roots_of(sc[i], p->spp) : (size_t)res[i].tile;
+    used += (double)queue_bytes(sc[i], tuned ? tuned_capacity(T[i], res[i].e) : res[i].cap);
+  }
+  while (used > (double)budget) {
+    int best = -1;
+    size_t bytes = 0;
+    for (int i : todo) {
+      const size_t floor_t = std::min<size_t>(roots_of(sc[i], p->spp), 65536);
+      const size_t b = queue_bytes(sc[i], tuned_capacity(T[i], res[i].e));
+      if (T[i] > floor_t && b > bytes) { best = i; bytes = b; }
+    }
+    if (best < 0) throw Status(MARS_E_OOM, "queue memory budget too small for the batch");
+    const size_t floor_t = std::min<size_t>(roots_of(sc[best], p->spp), 65536);
+    T[best] = std::max(floor_t, (T[best] + 1) / 2);
+    used += (double)queue_bytes(sc[best], tuned_capacity(T[best], res[best].e)) - (double)bytes;
+  }
+  // measure: the planned tile and two smaller ones, one timed iteration each
+  for (int i : todo) {
+    Scene* s = sc[i];
+    const size_t floor_t = std::min<size_t>(roots_of(s, p->spp), 65536);
+    std::vector<size_t> cand;
+    for (size_t t = T[i]; cand.size() < 3; t /= 2) {
+      const size_t tt = std::max(floor_t, t);
+      if (std::find(cand.begin(), cand.end(), tt) == cand.end()) cand.push_back(tt);
+      if (tt == floor_t) break;
+    }
+    double best_ms = INFINITY;
+    size_t best_t = cand[0];
+    for (size_t k = 0; k < cand.size(); ++k) {
+      configure(s, tuned_capacity(cand[k], res[i].e), (int)std::min<size_t>(cand[k], 0x7FFFFFFF));
+      if (k == 0) render_iteration(s, p, nullptr);  // first use of the new buffers
+      mars_iter_stats S{};
+      render_iteration(s, p, &S);
+      if (S.ms < best_ms) { best_ms = S.ms; best_t = cand[k]; }
+    }
+    res[i].tile = (int)std::min<size_t>(best_t, 0x7FFFFFFF);
+    res[i].cap = tuned_capacity(best_t, res[i].e);
+    res[i].ms = best_ms;
+    configure(s, res[i].cap, res[i].tile);
+    const std::string k = scene_class(s, p);
+    if (TuneEntry* t = find(k)) *t = res[i];
+    else cache.push_back({k, res[i]});
+  }
+  if (path && !todo.empty()) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) throw Status(MARS_E_IO, "cannot write the autotuner cache");
+    for (auto& e : cache)
+      std::fprintf(f, "%s %llu %d %.6g %.6g\n", e.first.c_str(), (unsigned long long)e.second.cap,
+                   e.second.tile, e.second.e, e.second.ms);
+    if (std::fclose(f) != 0) throw Status(MARS_E_IO, "cannot write the autotuner cache");
+  }
+  for (int i = 0; i < n; ++i) {
+    if (ocap) ocap[i] = (int64_t)sc[i]->cap;
+    if (otile) otile[i] = sc[i]->tile_roots;
+    if (opeak) opeak[i] = res[i].e;
   }
 }
 
@@ -841,6 +1309,12 @@ mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
 
 mars_status mars_destroy(mars_ctx* ctx) {
   if (!ctx) return MARS_E_ARG;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& g : ctx->graphs) ctx->drop_graph(g);
+  ctx->graphs.clear();
+  for (auto s : ctx->pool) (void)hipStreamDestroy(s);
+  for (auto e : ctx->pool_ev) (void)hipEventDestroy(e);
+  if (ctx->origin) (void)hipStreamDestroy(ctx->origin);
   for (auto& s : ctx->scenes) release_scene(s.get());
   if (ctx->tcount) ctx->dfree(ctx->tcount);
   delete ctx;
@@ -919,18 +1393,72 @@ mars_status mars_render_iteration(mars_ctx* ctx, int32_t scene_id, const mars_it
 
 mars_status mars_render_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
                               const mars_iter_params* p, mars_iter_stats* stats) {
-  if (!ctx || !scene_ids || n <= 0) return MARS_E_ARG;
+  if (!ctx || !scene_ids || n <= 0 || !p) return MARS_E_ARG;
   return guard(ctx, [&] {
-    mars_iter_stats tot{};
-    for (int i = 0; i < n; ++i) {
-      mars_iter_stats one{};
-      render_iteration(ctx->scene(scene_ids[i]), p, &one);
-      tot.rays_camera += one.rays_camera; tot.rays_ext += one.rays_ext;
-      tot.rays_shadow += one.rays_shadow; tot.rays_light += one.rays_light;
-      tot.rays_conn += one.rays_conn; tot.vertices += one.vertices; tot.samples += one.samples;
-      tot.tiles += one.tiles; tot.overflow_retries += one.overflow_retries; tot.ms += one.ms;
+    auto t0 = std::chrono::steady_clock::now();
+    bool graph = p->debug_depth <= 0;
+    for (int i = 0; i < n; ++i)
+      if (ctx->scene(scene_ids[i])->mlp_on) graph = false;
+    std::vector<mars_iter_stats> one(n);
+    if (graph) {
+      batch_iterate(ctx, scene_ids, n, p, 0, one.data(), nullptr);
+    } else {
+      for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < i; ++j)
+          if (scene_ids[j] == scene_ids[i]) throw Status(MARS_E_ARG, "a scene appears twice in the batch");
+        render_iteration(ctx->scene(scene_ids[i]), p, &one[i]);
+      }
     }
+    mars_iter_stats tot{};
+    for (const auto& o : one) {
+      tot.rays_camera += o.rays_camera; tot.rays_ext += o.rays_ext;
+      tot.rays_shadow += o.rays_shadow; tot.rays_light += o.rays_light;
+      tot.rays_conn += o.rays_conn; tot.vertices += o.vertices; tot.samples += o.samples;
+      tot.tiles += o.tiles; tot.overflow_retries += o.overflow_retries;
+    }
+    tot.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = tot;
+  });
+}
+
+mars_status mars_iterate_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                               const mars_iter_params* p, int32_t flags,
+                               mars_iter_stats* iter_stats, mars_update_stats* upd_stats) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] { batch_iterate(ctx, scene_ids, n, p, flags, iter_stats, upd_stats); });
+}
+
+mars_status mars_scene_configure(mars_ctx* ctx, int32_t scene_id, int64_t queue_capacity,
+                                 int32_t tile_roots) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (queue_capacity < 0 || queue_capacity > (int64_t)0xFFFF0000ull || tile_roots < 0)
+      throw Status(MARS_E_ARG, "bad queue capacity or tile size");
+    const size_t cap = queue_capacity > 0 ? (size_t)queue_capacity : s->cap;
+    const size_t tile = tile_roots > 0 ? (size_t)tile_roots : (size_t)s->tile_roots;
+    if (tile > cap) throw Status(MARS_E_ARG, "tile larger than the queue capacity");
+    configure(s, cap, (int)tile);
+  });
+}
+
+mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_capacity,
+                             int32_t* tile_roots, double* peak_per_root) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (queue_capacity) *queue_capacity = (int64_t)s->cap;
+    if (tile_roots) *tile_roots = s->tile_roots;
+    if (peak_per_root) *peak_per_root = s->peak_per_root;
+  });
+}
+
+mars_status mars_autotune(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                          const mars_iter_params* p, int64_t mem_budget, const char* cache_path,
+                          int64_t* out_capacity, int32_t* out_tile, double* out_peak) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    autotune(ctx, scene_ids, n, p, mem_budget, cache_path, out_capacity, out_tile, out_peak);
   });
 }
 
@@ -947,11 +1475,12 @@ mars_status mars_set_fixed_counts(mars_ctx* ctx, int32_t scene_id, const float* 
     if (n != 1 && n != s->n_cells) throw Status(MARS_E_ARG, "n must be 1 or the number of cells");
     for (int i = 0; i < 3 * n; ++i)
       if (!std::isfinite(beta[i]) || beta[i] < 0.0f) throw Status(MARS_E_ARG, "bad fixed count");
-    if (n > s->n_fixed) s->fixed = salloc<float>(s, 3 * (size_t)s->max_cells);
+    if (!s->fixed) s->fixed = salloc<float>(s, 3 * (size_t)s->max_cells);
     h2d(s->fixed, beta, 12 * (size_t)n, ctx->stream);
     s->n_fixed = n;
     s->cd.fixed = s->fixed;
     s->cd.n_fixed = n;
+    s->epoch++;  // the cache view is captured by value
     HIPCHK(hipStreamSynchronize(ctx->stream));
   });
 }
@@ -994,7 +1523,8 @@ mars_status mars_update_cells_only(mars_ctx* ctx, int32_t scene_id, double V_I, 
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
     Scene* s = ctx->scene(scene_id);
-    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, 0, V_I, s->max_cells, ctx->stream);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 0, V_I, s->max_cells,
+                  nullptr, ctx->stream);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
   });
@@ -1006,7 +1536,7 @@ mars_status mars_refine_only(mars_ctx* ctx, int32_t scene_id, int32_t* n_split) 
     Scene* s = ctx->scene(scene_id);
     const int before = s->n_cells;
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
-             s->max_tree_depth, s->max_cells, ctx->stream);
+             s->max_tree_depth, s->max_cells, nullptr, ctx->stream);
     int32_t nc[4];
     d2h(nc, s->n_cells_dev, sizeof(nc), ctx->stream);
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1225,6 +1755,7 @@ mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* pa
     h2d(s->n_cells_dev, ncv, 16, st);
     std::vector<double> red(8, 0.0);
     red[5] = h.ivw_w;
+    red[6] = h.total_spp;
     h2d(s->img.red, red.data(), 64, st);
     HIPCHK(hipStreamSynchronize(st));
     s->n_cells = h.n_cells;

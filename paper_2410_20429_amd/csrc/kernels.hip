@@ -59,6 +59,27 @@ void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 void k_fill_f64(double* p, double v, size_t n, hipStream_t s) {
   if (n) fill_kernel<double><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
 }
+// update kernels become no-ops while a skip flag is set (an overflowed
+// iteration that is rendered again before its update)
+#define SKIP_IF(flag) \
+  if ((flag) && *(flag)) return
+
+template <typename T>
+__global__ void fill_dev_kernel(T* p, T v, const int32_t* n_dev, int mult, size_t max_n) {
+  const size_t n = min((size_t)(*n_dev) * (size_t)mult, max_n);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void k_fill_f64_dev(double* p, double v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s) {
+  fill_dev_kernel<double><<<(unsigned)std::min<size_t>((max_n + 255) / 256, 4096), 256, 0, s>>>(
+      p, v, n_dev, mult, max_n);
+}
+void k_fill_u32_dev(uint32_t* p, uint32_t v, const int32_t* n_dev, int mult, size_t max_n,
+                    hipStream_t s) {
+  fill_dev_kernel<uint32_t><<<(unsigned)std::min<size_t>((max_n + 255) / 256, 4096), 256, 0, s>>>(
+      p, v, n_dev, mult, max_n);
+}
 void k_fill_f32(float* p, float v, size_t n, hipStream_t s) {
   if (n) fill_kernel<float><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
 }
@@ -75,7 +96,7 @@ __global__ void raygen_kernel(SceneDev sc, QueuesDev q, Counters* cnt, IterDev i
   const uint32_t root = root0 + j;
   const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
   const int px = (int)(pix % (uint32_t)sc.W), py = (int)(pix / (uint32_t)sc.W);
-  const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagCam);
+  const uint2 st = stream_root(key, pix, s, (uint32_t)iter_index(it), kTagCam);
   const float4 u = draw4(key, st, 1);
   const float jx = it.center_jitter ? 0.5f : u.x, jy = it.center_jitter ? 0.5f : u.y;
   const float sx = (((float)px + jx) / (float)sc.W) * 2.0f - 1.0f;
@@ -435,6 +456,7 @@ __global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, 
     if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.cap)) {
       ovf = true;
       atomicMax(&cnt->overflow, 1u);
+      atomicMax(&cnt->overflow_any, 1u);
     }
     if (!active) continue;
     q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
@@ -627,6 +649,8 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
                                                           const Counters* cnt, IterDev it,
                                                           ImageDev img, int d) {
   __shared__ AggTable A;
+  // an overflowed tile left child ranges unwritten: it is rendered again
+  if (cnt->overflow) return;
   for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
     A.key[k] = kAggEmpty;
     for (int i = 0; i < kAggVals; ++i) A.val[k][i] = 0.0;
@@ -856,7 +880,7 @@ __global__ void light_start_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counte
   q.R1[j] = make_float4(0.0f, 0.0f, 0.0f, fbits(root));
   if (sc.n_lights == 0) return;
   const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
-  const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagLight);
+  const uint2 st = stream_root(key, pix, s, (uint32_t)iter_index(it), kTagLight);
   const float4 u = draw4(key, st, 0), u2 = draw4(key, st, 1);
   int lo = 0, hi = sc.n_lights - 1;
   while (lo < hi) {
@@ -922,7 +946,7 @@ __global__ void light_shade_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counte
     bool alive = false;
     if (i < lt.lmax) {
       const uint32_t pix = root / (uint32_t)it.spp, s = root % (uint32_t)it.spp;
-      const uint2 st = stream_root(key, pix, s, (uint32_t)it.iteration, kTagLight);
+      const uint2 st = stream_root(key, pix, s, (uint32_t)iter_index(it), kTagLight);
       const float4 u = draw4(key, st, (uint32_t)(1 + i));
       const float4 rr = q.S1[j];
       const float qv = fminf(1.0f, fmaxf(fmaxf(rr.x, rr.y), rr.z));
@@ -1062,6 +1086,7 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
     if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nsh > q.cap)) {
       ovf = true;
       atomicMax(&cnt->overflow, 1u);
+      atomicMax(&cnt->overflow_any, 1u);
     }
     if (!active) continue;
     q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
@@ -1229,6 +1254,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
                                                             IterDev it, ImageDev img, int d,
                                                             uint32_t npool) {
   __shared__ AggTable A;
+  if (cnt->overflow) return;
   for (int k = threadIdx.x; k < kAggSlots; k += blockDim.x) {
     A.key[k] = kAggEmpty;
     for (int i = 0; i < kAggVals; ++i) A.val[k][i] = 0.0;
@@ -1338,7 +1364,8 @@ void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
 //   least 4 samples of technique t in the iteration, else 0
 // ---------------------------------------------------------------------------
 __global__ void mlp_targets_kernel(SceneDev sc, CacheDev c, MlpDev m, ImageDev img, IterDev it,
-                                   uint32_t cap) {
+                                   uint32_t cap, const uint32_t* skip) {
+  SKIP_IF(skip);
   const uint32_t n = min(*m.n_rec, cap);
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -1376,8 +1403,8 @@ __global__ void mlp_targets_kernel(SceneDev sc, CacheDev c, MlpDev m, ImageDev i
   }
 }
 void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const ImageDev& img,
-                   const IterDev& it, uint32_t n, hipStream_t s) {
-  if (n) mlp_targets_kernel<<<(n + 255) / 256, 256, 0, s>>>(sc, c, m, img, it, n);
+                   const IterDev& it, uint32_t n, const uint32_t* skip, hipStream_t s) {
+  if (n) mlp_targets_kernel<<<(n + 255) / 256, 256, 0, s>>>(sc, c, m, img, it, n, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1425,7 +1452,18 @@ __device__ __forceinline__ void block_add_d(double v, double* dst) {
   __syncthreads();
 }
 
-__global__ void accum_mean_kernel(ImageDev img, int npx, float tsp) {
+__global__ void add_spp_kernel(double* total, int spp, const uint32_t* skip) {
+  SKIP_IF(skip);
+  *total += (double)spp;
+}
+void k_add_spp(double* total_spp, int spp, const uint32_t* skip, hipStream_t s) {
+  add_spp_kernel<<<1, 1, 0, s>>>(total_spp, spp, skip);
+}
+
+__global__ void accum_mean_kernel(ImageDev img, int npx, const double* total_spp,
+                                  const uint32_t* skip) {
+  SKIP_IF(skip);
+  const float tsp = (float)*total_spp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double m[3] = {0.0, 0.0, 0.0};
   if (i < npx) {
@@ -1441,7 +1479,8 @@ __global__ void accum_mean_kernel(ImageDev img, int npx, float tsp) {
   for (int ch = 0; ch < 3; ++ch) block_add_d(m[ch], img.red + ch);
 }
 
-__global__ void itilde_kernel(ImageDev img, int W, int H) {
+__global__ void itilde_kernel(ImageDev img, int W, int H, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * H) return;
   const int y = i / W, x = i % W;
@@ -1467,9 +1506,10 @@ __global__ void itilde_kernel(ImageDev img, int W, int H) {
 
 // BDPT: the 10 pixels with the largest iteration luminance leave V_I
 // (Sec. 5.1); ties go to the lower index.  One workgroup, ten passes.
-__global__ void brightest_kernel(ImageDev img, int npx) {
+__global__ void brightest_kernel(ImageDev img, int npx, const uint32_t* skip) {
   __shared__ float bl[1024];
   __shared__ int bi[1024];
+  SKIP_IF(skip);
   for (int k = 0; k < 10 && k < npx; ++k) {
     float best = -1.0f;
     int idx = -1;
@@ -1499,7 +1539,8 @@ __global__ void brightest_kernel(ImageDev img, int npx) {
   }
 }
 
-__global__ void vi_kernel(ImageDev img, int npx, int spp, float kc) {
+__global__ void vi_kernel(ImageDev img, int npx, int spp, float kc, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0.0, inc = 0.0;
   if (i < npx && img.excl[i] == 0) {
@@ -1520,14 +1561,18 @@ __global__ void vi_kernel(ImageDev img, int npx, int spp, float kc) {
   block_add_d(inc, img.red + 4);
 }
 
-void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
-                    float stat_clamp, hipStream_t s) {
+__global__ void clear_red_kernel(double* red, const uint32_t* skip) {
+  SKIP_IF(skip);
+  if (threadIdx.x < 5) red[threadIdx.x] = 0.0;
+}
+void k_update_image(const ImageDev& img, int W, int H, int spp, const double* total_spp, int bdpt,
+                    float stat_clamp, const uint32_t* skip, hipStream_t s) {
   const int npx = W * H;
-  k_fill_f64(img.red, 0.0, 5, s);
-  accum_mean_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, total_spp);
-  itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H);
-  if (bdpt) brightest_kernel<<<1, 1024, 0, s>>>(img, npx);
-  vi_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, stat_clamp);
+  clear_red_kernel<<<1, 64, 0, s>>>(img.red, skip);
+  accum_mean_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, total_spp, skip);
+  itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H, skip);
+  if (bdpt) brightest_kernel<<<1, 1024, 0, s>>>(img, npx, skip);
+  vi_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, stat_clamp, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1536,7 +1581,14 @@ void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp,
 //   a^RR = C_I / (C_t V_I) E[v^2],  a^S = C_I / (C_t V_I) V[v]   per channel
 // ---------------------------------------------------------------------------
 __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const double* red,
-                                   double C_I, int use_dev, double V_host) {
+                                   double C_I, const Counters* cnt, double roots, int use_dev,
+                                   double V_host, const uint32_t* skip) {
+  SKIP_IF(skip);
+  if (cnt) {
+    const double rays = roots + (double)(cnt->rays_ext + cnt->rays_shadow + cnt->rays_light +
+                                         cnt->rays_conn);
+    C_I = rays / roots;
+  }
   const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (cidx >= *n_cells_dev) return;
   const double V_I = use_dev ? (red[4] > 0.0 ? red[3] / red[4] : 0.0) : V_host;
@@ -1558,13 +1610,15 @@ __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const
   }
 }
 void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
-                   int use_device_vi, double V_I_host, int max_cells, hipStream_t s) {
-  fixed_point_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, red, C_I,
-                                                               use_device_vi, V_I_host);
+                   const Counters* cnt, double roots, int use_device_vi, double V_I_host,
+                   int max_cells, const uint32_t* skip, hipStream_t s) {
+  fixed_point_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, red, C_I, cnt, roots,
+                                                               use_device_vi, V_I_host, skip);
 }
 
 // guided distribution of the next iteration: 0.9 learned + 0.1 uniform
-__global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev) {
+__global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (cidx >= *n_cells_dev) return;
   const double* h = c.hacc + 64 * (size_t)cidx;
@@ -1579,8 +1633,9 @@ __global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev) {
     c.cdf[64 * (size_t)cidx + b] = b == 63 ? 1.0f : (float)run;
   }
 }
-void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells, hipStream_t s) {
-  hist_normalize_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev);
+void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells,
+                      const uint32_t* skip, hipStream_t s) {
+  hist_normalize_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1589,14 +1644,17 @@ void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cel
 // allows.  flags -> one-workgroup exclusive scan -> apply.
 // ---------------------------------------------------------------------------
 __global__ void split_flags_kernel(CacheDev c, const int32_t* n_cells_dev, uint32_t* flags,
-                                   int split_visits, int max_tree_depth) {
+                                   int split_visits, int max_tree_depth, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= *n_cells_dev) return;
   flags[l] = (c.visits[l] > (uint32_t)split_visits && c.leaf_depth[l] < (uint32_t)max_tree_depth)
                  ? 1u : 0u;
 }
-__global__ void scan_flags_kernel(const int32_t* n_cells_dev, uint32_t* flags, uint32_t* total) {
+__global__ void scan_flags_kernel(const int32_t* n_cells_dev, uint32_t* flags, uint32_t* total,
+                                  const uint32_t* skip) {
   __shared__ uint32_t part[1024];
+  SKIP_IF(skip);
   const int n = *n_cells_dev;
   const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
   const int b = threadIdx.x * chunk, e = min(n, b + chunk);
@@ -1620,7 +1678,8 @@ __global__ void scan_flags_kernel(const int32_t* n_cells_dev, uint32_t* flags, u
 }
 __global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
                                    const int32_t* n_nodes_dev, const uint32_t* rank,
-                                   const uint32_t* total, int max_cells) {
+                                   const uint32_t* total, int max_cells, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int n0 = *n_cells_dev, nn0 = *n_nodes_dev;
   if (l >= n0) return;
@@ -1648,7 +1707,8 @@ __global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
   }
 }
 __global__ void finish_split_kernel(int32_t* n_cells_dev, int32_t* n_nodes_dev,
-                                    const uint32_t* total, int max_cells) {
+                                    const uint32_t* total, int max_cells, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int n0 = *n_cells_dev;
   const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
   const uint32_t acc = min(*total, room);
@@ -1656,17 +1716,43 @@ __global__ void finish_split_kernel(int32_t* n_cells_dev, int32_t* n_nodes_dev,
   *n_nodes_dev = *n_nodes_dev + 8 * (int)acc;
 }
 void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
-              int split_visits, int max_tree_depth, int max_cells, hipStream_t s) {
+              int split_visits, int max_tree_depth, int max_cells, const uint32_t* skip,
+              hipStream_t s) {
   const int g = (max_cells + 255) / 256;
-  split_flags_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, scratch, split_visits, max_tree_depth);
-  scan_flags_kernel<<<1, 1024, 0, s>>>(n_cells_dev, scratch, scratch + max_cells);
+  split_flags_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, scratch, split_visits, max_tree_depth, skip);
+  scan_flags_kernel<<<1, 1024, 0, s>>>(n_cells_dev, scratch, scratch + max_cells, skip);
   apply_split_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch, scratch + max_cells,
-                                       max_cells);
-  finish_split_kernel<<<1, 1, 0, s>>>(n_cells_dev, n_nodes_dev, scratch + max_cells, max_cells);
+                                       max_cells, skip);
+  finish_split_kernel<<<1, 1, 0, s>>>(n_cells_dev, n_nodes_dev, scratch + max_cells, max_cells, skip);
 }
 
 // inverse-variance weighted combination of the iterations (Sec. 5.1)
-__global__ void ivw_kernel(ImageDev img, int npx, int spp) {
+// per-scene summary of a batched iteration, gathered for one read-back:
+// [0] overflow, [1..6] ray / vertex / sample totals, [7..14] image
+// reductions, [15] cells, [16] nodes
+__global__ void batch_summary_kernel(const Counters* cnt, const double* red,
+                                     const int32_t* n_cells_dev, double* out) {
+  const int t = threadIdx.x;
+  if (t == 0) out[0] = (double)cnt->overflow_any;
+  if (t == 1) out[1] = (double)cnt->rays_ext;
+  if (t == 2) out[2] = (double)cnt->rays_shadow;
+  if (t == 3) out[3] = (double)cnt->rays_light;
+  if (t == 4) out[4] = (double)cnt->rays_conn;
+  if (t == 5) out[5] = (double)cnt->vertices;
+  if (t == 6) out[6] = (double)cnt->samples;
+  if (t >= 7 && t < 15) out[t] = red[t - 7];
+  if (t == 15) out[15] = (double)n_cells_dev[0];
+  if (t == 16) out[16] = (double)n_cells_dev[1];
+}
+void k_batch_summary(const Counters* cnt, const double* red, const int32_t* n_cells_dev,
+                     double* out, hipStream_t s) {
+  batch_summary_kernel<<<1, 64, 0, s>>>(cnt, red, n_cells_dev, out);
+}
+__global__ void set_i32_kernel(int32_t* p, int32_t v) { *p = v; }
+void k_set_i32(int32_t* p, int32_t v, hipStream_t s) { set_i32_kernel<<<1, 1, 0, s>>>(p, v); }
+
+__global__ void ivw_kernel(ImageDev img, int npx, int spp, const uint32_t* skip) {
+  SKIP_IF(skip);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double V_I = img.red[4] > 0.0 ? img.red[3] / img.red[4] : 0.0;
   if (!(V_I > 0.0)) return;
@@ -1678,8 +1764,8 @@ __global__ void ivw_kernel(ImageDev img, int npx, int spp) {
     img.ivw_acc[e] += w * (double)(img.iter_sum[e] / (float)spp);
   }
 }
-void k_ivw(const ImageDev& img, int npx, int spp, hipStream_t s) {
-  ivw_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp);
+void k_ivw(const ImageDev& img, int npx, int spp, const uint32_t* skip, hipStream_t s) {
+  ivw_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, skip);
 }
 
 // ---------------------------------------------------------------------------

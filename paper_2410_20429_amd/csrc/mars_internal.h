@@ -70,13 +70,18 @@ struct QueuesDev {
   size_t cap;   // entries per depth (rays and shadow rays each)
 };
 
+// queue counters of a tile (the first kTileWords words, reset per tile) and
+// totals of an iteration (reset per iteration)
 struct Counters {
   uint32_t n_ray[kMaxDepth + 2];
   uint32_t n_shadow[kMaxDepth + 2];
   uint32_t overflow;
+  uint32_t overflow_any;  // sticky over the iteration: the update then skips
   uint32_t n_debug;
+  uint32_t pad;
   unsigned long long rays_ext, rays_shadow, vertices, samples, rays_light, rays_conn;
 };
+constexpr int kTileWords = 2 * (kMaxDepth + 2) + 1;
 
 // BDPT light subpaths of an iteration, one per camera sample (root)
 struct LightDev {
@@ -92,7 +97,11 @@ struct IterDev {
   int32_t iteration, spp, alloc, aware, rr_start, fixed_scale;
   float clamp_lo, clamp_hi, stat_clamp;
   int32_t center_jitter, debug_depth, lp_stride;
+  const int32_t* iter_dev;  // if set, the iteration index is read here (graph replays)
 };
+__host__ __device__ inline int32_t iter_index(const IterDev& it) {
+  return it.iter_dev ? *it.iter_dev : it.iteration;
+}
 
 struct DebugRec {
   uint32_t root, depth, stream_lo, stream_hi, cell;
@@ -164,7 +173,7 @@ void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s);
 void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const ImageDev& img,
-                   const IterDev& it, uint32_t n, hipStream_t s);
+                   const IterDev& it, uint32_t n, const uint32_t* skip, hipStream_t s);
 // ---- launchers (mlp.hip) ----
 void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream_t s);
 void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
@@ -177,14 +186,29 @@ void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, 
 void k_mlp_quantize(const MlpDev& m, hipStream_t s);
 void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D, hipStream_t s);
 void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s);
-void k_update_image(const ImageDev& img, int W, int H, int spp, float total_spp, int bdpt,
-                    float stat_clamp, hipStream_t s);
+// update kernels: `skip` (optional) points at a flag that makes them no-ops
+// (an iteration whose queues overflowed is re-run before its update)
+void k_update_image(const ImageDev& img, int W, int H, int spp, const double* total_spp, int bdpt,
+                    float stat_clamp, const uint32_t* skip, hipStream_t s);
+void k_add_spp(double* total_spp, int spp, const uint32_t* skip, hipStream_t s);
+// C_I from rays / (pixels x spp): given on the host (cnt == null) or taken
+// from the iteration totals in `cnt` plus the camera rays `roots`
 void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
-                   int use_device_vi, double V_I_host, int max_cells, hipStream_t s);
-void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells, hipStream_t s);
+                   const Counters* cnt, double roots, int use_device_vi, double V_I_host,
+                   int max_cells, const uint32_t* skip, hipStream_t s);
+void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells,
+                      const uint32_t* skip, hipStream_t s);
 void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
-              int split_visits, int max_tree_depth, int max_cells, hipStream_t s);
-void k_ivw(const ImageDev& img, int npx, int spp, hipStream_t s);
+              int split_visits, int max_tree_depth, int max_cells, const uint32_t* skip,
+              hipStream_t s);
+void k_ivw(const ImageDev& img, int npx, int spp, const uint32_t* skip, hipStream_t s);
+constexpr int kSumWords = 17;
+void k_batch_summary(const Counters* cnt, const double* red, const int32_t* n_cells_dev,
+                     double* out, hipStream_t s);
+void k_set_i32(int32_t* p, int32_t v, hipStream_t s);
+// fills n_dev[0] * mult elements (n_dev read on the device)
+void k_fill_f64_dev(double* p, double v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s);
+void k_fill_u32_dev(uint32_t* p, uint32_t v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s);
 void k_probe(int kind, int n, const void* in, void* out, hipStream_t s);
 
 }  // namespace mars

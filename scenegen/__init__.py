@@ -307,3 +307,39 @@ def make_interior(seed=1, width=1280, height=720, n_pieces=2000, n_proto=16, tes
     tm += [occ_id] * len(panel)
     cam = [-4.3, 1.6, -3.4, 1.0, 0.9, 1.5, 0.0, 1.0, 0.0, 60.0]
     return _finish(np.concatenate(chunks), tm, mats, cam, width, height, f"interior_s{seed}")
+
+
+# --------------------------------------------------------------------------
+# Batched workload: independent requests of uneven size.  Resolution uniform
+# over {64, 128, 256, 512, 1024}^2, triangle count log-uniform in
+# [tris_lo, tris_hi], half guided-PT heightfields and half BDPT interiors
+# (shuffled), path depth uniform in [6, 12].  Each entry is a scene dict
+# with the extra keys "mode" ("guided" or "bdpt") and "max_depth".
+# --------------------------------------------------------------------------
+def make_batch(seed=1, n=32, tris_lo=1000, tris_hi=500000, res=(64, 128, 256, 512, 1024),
+               depth_lo=6, depth_hi=12):
+    rng = np.random.default_rng(seed)
+    kinds = np.array(["guided"] * (n // 2) + ["bdpt"] * (n - n // 2))
+    rng.shuffle(kinds)
+    out = []
+    for j in range(n):
+        r = int(rng.choice(res))
+        target = math.exp(rng.uniform(math.log(tris_lo), math.log(tris_hi)))
+        depth = int(rng.integers(depth_lo, depth_hi + 1))
+        sub = int(rng.integers(1, 1 << 30))
+        if kinds[j] == "guided":
+            # 2 (grid - 1)^2 heightfield triangles carry ~90 % of the target
+            grid = max(8, int(round(math.sqrt(0.45 * target))) + 1)
+            boxes = max(2, int(0.1 * target / 12))
+            sc = make_heightfield_scene(seed=sub, width=r, height=r, grid=grid, n_boxes=boxes)
+        else:
+            tess = 3 if target > 20000 else 1
+            per_piece = 4.5 * 6 * tess * tess * 2
+            pieces = max(1, int(round((target - 26) / per_piece)))
+            sc = make_interior(seed=sub, width=r, height=r, n_pieces=pieces,
+                               n_proto=min(16, pieces), tess=tess)
+        sc["mode"] = str(kinds[j])
+        sc["max_depth"] = depth
+        sc["name"] = f"batch{seed}_{j}_{sc['mode']}_{r}"
+        out.append(sc)
+    return out
