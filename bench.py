@@ -88,6 +88,112 @@ def cells_budget(mbytes=72.0):
     return int(mbytes * 1e6 / (72 + 192 + 12 + 512 + 512 + 32))
 
 
+BATCH_WORKLOAD = "batch32_mixed_guided_bdpt"
+
+
+def run_batch(args, api, torch, seed=1, budget=64 << 30):
+    """The batched workload: 32 independent scenes (resolution uniform over
+    64^2 .. 1024^2, 1k-500k triangles log-uniform, half guided PT and half
+    BDPT, depth 6-12, counts clamped to 8), one step = one iteration of every
+    scene (render at 1 spp + update) as one replay of the captured graph.
+    Queue and tile sizes come from the autotuner under a 64 GiB queue budget.
+    Beside it: the same iterations through the per-scene calls."""
+    import scenegen
+    t0 = time.perf_counter()
+    scenes = scenegen.make_batch(seed=seed)
+    ctx = api.Context(0)
+    modes = {"guided": api.MODE_PT_GUIDED, "bdpt": api.MODE_BDPT}
+    S, E = [], []
+    for sc in scenes:
+        roots = sc["width"] * sc["height"]
+        kw = dict(mode=modes[sc["mode"]], max_depth=sc["max_depth"], max_cells=cells_budget(),
+                  queue_capacity=min(4 * roots, 1 << 19), tile_roots=min(roots, 1 << 17))
+        S.append(api.Scene(ctx, sc, **kw))
+        E.append(api.Scene(ctx, sc, **kw))
+    print(f"[bench] batch: {len(S)} scenes uploaded twice in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def params(i):
+        alloc = api.ALLOC_CLASSIC if i < 2 else api.ALLOC_MARS
+        return api.iter_params(iteration=i, spp=1, alloc=alloc, stat_clamp=50.0, clamp_hi=8.0)
+
+    warm = max(3, args.warmup)
+    for i in range(warm):
+        api.iterate_batch(S, params(i))
+        for e in E:
+            e.render_iteration(params(i))
+            e.update(params(i))
+    torch.cuda.synchronize()
+    # tuned on a MARS iteration: splitting sets the queue peaks
+    t1 = time.perf_counter()
+    tuned = api.autotune(S, params(warm), mem_budget=budget)
+    for e, (cap, tile, _) in zip(E, tuned):
+        e.configure(queue_capacity=cap, tile_roots=tile)
+    torch.cuda.empty_cache()  # queue buffers replaced while tuning
+    print(f"[bench] batch: autotuned in {time.perf_counter() - t1:.1f} s", file=sys.stderr,
+          flush=True)
+    # first use of the tuned sizes (graph capture) outside the timed region
+    api.iterate_batch(S, params(warm))
+    for e in E:
+        e.render_iteration(params(warm))
+        e.update(params(warm))
+    torch.cuda.synchronize()
+    print("[bench] batch: warm", file=sys.stderr, flush=True)
+    warm += 1
+    reruns = []
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def graph_steps(i0):
+        for k in range(args.steps):
+            its, _ = api.iterate_batch(S, params(i0 + k))
+            reruns.append(sum(1 for s in its if s.overflow_retries > 0))
+
+    def eager_steps(i0):
+        for k in range(args.steps):
+            for e in E:
+                e.render_iteration(params(i0 + k))
+                e.update(params(i0 + k))
+
+    def pool_steps(i0):
+        for k in range(args.steps):
+            api.iterate_batch(E, params(i0 + k), graph=False)
+
+    dt = timed(lambda: graph_steps(warm))
+    ctx.profile(True)
+    dt_eager = timed(lambda: eager_steps(warm))
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    dt_pool = timed(lambda: pool_steps(warm + args.steps))
+    px = sum(sc["width"] * sc["height"] for sc in scenes)
+    tris = sum(int(sc["V"].shape[0]) for sc in scenes)
+    ctx_out = {
+        "metric": "Mpaths/s (batched iterations of 32 scenes)",
+        "value": px * args.steps / dt / 1e6,
+        "unit": "Mpaths/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": warm,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD, "scenes": len(scenes), "pixels_per_step": px,
+                   "triangles": tris, "spp_per_step": 1, "clamp_hi": 8.0,
+                   "guided": sum(sc["mode"] == "guided" for sc in scenes),
+                   "bdpt": sum(sc["mode"] == "bdpt" for sc in scenes),
+                   "queue_bytes": sum(c * (s.max_depth + 2) * 216 for s, (c, _, _) in zip(S, tuned))},
+        "eager_ms_per_step": dt_eager * 1e3 / args.steps,
+        "stream_pool_ms_per_step": dt_pool * 1e3 / args.steps,
+        "graph_speedup_vs_eager": dt_eager / dt,
+        "overflow_reruns_per_step": reruns,
+        "eager_kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+    }
+    return ctx_out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +204,8 @@ def main():
                     help="(profiling runs) skip the instrumented iteration and the CPU leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", default="guided", choices=["guided", "batch"],
+                    help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
@@ -109,6 +217,9 @@ def main():
     import scenegen
     from paper_2410_20429_amd import api
 
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args, api, torch)), flush=True)
+        return
     sc = scenegen.make_heightfield_scene(seed=1)
     ctx = api.Context(0)
     s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())

@@ -196,9 +196,10 @@ mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_cap
  * then hold the probe's) measures the peak queue occupancy per camera sample
  * e; tiles of up to all camera samples are planned under mem_budget bytes of
  * queue memory for the n scenes together (capacity = tile x e x 1.25,
- * largest scenes halved first); then up to three tile sizes (plan, plan/2,
- * plan/4; at least 65536 samples) are timed with one render iteration each
- * and the fastest kept.  cache_path (optional): a text file of lines
+ * largest scenes halved first, no tile below min(all samples, max(4096,
+ * 2^18 / e)) rounded up to 64); then up to three tile sizes (plan, plan/2,
+ * plan/4, same floor) are timed with one render iteration each and the
+ * fastest kept.  cache_path (optional): a text file of lines
  * "<class> <capacity> <tile> <e> <ms>" keyed by the scene class (resolution,
  * spp, mode, depth, triangles, allocation mode); classes found there are
  * applied without probing and new ones appended.  out (optional, n entries

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -132,7 +133,7 @@ struct Profiler {
 // a captured batch: the key lists everything the launches bake in
 struct BatchGraph {
   std::vector<uint64_t> key;
-  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphExec_t> exec;  // one single-chain graph per stream of the pool
   int32_t* iter = nullptr;    // device: iteration index read by the kernels
   double* summary = nullptr;  // device: [n][kSumWords]
 };
@@ -141,10 +142,10 @@ struct Ctx {
   int device = 0;
   uint64_t next_uid = 1;
   // batched iterations: a pool of default-priority streams and the graph cache
-  hipStream_t origin = nullptr;
   std::vector<hipStream_t> pool;
   std::vector<hipEvent_t> pool_ev;
   std::vector<BatchGraph> graphs;
+  int batch_streams = 4;
   Profiler prof;
   unsigned long long* tcount = nullptr;  // traversal counters (instrumented runs)
   bool counting = false;
@@ -173,7 +174,7 @@ struct Ctx {
     else (void)hipFree(p);
   }
   void drop_graph(BatchGraph& g) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto e : g.exec) (void)hipGraphExecDestroy(e);
     dfree(g.iter);
     dfree(g.summary);
     g = BatchGraph{};
@@ -826,7 +827,9 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
 // batched iterations: each scene's iteration enqueued with no host
 // synchronisation on one stream of a pool; the batch captured once as a graph
 // ---------------------------------------------------------------------------
-constexpr int kBatchStreams = 4;  // the hardware queues a process gets by default
+// streams of the batch pool: the hardware queues a process gets by default;
+// MARS_BATCH_STREAMS (1..16) overrides it at context creation
+constexpr int kBatchStreams = 4;
 constexpr int kGraphCache = 4;
 
 size_t roots_of(const Scene* s, int spp) { return (size_t)s->W * s->H * (size_t)spp; }
@@ -894,13 +897,12 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
 }
 
 void ensure_pool(Ctx* c) {
-  if (!c->origin) HIPCHK(hipStreamCreateWithFlags(&c->origin, hipStreamNonBlocking));
-  while ((int)c->pool.size() < kBatchStreams) {
+  while ((int)c->pool.size() < c->batch_streams) {
     hipStream_t s;
     HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     c->pool.push_back(s);
   }
-  while ((int)c->pool_ev.size() < kBatchStreams + 1) {
+  while ((int)c->pool_ev.size() < c->batch_streams + 1) {
     hipEvent_t e;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->pool_ev.push_back(e);
@@ -911,6 +913,14 @@ uint64_t fbits64(float f) {
   uint32_t u;
   std::memcpy(&u, &f, 4);
   return u;
+}
+
+void configure(Scene* s, size_t cap, int tile) {
+  if (cap && cap != s->cap) alloc_queues(s, cap);
+  if (tile > 0 && tile != s->tile_roots) {
+    s->tile_roots = tile;
+    s->epoch++;
+  }
 }
 
 void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int flags,
@@ -939,7 +949,7 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
   std::vector<int> order(n), lane(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-  const int K = std::min(n, kBatchStreams);
+  const int K = std::min(n, c->batch_streams);
   std::vector<double> load(K, 0.0);
   for (int i : order) {
     const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -971,29 +981,32 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
       ng.iter = (int32_t*)c->dalloc(sizeof(int32_t));
       ng.summary = (double*)c->dalloc((size_t)n * kSumWords * sizeof(double));
       if (use_graph) {
+        // one chain per stream: each lane's scenes captured on its own stream
+        // and launched there, the lanes running side by side
         IterDev it = to_dev(p);
         it.iter_dev = ng.iter;
-        HIPCHK(hipStreamBeginCapture(c->origin, hipStreamCaptureModeThreadLocal));
-        hipGraph_t graph = nullptr;
-        try {
-          HIPCHK(hipEventRecord(c->pool_ev[0], c->origin));
-          for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
-          for (int i : order)
-            enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, c->pool[lane[i]],
-                              ng.summary + (size_t)i * kSumWords);
-          for (int k = 0; k < K; ++k) {
-            HIPCHK(hipEventRecord(c->pool_ev[1 + k], c->pool[k]));
-            HIPCHK(hipStreamWaitEvent(c->origin, c->pool_ev[1 + k], 0));
+        for (int k = 0; k < K; ++k) {
+          hipStream_t ls = c->pool[k];
+          HIPCHK(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+          hipGraph_t graph = nullptr;
+          try {
+            for (int i : order)
+              if (lane[i] == k)
+                enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, ls,
+                                  ng.summary + (size_t)i * kSumWords);
+          } catch (...) {
+            (void)hipStreamEndCapture(ls, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
           }
-        } catch (...) {
-          (void)hipStreamEndCapture(c->origin, &graph);
-          if (graph) (void)hipGraphDestroy(graph);
-          throw;
+          HIPCHK(hipStreamEndCapture(ls, &graph));
+          hipGraphExec_t ex = nullptr;
+          const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          if (e != hipSuccess)
+            throw Status(MARS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+          ng.exec.push_back(ex);
         }
-        HIPCHK(hipStreamEndCapture(c->origin, &graph));
-        const hipError_t e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) throw Status(MARS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
       }
     } catch (...) {
       c->drop_graph(ng);
@@ -1005,20 +1018,20 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
   hipStream_t st = c->stream;
   k_set_i32(g->iter, p->iteration, st);
   timed(c, KID_BATCH, [&] {
+    HIPCHK(hipEventRecord(c->pool_ev[0], st));
+    for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
     if (use_graph) {
-      HIPCHK(hipGraphLaunch(g->exec, st));
+      for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(g->exec[k], c->pool[k]));
     } else {
       IterDev it = to_dev(p);
       it.iter_dev = g->iter;
-      HIPCHK(hipEventRecord(c->pool_ev[0], st));
-      for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
       for (int i : order)
         enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, c->pool[lane[i]],
                           g->summary + (size_t)i * kSumWords);
-      for (int k = 0; k < K; ++k) {
-        HIPCHK(hipEventRecord(c->pool_ev[1 + k], c->pool[k]));
-        HIPCHK(hipStreamWaitEvent(st, c->pool_ev[1 + k], 0));
-      }
+    }
+    for (int k = 0; k < K; ++k) {
+      HIPCHK(hipEventRecord(c->pool_ev[1 + k], c->pool[k]));
+      HIPCHK(hipStreamWaitEvent(st, c->pool_ev[1 + k], 0));
     }
   });
   std::vector<double> hs((size_t)n * kSumWords);
@@ -1031,9 +1044,12 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
     Scene* s = sc[i];
     const double* h = &hs[(size_t)i * kSumWords];
     if (h[0] != 0.0) {
-      // a queue overflowed: this scene again on its own, with tile halving
+      // a queue overflowed: this scene again on its own, with tile halving,
+      // and half the tile for later batches (same queue memory; tiles do
+      // not change results)
       mars_iter_stats S{};
       render_iteration(s, p, &S);
+      configure(s, 0, std::max(1, std::min(s->tile_roots, (int)std::min<size_t>(s->cap, 0x7FFFFFFF)) / 2));
       if (its) its[i] = S;
       if (with_update) {
         mars_update_stats U{};
@@ -1085,16 +1101,16 @@ size_t tuned_capacity(size_t tile, double e) {
   return std::min<size_t>(std::max<size_t>(cap, 4096), 0xFFFF0000ull);
 }
 
-size_t queue_bytes(const Scene* s, size_t cap) {
-  return cap * (size_t)(s->max_depth + 2) * (kQueueEntryBytes + (s->mlp_on ? 16 : 0));
+// smallest tile worth a launch sequence: about 2^18 queue entries at the
+// peak level (enough rays to fill the chip), at least 4096 camera samples
+constexpr double kTuneMinEntries = 262144.0;
+size_t min_tile(size_t roots, double e) {
+  const size_t t = (size_t)std::ceil(kTuneMinEntries / std::max(1.0, e));
+  return std::min(roots, (std::max<size_t>(t, 4096) + 63) / 64 * 64);
 }
 
-void configure(Scene* s, size_t cap, int tile) {
-  if (cap && cap != s->cap) alloc_queues(s, cap);
-  if (tile > 0 && tile != s->tile_roots) {
-    s->tile_roots = tile;
-    s->epoch++;
-  }
+size_t queue_bytes(const Scene* s, size_t cap) {
+  return cap * (size_t)(s->max_depth + 2) * (kQueueEntryBytes + (s->mlp_on ? 16 : 0));
 }
 
 std::string scene_class(const Scene* s, const mars_iter_params* p) {
@@ -1168,19 +1184,19 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
     int best = -1;
     size_t bytes = 0;
     for (int i : todo) {
-      const size_t floor_t = std::min<size_t>(roots_of(sc[i], p->spp), 65536);
+      const size_t floor_t = min_tile(roots_of(sc[i], p->spp), res[i].e);
       const size_t b = queue_bytes(sc[i], tuned_capacity(T[i], res[i].e));
       if (T[i] > floor_t && b > bytes) { best = i; bytes = b; }
     }
     if (best < 0) throw Status(MARS_E_OOM, "queue memory budget too small for the batch");
-    const size_t floor_t = std::min<size_t>(roots_of(sc[best], p->spp), 65536);
+    const size_t floor_t = min_tile(roots_of(sc[best], p->spp), res[best].e);
     T[best] = std::max(floor_t, (T[best] + 1) / 2);
     used += (double)queue_bytes(sc[best], tuned_capacity(T[best], res[best].e)) - (double)bytes;
   }
   // measure: the planned tile and two smaller ones, one timed iteration each
   for (int i : todo) {
     Scene* s = sc[i];
-    const size_t floor_t = std::min<size_t>(roots_of(s, p->spp), 65536);
+    const size_t floor_t = min_tile(roots_of(s, p->spp), res[i].e);
     std::vector<size_t> cand;
     for (size_t t = T[i]; cand.size() < 3; t /= 2) {
       const size_t tt = std::max(floor_t, t);
@@ -1303,6 +1319,11 @@ mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess &&
       cu > 0)
     c->cu = cu;
+  c->batch_streams = kBatchStreams;
+  if (const char* e = std::getenv("MARS_BATCH_STREAMS")) {
+    const int k = std::atoi(e);
+    if (k >= 1 && k <= 16) c->batch_streams = k;
+  }
   *out = c;
   return MARS_OK;
 }
@@ -1314,7 +1335,6 @@ mars_status mars_destroy(mars_ctx* ctx) {
   ctx->graphs.clear();
   for (auto s : ctx->pool) (void)hipStreamDestroy(s);
   for (auto e : ctx->pool_ev) (void)hipEventDestroy(e);
-  if (ctx->origin) (void)hipStreamDestroy(ctx->origin);
   for (auto& s : ctx->scenes) release_scene(s.get());
   if (ctx->tcount) ctx->dfree(ctx->tcount);
   delete ctx;
