@@ -82,6 +82,75 @@ def cpu_baseline(sc, n_pix=16384, seed=7):
                       f"(render+update) after one classic iteration, {dt:.1f} s"}
 
 
+def relmse(img, ref, eps=1e-2, drop=1e-4):
+    """relMSE: mean over pixels of the channel-mean (I - R)^2 / (R^2 + eps),
+    the largest fraction `drop` of the per-pixel terms discarded."""
+    import numpy as np
+    d = img.astype(np.float64) - ref
+    e = np.sort(np.mean(d * d / (ref * ref + eps), axis=-1).ravel())
+    keep = e.size - int(np.floor(drop * e.size))
+    return float(np.mean(e[:keep]))
+
+
+def reference_image(api, ctx, sc, spp=16, iters=128, seed_iter=100000):
+    """Classic-RR guided path tracing at spp x iters samples per pixel (the
+    same integrand; independent random streams via the iteration index)."""
+    import numpy as np
+    r = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+    acc = np.zeros((sc["height"], sc["width"], 3))
+    for i in range(iters):
+        r.render_iteration(api.iter_params(iteration=seed_iter + i, spp=spp))
+        acc += r.image(api.IMAGE_LAST)
+    r.release()
+    return acc / iters
+
+
+def efficiency_leg(api, ctx, sc, torch, n_iter=7):
+    """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
+    paper's guiding evaluation: iterations of 1, 2, 4, ... spp, the first
+    three with classic RR, then MARS (render + update each); the MARS image
+    is the inverse-variance weighted combination of all iterations; classic
+    RR renders the same sample counts (mean image).  relMSE against a
+    2048 spp classic reference, 0.01% brightest outliers discarded."""
+    import numpy as np
+    ref = reference_image(api, ctx, sc)
+
+    def run(alloc_after):
+        s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+        acc = np.zeros_like(ref)
+        spp_tot = rays = 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(n_iter):
+            alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
+            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=50.0)
+            rays += s.render_iteration(p).total_rays()
+            if alloc_after == api.ALLOC_MARS:
+                s.update(p)
+            else:
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                acc += s.image(api.IMAGE_LAST) * (1 << i)
+                t += time.perf_counter() - t_pause  # read-back excluded
+            spp_tot += 1 << i
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        img = s.image(api.IMAGE_IVW) if alloc_after == api.ALLOC_MARS else acc / spp_tot
+        s.release()
+        return relmse(img, ref), dt, spp_tot, rays
+
+    e_m, t_m, spp, r_m = run(api.ALLOC_MARS)
+    e_c, t_c, _, r_c = run(api.ALLOC_CLASSIC)
+    return {"definition": "1/(relMSE*s); relMSE = mean (I-R)^2/(R^2+0.01), 0.01% outliers "
+                          "discarded, vs a 2048 spp classic reference; iterations of 1,2,4.. spp",
+            "mars": 1.0 / (e_m * t_m), "classic": 1.0 / (e_c * t_c),
+            "gain_vs_classic": (e_c * t_c) / (e_m * t_m),
+            "relmse_mars": e_m, "relmse_classic": e_c, "seconds_mars": t_m,
+            "seconds_classic": t_c, "spp": spp, "iterations": n_iter, "reference_spp": 2048,
+            "rays_mars": r_m, "rays_classic": r_c,
+            "ray_efficiency_gain_vs_classic": (e_c * r_c) / (e_m * r_m)}
+
+
 def cells_budget(mbytes=72.0):
     # bytes per cell: factors 72, accumulators 192, visits/leaf data 12,
     # directional pmf+cdf 512, training sums 512, octree node words 32
@@ -240,8 +309,13 @@ def main():
         bcopy.copy_(a)
         torch.cuda.synchronize()
         del a, bcopy
+    t_warm = 0.0
     for i in range(args.warmup):
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
         step(i)
+        torch.cuda.synchronize()
+        t_warm += time.perf_counter() - tw
         print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.profile(True)
@@ -279,6 +353,8 @@ def main():
         "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
     }
     if args.profile_steps < 0:
+        print("[bench] efficiency", file=sys.stderr, flush=True)
+        out["efficiency"] = efficiency_leg(api, ctx, sc, torch)
         # algorithmic bytes of the dominant kernel from one instrumented iteration
         ctx.trace_counting(True)
         st, _ = step(args.warmup + args.steps)
