@@ -437,6 +437,8 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   }
   uint32_t dbg_total = 0;
   double peak = 0.0;
+  uint32_t ok_tile = 0;  // largest tile that fit after an overflow
+  bool overflowed = false;
   while (!work.empty()) {
     auto [r0, n] = work.back();
     work.pop_back();
@@ -448,12 +450,14 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     if (!ok) {
       if (n == 1) throw Status(MARS_E_OVERFLOW, "a single path tree exceeds the queue capacity");
       S.overflow_retries++;
+      overflowed = true;
       const uint32_t h = n / 2;
       work.emplace_back(r0 + h, n - h);
       work.emplace_back(r0, h);
       continue;
     }
     dbg_total = hc.n_debug;
+    ok_tile = std::max(ok_tile, n);
     S.rays_ext += hc.rays_ext;
     S.rays_shadow += hc.rays_shadow;
     S.vertices += hc.vertices;
@@ -469,6 +473,11 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
   s->dbg_last = dbg_total;
   s->peak_per_root = peak;
+  // later iterations start from a tile that fitted (tiles do not change results)
+  if (overflowed && ok_tile > 0 && (int)ok_tile < s->tile_roots) {
+    s->tile_roots = (int)ok_tile;
+    s->epoch++;
+  }
   S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = S;
 }

@@ -981,6 +981,32 @@ void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, C
   light_shade_kernel<<<grid, 256, 0, s>>>(sc, q, lt, cnt, it, bounce);
 }
 
+// shadow-entry requests written by the vertex kernel: kind in SH1.x, the
+// camera vertex in SH1.w; NEE: emitter point and triangle in SH0; light
+// path: subpath index and light vertex index in SH0.xy
+constexpr uint32_t kConnNee = 1u, kConnLight = 2u;
+
+// camera prefix z_0..z_d of the camera vertex j of depth d (hit point x on
+// primitive prim, reached along dir) from the parent chain
+__device__ __forceinline__ void camera_prefix(const SceneDev& sc, const QueuesDev& q, int d,
+                                              uint32_t j, f3 x, f3 ng, uint32_t prim, f3 dir,
+                                              PV* z) {
+  z[0].P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
+  z[0].ng = dir;
+  z[0].mat = 0;
+  z[0].lpdf = 0.0f;
+  z[d] = PV{x, ng, sc.tri_mat[prim], sc.tri_ng[prim].w};
+  uint32_t e = ubits(q.S0[(size_t)d * q.cap + j].w);
+  for (int l = d - 1; l >= 1; --l) {
+    const size_t ee = (size_t)l * q.cap + e;
+    const float4 a0 = q.R0[ee], a1 = q.R1[ee];
+    const uint2 ah = q.H[ee];
+    const float at = fbits(ah.x);
+    z[l] = prim_vertex(sc, mk3(a0.x + at * a1.x, a0.y + at * a1.y, a0.z + at * a1.z), ah.y);
+    e = ubits(q.S0[ee].w);
+  }
+}
+
 __device__ __forceinline__ uint32_t lp_index(uint32_t root, uint32_t j, int32_t stride,
                                              uint32_t npool) {
   return (uint32_t)(((unsigned long long)root + (unsigned long long)j * (uint32_t)stride) % npool);
@@ -995,7 +1021,7 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
   const int lane = threadIdx.x & 63;
   const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
-  uint32_t my_vert = 0, my_samp = 0, my_ext = 0, my_sh = 0, my_conn = 0;
+  uint32_t my_vert = 0, my_samp = 0, my_ext = 0;
   PV z[2 * kMaxDepth + 4];
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t j = base + threadIdx.x;
@@ -1028,24 +1054,13 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
         It[0] = img.itilde[3 * (size_t)pix];
         It[1] = img.itilde[3 * (size_t)pix + 1];
         It[2] = img.itilde[3 * (size_t)pix + 2];
-        // camera prefix z_1..z_d from the parent chain
-        z[0].P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
-        z[0].ng = dir;
-        z[0].mat = 0;
-        z[0].lpdf = 0.0f;
-        z[d] = PV{x, ng, sc.tri_mat[prim], ngl.w};
-        uint32_t e = ubits(q.S0[L + j].w);
-        for (int l = d - 1; l >= 1; --l) {
-          const size_t ee = (size_t)l * q.cap + e;
-          const float4 a0 = q.R0[ee], a1 = q.R1[ee];
-          const uint2 ah = q.H[ee];
-          const float at = fbits(ah.x);
-          z[l] = prim_vertex(sc, mk3(a0.x + at * a1.x, a0.y + at * a1.y, a0.z + at * a1.z), ah.y);
-          e = ubits(q.S0[ee].w);
-        }
         const float cosl = -dot3(dir, ng);
         if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
-          const float w = d == 1 ? 1.0f : bdpt_weight(sc, c, it, z, d, d + 1, It);
+          float w = 1.0f;
+          if (d > 1) {
+            camera_prefix(sc, q, d, j, x, ng, prim, dir, z);
+            w = bdpt_weight(sc, c, it, z, d, d + 1, It);
+          }
           Ew = mk3(w * m[5], w * m[6], w * m[7]);
         }
         if (d < sc.max_depth) {
@@ -1113,7 +1128,8 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
       }
     }
     const Mat mat = load_mat(sc.mats + 8 * (size_t)sc.tri_mat[prim]);
-    // NEE
+    // NEE: the emitter point is drawn here; weight and contribution follow in
+    // connect_bdpt_kernel, one thread per shadow entry
     for (uint32_t k = 0; k < gam[1]; ++k) {
       const uint2 ss = stream_child(key, strm, 1u, k, (uint32_t)d);
       const float4 u = draw4(key, ss, 1);
@@ -1129,29 +1145,9 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
       const float a = su * (1.0f - u.z), b = su * u.z;
       const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
                        (v0.z + a * e1.z) + b * e2.z);
-      const f3 dv = sub3(y, ov);
-      const float d2 = dot3(dv, dv);
-      const float dist = sqrtf(d2);
-      const f3 w = scl3(dv, 1.0f / dist);
-      const float4 lng = sc.tri_ng[li];
-      const float cl = -dot3(w, xyz(lng));
-      f3 fc;
-      float pB;
-      eval_bsdf(mat, n_s, wo, w, &fc, &pB);
-      float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
-        const float pN = (lng.w * d2) / cl;
-        z[d + 1] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
-        const float wN = bdpt_weight(sc, c, it, z, d + 1, d + 1, It);
-        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
-        sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
-                          (fc.z / pN) * (wN * Le[2]), 1.0f);
-        ++my_sh;
-      }
       const size_t e = L + sfirst + k;
-      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
-      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
-      q.SH2[e] = sh2;
+      q.SH0[e] = make_float4(y.x, y.y, y.z, fbits((uint32_t)li));
+      q.SH1[e] = make_float4(fbits(kConnNee), 0.0f, 0.0f, fbits(j));
     }
     // BSDF continuation (the only continuing technique: w_ind = 1)
     for (uint32_t k = 0; k < gam[0]; ++k) {
@@ -1183,69 +1179,143 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
       q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, beta[0]);
       q.S3[e] = make_uint4(ss.x, ss.y, k, root);
     }
-    // light-path connections
+    // light-path connections: one shadow entry per (sample, light vertex)
     uint32_t slot = sfirst + gam[1];
     const int imax0 = sc.max_depth - d - 1;
     for (uint32_t k = 0; k < gam[2]; ++k) {
       const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
       const int imax = max(0, min(imax0, (int)lt.len[lpi].x));
       for (int i = 1; i <= imax; ++i, ++slot) {
-        const size_t ye = (size_t)lpi * lt.lmax + (i - 1);
-        const float4 y0v = lt.V0[ye], y1v = lt.V1[ye], y2v = lt.V2[ye];
-        const f3 yP = xyz(y0v);
-        const uint32_t yprim = ubits(y0v.w);
-        const PV yv = prim_vertex(sc, yP, yprim);
-        float d2;
-        const f3 w = dir_between(x, yP, &d2);
-        f3 fcC, fcL;
-        float pc, pl;
-        eval_bsdf(mat, n_s, wo, w, &fcC, &pc);
-        const Mat ym = load_mat(sc.mats + 8 * (size_t)yv.mat);
-        const f3 ywo = xyz(y1v);
-        eval_facing(ym, yv.ng, ywo, mk3(-w.x, -w.y, -w.z), &fcL, &pl);
-        float4 sh0 = make_float4(ov.x, ov.y, ov.z, 0.0f), sh1 = make_float4(w.x, w.y, w.z, fbits(j));
-        float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
-            (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
-          for (int jj = 1; jj <= i; ++jj) {
-            const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
-            z[d + jj] = prim_vertex(sc, xyz(pv), ubits(pv.w));
-          }
-          const float4 y0r = lt.Y0[lpi];
-          z[d + i + 1] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
-          const float wc = bdpt_weight(sc, c, it, z, d + 1 + i, d + 1, It);
-          const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
-          const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
-          float sd2;
-          const f3 sw = dir_between(ov, yo, &sd2);
-          const f3 al = mk3(y1v.w, y2v.x, y2v.y);
-          sh0 = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
-          sh1 = make_float4(sw.x, sw.y, sw.z, fbits(j));
-          sh2 = make_float4(wc * (((al.x * fcL.x) * fcC.x) / d2), wc * (((al.y * fcL.y) * fcC.y) / d2),
-                            wc * (((al.z * fcL.z) * fcC.z) / d2), 1.0f);
-          ++my_conn;
-        }
         const size_t e = L + slot;
-        q.SH0[e] = sh0;
-        q.SH1[e] = sh1;
-        q.SH2[e] = sh2;
+        q.SH0[e] = make_float4(fbits(lpi), fbits((uint32_t)i), 0.0f, 0.0f);
+        q.SH1[e] = make_float4(fbits(kConnLight), 0.0f, 0.0f, fbits(j));
       }
     }
   }
-  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext),
-                 sh = wave_sum(my_sh), sn = wave_sum(my_conn);
+  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext);
   if (lane == 0) {
     if (sv) atomicAdd(&cnt->vertices, (unsigned long long)sv);
     if (ss) atomicAdd(&cnt->samples, (unsigned long long)ss);
     if (se) atomicAdd(&cnt->rays_ext, (unsigned long long)se);
+  }
+}
+
+// NEE samples and light-path connections of the camera vertices of depth d,
+// one thread per shadow entry: the full-path MIS weight and the weighted
+// contribution, then the shadow ray.  Splitting gives vertices very uneven
+// numbers of connections; this keeps the waves balanced.
+__global__ __launch_bounds__(256) void connect_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+                                                           LightDev lt, Counters* cnt, IterDev it,
+                                                           ImageDev img, int d) {
+  if (cnt->overflow) return;
+  const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
+  const size_t L = (size_t)d * q.cap;
+  uint32_t my_sh = 0, my_conn = 0;
+  PV z[2 * kMaxDepth + 4];
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    const size_t e = L + s;
+    const float4 s0 = q.SH0[e], s1 = q.SH1[e];
+    const uint32_t kind = ubits(s1.x), j = ubits(s1.w);
+    // the camera vertex
+    const uint2 h = q.H[L + j];
+    const uint32_t prim = h.y;
+    const float4 r0 = q.R0[L + j], r1 = q.R1[L + j];
+    const float t = fbits(h.x);
+    const f3 dir = xyz(r1);
+    const uint32_t pix = ubits(r1.w);
+    const float4 ngl = sc.tri_ng[prim];
+    const f3 ng = xyz(ngl);
+    const f3 x = mk3(r0.x + t * dir.x, r0.y + t * dir.y, r0.z + t * dir.z);
+    float It[3];
+    It[0] = img.itilde[3 * (size_t)pix];
+    It[1] = img.itilde[3 * (size_t)pix + 1];
+    It[2] = img.itilde[3 * (size_t)pix + 2];
+    const f3 n_s = dot3(ng, dir) < 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
+    const f3 wo = mk3(-dir.x, -dir.y, -dir.z);
+    const f3 ov = mk3(x.x + n_s.x * sc.eps, x.y + n_s.y * sc.eps, x.z + n_s.z * sc.eps);
+    const Mat mat = load_mat(sc.mats + 8 * (size_t)sc.tri_mat[prim]);
+    camera_prefix(sc, q, d, j, x, ng, prim, dir, z);
+    if (kind == kConnNee) {
+      const f3 y = xyz(s0);
+      const uint32_t li = ubits(s0.w);
+      const f3 dv = sub3(y, ov);
+      const float d2 = dot3(dv, dv);
+      const float dist = sqrtf(d2);
+      const f3 w = scl3(dv, 1.0f / dist);
+      const float4 lng = sc.tri_ng[li];
+      const float cl = -dot3(w, xyz(lng));
+      f3 fc;
+      float pB;
+      eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+      float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+        const float pN = (lng.w * d2) / cl;
+        z[d + 1] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
+        const float wN = bdpt_weight(sc, c, it, z, d + 1, d + 1, It);
+        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
+        sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
+                          (fc.z / pN) * (wN * Le[2]), 1.0f);
+        ++my_sh;
+      }
+      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
+      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      q.SH2[e] = sh2;
+    } else {
+      const uint32_t lpi = ubits(s0.x);
+      const int i = (int)ubits(s0.y);
+      const size_t ye = (size_t)lpi * lt.lmax + (i - 1);
+      const float4 y0v = lt.V0[ye], y1v = lt.V1[ye], y2v = lt.V2[ye];
+      const f3 yP = xyz(y0v);
+      const uint32_t yprim = ubits(y0v.w);
+      const PV yv = prim_vertex(sc, yP, yprim);
+      float d2;
+      const f3 w = dir_between(x, yP, &d2);
+      f3 fcC, fcL;
+      float pc, pl;
+      eval_bsdf(mat, n_s, wo, w, &fcC, &pc);
+      const Mat ym = load_mat(sc.mats + 8 * (size_t)yv.mat);
+      const f3 ywo = xyz(y1v);
+      eval_facing(ym, yv.ng, ywo, mk3(-w.x, -w.y, -w.z), &fcL, &pl);
+      float4 sh0 = make_float4(ov.x, ov.y, ov.z, 0.0f), sh1 = make_float4(w.x, w.y, w.z, fbits(j));
+      float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
+          (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
+        for (int jj = 1; jj <= i; ++jj) {
+          const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
+          z[d + jj] = prim_vertex(sc, xyz(pv), ubits(pv.w));
+        }
+        const float4 y0r = lt.Y0[lpi];
+        z[d + i + 1] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
+        const float wc = bdpt_weight(sc, c, it, z, d + 1 + i, d + 1, It);
+        const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
+        const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
+        float sd2;
+        const f3 sw = dir_between(ov, yo, &sd2);
+        const f3 al = mk3(y1v.w, y2v.x, y2v.y);
+        sh0 = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
+        sh1 = make_float4(sw.x, sw.y, sw.z, fbits(j));
+        sh2 = make_float4(wc * (((al.x * fcL.x) * fcC.x) / d2), wc * (((al.y * fcL.y) * fcC.y) / d2),
+                          wc * (((al.z * fcL.z) * fcC.z) / d2), 1.0f);
+        ++my_conn;
+      }
+      q.SH0[e] = sh0;
+      q.SH1[e] = sh1;
+      q.SH2[e] = sh2;
+    }
+  }
+  const uint32_t sh = wave_sum(my_sh), sn = wave_sum(my_conn);
+  if ((threadIdx.x & 63) == 0) {
     if (sh) atomicAdd(&cnt->rays_shadow, (unsigned long long)sh);
     if (sn) atomicAdd(&cnt->rays_conn, (unsigned long long)sn);
   }
 }
+
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s) {
   shade_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
+  if (d < sc.max_depth)
+    connect_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d);
 }
 
 // back-propagation for BDPT: NEE, BSDF and LP samples in that order

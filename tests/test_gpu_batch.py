@@ -163,12 +163,11 @@ def test_batch_overflow_reruns_scene(ctx):
             o.update(po)
             _cmp_twins(g, e)
             _cmp_oracle(g, o)
-            if k == 0:
+            if k == 0 and it == 0:
                 assert se.overflow_retries > 0, "the small queue never overflowed"
-                if it == 0:
-                    assert its[0].overflow_retries > 0
-    # each re-run halved the scene's tile for later batches
-    assert G[0].query()[1] < 1024 and E[0].query()[1] == 1024
+                assert its[0].overflow_retries > 0
+    # both paths start later iterations from a smaller tile
+    assert G[0].query()[1] < 1024 and E[0].query()[1] < 1024
 
 
 def _cap(tile, e):
