@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "guided_pt_512x512_heightfield132k_d10"
 BYTES_RAY_IO = 48.0      # ray 32 B in (origin, direction) + hit 16 B out
 BYTES_SHADOW_IO = 36.0   # shadow ray 32 B in (origin + tmax, direction) + 4 B visibility out
-BYTES_NODE = 64.0        # one BVH node (two child boxes + references)
+BYTES_NODE = 128.0       # one 4-wide BVH node (four child boxes + references)
 BYTES_TRI = 48.0         # one triangle record (v0, e1, e2)
 
 

@@ -1,15 +1,23 @@
-// Host BVH builder: binned SAH (16 bins per axis), at most 4 triangles per
-// leaf unless a split cannot separate them (then up to 15), depth bounded so
-// that the traversal's 32-entry stack always suffices (median splits take
-// over when the remaining triangles could otherwise exceed the bound).
-// Output layout (64 B per inner node, depth-first order):
-//   float4 (c0.lo.xyz, c0.hi.x), (c0.hi.yz, c1.lo.xy), (c1.lo.z, c1.hi.xyz),
-//   (child0, child1, 0, 0) as int bits; child >= 0: inner node index,
-//   child < 0: leaf = -1 - (first << 4 | count).
+// Host BVH builder: binned SAH (16 bins per axis) binary tree, at most 4
+// triangles per leaf unless a split cannot separate them (then up to 15),
+// depth bounded by 30 (median splits take over when the remaining triangles
+// could otherwise exceed the bound), then collapsed to a 4-wide tree: each
+// node takes up to four descendants, expanding the inner child of largest
+// surface area first.
+// Output layout (128 B = one cache line per node, depth-first order):
+//   float4 lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4] of the four
+//   child boxes, int4 child references, float4 unused;
+//   reference >= 0: node index; < 0: leaf = -1 - (first << 4 | count);
+//   kBvhEmpty: no child.
+// Traversal pushes at most 3 children per visited node and the 4-wide depth
+// is at most the binary depth, so the stack never exceeds 3 x 30 entries;
+// max_stack reports the exact bound of the built tree.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
+#include <utility>
 #include <vector>
 
 #include "bvh_build.h"
@@ -170,58 +178,63 @@ BvhResult build_bvh(const float* V, int n_tris, float pad) {
   BvhResult out;
   out.max_depth = B.max_depth_seen;
   out.prim_order = B.idx;
-  // depth-first numbering of inner nodes
-  std::vector<int> gpu_id(B.nodes.size(), -1);
-  std::vector<int> order;
-  std::vector<int> st{0};
-  const bool root_leaf = B.nodes[0].left < 0;
-  if (!root_leaf) {
-    while (!st.empty()) {
-      const int n = st.back();
-      st.pop_back();
-      gpu_id[n] = (int)order.size();
-      order.push_back(n);
-      const Node& nd = B.nodes[n];
-      if (B.nodes[nd.right].left >= 0) st.push_back(nd.right);
-      if (B.nodes[nd.left].left >= 0) st.push_back(nd.left);
-    }
-  }
-  auto child_ref = [&](int n) -> int32_t {
+  auto area = [&](int n) { return B.nodes[n].box.area(); };
+  auto is_leaf = [&](int n) { return B.nodes[n].left < 0; };
+  auto leaf_ref = [&](int n) -> int32_t {
     const Node& c = B.nodes[n];
-    if (c.left >= 0) return gpu_id[n];
     return -1 - (int32_t)(((uint32_t)c.first << 4) | (uint32_t)c.count);
   };
-  auto put_box = [&](const Box& b, float* lo, float* hi) {
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = b.lo[a] - pad;
-      hi[a] = b.hi[a] + pad;
-    }
-  };
-  const size_t nn = root_leaf ? 1 : order.size();
-  out.nodes.assign(nn * 16, 0.0f);
-  for (size_t g = 0; g < nn; ++g) {
-    float lo0[3], hi0[3], lo1[3], hi1[3];
-    int32_t r0, r1;
-    if (root_leaf) {
-      put_box(B.nodes[0].box, lo0, hi0);
-      r0 = -1 - (int32_t)(((uint32_t)0 << 4) | (uint32_t)B.nodes[0].count);
-      for (int a = 0; a < 3; ++a) { lo1[a] = INFINITY; hi1[a] = -INFINITY; }
-      r1 = -1;  // empty leaf
+  // returns (node index, stack bound of its subtree)
+  std::function<std::pair<int, int>(int)> emit = [&](int n) -> std::pair<int, int> {
+    const int id = (int)(out.nodes.size() / 32);
+    out.nodes.resize(out.nodes.size() + 32, 0.0f);
+    std::vector<int> ch;
+    if (is_leaf(n)) {
+      ch.push_back(n);  // a root that is a leaf
     } else {
-      const Node& nd = B.nodes[order[g]];
-      put_box(B.nodes[nd.left].box, lo0, hi0);
-      put_box(B.nodes[nd.right].box, lo1, hi1);
-      r0 = child_ref(nd.left);
-      r1 = child_ref(nd.right);
+      ch = {B.nodes[n].left, B.nodes[n].right};
+      while (ch.size() < 4) {
+        int best = -1;
+        float ba = -1.0f;
+        for (size_t i = 0; i < ch.size(); ++i)
+          if (!is_leaf(ch[i]) && area(ch[i]) > ba) { ba = area(ch[i]); best = (int)i; }
+        if (best < 0) break;
+        const int x = ch[best];
+        ch[best] = B.nodes[x].left;
+        ch.insert(ch.begin() + best + 1, B.nodes[x].right);
+      }
     }
-    float* f = &out.nodes[g * 16];
-    f[0] = lo0[0]; f[1] = lo0[1]; f[2] = lo0[2]; f[3] = hi0[0];
-    f[4] = hi0[1]; f[5] = hi0[2]; f[6] = lo1[0]; f[7] = lo1[1];
-    f[8] = lo1[2]; f[9] = hi1[0]; f[10] = hi1[1]; f[11] = hi1[2];
-    uint32_t u0 = (uint32_t)r0, u1 = (uint32_t)r1;
-    std::memcpy(&f[12], &u0, 4);
-    std::memcpy(&f[13], &u1, 4);
-  }
+    int32_t ref[4] = {kBvhEmpty, kBvhEmpty, kBvhEmpty, kBvhEmpty};
+    float lo[3][4], hi[3][4];
+    int inner = 0, sub = 0;
+    for (int k = 0; k < 4; ++k)
+      for (int a = 0; a < 3; ++a) { lo[a][k] = INFINITY; hi[a][k] = -INFINITY; }
+    for (size_t k = 0; k < ch.size(); ++k) {
+      const Box& b = B.nodes[ch[k]].box;
+      for (int a = 0; a < 3; ++a) { lo[a][k] = b.lo[a] - pad; hi[a][k] = b.hi[a] + pad; }
+      if (is_leaf(ch[k])) {
+        ref[k] = leaf_ref(ch[k]);
+      } else {
+        const auto r = emit(ch[k]);
+        ref[k] = r.first;
+        sub = std::max(sub, r.second);
+        ++inner;
+      }
+    }
+    float* f = &out.nodes[(size_t)id * 32];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 4; ++k) {
+        f[4 * a + k] = lo[a][k];
+        f[12 + 4 * a + k] = hi[a][k];
+      }
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t u = (uint32_t)ref[k];
+      std::memcpy(&f[24 + k], &u, 4);
+    }
+    return {id, std::max(0, inner - 1) + sub};
+  };
+  out.nodes.reserve((size_t)n_tris * 16);
+  out.max_stack = emit(0).second;
   // triangles in leaf order: (v0, prim), (e1, 0), (e2, 0)
   out.tris.assign((size_t)n_tris * 12, 0.0f);
   for (int k = 0; k < n_tris; ++k) {

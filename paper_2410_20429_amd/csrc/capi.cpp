@@ -650,9 +650,16 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     // BVH
     BvhResult bvh = build_bvh(d->V, nt, (float)(1e-5 * ext) + 1e-7f);
     s->bvh_depth = bvh.max_depth;
-    s->n_bvh_nodes = (int)(bvh.nodes.size() / 16);
-    if (bvh.max_depth >= kStackDepth) throw Status(MARS_E_STATE, "BVH deeper than the traversal stack");
+    s->n_bvh_nodes = (int)(bvh.nodes.size() / 32);
+    static_assert(kBvhEmpty == kBvhNoChild, "empty child reference");
     float4* dbvh = salloc<float4>(s, bvh.nodes.size() / 4);
+    sd.stack_spill = nullptr;
+    sd.spill_threads = 0;
+    if (bvh.max_stack > kStackDepth) {
+      // the rest of the stack bound in device memory, one column per thread
+      sd.spill_threads = (uint32_t)c->cu * 10u * (uint32_t)kTraceBlock;
+      sd.stack_spill = salloc<int32_t>(s, (size_t)(bvh.max_stack - kStackDepth) * sd.spill_threads);
+    }
     float4* dtri = salloc<float4>(s, bvh.tris.size() / 4);
     float4* dgeo = salloc<float4>(s, geo.size() / 4);
     float4* dng = salloc<float4>(s, ng.size() / 4);

@@ -163,6 +163,20 @@ __device__ __forceinline__ bool tri_hit(f3 o, f3 d, float4 A, float4 B, float4 C
   return true;
 }
 
+// ordered swap of two (distance, reference) pairs
+__device__ __forceinline__ void cswap(float& ta, int& ra, float& tb, int& rb) {
+  if (tb < ta) {
+    const float t = ta; ta = tb; tb = t;
+    const int r = ra; ra = rb; rb = r;
+  }
+}
+
+// 4-wide BVH traversal.  Leaf children are intersected when their box is
+// hit; the hit inner children are sorted by entry distance, the nearest
+// visited next and the others pushed (far first).  The stack's first
+// kStackDepth entries per lane live in LDS, deeper ones (rare; bounded by
+// the builder) in the scene's spill area.  Closest hit: smallest t, ties by
+// smaller primitive index (independent of the traversal order).
 template <bool kAny, bool kCount>
 __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
                                          float* bt_out, uint32_t* bp_out, uint32_t* n_nodes,
@@ -173,18 +187,26 @@ __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float t
   int sp = 0;
   int node = 0;
   const int lane = threadIdx.x;
+  const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto push = [&](int v) {
+    if (sp < kStackDepth) stk[sp * kTraceBlock + lane] = v;
+    else sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid] = v;
+    ++sp;
+  };
   while (true) {
-    const float4* N = sc.bvh + (size_t)node * 4;
+    const float4* N = sc.bvh + (size_t)node * 8;
     if (kCount) ++*n_nodes;
-    const float4 a = N[0], b = N[1], c = N[2];
-    const float4 rr = N[3];
-    const int c0 = (int)ubits(rr.x), c1 = (int)ubits(rr.y);
-    float t0 = box_near(ri, a.x, a.y, a.z, a.w, b.x, b.y, bt);
-    float t1 = box_near(ri, b.z, b.w, c.x, c.y, c.z, c.w, bt);
+    const float4 lx = N[0], ly = N[1], lz = N[2], hx = N[3], hy = N[4], hz = N[5];
+    const float4 rf = N[6];
+    int r0 = (int)ubits(rf.x), r1 = (int)ubits(rf.y), r2 = (int)ubits(rf.z), r3 = (int)ubits(rf.w);
+    float t0 = r0 == kBvhNoChild ? INFINITY : box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
+    float t1 = r1 == kBvhNoChild ? INFINITY : box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
+    float t2 = r2 == kBvhNoChild ? INFINITY : box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
+    float t3 = r3 == kBvhNoChild ? INFINITY : box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int ch = side ? c1 : c0;
-      const float tn = side ? t1 : t0;
+    for (int side = 0; side < 4; ++side) {
+      const int ch = side == 0 ? r0 : side == 1 ? r1 : side == 2 ? r2 : r3;
+      const float tn = side == 0 ? t0 : side == 1 ? t1 : side == 2 ? t2 : t3;
       if (ch < 0 && tn != INFINITY) {
         const uint32_t code = (uint32_t)(-1 - ch);
         const uint32_t first = code >> 4, count = code & 15u;
@@ -206,24 +228,29 @@ __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float t
             bp = prim;
           }
         }
-        if (side) t1 = INFINITY; else t0 = INFINITY;
       }
     }
-    const bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
-    if (h0 && h1) {
-      int nearc = c0, farc = c1;
-      if (t1 < t0) { nearc = c1; farc = c0; }
-      stk[sp * kTraceBlock + lane] = farc;
-      ++sp;
-      node = nearc;
-    } else if (h0) {
-      node = c0;
-    } else if (h1) {
-      node = c1;
+    // inner children still in front of the closest hit (a box entered at
+    // exactly bt may hold an equal-t hit of smaller index)
+    if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
+    if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
+    if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
+    if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
+    cswap(t0, r0, t1, r1);
+    cswap(t2, r2, t3, r3);
+    cswap(t0, r0, t2, r2);
+    cswap(t1, r1, t3, r3);
+    cswap(t1, r1, t2, r2);
+    if (t0 != INFINITY) {
+      if (t3 != INFINITY) push(r3);
+      if (t2 != INFINITY) push(r2);
+      if (t1 != INFINITY) push(r1);
+      node = r0;
     } else {
       if (sp == 0) break;
       --sp;
-      node = stk[sp * kTraceBlock + lane];
+      node = sp < kStackDepth ? stk[sp * kTraceBlock + lane]
+                              : sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid];
     }
   }
   *bt_out = bt;
@@ -285,6 +312,8 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
 }
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
                   int grid, hipStream_t s, unsigned long long* tc) {
+  // the spill area has one column per thread of the launch
+  if (sc.stack_spill) grid = std::min(grid, (int)(sc.spill_threads / kTraceBlock));
   if (tc) trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
   else trace_pair_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, nullptr);
 }
@@ -1768,11 +1797,15 @@ __global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
     c.leaf_node[id] = base + ch;
     c.leaf_depth[id] = dep;
     if (ch) {
+      // new cells: the parent's factors and distribution, no statistics yet
       for (int k = 0; k < 18; ++k) c.fac[(size_t)id * 18 + k] = c.fac[(size_t)l * 18 + k];
       for (int k = 0; k < 64; ++k) {
         c.pm[(size_t)id * 64 + k] = c.pm[(size_t)l * 64 + k];
         c.cdf[(size_t)id * 64 + k] = c.cdf[(size_t)l * 64 + k];
+        c.hacc[(size_t)id * 64 + k] = 0.0;
       }
+      for (int k = 0; k < 24; ++k) c.acc[(size_t)id * 24 + k] = 0.0;
+      c.visits[id] = 0u;
     }
   }
 }

@@ -9,11 +9,12 @@ namespace mars {
 constexpr uint32_t kLeafBit = 0x80000000u;  // octree node word: leaf flag | leaf id
 constexpr int kMaxDepth = 16;       // maximum path segments supported
 constexpr int kTraceBlock = 128;    // threads per traversal workgroup
-constexpr int kStackDepth = 32;     // per-lane LDS traversal stack (BVH depth <= 31)
+constexpr int kStackDepth = 32;     // per-lane LDS part of the traversal stack
+constexpr int32_t kBvhNoChild = 0x7FFFFFFF;  // unused slot of a 4-wide node
 
 // scene on the device (read-only during an iteration)
 struct SceneDev {
-  const float4* bvh;       // [n_nodes][4]: two child boxes + child references
+  const float4* bvh;       // [n_nodes][8]: four child boxes (SoA) + child references
   const float4* tri_bvh;   // [n_tris][3] leaf order: (v0, prim bits), (e1, 0), (e2, 0)
   const float4* tri_geo;   // [n_tris][3] primitive order: v0, e1, e2
   const float4* tri_ng;    // [n_tris] primitive order: (geometric normal, p_select / area)
@@ -29,6 +30,10 @@ struct SceneDev {
   float oct_inv;
   int32_t mode, max_depth, nee;
   uint32_t key0, key1;
+  // traversal stack entries beyond the LDS part, [depth][spill_threads]
+  // (null when the tree's stack bound fits in LDS)
+  int32_t* stack_spill;
+  uint32_t spill_threads;
 };
 
 // spatial cache (octree leaves = cells)
