@@ -333,7 +333,7 @@ constexpr size_t kQueueEntryBytes = 13 * 16 + 8;
 uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
   hipStream_t st = s->ctx->stream;
   Ctx* c = s->ctx;
-  const int grid_trace = c->cu * 10, grid = c->cu * 8;
+  const int grid_trace = c->cu * kTraceBlocksPerCU, grid = c->cu * 8;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   for (size_t r0 = 0; r0 < roots; r0 += s->cap) {
@@ -355,8 +355,8 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
               uint32_t npool, Counters* hc) {
   const bool bdpt = s->mode == MARS_MODE_BDPT;
   hipStream_t st = s->ctx->stream;
-  // traversal: 128-thread groups, LDS-limited to 10 per CU; others 256-thread groups
-  const int grid_trace = s->ctx->cu * 10, grid = s->ctx->cu * 8;
+  // traversal: 128-thread groups, kTraceBlocksPerCU resident per CU; others 256-thread groups
+  const int grid_trace = s->ctx->cu * kTraceBlocksPerCU, grid = s->ctx->cu * 8;
   Ctx* c = s->ctx;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
@@ -657,7 +657,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     sd.spill_threads = 0;
     if (bvh.max_stack > kStackDepth) {
       // the rest of the stack bound in device memory, one column per thread
-      sd.spill_threads = (uint32_t)c->cu * 10u * (uint32_t)kTraceBlock;
+      sd.spill_threads = (uint32_t)c->cu * (uint32_t)kTraceBlocksPerCU * (uint32_t)kTraceBlock;
       sd.stack_spill = salloc<int32_t>(s, (size_t)(bvh.max_stack - kStackDepth) * sd.spill_threads);
     }
     float4* dtri = salloc<float4>(s, bvh.tris.size() / 4);
@@ -859,7 +859,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
   Ctx* c = s->ctx;
   const bool bdpt = s->mode == MARS_MODE_BDPT;
   const size_t roots = roots_of(s, spp), mc = (size_t)s->max_cells;
-  const int grid_trace = c->cu * 10, grid = c->cu * 8;
+  const int grid_trace = c->cu * kTraceBlocksPerCU, grid = c->cu * 8;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   k_fill_f64_dev(s->cd.acc, 0.0, s->n_cells_dev, 24, mc * 24, st);

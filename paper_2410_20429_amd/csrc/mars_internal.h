@@ -9,7 +9,10 @@ namespace mars {
 constexpr uint32_t kLeafBit = 0x80000000u;  // octree node word: leaf flag | leaf id
 constexpr int kMaxDepth = 16;       // maximum path segments supported
 constexpr int kTraceBlock = 128;    // threads per traversal workgroup
-constexpr int kStackDepth = 32;     // per-lane LDS part of the traversal stack
+constexpr int kStackDepth = 16;     // per-lane LDS part of the traversal stack
+// traversal launch: 128-thread groups with 8 KB of LDS stack each; at <= 64
+// VGPRs 16 groups (32 waves) fit a CU
+constexpr int kTraceBlocksPerCU = 16;
 constexpr int32_t kBvhNoChild = 0x7FFFFFFF;  // unused slot of a 4-wide node
 
 // scene on the device (read-only during an iteration)
