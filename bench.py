@@ -92,38 +92,43 @@ def relmse(img, ref, eps=1e-2, drop=1e-4):
     return float(np.mean(e[:keep]))
 
 
-def reference_image(api, ctx, sc, spp=16, iters=128, seed_iter=100000):
-    """Classic-RR guided path tracing at spp x iters samples per pixel (the
-    same integrand; independent random streams via the iteration index)."""
+def reference_image(api, ctx, sc, spp=16, iters=256, seed_iter=100000, mode=None, depth=10):
+    """Classic-RR rendering at spp x iters samples per pixel (the same
+    integrand; independent random streams via the iteration index)."""
     import numpy as np
-    r = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+    mode = api.MODE_PT_GUIDED if mode is None else mode
+    r = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget())
     acc = np.zeros((sc["height"], sc["width"], 3))
     for i in range(iters):
-        r.render_iteration(api.iter_params(iteration=seed_iter + i, spp=spp))
+        r.render_iteration(api.iter_params(iteration=seed_iter + i, spp=spp,
+                                           stat_clamp=0.0 if mode == api.MODE_BDPT else 50.0))
         acc += r.image(api.IMAGE_LAST)
     r.release()
     return acc / iters
 
 
-def efficiency_leg(api, ctx, sc, torch, n_iter=7):
+def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256)):
     """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
-    paper's guiding evaluation: iterations of 1, 2, 4, ... spp, the first
+    paper's evaluation: n_iter iterations of 1, 2, 4, ... spp, the first
     three with classic RR, then MARS (render + update each); the MARS image
     is the inverse-variance weighted combination of all iterations; classic
     RR renders the same sample counts (mean image).  relMSE against a
-    2048 spp classic reference, 0.01% brightest outliers discarded."""
+    classic reference of ref_spp[0] x ref_spp[1] spp, 0.01% brightest
+    outliers discarded."""
     import numpy as np
-    ref = reference_image(api, ctx, sc)
+    mode = api.MODE_PT_GUIDED if mode is None else mode
+    kc = 0.0 if mode == api.MODE_BDPT else 50.0
+    ref = reference_image(api, ctx, sc, spp=ref_spp[0], iters=ref_spp[1], mode=mode, depth=depth)
 
     def run(alloc_after):
-        s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+        s = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget())
         acc = np.zeros_like(ref)
         spp_tot = rays = 0
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(n_iter):
             alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
-            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=50.0)
+            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=kc)
             rays += s.render_iteration(p).total_rays()
             if alloc_after == api.ALLOC_MARS:
                 s.update(p)
@@ -141,14 +146,122 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=7):
 
     e_m, t_m, spp, r_m = run(api.ALLOC_MARS)
     e_c, t_c, _, r_c = run(api.ALLOC_CLASSIC)
+    rs = ref_spp[0] * ref_spp[1]
     return {"definition": "1/(relMSE*s); relMSE = mean (I-R)^2/(R^2+0.01), 0.01% outliers "
-                          "discarded, vs a 2048 spp classic reference; iterations of 1,2,4.. spp",
+                          f"discarded, vs a {rs} spp classic reference; iterations of 1,2,4.. spp",
             "mars": 1.0 / (e_m * t_m), "classic": 1.0 / (e_c * t_c),
             "gain_vs_classic": (e_c * t_c) / (e_m * t_m),
             "relmse_mars": e_m, "relmse_classic": e_c, "seconds_mars": t_m,
-            "seconds_classic": t_c, "spp": spp, "iterations": n_iter, "reference_spp": 2048,
+            "seconds_classic": t_c, "spp": spp, "iterations": n_iter, "reference_spp": rs,
             "rays_mars": r_m, "rays_classic": r_c,
             "ray_efficiency_gain_vs_classic": (e_c * r_c) / (e_m * r_m)}
+
+
+def run_bdpt(args, api, torch):
+    """Bidirectional workload: 1280x720 interior, 1,040,714 triangles, max
+    path length 12.  One step = one MARS iteration at 1 spp (render + update)
+    after classic warm-up iterations; efficiency of MARS vs classic-RR BDPT
+    with the doubling schedule (1..64 spp) against a 1024 spp reference."""
+    import scenegen
+    sc = scenegen.make_interior(seed=1)
+    ctx = api.Context(0)
+    s = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget())
+    warm = max(4, args.warmup)
+
+    def step(i):
+        alloc = api.ALLOC_CLASSIC if i < 3 else api.ALLOC_MARS
+        p = api.iter_params(iteration=i, spp=1, alloc=alloc, stat_clamp=0.0)
+        st = s.render_iteration(p)
+        s.update(p)
+        return st
+    for i in range(warm):
+        step(i)
+    print("[bench] bdpt: warm", file=sys.stderr, flush=True)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rays = 0
+    for k in range(args.steps):
+        rays += step(warm + k).total_rays()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    s.release()
+    px = sc["width"] * sc["height"]
+    out = {"metric": "Mpaths/s (bidirectional MARS iterations)", "value": px * args.steps / dt / 1e6,
+           "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps, "warmup": warm,
+           "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "bdpt_1280x720_interior1m_d12", "width": sc["width"],
+                      "height": sc["height"], "triangles": int(sc["V"].shape[0]), "max_depth": 12,
+                      "spp_per_step": 1, "techniques": ["bsdf", "nee", "light_path"]},
+           "mrays_per_s": rays / dt / 1e6,
+           "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
+    if not args.no_efficiency:
+        print("[bench] bdpt: efficiency", file=sys.stderr, flush=True)
+        out["efficiency"] = efficiency_leg(api, ctx, sc, torch, n_iter=7, mode=api.MODE_BDPT,
+                                           depth=12, ref_spp=(16, 64))
+    return out
+
+
+def run_mlp(args, api, torch, n_iter=14):
+    """Learned-cache workload: 1920x1080 BDPT interior of 2.08M triangles,
+    max path length 12.  Octree MARS and learned-cache MARS run the same
+    schedule (3 classic iterations, MARS from the 4th, the network's counts
+    from the 6th; iterations of 2 spp; the network trained 16 Adam steps of
+    8192 samples after every update).  Efficiency 1/(relMSE * s) of the IVW
+    image of each against a 256 spp classic reference, and the mean
+    1/(V_I C_I) of the last 6 iterations."""
+    import numpy as np
+    import scenegen
+    sc = scenegen.make_interior(seed=3, width=1920, height=1080, n_pieces=4500)
+    ctx = api.Context(0)
+    ref = reference_image(api, ctx, sc, spp=16, iters=16, mode=api.MODE_BDPT, depth=12)
+    print("[bench] mlp: reference done", file=sys.stderr, flush=True)
+    res = {}
+    for kind in ("octree", "mlp"):
+        s = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget(),
+                      mlp=(kind == "mlp"))
+        vc = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_train = 0.0
+        for i in range(n_iter):
+            alloc = api.ALLOC_CLASSIC if i < 3 else api.ALLOC_MARS
+            if kind == "mlp" and i >= 5:
+                alloc = api.ALLOC_MLP
+            p = api.iter_params(iteration=i, spp=2, alloc=alloc, stat_clamp=0.0)
+            s.render_iteration(p)
+            us = s.update(p)
+            if kind == "mlp" and i >= 3:
+                torch.cuda.synchronize()
+                tt = time.perf_counter()
+                s.mlp_train(steps=16, batch=8192, lr=2e-3)
+                torch.cuda.synchronize()
+                t_train += time.perf_counter() - tt
+            if i >= n_iter - 6:
+                vc.append(1.0 / (us.V_I * us.C_I))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e = relmse(s.image(api.IMAGE_IVW), ref)
+        res[kind] = {"relmse": e, "seconds": dt, "efficiency": 1.0 / (e * dt),
+                     "inv_vi_ci_last6": float(np.mean(vc)), "train_seconds": t_train}
+        s.release()
+        print(f"[bench] mlp: {kind} done", file=sys.stderr, flush=True)
+    px = sc["width"] * sc["height"]
+    return {"metric": "efficiency 1/(relMSE*s): learned cache vs octree MARS",
+            "value": res["mlp"]["efficiency"] / res["octree"]["efficiency"],
+            "unit": "ratio", "n_gpus": 1, "steps": n_iter, "warmup": 3,
+            "ms_per_step": res["mlp"]["seconds"] * 1e3 / n_iter, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network, f32 radiance",
+            "data": "synthetic",
+            "config": {"workload": "mlp_bdpt_1920x1080_interior2m_d12", "width": sc["width"],
+                       "height": sc["height"], "triangles": int(sc["V"].shape[0]),
+                       "max_depth": 12, "spp_per_iteration": 2, "reference_spp": 256},
+            "octree": res["octree"], "mlp": res["mlp"],
+            "paths_per_s_mlp": px * 2 * n_iter / res["mlp"]["seconds"] / 1e6,
+            "inv_vi_ci_ratio": res["mlp"]["inv_vi_ci_last6"] / res["octree"]["inv_vi_ci_last6"]}
 
 
 def cells_budget(mbytes=72.0):
@@ -273,8 +386,10 @@ def main():
                     help="(profiling runs) skip the instrumented iteration and the CPU leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="guided", choices=["guided", "batch"],
-                    help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes")
+    ap.add_argument("--workload", default="guided", choices=["guided", "batch", "bdpt", "mlp"],
+                    help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes; "
+                         "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree")
+    ap.add_argument("--no-efficiency", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
@@ -286,8 +401,9 @@ def main():
     import scenegen
     from paper_2410_20429_amd import api
 
-    if args.workload == "batch":
-        print(json.dumps(run_batch(args, api, torch)), flush=True)
+    if args.workload != "guided":
+        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp}[args.workload]
+        print(json.dumps(run(args, api, torch)), flush=True)
         return
     sc = scenegen.make_heightfield_scene(seed=1)
     ctx = api.Context(0)
@@ -353,8 +469,9 @@ def main():
         "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
     }
     if args.profile_steps < 0:
-        print("[bench] efficiency", file=sys.stderr, flush=True)
-        out["efficiency"] = efficiency_leg(api, ctx, sc, torch)
+        if not args.no_efficiency:
+            print("[bench] efficiency", file=sys.stderr, flush=True)
+            out["efficiency"] = efficiency_leg(api, ctx, sc, torch)
         # algorithmic bytes of the dominant kernel from one instrumented iteration
         ctx.trace_counting(True)
         st, _ = step(args.warmup + args.steps)

@@ -1720,7 +1720,9 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
     uint32_t lpi = (uint32_t)(((uint64_t)c->root + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
     const lightpath* lp = &o->lpaths[lpi];
     v3 v = mk(0, 0, 0);
-    uint32_t scost = (uint32_t)lp->rays;
+    /* cost of an LP sample: its connection rays (at least 1); the light
+     * subpath is traced once per camera sample whatever the counts */
+    uint32_t scost = 0;
     int imax = o->cfg.max_depth - depth - 1;
     if (imax > lp->len) imax = lp->len;
     for (int i = 1; i <= imax; ++i) {
@@ -1749,6 +1751,7 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
                v.z + wc * (((a.z * fcL.z) * fcC.z) / d2));
       }
     }
+    if (scost == 0) scost = 1;
     R = mk(R.x + v.x / beta[2], R.y + v.y / beta[2], R.z + v.z / beta[2]);
     cost += scost;
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_G, 0, {v.x, v.y, v.z}, scost, 0};

@@ -1412,7 +1412,9 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         const uint2 ll = lt.len[lpi];
         const int imax = max(0, min(imax0, (int)ll.x));
         f3 v = mk3(0.0f, 0.0f, 0.0f);
-        uint32_t sc_ = ll.y;
+        // an LP sample costs its connection rays (at least 1): the light
+        // subpath is traced once per camera sample whatever the counts
+        uint32_t sc_ = 0;
         for (int i = 1; i <= imax; ++i, ++slot) {
           const float4 r = q.SH2[L + slot];
           if (r.w != 0.0f) {
@@ -1420,6 +1422,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
             v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
           }
         }
+        sc_ = max(sc_, 1u);
         R = mk3(R.x + v.x / b.z, R.y + v.y / b.z, R.z + v.z / b.z);
         cost += sc_;
         record(2, v, sc_);
