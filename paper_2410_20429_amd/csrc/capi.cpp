@@ -750,6 +750,9 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     im.ivw_acc = salloc<double>(s, px * 3);
     im.count_map = salloc<float>(s, px * 3);
     im.red = salloc<double>(s, 8);
+    const size_t nbright = (px + kBrightChunk - 1) / kBrightChunk * kBright;
+    im.bright_l = salloc<float>(s, nbright);
+    im.bright_i = salloc<int32_t>(s, nbright);
     k_fill_f32(im.iter_sum, 0.0f, px * 3, st);
     k_fill_f32(im.accum, 0.0f, px * 3, st);
     k_fill_f32(im.itilde, INFINITY, px * 3, st);

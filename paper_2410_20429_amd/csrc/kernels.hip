@@ -1608,36 +1608,88 @@ __global__ void itilde_kernel(ImageDev img, int W, int H, const uint32_t* skip) 
 
 // BDPT: the 10 pixels with the largest iteration luminance leave V_I
 // (Sec. 5.1); ties go to the lower index.  One workgroup, ten passes.
-__global__ void brightest_kernel(ImageDev img, int npx, const uint32_t* skip) {
+// the kBright brightest pixels of the iteration (luminance of the pixel sum,
+// ties to the lower index): each chunk's top kBright, then the top kBright
+// of the candidates.  Round r takes the best key strictly below round r-1's.
+__device__ __forceinline__ bool ranks_above(float a, int ai, float b, int bi) {
+  return a > b || (a == b && ai < bi);
+}
+template <int kThreads>
+__device__ __forceinline__ void block_best(float* bl, int* bi, float& best, int& idx) {
+  bl[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const float o = bl[threadIdx.x + s];
+      const int oi = bi[threadIdx.x + s];
+      if (o > bl[threadIdx.x] || (o == bl[threadIdx.x] && oi >= 0 &&
+                                  (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
+        bl[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  best = bl[0];
+  idx = bi[0];
+  __syncthreads();
+}
+__global__ __launch_bounds__(256) void brightest_part_kernel(ImageDev img, int npx,
+                                                             const uint32_t* skip) {
+  __shared__ float bl[256];
+  __shared__ int bi[256];
+  SKIP_IF(skip);
+  const int lo = blockIdx.x * kBrightChunk, hi = min(npx, lo + kBrightChunk);
+  float pl = INFINITY;
+  int pi = -1;
+  for (int r = 0; r < kBright; ++r) {
+    float best = -1.0f;
+    int idx = -1;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+      const float l = lum(mk3(img.iter_sum[3 * (size_t)i], img.iter_sum[3 * (size_t)i + 1],
+                              img.iter_sum[3 * (size_t)i + 2]));
+      if (!ranks_above(pl, pi, l, i)) continue;
+      if (l > best) { best = l; idx = i; }
+    }
+    block_best<256>(bl, bi, best, idx);
+    if (threadIdx.x == 0) {
+      img.bright_l[blockIdx.x * kBright + r] = best;
+      img.bright_i[blockIdx.x * kBright + r] = idx;
+    }
+    if (idx < 0) {
+      for (int q = r + 1 + (int)threadIdx.x; q < kBright; q += 256) {
+        img.bright_l[blockIdx.x * kBright + q] = -1.0f;
+        img.bright_i[blockIdx.x * kBright + q] = -1;
+      }
+      return;
+    }
+    pl = best;
+    pi = idx;
+  }
+}
+__global__ __launch_bounds__(1024) void brightest_final_kernel(ImageDev img, int ncand,
+                                                               const uint32_t* skip) {
   __shared__ float bl[1024];
   __shared__ int bi[1024];
   SKIP_IF(skip);
-  for (int k = 0; k < 10 && k < npx; ++k) {
+  float pl = INFINITY;
+  int pi = -1;
+  for (int r = 0; r < kBright; ++r) {
     float best = -1.0f;
     int idx = -1;
-    for (int i = threadIdx.x; i < npx; i += blockDim.x) {
-      if (img.excl[i] == 2) continue;
-      const float l = lum(mk3(img.iter_sum[3 * (size_t)i], img.iter_sum[3 * (size_t)i + 1],
-                              img.iter_sum[3 * (size_t)i + 2]));
-      if (l > best) { best = l; idx = i; }
+    for (int c = threadIdx.x; c < ncand; c += 1024) {
+      const int i = img.bright_i[c];
+      if (i < 0) continue;
+      const float l = img.bright_l[c];
+      if (!ranks_above(pl, pi, l, i)) continue;
+      if (l > best || (l == best && i < idx)) { best = l; idx = i; }
     }
-    bl[threadIdx.x] = best;
-    bi[threadIdx.x] = idx;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) {
-        const float o = bl[threadIdx.x + s];
-        const int oi = bi[threadIdx.x + s];
-        if (o > bl[threadIdx.x] || (o == bl[threadIdx.x] && oi >= 0 &&
-                                    (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
-          bl[threadIdx.x] = o;
-          bi[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0 && bi[0] >= 0) img.excl[bi[0]] = 2;
-    __syncthreads();
+    block_best<1024>(bl, bi, best, idx);
+    if (idx < 0) return;
+    if (threadIdx.x == 0) img.excl[idx] = 2;
+    pl = best;
+    pi = idx;
   }
 }
 
@@ -1673,7 +1725,11 @@ void k_update_image(const ImageDev& img, int W, int H, int spp, const double* to
   clear_red_kernel<<<1, 64, 0, s>>>(img.red, skip);
   accum_mean_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, total_spp, skip);
   itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H, skip);
-  if (bdpt) brightest_kernel<<<1, 1024, 0, s>>>(img, npx, skip);
+  if (bdpt) {
+    const int nb = (npx + kBrightChunk - 1) / kBrightChunk;
+    brightest_part_kernel<<<nb, 256, 0, s>>>(img, npx, skip);
+    brightest_final_kernel<<<1, 1024, 0, s>>>(img, nb * kBright, skip);
+  }
   vi_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, stat_clamp, skip);
 }
 

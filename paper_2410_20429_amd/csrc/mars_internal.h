@@ -130,7 +130,11 @@ struct ImageDev {
   double* ivw_acc;  // [px][3]
   float* count_map; // [px][3]
   double* red;      // [8] reductions: image mean rgb, V_I sum, included count, ...
+  float* bright_l;  // [ceil(px / kBrightChunk)][kBright] brightest-pixel candidates
+  int32_t* bright_i;
 };
+// brightest pixels dropped from V_I in BDPT, selected in chunks of pixels
+constexpr int kBright = 10, kBrightChunk = 4096;
 
 // learned cache: parameter layout (binary32 master) -- W1 [64][80], b1 [64],
 // W2 [64][64], b2, W3 [64][64], b3, W4 [16][64] (rows 3..15 zero), b4 [16]
