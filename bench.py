@@ -209,8 +209,8 @@ def run_mlp(args, api, torch, n_iter=14):
     """Learned-cache workload: 1920x1080 BDPT interior of 2.08M triangles,
     max path length 12.  Octree MARS and learned-cache MARS run the same
     schedule (3 classic iterations, MARS from the 4th, the network's counts
-    from the 6th; iterations of 2 spp; the network trained 16 Adam steps of
-    8192 samples after every update).  Efficiency 1/(relMSE * s) of the IVW
+    from the 9th; iterations of 2 spp; the network trained 64 Adam steps of
+    8192 samples after every update from the 4th iteration on).  Efficiency 1/(relMSE * s) of the IVW
     image of each against a 256 spp classic reference, and the mean
     1/(V_I C_I) of the last 6 iterations."""
     import numpy as np
@@ -229,7 +229,7 @@ def run_mlp(args, api, torch, n_iter=14):
         t_train = 0.0
         for i in range(n_iter):
             alloc = api.ALLOC_CLASSIC if i < 3 else api.ALLOC_MARS
-            if kind == "mlp" and i >= 5:
+            if kind == "mlp" and i >= 8:
                 alloc = api.ALLOC_MLP
             p = api.iter_params(iteration=i, spp=2, alloc=alloc, stat_clamp=0.0)
             s.render_iteration(p)
@@ -237,7 +237,7 @@ def run_mlp(args, api, torch, n_iter=14):
             if kind == "mlp" and i >= 3:
                 torch.cuda.synchronize()
                 tt = time.perf_counter()
-                s.mlp_train(steps=16, batch=8192, lr=2e-3)
+                s.mlp_train(steps=64, batch=8192, lr=2e-3)
                 torch.cuda.synchronize()
                 t_train += time.perf_counter() - tt
             if i >= n_iter - 6:
