@@ -36,6 +36,75 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// shading kernels: 1024-thread groups (one queue allocation per group); the
+// connection kernel (statistics atomics only, 78 VGPRs): 512-thread groups,
+// three per CU
+constexpr int kShadeBlock = 1024, kConnectBlock = 512;
+// launch grid for the shading kernels: the thread count of `grid` groups of 256
+inline int shade_grid(int grid) { return grid * 256 / kShadeBlock > 0 ? grid * 256 / kShadeBlock : 1; }
+
+// the overflow flag read once per workgroup, so that every thread of the
+// group takes the same exit (the kernels below use workgroup barriers)
+__device__ __forceinline__ bool group_overflowed(const Counters* cnt) {
+  __shared__ uint32_t flag;
+  if (threadIdx.x == 0) flag = cnt->overflow;
+  __syncthreads();
+  return flag != 0u;
+}
+
+// Workgroup-wide allocation in two queues: lane counts (a, b) -> the lane's
+// first slot in each.  One atomic per queue per workgroup: device-scope
+// atomics on one address serialise across the chip, so the fewer the better.
+// lds: 2 * kThreads / 64 + 2 words.  Every thread of the group must call it.
+template <int kThreads>
+__device__ __forceinline__ void group_alloc(uint32_t a, uint32_t b, uint32_t* ca, uint32_t* cb,
+                                            uint32_t* fa, uint32_t* fb, uint32_t* lds) {
+  constexpr int kW = kThreads / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t ia = wave_scan_incl(a), ib = wave_scan_incl(b);
+  if (lane == 63) {
+    lds[wid] = ia;
+    lds[kW + wid] = ib;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sa = 0, sb = 0;
+    for (int w = 0; w < kW; ++w) {
+      const uint32_t x = lds[w], y = lds[kW + w];
+      lds[w] = sa;
+      lds[kW + w] = sb;
+      sa += x;
+      sb += y;
+    }
+    lds[2 * kW] = sa ? atomicAdd(ca, sa) : 0u;
+    lds[2 * kW + 1] = sb ? atomicAdd(cb, sb) : 0u;
+  }
+  __syncthreads();
+  *fa = lds[2 * kW] + lds[wid] + (ia - a);
+  *fb = lds[2 * kW + 1] + lds[kW + wid] + (ib - b);
+  __syncthreads();
+}
+
+// adds per-thread counts into N 64-bit counters, one atomic per counter per
+// workgroup; lds: N * kThreads / 64 words.  Every thread must call it.
+template <int kThreads, int N>
+__device__ __forceinline__ void group_add(const uint32_t (&v)[N], unsigned long long* const (&dst)[N],
+                                          uint32_t* lds) {
+  constexpr int kW = kThreads / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const uint32_t s = wave_sum(v[i]);
+    if (lane == 0) lds[i * kW + wid] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < N) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kW; ++w) s += lds[threadIdx.x * kW + w];
+    if (s) atomicAdd(dst[threadIdx.x], s);
+  }
+}
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -399,10 +468,11 @@ __device__ __forceinline__ void mlp_record(const CacheDev& c, uint2 strm, f3 x, 
 // {B,G} for indirect light; budget-aware multiplies every density by beta.
 // Child throughput T' = T B|cos| / p_t * w_ind,t / beta_t (Sec. 3.1).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+__global__ __launch_bounds__(kShadeBlock) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                        Counters* cnt, IterDev it, ImageDev img,
                                                        DebugRec* dbg, uint32_t dbg_cap, int d) {
-  if (cnt->overflow) return;
+  __shared__ uint32_t alloc_lds[4 * kShadeBlock / 64 + 2];
+  if (group_overflowed(cnt)) return;
   const Key key{sc.key0, sc.key1};
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
   const int lane = threadIdx.x & 63;
@@ -468,19 +538,10 @@ __global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, 
       }
     }
     const uint32_t ncont = vert ? gam[0] + gam[2] : 0u, nnee = vert ? gam[1] : 0u;
-    // wave-level allocation in the next-depth and shadow queues
-    const uint32_t packed = ncont | (nnee << 16);
-    const uint32_t incl = wave_scan_incl(packed);
-    const uint32_t excl = incl - packed;
-    const uint32_t tot = __shfl(incl, 63, 64);
-    uint32_t bc = 0, bs = 0;
-    if (lane == 63) {
-      if (tot & 0xFFFFu) bc = atomicAdd(&cnt->n_ray[d + 1], tot & 0xFFFFu);
-      if (tot >> 16) bs = atomicAdd(&cnt->n_shadow[d], tot >> 16);
-    }
-    bc = __shfl(bc, 63, 64);
-    bs = __shfl(bs, 63, 64);
-    const uint32_t cfirst = bc + (excl & 0xFFFFu), sfirst = bs + (excl >> 16);
+    // workgroup-level allocation in the next-depth and shadow queues
+    uint32_t cfirst, sfirst;
+    group_alloc<kShadeBlock>(ncont, nnee, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
+                             alloc_lds);
     bool ovf = false;
     if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.cap)) {
       ovf = true;
@@ -609,19 +670,14 @@ __global__ __launch_bounds__(256) void shade_pt_kernel(SceneDev sc, CacheDev c, 
     }
   }
   // one atomic per wave for the iteration counters
-  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext),
-                 sh = wave_sum(my_sh);
-  if (lane == 0) {
-    if (sv) atomicAdd(&cnt->vertices, (unsigned long long)sv);
-    if (ss) atomicAdd(&cnt->samples, (unsigned long long)ss);
-    if (se) atomicAdd(&cnt->rays_ext, (unsigned long long)se);
-    if (sh) atomicAdd(&cnt->rays_shadow, (unsigned long long)sh);
-  }
+  group_add<kShadeBlock, 4>({my_vert, my_samp, my_ext, my_sh},
+                            {&cnt->vertices, &cnt->samples, &cnt->rays_ext, &cnt->rays_shadow},
+                            alloc_lds);
 }
 void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s) {
-  shade_pt_kernel<<<grid, 256, 0, s>>>(sc, c, q, cnt, it, img, dbg, dbg_cap, d);
+  shade_pt_kernel<<<shade_grid(grid), kShadeBlock, 0, s>>>(sc, c, q, cnt, it, img, dbg, dbg_cap, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1041,11 +1097,12 @@ __device__ __forceinline__ uint32_t lp_index(uint32_t root, uint32_t j, int32_t 
   return (uint32_t)(((unsigned long long)root + (unsigned long long)j * (uint32_t)stride) % npool);
 }
 
-__global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+__global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                          LightDev lt, Counters* cnt, IterDev it,
                                                          ImageDev img, DebugRec* dbg,
                                                          uint32_t dbg_cap, int d, uint32_t npool) {
-  if (cnt->overflow) return;
+  __shared__ uint32_t alloc_lds[4 * kShadeBlock / 64 + 2];
+  if (group_overflowed(cnt)) return;
   const Key key{sc.key0, sc.key1};
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
   const int lane = threadIdx.x & 63;
@@ -1114,18 +1171,9 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
       }
     }
     const uint32_t ncont = vert ? gam[0] : 0u, nsh = vert ? gam[1] + nconn : 0u;
-    const uint32_t packed = ncont | (nsh << 16);
-    const uint32_t incl = wave_scan_incl(packed);
-    const uint32_t excl = incl - packed;
-    const uint32_t tot = __shfl(incl, 63, 64);
-    uint32_t bc = 0, bs = 0;
-    if (lane == 63) {
-      if (tot & 0xFFFFu) bc = atomicAdd(&cnt->n_ray[d + 1], tot & 0xFFFFu);
-      if (tot >> 16) bs = atomicAdd(&cnt->n_shadow[d], tot >> 16);
-    }
-    bc = __shfl(bc, 63, 64);
-    bs = __shfl(bs, 63, 64);
-    const uint32_t cfirst = bc + (excl & 0xFFFFu), sfirst = bs + (excl >> 16);
+    uint32_t cfirst, sfirst;
+    group_alloc<kShadeBlock>(ncont, nsh, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
+                             alloc_lds);
     bool ovf = false;
     if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nsh > q.cap)) {
       ovf = true;
@@ -1221,22 +1269,18 @@ __global__ __launch_bounds__(256) void shade_bdpt_kernel(SceneDev sc, CacheDev c
       }
     }
   }
-  const uint32_t sv = wave_sum(my_vert), ss = wave_sum(my_samp), se = wave_sum(my_ext);
-  if (lane == 0) {
-    if (sv) atomicAdd(&cnt->vertices, (unsigned long long)sv);
-    if (ss) atomicAdd(&cnt->samples, (unsigned long long)ss);
-    if (se) atomicAdd(&cnt->rays_ext, (unsigned long long)se);
-  }
+  group_add<kShadeBlock, 3>({my_vert, my_samp, my_ext},
+                            {&cnt->vertices, &cnt->samples, &cnt->rays_ext}, alloc_lds);
 }
 
 // NEE samples and light-path connections of the camera vertices of depth d,
 // one thread per shadow entry: the full-path MIS weight and the weighted
 // contribution, then the shadow ray.  Splitting gives vertices very uneven
 // numbers of connections; this keeps the waves balanced.
-__global__ __launch_bounds__(256) void connect_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+__global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                            LightDev lt, Counters* cnt, IterDev it,
                                                            ImageDev img, int d) {
-  if (cnt->overflow) return;
+  if (group_overflowed(cnt)) return;
   const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
   const size_t L = (size_t)d * q.cap;
   uint32_t my_sh = 0, my_conn = 0;
@@ -1332,19 +1376,18 @@ __global__ __launch_bounds__(256) void connect_bdpt_kernel(SceneDev sc, CacheDev
       q.SH2[e] = sh2;
     }
   }
-  const uint32_t sh = wave_sum(my_sh), sn = wave_sum(my_conn);
-  if ((threadIdx.x & 63) == 0) {
-    if (sh) atomicAdd(&cnt->rays_shadow, (unsigned long long)sh);
-    if (sn) atomicAdd(&cnt->rays_conn, (unsigned long long)sn);
-  }
+  __shared__ uint32_t stat_lds[2 * kConnectBlock / 64];
+  group_add<kConnectBlock, 2>({my_sh, my_conn}, {&cnt->rays_shadow, &cnt->rays_conn}, stat_lds);
 }
 
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s) {
-  shade_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
+  shade_bdpt_kernel<<<shade_grid(grid), kShadeBlock, 0, s>>>(sc, c, q, lt, cnt, it, img, dbg, dbg_cap,
+                                                               d, npool);
   if (d < sc.max_depth)
-    connect_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d);
+    connect_bdpt_kernel<<<std::max(1, grid * 3 / 8), kConnectBlock, 0, s>>>(sc, c, q, lt, cnt, it,
+                                                                           img, d);
 }
 
 // back-propagation for BDPT: NEE, BSDF and LP samples in that order
