@@ -753,6 +753,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     const size_t nbright = (px + kBrightChunk - 1) / kBrightChunk * kBright;
     im.bright_l = salloc<float>(s, nbright);
     im.bright_i = salloc<int32_t>(s, nbright);
+    im.part = salloc<double>(s, 8 * (size_t)kRedBlocks);
     k_fill_f32(im.iter_sum, 0.0f, px * 3, st);
     k_fill_f32(im.accum, 0.0f, px * 3, st);
     k_fill_f32(im.itilde, INFINITY, px * 3, st);

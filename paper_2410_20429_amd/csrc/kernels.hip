@@ -1583,19 +1583,6 @@ void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s) {
 // red[0..2]: image-mean sums, red[3]: V_I sum, red[4]: included pixels,
 // red[5]: inverse-variance weight sum.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_add_d(double v, double* dst) {
-  __shared__ double part[16];
-  v = wave_sum_d(v);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) part[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += part[k];
-    atomicAdd(dst, s);
-  }
-  __syncthreads();
-}
 
 __global__ void add_spp_kernel(double* total, int spp, const uint32_t* skip) {
   SKIP_IF(skip);
@@ -1605,23 +1592,48 @@ void k_add_spp(double* total_spp, int spp, const uint32_t* skip, hipStream_t s) 
   add_spp_kernel<<<1, 1, 0, s>>>(total_spp, spp, skip);
 }
 
-__global__ void accum_mean_kernel(ImageDev img, int npx, const double* total_spp,
-                                  const uint32_t* skip) {
+// sum of v over the workgroup (fixed order), valid in thread 0
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double part[16];
+  v = wave_sum_d(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += part[k];
+  __syncthreads();
+  return s;
+}
+// red[first + j] = sum over the workgroups' partials part[b][first + j], in order
+__global__ void reduce_parts_kernel(ImageDev img, int first, int count, const uint32_t* skip) {
+  SKIP_IF(skip);
+  const int j = threadIdx.x;
+  if (j >= count) return;
+  double s = 0.0;
+  for (int b = 0; b < kRedBlocks; ++b) s += img.part[8 * b + first + j];
+  img.red[first + j] = s;
+}
+
+__global__ __launch_bounds__(256) void accum_mean_kernel(ImageDev img, int npx,
+                                                         const double* total_spp,
+                                                         const uint32_t* skip) {
   SKIP_IF(skip);
   const float tsp = (float)*total_spp;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double m[3] = {0.0, 0.0, 0.0};
-  if (i < npx) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x)
     for (int ch = 0; ch < 3; ++ch) {
       const size_t e = 3 * (size_t)i + ch;
       const float a = img.accum[e] + img.iter_sum[e];
       img.accum[e] = a;
       const float mv = a / tsp;
       img.mean[e] = mv;
-      m[ch] = (double)mv;
+      m[ch] += (double)mv;
     }
+  for (int ch = 0; ch < 3; ++ch) {
+    const double s = block_sum_d(m[ch]);
+    if (threadIdx.x == 0) img.part[8 * blockIdx.x + ch] = s;
   }
-  for (int ch = 0; ch < 3; ++ch) block_add_d(m[ch], img.red + ch);
 }
 
 __global__ void itilde_kernel(ImageDev img, int W, int H, const uint32_t* skip) {
@@ -1736,12 +1748,14 @@ __global__ __launch_bounds__(1024) void brightest_final_kernel(ImageDev img, int
   }
 }
 
-__global__ void vi_kernel(ImageDev img, int npx, int spp, float kc, const uint32_t* skip) {
+__global__ __launch_bounds__(256) void vi_kernel(ImageDev img, int npx, int spp, float kc,
+                                                  const uint32_t* skip) {
   SKIP_IF(skip);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0.0, inc = 0.0;
-  if (i < npx && img.excl[i] == 0) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
+    if (img.excl[i] != 0) continue;
     const float* It = img.itilde + 3 * (size_t)i;
+    double ep = 0.0;
     for (int s = 0; s < spp; ++s) {
       const float* l = img.Ls + 3 * ((size_t)i * spp + s);
       float dd[3];
@@ -1749,13 +1763,16 @@ __global__ void vi_kernel(ImageDev img, int npx, int spp, float kc, const uint32
         const float xv = kc > 0.0f ? fminf(l[ch], kc * It[ch]) : l[ch];
         dd[ch] = (xv - It[ch]) / It[ch];
       }
-      e += (double)((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+      ep += (double)((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
     }
-    e = e / (3.0 * (double)spp);
-    inc = 1.0;
+    e += ep / (3.0 * (double)spp);
+    inc += 1.0;
   }
-  block_add_d(e, img.red + 3);
-  block_add_d(inc, img.red + 4);
+  const double se = block_sum_d(e), si = block_sum_d(inc);
+  if (threadIdx.x == 0) {
+    img.part[8 * blockIdx.x + 3] = se;
+    img.part[8 * blockIdx.x + 4] = si;
+  }
 }
 
 __global__ void clear_red_kernel(double* red, const uint32_t* skip) {
@@ -1766,14 +1783,16 @@ void k_update_image(const ImageDev& img, int W, int H, int spp, const double* to
                     float stat_clamp, const uint32_t* skip, hipStream_t s) {
   const int npx = W * H;
   clear_red_kernel<<<1, 64, 0, s>>>(img.red, skip);
-  accum_mean_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, total_spp, skip);
+  accum_mean_kernel<<<kRedBlocks, 256, 0, s>>>(img, npx, total_spp, skip);
+  reduce_parts_kernel<<<1, 64, 0, s>>>(img, 0, 3, skip);
   itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H, skip);
   if (bdpt) {
     const int nb = (npx + kBrightChunk - 1) / kBrightChunk;
     brightest_part_kernel<<<nb, 256, 0, s>>>(img, npx, skip);
     brightest_final_kernel<<<1, 1024, 0, s>>>(img, nb * kBright, skip);
   }
-  vi_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, stat_clamp, skip);
+  vi_kernel<<<kRedBlocks, 256, 0, s>>>(img, npx, spp, stat_clamp, skip);
+  reduce_parts_kernel<<<1, 64, 0, s>>>(img, 3, 2, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1852,36 +1871,50 @@ __global__ void split_flags_kernel(CacheDev c, const int32_t* n_cells_dev, uint3
   flags[l] = (c.visits[l] > (uint32_t)split_visits && c.leaf_depth[l] < (uint32_t)max_tree_depth)
                  ? 1u : 0u;
 }
-__global__ void scan_flags_kernel(const int32_t* n_cells_dev, uint32_t* flags, uint32_t* total,
-                                  const uint32_t* skip) {
-  __shared__ uint32_t part[1024];
+// rank of every flagged leaf among the flagged ones (index order), sentinel
+// otherwise, and the number flagged: one workgroup over tiles of 1024 flags,
+// coalesced loads, wave ballots and a carry across tiles
+__global__ __launch_bounds__(1024) void scan_flags_kernel(const int32_t* n_cells_dev,
+                                                          uint32_t* flags, uint32_t* total,
+                                                          const uint32_t* skip) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
   SKIP_IF(skip);
   const int n = *n_cells_dev;
-  const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
-  const int b = threadIdx.x * chunk, e = min(n, b + chunk);
-  uint32_t s = 0;
-  for (int i = b; i < e; ++i) s += flags[i];
-  part[threadIdx.x] = s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0u;
   __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const uint32_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    const uint32_t f = i < n ? flags[i] : 0u;
+    const unsigned long long m = __ballot(f != 0u);
+    const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = (uint32_t)__popcll(m);
     __syncthreads();
-    part[threadIdx.x] += v;
+    uint32_t off = carry;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    if (i < n) flags[i] = f ? off + below : 0xFFFFFFFFu;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0u;
+      for (int w = 0; w < 16; ++w) t += wsum[w];
+      carry += t;
+    }
     __syncthreads();
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int i = b; i < e; ++i) {
-    const uint32_t f = flags[i];
-    flags[i] = f ? run : 0xFFFFFFFFu;  // rank of flagged leaves, sentinel otherwise
-    run += f;
-  }
-  if (threadIdx.x == blockDim.x - 1) *total = part[threadIdx.x];
+  if (threadIdx.x == 0) *total = carry;
 }
-__global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
-                                   const int32_t* n_nodes_dev, const uint32_t* rank,
-                                   const uint32_t* total, int max_cells, const uint32_t* skip) {
+// one wave per leaf: lane 0 links the eight children into the tree, the
+// lanes copy the parent's factors and distribution into the seven new cells
+// and clear their statistics
+__global__ __launch_bounds__(256) void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
+                                                          const int32_t* n_nodes_dev,
+                                                          const uint32_t* rank,
+                                                          const uint32_t* total, int max_cells,
+                                                          const uint32_t* skip) {
   SKIP_IF(skip);
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int l = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int n0 = *n_cells_dev, nn0 = *n_nodes_dev;
   if (l >= n0) return;
   const uint32_t r = rank[l];
@@ -1889,27 +1922,29 @@ __global__ void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
   const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
   const uint32_t acc = min(*total, room);
   if (r >= acc) return;
-  const uint32_t node = c.leaf_node[l];
   const uint32_t base = (uint32_t)nn0 + 8u * r;
-  c.nodes[node] = base;
-  const uint32_t dep = c.leaf_depth[l] + 1u;
-  for (int ch = 0; ch < 8; ++ch) {
-    const uint32_t id = ch == 0 ? (uint32_t)l : (uint32_t)n0 + 7u * r + (uint32_t)(ch - 1);
-    c.nodes[base + ch] = kLeafBit | id;
-    c.leaf_node[id] = base + ch;
-    c.leaf_depth[id] = dep;
-    if (ch) {
-      // new cells: the parent's factors and distribution, no statistics yet
-      for (int k = 0; k < 18; ++k) c.fac[(size_t)id * 18 + k] = c.fac[(size_t)l * 18 + k];
-      for (int k = 0; k < 64; ++k) {
-        c.pm[(size_t)id * 64 + k] = c.pm[(size_t)l * 64 + k];
-        c.cdf[(size_t)id * 64 + k] = c.cdf[(size_t)l * 64 + k];
-        c.hacc[(size_t)id * 64 + k] = 0.0;
-      }
-      for (int k = 0; k < 24; ++k) c.acc[(size_t)id * 24 + k] = 0.0;
-      c.visits[id] = 0u;
+  const uint32_t first = (uint32_t)n0 + 7u * r;  // ids of children 1..7
+  if (lane == 0) {
+    const uint32_t node = c.leaf_node[l];
+    const uint32_t dep = c.leaf_depth[l] + 1u;
+    c.nodes[node] = base;
+    for (int ch = 0; ch < 8; ++ch) {
+      const uint32_t id = ch == 0 ? (uint32_t)l : first + (uint32_t)(ch - 1);
+      c.nodes[base + ch] = kLeafBit | id;
+      c.leaf_node[id] = base + ch;
+      c.leaf_depth[id] = dep;
     }
   }
+  for (int k = lane; k < 7 * 18; k += 64)
+    c.fac[(size_t)(first + k / 18) * 18 + k % 18] = c.fac[(size_t)l * 18 + k % 18];
+  for (int k = lane; k < 7 * 64; k += 64) {
+    const size_t dst = (size_t)(first + k / 64) * 64 + k % 64, src = (size_t)l * 64 + k % 64;
+    c.pm[dst] = c.pm[src];
+    c.cdf[dst] = c.cdf[src];
+    c.hacc[dst] = 0.0;
+  }
+  for (int k = lane; k < 7 * 24; k += 64) c.acc[(size_t)(first + k / 24) * 24 + k % 24] = 0.0;
+  if (lane < 7) c.visits[first + lane] = 0u;
 }
 __global__ void finish_split_kernel(int32_t* n_cells_dev, int32_t* n_nodes_dev,
                                     const uint32_t* total, int max_cells, const uint32_t* skip) {
@@ -1926,8 +1961,8 @@ void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uin
   const int g = (max_cells + 255) / 256;
   split_flags_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, scratch, split_visits, max_tree_depth, skip);
   scan_flags_kernel<<<1, 1024, 0, s>>>(n_cells_dev, scratch, scratch + max_cells, skip);
-  apply_split_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch, scratch + max_cells,
-                                       max_cells, skip);
+  apply_split_kernel<<<(max_cells + 3) / 4, 256, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch,
+                                                         scratch + max_cells, max_cells, skip);
   finish_split_kernel<<<1, 1, 0, s>>>(n_cells_dev, n_nodes_dev, scratch + max_cells, max_cells, skip);
 }
 

@@ -132,7 +132,11 @@ struct ImageDev {
   double* red;      // [8] reductions: image mean rgb, V_I sum, included count, ...
   float* bright_l;  // [ceil(px / kBrightChunk)][kBright] brightest-pixel candidates
   int32_t* bright_i;
+  double* part;     // [kRedBlocks][8] per-workgroup partial sums of the image reductions
 };
+// image reductions: a fixed grid of workgroups, partial sums summed in order
+// (deterministic, no contended atomics)
+constexpr int kRedBlocks = 256;
 // brightest pixels dropped from V_I in BDPT, selected in chunks of pixels
 constexpr int kBright = 10, kBrightChunk = 4096;
 
