@@ -492,7 +492,9 @@ def main():
                            "bytes_per_closest_ray": bpr_c, "bytes_per_shadow_ray": bpr_s,
                            "nodes_per_closest_ray": tc[1] / max(tc[0], 1),
                            "tris_per_closest_ray": tc[2] / max(tc[0], 1),
-                           "nodes_per_shadow_ray": tc[4] / max(tc[3], 1)}
+                           "nodes_per_shadow_ray": tc[4] / max(tc[3], 1),
+                           "max_nodes_closest_ray": tc[6], "max_nodes_shadow_ray": tc[7],
+                           "rays_over_64_nodes": [tc[8], tc[9]]}
         if not args.no_cpu_baseline:
             print("[bench] cpu baseline", file=sys.stderr, flush=True)
             out["cpu_baseline"] = cpu_baseline(sc)

@@ -302,9 +302,11 @@ mars_status mars_profile_read(mars_ctx* ctx, double* ms, uint64_t* launches, int
 const char* mars_profile_kernel_name(int32_t id);
 /* Instrumented traversal (slower; for the algorithmic byte count per ray):
  * out[0..2] = closest-hit rays, BVH nodes visited, triangles tested;
- * out[3..5] = the same for shadow rays.  Enabling resets the counters. */
+ * out[3..5] = the same for shadow rays; out[6], out[7] = most nodes visited
+ * by one closest-hit / shadow ray; out[8], out[9] = closest-hit / shadow
+ * rays that visited more than 64 nodes.  Enabling resets the counters. */
 mars_status mars_trace_counting(mars_ctx* ctx, int32_t on);
-mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[6]);
+mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[10]);
 
 /* ---- device probes (tests): evaluates a building block on the GPU ------ */
 /* kind 0: Philox4x32-10, in [n][6] u32 (key0, key1, ctr0..3), out [n][4] u32

@@ -332,7 +332,7 @@ def mars_trace_counting(ctx, on):
 
 
 def mars_read_trace_counts(ctx):
-    out = (C.c_uint64 * 6)()
+    out = (C.c_uint64 * 10)()
     _call("mars_read_trace_counts", ctx, C.cast(out, C.c_void_p))
     return list(out)
 

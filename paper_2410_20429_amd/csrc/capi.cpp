@@ -1392,18 +1392,18 @@ const char* mars_profile_kernel_name(int32_t id) {
 mars_status mars_trace_counting(mars_ctx* ctx, int32_t on) {
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
-    if (!ctx->tcount) ctx->tcount = (unsigned long long*)ctx->dalloc(8 * 8);
-    k_fill_u32((uint32_t*)ctx->tcount, 0u, 16, ctx->stream);
+    if (!ctx->tcount) ctx->tcount = (unsigned long long*)ctx->dalloc(8 * 16);
+    k_fill_u32((uint32_t*)ctx->tcount, 0u, 32, ctx->stream);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->counting = on != 0;
   });
 }
 
-mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[6]) {
+mars_status mars_read_trace_counts(mars_ctx* ctx, uint64_t out[10]) {
   if (!ctx || !out) return MARS_E_ARG;
   return guard(ctx, [&] {
     if (!ctx->tcount) throw Status(MARS_E_STATE, "trace counting never enabled");
-    d2h(out, ctx->tcount, 48, ctx->stream);
+    d2h(out, ctx->tcount, 80, ctx->stream);
     HIPCHK(hipStreamSynchronize(ctx->stream));
   });
 }

@@ -350,6 +350,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
   const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
   const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
   uint32_t cr = 0, cn = 0, ct = 0, sr = 0, sn = 0, st = 0;
+  uint32_t cmax = 0, smax = 0, clong = 0, slong = 0;  // per-ray node visits: max, rays > 64
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nc + ns;
        j += gridDim.x * blockDim.x) {
     float t;
@@ -360,8 +361,13 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
       if (r0.w != 0.0f) {
         const float4 r1 = q.R1[Lc + j];
         if (kCount) ++cr;
+        const uint32_t cn0 = cn;
         if (traverse<false, kCount>(sc, xyz(r0), xyz(r1), INFINITY, stk, &t, &p, &cn, &ct))
           h = make_uint2(ubits(t), p);
+        if (kCount) {
+          cmax = max(cmax, cn - cn0);
+          clong += (cn - cn0) > 64u ? 1u : 0u;
+        }
       }
       q.H[Lc + j] = h;
     } else {
@@ -370,13 +376,25 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
       if (v.w == 0.0f) continue;
       const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
       if (kCount) ++sr;
+      const uint32_t sn0 = sn;
       if (traverse<true, kCount>(sc, xyz(a), xyz(b), a.w, stk, &t, &p, &sn, &st))
         q.SH2[Ls + k] = make_float4(0.0f, 0.0f, 0.0f, v.w);
+      if (kCount) {
+        smax = max(smax, sn - sn0);
+        slong += (sn - sn0) > 64u ? 1u : 0u;
+      }
     }
   }
   if (kCount) {
     add_counts(tc, cr, cn, ct);
     add_counts(tc + 3, sr, sn, st);
+    const uint32_t cl = wave_sum(clong), sl = wave_sum(slong);
+    if ((threadIdx.x & 63) == 0) {
+      if (cl) atomicAdd(tc + 8, (unsigned long long)cl);
+      if (sl) atomicAdd(tc + 9, (unsigned long long)sl);
+    }
+    if (cmax) atomicMax(tc + 6, (unsigned long long)cmax);
+    if (smax) atomicMax(tc + 7, (unsigned long long)smax);
   }
 }
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
