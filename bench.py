@@ -176,7 +176,14 @@ def run_bdpt(args, api, torch):
         return st
     for i in range(warm):
         step(i)
-    print("[bench] bdpt: warm", file=sys.stderr, flush=True)
+    # queue and tile sizes from the autotuner on a MARS iteration (connections
+    # multiply the shadow queues), then one untimed iteration at those sizes
+    tuned = api.autotune([s], api.iter_params(iteration=warm, spp=1, alloc=api.ALLOC_MARS,
+                                              stat_clamp=0.0), mem_budget=96 << 30)
+    torch.cuda.empty_cache()
+    step(warm)
+    warm += 1
+    print(f"[bench] bdpt: warm, tuned {tuned}", file=sys.stderr, flush=True)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,7 +202,8 @@ def run_bdpt(args, api, torch):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "bdpt_1280x720_interior1m_d12", "width": sc["width"],
                       "height": sc["height"], "triangles": int(sc["V"].shape[0]), "max_depth": 12,
-                      "spp_per_step": 1, "techniques": ["bsdf", "nee", "light_path"]},
+                      "spp_per_step": 1, "techniques": ["bsdf", "nee", "light_path"],
+                      "queue_capacity": tuned[0][0], "tile_roots": tuned[0][1]},
            "mrays_per_s": rays / dt / 1e6,
            "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
     if not args.no_efficiency:

@@ -268,10 +268,16 @@ __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float t
     const float4 lx = N[0], ly = N[1], lz = N[2], hx = N[3], hy = N[4], hz = N[5];
     const float4 rf = N[6];
     int r0 = (int)ubits(rf.x), r1 = (int)ubits(rf.y), r2 = (int)ubits(rf.z), r3 = (int)ubits(rf.w);
-    float t0 = r0 == kBvhNoChild ? INFINITY : box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
-    float t1 = r1 == kBvhNoChild ? INFINITY : box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
-    float t2 = r2 == kBvhNoChild ? INFINITY : box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
-    float t3 = r3 == kBvhNoChild ? INFINITY : box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
+    // all four boxes tested unconditionally (branch-free, on the loaded
+    // registers), unused slots masked afterwards
+    float t0 = box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
+    float t1 = box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
+    float t2 = box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
+    float t3 = box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
+    t0 = r0 == kBvhNoChild ? INFINITY : t0;
+    t1 = r1 == kBvhNoChild ? INFINITY : t1;
+    t2 = r2 == kBvhNoChild ? INFINITY : t2;
+    t3 = r3 == kBvhNoChild ? INFINITY : t3;
 #pragma unroll
     for (int side = 0; side < 4; ++side) {
       const int ch = side == 0 ? r0 : side == 1 ? r1 : side == 2 ? r2 : r3;
