@@ -306,7 +306,7 @@ void alloc_queues(Scene* s, size_t cap) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     for (void* p : {(void*)q.R0, (void*)q.R1, (void*)q.S0, (void*)q.S1, (void*)q.S2, (void*)q.S3,
                     (void*)q.H, (void*)q.V0, (void*)q.V1, (void*)q.V2, (void*)q.RO, (void*)q.SH0,
-                    (void*)q.SH1, (void*)q.SH2, (void*)s->mlp.y})
+                    (void*)q.SH1, (void*)q.SH2, (void*)q.W0, (void*)q.W1, (void*)s->mlp.y})
       sfree(s, p);
     q = QueuesDev{};
     s->mlp.y = nullptr;
@@ -319,6 +319,10 @@ void alloc_queues(Scene* s, size_t cap) {
   q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
   q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
   q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
+  if (s->mode == MARS_MODE_BDPT) {
+    q.W0 = salloc<float4>(s, lv);
+    q.W1 = salloc<float4>(s, lv);
+  }
   q.cap = cap;
   if (s->mlp_on) s->mlp.y = salloc<float>(s, lv * 4);
   s->cap = cap;
@@ -1130,7 +1134,8 @@ size_t min_tile(size_t roots, double e) {
 }
 
 size_t queue_bytes(const Scene* s, size_t cap) {
-  return cap * (size_t)(s->max_depth + 2) * (kQueueEntryBytes + (s->mlp_on ? 16 : 0));
+  return cap * (size_t)(s->max_depth + 2) *
+         (kQueueEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0));
 }
 
 std::string scene_class(const Scene* s, const mars_iter_params* p) {

@@ -1090,6 +1090,180 @@ void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, C
   light_shade_kernel<<<grid, 256, 0, s>>>(sc, q, lt, cnt, it, bounce);
 }
 
+// ---------------------------------------------------------------------------
+// Full-path MIS weights from per-vertex records.  Every term of the weight
+// that depends on camera vertices only (pF, pR, counts along the
+// position-derived throughput) is computed once, when the vertex is shaded,
+// and stored with it; a NEE sample or connection then evaluates only the
+// terms that involve its light-side vertices and reads the rest walking up
+// the parent chain.  Each value is computed by the same operations and the
+// sums run in the same order as in bdpt_weight, so the weight is the same.
+// ---------------------------------------------------------------------------
+struct VRec {
+  f3 T;
+  float b0, b1, b2, pF, pRg;
+};
+__device__ __forceinline__ VRec load_rec(const QueuesDev& q, int l, uint32_t e) {
+  const size_t a = (size_t)l * q.cap + e;
+  const float4 w0 = q.W0[a], w1 = q.W1[a];
+  return VRec{xyz(w0), w0.w, w1.x, w1.y, w1.z, w1.w};
+}
+__device__ __forceinline__ float mis_count(const IterDev& it, float b) {
+  return it.aware ? b : (b > 0.0f ? 1.0f : 0.0f);
+}
+// the hit vertex of queue entry e at level l
+__device__ __forceinline__ PV hit_vertex(const SceneDev& sc, const QueuesDev& q, int l, uint32_t e) {
+  const size_t a = (size_t)l * q.cap + e;
+  const float4 a0 = q.R0[a], a1 = q.R1[a];
+  const uint2 ah = q.H[a];
+  const float at = fbits(ah.x);
+  return prim_vertex(sc, mk3(a0.x + at * a1.x, a0.y + at * a1.y, a0.z + at * a1.z), ah.y);
+}
+
+// record of the camera vertex j at depth d (hit x with geometric normal ng,
+// octree cell `cell`): pF[d] and pR[d-2] of any full path through it, the
+// camera-prefix throughput recomputed from positions and the raw counts there
+__device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& c,
+                                            const QueuesDev& q, const IterDev& it, int d,
+                                            uint32_t j, f3 x, f3 ng, uint32_t cell,
+                                            const float* It) {
+  f3 T = mk3(1.0f, 1.0f, 1.0f);
+  float pF = 0.0f, pRg = 0.0f;
+  if (d >= 2) {
+    const uint32_t e1 = ubits(q.S0[(size_t)d * q.cap + j].w);
+    const PV zp = hit_vertex(sc, q, d - 1, e1);
+    f3 zpp;
+    PV zg{};
+    if (d == 2) {
+      zpp = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
+    } else {
+      zg = hit_vertex(sc, q, d - 2, ubits(q.S0[(size_t)(d - 1) * q.cap + e1].w));
+      zpp = zg.P;
+    }
+    const VRec rp = load_rec(q, d - 1, e1);
+    const Mat mp = load_mat(sc.mats + 8 * (size_t)zp.mat);
+    float d2;
+    const f3 wo = dir_between(zp.P, zpp, &d2);
+    const f3 wi = dir_between(zp.P, x, &d2);
+    f3 fc;
+    float p;
+    eval_facing(mp, zp.ng, wo, wi, &fc, &p);
+    pF = (p * fabsf(dot3(ng, wi))) / d2;
+    if (p > 0.0f && rp.b0 > 0.0f)
+      T = mk3(rp.T.x * (((fc.x / p) * 1.0f) / rp.b0), rp.T.y * (((fc.y / p) * 1.0f) / rp.b0),
+              rp.T.z * (((fc.z / p) * 1.0f) / rp.b0));
+    else
+      T = mk3(0.0f, 0.0f, 0.0f);
+    if (d >= 3) {
+      const f3 wo2 = dir_between(zp.P, x, &d2);
+      const f3 wi2 = dir_between(zp.P, zpp, &d2);
+      f3 fc2;
+      float p2;
+      eval_facing(mp, zp.ng, wo2, wi2, &fc2, &p2);
+      pRg = (p2 * fabsf(dot3(zg.ng, wi2))) / d2;
+    }
+  }
+  float b[3];
+  counts_at(sc, c, it, cell, T, It, d, b);
+  const size_t a = (size_t)d * q.cap + j;
+  q.W0[a] = make_float4(T.x, T.y, T.z, b[0]);
+  q.W1[a] = make_float4(b[1], b[2], pF, pRg);
+}
+
+// weight of strategy t = d + 1 for the path z_0..z_d (camera vertex j of
+// depth d: zc, its parent zp, the camera for d = 1) continued by the
+// light-side vertices Y[0..m-1] = z_{d+1}..z_k (z_k on the emitter)
+__device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
+                                 const IterDev& it, int d, uint32_t j, const PV& zc, const PV& zp,
+                                 const PV* Y, int m, const float* It) {
+  const int k = d + m, t = d + 1;
+  auto Z = [&](int i) -> const PV& { return i == d ? zc : (i == d - 1 ? zp : Y[i - d - 1]); };
+  float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
+      nL[kMaxDepth + 2];
+  float d2;
+  for (int i = d + 1; i <= k; ++i) {
+    const f3 wo = dir_between(Z(i - 1).P, Z(i - 2).P, &d2);
+    const f3 wi = dir_between(Z(i - 1).P, Z(i).P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i - 1).mat), Z(i - 1).ng, wo, wi, &fc, &p);
+    pF[i] = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
+  }
+  pR[k] = Z(k).lpdf;
+  {
+    const f3 w = dir_between(Z(k).P, Z(k - 1).P, &d2);
+    const float cl = dot3(Z(k).ng, w);
+    const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+    pR[k - 1] = (pe * fabsf(dot3(Z(k - 1).ng, w))) / d2;
+  }
+  for (int i = k - 2; i >= d - 1 && i >= 1; --i) {
+    const f3 wo = dir_between(Z(i + 1).P, Z(i + 2).P, &d2);
+    const f3 wi = dir_between(Z(i + 1).P, Z(i).P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i + 1).mat), Z(i + 1).ng, wo, wi, &fc, &p);
+    pR[i] = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
+  }
+  // counts at z_d (its record) and along the light side
+  const VRec rd = load_rec(q, d, j);
+  f3 T = rd.T;
+  float b[3] = {rd.b0, rd.b1, rd.b2};
+  const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
+  for (int i = d; i <= k - 1; ++i) {
+    if (i > d) {
+      const uint32_t cell = cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
+      counts_at(sc, c, it, cell, T, It, i, b);
+    }
+    nB[i] = mis_count(it, b[0]);
+    nN[i] = mis_count(it, b[1]);
+    nL[i] = mis_count(it, b[2]);
+    if (i < k - 1) {
+      const f3 wo = dir_between(Z(i).P, Z(i - 1).P, &d2);
+      const f3 wi = dir_between(Z(i).P, Z(i + 1).P, &d2);
+      f3 fc;
+      float p;
+      eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i).mat), Z(i).ng, wo, wi, &fc, &p);
+      if (p > 0.0f && b[0] > 0.0f)
+        T = mk3(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
+                T.z * (((fc.z / p) * 1.0f) / b[0]));
+      else
+        T = mk3(0.0f, 0.0f, 0.0f);
+    }
+  }
+  auto tf = [&](int tt) -> float {
+    return tt == k + 1 ? 1.0f : (tt == k ? nN[k - 1] : nL[tt - 1]);
+  };
+  const float tft = tf(t);
+  if (!(tft > 0.0f)) return 0.0f;
+  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
+  for (int tt = t + 1; tt <= k + 1; ++tt) {
+    rp = rp * (pF[tt - 1] / pR[tt - 1]);
+    rb = rb * nB[tt - 2];
+    sum = sum + (rp * rb) * (tf(tt) / tft);
+  }
+  // camera side, walking up the parent chain: pF[tt] of vertex tt, pR[tt] of
+  // vertex tt + 2 (tt <= d - 2), counts of vertex tt - 1
+  rp = 1.0f;
+  rb = 1.0f;
+  VRec cur = rd;
+  uint32_t ecur = j;
+  float prg1 = 0.0f, prg2 = 0.0f;
+  for (int tt = d; tt >= 2; --tt) {
+    const float pRt = tt >= d - 1 ? pR[tt] : prg2;
+    const uint32_t epar = ubits(q.S0[(size_t)tt * q.cap + ecur].w);
+    const VRec par = load_rec(q, tt - 1, epar);
+    rp = rp * (pRt / cur.pF);
+    rb = rb * mis_count(it, par.b0);
+    sum = sum + rp * (mis_count(it, par.b2) / (rb * tft));
+    prg2 = prg1;
+    prg1 = cur.pRg;
+    cur = par;
+    ecur = epar;
+  }
+  if (!(sum < INFINITY)) return 0.0f;
+  return 1.0f / sum;
+}
+
 // shadow-entry requests written by the vertex kernel: kind in SH1.x, the
 // camera vertex in SH1.w; NEE: emitter point and triangle in SH0; light
 // path: subpath index and light vertex index in SH0.xy
@@ -1181,6 +1355,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
           T = xyz(q.S0[L + j]);
           counts_at(sc, c, it, cell, T, It, d, beta);
+          bdpt_record(sc, c, q, it, d, j, x, ng, cell, It);
           mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
@@ -1308,7 +1483,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
   const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
   const size_t L = (size_t)d * q.cap;
   uint32_t my_sh = 0, my_conn = 0;
-  PV z[2 * kMaxDepth + 4];
+  PV Y[kMaxDepth + 1];
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     const size_t e = L + s;
     const float4 s0 = q.SH0[e], s1 = q.SH1[e];
@@ -1331,7 +1506,14 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
     const f3 wo = mk3(-dir.x, -dir.y, -dir.z);
     const f3 ov = mk3(x.x + n_s.x * sc.eps, x.y + n_s.y * sc.eps, x.z + n_s.z * sc.eps);
     const Mat mat = load_mat(sc.mats + 8 * (size_t)sc.tri_mat[prim]);
-    camera_prefix(sc, q, d, j, x, ng, prim, dir, z);
+    // the camera vertex and its parent (the camera itself at depth 1)
+    const PV zc = PV{x, ng, sc.tri_mat[prim], ngl.w};
+    PV zp;
+    if (d == 1) {
+      zp = PV{mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]), dir, 0u, 0.0f};
+    } else {
+      zp = hit_vertex(sc, q, d - 1, ubits(q.S0[L + j].w));
+    }
     if (kind == kConnNee) {
       const f3 y = xyz(s0);
       const uint32_t li = ubits(s0.w);
@@ -1347,8 +1529,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
         const float pN = (lng.w * d2) / cl;
-        z[d + 1] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
-        const float wN = bdpt_weight(sc, c, it, z, d + 1, d + 1, It);
+        Y[0] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
+        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It);
         const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
         sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
@@ -1379,11 +1561,11 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
           (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
         for (int jj = 1; jj <= i; ++jj) {
           const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
-          z[d + jj] = prim_vertex(sc, xyz(pv), ubits(pv.w));
+          Y[jj - 1] = prim_vertex(sc, xyz(pv), ubits(pv.w));
         }
         const float4 y0r = lt.Y0[lpi];
-        z[d + i + 1] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
-        const float wc = bdpt_weight(sc, c, it, z, d + 1 + i, d + 1, It);
+        Y[i] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
+        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It);
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;

@@ -72,6 +72,11 @@ struct QueuesDev {
   float4* V1;   // beta_B, beta_N, beta_third, unused
   uint4* V2;    // NEE first, NEE count, continuation first, continuation count
   float4* RO;   // back-propagated secondary estimate, subtree cost (bits)
+  // BDPT camera-vertex records for the full-path MIS weights (null otherwise):
+  // W0 = (throughput of the camera prefix recomputed from positions, raw
+  // BSDF count), W1 = (raw NEE count, raw LP count, pF here, pR two back)
+  float4* W0;
+  float4* W1;
   float4* SH0;  // shadow origin, tmax
   float4* SH1;  // shadow direction, parent vertex (bits)
   float4* SH2;  // unoccluded NEE sample value, flags (1 = traced)

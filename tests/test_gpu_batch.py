@@ -183,7 +183,9 @@ def _floor(roots, e):
 
 
 def _qbytes(scene, cap):
-    return cap * (scene.max_depth + 2) * 216
+    # 216 B per queue entry and level; BDPT adds the 32 B camera-vertex record
+    per = 216 + (32 if scene.mode == orc.MODE_BDPT else 0)
+    return cap * (scene.max_depth + 2) * per
 
 
 def test_autotune_and_cache(ctx, tmp_path):
