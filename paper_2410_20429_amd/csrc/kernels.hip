@@ -41,6 +41,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // connection kernel (statistics atomics only, 78 VGPRs): 512-thread groups,
 // three per CU
 constexpr int kShadeBlock = 1024, kConnectBlock = 512;
+// unidirectional shading: 256-thread groups held to 80 VGPRs (6 waves per
+// SIMD) to hide its dependent loads (octree walk, distribution search)
+constexpr int kShadePtBlock = 256;
 // launch grid for the shading kernels: the thread count of `grid` groups of 256
 inline int shade_grid(int grid) { return grid * 256 / kShadeBlock > 0 ? grid * 256 / kShadeBlock : 1; }
 
@@ -492,10 +495,10 @@ __device__ __forceinline__ void mlp_record(const CacheDev& c, uint2 strm, f3 x, 
 // {B,G} for indirect light; budget-aware multiplies every density by beta.
 // Child throughput T' = T B|cos| / p_t * w_ind,t / beta_t (Sec. 3.1).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kShadeBlock) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
+__global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                        Counters* cnt, IterDev it, ImageDev img,
                                                        DebugRec* dbg, uint32_t dbg_cap, int d) {
-  __shared__ uint32_t alloc_lds[4 * kShadeBlock / 64 + 2];
+  __shared__ uint32_t alloc_lds[4 * kShadePtBlock / 64 + 2];
   if (group_overflowed(cnt)) return;
   const Key key{sc.key0, sc.key1};
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_pt_kernel(SceneDev sc, Cach
     const uint32_t ncont = vert ? gam[0] + gam[2] : 0u, nnee = vert ? gam[1] : 0u;
     // workgroup-level allocation in the next-depth and shadow queues
     uint32_t cfirst, sfirst;
-    group_alloc<kShadeBlock>(ncont, nnee, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
+    group_alloc<kShadePtBlock>(ncont, nnee, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
                              alloc_lds);
     bool ovf = false;
     if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.cap)) {
@@ -694,14 +697,15 @@ __global__ __launch_bounds__(kShadeBlock) void shade_pt_kernel(SceneDev sc, Cach
     }
   }
   // one atomic per wave for the iteration counters
-  group_add<kShadeBlock, 4>({my_vert, my_samp, my_ext, my_sh},
+  group_add<kShadePtBlock, 4>({my_vert, my_samp, my_ext, my_sh},
                             {&cnt->vertices, &cnt->samples, &cnt->rays_ext, &cnt->rays_shadow},
                             alloc_lds);
 }
 void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s) {
-  shade_pt_kernel<<<shade_grid(grid), kShadeBlock, 0, s>>>(sc, c, q, cnt, it, img, dbg, dbg_cap, d);
+  shade_pt_kernel<<<grid * 256 / kShadePtBlock * 6 / 8, kShadePtBlock, 0, s>>>(sc, c, q, cnt, it, img,
+                                                                              dbg, dbg_cap, d);
 }
 
 // ---------------------------------------------------------------------------
