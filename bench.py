@@ -339,9 +339,15 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
+    step_ms = {"graph": [], "pool": []}
+    reruns_pool = []
+
     def graph_steps(i0):
         for k in range(args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
             its, _ = api.iterate_batch(S, params(i0 + k))
+            step_ms["graph"].append(round((time.perf_counter() - t) * 1e3, 1))
             reruns.append(sum(1 for s in its if s.overflow_retries > 0))
 
     def eager_steps(i0):
@@ -352,7 +358,11 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
 
     def pool_steps(i0):
         for k in range(args.steps):
-            api.iterate_batch(E, params(i0 + k), graph=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its, _ = api.iterate_batch(E, params(i0 + k), graph=False)
+            step_ms["pool"].append(round((time.perf_counter() - t) * 1e3, 1))
+            reruns_pool.append(sum(1 for s in its if s.overflow_retries > 0))
 
     dt = timed(lambda: graph_steps(warm))
     ctx.profile(True)
@@ -379,6 +389,7 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
         "stream_pool_ms_per_step": dt_pool * 1e3 / args.steps,
         "graph_speedup_vs_eager": dt_eager / dt,
         "overflow_reruns_per_step": reruns,
+        "step_ms": step_ms, "overflow_reruns_per_step_pool": reruns_pool,
         "eager_kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
     }
     return ctx_out

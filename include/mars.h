@@ -164,13 +164,15 @@ mars_status mars_render_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t n
 /* Batched iteration: the render iteration of each of n distinct scenes and,
  * with MARS_BATCH_UPDATE, its update (as mars_update_counts), every scene's
  * work enqueued without host synchronisation on one stream of a pool
- * (scenes assigned longest-first to the least loaded stream), the whole
- * batch captured once as a HIP graph and replayed by later calls with the
- * same scenes and parameters apart from the iteration index.  The device
+ * (scenes assigned longest-first to the least loaded stream), each scene's
+ * iteration captured once as a HIP graph and the graphs replayed, in the
+ * same order on the same streams, by later calls with the same scenes and
+ * parameters apart from the iteration index.  The device
  * reads the iteration index, the image cost C_I and the number of cells
  * itself.  A scene whose queues overflowed skips its update inside the graph
- * and is rendered (and updated) again on its own with tile halving, so the
- * result always equals the per-scene calls.  Scenes with the learned cache
+ * and is rendered (and updated) again on its own with tile halving (its
+ * tile for later batches unchanged), so the result always equals the
+ * per-scene calls.  Scenes with the learned cache
  * and debug records (p->debug_depth > 0) are refused (MARS_E_ARG).
  * iter_stats / upd_stats: optional host arrays of n.  The graph keeps device
  * pointers of the scenes: mars_scene_configure, mars_set_fixed_counts,

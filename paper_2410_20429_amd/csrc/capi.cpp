@@ -133,7 +133,7 @@ struct Profiler {
 // a captured batch: the key lists everything the launches bake in
 struct BatchGraph {
   std::vector<uint64_t> key;
-  std::vector<hipGraphExec_t> exec;  // one single-chain graph per stream of the pool
+  std::vector<hipGraphExec_t> exec;  // one single-chain graph per scene (batch order)
   int32_t* iter = nullptr;    // device: iteration index read by the kernels
   double* summary = nullptr;  // device: [n][kSumWords]
 };
@@ -478,10 +478,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   s->dbg_last = dbg_total;
   s->peak_per_root = peak;
   // later iterations start from a tile that fitted (tiles do not change results)
-  if (overflowed && ok_tile > 0 && (int)ok_tile < s->tile_roots) {
-    s->tile_roots = (int)ok_tile;
-    s->epoch++;
-  }
+  if (overflowed && ok_tile > 0 && (int)ok_tile < s->tile_roots) s->tile_roots = (int)ok_tile;
   S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = S;
 }
@@ -941,10 +938,7 @@ uint64_t fbits64(float f) {
 
 void configure(Scene* s, size_t cap, int tile) {
   if (cap && cap != s->cap) alloc_queues(s, cap);
-  if (tile > 0 && tile != s->tile_roots) {
-    s->tile_roots = tile;
-    s->epoch++;
-  }
+  if (tile > 0) s->tile_roots = tile;  // part of the graph key, no new epoch needed
 }
 
 void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int flags,
@@ -989,6 +983,8 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
     key.push_back(sc[i]->uid);
     key.push_back(sc[i]->epoch);
     key.push_back((uint64_t)lane[i]);
+    key.push_back((uint64_t)sc[i]->tile_roots);
+    key.push_back((uint64_t)sc[i]->cap);
   }
   BatchGraph* g = nullptr;
   for (auto& e : c->graphs)
@@ -1005,19 +1001,18 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
       ng.iter = (int32_t*)c->dalloc(sizeof(int32_t));
       ng.summary = (double*)c->dalloc((size_t)n * kSumWords * sizeof(double));
       if (use_graph) {
-        // one chain per stream: each lane's scenes captured on its own stream
-        // and launched there, the lanes running side by side
+        // one chain per scene, captured on its stream of the pool; launched
+        // in the batch order, so that every stream gets work at once (a graph
+        // launch submits its kernels one by one on the host)
         IterDev it = to_dev(p);
         it.iter_dev = ng.iter;
-        for (int k = 0; k < K; ++k) {
-          hipStream_t ls = c->pool[k];
+        for (int i : order) {
+          hipStream_t ls = c->pool[lane[i]];
           HIPCHK(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
           hipGraph_t graph = nullptr;
           try {
-            for (int i : order)
-              if (lane[i] == k)
-                enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, ls,
-                                  ng.summary + (size_t)i * kSumWords);
+            enqueue_iteration(sc[i], it, p->spp, with_update, p->stat_clamp, ls,
+                              ng.summary + (size_t)i * kSumWords);
           } catch (...) {
             (void)hipStreamEndCapture(ls, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -1045,7 +1040,8 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
     HIPCHK(hipEventRecord(c->pool_ev[0], st));
     for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(c->pool[k], c->pool_ev[0], 0));
     if (use_graph) {
-      for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(g->exec[k], c->pool[k]));
+      for (size_t o = 0; o < order.size(); ++o)
+        HIPCHK(hipGraphLaunch(g->exec[o], c->pool[lane[order[o]]]));
     } else {
       IterDev it = to_dev(p);
       it.iter_dev = g->iter;
@@ -1068,12 +1064,13 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
     Scene* s = sc[i];
     const double* h = &hs[(size_t)i * kSumWords];
     if (h[0] != 0.0) {
-      // a queue overflowed: this scene again on its own, with tile halving,
-      // and half the tile for later batches (same queue memory; tiles do
-      // not change results)
+      // a queue overflowed: this scene again on its own, with tile halving;
+      // later batches keep its tile (overflows are occasional, and smaller
+      // tiles cost every iteration; tiles do not change results)
+      const int tile0 = s->tile_roots;
       mars_iter_stats S{};
       render_iteration(s, p, &S);
-      configure(s, 0, std::max(1, std::min(s->tile_roots, (int)std::min<size_t>(s->cap, 0x7FFFFFFF)) / 2));
+      s->tile_roots = tile0;
       if (its) its[i] = S;
       if (with_update) {
         mars_update_stats U{};
