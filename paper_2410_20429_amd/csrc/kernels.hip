@@ -406,12 +406,159 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
     if (smax) atomicMax(tc + 7, (unsigned long long)smax);
   }
 }
+constexpr int kStreamBlocksPerCU = 12;
+
+// Streaming traversal of the same rays: every loop iteration is one node
+// visit, and a lane whose ray has ended takes its next ray (rays j, j + G,
+// j + 2G, ... of the launch, no atomics) while the other lanes of its wave
+// keep traversing, so a wave is not held by its slowest ray once the queues
+// are longer than the lanes resident.  Same node visit, same tests, same
+// results as traverse().
+__global__ __launch_bounds__(kTraceBlock) void trace_stream_kernel(SceneDev sc, QueuesDev q,
+                                                                   const Counters* cnt, int dc,
+                                                                   int ds) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  if (cnt->overflow) return;
+  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
+  const uint32_t total = nc + ns;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+  const uint32_t G = gridDim.x * blockDim.x;
+  const int lane = threadIdx.x;
+  const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t next = (uint32_t)gtid, cur = 0;
+  bool has = false, any = false;
+  RayInv ri{};
+  f3 o = mk3(0, 0, 0), dir = mk3(0, 0, 0);
+  float tmax = 0.0f, bt = 0.0f, vw = 0.0f;
+  uint32_t bp = kMiss;
+  int sp = 0, node = 0;
+  auto push = [&](int v) {
+    if (sp < kStackDepth) stk[sp * kTraceBlock + lane] = v;
+    else sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid] = v;
+    ++sp;
+  };
+  while (true) {
+    // a lane without a ray takes its next one (rays that need no tracing are
+    // settled on the way)
+    while (!has && next < total) {
+      cur = next;
+      next += G;
+      if (cur < nc) {
+        const float4 r0 = q.R0[Lc + cur];
+        if (r0.w == 0.0f) {
+          q.H[Lc + cur] = make_uint2(ubits(INFINITY), kMiss);
+          continue;
+        }
+        const float4 r1 = q.R1[Lc + cur];
+        o = xyz(r0);
+        dir = xyz(r1);
+        tmax = INFINITY;
+        any = false;
+      } else {
+        const uint32_t k = cur - nc;
+        const float4 v = q.SH2[Ls + k];
+        if (v.w == 0.0f) continue;
+        const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
+        o = xyz(a);
+        dir = xyz(b);
+        tmax = a.w;
+        vw = v.w;
+        any = true;
+      }
+      ri = ray_inv(o, dir);
+      bt = tmax;
+      bp = kMiss;
+      sp = 0;
+      node = 0;
+      has = true;
+    }
+    if (!__any(has)) break;
+    if (!has) continue;
+    // one node visit
+    const float4* N = sc.bvh + (size_t)node * 8;
+    const float4 lx = N[0], ly = N[1], lz = N[2], hx = N[3], hy = N[4], hz = N[5];
+    const float4 rf = N[6];
+    int r0 = (int)ubits(rf.x), r1 = (int)ubits(rf.y), r2 = (int)ubits(rf.z), r3 = (int)ubits(rf.w);
+    float t0 = box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
+    float t1 = box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
+    float t2 = box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
+    float t3 = box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
+    t0 = r0 == kBvhNoChild ? INFINITY : t0;
+    t1 = r1 == kBvhNoChild ? INFINITY : t1;
+    t2 = r2 == kBvhNoChild ? INFINITY : t2;
+    t3 = r3 == kBvhNoChild ? INFINITY : t3;
+    bool occluded = false;
+#pragma unroll
+    for (int side = 0; side < 4; ++side) {
+      const int ch = side == 0 ? r0 : side == 1 ? r1 : side == 2 ? r2 : r3;
+      const float tn = side == 0 ? t0 : side == 1 ? t1 : side == 2 ? t2 : t3;
+      if (ch < 0 && tn != INFINITY && !occluded) {
+        const uint32_t code = (uint32_t)(-1 - ch);
+        const uint32_t first = code >> 4, count = code & 15u;
+        for (uint32_t kk = first; kk < first + count; ++kk) {
+          const float4* T = sc.tri_bvh + (size_t)kk * 3;
+          const float4 A = T[0];
+          float t;
+          if (!tri_hit(o, dir, A, T[1], T[2], &t)) continue;
+          if (!(t > 0.0f && t < tmax)) continue;
+          const uint32_t prim = ubits(A.w);
+          if (any) {
+            occluded = true;
+            break;
+          }
+          if (t < bt || (t == bt && prim < bp)) {
+            bt = t;
+            bp = prim;
+          }
+        }
+      }
+    }
+    bool done = occluded;
+    if (!done) {
+      if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
+      if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
+      if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
+      if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
+      cswap(t0, r0, t1, r1);
+      cswap(t2, r2, t3, r3);
+      cswap(t0, r0, t2, r2);
+      cswap(t1, r1, t3, r3);
+      cswap(t1, r1, t2, r2);
+      if (t0 != INFINITY) {
+        if (t3 != INFINITY) push(r3);
+        if (t2 != INFINITY) push(r2);
+        if (t1 != INFINITY) push(r1);
+        node = r0;
+      } else if (sp == 0) {
+        done = true;
+      } else {
+        --sp;
+        node = sp < kStackDepth ? stk[sp * kTraceBlock + lane]
+                                : sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid];
+      }
+    }
+    if (done) {
+      if (!any)
+        q.H[Lc + cur] = bp != kMiss ? make_uint2(ubits(bt), bp) : make_uint2(ubits(INFINITY), kMiss);
+      else if (occluded)
+        q.SH2[Ls + (cur - nc)] = make_float4(0.0f, 0.0f, 0.0f, vw);
+      has = false;
+    }
+  }
+}
+
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
-                  int grid, hipStream_t s, unsigned long long* tc) {
+                  int grid, hipStream_t s, unsigned long long* tc, bool stream) {
   // the spill area has one column per thread of the launch
   if (sc.stack_spill) grid = std::min(grid, (int)(sc.spill_threads / kTraceBlock));
+  // instrumented runs count node visits per ray with the per-ray loop
   if (tc) trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
-  else trace_pair_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, nullptr);
+  else if (!stream) trace_pair_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, nullptr);
+  // rays are assigned statically to lanes: launch exactly the groups that
+  // are resident (75 VGPRs: 6 waves per SIMD, 12 groups of 2 waves per CU)
+  else trace_stream_kernel<<<std::max(1, grid * kStreamBlocksPerCU / kTraceBlocksPerCU), kTraceBlock,
+                             0, s>>>(sc, q, cnt, dc, ds);
 }
 
 // ---------------------------------------------------------------------------
