@@ -496,7 +496,7 @@ def main():
         st, _ = step(args.warmup + args.steps)
         tc = ctx.trace_counts()
         ctx.trace_counting(False)
-        # per ray: I/O plus one 64 B node per visited node and 48 B per tested triangle
+        # per ray: I/O plus one 128 B node per visited node and 48 B per tested triangle
         bpr_c = BYTES_RAY_IO + (BYTES_NODE * tc[1] + BYTES_TRI * tc[2]) / max(tc[0], 1)
         bpr_s = BYTES_SHADOW_IO + (BYTES_NODE * tc[4] + BYTES_TRI * tc[5]) / max(tc[3], 1)
         ms_tr, n_tr = prof["trace"]

@@ -332,13 +332,6 @@ void alloc_queues(Scene* s, size_t cap) {
 // bytes of queue memory per entry of one level
 constexpr size_t kQueueEntryBytes = 13 * 16 + 8;
 
-// streaming traversal when the rays of a launch outnumber the lanes resident:
-// BDPT (connections multiply the shadow queues) or tiles above that size
-bool stream_trace(const Scene* s, size_t tile) {
-  return s->mode == MARS_MODE_BDPT ||
-         tile > (size_t)s->ctx->cu * (size_t)kTraceBlocksPerCU * (size_t)kTraceBlock;
-}
-
 // BDPT: one light subpath per camera sample of the iteration, before any
 // camera tile (connections may use any sample's subpath)
 uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
@@ -351,7 +344,7 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
     const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
     timed(c, KID_LIGHT, [&] { k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st); });
     for (int i = 1; i <= s->lt.lmax; ++i) {
-      timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc, true); });
+      timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc); });
       timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st); });
     }
   }
@@ -373,8 +366,7 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   if (dbg0) h2d(&s->cnt->n_debug, &dbg0, 4, st);  // debug records accumulate across tiles
   timed(c, KID_RAYGEN, [&] { k_raygen(s->sd, s->qd, s->cnt, it, root0, n, st); });
-  const bool strm = stream_trace(s, n);
-  timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc, strm); });
+  timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc); });
   for (int d = 1; d <= s->max_depth; ++d) {
     if (it.alloc == MARS_ALLOC_MLP && d < s->max_depth)
       timed(c, KID_MLP, [&] { k_mlp_infer_queue(s->sd, s->qd, s->mlp, s->cnt, d, grid * 4, st); });
@@ -387,7 +379,7 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
     });
     // shadow rays of depth d with the continuation rays of depth d + 1
     const int dc = d < s->max_depth ? d + 1 : -1;
-    timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc, strm); });
+    timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc); });
   }
   d2h(hc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));
@@ -884,7 +876,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
       const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
       k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st);
       for (int i = 1; i <= s->lt.lmax; ++i) {
-        k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc, true);
+        k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc);
         k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st);
       }
     }
@@ -894,15 +886,14 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
     const uint32_t n = (uint32_t)std::min(tile, roots - r0);
     k_fill_u32((uint32_t*)s->cnt, 0u, kTileWords, st);
     k_raygen(s->sd, s->qd, s->cnt, it, (uint32_t)r0, n, st);
-    const bool strm = stream_trace(s, n);
-    k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc, strm);
+      k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc);
     for (int d = 1; d <= s->max_depth; ++d) {
       if (bdpt)
         k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, nullptr, 0, d, (uint32_t)roots,
                      grid, st);
       else
         k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, nullptr, 0, d, grid, st);
-      k_trace_pair(s->sd, s->qd, s->cnt, d < s->max_depth ? d + 1 : -1, d, grid_trace, st, tc, strm);
+      k_trace_pair(s->sd, s->qd, s->cnt, d < s->max_depth ? d + 1 : -1, d, grid_trace, st, tc);
     }
     for (int d = s->max_depth; d >= 1; --d) {
       if (bdpt)

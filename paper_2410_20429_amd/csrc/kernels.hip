@@ -190,11 +190,12 @@ void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterD
 }
 
 // ---------------------------------------------------------------------------
-// BVH traversal.  Node: two child boxes + two child references (>= 0 inner
-// node, < 0 leaf = -1 - (first << 4 | count)).  Per-lane stack in LDS,
-// column-major so that lanes of a wave hit distinct banks.  Leaf children
-// are intersected as soon as their box is hit; the nearer inner child is
-// visited first.
+// BVH traversal.  Node (128 B): four child boxes as SoA float4s and four
+// child references (>= 0 inner node, < 0 leaf = -1 - (first << 4 | count),
+// kBvhNoChild unused).  Leaf children are intersected as soon as their box
+// is hit; the nearest inner child is visited next and the others are pushed.
+// traverse() is the one-lane form (instrumented runs count node visits with
+// it); traverse_quad() is the four-lane form every other launch uses.
 // ---------------------------------------------------------------------------
 struct RayInv {
   float ix, iy, iz, ox, oy, oz;
@@ -406,159 +407,190 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
     if (smax) atomicMax(tc + 7, (unsigned long long)smax);
   }
 }
-constexpr int kStreamBlocksPerCU = 12;
+// ---------------------------------------------------------------------------
+// Quad traversal: four lanes per ray.  Lane s of a quad loads and tests
+// child s of the node; the quad's four (entry distance, reference) pairs are
+// gathered into every lane with quad permutes and sorted alike, so all four
+// lanes take the decisions of traverse(): the same visit order, the same
+// stack and the same result.  The triangles of a hit leaf are dealt
+// round-robin to the four lanes and the quad's closest hit is reduced in the
+// (t, primitive index) order, which is the order traverse() keeps.  Every
+// branch below is taken alike by the four lanes of a quad (their inputs are
+// quad-uniform), except the per-lane triangle loop, which closes before the
+// reductions, so the permutes never read a lane of the quad that is off.
+// ---------------------------------------------------------------------------
+constexpr int kQuadsPerBlock = kTraceBlock / 4;
+constexpr int kQuadStack = 4 * kStackDepth;      // LDS entries per ray
+constexpr int kQuadStride = kQuadsPerBlock + 1;  // padded: a quad's pushes hit distinct banks
 
-// Streaming traversal of the same rays: every loop iteration is one node
-// visit, and a lane whose ray has ended takes its next ray (rays j, j + G,
-// j + 2G, ... of the launch, no atomics) while the other lanes of its wave
-// keep traversing, so a wave is not held by its slowest ray once the queues
-// are longer than the lanes resident.  Same node visit, same tests, same
-// results as traverse().
-__global__ __launch_bounds__(kTraceBlock) void trace_stream_kernel(SceneDev sc, QueuesDev q,
-                                                                   const Counters* cnt, int dc,
-                                                                   int ds) {
-  __shared__ int stk[kStackDepth * kTraceBlock];
-  if (cnt->overflow) return;
-  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
-  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
-  const uint32_t total = nc + ns;
-  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
-  const uint32_t G = gridDim.x * blockDim.x;
-  const int lane = threadIdx.x;
-  const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t next = (uint32_t)gtid, cur = 0;
-  bool has = false, any = false;
-  RayInv ri{};
-  f3 o = mk3(0, 0, 0), dir = mk3(0, 0, 0);
-  float tmax = 0.0f, bt = 0.0f, vw = 0.0f;
+template <int k>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, k * 0x55, 0xF, 0xF, false);
+}
+template <int k>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(quad_bcast<k>(__float_as_int(v)));
+}
+// value of lane (s ^ m) of the quad
+template <int m>
+__device__ __forceinline__ int quad_xor(int v) {
+  return __builtin_amdgcn_mov_dpp(v, m == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+// (t, primitive) minimum over the quad: smaller t, ties by smaller index
+__device__ __forceinline__ void quad_min_hit(float& t, uint32_t& p) {
+  float t2 = __int_as_float(quad_xor<1>(__float_as_int(t)));
+  uint32_t p2 = (uint32_t)quad_xor<1>((int)p);
+  if (t2 < t || (t2 == t && p2 < p)) { t = t2; p = p2; }
+  t2 = __int_as_float(quad_xor<2>(__float_as_int(t)));
+  p2 = (uint32_t)quad_xor<2>((int)p);
+  if (t2 < t || (t2 == t && p2 < p)) { t = t2; p = p2; }
+}
+__device__ __forceinline__ bool quad_any(bool b) {
+  int v = b ? 1 : 0;
+  v |= quad_xor<1>(v);
+  v |= quad_xor<2>(v);
+  return v != 0;
+}
+
+template <bool kAny>
+__device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
+                                              int sub, int qcol, size_t qid, float* bt_out,
+                                              uint32_t* bp_out) {
+  const RayInv ri = ray_inv(o, d);
+  float bt = tmax;
   uint32_t bp = kMiss;
-  int sp = 0, node = 0;
-  auto push = [&](int v) {
-    if (sp < kStackDepth) stk[sp * kTraceBlock + lane] = v;
-    else sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid] = v;
-    ++sp;
-  };
+  int sp = 0;
+  int node = 0;
   while (true) {
-    // a lane without a ray takes its next one (rays that need no tracing are
-    // settled on the way)
-    while (!has && next < total) {
-      cur = next;
-      next += G;
-      if (cur < nc) {
-        const float4 r0 = q.R0[Lc + cur];
-        if (r0.w == 0.0f) {
-          q.H[Lc + cur] = make_uint2(ubits(INFINITY), kMiss);
-          continue;
-        }
-        const float4 r1 = q.R1[Lc + cur];
-        o = xyz(r0);
-        dir = xyz(r1);
-        tmax = INFINITY;
-        any = false;
-      } else {
-        const uint32_t k = cur - nc;
-        const float4 v = q.SH2[Ls + k];
-        if (v.w == 0.0f) continue;
-        const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
-        o = xyz(a);
-        dir = xyz(b);
-        tmax = a.w;
-        vw = v.w;
-        any = true;
-      }
-      ri = ray_inv(o, dir);
-      bt = tmax;
-      bp = kMiss;
-      sp = 0;
-      node = 0;
-      has = true;
-    }
-    if (!__any(has)) break;
-    if (!has) continue;
-    // one node visit
-    const float4* N = sc.bvh + (size_t)node * 8;
-    const float4 lx = N[0], ly = N[1], lz = N[2], hx = N[3], hy = N[4], hz = N[5];
-    const float4 rf = N[6];
-    int r0 = (int)ubits(rf.x), r1 = (int)ubits(rf.y), r2 = (int)ubits(rf.z), r3 = (int)ubits(rf.w);
-    float t0 = box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
-    float t1 = box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
-    float t2 = box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
-    float t3 = box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
-    t0 = r0 == kBvhNoChild ? INFINITY : t0;
-    t1 = r1 == kBvhNoChild ? INFINITY : t1;
-    t2 = r2 == kBvhNoChild ? INFINITY : t2;
-    t3 = r3 == kBvhNoChild ? INFINITY : t3;
-    bool occluded = false;
+    // child `sub` of the node: its box bounds and reference (SoA node layout)
+    const float* N = reinterpret_cast<const float*>(sc.bvh + (size_t)node * 8) + sub;
+    const float lx = N[0], ly = N[4], lz = N[8], hx = N[12], hy = N[16], hz = N[20];
+    const int rs = __float_as_int(N[24]);
+    float ts = box_near(ri, lx, ly, lz, hx, hy, hz, bt);
+    ts = rs == kBvhNoChild ? INFINITY : ts;
+    float t0 = quad_bcast<0>(ts), t1 = quad_bcast<1>(ts), t2 = quad_bcast<2>(ts),
+          t3 = quad_bcast<3>(ts);
+    int r0 = quad_bcast<0>(rs), r1 = quad_bcast<1>(rs), r2 = quad_bcast<2>(rs),
+        r3 = quad_bcast<3>(rs);
 #pragma unroll
     for (int side = 0; side < 4; ++side) {
       const int ch = side == 0 ? r0 : side == 1 ? r1 : side == 2 ? r2 : r3;
       const float tn = side == 0 ? t0 : side == 1 ? t1 : side == 2 ? t2 : t3;
-      if (ch < 0 && tn != INFINITY && !occluded) {
+      if (ch < 0 && tn != INFINITY) {
         const uint32_t code = (uint32_t)(-1 - ch);
         const uint32_t first = code >> 4, count = code & 15u;
-        for (uint32_t kk = first; kk < first + count; ++kk) {
-          const float4* T = sc.tri_bvh + (size_t)kk * 3;
+        float ht = INFINITY;
+        uint32_t hp = kMiss;
+        bool hit = false;
+        for (uint32_t k = first + (uint32_t)sub; k < first + count; k += 4) {
+          const float4* T = sc.tri_bvh + (size_t)k * 3;
           const float4 A = T[0];
           float t;
-          if (!tri_hit(o, dir, A, T[1], T[2], &t)) continue;
+          if (!tri_hit(o, d, A, T[1], T[2], &t)) continue;
           if (!(t > 0.0f && t < tmax)) continue;
           const uint32_t prim = ubits(A.w);
-          if (any) {
-            occluded = true;
+          if (kAny) {
+            hit = true;
+            ht = t;
+            hp = prim;
             break;
           }
-          if (t < bt || (t == bt && prim < bp)) {
-            bt = t;
-            bp = prim;
+          if (t < ht || (t == ht && prim < hp)) {
+            ht = t;
+            hp = prim;
+          }
+        }
+        if (kAny) {
+          if (quad_any(hit)) {
+            *bt_out = ht;
+            *bp_out = hp;
+            return true;
+          }
+        } else {
+          quad_min_hit(ht, hp);
+          if (ht < bt || (ht == bt && hp < bp)) {
+            bt = ht;
+            bp = hp;
           }
         }
       }
     }
-    bool done = occluded;
-    if (!done) {
-      if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
-      if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
-      if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
-      if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
-      cswap(t0, r0, t1, r1);
-      cswap(t2, r2, t3, r3);
-      cswap(t0, r0, t2, r2);
-      cswap(t1, r1, t3, r3);
-      cswap(t1, r1, t2, r2);
-      if (t0 != INFINITY) {
-        if (t3 != INFINITY) push(r3);
-        if (t2 != INFINITY) push(r2);
-        if (t1 != INFINITY) push(r1);
-        node = r0;
-      } else if (sp == 0) {
-        done = true;
-      } else {
-        --sp;
-        node = sp < kStackDepth ? stk[sp * kTraceBlock + lane]
-                                : sc.stack_spill[(size_t)(sp - kStackDepth) * sc.spill_threads + gtid];
+    if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
+    if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
+    if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
+    if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
+    cswap(t0, r0, t1, r1);
+    cswap(t2, r2, t3, r3);
+    cswap(t0, r0, t2, r2);
+    cswap(t1, r1, t3, r3);
+    cswap(t1, r1, t2, r2);
+    if (t0 != INFINITY) {
+      // the hit children other than the nearest, far first: r_s goes to
+      // sp + k - s, written by lane s
+      const int k = (t1 != INFINITY ? 1 : 0) + (t2 != INFINITY ? 1 : 0) + (t3 != INFINITY ? 1 : 0);
+      if (sub >= 1 && sub <= k) {
+        const int pos = sp + k - sub;
+        const int v = sub == 1 ? r1 : sub == 2 ? r2 : r3;
+        if (pos < kQuadStack) stk[pos * kQuadStride + qcol] = v;
+        else sc.stack_spill[(size_t)(pos - kQuadStack) * sc.spill_threads + qid] = v;
       }
+      sp += k;
+      node = r0;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = sp < kQuadStack ? stk[sp * kQuadStride + qcol]
+                             : sc.stack_spill[(size_t)(sp - kQuadStack) * sc.spill_threads + qid];
     }
-    if (done) {
-      if (!any)
-        q.H[Lc + cur] = bp != kMiss ? make_uint2(ubits(bt), bp) : make_uint2(ubits(INFINITY), kMiss);
-      else if (occluded)
-        q.SH2[Ls + (cur - nc)] = make_float4(0.0f, 0.0f, 0.0f, vw);
-      has = false;
+  }
+  *bt_out = bt;
+  *bp_out = bp;
+  return bp != kMiss;
+}
+
+// The rays of trace_pair_kernel, one quad per ray (rays q, q + Q, ... for
+// quad q of Q); lane 0 of the quad writes the result.
+__global__ __launch_bounds__(kTraceBlock) void trace_quad_kernel(SceneDev sc, QueuesDev q,
+                                                                 const Counters* cnt, int dc,
+                                                                 int ds) {
+  __shared__ int stk[kQuadStack * kQuadStride];
+  if (cnt->overflow) return;
+  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+  const int sub = threadIdx.x & 3, qcol = threadIdx.x >> 2;
+  const size_t qid = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const uint32_t Q = gridDim.x * (blockDim.x >> 2);
+  for (uint32_t j = (uint32_t)qid; j < nc + ns; j += Q) {
+    float t;
+    uint32_t p;
+    if (j < nc) {
+      const float4 r0 = q.R0[Lc + j];
+      uint2 h = make_uint2(ubits(INFINITY), kMiss);
+      if (r0.w != 0.0f) {
+        const float4 r1 = q.R1[Lc + j];
+        if (traverse_quad<false>(sc, xyz(r0), xyz(r1), INFINITY, stk, sub, qcol, qid, &t, &p))
+          h = make_uint2(ubits(t), p);
+      }
+      if (sub == 0) q.H[Lc + j] = h;
+    } else {
+      const uint32_t k = j - nc;
+      const float4 v = q.SH2[Ls + k];
+      if (v.w == 0.0f) continue;
+      const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
+      if (traverse_quad<true>(sc, xyz(a), xyz(b), a.w, stk, sub, qcol, qid, &t, &p) && sub == 0)
+        q.SH2[Ls + k] = make_float4(0.0f, 0.0f, 0.0f, v.w);
     }
   }
 }
 
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
-                  int grid, hipStream_t s, unsigned long long* tc, bool stream) {
+                  int grid, hipStream_t s, unsigned long long* tc) {
   // the spill area has one column per thread of the launch
   if (sc.stack_spill) grid = std::min(grid, (int)(sc.spill_threads / kTraceBlock));
-  // instrumented runs count node visits per ray with the per-ray loop
+  // instrumented runs count node visits per ray with the one-lane loop
   if (tc) trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
-  else if (!stream) trace_pair_kernel<false><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, nullptr);
-  // rays are assigned statically to lanes: launch exactly the groups that
-  // are resident (75 VGPRs: 6 waves per SIMD, 12 groups of 2 waves per CU)
-  else trace_stream_kernel<<<std::max(1, grid * kStreamBlocksPerCU / kTraceBlocksPerCU), kTraceBlock,
-                             0, s>>>(sc, q, cnt, dc, ds);
+  else trace_quad_kernel<<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds);
 }
 
 // ---------------------------------------------------------------------------

@@ -178,8 +178,7 @@ void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterD
 // nodes, triangles} of closest-hit rays at tc[0..2], shadow rays at tc[3..5]
 // stream: the streaming traversal (queues longer than the lanes resident)
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
-                  int grid, hipStream_t s, unsigned long long* tc,
-                  bool stream);
+                  int grid, hipStream_t s, unsigned long long* tc);
 void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s);
