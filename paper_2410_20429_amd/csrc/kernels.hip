@@ -674,9 +674,66 @@ __device__ __forceinline__ void mlp_record(const CacheDev& c, uint2 strm, f3 x, 
 // {B,G} for indirect light; budget-aware multiplies every density by beta.
 // Child throughput T' = T B|cos| / p_t * w_ind,t / beta_t (Sec. 3.1).
 // ---------------------------------------------------------------------------
+// Vertex state shared with the sample phase of shade_pt_kernel (SoA, one
+// column per thread of the group) and the group's inclusive prefix sums of
+// its NEE, BSDF and guided sample counts.
+struct ShadeVerts {
+  float ov[3][kShadePtBlock], ns[3][kShadePtBlock], wo[3][kShadePtBlock], T[3][kShadePtBlock],
+      beta[3][kShadePtBlock];
+  uint32_t s0[kShadePtBlock], s1[kShadePtBlock], cell[kShadePtBlock], mat[kShadePtBlock],
+      j[kShadePtBlock], root[kShadePtBlock], sfirst[kShadePtBlock], cfirst[kShadePtBlock];
+  uint32_t pre[3][kShadePtBlock];
+};
+
+// inclusive prefix sums over the group of three per-thread counts, into
+// pre[0..2][thread]; lds: 3 * kThreads / 64 words.  Every thread must call it.
+template <int kThreads>
+__device__ __forceinline__ void group_scan3(uint32_t a, uint32_t b, uint32_t c,
+                                            uint32_t (&pre)[3][kThreads], uint32_t* lds) {
+  constexpr int kW = kThreads / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t ia = wave_scan_incl(a), ib = wave_scan_incl(b), ic = wave_scan_incl(c);
+  if (lane == 63) {
+    lds[wid] = ia;
+    lds[kW + wid] = ib;
+    lds[2 * kW + wid] = ic;
+  }
+  __syncthreads();
+  uint32_t oa = 0, ob = 0, oc = 0;
+  for (int w = 0; w < wid; ++w) {
+    oa += lds[w];
+    ob += lds[kW + w];
+    oc += lds[2 * kW + w];
+  }
+  pre[0][threadIdx.x] = oa + ia;
+  pre[1][threadIdx.x] = ob + ib;
+  pre[2][threadIdx.x] = oc + ic;
+  __syncthreads();
+}
+
+// the thread (vertex) that owns sample i of the group: the first v with
+// pre[v] > i, and the sample's index among that vertex's samples
+template <int kThreads>
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* pre, uint32_t i, uint32_t* k) {
+  int lo = 0, hi = kThreads - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (i < pre[mid]) hi = mid; else lo = mid + 1;
+  }
+  *k = i - (lo > 0 ? pre[lo - 1] : 0u);
+  return (uint32_t)lo;
+}
+
+// Unidirectional shading of depth d.  Vertex phase, one thread per queue
+// entry: emission, cell, counts, rounding, queue allocation.  Sample phase:
+// the group's NEE, BSDF and guided samples are dealt to its threads, one
+// sample per thread at a time, so that a vertex that splits into many samples
+// does not hold its wave; each sample computes exactly what it would on its
+// vertex's thread and writes the same queue slot.
 __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void shade_pt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                        Counters* cnt, IterDev it, ImageDev img,
                                                        DebugRec* dbg, uint32_t dbg_cap, int d) {
+  __shared__ ShadeVerts sv;
   __shared__ uint32_t alloc_lds[4 * kShadePtBlock / 64 + 2];
   if (group_overflowed(cnt)) return;
   const Key key{sc.key0, sc.key1};
@@ -754,39 +811,54 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
       atomicMax(&cnt->overflow, 1u);
       atomicMax(&cnt->overflow_any, 1u);
     }
-    if (!active) continue;
-    q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
-    q.V1[L + j] = make_float4(beta[0], beta[1], beta[2], 0.0f);
-    q.V2[L + j] = ovf ? make_uint4(0, 0, 0, 0) : make_uint4(sfirst, nnee, cfirst, ncont);
-    if (d == 1) {
-      img.beta1[3 * (size_t)root] = beta[0];
-      img.beta1[3 * (size_t)root + 1] = beta[1];
-      img.beta1[3 * (size_t)root + 2] = beta[2];
-    }
-    if (!vert || ovf) continue;
-    ++my_vert;
-    my_samp += gam[0] + gam[1] + gam[2];
-    if (d <= it.debug_depth && dbg) {
-      const uint32_t k = atomicAdd(&cnt->n_debug, 1u);
-      if (k < dbg_cap) {
-        DebugRec r;
-        r.root = root; r.depth = (uint32_t)d; r.stream_lo = strm.x; r.stream_hi = strm.y;
-        r.cell = cell;
-        for (int t = 0; t < 3; ++t) { r.beta[t] = beta[t]; r.gamma[t] = gam[t]; }
-        r.T[0] = T.x; r.T[1] = T.y; r.T[2] = T.z;
-        dbg[k] = r;
+    const bool live = active && vert && !ovf;
+    if (active) {
+      q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
+      q.V1[L + j] = make_float4(beta[0], beta[1], beta[2], 0.0f);
+      q.V2[L + j] = ovf ? make_uint4(0, 0, 0, 0) : make_uint4(sfirst, nnee, cfirst, ncont);
+      if (d == 1) {
+        img.beta1[3 * (size_t)root] = beta[0];
+        img.beta1[3 * (size_t)root + 1] = beta[1];
+        img.beta1[3 * (size_t)root + 2] = beta[2];
       }
     }
-    const float* m = sc.mats + 8 * (size_t)sc.tri_mat[prim];
-    const Mat mat = load_mat(m);
-    const float* pmf = c.pm + 64 * (size_t)cell;
-    const float* cdf = c.cdf + 64 * (size_t)cell;
-    const float bB = it.aware ? beta[0] : (beta[0] > 0.0f ? 1.0f : 0.0f);
-    const float bN = it.aware ? beta[1] : (beta[1] > 0.0f ? 1.0f : 0.0f);
-    const float bG = it.aware ? beta[2] : (beta[2] > 0.0f ? 1.0f : 0.0f);
+    if (live) {
+      ++my_vert;
+      my_samp += gam[0] + gam[1] + gam[2];
+      if (d <= it.debug_depth && dbg) {
+        const uint32_t k = atomicAdd(&cnt->n_debug, 1u);
+        if (k < dbg_cap) {
+          DebugRec r;
+          r.root = root; r.depth = (uint32_t)d; r.stream_lo = strm.x; r.stream_hi = strm.y;
+          r.cell = cell;
+          for (int t = 0; t < 3; ++t) { r.beta[t] = beta[t]; r.gamma[t] = gam[t]; }
+          r.T[0] = T.x; r.T[1] = T.y; r.T[2] = T.z;
+          dbg[k] = r;
+        }
+      }
+      const int t = threadIdx.x;
+      sv.ov[0][t] = ov.x; sv.ov[1][t] = ov.y; sv.ov[2][t] = ov.z;
+      sv.ns[0][t] = n_s.x; sv.ns[1][t] = n_s.y; sv.ns[2][t] = n_s.z;
+      sv.wo[0][t] = wo.x; sv.wo[1][t] = wo.y; sv.wo[2][t] = wo.z;
+      sv.T[0][t] = T.x; sv.T[1][t] = T.y; sv.T[2][t] = T.z;
+      sv.beta[0][t] = beta[0]; sv.beta[1][t] = beta[1]; sv.beta[2][t] = beta[2];
+      sv.s0[t] = strm.x; sv.s1[t] = strm.y;
+      sv.cell[t] = cell;
+      sv.mat[t] = sc.tri_mat[prim];
+      sv.j[t] = j;
+      sv.root[t] = root;
+      sv.sfirst[t] = sfirst;
+      sv.cfirst[t] = cfirst;
+    }
+    group_scan3<kShadePtBlock>(live ? gam[1] : 0u, live ? gam[0] : 0u, live ? gam[2] : 0u, sv.pre,
+                               alloc_lds);
+    const uint32_t nN = sv.pre[0][kShadePtBlock - 1], nB = sv.pre[1][kShadePtBlock - 1],
+                   nG = sv.pre[2][kShadePtBlock - 1];
     // NEE: light by power, uniform point on the triangle
-    for (uint32_t k = 0; k < gam[1]; ++k) {
-      const uint2 ss = stream_child(key, strm, 1u, k, (uint32_t)d);
+    for (uint32_t i = threadIdx.x; i < nN; i += kShadePtBlock) {
+      uint32_t k;
+      const uint32_t v = owner_of<kShadePtBlock>(sv.pre[0], i, &k);
+      const uint2 ss = stream_child(key, make_uint2(sv.s0[v], sv.s1[v]), 1u, k, (uint32_t)d);
       const float4 u = draw4(key, ss, 1);
       int lo = 0, hi = sc.n_lights - 1;
       while (lo < hi) {
@@ -800,19 +872,26 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
       const float a = su * (1.0f - u.z), b = su * u.z;
       const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
                        (v0.z + a * e1.z) + b * e2.z);
-      const f3 dv = sub3(y, ov);
+      const f3 vo = mk3(sv.ov[0][v], sv.ov[1][v], sv.ov[2][v]);
+      const f3 dv = sub3(y, vo);
       const float d2 = dot3(dv, dv);
       const float dist = sqrtf(d2);
       const f3 w = scl3(dv, 1.0f / dist);
       const float4 lng = sc.tri_ng[lt];
       const float cl = -dot3(w, xyz(lng));
+      const Mat mat = load_mat(sc.mats + 8 * (size_t)sv.mat[v]);
       f3 fc;
       float pB;
-      eval_bsdf(mat, n_s, wo, w, &fc, &pB);
+      eval_bsdf(mat, mk3(sv.ns[0][v], sv.ns[1][v], sv.ns[2][v]),
+                mk3(sv.wo[0][v], sv.wo[1][v], sv.wo[2][v]), w, &fc, &pB);
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+        const float b0 = sv.beta[0][v], b1 = sv.beta[1][v], b2 = sv.beta[2][v];
+        const float bB = it.aware ? b0 : (b0 > 0.0f ? 1.0f : 0.0f);
+        const float bN = it.aware ? b1 : (b1 > 0.0f ? 1.0f : 0.0f);
+        const float bG = it.aware ? b2 : (b2 > 0.0f ? 1.0f : 0.0f);
         const float pN = (lng.w * d2) / cl;
-        const float pG = guided ? guided_density(pmf, w) : 0.0f;
+        const float pG = guided ? guided_density(c.pm + 64 * (size_t)sv.cell[v], w) : 0.0f;
         const float nb = bB * pB, nn = bN * pN, ngd = bG * pG;
         const float ddir = (nb + ngd) + nn;
         const float wN = ddir > 0.0f ? nn / ddir : 0.0f;
@@ -821,59 +900,80 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
         ++my_sh;
       }
-      const size_t e = L + sfirst + k;
-      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
-      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      const size_t e = L + sv.sfirst[v] + k;
+      q.SH0[e] = make_float4(vo.x, vo.y, vo.z, dist * (1.0f - 1e-3f));
+      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(sv.j[v]));
       q.SH2[e] = sh2;
     }
-    // continuation: BSDF samples then guided samples
-    uint32_t slot = 0;
+    // continuation: BSDF samples (slots 0..) then guided samples (after the
+    // vertex's BSDF samples)
     for (int tech = 0; tech < 3; tech += 2) {
-      for (uint32_t k = 0; k < gam[tech]; ++k, ++slot) {
-        const uint2 ss = stream_child(key, strm, (uint32_t)tech, k, (uint32_t)d);
+      const uint32_t* pre = sv.pre[tech == 0 ? 1 : 2];
+      const uint32_t nt = tech == 0 ? nB : nG;
+      for (uint32_t i = threadIdx.x; i < nt; i += kShadePtBlock) {
+        uint32_t k;
+        const uint32_t v = owner_of<kShadePtBlock>(pre, i, &k);
+        const uint2 ss = stream_child(key, make_uint2(sv.s0[v], sv.s1[v]), (uint32_t)tech, k,
+                                      (uint32_t)d);
         const float4 u = draw4(key, ss, 1);
+        const Mat mat = load_mat(sc.mats + 8 * (size_t)sv.mat[v]);
+        const f3 ns = mk3(sv.ns[0][v], sv.ns[1][v], sv.ns[2][v]);
+        const f3 wo = mk3(sv.wo[0][v], sv.wo[1][v], sv.wo[2][v]);
+        const uint32_t cl = sv.cell[v];
         f3 w;
         bool ok;
         if (tech == 0) {
-          ok = sample_bsdf(mat, n_s, wo, u.x, u.y, &w);
+          ok = sample_bsdf(mat, ns, wo, u.x, u.y, &w);
         } else {
-          w = guided_direction(cdf, u.x, u.y, u.z);
-          ok = dot3(n_s, w) > 0.0f;
+          w = guided_direction(c.cdf + 64 * (size_t)cl, u.x, u.y, u.z);
+          ok = dot3(ns, w) > 0.0f;
         }
         f3 fc = mk3(0.0f, 0.0f, 0.0f);
         float pB = 0.0f, pG = 0.0f, pt = 0.0f;
         if (ok) {
-          eval_bsdf(mat, n_s, wo, w, &fc, &pB);
-          pG = guided ? guided_density(pmf, w) : 0.0f;
+          eval_bsdf(mat, ns, wo, w, &fc, &pB);
+          pG = guided ? guided_density(c.pm + 64 * (size_t)cl, w) : 0.0f;
           pt = tech == 0 ? pB : pG;
           ok = (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f) && pt > 0.0f;
         }
-        const size_t e = Ln + cfirst + slot;
+        // guided samples follow the vertex's BSDF samples
+        const uint32_t nb0 = sv.pre[1][v] - (v > 0 ? sv.pre[1][v - 1] : 0u);
+        const uint32_t slot = tech == 0 ? k : nb0 + k;
+        const size_t e = Ln + sv.cfirst[v] + slot;
+        const f3 vo = mk3(sv.ov[0][v], sv.ov[1][v], sv.ov[2][v]);
+        const uint32_t vj = sv.j[v], vroot = sv.root[v];
+        const uint32_t pix = vroot / (uint32_t)it.spp;
+        const float bt = sv.beta[tech][v];
         if (ok) {
+          const float b0 = sv.beta[0][v], b1 = sv.beta[1][v], b2 = sv.beta[2][v];
+          const float bB = it.aware ? b0 : (b0 > 0.0f ? 1.0f : 0.0f);
+          const float bN = it.aware ? b1 : (b1 > 0.0f ? 1.0f : 0.0f);
+          const float bG = it.aware ? b2 : (b2 > 0.0f ? 1.0f : 0.0f);
           const float nb = bB * pB, ngd = bG * pG;
           const float dind = nb + ngd;
           const float wind = dind > 0.0f ? (tech == 0 ? nb : ngd) / dind : 0.0f;
           const float dsum = bB * pB + bG * pG;
-          const float bt = beta[tech];
           const float c0 = fc.x / pt, c1 = fc.y / pt, c2 = fc.z / pt;
-          const f3 Tc = mk3(T.x * ((c0 * wind) / bt), T.y * ((c1 * wind) / bt),
-                            T.z * ((c2 * wind) / bt));
-          q.R0[e] = make_float4(ov.x, ov.y, ov.z, 1.0f);
+          const f3 Tc = mk3(sv.T[0][v] * ((c0 * wind) / bt), sv.T[1][v] * ((c1 * wind) / bt),
+                            sv.T[2][v] * ((c2 * wind) / bt));
+          q.R0[e] = make_float4(vo.x, vo.y, vo.z, 1.0f);
           q.R1[e] = make_float4(w.x, w.y, w.z, fbits(pix));
-          q.S0[e] = make_float4(Tc.x, Tc.y, Tc.z, fbits(j));
+          q.S0[e] = make_float4(Tc.x, Tc.y, Tc.z, fbits(vj));
           q.S1[e] = make_float4(c0, c1, c2, wind);
           q.S2[e] = make_float4((tech == 0 ? bB : bG) * pt, dsum, bN, bt);
           ++my_ext;
         } else {
-          q.R0[e] = make_float4(ov.x, ov.y, ov.z, 0.0f);
+          q.R0[e] = make_float4(vo.x, vo.y, vo.z, 0.0f);
           q.R1[e] = make_float4(w.x, w.y, w.z, fbits(pix));
-          q.S0[e] = make_float4(0.0f, 0.0f, 0.0f, fbits(j));
+          q.S0[e] = make_float4(0.0f, 0.0f, 0.0f, fbits(vj));
           q.S1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, beta[tech]);
+          q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, bt);
         }
-        q.S3[e] = make_uint4(ss.x, ss.y, ((uint32_t)tech << 16) | k, root);
+        q.S3[e] = make_uint4(ss.x, ss.y, ((uint32_t)tech << 16) | k, vroot);
       }
     }
+    // the next round of the loop overwrites the shared vertex state
+    __syncthreads();
   }
   // one atomic per wave for the iteration counters
   group_add<kShadePtBlock, 4>({my_vert, my_samp, my_ext, my_sh},
