@@ -298,6 +298,10 @@ mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* gr
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch.  Enabling resets the totals. */
 mars_status mars_profile_enable(mars_ctx* ctx, int32_t on);
+/* The same for a subset: bit k of kernel_mask times kernel k (names from
+ * mars_profile_kernel_name); the others launch without events, so a timed
+ * run carries the events of the kernels it reports only.  0 turns it off. */
+mars_status mars_profile_enable_mask(mars_ctx* ctx, uint64_t kernel_mask);
 /* ms[k], launches[k] for kernel k < n; *n_kernels receives the kernel count */
 mars_status mars_profile_read(mars_ctx* ctx, double* ms, uint64_t* launches, int32_t n,
                               int32_t* n_kernels);

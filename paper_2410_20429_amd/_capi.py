@@ -104,6 +104,7 @@ SIGNATURES = {
     "mars_checkpoint_load": [P, I32, C.c_char_p],
     "mars_probe": [P, I32, I32, P, P],
     "mars_profile_enable": [P, I32],
+    "mars_profile_enable_mask": [P, C.c_uint64],
     "mars_profile_read": [P, P, P, I32, PI32],
     "mars_trace_counting": [P, I32],
     "mars_read_trace_counts": [P, P],
@@ -310,6 +311,10 @@ def mars_probe(ctx, kind, n, in_ptr, out_ptr):
 
 def mars_profile_enable(ctx, on):
     _call("mars_profile_enable", ctx, int(bool(on)))
+
+
+def mars_profile_enable_mask(ctx, mask):
+    _call("mars_profile_enable_mask", ctx, int(mask))
 
 
 def mars_profile_read(ctx):

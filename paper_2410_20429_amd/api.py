@@ -59,8 +59,18 @@ class Context:
         except Exception:
             pass
 
-    def profile(self, on=True):
-        capi.mars_profile_enable(self.h, on)
+    def profile(self, on=True, kernels=None):
+        """Per-kernel HIP-event timing; `kernels` (names) limits it to those."""
+        if kernels is None or not on:
+            capi.mars_profile_enable(self.h, on)
+            return
+        names = {capi.mars_profile_kernel_name(k): k for k in range(64)}
+        mask = 0
+        for name in kernels:
+            if name not in names:
+                raise ValueError(f"unknown kernel {name!r}")
+            mask |= 1 << names[name]
+        capi.mars_profile_enable_mask(self.h, mask)
 
     def profile_read(self):
         return capi.mars_profile_read(self.h)

@@ -83,18 +83,18 @@ struct Scene {
 };
 
 // per-kernel HIP-event timing on the context's stream
+// (fixed_point: the per-cell update with the guided distribution and the
+// inverse-variance weighted image)
 enum KernelId {
   KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
-  KID_FIXED_POINT, KID_HIST, KID_REFINE, KID_IVW, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_BATCH,
-  KID_COUNT
+  KID_FIXED_POINT, KID_REFINE, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_BATCH, KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
     "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
-    "fixed_point", "hist_normalize", "refine", "ivw", "light", "mlp_infer", "mlp_train",
-    "batch"};
+    "fixed_point", "refine", "light", "mlp_infer", "mlp_train", "batch"};
 
 struct Profiler {
-  bool on = false;
+  uint64_t mask = 0;  // bit k: kernel k is timed
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   std::vector<hipEvent_t> pool;
   double ms[KID_COUNT] = {0};
@@ -188,7 +188,7 @@ struct Ctx {
 
 template <typename F>
 void timed(Ctx* c, int kid, F&& launch) {
-  if (!c->prof.on) {
+  if (!((c->prof.mask >> kid) & 1u)) {
     launch();
     return;
   }
@@ -354,9 +354,12 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
   return hc.rays_light;
 }
 
-// one wavefront tile: returns false on queue overflow
+// One wavefront tile: returns false on queue overflow.  The bottom-up pass is
+// enqueued before the counters are read back (its kernels do nothing after an
+// overflow), and so are the per-pixel sums after the last tile (a re-rendered
+// tile enqueues them again), so that the host waits once per tile.
 bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t dbg0,
-              uint32_t npool, Counters* hc) {
+              uint32_t npool, bool last, int spp, Counters* hc) {
   const bool bdpt = s->mode == MARS_MODE_BDPT;
   hipStream_t st = s->ctx->stream;
   // traversal: 128-thread groups, kTraceBlocksPerCU resident per CU; others 256-thread groups
@@ -381,9 +384,6 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
     const int dc = d < s->max_depth ? d + 1 : -1;
     timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc); });
   }
-  d2h(hc, s->cnt, sizeof(Counters), st);
-  HIPCHK(hipStreamSynchronize(st));
-  if (hc->overflow) return false;
   for (int d = s->max_depth; d >= 1; --d)
     timed(c, KID_BACKPROP, [&] {
       if (bdpt)
@@ -391,7 +391,10 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
       else
         k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
     });
-  return true;
+  if (last) timed(c, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, spp, st); });
+  d2h(hc, s->cnt, sizeof(Counters), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return hc->overflow == 0;
 }
 
 void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out) {
@@ -403,10 +406,8 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   ensure_roots(s, roots);
   IterDev it = to_dev(p);
   // per-iteration statistics start at zero (Sec. 4.1: estimates per iteration)
-  k_fill_f64(s->cd.acc, 0.0, (size_t)s->n_cells * 24, st);
-  k_fill_f64(s->cd.hacc, 0.0, (size_t)s->n_cells * 64, st);
-  k_fill_u32(s->cd.visits, 0u, (size_t)s->n_cells, st);
-  k_fill_f32(s->img.beta1, 0.0f, roots * 3, st);
+  k_clear_iteration(s->cd, s->n_cells_dev, s->mode == MARS_MODE_PT_GUIDED, s->img.beta1, roots * 3,
+                    st);
   if (p->debug_depth > 0) {
     // room for every vertex up to debug_depth with splitting headroom
     const size_t want = std::min<size_t>(roots * (size_t)p->debug_depth * 4 + 1024, 1u << 25);
@@ -447,7 +448,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     auto [r0, n] = work.back();
     work.pop_back();
     Counters hc;
-    const bool ok = run_tile(s, it, r0, n, dbg_total, (uint32_t)roots, &hc);
+    const bool ok = run_tile(s, it, r0, n, dbg_total, (uint32_t)roots, work.empty(), p->spp, &hc);
     S.tiles++;
     for (int d = 1; d <= s->max_depth + 1; ++d)
       peak = std::max(peak, (double)std::max(hc.n_ray[d], hc.n_shadow[d]) / (double)n);
@@ -468,8 +469,6 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     S.samples += hc.samples;
     S.rays_conn += hc.rays_conn;
   }
-  timed(s->ctx, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, p->spp, st); });
-  HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   s->ctx->prof.flush();
   s->spp_last = p->spp;
@@ -709,7 +708,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     cd.n_fixed = 0;
     cd.max_cells = d->max_cells;
     s->n_cells_dev = salloc<int32_t>(s, 4);
-    s->scratch = salloc<uint32_t>(s, mc + 1);
+    s->scratch = salloc<uint32_t>(s, mc + 4);
     {
       const uint32_t root = kLeafBit;
       const int32_t nc[4] = {1, 1, 0, 0};
@@ -799,18 +798,15 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   // the running sample count lives on the device (red[6]) so that captured
   // iterations can advance it
   timed(c, KID_UPDATE_IMAGE, [&] {
-    k_add_spp(s->img.red + 6, spp, nullptr, st);
     k_update_image(s->img, s->W, s->H, spp, s->img.red + 6, s->mode == MARS_MODE_BDPT, kc,
                    nullptr, st);
   });
   const double C_I = (double)s->rays_last / ((double)npx * (double)spp);
   const int nb = s->n_cells;
   timed(c, KID_FIXED_POINT, [&] {
-    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 1, 0.0, s->max_cells,
-                  nullptr, st);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 1, 0.0,
+                  s->mode == MARS_MODE_PT_GUIDED, s->max_cells, &s->img, npx, spp, nullptr, st);
   });
-  if (s->mode == MARS_MODE_PT_GUIDED)
-    timed(c, KID_HIST, [&] { k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, nullptr, st); });
   if (s->mlp_on) {
     IterDev itd = p ? to_dev(p) : IterDev{};
     timed(c, KID_MLP, [&] {
@@ -821,7 +817,6 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
              s->max_tree_depth, s->max_cells, nullptr, st);
   });
-  timed(c, KID_IVW, [&] { k_ivw(s->img, npx, spp, nullptr, st); });
   double red[8];
   int32_t nc[4];
   uint32_t nrec = 0;
@@ -863,14 +858,12 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
                        hipStream_t st, double* summary) {
   Ctx* c = s->ctx;
   const bool bdpt = s->mode == MARS_MODE_BDPT;
-  const size_t roots = roots_of(s, spp), mc = (size_t)s->max_cells;
+  const size_t roots = roots_of(s, spp);
   const int grid_trace = c->cu * kTraceBlocksPerCU, grid = c->cu * 8;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
-  k_fill_f64_dev(s->cd.acc, 0.0, s->n_cells_dev, 24, mc * 24, st);
-  k_fill_f64_dev(s->cd.hacc, 0.0, s->n_cells_dev, 64, mc * 64, st);
-  k_fill_u32_dev(s->cd.visits, 0u, s->n_cells_dev, 1, mc, st);
-  k_fill_f32(s->img.beta1, 0.0f, roots * 3, st);
+  k_clear_iteration(s->cd, s->n_cells_dev, s->mode == MARS_MODE_PT_GUIDED, s->img.beta1, roots * 3,
+                    st);
   if (bdpt) {
     for (size_t r0 = 0; r0 < roots; r0 += s->cap) {
       const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
@@ -905,14 +898,12 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
   k_pixel_sums(s->img, s->W * s->H, spp, st);
   if (with_update) {
     const uint32_t* skip = &s->cnt->overflow_any;
-    k_add_spp(s->img.red + 6, spp, skip, st);
     k_update_image(s->img, s->W, s->H, spp, s->img.red + 6, bdpt, stat_clamp, skip, st);
     k_fixed_point(s->cd, s->n_cells_dev, s->img.red, 0.0, s->cnt, (double)roots, 1, 0.0,
-                  s->max_cells, skip, st);
-    if (s->mode == MARS_MODE_PT_GUIDED) k_hist_normalize(s->cd, s->n_cells_dev, s->max_cells, skip, st);
+                  s->mode == MARS_MODE_PT_GUIDED, s->max_cells, &s->img, s->W * s->H, spp, skip,
+                  st);
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
              s->max_tree_depth, s->max_cells, skip, st);
-    k_ivw(s->img, s->W * s->H, spp, skip, st);
   }
   k_batch_summary(s->cnt, s->img.red, s->n_cells_dev, summary, st);
 }
@@ -1363,14 +1354,18 @@ mars_status mars_destroy(mars_ctx* ctx) {
   return MARS_OK;
 }
 
-mars_status mars_profile_enable(mars_ctx* ctx, int32_t on) {
+mars_status mars_profile_enable_mask(mars_ctx* ctx, uint64_t kernel_mask) {
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->prof.flush();
     ctx->prof.reset();
-    ctx->prof.on = on != 0;
+    ctx->prof.mask = kernel_mask & ((1ull << KID_COUNT) - 1);
   });
+}
+
+mars_status mars_profile_enable(mars_ctx* ctx, int32_t on) {
+  return mars_profile_enable_mask(ctx, on ? ~0ull : 0ull);
 }
 
 mars_status mars_profile_read(mars_ctx* ctx, double* ms, uint64_t* launches, int32_t n,
@@ -1565,8 +1560,8 @@ mars_status mars_update_cells_only(mars_ctx* ctx, int32_t scene_id, double V_I, 
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
     Scene* s = ctx->scene(scene_id);
-    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 0, V_I, s->max_cells,
-                  nullptr, ctx->stream);
+    k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 0, V_I, 0, s->max_cells,
+                  nullptr, 0, 1, nullptr, ctx->stream);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipGetLastError());
   });

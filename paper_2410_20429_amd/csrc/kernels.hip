@@ -131,27 +131,36 @@ void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 void k_fill_f64(double* p, double v, size_t n, hipStream_t s) {
   if (n) fill_kernel<double><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
 }
+// Per-iteration clear in one launch: the moment and cost accumulators and
+// visit counts of the cells in use (count read on the device), the guided
+// training histograms when used, and the first-hit counts.
+__global__ void clear_iteration_kernel(CacheDev c, const int32_t* n_cells_dev, int guided,
+                                       float* beta1, size_t n_beta) {
+  const size_t n = (size_t)*n_cells_dev;
+  const size_t na = n * 24, nh = guided ? n * 64 : 0, nv = n;
+  const size_t total = na + nh + nv + n_beta;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    size_t k = i;
+    if (k < na) { c.acc[k] = 0.0; continue; }
+    k -= na;
+    if (k < nh) { c.hacc[k] = 0.0; continue; }
+    k -= nh;
+    if (k < nv) { c.visits[k] = 0u; continue; }
+    k -= nv;
+    beta1[k] = 0.0f;
+  }
+}
+void k_clear_iteration(const CacheDev& c, const int32_t* n_cells_dev, int guided, float* beta1,
+                       size_t n_beta, hipStream_t s) {
+  clear_iteration_kernel<<<2048, 256, 0, s>>>(c, n_cells_dev, guided, beta1, n_beta);
+}
+
 // update kernels become no-ops while a skip flag is set (an overflowed
 // iteration that is rendered again before its update)
 #define SKIP_IF(flag) \
   if ((flag) && *(flag)) return
 
-template <typename T>
-__global__ void fill_dev_kernel(T* p, T v, const int32_t* n_dev, int mult, size_t max_n) {
-  const size_t n = min((size_t)(*n_dev) * (size_t)mult, max_n);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-void k_fill_f64_dev(double* p, double v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s) {
-  fill_dev_kernel<double><<<(unsigned)std::min<size_t>((max_n + 255) / 256, 4096), 256, 0, s>>>(
-      p, v, n_dev, mult, max_n);
-}
-void k_fill_u32_dev(uint32_t* p, uint32_t v, const int32_t* n_dev, int mult, size_t max_n,
-                    hipStream_t s) {
-  fill_dev_kernel<uint32_t><<<(unsigned)std::min<size_t>((max_n + 255) / 256, 4096), 256, 0, s>>>(
-      p, v, n_dev, mult, max_n);
-}
 void k_fill_f32(float* p, float v, size_t n, hipStream_t s) {
   if (n) fill_kernel<float><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, v, n);
 }
@@ -2070,16 +2079,8 @@ void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s) {
 //   at 1e-3 x the image-mean channel value; V_I = mean over included pixels
 //   of (1/spp) sum_s (1/3) sum_ch ((min(I_s, k I~) - I~) / I~)^2.
 // red[0..2]: image-mean sums, red[3]: V_I sum, red[4]: included pixels,
-// red[5]: inverse-variance weight sum.
+// red[5]: inverse-variance weight sum, red[6]: samples per pixel so far.
 // ---------------------------------------------------------------------------
-
-__global__ void add_spp_kernel(double* total, int spp, const uint32_t* skip) {
-  SKIP_IF(skip);
-  *total += (double)spp;
-}
-void k_add_spp(double* total_spp, int spp, const uint32_t* skip, hipStream_t s) {
-  add_spp_kernel<<<1, 1, 0, s>>>(total_spp, spp, skip);
-}
 
 // sum of v over the workgroup (fixed order), valid in thread 0
 __device__ __forceinline__ double block_sum_d(double v) {
@@ -2094,21 +2095,33 @@ __device__ __forceinline__ double block_sum_d(double v) {
   __syncthreads();
   return s;
 }
-// red[first + j] = sum over the workgroups' partials part[b][first + j], in order
-__global__ void reduce_parts_kernel(ImageDev img, int first, int count, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int j = threadIdx.x;
-  if (j >= count) return;
-  double s = 0.0;
-  for (int b = 0; b < kRedBlocks; ++b) s += img.part[8 * b + first + j];
-  img.red[first + j] = s;
+// red[first + j] for j < N: the sum of the previous kernel's per-workgroup
+// partials part[b][first + j], computed by every workgroup that needs it in
+// one fixed order (thread t sums partials t, t + blockDim, ... in turn, then
+// the group sum), so all of them hold the same value and none waits on
+// another.  Every thread must call it; out[] is valid in every thread.
+template <int N>
+__device__ __forceinline__ void sum_parts(const ImageDev& img, int first, double (&out)[N]) {
+  __shared__ double res[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) s += img.part[8 * b + first + j];
+    s = block_sum_d(s);
+    if (threadIdx.x == 0) res[j] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) out[j] = res[j];
 }
 
+// running image: accum += iteration sums, mean = accum / total samples (the
+// total after this iteration, red[6] + spp, stored by the per-cell update)
 __global__ __launch_bounds__(256) void accum_mean_kernel(ImageDev img, int npx,
-                                                         const double* total_spp,
+                                                         const double* total_spp, int spp,
                                                          const uint32_t* skip) {
   SKIP_IF(skip);
-  const float tsp = (float)*total_spp;
+  const float tsp = (float)(*total_spp + (double)spp);
   double m[3] = {0.0, 0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x)
     for (int ch = 0; ch < 3; ++ch) {
@@ -2125,15 +2138,15 @@ __global__ __launch_bounds__(256) void accum_mean_kernel(ImageDev img, int npx,
   }
 }
 
-__global__ void itilde_kernel(ImageDev img, int W, int H, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= W * H) return;
+// I~ of pixel i (3x3 box filter of the running mean, edge clamped, floored)
+// into itilde; returns the exclusion flag (1: floored), also stored
+__device__ __forceinline__ uint8_t itilde_at(ImageDev& img, int W, int H, int i,
+                                             const double (&msum)[3]) {
   const int y = i / W, x = i % W;
   const double npx = (double)W * (double)H;
   uint8_t ex = 0;
   for (int ch = 0; ch < 3; ++ch) {
-    const float flo = fmaxf(1e-3f * (float)(img.red[ch] / npx), 1e-6f);
+    const float flo = fmaxf(1e-3f * (float)(msum[ch] / npx), 1e-6f);
     float s = 0.0f;
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
@@ -2148,6 +2161,22 @@ __global__ void itilde_kernel(ImageDev img, int W, int H, const uint32_t* skip) 
     img.itilde[3 * (size_t)i + ch] = s;
   }
   img.excl[i] = ex;
+  return ex;
+}
+// the image-mean sums (red[0..2]) from accum_mean's partials; stored by
+// workgroup 0
+__device__ __forceinline__ void mean_sums(ImageDev& img, double (&msum)[3]) {
+  sum_parts<3>(img, 0, msum);
+  if (blockIdx.x == 0 && threadIdx.x < 3) img.red[threadIdx.x] = msum[threadIdx.x];
+}
+__global__ __launch_bounds__(256) void itilde_kernel(ImageDev img, int W, int H,
+                                                     const uint32_t* skip) {
+  SKIP_IF(skip);
+  double msum[3];
+  mean_sums(img, msum);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  itilde_at(img, W, H, i, msum);
 }
 
 // BDPT: the 10 pixels with the largest iteration luminance leave V_I
@@ -2237,12 +2266,18 @@ __global__ __launch_bounds__(1024) void brightest_final_kernel(ImageDev img, int
   }
 }
 
-__global__ __launch_bounds__(256) void vi_kernel(ImageDev img, int npx, int spp, float kc,
-                                                  const uint32_t* skip) {
+// V_I partial sums; with_itilde: I~ and the exclusion flag of each pixel are
+// computed here first (no brightest-pixel pass in between)
+__global__ __launch_bounds__(256) void vi_kernel(ImageDev img, int W, int H, int spp, float kc,
+                                                  int with_itilde, const uint32_t* skip) {
   SKIP_IF(skip);
+  const int npx = W * H;
+  double msum[3] = {0.0, 0.0, 0.0};
+  if (with_itilde) mean_sums(img, msum);
   double e = 0.0, inc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
-    if (img.excl[i] != 0) continue;
+    const uint8_t ex = with_itilde ? itilde_at(img, W, H, i, msum) : img.excl[i];
+    if (ex != 0) continue;
     const float* It = img.itilde + 3 * (size_t)i;
     double ep = 0.0;
     for (int s = 0; s < spp; ++s) {
@@ -2263,25 +2298,17 @@ __global__ __launch_bounds__(256) void vi_kernel(ImageDev img, int npx, int spp,
     img.part[8 * blockIdx.x + 4] = si;
   }
 }
-
-__global__ void clear_red_kernel(double* red, const uint32_t* skip) {
-  SKIP_IF(skip);
-  if (threadIdx.x < 5) red[threadIdx.x] = 0.0;
-}
 void k_update_image(const ImageDev& img, int W, int H, int spp, const double* total_spp, int bdpt,
                     float stat_clamp, const uint32_t* skip, hipStream_t s) {
   const int npx = W * H;
-  clear_red_kernel<<<1, 64, 0, s>>>(img.red, skip);
-  accum_mean_kernel<<<kRedBlocks, 256, 0, s>>>(img, npx, total_spp, skip);
-  reduce_parts_kernel<<<1, 64, 0, s>>>(img, 0, 3, skip);
-  itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H, skip);
+  accum_mean_kernel<<<kRedBlocks, 256, 0, s>>>(img, npx, total_spp, spp, skip);
   if (bdpt) {
+    itilde_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, W, H, skip);
     const int nb = (npx + kBrightChunk - 1) / kBrightChunk;
     brightest_part_kernel<<<nb, 256, 0, s>>>(img, npx, skip);
     brightest_final_kernel<<<1, 1024, 0, s>>>(img, nb * kBright, skip);
   }
-  vi_kernel<<<kRedBlocks, 256, 0, s>>>(img, npx, spp, stat_clamp, skip);
-  reduce_parts_kernel<<<1, 64, 0, s>>>(img, 3, 2, skip);
+  vi_kernel<<<kRedBlocks, 256, 0, s>>>(img, W, H, spp, stat_clamp, bdpt ? 0 : 1, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -2289,10 +2316,31 @@ void k_update_image(const ImageDev& img, int W, int H, int spp, const double* to
 // technique with samples, in binary64,
 //   a^RR = C_I / (C_t V_I) E[v^2],  a^S = C_I / (C_t V_I) V[v]   per channel
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void ivw_at(ImageDev& img, int i, int spp, const double (&vs)[2]);
+// Blocks [0, cell_blocks): per cell, the fixed point and (guided) the
+// directional distribution; blocks after that: the inverse-variance weighted
+// accumulation of the iteration's image, per pixel (npx pixels).
 __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const double* red,
                                    double C_I, const Counters* cnt, double roots, int use_dev,
-                                   double V_host, const uint32_t* skip) {
+                                   double V_host, int guided, ImageDev img, int npx, int spp,
+                                   int cell_blocks, const uint32_t* skip) {
   SKIP_IF(skip);
+  // V_I sums (red[3], red[4]) from vi's partials; workgroup 0 stores them
+  // and advances the sample total (red[6]) by this iteration's spp
+  double vs[2] = {0.0, 0.0};
+  if (use_dev) {
+    sum_parts<2>(img, 3, vs);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      img.red[3] = vs[0];
+      img.red[4] = vs[1];
+      if (npx > 0) img.red[6] += (double)spp;
+    }
+  }
+  if ((int)blockIdx.x >= cell_blocks) {
+    const int i = (blockIdx.x - cell_blocks) * blockDim.x + threadIdx.x;
+    if (i < npx) ivw_at(img, i, spp, vs);
+    return;
+  }
   if (cnt) {
     const double rays = roots + (double)(cnt->rays_ext + cnt->rays_shadow + cnt->rays_light +
                                          cnt->rays_conn);
@@ -2300,36 +2348,26 @@ __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const
   }
   const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (cidx >= *n_cells_dev) return;
-  const double V_I = use_dev ? (red[4] > 0.0 ? red[3] / red[4] : 0.0) : V_host;
-  if (!(V_I > 0.0) || !(C_I > 0.0)) return;
-  for (int t = 0; t < 3; ++t) {
-    const double* a = c.acc + ((size_t)cidx * 3 + t) * 8;
-    const double n = a[6];
-    if (!(n > 0.0)) continue;
-    const double Ct = a[7] / n;
-    if (!(Ct > 0.0)) continue;
-    const double k = C_I / (Ct * V_I);
-    for (int ch = 0; ch < 3; ++ch) {
-      const double E1 = a[ch] / n, E2 = a[3 + ch] / n;
-      double var = E2 - E1 * E1;
-      if (var < 0.0) var = 0.0;
-      c.fac[(size_t)cidx * 18 + (0 * 3 + t) * 3 + ch] = (float)(k * E2);
-      c.fac[(size_t)cidx * 18 + (1 * 3 + t) * 3 + ch] = (float)(k * var);
+  const double V_I = use_dev ? (vs[1] > 0.0 ? vs[0] / vs[1] : 0.0) : V_host;
+  if (V_I > 0.0 && C_I > 0.0) {
+    for (int t = 0; t < 3; ++t) {
+      const double* a = c.acc + ((size_t)cidx * 3 + t) * 8;
+      const double n = a[6];
+      if (!(n > 0.0)) continue;
+      const double Ct = a[7] / n;
+      if (!(Ct > 0.0)) continue;
+      const double k = C_I / (Ct * V_I);
+      for (int ch = 0; ch < 3; ++ch) {
+        const double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+        double var = E2 - E1 * E1;
+        if (var < 0.0) var = 0.0;
+        c.fac[(size_t)cidx * 18 + (0 * 3 + t) * 3 + ch] = (float)(k * E2);
+        c.fac[(size_t)cidx * 18 + (1 * 3 + t) * 3 + ch] = (float)(k * var);
+      }
     }
   }
-}
-void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
-                   const Counters* cnt, double roots, int use_device_vi, double V_I_host,
-                   int max_cells, const uint32_t* skip, hipStream_t s) {
-  fixed_point_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, red, C_I, cnt, roots,
-                                                               use_device_vi, V_I_host, skip);
-}
-
-// guided distribution of the next iteration: 0.9 learned + 0.1 uniform
-__global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cidx >= *n_cells_dev) return;
+  if (!guided) return;
+  // guided distribution of the next iteration: 0.9 learned + 0.1 uniform
   const double* h = c.hacc + 64 * (size_t)cidx;
   double tot = 0.0;
   for (int b = 0; b < 64; ++b) tot += h[b];
@@ -2342,75 +2380,117 @@ __global__ void hist_normalize_kernel(CacheDev c, const int32_t* n_cells_dev, co
     c.cdf[64 * (size_t)cidx + b] = b == 63 ? 1.0f : (float)run;
   }
 }
-void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells,
-                      const uint32_t* skip, hipStream_t s) {
-  hist_normalize_kernel<<<(max_cells + 255) / 256, 256, 0, s>>>(c, n_cells_dev, skip);
+// per cell: the fixed point, then (guided) the directional distribution;
+// with img and npx > 0 also the inverse-variance weighted image (uses the
+// device V_I)
+void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
+                   const Counters* cnt, double roots, int use_device_vi, double V_I_host,
+                   int guided, int max_cells, const ImageDev* img, int npx, int spp,
+                   const uint32_t* skip, hipStream_t s) {
+  const int cb = (max_cells + 255) / 256, pb = img ? (npx + 255) / 256 : 0;
+  fixed_point_kernel<<<cb + pb, 256, 0, s>>>(c, n_cells_dev, red, C_I, cnt, roots, use_device_vi,
+                                              V_I_host, guided, img ? *img : ImageDev{},
+                                              img ? npx : 0, spp, cb, skip);
 }
 
 // ---------------------------------------------------------------------------
 // octree refinement: leaves with more than split_visits visits and depth
 // below the maximum split, in increasing leaf order, while the leaf budget
-// allows.  flags -> one-workgroup exclusive scan -> apply.
+// allows.  One workgroup ranks the flagged leaves and advances the cell and
+// node counts; then one wave per accepted leaf applies the split.
+// scratch: [max_cells] ranks, then flagged total, old cell count, old node
+// count.
 // ---------------------------------------------------------------------------
-__global__ void split_flags_kernel(CacheDev c, const int32_t* n_cells_dev, uint32_t* flags,
-                                   int split_visits, int max_tree_depth, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= *n_cells_dev) return;
-  flags[l] = (c.visits[l] > (uint32_t)split_visits && c.leaf_depth[l] < (uint32_t)max_tree_depth)
-                 ? 1u : 0u;
-}
-// rank of every flagged leaf among the flagged ones (index order), sentinel
-// otherwise, and the number flagged: one workgroup over tiles of 1024 flags,
-// coalesced loads, wave ballots and a carry across tiles
-__global__ __launch_bounds__(1024) void scan_flags_kernel(const int32_t* n_cells_dev,
-                                                          uint32_t* flags, uint32_t* total,
+constexpr int kScanRows = 16;  // rows of 1024 leaves per round
+__global__ __launch_bounds__(1024) void scan_split_kernel(CacheDev c, int32_t* n_cells_dev,
+                                                          int32_t* n_nodes_dev, uint32_t* rank,
+                                                          uint32_t* tail, int split_visits,
+                                                          int max_tree_depth, int max_cells,
                                                           const uint32_t* skip) {
-  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t wcnt[kScanRows][16];  // flagged leaves per (row, wave), then prefixes
+  __shared__ uint32_t rowbase[kScanRows + 1];
   __shared__ uint32_t carry;
   SKIP_IF(skip);
   const int n = *n_cells_dev;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = 0u;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, tid = threadIdx.x;
+  if (tid == 0) carry = 0u;
   __syncthreads();
-  for (int base = 0; base < n; base += 1024) {
-    const int i = base + (int)threadIdx.x;
-    const uint32_t f = i < n ? flags[i] : 0u;
-    const unsigned long long m = __ballot(f != 0u);
-    const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[wid] = (uint32_t)__popcll(m);
-    __syncthreads();
-    uint32_t off = carry;
-    for (int w = 0; w < wid; ++w) off += wsum[w];
-    if (i < n) flags[i] = f ? off + below : 0xFFFFFFFFu;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t t = 0u;
-      for (int w = 0; w < 16; ++w) t += wsum[w];
-      carry += t;
+  for (int base = 0; base < n; base += 1024 * kScanRows) {
+    // leaf base + 1024 k + tid of row k: coalesced loads, all issued first
+    uint32_t vis[kScanRows], dep[kScanRows];
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+      const int l = min(base + 1024 * k + tid, n - 1);
+      vis[k] = c.visits[l];
+      dep[k] = c.leaf_depth[l];
+    }
+    uint32_t flags = 0u, below[kScanRows];
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+      const bool f = base + 1024 * k + tid < n && vis[k] > (uint32_t)split_visits &&
+                     dep[k] < (uint32_t)max_tree_depth;
+      const unsigned long long m = __ballot(f);
+      below[k] = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (f) flags |= 1u << k;
+      if (lane == 0) wcnt[k][wid] = (uint32_t)__popcll(m);
     }
     __syncthreads();
+    // exclusive prefixes over the waves of each row, and of the rows
+    if (tid < kScanRows) {
+      uint32_t run = 0u;
+      for (int w = 0; w < 16; ++w) {
+        const uint32_t x = wcnt[tid][w];
+        wcnt[tid][w] = run;
+        run += x;
+      }
+      rowbase[tid + 1] = run;  // row total for now
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = carry;
+      for (int k = 0; k < kScanRows; ++k) {
+        const uint32_t x = rowbase[k + 1];
+        rowbase[k] = run;
+        run += x;
+      }
+      rowbase[kScanRows] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+      const int l = base + 1024 * k + tid;
+      if (l < n)
+        rank[l] = ((flags >> k) & 1u) ? rowbase[k] + wcnt[k][wid] + below[k] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    if (tid == 0) carry = rowbase[kScanRows];
+    __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (tid == 0) {
+    const int nn0 = *n_nodes_dev;
+    const uint32_t room = max_cells > n ? (uint32_t)((max_cells - n) / 7) : 0u;
+    const uint32_t acc = min(carry, room);
+    tail[0] = acc;
+    tail[1] = (uint32_t)n;
+    tail[2] = (uint32_t)nn0;
+    *n_cells_dev = n + 7 * (int)acc;
+    *n_nodes_dev = nn0 + 8 * (int)acc;
+  }
 }
 // one wave per leaf: lane 0 links the eight children into the tree, the
 // lanes copy the parent's factors and distribution into the seven new cells
 // and clear their statistics
-__global__ __launch_bounds__(256) void apply_split_kernel(CacheDev c, const int32_t* n_cells_dev,
-                                                          const int32_t* n_nodes_dev,
-                                                          const uint32_t* rank,
-                                                          const uint32_t* total, int max_cells,
+__global__ __launch_bounds__(256) void apply_split_kernel(CacheDev c, const uint32_t* rank,
+                                                          const uint32_t* tail,
                                                           const uint32_t* skip) {
   SKIP_IF(skip);
   const int lane = threadIdx.x & 63;
   const int l = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const int n0 = *n_cells_dev, nn0 = *n_nodes_dev;
+  const uint32_t acc = tail[0];
+  const int n0 = (int)tail[1], nn0 = (int)tail[2];
   if (l >= n0) return;
   const uint32_t r = rank[l];
-  if (r == 0xFFFFFFFFu) return;
-  const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
-  const uint32_t acc = min(*total, room);
-  if (r >= acc) return;
+  if (r >= acc) return;  // not flagged (sentinel) or beyond the budget
   const uint32_t base = (uint32_t)nn0 + 8u * r;
   const uint32_t first = (uint32_t)n0 + 7u * r;  // ids of children 1..7
   if (lane == 0) {
@@ -2435,27 +2515,14 @@ __global__ __launch_bounds__(256) void apply_split_kernel(CacheDev c, const int3
   for (int k = lane; k < 7 * 24; k += 64) c.acc[(size_t)(first + k / 24) * 24 + k % 24] = 0.0;
   if (lane < 7) c.visits[first + lane] = 0u;
 }
-__global__ void finish_split_kernel(int32_t* n_cells_dev, int32_t* n_nodes_dev,
-                                    const uint32_t* total, int max_cells, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int n0 = *n_cells_dev;
-  const uint32_t room = max_cells > n0 ? (uint32_t)((max_cells - n0) / 7) : 0u;
-  const uint32_t acc = min(*total, room);
-  *n_cells_dev = n0 + 7 * (int)acc;
-  *n_nodes_dev = *n_nodes_dev + 8 * (int)acc;
-}
 void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
               int split_visits, int max_tree_depth, int max_cells, const uint32_t* skip,
               hipStream_t s) {
-  const int g = (max_cells + 255) / 256;
-  split_flags_kernel<<<g, 256, 0, s>>>(c, n_cells_dev, scratch, split_visits, max_tree_depth, skip);
-  scan_flags_kernel<<<1, 1024, 0, s>>>(n_cells_dev, scratch, scratch + max_cells, skip);
-  apply_split_kernel<<<(max_cells + 3) / 4, 256, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch,
-                                                         scratch + max_cells, max_cells, skip);
-  finish_split_kernel<<<1, 1, 0, s>>>(n_cells_dev, n_nodes_dev, scratch + max_cells, max_cells, skip);
+  scan_split_kernel<<<1, 1024, 0, s>>>(c, n_cells_dev, n_nodes_dev, scratch, scratch + max_cells,
+                                       split_visits, max_tree_depth, max_cells, skip);
+  apply_split_kernel<<<(max_cells + 3) / 4, 256, 0, s>>>(c, scratch, scratch + max_cells, skip);
 }
 
-// inverse-variance weighted combination of the iterations (Sec. 5.1)
 // per-scene summary of a batched iteration, gathered for one read-back:
 // [0] overflow, [1..6] ray / vertex / sample totals, [7..14] image
 // reductions, [15] cells, [16] nodes
@@ -2480,21 +2547,17 @@ void k_batch_summary(const Counters* cnt, const double* red, const int32_t* n_ce
 __global__ void set_i32_kernel(int32_t* p, int32_t v) { *p = v; }
 void k_set_i32(int32_t* p, int32_t v, hipStream_t s) { set_i32_kernel<<<1, 1, 0, s>>>(p, v); }
 
-__global__ void ivw_kernel(ImageDev img, int npx, int spp, const uint32_t* skip) {
-  SKIP_IF(skip);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double V_I = img.red[4] > 0.0 ? img.red[3] / img.red[4] : 0.0;
+// inverse-variance weighted combination of the iterations (Sec. 5.1):
+// iteration images weighted by spp / V_I
+__device__ __forceinline__ void ivw_at(ImageDev& img, int i, int spp, const double (&vs)[2]) {
+  const double V_I = vs[1] > 0.0 ? vs[0] / vs[1] : 0.0;
   if (!(V_I > 0.0)) return;
   const double w = (double)spp / V_I;
   if (i == 0) img.red[5] += w;
-  if (i >= npx) return;
   for (int ch = 0; ch < 3; ++ch) {
     const size_t e = 3 * (size_t)i + ch;
     img.ivw_acc[e] += w * (double)(img.iter_sum[e] / (float)spp);
   }
-}
-void k_ivw(const ImageDev& img, int npx, int spp, const uint32_t* skip, hipStream_t s) {
-  ivw_kernel<<<(npx + 255) / 256, 256, 0, s>>>(img, npx, spp, skip);
 }
 
 // ---------------------------------------------------------------------------

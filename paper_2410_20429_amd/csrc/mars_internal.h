@@ -141,7 +141,7 @@ struct ImageDev {
 };
 // image reductions: a fixed grid of workgroups, partial sums summed in order
 // (deterministic, no contended atomics)
-constexpr int kRedBlocks = 256;
+constexpr int kRedBlocks = 1024;
 // brightest pixels dropped from V_I in BDPT, selected in chunks of pixels
 constexpr int kBright = 10, kBrightChunk = 4096;
 
@@ -168,6 +168,8 @@ struct MlpDev {
 };
 
 // ---- launchers (kernels.hip) ----
+void k_clear_iteration(const CacheDev& c, const int32_t* n_cells_dev, int guided, float* beta1,
+                       size_t n_beta, hipStream_t s);
 void k_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void k_fill_f64(double* p, double v, size_t n, hipStream_t s);
 void k_fill_f32(float* p, float v, size_t n, hipStream_t s);
@@ -212,25 +214,20 @@ void k_pixel_sums(const ImageDev& img, int npx, int spp, hipStream_t s);
 // (an iteration whose queues overflowed is re-run before its update)
 void k_update_image(const ImageDev& img, int W, int H, int spp, const double* total_spp, int bdpt,
                     float stat_clamp, const uint32_t* skip, hipStream_t s);
-void k_add_spp(double* total_spp, int spp, const uint32_t* skip, hipStream_t s);
 // C_I from rays / (pixels x spp): given on the host (cnt == null) or taken
 // from the iteration totals in `cnt` plus the camera rays `roots`
 void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
                    const Counters* cnt, double roots, int use_device_vi, double V_I_host,
-                   int max_cells, const uint32_t* skip, hipStream_t s);
-void k_hist_normalize(const CacheDev& c, const int32_t* n_cells_dev, int max_cells,
-                      const uint32_t* skip, hipStream_t s);
+                   int guided, int max_cells, const ImageDev* img, int npx, int spp,
+                   const uint32_t* skip, hipStream_t s);
 void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
               int split_visits, int max_tree_depth, int max_cells, const uint32_t* skip,
               hipStream_t s);
-void k_ivw(const ImageDev& img, int npx, int spp, const uint32_t* skip, hipStream_t s);
 constexpr int kSumWords = 17;
 void k_batch_summary(const Counters* cnt, const double* red, const int32_t* n_cells_dev,
                      double* out, hipStream_t s);
 void k_set_i32(int32_t* p, int32_t v, hipStream_t s);
 // fills n_dev[0] * mult elements (n_dev read on the device)
-void k_fill_f64_dev(double* p, double v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s);
-void k_fill_u32_dev(uint32_t* p, uint32_t v, const int32_t* n_dev, int mult, size_t max_n, hipStream_t s);
 void k_probe(int kind, int n, const void* in, void* out, hipStream_t s);
 
 }  // namespace mars
