@@ -1,6 +1,6 @@
 // Host BVH builder: binned SAH (16 bins per axis) binary tree, at most 4
-// triangles per leaf unless a split cannot separate them (then up to 15),
-// depth bounded by 30 (median splits take over when the remaining triangles
+// triangles per leaf (a median split separates any larger set), depth
+// bounded by 30 (median splits take over when the remaining triangles
 // could otherwise exceed the bound), then collapsed to a 4-wide tree: each
 // node takes up to four descendants, expanding the inner child of largest
 // surface area first.

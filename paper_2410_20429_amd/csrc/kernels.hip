@@ -481,46 +481,49 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
           t3 = quad_bcast<3>(ts);
     int r0 = quad_bcast<0>(rs), r1 = quad_bcast<1>(rs), r2 = quad_bcast<2>(rs),
         r3 = quad_bcast<3>(rs);
-#pragma unroll
-    for (int side = 0; side < 4; ++side) {
-      const int ch = side == 0 ? r0 : side == 1 ? r1 : side == 2 ? r2 : r3;
-      const float tn = side == 0 ? t0 : side == 1 ? t1 : side == 2 ? t2 : t3;
-      if (ch < 0 && tn != INFINITY) {
-        const uint32_t code = (uint32_t)(-1 - ch);
-        const uint32_t first = code >> 4, count = code & 15u;
-        float ht = INFINITY;
-        uint32_t hp = kMiss;
-        bool hit = false;
-        for (uint32_t k = first + (uint32_t)sub; k < first + count; k += 4) {
-          const float4* T = sc.tri_bvh + (size_t)k * 3;
-          const float4 A = T[0];
-          float t;
-          if (!tri_hit(o, d, A, T[1], T[2], &t)) continue;
-          if (!(t > 0.0f && t < tmax)) continue;
-          const uint32_t prim = ubits(A.w);
-          if (kAny) {
-            hit = true;
-            ht = t;
-            hp = prim;
-            break;
-          }
-          if (t < ht || (t == ht && prim < hp)) {
-            ht = t;
-            hp = prim;
-          }
-        }
+    // the triangles of the leaf children hit here (at most 4 per leaf),
+    // numbered in child order and dealt round-robin to the quad's lanes
+    const uint32_t c0 = (r0 < 0 && t0 != INFINITY) ? ((uint32_t)(-1 - r0) & 15u) : 0u;
+    const uint32_t c1 = (r1 < 0 && t1 != INFINITY) ? ((uint32_t)(-1 - r1) & 15u) : 0u;
+    const uint32_t c2 = (r2 < 0 && t2 != INFINITY) ? ((uint32_t)(-1 - r2) & 15u) : 0u;
+    const uint32_t c3 = (r3 < 0 && t3 != INFINITY) ? ((uint32_t)(-1 - r3) & 15u) : 0u;
+    const uint32_t p1 = c0, p2 = p1 + c1, p3 = p2 + c2, ntri = p3 + c3;
+    if (ntri != 0u) {
+      float ht = INFINITY;
+      uint32_t hp = kMiss;
+      bool hit = false;
+      for (uint32_t m = (uint32_t)sub; m < ntri; m += 4) {
+        const int ref = m < p1 ? r0 : m < p2 ? r1 : m < p3 ? r2 : r3;
+        const uint32_t off = m < p1 ? m : m < p2 ? m - p1 : m < p3 ? m - p2 : m - p3;
+        const uint32_t k = ((uint32_t)(-1 - ref) >> 4) + off;
+        const float4* T = sc.tri_bvh + (size_t)k * 3;
+        const float4 A = T[0];
+        float t;
+        if (!tri_hit(o, d, A, T[1], T[2], &t)) continue;
+        if (!(t > 0.0f && t < tmax)) continue;
+        const uint32_t prim = ubits(A.w);
         if (kAny) {
-          if (quad_any(hit)) {
-            *bt_out = ht;
-            *bp_out = hp;
-            return true;
-          }
-        } else {
-          quad_min_hit(ht, hp);
-          if (ht < bt || (ht == bt && hp < bp)) {
-            bt = ht;
-            bp = hp;
-          }
+          hit = true;
+          ht = t;
+          hp = prim;
+          break;
+        }
+        if (t < ht || (t == ht && prim < hp)) {
+          ht = t;
+          hp = prim;
+        }
+      }
+      if (kAny) {
+        if (quad_any(hit)) {
+          *bt_out = ht;
+          *bp_out = hp;
+          return true;
+        }
+      } else {
+        quad_min_hit(ht, hp);
+        if (ht < bt || (ht == bt && hp < bp)) {
+          bt = ht;
+          bp = hp;
         }
       }
     }
@@ -559,7 +562,7 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
 
 // The rays of trace_pair_kernel, one quad per ray (rays q, q + Q, ... for
 // quad q of Q); lane 0 of the quad writes the result.
-__global__ __launch_bounds__(kTraceBlock) void trace_quad_kernel(SceneDev sc, QueuesDev q,
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_quad_kernel(SceneDev sc, QueuesDev q,
                                                                  const Counters* cnt, int dc,
                                                                  int ds) {
   __shared__ int stk[kQuadStack * kQuadStride];
