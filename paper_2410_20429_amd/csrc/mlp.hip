@@ -49,12 +49,26 @@ __device__ __forceinline__ float feature(const float* x, int k) {
   return (k & 1) ? cospif(a) : sinpif(a);
 }
 
+// LDS written by some lanes of a wave and read by others of the same wave
+// (the workgroups using it hold several waves that do not meet): the wave's
+// own writes completed (workgroup-scope release), no code motion across it
+// (wave barrier), then the reads (acquire)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Forward pass of one 16-sample tile by one wave.  x: this lane's sample
-// inputs (sample = lane % 16).  Hidden activations go to hs[l][16][64]
-// (bfloat16), features to xs[16][80] when xs != nullptr.  Returns the output
-// tile in D layout (rows = samples, columns = outputs).
-__device__ v4f mlp_forward_tile(const float* __restrict__ master, const uint16_t* __restrict__ wq,
-                                const float* x, uint16_t (*hs)[16][64], uint16_t (*xs)[80]) {
+// inputs (sample = lane % 16).  wq: the bfloat16 weights (global memory or a
+// copy in LDS).  Hidden activations go to hs[l][16][64] (bfloat16), features
+// to xs[16][80] when xs != nullptr.  Returns the output tile in D layout (rows
+// = samples, columns = outputs).  kGroupSync: one-wave workgroups meet at
+// workgroup barriers; otherwise only the wave's own order is kept.
+template <bool kGroupSync>
+__device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master,
+                                                const uint16_t* __restrict__ wq, const float* x,
+                                                uint16_t (*hs)[16][64], uint16_t (*xs)[80]) {
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   v4f acc[4];
 #pragma unroll
@@ -87,7 +101,8 @@ __device__ v4f mlp_forward_tile(const float* __restrict__ master, const uint16_t
         const float z = acc[nt][r] + master[boff[l] + j];
         hs[l][4 * lg + r][j] = to_bf16(fmaxf(z, 0.0f));
       }
-    __syncthreads();
+    if (kGroupSync) __syncthreads();
+    else wave_lds_sync();
     const int ntn = l < 2 ? 4 : 1;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -118,7 +133,7 @@ __global__ __launch_bounds__(64) void mlp_infer_inputs_kernel(MlpDev m, const fl
     float x[6] = {0, 0, 0, 0, 0, 0};
     if (s < n)
       for (int k = 0; k < 6; ++k) x[k] = x6[6 * (size_t)s + k];
-    const v4f y = mlp_forward_tile(m.master, m.wq, x, hs, nullptr);
+    const v4f y = mlp_forward_tile<true>(m.master, m.wq, x, hs, nullptr);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int si = tile * 16 + 4 * lg + r;
@@ -133,15 +148,27 @@ void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream
 }
 
 // inference at the vertices of one depth's queue (hits with d < D): inputs
-// from the hit point and the shading normal, outputs to m.y[d * cap + j]
-__global__ __launch_bounds__(64) void mlp_infer_queue_kernel(SceneDev sc, QueuesDev q, MlpDev m,
-                                                             const Counters* cnt, int d) {
-  __shared__ uint16_t hs[3][16][64];
+// from the hit point and the shading normal, outputs to m.y[d * cap + j].
+// The bfloat16 weights are copied once per workgroup into LDS; each of its
+// four waves then runs 16-sample tiles of the queue.
+constexpr int kInferWaves = 4;
+__global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_queue_kernel(SceneDev sc,
+                                                                           QueuesDev q, MlpDev m,
+                                                                           const Counters* cnt,
+                                                                           int d) {
+  __shared__ uint4 wl4[kQW / 8];
+  __shared__ uint16_t hs[kInferWaves][3][16][64];
   if (cnt->overflow) return;
-  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
+  if ((size_t)blockIdx.x * kInferWaves * 16 >= n) return;  // no tile for this workgroup
+  for (int k = threadIdx.x; k < kQW / 8; k += blockDim.x)
+    wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
+  __syncthreads();
+  const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
   const size_t L = (size_t)d * q.cap;
-  for (uint32_t tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
+  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile * 16 < n;
+       tile += gridDim.x * kInferWaves) {
     const uint32_t s = tile * 16 + lr;
     float x[6] = {0, 0, 0, 0, 0, 0};
     if (s < n) {
@@ -158,18 +185,20 @@ __global__ __launch_bounds__(64) void mlp_infer_queue_kernel(SceneDev sc, Queues
         x[3] = ns.x; x[4] = ns.y; x[5] = ns.z;
       }
     }
-    const v4f y = mlp_forward_tile(m.master, m.wq, x, hs, nullptr);
+    const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint32_t si = tile * 16 + 4 * lg + r;
       if (si < n && lr < 3) m.y[(L + si) * 4 + lr] = y[r];
     }
-    __syncthreads();
+    // the next tile rewrites hs[w] only after every lane has read it
+    wave_lds_sync();
   }
 }
 void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
                        int d, int grid, hipStream_t s) {
-  mlp_infer_queue_kernel<<<grid, 64, 0, s>>>(sc, q, m, cnt, d);
+  // three workgroups (53 KB of LDS each) per CU; grid = 32 per CU
+  mlp_infer_queue_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, cnt, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,7 +290,7 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
       const size_t s = (size_t)((offset + bi) % n_set);
       for (int k = 0; k < 6; ++k) x[k] = x6[6 * s + k];
     }
-    const v4f y = mlp_forward_tile(m.master, m.wq, x, S.hs, S.xs);
+    const v4f y = mlp_forward_tile<true>(m.master, m.wq, x, S.hs, S.xs);
     v4f dz[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
