@@ -275,10 +275,15 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
                                                        const float* wt, int n_set, int offset,
                                                        int batch, int tiles_per_block) {
   __shared__ TrainLds S;
+  // the bfloat16 weights, read by every product of the forward and backward
+  // passes, copied once into LDS
+  __shared__ uint4 wl4[kQW / 8];
   const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
   for (int p = lane; p < kMlpParams; p += 64) S.g[p] = 0.0f;
+  for (int k = lane; k < kQW / 8; k += 64) wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
   if (lane == 0) S.loss = 0.0f;
   __syncthreads();
+  const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
   const int ntiles = (batch + 15) / 16;
   const int t0 = blockIdx.x * tiles_per_block, t1 = min(ntiles, t0 + tiles_per_block);
   const float inv_n = 1.0f / (float)batch;
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
       const size_t s = (size_t)((offset + bi) % n_set);
       for (int k = 0; k < 6; ++k) x[k] = x6[6 * s + k];
     }
-    const v4f y = mlp_forward_tile<true>(m.master, m.wq, x, S.hs, S.xs);
+    const v4f y = mlp_forward_tile<true>(m.master, wl, x, S.hs, S.xs);
     v4f dz[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -306,13 +311,13 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
       dz[0][r] = g;
     }
     v4f dp[5];
-    dense_backward(m.wq, qW4, 16, 64, &S.hs[2][0][0], 64, S.g + kMlpW4, S.g + kMlpB4, dz, S.dz, dp,
+    dense_backward(wl, qW4, 16, 64, &S.hs[2][0][0], 64, S.g + kMlpW4, S.g + kMlpB4, dz, S.dz, dp,
                    true);
-    dense_backward(m.wq, qW3, 64, 64, &S.hs[1][0][0], 64, S.g + kMlpW3, S.g + kMlpB3, dp, S.dz, dz,
+    dense_backward(wl, qW3, 64, 64, &S.hs[1][0][0], 64, S.g + kMlpW3, S.g + kMlpB3, dp, S.dz, dz,
                    true);
-    dense_backward(m.wq, qW2, 64, 64, &S.hs[0][0][0], 64, S.g + kMlpW2, S.g + kMlpB2, dz, S.dz, dp,
+    dense_backward(wl, qW2, 64, 64, &S.hs[0][0][0], 64, S.g + kMlpW2, S.g + kMlpB2, dz, S.dz, dp,
                    true);
-    dense_backward(m.wq, qW1, 64, 80, &S.xs[0][0], 80, S.g + kMlpW1, S.g + kMlpB1, dp, S.dz, dz,
+    dense_backward(wl, qW1, 64, 80, &S.xs[0][0], 80, S.g + kMlpW1, S.g + kMlpB1, dp, S.dz, dz,
                    false);
     __syncthreads();
   }
