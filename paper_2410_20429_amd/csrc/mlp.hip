@@ -20,11 +20,14 @@ namespace mars {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// binary32 -> bfloat16, round to nearest even (two neighbouring conversions
+// become one packed gfx950 conversion)
 __device__ __forceinline__ uint16_t to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0;  // NaN stays NaN
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ void to_bf16x2(float x, float y, uint16_t* hx, uint16_t* hy) {
+  *hx = to_bf16(x);
+  *hy = to_bf16(y);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -41,12 +44,17 @@ __host__ __device__ constexpr int qindex(int p) {
        : (p >= kMlpW4 && p < kMlpB4) ? qW4 + (p - kMlpW4) : -1;
 }
 
-// features of one vertex: x = (q.xyz, n.xyz); f[(d*6+k)*2 + s] = sin/cos(2^k pi x_d)
-__device__ __forceinline__ float feature(const float* x, int k) {
-  if (k >= 72) return 0.0f;
+// features of one vertex: x = (q.xyz, n.xyz); f[(d*6+k)*2 + s] = sin/cos(2^k pi x_d).
+// Features k (even) and k + 1 are the sine and cosine of one angle.
+__device__ __forceinline__ void feature_pair(const float* x, int k, float* fs, float* fc) {
+  if (k >= 72) {
+    *fs = 0.0f;
+    *fc = 0.0f;
+    return;
+  }
   const int d = k / 12, kk = (k % 12) >> 1;
   const float a = ldexpf(x[d], kk);
-  return (k & 1) ? cospif(a) : sinpif(a);
+  sincospif(a, fs, fc);
 }
 
 // LDS written by some lanes of a wave and read by others of the same wave
@@ -77,11 +85,18 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
   for (int ks = 0; ks < 5; ++ks) {
     v4s a;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 4; r += 2) {
       const int k = 16 * ks + 4 * lg + r;
-      const uint16_t h = to_bf16(feature(x, k));
-      a[r] = (short)h;
-      if (xs) xs[lr][k] = h;
+      float fs, fc;
+      feature_pair(x, k, &fs, &fc);
+      uint16_t hs0, hc0;
+      to_bf16x2(fs, fc, &hs0, &hc0);
+      a[r] = (short)hs0;
+      a[r + 1] = (short)hc0;
+      if (xs) {
+        xs[lr][k] = hs0;
+        xs[lr][k + 1] = hc0;
+      }
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -94,13 +109,17 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
   int woff[3] = {qW2, qW3, qW4};
   for (int l = 0; l < 3; ++l) {
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+      const int j = 16 * nt + lr;
+      const float bj = master[boff[l] + j];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 16 * nt + lr;
-        const float z = acc[nt][r] + master[boff[l] + j];
-        hs[l][4 * lg + r][j] = to_bf16(fmaxf(z, 0.0f));
+      for (int r = 0; r < 4; r += 2) {
+        uint16_t h0, h1;
+        to_bf16x2(fmaxf(acc[nt][r] + bj, 0.0f), fmaxf(acc[nt][r + 1] + bj, 0.0f), &h0, &h1);
+        hs[l][4 * lg + r][j] = h0;
+        hs[l][4 * lg + r + 1][j] = h1;
       }
+    }
     if (kGroupSync) __syncthreads();
     else wave_lds_sync();
     const int ntn = l < 2 ? 4 : 1;
