@@ -214,11 +214,13 @@ def run_bdpt(args, api, torch):
 
 
 def run_mlp(args, api, torch, n_iter=14, seeds=(1, 2, 3)):
+    train_steps = args.mlp_train_steps
     """Learned-cache workload: 1920x1080 BDPT interior of 2.08M triangles,
     max path length 12.  Octree MARS and learned-cache MARS run the same
     schedule (3 classic iterations, MARS from the 4th, the network's counts
-    from the 9th; iterations of 2 spp; the network trained 64 Adam steps of
-    8192 samples after every update from the 4th iteration on; queue and tile
+    from the 9th; iterations of 2 spp; the network trained --mlp-train-steps
+    (32) Adam steps of 8192 samples after every update from the 4th iteration
+    on; queue and tile
     sizes from the autotuner before the 4th).  Efficiency
     1/(relMSE * s) of the IVW image of each against a 256 spp classic
     reference, and the mean 1/(V_I C_I) of the last 6 iterations; each pair is
@@ -256,7 +258,7 @@ def run_mlp(args, api, torch, n_iter=14, seeds=(1, 2, 3)):
                 if kind == "mlp" and i >= 3:
                     torch.cuda.synchronize()
                     tt = time.perf_counter()
-                    s.mlp_train(steps=64, batch=8192, lr=2e-3)
+                    s.mlp_train(steps=train_steps, batch=8192, lr=2e-3)
                     torch.cuda.synchronize()
                     t_train += time.perf_counter() - tt
                 torch.cuda.synchronize()
@@ -284,7 +286,7 @@ def run_mlp(args, api, torch, n_iter=14, seeds=(1, 2, 3)):
             "config": {"workload": "mlp_bdpt_1920x1080_interior2m_d12", "width": sc["width"],
                        "height": sc["height"], "triangles": int(sc["V"].shape[0]),
                        "max_depth": 12, "spp_per_iteration": 2, "reference_spp": 256,
-                       "seeds": list(seeds)},
+                       "seeds": list(seeds), "train_steps": train_steps},
             "per_seed": runs,
             "paths_per_s_mlp": px * 2 * n_iter / mlp_seconds / 1e6,
             "inv_vi_ci_ratio": float(np.exp(np.mean(np.log([r["inv_vi_ci_ratio"] for r in runs]))))}
@@ -427,6 +429,8 @@ def main():
                     help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes; "
                          "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree")
     ap.add_argument("--no-efficiency", action="store_true")
+    ap.add_argument("--mlp-train-steps", type=int, default=32,
+                    help="learned-cache workload: Adam steps of 8192 samples after each update")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "

@@ -281,7 +281,7 @@ void ensure_roots(Scene* s, size_t roots) {
   if (s->roots_cap) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     for (void* p : {(void*)s->img.Ls, (void*)s->img.beta1, (void*)s->lt.V0, (void*)s->lt.V1,
-                    (void*)s->lt.V2, (void*)s->lt.Y0, (void*)s->lt.len})
+                    (void*)s->lt.V2, (void*)s->lt.Y0, (void*)s->lt.len, (void*)s->lt.y})
       sfree(s, p);
   }
   s->img.Ls = salloc<float>(s, roots * 3);
@@ -293,6 +293,8 @@ void ensure_roots(Scene* s, size_t roots) {
     s->lt.V2 = salloc<float4>(s, roots * lm);
     s->lt.Y0 = salloc<float4>(s, roots);
     s->lt.len = salloc<uint2>(s, roots);
+    // learned cache: network outputs at the light vertices (MIS weights)
+    s->lt.y = s->mlp_on ? salloc<float>(s, roots * lm * 4) : nullptr;
   }
   s->roots_cap = roots;
   s->epoch++;
@@ -432,7 +434,15 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   }
   mars_iter_stats S{};
   S.rays_camera = roots;
-  if (s->mode == MARS_MODE_BDPT) S.rays_light = trace_light_paths(s, it, roots);
+  if (s->mode == MARS_MODE_BDPT) {
+    S.rays_light = trace_light_paths(s, it, roots);
+    // learned-cache iterations: the network's counts at the light vertices,
+    // which the connections' MIS weights evaluate as if on the camera side
+    if (p->alloc == MARS_ALLOC_MLP && s->lt.y)
+      timed(s->ctx, KID_MLP, [&] {
+        k_mlp_infer_light(s->sd, s->lt, s->mlp, (uint32_t)roots, s->ctx->cu * 32, st);
+      });
+  }
   const uint32_t tile = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
   std::vector<std::pair<uint32_t, uint32_t>> work;
   for (size_t r = roots; r > 0;) {

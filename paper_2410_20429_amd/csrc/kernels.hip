@@ -651,20 +651,32 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
   }
 }
 
-// learned cache (alloc mode 3): beta_t = |T / I~| exp(y_t), clamped; the
-// octree count stays where the network output is not finite
-__device__ __forceinline__ void mlp_counts(const CacheDev& c, const IterDev& it, size_t e, f3 T,
-                                           const float* It, float beta[3]) {
-  if (it.alloc != 3 || !c.mlp_y) return;
+// learned cache (alloc mode 3): from the network's outputs y at a vertex,
+// its count |T / I~| exp(y_t) (colour rule's norm) is pooled with the
+// octree's count beta_t as their geometric mean, then clamped; the octree
+// count stays where the result is not finite, and techniques it disables
+// stay off.  The network's input normal is the geometric normal as stored
+// (not turned toward the incoming ray), so that the same counts can be
+// evaluated at a light vertex for the MIS weights of bidirectional paths.
+__device__ __forceinline__ void mlp_apply(const IterDev& it, f3 T, const float* It, const float* y,
+                                          float beta[3]) {
   const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
   const float sm = sqrtf(((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f));
-  const float* y = c.mlp_y + e * 4;
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     if (!(beta[t] > 0.0f)) continue;
-    const float b = sm * expf(y[t]);
+    const float b = sqrtf(beta[t] * (sm * expf(y[t])));
     if (isfinite(b)) beta[t] = fminf(fmaxf(b, it.clamp_lo), it.clamp_hi);
   }
+}
+// in learned-cache iterations, the counts of queue entry e from the network
+__device__ __forceinline__ bool mlp_active(const CacheDev& c, const IterDev& it) {
+  return it.alloc == 3 && c.mlp_y != nullptr;
+}
+__device__ __forceinline__ void mlp_counts(const CacheDev& c, const IterDev& it, size_t e, f3 T,
+                                           const float* It, float beta[3]) {
+  if (!mlp_active(c, it)) return;
+  mlp_apply(it, T, It, c.mlp_y + e * 4, beta);
 }
 
 // training vertices for the learned cache: a seeded random subset
@@ -808,7 +820,7 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
           round_counts(beta, u.x, gam);
-          mlp_record(c, strm, x, pix, n_s, T);
+          mlp_record(c, strm, x, pix, ng, T);
         }
       }
     }
@@ -1196,8 +1208,25 @@ __device__ __forceinline__ PV prim_vertex(const SceneDev& sc, f3 P, uint32_t pri
   return PV{P, xyz(ng), sc.tri_mat[prim], ng.w};
 }
 
-__device__ float bdpt_weight(const SceneDev& sc, const CacheDev& c, const IterDev& it,
-                             const PV* z, int k, int t, const float* It) {
+// per-vertex record of a camera vertex (see bdpt_record): the camera-prefix
+// throughput recomputed from positions, the counts there, pF and pR terms
+struct VRec {
+  f3 T;
+  float b0, b1, b2, pF, pRg;
+};
+__device__ __forceinline__ VRec load_rec(const QueuesDev& q, int l, uint32_t e) {
+  const size_t a = (size_t)l * q.cap + e;
+  const float4 w0 = q.W0[a], w1 = q.W1[a];
+  return VRec{xyz(w0), w0.w, w1.x, w1.y, w1.z, w1.w};
+}
+__device__ __forceinline__ float mis_count(const IterDev& it, float b) {
+  return it.aware ? b : (b > 0.0f ? 1.0f : 0.0f);
+}
+// full-path weight of strategy t for the path z_0..z_k whose camera
+// vertices z_1..z_{k-1} are the queue entries ez[1..k-1] (their counts are
+// read from their records, the counts their samples were drawn with)
+__device__ float bdpt_weight(const SceneDev& sc, const QueuesDev& q, const IterDev& it,
+                             const PV* z, const uint32_t* ez, int k, int t) {
   if (k <= 1) return 1.0f;
   float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
       nL[kMaxDepth + 2];
@@ -1225,27 +1254,11 @@ __device__ float bdpt_weight(const SceneDev& sc, const CacheDev& c, const IterDe
     eval_facing(load_mat(sc.mats + 8 * (size_t)z[i + 1].mat), z[i + 1].ng, wo, wi, &fc, &p);
     pR[i] = (p * fabsf(dot3(z[i].ng, wi))) / d2;
   }
-  f3 T = mk3(1.0f, 1.0f, 1.0f);
-  const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
   for (int i = 1; i <= k - 1; ++i) {
-    float b[3];
-    const uint32_t cell = cell_of(c.nodes, olo, sc.oct_inv, z[i].P);
-    counts_at(sc, c, it, cell, T, It, i, b);
-    nB[i] = it.aware ? b[0] : (b[0] > 0.0f ? 1.0f : 0.0f);
-    nN[i] = it.aware ? b[1] : (b[1] > 0.0f ? 1.0f : 0.0f);
-    nL[i] = it.aware ? b[2] : (b[2] > 0.0f ? 1.0f : 0.0f);
-    if (i < k - 1) {
-      const f3 wo = dir_between(z[i].P, z[i - 1].P, &d2);
-      const f3 wi = dir_between(z[i].P, z[i + 1].P, &d2);
-      f3 fc;
-      float p;
-      eval_facing(load_mat(sc.mats + 8 * (size_t)z[i].mat), z[i].ng, wo, wi, &fc, &p);
-      if (p > 0.0f && b[0] > 0.0f)
-        T = mk3(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
-                T.z * (((fc.z / p) * 1.0f) / b[0]));
-      else
-        T = mk3(0.0f, 0.0f, 0.0f);
-    }
+    const VRec r = load_rec(q, i, ez[i]);
+    nB[i] = mis_count(it, r.b0);
+    nN[i] = mis_count(it, r.b1);
+    nL[i] = mis_count(it, r.b2);
   }
   auto tf = [&](int tt) -> float {
     return tt == k + 1 ? 1.0f : (tt == k ? nN[k - 1] : nL[tt - 1]);
@@ -1394,18 +1407,6 @@ void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, C
 // the parent chain.  Each value is computed by the same operations and the
 // sums run in the same order as in bdpt_weight, so the weight is the same.
 // ---------------------------------------------------------------------------
-struct VRec {
-  f3 T;
-  float b0, b1, b2, pF, pRg;
-};
-__device__ __forceinline__ VRec load_rec(const QueuesDev& q, int l, uint32_t e) {
-  const size_t a = (size_t)l * q.cap + e;
-  const float4 w0 = q.W0[a], w1 = q.W1[a];
-  return VRec{xyz(w0), w0.w, w1.x, w1.y, w1.z, w1.w};
-}
-__device__ __forceinline__ float mis_count(const IterDev& it, float b) {
-  return it.aware ? b : (b > 0.0f ? 1.0f : 0.0f);
-}
 // the hit vertex of queue entry e at level l
 __device__ __forceinline__ PV hit_vertex(const SceneDev& sc, const QueuesDev& q, int l, uint32_t e) {
   const size_t a = (size_t)l * q.cap + e;
@@ -1417,7 +1418,8 @@ __device__ __forceinline__ PV hit_vertex(const SceneDev& sc, const QueuesDev& q,
 
 // record of the camera vertex j at depth d (hit x with geometric normal ng,
 // octree cell `cell`): pF[d] and pR[d-2] of any full path through it, the
-// camera-prefix throughput recomputed from positions and the raw counts there
+// camera-prefix throughput recomputed from positions and the counts there
+// (in learned-cache iterations the network's, as the vertex's samples use)
 __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& c,
                                             const QueuesDev& q, const IterDev& it, int d,
                                             uint32_t j, f3 x, f3 ng, uint32_t cell,
@@ -1461,6 +1463,7 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
   float b[3];
   counts_at(sc, c, it, cell, T, It, d, b);
   const size_t a = (size_t)d * q.cap + j;
+  if (mlp_active(c, it)) mlp_apply(it, T, It, c.mlp_y + a * 4, b);
   q.W0[a] = make_float4(T.x, T.y, T.z, b[0]);
   q.W1[a] = make_float4(b[1], b[2], pF, pRg);
 }
@@ -1468,9 +1471,11 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
 // weight of strategy t = d + 1 for the path z_0..z_d (camera vertex j of
 // depth d: zc, its parent zp, the camera for d = 1) continued by the
 // light-side vertices Y[0..m-1] = z_{d+1}..z_k (z_k on the emitter)
+// ly: in learned-cache iterations, the network outputs of the light subpath's
+// vertices (light vertex i at ly[4 (i - 1)]), z_{d+1} being light vertex li0
 __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                                  const IterDev& it, int d, uint32_t j, const PV& zc, const PV& zp,
-                                 const PV* Y, int m, const float* It) {
+                                 const PV* Y, int m, const float* It, const float* ly, int li0) {
   const int k = d + m, t = d + 1;
   auto Z = [&](int i) -> const PV& { return i == d ? zc : (i == d - 1 ? zp : Y[i - d - 1]); };
   float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
@@ -1506,8 +1511,11 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
   const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
   for (int i = d; i <= k - 1; ++i) {
     if (i > d) {
+      // a light vertex in the role of a camera vertex: the counts a camera
+      // path would draw there (the same count function as the sampling)
       const uint32_t cell = cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
       counts_at(sc, c, it, cell, T, It, i, b);
+      if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
     }
     nB[i] = mis_count(it, b[0]);
     nN[i] = mis_count(it, b[1]);
@@ -1568,14 +1576,16 @@ constexpr uint32_t kConnNee = 1u, kConnLight = 2u;
 // primitive prim, reached along dir) from the parent chain
 __device__ __forceinline__ void camera_prefix(const SceneDev& sc, const QueuesDev& q, int d,
                                               uint32_t j, f3 x, f3 ng, uint32_t prim, f3 dir,
-                                              PV* z) {
+                                              PV* z, uint32_t* ez) {
   z[0].P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
   z[0].ng = dir;
   z[0].mat = 0;
   z[0].lpdf = 0.0f;
   z[d] = PV{x, ng, sc.tri_mat[prim], sc.tri_ng[prim].w};
+  ez[d] = j;
   uint32_t e = ubits(q.S0[(size_t)d * q.cap + j].w);
   for (int l = d - 1; l >= 1; --l) {
+    ez[l] = e;
     const size_t ee = (size_t)l * q.cap + e;
     const float4 a0 = q.R0[ee], a1 = q.R1[ee];
     const uint2 ah = q.H[ee];
@@ -1602,6 +1612,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
   const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
   uint32_t my_vert = 0, my_samp = 0, my_ext = 0;
   PV z[2 * kMaxDepth + 4];
+  uint32_t ez[kMaxDepth + 2];
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t j = base + threadIdx.x;
     const bool active = j < n;
@@ -1637,8 +1648,8 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
         if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
           float w = 1.0f;
           if (d > 1) {
-            camera_prefix(sc, q, d, j, x, ng, prim, dir, z);
-            w = bdpt_weight(sc, c, it, z, d, d + 1, It);
+            camera_prefix(sc, q, d, j, x, ng, prim, dir, z, ez);
+            w = bdpt_weight(sc, q, it, z, ez, d, d + 1);
           }
           Ew = mk3(w * m[5], w * m[6], w * m[7]);
         }
@@ -1655,7 +1666,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
           round_counts(beta, u.x, gam);
-          mlp_record(c, strm, x, pix, n_s, T);
+          mlp_record(c, strm, x, pix, ng, T);
           const int imax0 = sc.max_depth - d - 1;
           for (uint32_t k = 0; k < gam[2]; ++k) {
             const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
@@ -1825,7 +1836,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
         const float pN = (lng.w * d2) / cl;
         Y[0] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
-        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It);
+        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0);
         const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
         sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
@@ -1860,7 +1871,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
         }
         const float4 y0r = lt.Y0[lpi];
         Y[i] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
-        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It);
+        const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
+        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i);
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;

@@ -166,8 +166,17 @@ void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream
   mlp_infer_inputs_kernel<<<std::min(tiles, 8192), 64, 0, s>>>(m, x6, n, y3);
 }
 
+// network inputs of a vertex: position normalised to the octree cube, and
+// the geometric normal as stored
+__device__ __forceinline__ void mlp_input(const SceneDev& sc, f3 p, f3 ng, float* x) {
+  x[0] = fminf(fmaxf((p.x - sc.oct_lo[0]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[1] = fminf(fmaxf((p.y - sc.oct_lo[1]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[2] = fminf(fmaxf((p.z - sc.oct_lo[2]) * sc.oct_inv, 0.0f), kOneMinus);
+  x[3] = ng.x; x[4] = ng.y; x[5] = ng.z;
+}
+
 // inference at the vertices of one depth's queue (hits with d < D): inputs
-// from the hit point and the shading normal, outputs to m.y[d * cap + j].
+// from the hit point and the geometric normal, outputs to m.y[d * cap + j].
 // The bfloat16 weights are copied once per workgroup into LDS; each of its
 // four waves then runs 16-sample tiles of the queue.
 constexpr int kInferWaves = 4;
@@ -197,11 +206,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_queue_kernel(Scene
         const float t = __uint_as_float(h.x);
         const f3 ng = xyz(sc.tri_ng[h.y]);
         const f3 p = mk3(r0.x + t * r1.x, r0.y + t * r1.y, r0.z + t * r1.z);
-        const f3 ns = dot3(ng, xyz(r1)) < 0.0f ? ng : mk3(-ng.x, -ng.y, -ng.z);
-        x[0] = fminf(fmaxf((p.x - sc.oct_lo[0]) * sc.oct_inv, 0.0f), kOneMinus);
-        x[1] = fminf(fmaxf((p.y - sc.oct_lo[1]) * sc.oct_inv, 0.0f), kOneMinus);
-        x[2] = fminf(fmaxf((p.z - sc.oct_lo[2]) * sc.oct_inv, 0.0f), kOneMinus);
-        x[3] = ns.x; x[4] = ns.y; x[5] = ns.z;
+        mlp_input(sc, p, ng, x);
       }
     }
     const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
@@ -218,6 +223,51 @@ void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, 
                        int d, int grid, hipStream_t s) {
   // three workgroups (53 KB of LDS each) per CU; grid = 32 per CU
   mlp_infer_queue_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, cnt, d);
+}
+
+// inference at the stored light vertices (bidirectional learned-cache
+// iterations): light vertex i of the subpath of root r (entry e = r * lmax +
+// i - 1, stored when the subpath has at least i vertices), outputs to
+// lt.y[4 e]; the MIS weights evaluate the network's counts there as if the
+// vertex were on the camera side.  A tile holds vertex i of 16 consecutive
+// subpaths, so that the tiles of the deep vertices, which few subpaths reach,
+// are skipped whole.
+__global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_light_kernel(SceneDev sc, LightDev lt,
+                                                                           MlpDev m, uint32_t roots) {
+  __shared__ uint4 wl4[kQW / 8];
+  __shared__ uint16_t hs[kInferWaves][3][16][64];
+  const uint32_t lm = (uint32_t)lt.lmax, rt = (roots + 15) / 16, ntiles = rt * lm;
+  if ((size_t)blockIdx.x * kInferWaves >= ntiles) return;
+  for (int k = threadIdx.x; k < kQW / 8; k += blockDim.x)
+    wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
+  __syncthreads();
+  const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
+  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile < ntiles;
+       tile += gridDim.x * kInferWaves) {
+    const uint32_t i = tile / rt;            // vertex index - 1
+    const uint32_t r0 = (tile % rt) * 16;    // first subpath of the tile
+    const uint32_t r = r0 + lr;
+    const bool valid = r < roots && i < lt.len[min(r, roots - 1)].x;
+    if (!__any(valid)) continue;             // wave-uniform
+    float x[6] = {0, 0, 0, 0, 0, 0};
+    if (valid) {
+      const float4 v0 = lt.V0[(size_t)r * lm + i];
+      mlp_input(sc, xyz(v0), xyz(sc.tri_ng[__float_as_uint(v0.w)]), x);
+    }
+    const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t rq = r0 + 4 * lg + q;
+      if (rq < roots && lr < 3) lt.y[((size_t)rq * lm + i) * 4 + lr] = y[q];
+    }
+    wave_lds_sync();
+  }
+}
+void k_mlp_infer_light(const SceneDev& sc, const LightDev& lt, const MlpDev& m, uint32_t roots,
+                       int grid, hipStream_t s) {
+  if (roots && lt.lmax > 0)
+    mlp_infer_light_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, lt, m, roots);
 }
 
 // ---------------------------------------------------------------------------

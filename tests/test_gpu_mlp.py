@@ -178,3 +178,32 @@ def test_mlp_render_unbiased_and_gain(ctx):
     # the learned cache's gain over the plain octree on this seeded
     # configuration (target: at least the octree's efficiency)
     assert effs["mlp"] >= 1.0 * effs["octree"], effs
+
+
+def test_mlp_bdpt_furnace_unbiased(ctx):
+    """Bidirectional MARS with the learned cache in the white furnace, with a
+    network whose counts vary strongly over the scene: the MIS weights of
+    every strategy evaluate the count function the samples are drawn with
+    (the network's at the camera vertices, from their records, and at the
+    light vertices for the strategies that would have reached them from the
+    camera side), so the weights of a path sum to one and the estimate keeps
+    the closed-form mean."""
+    api = _api()
+    sc = scenegen.make_furnace(48, 48)
+    g = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=5, mlp=True)
+    params = M.init_params(11)
+    p = M.unpack(params)
+    p["W4"][:3] *= 10.0  # log-count outputs with a spread of about +-2
+    g.set_mlp_params(M.pack(p).astype(np.float32))
+    L = []
+    for it in range(10):
+        alloc = api.ALLOC_CLASSIC if it < 1 else (api.ALLOC_MARS if it < 2 else api.ALLOC_MLP)
+        par = api.iter_params(iteration=it, spp=4, stat_clamp=0.0, alloc=alloc, clamp_hi=6.0)
+        g.render_iteration(par)
+        if it >= 2:
+            L.append(g.sample_radiance()[:, 0].copy())
+        g.update(par)
+    L = np.concatenate(L)
+    z = (L.mean() - 1.9375) / (L.std() / math.sqrt(len(L)))
+    say("bdpt furnace with the learned cache: mean", L.mean(), "z", z)
+    assert abs(z) < 4.0, (L.mean(), z)
