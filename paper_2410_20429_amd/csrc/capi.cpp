@@ -347,6 +347,13 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
     timed(c, KID_LIGHT, [&] { k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st); });
     for (int i = 1; i <= s->lt.lmax; ++i) {
       timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc); });
+      // learned-cache iterations: the network's counts at the new light
+      // vertices, which the connections' MIS weights evaluate as if on the
+      // camera side
+      if (it.alloc == MARS_ALLOC_MLP && s->lt.y)
+        timed(c, KID_MLP, [&] {
+          k_mlp_infer_light(s->sd, s->qd, s->mlp, s->lt, s->cnt, i, c->cu * 32, st);
+        });
       timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st); });
     }
   }
@@ -434,15 +441,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   }
   mars_iter_stats S{};
   S.rays_camera = roots;
-  if (s->mode == MARS_MODE_BDPT) {
-    S.rays_light = trace_light_paths(s, it, roots);
-    // learned-cache iterations: the network's counts at the light vertices,
-    // which the connections' MIS weights evaluate as if on the camera side
-    if (p->alloc == MARS_ALLOC_MLP && s->lt.y)
-      timed(s->ctx, KID_MLP, [&] {
-        k_mlp_infer_light(s->sd, s->lt, s->mlp, (uint32_t)roots, s->ctx->cu * 32, st);
-      });
-  }
+  if (s->mode == MARS_MODE_BDPT) S.rays_light = trace_light_paths(s, it, roots);
   const uint32_t tile = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
   std::vector<std::pair<uint32_t, uint32_t>> work;
   for (size_t r = roots; r > 0;) {

@@ -203,8 +203,8 @@ void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const
 void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream_t s);
 void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
                        int d, int grid, hipStream_t s);
-void k_mlp_infer_light(const SceneDev& sc, const LightDev& lt, const MlpDev& m, uint32_t roots,
-                       int grid, hipStream_t s);
+void k_mlp_infer_light(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const LightDev& lt,
+                       const Counters* cnt, int i, int grid, hipStream_t s);
 void k_mlp_train_pass(const MlpDev& m, const float* x6, const float* tgt, const float* wt, int n_set,
                       int offset, int batch, int* nblocks_out, hipStream_t s);
 void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, float bc1, float bc2,

@@ -225,49 +225,58 @@ void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, 
   mlp_infer_queue_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, cnt, d);
 }
 
-// inference at the stored light vertices (bidirectional learned-cache
-// iterations): light vertex i of the subpath of root r (entry e = r * lmax +
-// i - 1, stored when the subpath has at least i vertices), outputs to
-// lt.y[4 e]; the MIS weights evaluate the network's counts there as if the
-// vertex were on the camera side.  A tile holds vertex i of 16 consecutive
-// subpaths, so that the tiles of the deep vertices, which few subpaths reach,
-// are skipped whole.
-__global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_light_kernel(SceneDev sc, LightDev lt,
-                                                                           MlpDev m, uint32_t roots) {
+// inference at the light vertices of bounce i (bidirectional learned-cache
+// iterations), on the light queue (level 0) between its traversal and the
+// light shading: a hit of the light ray of root r is light vertex i of r's
+// subpath, and its outputs go to lt.y[4 (r * lmax + i - 1)] (each root has
+// one light ray per bounce).  The MIS weights evaluate the network's counts
+// there as if the vertex were on the camera side.
+__global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_light_kernel(SceneDev sc, QueuesDev q,
+                                                                           MlpDev m, LightDev lt,
+                                                                           const Counters* cnt,
+                                                                           int i) {
   __shared__ uint4 wl4[kQW / 8];
   __shared__ uint16_t hs[kInferWaves][3][16][64];
-  const uint32_t lm = (uint32_t)lt.lmax, rt = (roots + 15) / 16, ntiles = rt * lm;
-  if ((size_t)blockIdx.x * kInferWaves >= ntiles) return;
+  const uint32_t n = min(cnt->n_ray[0], (uint32_t)q.cap);
+  if ((size_t)blockIdx.x * kInferWaves * 16 >= n) return;
   for (int k = threadIdx.x; k < kQW / 8; k += blockDim.x)
     wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
   __syncthreads();
   const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
-  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile < ntiles;
+  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile * 16 < n;
        tile += gridDim.x * kInferWaves) {
-    const uint32_t i = tile / rt;            // vertex index - 1
-    const uint32_t r0 = (tile % rt) * 16;    // first subpath of the tile
-    const uint32_t r = r0 + lr;
-    const bool valid = r < roots && i < lt.len[min(r, roots - 1)].x;
-    if (!__any(valid)) continue;             // wave-uniform
+    const uint32_t s = tile * 16 + lr;
     float x[6] = {0, 0, 0, 0, 0, 0};
-    if (valid) {
-      const float4 v0 = lt.V0[(size_t)r * lm + i];
-      mlp_input(sc, xyz(v0), xyz(sc.tri_ng[__float_as_uint(v0.w)]), x);
+    float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint2 h = make_uint2(0u, kMiss);
+    if (s < n) {
+      r0 = q.R0[s];
+      h = q.H[s];
+    }
+    const bool hit = r0.w != 0.0f && h.y != kMiss;
+    if (!__any(hit)) continue;  // no light vertex in the tile (wave-uniform)
+    if (hit) {
+      const float4 r1 = q.R1[s];
+      const float t = __uint_as_float(h.x);
+      const f3 p = mk3(r0.x + t * r1.x, r0.y + t * r1.y, r0.z + t * r1.z);
+      mlp_input(sc, p, xyz(sc.tri_ng[h.y]), x);
     }
     const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t rq = r0 + 4 * lg + q;
-      if (rq < roots && lr < 3) lt.y[((size_t)rq * lm + i) * 4 + lr] = y[q];
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t si = tile * 16 + 4 * lg + r;
+      if (si < n && lr < 3) {
+        const uint32_t root = __float_as_uint(q.R1[si].w);
+        lt.y[((size_t)root * lt.lmax + (i - 1)) * 4 + lr] = y[r];
+      }
     }
     wave_lds_sync();
   }
 }
-void k_mlp_infer_light(const SceneDev& sc, const LightDev& lt, const MlpDev& m, uint32_t roots,
-                       int grid, hipStream_t s) {
-  if (roots && lt.lmax > 0)
-    mlp_infer_light_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, lt, m, roots);
+void k_mlp_infer_light(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const LightDev& lt,
+                       const Counters* cnt, int i, int grid, hipStream_t s) {
+  mlp_infer_light_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, lt, cnt, i);
 }
 
 // ---------------------------------------------------------------------------
