@@ -4,11 +4,13 @@
 // could otherwise exceed the bound), then collapsed to a 4-wide tree: each
 // node takes up to four descendants, expanding the inner child of largest
 // surface area first.
-// Output layout (128 B = one cache line per node, depth-first order):
-//   float4 lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4] of the four
-//   child boxes, int4 child references, float4 unused;
+// Output layout (128 B = one cache line per node, depth-first order): four
+// 32-byte child records, child k at bytes [32k, 32k + 32):
+//   float lo.x, lo.y, lo.z, int32 reference, float hi.x, hi.y, hi.z, unused;
 //   reference >= 0: node index; < 0: leaf = -1 - (first << 4 | count);
-//   kBvhEmpty: no child.
+//   kBvhEmpty: no child (its box is empty: lo = +inf, hi = -inf).
+// A child's record is two aligned 16-byte words, so the lane that tests it
+// fetches it with two vector loads.
 // Traversal pushes at most 3 children per visited node and the 4-wide depth
 // is at most the binary depth, so the stack never exceeds 3 x 30 entries;
 // max_stack reports the exact bound of the built tree.
@@ -222,14 +224,14 @@ BvhResult build_bvh(const float* V, int n_tris, float pad) {
       }
     }
     float* f = &out.nodes[(size_t)id * 32];
-    for (int a = 0; a < 3; ++a)
-      for (int k = 0; k < 4; ++k) {
-        f[4 * a + k] = lo[a][k];
-        f[12 + 4 * a + k] = hi[a][k];
-      }
     for (int k = 0; k < 4; ++k) {
+      float* c = f + 8 * k;
+      for (int a = 0; a < 3; ++a) {
+        c[a] = lo[a][k];
+        c[4 + a] = hi[a][k];
+      }
       const uint32_t u = (uint32_t)ref[k];
-      std::memcpy(&f[24 + k], &u, 4);
+      std::memcpy(&c[3], &u, 4);
     }
     return {id, std::max(0, inner - 1) + sub};
   };

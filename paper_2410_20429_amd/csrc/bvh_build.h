@@ -9,7 +9,7 @@ namespace mars {
 constexpr int32_t kBvhEmpty = 0x7FFFFFFF;
 
 struct BvhResult {
-  std::vector<float> nodes;        // [n_nodes][32] floats (128 B per 4-wide node)
+  std::vector<float> nodes;        // [n_nodes][4 children][8] floats (128 B per 4-wide node)
   std::vector<float> tris;         // [n_tris][12] floats, leaf order
   std::vector<int32_t> prim_order; // leaf order -> primitive index
   int max_depth = 0;  // of the binary tree

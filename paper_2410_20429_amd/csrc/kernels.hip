@@ -199,9 +199,10 @@ void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterD
 }
 
 // ---------------------------------------------------------------------------
-// BVH traversal.  Node (128 B): four child boxes as SoA float4s and four
-// child references (>= 0 inner node, < 0 leaf = -1 - (first << 4 | count),
-// kBvhNoChild unused).  Leaf children are intersected as soon as their box
+// BVH traversal.  Node (128 B): four 32-byte child records, each a float4
+// (lo.x, lo.y, lo.z, reference bits) and a float4 (hi.x, hi.y, hi.z, -);
+// reference >= 0 inner node, < 0 leaf = -1 - (first << 4 | count),
+// kBvhNoChild unused.  Leaf children are intersected as soon as their box
 // is hit; the nearest inner child is visited next and the others are pushed.
 // traverse() is the one-lane form (instrumented runs count node visits with
 // it); traverse_quad() is the four-lane form every other launch uses.
@@ -228,29 +229,32 @@ __device__ __forceinline__ float box_near(const RayInv& r, float lx, float ly, f
   return (tn <= tf && tf >= 0.0f && tn <= tmax) ? tn : INFINITY;
 }
 
-// Moller-Trumbore, two-sided, fixed operation order
+// Moller-Trumbore, two-sided, fixed operation order.  Evaluated without
+// early exits (a wave's lanes rarely all leave at the same test, and the
+// three loads then go out together); the hit conditions are the rejections
+// det == 0, u < 0, u > 1, v < 0, u + v > 1 negated, so a NaN u or v is
+// rejected only by the caller's test of t.  *t is written in every case and
+// is meaningful only when the result is true.
 __device__ __forceinline__ bool tri_hit(f3 o, f3 d, float4 A, float4 B, float4 Cc, float* t) {
   const f3 v0 = xyz(A), e1 = xyz(B), e2 = xyz(Cc);
   const f3 p = cross3(d, e2);
   const float det = dot3(e1, p);
-  if (det == 0.0f) return false;
   const float inv = 1.0f / det;
   const f3 s = sub3(o, v0);
   const float u = dot3(s, p) * inv;
-  if (u < 0.0f || u > 1.0f) return false;
   const f3 qv = cross3(s, e1);
   const float v = dot3(d, qv) * inv;
-  if (v < 0.0f || u + v > 1.0f) return false;
   *t = dot3(e2, qv) * inv;
-  return true;
+  return (det != 0.0f) & !(u < 0.0f) & !(u > 1.0f) & !(v < 0.0f) & !(u + v > 1.0f);
 }
 
 // ordered swap of two (distance, reference) pairs
 __device__ __forceinline__ void cswap(float& ta, int& ra, float& tb, int& rb) {
-  if (tb < ta) {
-    const float t = ta; ta = tb; tb = t;
-    const int r = ra; ra = rb; rb = r;
-  }
+  // selects, not a branch: the pair is swapped iff tb < ta
+  const bool sw = tb < ta;
+  const float lo = sw ? tb : ta, hi = sw ? ta : tb;
+  const int rlo = sw ? rb : ra, rhi = sw ? ra : rb;
+  ta = lo; tb = hi; ra = rlo; rb = rhi;
 }
 
 // 4-wide BVH traversal.  Leaf children are intersected when their box is
@@ -278,15 +282,15 @@ __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float t
   while (true) {
     const float4* N = sc.bvh + (size_t)node * 8;
     if (kCount) ++*n_nodes;
-    const float4 lx = N[0], ly = N[1], lz = N[2], hx = N[3], hy = N[4], hz = N[5];
-    const float4 rf = N[6];
-    int r0 = (int)ubits(rf.x), r1 = (int)ubits(rf.y), r2 = (int)ubits(rf.z), r3 = (int)ubits(rf.w);
+    const float4 a0 = N[0], b0 = N[1], a1 = N[2], b1 = N[3];
+    const float4 a2 = N[4], b2 = N[5], a3 = N[6], b3 = N[7];
+    int r0 = (int)ubits(a0.w), r1 = (int)ubits(a1.w), r2 = (int)ubits(a2.w), r3 = (int)ubits(a3.w);
     // all four boxes tested unconditionally (branch-free, on the loaded
     // registers), unused slots masked afterwards
-    float t0 = box_near(ri, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, bt);
-    float t1 = box_near(ri, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, bt);
-    float t2 = box_near(ri, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, bt);
-    float t3 = box_near(ri, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, bt);
+    float t0 = box_near(ri, a0.x, a0.y, a0.z, b0.x, b0.y, b0.z, bt);
+    float t1 = box_near(ri, a1.x, a1.y, a1.z, b1.x, b1.y, b1.z, bt);
+    float t2 = box_near(ri, a2.x, a2.y, a2.z, b2.x, b2.y, b2.z, bt);
+    float t3 = box_near(ri, a3.x, a3.y, a3.z, b3.x, b3.y, b3.z, bt);
     t0 = r0 == kBvhNoChild ? INFINITY : t0;
     t1 = r1 == kBvhNoChild ? INFINITY : t1;
     t2 = r2 == kBvhNoChild ? INFINITY : t2;
@@ -447,12 +451,17 @@ __device__ __forceinline__ int quad_xor(int v) {
 }
 // (t, primitive) minimum over the quad: smaller t, ties by smaller index
 __device__ __forceinline__ void quad_min_hit(float& t, uint32_t& p) {
+  // non-short-circuit conditions and selects keep the reduction branch-free
   float t2 = __int_as_float(quad_xor<1>(__float_as_int(t)));
   uint32_t p2 = (uint32_t)quad_xor<1>((int)p);
-  if (t2 < t || (t2 == t && p2 < p)) { t = t2; p = p2; }
+  bool take = (t2 < t) | ((t2 == t) & (p2 < p));
+  t = take ? t2 : t;
+  p = take ? p2 : p;
   t2 = __int_as_float(quad_xor<2>(__float_as_int(t)));
   p2 = (uint32_t)quad_xor<2>((int)p);
-  if (t2 < t || (t2 == t && p2 < p)) { t = t2; p = p2; }
+  take = (t2 < t) | ((t2 == t) & (p2 < p));
+  t = take ? t2 : t;
+  p = take ? p2 : p;
 }
 __device__ __forceinline__ bool quad_any(bool b) {
   int v = b ? 1 : 0;
@@ -471,11 +480,11 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
   int sp = 0;
   int node = 0;
   while (true) {
-    // child `sub` of the node: its box bounds and reference (SoA node layout)
-    const float* N = reinterpret_cast<const float*>(sc.bvh + (size_t)node * 8) + sub;
-    const float lx = N[0], ly = N[4], lz = N[8], hx = N[12], hy = N[16], hz = N[20];
-    const int rs = __float_as_int(N[24]);
-    float ts = box_near(ri, lx, ly, lz, hx, hy, hz, bt);
+    // child `sub` of the node: its record's two 16-byte words
+    const float4* N = sc.bvh + (size_t)node * 8 + 2 * sub;
+    const float4 ca = N[0], cb = N[1];
+    const int rs = __float_as_int(ca.w);
+    float ts = box_near(ri, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, bt);
     ts = rs == kBvhNoChild ? INFINITY : ts;
     float t0 = quad_bcast<0>(ts), t1 = quad_bcast<1>(ts), t2 = quad_bcast<2>(ts),
           t3 = quad_bcast<3>(ts);
@@ -493,24 +502,27 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       uint32_t hp = kMiss;
       bool hit = false;
       for (uint32_t m = (uint32_t)sub; m < ntri; m += 4) {
-        const int ref = m < p1 ? r0 : m < p2 ? r1 : m < p3 ? r2 : r3;
-        const uint32_t off = m < p1 ? m : m < p2 ? m - p1 : m < p3 ? m - p2 : m - p3;
-        const uint32_t k = ((uint32_t)(-1 - ref) >> 4) + off;
+        // the leaf holding triangle m and m's offset in it, by selects
+        const bool b1 = m >= p1, b2 = m >= p2, b3 = m >= p3;
+        const int ref = b3 ? r3 : b2 ? r2 : b1 ? r1 : r0;
+        const uint32_t base = b3 ? p3 : b2 ? p2 : b1 ? p1 : 0u;
+        const uint32_t k = ((uint32_t)(-1 - ref) >> 4) + (m - base);
         const float4* T = sc.tri_bvh + (size_t)k * 3;
         const float4 A = T[0];
         float t;
-        if (!tri_hit(o, d, A, T[1], T[2], &t)) continue;
-        if (!(t > 0.0f && t < tmax)) continue;
+        const bool h = tri_hit(o, d, A, T[1], T[2], &t) & (t > 0.0f) & (t < tmax);
         const uint32_t prim = ubits(A.w);
         if (kAny) {
-          hit = true;
-          ht = t;
-          hp = prim;
-          break;
-        }
-        if (t < ht || (t == ht && prim < hp)) {
-          ht = t;
-          hp = prim;
+          if (h) {
+            hit = true;
+            ht = t;
+            hp = prim;
+            break;
+          }
+        } else {
+          const bool take = h & ((t < ht) | ((t == ht) & (prim < hp)));
+          ht = take ? t : ht;
+          hp = take ? prim : hp;
         }
       }
       if (kAny) {
@@ -521,10 +533,9 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
         }
       } else {
         quad_min_hit(ht, hp);
-        if (ht < bt || (ht == bt && hp < bp)) {
-          bt = ht;
-          bp = hp;
-        }
+        const bool take = (ht < bt) | ((ht == bt) & (hp < bp));
+        bt = take ? ht : bt;
+        bp = take ? hp : bp;
       }
     }
     if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;

@@ -17,7 +17,7 @@ constexpr int32_t kBvhNoChild = 0x7FFFFFFF;  // unused slot of a 4-wide node
 
 // scene on the device (read-only during an iteration)
 struct SceneDev {
-  const float4* bvh;       // [n_nodes][8]: four child boxes (SoA) + child references
+  const float4* bvh;       // [n_nodes][4][2]: per child (lo.xyz, reference), (hi.xyz, -)
   const float4* tri_bvh;   // [n_tris][3] leaf order: (v0, prim bits), (e1, 0), (e2, 0)
   const float4* tri_geo;   // [n_tris][3] primitive order: v0, e1, e2
   const float4* tri_ng;    // [n_tris] primitive order: (geometric normal, p_select / area)
