@@ -248,13 +248,24 @@ __device__ __forceinline__ bool tri_hit(f3 o, f3 d, float4 A, float4 B, float4 C
   return (det != 0.0f) & !(u < 0.0f) & !(u > 1.0f) & !(v < 0.0f) & !(u + v > 1.0f);
 }
 
-// ordered swap of two (distance, reference) pairs
-__device__ __forceinline__ void cswap(float& ta, int& ra, float& tb, int& rb) {
-  // selects, not a branch: the pair is swapped iff tb < ta
-  const bool sw = tb < ta;
-  const float lo = sw ? tb : ta, hi = sw ? ta : tb;
+// Visit order of the inner children of a node: by entry distance clamped at
+// 0 (every box holding the ray origin is entered at 0), children within 4
+// ulps of each other by slot.  The key is the distance's bit pattern with its
+// two low bits replaced by the slot, compared as an unsigned integer, so the
+// keys of a node are distinct; a culled child has key >= kKeyCulled.  Any
+// visit order gives the same closest hit (ties go to the smaller primitive
+// index), so the order only decides how much is visited.
+constexpr uint32_t kKeyCulled = 0x7F800000u;  // bits of +infinity
+__device__ __forceinline__ uint32_t visit_key(float t, int slot) {
+  return ((uint32_t)max(__float_as_int(t), 0) & ~3u) | (uint32_t)slot;
+}
+
+// ordered swap of two (key, reference) pairs, by selects
+__device__ __forceinline__ void kswap(uint32_t& ka, int& ra, uint32_t& kb, int& rb) {
+  const bool sw = kb < ka;
+  const uint32_t lo = sw ? kb : ka, hi = sw ? ka : kb;
   const int rlo = sw ? rb : ra, rhi = sw ? ra : rb;
-  ta = lo; tb = hi; ra = rlo; rb = rhi;
+  ka = lo; kb = hi; ra = rlo; rb = rhi;
 }
 
 // 4-wide BVH traversal.  Leaf children are intersected when their box is
@@ -323,20 +334,20 @@ __device__ __forceinline__ bool traverse(const SceneDev& sc, f3 o, f3 d, float t
       }
     }
     // inner children still in front of the closest hit (a box entered at
-    // exactly bt may hold an equal-t hit of smaller index)
-    if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
-    if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
-    if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
-    if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
-    cswap(t0, r0, t1, r1);
-    cswap(t2, r2, t3, r3);
-    cswap(t0, r0, t2, r2);
-    cswap(t1, r1, t3, r3);
-    cswap(t1, r1, t2, r2);
-    if (t0 != INFINITY) {
-      if (t3 != INFINITY) push(r3);
-      if (t2 != INFINITY) push(r2);
-      if (t1 != INFINITY) push(r1);
+    // exactly bt may hold an equal-t hit of smaller index), sorted by key
+    uint32_t k0 = visit_key((r0 >= 0 && t0 <= bt) ? t0 : INFINITY, 0);
+    uint32_t k1 = visit_key((r1 >= 0 && t1 <= bt) ? t1 : INFINITY, 1);
+    uint32_t k2 = visit_key((r2 >= 0 && t2 <= bt) ? t2 : INFINITY, 2);
+    uint32_t k3 = visit_key((r3 >= 0 && t3 <= bt) ? t3 : INFINITY, 3);
+    kswap(k0, r0, k1, r1);
+    kswap(k2, r2, k3, r3);
+    kswap(k0, r0, k2, r2);
+    kswap(k1, r1, k3, r3);
+    kswap(k1, r1, k2, r2);
+    if (k0 < kKeyCulled) {
+      if (k3 < kKeyCulled) push(r3);
+      if (k2 < kKeyCulled) push(r2);
+      if (k1 < kKeyCulled) push(r1);
       node = r0;
     } else {
       if (sp == 0) break;
@@ -422,15 +433,18 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
 }
 // ---------------------------------------------------------------------------
 // Quad traversal: four lanes per ray.  Lane s of a quad loads and tests
-// child s of the node; the quad's four (entry distance, reference) pairs are
-// gathered into every lane with quad permutes and sorted alike, so all four
-// lanes take the decisions of traverse(): the same visit order, the same
-// stack and the same result.  The triangles of a hit leaf are dealt
-// round-robin to the four lanes and the quad's closest hit is reduced in the
-// (t, primitive index) order, which is the order traverse() keeps.  Every
-// branch below is taken alike by the four lanes of a quad (their inputs are
-// quad-uniform), except the per-lane triangle loop, which closes before the
-// reductions, so the permutes never read a lane of the quad that is off.
+// child s of the node.  The hit leaf children are broadcast to the quad as
+// (first << 4 | count) words, their triangles numbered in child order and
+// dealt round-robin to the four lanes; the quad's closest hit is reduced in
+// the (t, primitive index) order, which is the order traverse() keeps.  Each
+// lane then ranks its own inner child among the quad's four visit keys (read
+// with quad rotations), and two quad reductions give every lane the number of
+// children to visit and the nearest one; lane s pushes its child by rank, far
+// first.  The quad thus takes the decisions of traverse(): the same visit
+// order, the same stack and the same result.  Every branch below is taken
+// alike by the four lanes of a quad (their inputs are quad-uniform), except
+// the per-lane triangle loop, which closes before the reductions, so the
+// permutes never read a lane of the quad that is off.
 // ---------------------------------------------------------------------------
 constexpr int kQuadsPerBlock = kTraceBlock / 4;
 constexpr int kQuadStack = 4 * kStackDepth;      // LDS entries per ray
@@ -441,13 +455,19 @@ __device__ __forceinline__ int quad_bcast(int v) {
   return __builtin_amdgcn_mov_dpp(v, k * 0x55, 0xF, 0xF, false);
 }
 template <int k>
-__device__ __forceinline__ float quad_bcast(float v) {
-  return __int_as_float(quad_bcast<k>(__float_as_int(v)));
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
+  return (uint32_t)quad_bcast<k>((int)v);
 }
 // value of lane (s ^ m) of the quad
 template <int m>
 __device__ __forceinline__ int quad_xor(int v) {
   return __builtin_amdgcn_mov_dpp(v, m == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+// value of lane (s + m) & 3 of the quad
+template <int m>
+__device__ __forceinline__ uint32_t quad_rot(uint32_t v) {
+  constexpr int ctrl = (m & 3) | (((1 + m) & 3) << 2) | (((2 + m) & 3) << 4) | (((3 + m) & 3) << 6);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
 }
 // (t, primitive) minimum over the quad: smaller t, ties by smaller index
 __device__ __forceinline__ void quad_min_hit(float& t, uint32_t& p) {
@@ -486,17 +506,12 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
     const int rs = __float_as_int(ca.w);
     float ts = box_near(ri, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, bt);
     ts = rs == kBvhNoChild ? INFINITY : ts;
-    float t0 = quad_bcast<0>(ts), t1 = quad_bcast<1>(ts), t2 = quad_bcast<2>(ts),
-          t3 = quad_bcast<3>(ts);
-    int r0 = quad_bcast<0>(rs), r1 = quad_bcast<1>(rs), r2 = quad_bcast<2>(rs),
-        r3 = quad_bcast<3>(rs);
-    // the triangles of the leaf children hit here (at most 4 per leaf),
-    // numbered in child order and dealt round-robin to the quad's lanes
-    const uint32_t c0 = (r0 < 0 && t0 != INFINITY) ? ((uint32_t)(-1 - r0) & 15u) : 0u;
-    const uint32_t c1 = (r1 < 0 && t1 != INFINITY) ? ((uint32_t)(-1 - r1) & 15u) : 0u;
-    const uint32_t c2 = (r2 < 0 && t2 != INFINITY) ? ((uint32_t)(-1 - r2) & 15u) : 0u;
-    const uint32_t c3 = (r3 < 0 && t3 != INFINITY) ? ((uint32_t)(-1 - r3) & 15u) : 0u;
-    const uint32_t p1 = c0, p2 = p1 + c1, p3 = p2 + c2, ntri = p3 + c3;
+    // the quad's hit leaf children and their triangle counts (at most 4 each)
+    const uint32_t lw = (rs < 0 && ts != INFINITY) ? (uint32_t)(-1 - rs) : 0u;
+    const uint32_t w0 = quad_bcast<0>(lw), w1 = quad_bcast<1>(lw), w2 = quad_bcast<2>(lw),
+                   w3 = quad_bcast<3>(lw);
+    const uint32_t p1 = w0 & 15u, p2 = p1 + (w1 & 15u), p3 = p2 + (w2 & 15u),
+                   ntri = p3 + (w3 & 15u);
     if (ntri != 0u) {
       float ht = INFINITY;
       uint32_t hp = kMiss;
@@ -504,9 +519,9 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       for (uint32_t m = (uint32_t)sub; m < ntri; m += 4) {
         // the leaf holding triangle m and m's offset in it, by selects
         const bool b1 = m >= p1, b2 = m >= p2, b3 = m >= p3;
-        const int ref = b3 ? r3 : b2 ? r2 : b1 ? r1 : r0;
+        const uint32_t w = b3 ? w3 : b2 ? w2 : b1 ? w1 : w0;
         const uint32_t base = b3 ? p3 : b2 ? p2 : b1 ? p1 : 0u;
-        const uint32_t k = ((uint32_t)(-1 - ref) >> 4) + (m - base);
+        const uint32_t k = (w >> 4) + (m - base);
         const float4* T = sc.tri_bvh + (size_t)k * 3;
         const float4 A = T[0];
         float t;
@@ -538,32 +553,38 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
         bp = take ? hp : bp;
       }
     }
-    if (!(r0 >= 0 && t0 <= bt)) t0 = INFINITY;
-    if (!(r1 >= 0 && t1 <= bt)) t1 = INFINITY;
-    if (!(r2 >= 0 && t2 <= bt)) t2 = INFINITY;
-    if (!(r3 >= 0 && t3 <= bt)) t3 = INFINITY;
-    cswap(t0, r0, t1, r1);
-    cswap(t2, r2, t3, r3);
-    cswap(t0, r0, t2, r2);
-    cswap(t1, r1, t3, r3);
-    cswap(t1, r1, t2, r2);
-    if (t0 != INFINITY) {
-      // the hit children other than the nearest, far first: r_s goes to
-      // sp + k - s, written by lane s
-      const int k = (t1 != INFINITY ? 1 : 0) + (t2 != INFINITY ? 1 : 0) + (t3 != INFINITY ? 1 : 0);
-      if (sub >= 1 && sub <= k) {
-        const int pos = sp + k - sub;
-        const int v = sub == 1 ? r1 : sub == 2 ? r2 : r3;
-        if (pos < kQuadStack) stk[pos * kQuadStride + qcol] = v;
-        else sc.stack_spill[(size_t)(pos - kQuadStack) * sc.spill_threads + qid] = v;
+    // this lane's inner child, if still in front of the closest hit (a box
+    // entered at exactly bt may hold an equal-t hit of smaller index): its
+    // key, its rank among the quad's keys, the number of children to visit
+    // and the nearest child
+    const uint32_t key = visit_key((rs >= 0 && ts <= bt) ? ts : INFINITY, sub);
+    const uint32_t q1 = quad_rot<1>(key), q2 = quad_rot<2>(key), q3 = quad_rot<3>(key);
+    const int rank = (q1 < key ? 1 : 0) + (q2 < key ? 1 : 0) + (q3 < key ? 1 : 0);
+    const bool live = key < kKeyCulled;
+    int nlive = live ? 1 : 0;
+    nlive += quad_xor<1>(nlive);
+    nlive += quad_xor<2>(nlive);
+    int nearest = (live && rank == 0) ? rs : -1;
+    nearest = max(nearest, quad_xor<1>(nearest));
+    nearest = max(nearest, quad_xor<2>(nearest));
+    if (nlive != 0) {
+      // the live children other than the nearest, far first: rank j goes to
+      // sp + nlive - 1 - j
+      if (live && rank != 0) {
+        const int pos = sp + nlive - 1 - rank;
+        if (pos < kQuadStack) stk[pos * kQuadStride + qcol] = rs;
+        else sc.stack_spill[(size_t)(pos - kQuadStack) * sc.spill_threads + qid] = rs;
       }
-      sp += k;
-      node = r0;
+      sp += nlive - 1;
+      node = nearest;
     } else {
       if (sp == 0) break;
       --sp;
-      node = sp < kQuadStack ? stk[sp * kQuadStride + qcol]
-                             : sc.stack_spill[(size_t)(sp - kQuadStack) * sc.spill_threads + qid];
+      // (the LDS read through an LDS-qualified pointer, so that it is not
+      // merged with the spill read into one generic-address load)
+      node = sp < kQuadStack
+                 ? ((__attribute__((address_space(3))) int*)stk)[sp * kQuadStride + qcol]
+                 : sc.stack_spill[(size_t)(sp - kQuadStack) * sc.spill_threads + qid];
     }
   }
   *bt_out = bt;
