@@ -354,7 +354,7 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
         timed(c, KID_MLP, [&] {
           k_mlp_infer_light(s->sd, s->qd, s->mlp, s->lt, s->cnt, i, c->cu * 32, st);
         });
-      timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st); });
+      timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st); });
     }
   }
   Counters hc;
@@ -879,7 +879,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
       k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st);
       for (int i = 1; i <= s->lt.lmax; ++i) {
         k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc);
-        k_light_shade(s->sd, s->qd, s->lt, s->cnt, it, i, grid, st);
+        k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st);
       }
     }
   }

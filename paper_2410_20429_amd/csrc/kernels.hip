@@ -1365,8 +1365,8 @@ void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, C
 }
 
 // stores light vertex y_i and continues with throughput RR and BSDF sampling
-__global__ void light_shade_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counters* cnt,
-                                   IterDev it, int i) {
+__global__ void light_shade_kernel(SceneDev sc, const uint32_t* __restrict__ oct_nodes, QueuesDev q,
+                                   LightDev lt, Counters* cnt, IterDev it, int i) {
   const uint32_t n = min(cnt->n_ray[0], (uint32_t)q.cap);
   const Key key{sc.key0, sc.key1};
   uint32_t my_rays = 0;
@@ -1390,7 +1390,11 @@ __global__ void light_shade_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counte
     const size_t e = (size_t)root * lt.lmax + (i - 1);
     lt.V0[e] = make_float4(x.x, x.y, x.z, fbits(h.y));
     lt.V1[e] = make_float4(wo.x, wo.y, wo.z, al.x);
-    lt.V2[e] = make_float4(al.y, al.z, 0.0f, 0.0f);
+    // the octree cell of y_i, which every connection to it evaluates counts
+    // in (the octree is fixed until the iteration's update)
+    const uint32_t ycell =
+        cell_of(oct_nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
+    lt.V2[e] = make_float4(al.y, al.z, fbits(ycell), 0.0f);
     lt.len[root] = make_uint2((uint32_t)i, lt.len[root].y + 1u);
     bool alive = false;
     if (i < lt.lmax) {
@@ -1425,9 +1429,9 @@ __global__ void light_shade_kernel(SceneDev sc, QueuesDev q, LightDev lt, Counte
   const uint32_t sr = wave_sum(my_rays);
   if ((threadIdx.x & 63) == 0 && sr) atomicAdd(&cnt->rays_light, (unsigned long long)sr);
 }
-void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
-                   const IterDev& it, int bounce, int grid, hipStream_t s) {
-  light_shade_kernel<<<grid, 256, 0, s>>>(sc, q, lt, cnt, it, bounce);
+void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                   Counters* cnt, const IterDev& it, int bounce, int grid, hipStream_t s) {
+  light_shade_kernel<<<grid, 256, 0, s>>>(sc, c.nodes, q, lt, cnt, it, bounce);
 }
 
 // ---------------------------------------------------------------------------
@@ -1505,9 +1509,11 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
 // light-side vertices Y[0..m-1] = z_{d+1}..z_k (z_k on the emitter)
 // ly: in learned-cache iterations, the network outputs of the light subpath's
 // vertices (light vertex i at ly[4 (i - 1)]), z_{d+1} being light vertex li0
+// ycell: the octree cells of Y[0..m-2] when known (else looked up here)
 __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                                  const IterDev& it, int d, uint32_t j, const PV& zc, const PV& zp,
-                                 const PV* Y, int m, const float* It, const float* ly, int li0) {
+                                 const PV* Y, int m, const float* It, const float* ly, int li0,
+                                 const uint32_t* ycell) {
   const int k = d + m, t = d + 1;
   auto Z = [&](int i) -> const PV& { return i == d ? zc : (i == d - 1 ? zp : Y[i - d - 1]); };
   float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
@@ -1545,7 +1551,7 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
     if (i > d) {
       // a light vertex in the role of a camera vertex: the counts a camera
       // path would draw there (the same count function as the sampling)
-      const uint32_t cell = cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
+      const uint32_t cell = ycell ? ycell[i - d - 1] : cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
       counts_at(sc, c, it, cell, T, It, i, b);
       if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
     }
@@ -1822,6 +1828,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
   const size_t L = (size_t)d * q.cap;
   uint32_t my_sh = 0, my_conn = 0;
   PV Y[kMaxDepth + 1];
+  uint32_t ycell[kMaxDepth + 1];
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     const size_t e = L + s;
     const float4 s0 = q.SH0[e], s1 = q.SH1[e];
@@ -1868,7 +1875,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
         const float pN = (lng.w * d2) / cl;
         Y[0] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
-        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0);
+        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0, nullptr);
         const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
         sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
@@ -1900,11 +1907,12 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
         for (int jj = 1; jj <= i; ++jj) {
           const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
           Y[jj - 1] = prim_vertex(sc, xyz(pv), ubits(pv.w));
+          ycell[jj - 1] = ubits(lt.V2[(size_t)lpi * lt.lmax + (i - jj)].z);
         }
         const float4 y0r = lt.Y0[lpi];
         Y[i] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
         const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
-        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i);
+        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i, ycell);
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;

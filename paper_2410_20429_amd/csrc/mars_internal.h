@@ -100,7 +100,7 @@ constexpr int kTileWords = 2 * (kMaxDepth + 2) + 1;
 struct LightDev {
   float4* V0;     // [root][lmax]: position y_i, primitive (bits)
   float4* V1;     // [root][lmax]: direction towards y_{i-1}, alpha.r
-  float4* V2;     // [root][lmax]: alpha.g, alpha.b, -, -
+  float4* V2;     // [root][lmax]: alpha.g, alpha.b, octree cell of y_i (bits), -
   float4* Y0;     // [root]: point on the emitter, emitter primitive (bits)
   uint2* len;     // [root]: vertices stored, rays traced
   float* y;       // [root][lmax][4]: learned-cache outputs at the light vertices (null if none)
@@ -189,8 +189,8 @@ void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, co
                    const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s);
 void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
                    const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s);
-void k_light_shade(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
-                   const IterDev& it, int bounce, int grid, hipStream_t s);
+void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                   Counters* cnt, const IterDev& it, int bounce, int grid, hipStream_t s);
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s);
