@@ -490,24 +490,53 @@ __device__ __forceinline__ bool quad_any(bool b) {
   return v != 0;
 }
 
-template <bool kAny>
+// Each ray is traced by 4^kSplit quads (kSplit = 0, 1, 2).  With kSplit > 0
+// the quads split the top kSplit levels of the tree: quad g follows child
+// (g >> 2l) & 3 at level l, a leaf met on that descent is intersected by the
+// one quad whose remaining digits are 0, and below the split each quad
+// traverses its subtree as usual.  Every leaf is reached by exactly one quad.
+// The quads of a ray share *sh (LDS): the bits of the smallest hit distance
+// found so far, which every quad culls with, or for any-hit rays a found
+// flag, on which the others stop.  Each quad returns its own closest hit; the
+// caller reduces them in the (t, primitive) order.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+template <bool kAny, int kSplit>
 __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
-                                              int sub, int qcol, size_t qid, float* bt_out,
-                                              uint32_t* bp_out) {
+                                              int sub, int qcol, uint32_t qid, int g, lds_u32* sh,
+                                              float* bt_out, uint32_t* bp_out) {
   const RayInv ri = ray_inv(o, d);
-  float bt = tmax;
+  float bt = tmax;  // this quad's closest hit so far (and the culling distance)
   uint32_t bp = kMiss;
   int sp = 0;
   int node = 0;
+  // while splitting: levels still to split (bits 4..) and the digits of the
+  // path below this level (bits 0..3, the next digit in bits 0..1)
+  uint32_t split = ((uint32_t)kSplit << 4) | (uint32_t)g;
   while (true) {
+    float cut = bt;
+    if (kSplit > 0) {
+      const uint32_t v = *(volatile lds_u32*)sh;
+      if (kAny) {
+        if (v != 0u) break;
+      } else {
+        cut = fminf(bt, __uint_as_float(v));
+      }
+    }
     // child `sub` of the node: its record's two 16-byte words
     const float4* N = sc.bvh + (size_t)node * 8 + 2 * sub;
     const float4 ca = N[0], cb = N[1];
     const int rs = __float_as_int(ca.w);
-    float ts = box_near(ri, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, bt);
+    float ts = box_near(ri, ca.x, ca.y, ca.z, cb.x, cb.y, cb.z, cut);
     ts = rs == kBvhNoChild ? INFINITY : ts;
+    // while splitting, only the child on this quad's path counts, and a leaf
+    // there only for the quad whose remaining digits are 0
+    bool mine = true, leaf_mine = true;
+    if (kSplit > 0 && split >= 16u) {
+      mine = (uint32_t)sub == (split & 3u);
+      leaf_mine = mine && (split & 12u) == 0u;
+    }
     // the quad's hit leaf children and their triangle counts (at most 4 each)
-    const uint32_t lw = (rs < 0 && ts != INFINITY) ? (uint32_t)(-1 - rs) : 0u;
+    const uint32_t lw = (rs < 0 && ts != INFINITY && leaf_mine) ? (uint32_t)(-1 - rs) : 0u;
     const uint32_t w0 = quad_bcast<0>(lw), w1 = quad_bcast<1>(lw), w2 = quad_bcast<2>(lw),
                    w3 = quad_bcast<3>(lw);
     const uint32_t p1 = w0 & 15u, p2 = p1 + (w1 & 15u), p3 = p2 + (w2 & 15u),
@@ -542,6 +571,7 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       }
       if (kAny) {
         if (quad_any(hit)) {
+          if (kSplit > 0 && sub == 0) *(volatile lds_u32*)sh = 1u;
           *bt_out = ht;
           *bp_out = hp;
           return true;
@@ -551,13 +581,17 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
         const bool take = (ht < bt) | ((ht == bt) & (hp < bp));
         bt = take ? ht : bt;
         bp = take ? hp : bp;
+        // hit distances are positive, so their bits order as the distances
+        if (kSplit > 0 && take && sub == 0)
+          __hip_atomic_fetch_min(sh, __float_as_uint(bt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        cut = fminf(cut, bt);
       }
     }
     // this lane's inner child, if still in front of the closest hit (a box
-    // entered at exactly bt may hold an equal-t hit of smaller index): its
-    // key, its rank among the quad's keys, the number of children to visit
-    // and the nearest child
-    const uint32_t key = visit_key((rs >= 0 && ts <= bt) ? ts : INFINITY, sub);
+    // entered at exactly the cut may hold an equal-t hit of smaller index):
+    // its key, its rank among the quad's keys, the number of children to
+    // visit and the nearest child
+    const uint32_t key = visit_key((rs >= 0 && ts <= cut && mine) ? ts : INFINITY, sub);
     const uint32_t q1 = quad_rot<1>(key), q2 = quad_rot<2>(key), q3 = quad_rot<3>(key);
     const int rank = (q1 < key ? 1 : 0) + (q2 < key ? 1 : 0) + (q3 < key ? 1 : 0);
     const bool live = key < kKeyCulled;
@@ -577,6 +611,7 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       }
       sp += nlive - 1;
       node = nearest;
+      if (kSplit > 0 && split >= 16u) split = ((split - 16u) & ~15u) | ((split & 15u) >> 2);
     } else {
       if (sp == 0) break;
       --sp;
@@ -592,40 +627,98 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
   return bp != kMiss;
 }
 
-// The rays of trace_pair_kernel, one quad per ray (rays q, q + Q, ... for
-// quad q of Q); lane 0 of the quad writes the result.
-__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_quad_kernel(SceneDev sc, QueuesDev q,
-                                                                 const Counters* cnt, int dc,
-                                                                 int ds) {
-  __shared__ int stk[kQuadStack * kQuadStride];
-  if (cnt->overflow) return;
-  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
-  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
-  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+// LDS writes of some lanes of a wave made visible to reads by other lanes of
+// the same wave: the writes complete (workgroup-scope release), no code moves
+// across (wave barrier), then the reads (acquire)
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The rays of one launch with 4^kSplit quads per ray: ray j is traced by the
+// quads of group j mod R (R groups), quad g of its group taking its share of
+// the tree; the group's first lane writes the result.
+template <int kSplit>
+__device__ __forceinline__ void trace_rays(const SceneDev& sc, const QueuesDev& q, uint32_t nc,
+                                           uint32_t ns, size_t Lc, size_t Ls, int* stk,
+                                           uint32_t* shared_t, uint2* res) {
+  constexpr int kLog = 2 * kSplit;
   const int sub = threadIdx.x & 3, qcol = threadIdx.x >> 2;
-  const size_t qid = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  const uint32_t Q = gridDim.x * (blockDim.x >> 2);
-  for (uint32_t j = (uint32_t)qid; j < nc + ns; j += Q) {
+  const uint32_t qid = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const int g = (int)(qid & ((1u << kLog) - 1u));
+  const uint32_t R = (gridDim.x * (blockDim.x >> 2)) >> kLog;
+  lds_u32* sh = (lds_u32*)shared_t + (qcol >> kLog);
+  const bool lead = g == 0 && sub == 0;
+  for (uint32_t j = (uint32_t)(qid >> kLog); j < nc + ns; j += R) {
     float t;
     uint32_t p;
     if (j < nc) {
       const float4 r0 = q.R0[Lc + j];
-      uint2 h = make_uint2(ubits(INFINITY), kMiss);
-      if (r0.w != 0.0f) {
-        const float4 r1 = q.R1[Lc + j];
-        if (traverse_quad<false>(sc, xyz(r0), xyz(r1), INFINITY, stk, sub, qcol, qid, &t, &p))
-          h = make_uint2(ubits(t), p);
+      if (r0.w == 0.0f) {
+        if (lead) q.H[Lc + j] = make_uint2(ubits(INFINITY), kMiss);
+        continue;
       }
-      if (sub == 0) q.H[Lc + j] = h;
+      const float4 r1 = q.R1[Lc + j];
+      if (kSplit > 0) {
+        if (lead) *sh = ubits(INFINITY);
+        wave_lds_fence();
+      }
+      const bool hit =
+          traverse_quad<false, kSplit>(sc, xyz(r0), xyz(r1), INFINITY, stk, sub, qcol, qid, g, sh, &t, &p);
+      uint2 h = hit ? make_uint2(ubits(t), p) : make_uint2(ubits(INFINITY), kMiss);
+      if (kSplit > 0) {
+        // the group's closest hit: smallest t, ties by smaller primitive
+        if (sub == 0) res[qcol] = h;
+        wave_lds_fence();
+        if (lead) {
+          for (int k = 1; k < (1 << kLog); ++k) {
+            const uint2 o = res[qcol + k];
+            const float to = fbits(o.x), th = fbits(h.x);
+            if (to < th || (to == th && o.y < h.y)) h = o;
+          }
+        }
+        wave_lds_fence();
+      }
+      if (lead) q.H[Lc + j] = h;
     } else {
       const uint32_t k = j - nc;
       const float4 v = q.SH2[Ls + k];
       if (v.w == 0.0f) continue;
       const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
-      if (traverse_quad<true>(sc, xyz(a), xyz(b), a.w, stk, sub, qcol, qid, &t, &p) && sub == 0)
-        q.SH2[Ls + k] = make_float4(0.0f, 0.0f, 0.0f, v.w);
+      if (kSplit > 0) {
+        if (lead) *sh = 0u;
+        wave_lds_fence();
+      }
+      bool hit = traverse_quad<true, kSplit>(sc, xyz(a), xyz(b), a.w, stk, sub, qcol, qid, g, sh, &t, &p);
+      if (kSplit > 0) {
+        wave_lds_fence();
+        hit = *(volatile lds_u32*)sh != 0u;
+        wave_lds_fence();
+      }
+      if (hit && lead) q.SH2[Ls + k] = make_float4(0.0f, 0.0f, 0.0f, v.w);
     }
   }
+}
+
+// The rays of trace_pair_kernel: one quad per ray, or when the launch has at
+// most a quarter (a sixteenth) as many rays as resident quads, 4 (16) quads
+// per ray, so that the few rays of the deep bounces finish sooner.
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_quad_kernel(SceneDev sc, QueuesDev q,
+                                                                 const Counters* cnt, int dc,
+                                                                 int ds) {
+  __shared__ int stk[kQuadStack * kQuadStride];
+  __shared__ uint32_t shared_t[kQuadsPerBlock];
+  __shared__ uint2 res[kQuadsPerBlock];
+  if (cnt->overflow) return;
+  const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+  const uint32_t Q = gridDim.x * (blockDim.x >> 2);
+  const uint32_t n = nc + ns;
+  if ((uint64_t)n * 16u <= Q) trace_rays<2>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
+  else if ((uint64_t)n * 4u <= Q) trace_rays<1>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
+  else trace_rays<0>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
 }
 
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
