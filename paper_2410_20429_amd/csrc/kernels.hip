@@ -704,6 +704,7 @@ __device__ __forceinline__ void trace_rays(const SceneDev& sc, const QueuesDev& 
 // The rays of trace_pair_kernel: one quad per ray, or when the launch has at
 // most a quarter (a sixteenth) as many rays as resident quads, 4 (16) quads
 // per ray, so that the few rays of the deep bounces finish sooner.
+constexpr uint64_t kSplitDiv16 = 16, kSplitDiv4 = 4;
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void trace_quad_kernel(SceneDev sc, QueuesDev q,
                                                                  const Counters* cnt, int dc,
                                                                  int ds) {
@@ -716,8 +717,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 
   const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
   const uint32_t Q = gridDim.x * (blockDim.x >> 2);
   const uint32_t n = nc + ns;
-  if ((uint64_t)n * 16u <= Q) trace_rays<2>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
-  else if ((uint64_t)n * 4u <= Q) trace_rays<1>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
+  if ((uint64_t)n * kSplitDiv16 <= Q) trace_rays<2>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
+  else if ((uint64_t)n * kSplitDiv4 <= Q) trace_rays<1>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
   else trace_rays<0>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
 }
 
