@@ -1923,7 +1923,41 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
   uint32_t my_sh = 0, my_conn = 0;
   PV Y[kMaxDepth + 1];
   uint32_t ycell[kMaxDepth + 1];
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+  // Each tile of blockDim.x entries is ranked by the length of its weight
+  // walk (NEE first, then connections by light vertex index) with a
+  // counting sort in LDS, and thread r takes the tile's r-th entry: a
+  // wave's lanes then walk paths of about one length.  Which thread takes
+  // an entry does not change what is computed for it.
+  constexpr int kKeys = kMaxDepth + 2;
+  __shared__ uint32_t key_count[kKeys];
+  __shared__ uint16_t tile_order[kConnectBlock];
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    {
+      const uint32_t sr = base + threadIdx.x;
+      uint32_t key = 0;
+      if (sr < n) {
+        const size_t er = L + sr;
+        if (ubits(q.SH1[er].x) != kConnNee) key = min(ubits(q.SH0[er].y), (uint32_t)kMaxDepth) + 1u;
+      }
+      if (threadIdx.x < kKeys) key_count[threadIdx.x] = 0u;
+      __syncthreads();
+      const uint32_t rank = sr < n ? atomicAdd(&key_count[key], 1u) : 0u;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < kKeys; ++k) {
+          const uint32_t c = key_count[k];
+          key_count[k] = acc;
+          acc += c;
+        }
+      }
+      __syncthreads();
+      if (sr < n) tile_order[key_count[key] + rank] = (uint16_t)threadIdx.x;
+      __syncthreads();
+    }
+    const uint32_t ntile = min(n - base, (uint32_t)blockDim.x);
+    const uint32_t s = base + ((uint32_t)threadIdx.x < ntile ? (uint32_t)tile_order[threadIdx.x] : 0u);
+    if ((uint32_t)threadIdx.x >= ntile) continue;
     const size_t e = L + s;
     const float4 s0 = q.SH0[e], s1 = q.SH1[e];
     const uint32_t kind = ubits(s1.x), j = ubits(s1.w);
