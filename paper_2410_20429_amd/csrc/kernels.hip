@@ -1610,81 +1610,75 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
                                  const uint32_t* ycell) {
   const int k = d + m, t = d + 1;
   auto Z = [&](int i) -> const PV& { return i == d ? zc : (i == d - 1 ? zp : Y[i - d - 1]); };
-  float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
-      nL[kMaxDepth + 2];
-  float d2;
-  for (int i = d + 1; i <= k; ++i) {
-    const f3 wo = dir_between(Z(i - 1).P, Z(i - 2).P, &d2);
-    const f3 wi = dir_between(Z(i - 1).P, Z(i).P, &d2);
-    f3 fc;
-    float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i - 1).mat), Z(i - 1).ng, wo, wi, &fc, &p);
-    pF[i] = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
-  }
-  pR[k] = Z(k).lpdf;
-  {
-    const f3 w = dir_between(Z(k).P, Z(k - 1).P, &d2);
-    const float cl = dot3(Z(k).ng, w);
-    const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
-    pR[k - 1] = (pe * fabsf(dot3(Z(k - 1).ng, w))) / d2;
-  }
-  for (int i = k - 2; i >= d - 1 && i >= 1; --i) {
+  // pR(i): the density of reaching z_i from z_{i+1} (whose outgoing
+  // direction is towards z_{i+2}) as area density at z_i; z_k's emitter pdf
+  // and z_{k-1}'s emission density at the end of the path
+  auto pR = [&](int i) -> float {
+    float d2;
+    if (i == k) return Z(k).lpdf;
+    if (i == k - 1) {
+      const f3 w = dir_between(Z(k).P, Z(k - 1).P, &d2);
+      const float cl = dot3(Z(k).ng, w);
+      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+      return (pe * fabsf(dot3(Z(k - 1).ng, w))) / d2;
+    }
     const f3 wo = dir_between(Z(i + 1).P, Z(i + 2).P, &d2);
     const f3 wi = dir_between(Z(i + 1).P, Z(i).P, &d2);
     f3 fc;
     float p;
     eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i + 1).mat), Z(i + 1).ng, wo, wi, &fc, &p);
-    pR[i] = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
-  }
-  // counts at z_d (its record) and along the light side
+    return (p * fabsf(dot3(Z(i).ng, wi))) / d2;
+  };
+  // counts at z_d (its record); t's own technique count
   const VRec rd = load_rec(q, d, j);
   f3 T = rd.T;
   float b[3] = {rd.b0, rd.b1, rd.b2};
   const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
-  for (int i = d; i <= k - 1; ++i) {
-    if (i > d) {
-      // a light vertex in the role of a camera vertex: the counts a camera
-      // path would draw there (the same count function as the sampling)
-      const uint32_t cell = ycell ? ycell[i - d - 1] : cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
-      counts_at(sc, c, it, cell, T, It, i, b);
-      if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
-    }
-    nB[i] = mis_count(it, b[0]);
-    nN[i] = mis_count(it, b[1]);
-    nL[i] = mis_count(it, b[2]);
-    if (i < k - 1) {
-      const f3 wo = dir_between(Z(i).P, Z(i - 1).P, &d2);
-      const f3 wi = dir_between(Z(i).P, Z(i + 1).P, &d2);
-      f3 fc;
-      float p;
-      eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i).mat), Z(i).ng, wo, wi, &fc, &p);
+  float nB_prev = mis_count(it, b[0]);
+  const float tft = t == k ? mis_count(it, b[1]) : mis_count(it, b[2]);
+  if (!(tft > 0.0f)) return 0.0f;
+  // the strategies tt = t + 1 .. k + 1, in that order, walking the light
+  // side one vertex z_i = z_{tt-1} at a time: the BSDF at z_{i-1} gives both
+  // pF(i) and the throughput factor into z_i, and the counts at z_i (a light
+  // vertex in the role of a camera vertex: the count function of the
+  // sampling, along the camera-prefix throughput) give tt's count products
+  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
+  for (int i = d + 1; i <= k; ++i) {
+    float d2;
+    const f3 wo = dir_between(Z(i - 1).P, Z(i - 2).P, &d2);
+    const f3 wi = dir_between(Z(i - 1).P, Z(i).P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i - 1).mat), Z(i - 1).ng, wo, wi, &fc, &p);
+    const float pFi = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
+    float tf = 1.0f;  // strategy k + 1
+    float nB_i = 0.0f;
+    if (i < k) {
       if (p > 0.0f && b[0] > 0.0f)
         T = mk3(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
                 T.z * (((fc.z / p) * 1.0f) / b[0]));
       else
         T = mk3(0.0f, 0.0f, 0.0f);
+      const uint32_t cell = ycell ? ycell[i - d - 1] : cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
+      counts_at(sc, c, it, cell, T, It, i, b);
+      if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
+      nB_i = mis_count(it, b[0]);
+      tf = i == k - 1 ? mis_count(it, b[1]) : mis_count(it, b[2]);
     }
+    rp = rp * (pFi / pR(i));
+    rb = rb * nB_prev;
+    sum = sum + (rp * rb) * (tf / tft);
+    nB_prev = nB_i;
   }
-  auto tf = [&](int tt) -> float {
-    return tt == k + 1 ? 1.0f : (tt == k ? nN[k - 1] : nL[tt - 1]);
-  };
-  const float tft = tf(t);
-  if (!(tft > 0.0f)) return 0.0f;
-  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
-  for (int tt = t + 1; tt <= k + 1; ++tt) {
-    rp = rp * (pF[tt - 1] / pR[tt - 1]);
-    rb = rb * nB[tt - 2];
-    sum = sum + (rp * rb) * (tf(tt) / tft);
-  }
-  // camera side, walking up the parent chain: pF[tt] of vertex tt, pR[tt] of
-  // vertex tt + 2 (tt <= d - 2), counts of vertex tt - 1
+  // camera side, walking up the parent chain: pF of vertex tt, pR of vertex
+  // tt + 2 (tt <= d - 2), counts of vertex tt - 1
   rp = 1.0f;
   rb = 1.0f;
   VRec cur = rd;
   uint32_t ecur = j;
   float prg1 = 0.0f, prg2 = 0.0f;
   for (int tt = d; tt >= 2; --tt) {
-    const float pRt = tt >= d - 1 ? pR[tt] : prg2;
+    const float pRt = tt >= d - 1 ? pR(tt) : prg2;
     const uint32_t epar = ubits(q.S0[(size_t)tt * q.cap + ecur].w);
     const VRec par = load_rec(q, tt - 1, epar);
     rp = rp * (pRt / cur.pF);
