@@ -1354,55 +1354,55 @@ __device__ __forceinline__ float mis_count(const IterDev& it, float b) {
 __device__ float bdpt_weight(const SceneDev& sc, const QueuesDev& q, const IterDev& it,
                              const PV* z, const uint32_t* ez, int k, int t) {
   if (k <= 1) return 1.0f;
-  float pF[kMaxDepth + 2], pR[kMaxDepth + 2], nB[kMaxDepth + 2], nN[kMaxDepth + 2],
-      nL[kMaxDepth + 2];
-  float d2;
-  for (int i = 2; i <= k; ++i) {
+  // pF(i): the density of reaching z_i from z_{i-1} (incoming from z_{i-2});
+  // pR(i): of reaching z_i from z_{i+1} (incoming from z_{i+2}), z_k's
+  // emitter pdf and z_{k-1}'s emission density at the end; both as area
+  // densities at z_i, evaluated where the sums below need them
+  auto pF = [&](int i) -> float {
+    float d2;
     const f3 wo = dir_between(z[i - 1].P, z[i - 2].P, &d2);
     const f3 wi = dir_between(z[i - 1].P, z[i].P, &d2);
     f3 fc;
     float p;
     eval_facing(load_mat(sc.mats + 8 * (size_t)z[i - 1].mat), z[i - 1].ng, wo, wi, &fc, &p);
-    pF[i] = (p * fabsf(dot3(z[i].ng, wi))) / d2;
-  }
-  pR[k] = z[k].lpdf;
-  {
-    const f3 w = dir_between(z[k].P, z[k - 1].P, &d2);
-    const float cl = dot3(z[k].ng, w);
-    const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
-    pR[k - 1] = (pe * fabsf(dot3(z[k - 1].ng, w))) / d2;
-  }
-  for (int i = k - 2; i >= 1; --i) {
+    return (p * fabsf(dot3(z[i].ng, wi))) / d2;
+  };
+  auto pR = [&](int i) -> float {
+    float d2;
+    if (i == k) return z[k].lpdf;
+    if (i == k - 1) {
+      const f3 w = dir_between(z[k].P, z[k - 1].P, &d2);
+      const float cl = dot3(z[k].ng, w);
+      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+      return (pe * fabsf(dot3(z[k - 1].ng, w))) / d2;
+    }
     const f3 wo = dir_between(z[i + 1].P, z[i + 2].P, &d2);
     const f3 wi = dir_between(z[i + 1].P, z[i].P, &d2);
     f3 fc;
     float p;
     eval_facing(load_mat(sc.mats + 8 * (size_t)z[i + 1].mat), z[i + 1].ng, wo, wi, &fc, &p);
-    pR[i] = (p * fabsf(dot3(z[i].ng, wi))) / d2;
-  }
-  for (int i = 1; i <= k - 1; ++i) {
-    const VRec r = load_rec(q, i, ez[i]);
-    nB[i] = mis_count(it, r.b0);
-    nN[i] = mis_count(it, r.b1);
-    nL[i] = mis_count(it, r.b2);
-  }
-  auto tf = [&](int tt) -> float {
-    return tt == k + 1 ? 1.0f : (tt == k ? nN[k - 1] : nL[tt - 1]);
+    return (p * fabsf(dot3(z[i].ng, wi))) / d2;
   };
-  const float tft = tf(t);
+  // strategy tt's own technique count, from the record of z_{tt-1}
+  auto tf = [&](int tt, const VRec& r) -> float {
+    return tt == k + 1 ? 1.0f : (tt == k ? mis_count(it, r.b1) : mis_count(it, r.b2));
+  };
+  const float tft = t == k + 1 ? 1.0f : tf(t, load_rec(q, t - 1, ez[t - 1]));
   if (!(tft > 0.0f)) return 0.0f;
   float sum = 1.0f, rp = 1.0f, rb = 1.0f;
   for (int tt = t + 1; tt <= k + 1; ++tt) {
-    rp = rp * (pF[tt - 1] / pR[tt - 1]);
-    rb = rb * nB[tt - 2];
-    sum = sum + (rp * rb) * (tf(tt) / tft);
+    rp = rp * (pF(tt - 1) / pR(tt - 1));
+    rb = rb * mis_count(it, load_rec(q, tt - 2, ez[tt - 2]).b0);
+    const float f = tt == k + 1 ? 1.0f : tf(tt, load_rec(q, tt - 1, ez[tt - 1]));
+    sum = sum + (rp * rb) * (f / tft);
   }
   rp = 1.0f;
   rb = 1.0f;
   for (int tt = t - 1; tt >= 2; --tt) {
-    rp = rp * (pR[tt] / pF[tt]);
-    rb = rb * nB[tt - 1];
-    sum = sum + rp * (tf(tt) / (rb * tft));
+    const VRec r = load_rec(q, tt - 1, ez[tt - 1]);
+    rp = rp * (pR(tt) / pF(tt));
+    rb = rb * mis_count(it, r.b0);
+    sum = sum + rp * (tf(tt, r) / (rb * tft));
   }
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
