@@ -48,8 +48,13 @@ typedef enum {
 enum { MARS_MODE_PT = 0, MARS_MODE_PT_GUIDED = 1, MARS_MODE_BDPT = 2 };
 /* how per-vertex counts are chosen: classic throughput RR (the baseline and
  * warm-up of Sec. 4.1/5.2), the MARS fixed point (Sec. 3.1 "Optimization"),
- * fixed counts (tests of unbiasedness, supplement A.1), or the learned cache */
-enum { MARS_ALLOC_CLASSIC = 0, MARS_ALLOC_MARS = 1, MARS_ALLOC_FIXED = 2, MARS_ALLOC_MLP = 3 };
+ * fixed counts (tests of unbiasedness, supplement A.1), the learned cache, or
+ * EARS (the comparison method of Sec. 5: one count shared by every technique
+ * of a vertex, beta_t = r_t lambda with the classic ratios r, lambda from the
+ * same fixed point restricted to that line; the update of an EARS iteration
+ * keeps the shared factors in technique slot 0 of the cell factors) */
+enum { MARS_ALLOC_CLASSIC = 0, MARS_ALLOC_MARS = 1, MARS_ALLOC_FIXED = 2, MARS_ALLOC_MLP = 3,
+       MARS_ALLOC_EARS = 4 };
 /* technique slots: 0 BSDF, 1 NEE, 2 guided (PT_GUIDED) or light path (BDPT) */
 enum { MARS_TECH_BSDF = 0, MARS_TECH_NEE = 1, MARS_TECH_THIRD = 2 };
 enum { MARS_IMAGE_MEAN = 0, MARS_IMAGE_IVW = 1, MARS_IMAGE_LAST = 2 };

@@ -228,6 +228,7 @@ struct oracle {
   float *pm, *cdf;/* [maxc][64] */
   double* hacc;   /* [maxc][64] */
   float* fixed_beta; int32_t nfixed;
+  int32_t ears_update; /* the running update belongs to an EARS iteration */
   /* image */
   int32_t spp_last;
   float* Ls;      /* per root radiance [W*H*spp][3] */
@@ -814,6 +815,23 @@ static void classic_beta(const tctx* c, v3 T, int depth, float beta[3]) {
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* EARS (the baseline of Sec. 5; Fig. 1: the same number of samples for    */
+/* every technique).  Counts beta_t = r_t lambda with the per-technique    */
+/* ratios r of the classic scheme at q = 1.  On that line the efficiency   */
+/* model of Sec. 3.1 (variance sum_t V_t / beta_t, cost sum_t beta_t C_t)  */
+/* is optimal at lambda^2 = (C_I / V_I) sum_t (M_t / r_t) / sum_t r_t C_t, */
+/* with M the per-sample second moment (RR) or variance (splitting) of     */
+/* technique t: the fixed point of Sec. 3.1 restricted to that line, which */
+/* the supplemental derivation notes reduces to the EARS scheme.  The      */
+/* shared factors are kept in technique slot 0 of the cell factors.        */
+/* ------------------------------------------------------------------------ */
+static void ears_ratios(int mode, double r[3]) {
+  if (mode == ORC_MODE_PT_GUIDED) { r[0] = 0.5; r[1] = 1.0; r[2] = 0.5; }
+  else if (mode == ORC_MODE_BDPT) { r[0] = 1.0; r[1] = 1.0; r[2] = 1.0; }
+  else { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; }
+}
+
 static void vertex_beta(const tctx* c, uint32_t cell, v3 T, int depth, float beta[3]) {
   const oracle* o = c->o;
   const orc_iter_params* p = c->p;
@@ -821,6 +839,29 @@ static void vertex_beta(const tctx* c, uint32_t cell, v3 T, int depth, float bet
   classic_beta(c, T, depth, cb);
   int enabled[3] = {1, o->cfg.nee_enabled && o->nlights > 0, o->cfg.mode != ORC_MODE_PT};
   float z[3] = {T.x / c->It[0], T.y / c->It[1], T.z / c->It[2]};
+  if (p->alloc == ORC_ALLOC_EARS) {
+    const float* aRR = o->fac + ((cell * 2 + 0) * 3 + 0) * 3;
+    const float* aS = o->fac + ((cell * 2 + 1) * 3 + 0) * 3;
+    double r[3];
+    ears_ratios(o->cfg.mode, r);
+    float lam = 0.0f;
+    if (!(aRR[0] < 0.0f)) {
+      float sr = ((z[0] * z[0]) * aRR[0] + (z[1] * z[1]) * aRR[1]) + (z[2] * z[2]) * aRR[2];
+      float ss = ((z[0] * z[0]) * aS[0] + (z[1] * z[1]) * aS[1]) + (z[2] * z[2]) * aS[2];
+      float bRR = sqrtf(sr * (1.0f / 3.0f));
+      float bS = sqrtf(ss * (1.0f / 3.0f));
+      if (bRR < 1.0f) lam = bRR;
+      else if (bS > 1.0f) lam = bS;
+      else lam = 1.0f;
+      lam = fminf(fmaxf(lam, p->clamp_lo), p->clamp_hi);
+    }
+    for (int t = 0; t < 3; ++t) {
+      if (!enabled[t]) beta[t] = 0.0f;
+      else if (aRR[0] < 0.0f) beta[t] = cb[t]; /* no data yet: classic */
+      else beta[t] = (float)r[t] * lam;
+    }
+    return;
+  }
   for (int t = 0; t < 3; ++t) {
     float b;
     if (!enabled[t]) { beta[t] = 0.0f; continue; }
@@ -1184,8 +1225,44 @@ int32_t orc_update_cells_only(oracle* o, double V_I, double C_I) {
         o->fac[((cidx * 2 + 1) * 3 + t) * 3 + ch] = (float)(k * var);
       }
     }
+    if (o->ears_update) {
+      /* the shared EARS factors of the cell, into technique slot 0 */
+      double r[3], num[2][3] = {{0, 0, 0}, {0, 0, 0}}, den = 0.0;
+      int any = 0;
+      ears_ratios(o->cfg.mode, r);
+      for (int t = 0; t < 3; ++t) {
+        const double* a = o->acc + ((size_t)cidx * 3 + t) * 8;
+        double n = a[6];
+        if (!(r[t] > 0.0) || !(n > 0.0)) continue;
+        double Ct = a[7] / n;
+        if (!(Ct > 0.0)) continue;
+        any = 1;
+        den = den + r[t] * Ct;
+        for (int ch = 0; ch < 3; ++ch) {
+          double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+          double var = E2 - E1 * E1;
+          if (var < 0.0) var = 0.0;
+          num[0][ch] = num[0][ch] + E2 / r[t];
+          num[1][ch] = num[1][ch] + var / r[t];
+        }
+      }
+      if (any) {
+        double k = C_I / V_I;
+        for (int ch = 0; ch < 3; ++ch) {
+          o->fac[((cidx * 2 + 0) * 3 + 0) * 3 + ch] = (float)(k * (num[0][ch] / den));
+          o->fac[((cidx * 2 + 1) * 3 + 0) * 3 + ch] = (float)(k * (num[1][ch] / den));
+        }
+      }
+    }
   }
   return 1;
+}
+
+int32_t orc_update_cells_ears(oracle* o, double V_I, double C_I) {
+  o->ears_update = 1;
+  int32_t r = orc_update_cells_only(o, V_I, C_I);
+  o->ears_update = 0;
+  return r;
 }
 
 /* learned directional distribution of the next iteration: 0.9 learned +  */
@@ -1315,7 +1392,9 @@ int32_t orc_update(oracle* o, const orc_iter_params* p, orc_update_stats* st) {
   double V_I = nin ? vsum / (double)nin : 0.0;
   double C_I = (double)o->rays_last / ((double)npx * (double)spp);
   int32_t nb = o->ncells;
+  o->ears_update = p && p->alloc == ORC_ALLOC_EARS;
   orc_update_cells_only(o, V_I, C_I);
+  o->ears_update = 0;
   if (o->cfg.mode == ORC_MODE_PT_GUIDED) hist_normalize(o);
   orc_refine_only(o);
   /* inverse-variance weighted combination of iterations (Sec. 5.1) */

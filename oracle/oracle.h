@@ -26,7 +26,9 @@ extern "C" {
 #endif
 
 enum { ORC_MODE_PT = 0, ORC_MODE_PT_GUIDED = 1, ORC_MODE_BDPT = 2 };
-enum { ORC_ALLOC_CLASSIC = 0, ORC_ALLOC_MARS = 1, ORC_ALLOC_FIXED = 2 };
+/* EARS: one shared count per vertex for every technique, scaled by the
+ * classic per-technique ratios (value 3 is the GPU library's learned cache) */
+enum { ORC_ALLOC_CLASSIC = 0, ORC_ALLOC_MARS = 1, ORC_ALLOC_FIXED = 2, ORC_ALLOC_EARS = 4 };
 enum { ORC_TECH_B = 0, ORC_TECH_N = 1, ORC_TECH_G = 2 }; /* third = guided or light path */
 
 typedef struct {
@@ -102,6 +104,8 @@ void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n);
 void orc_set_fixed_beta(oracle* o, const float* beta, int32_t n);
 void orc_set_hist(oracle* o, int32_t n, const float* pm, const float* cdf);
 int32_t orc_update_cells_only(oracle* o, double V_I, double C_I);
+/* the same update as an EARS iteration's: shared factors into slot 0 */
+int32_t orc_update_cells_ears(oracle* o, double V_I, double C_I);
 int32_t orc_refine_only(oracle* o);
 
 /* building blocks exported for the pin tests */

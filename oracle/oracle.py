@@ -9,7 +9,7 @@ import numpy as np
 from . import build as _build
 
 MODE_PT, MODE_PT_GUIDED, MODE_BDPT = 0, 1, 2
-ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED = 0, 1, 2
+ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_EARS = 0, 1, 2, 4
 
 
 class Config(C.Structure):
@@ -89,6 +89,8 @@ def lib():
         L.orc_set_hist.argtypes = [P, C.c_int32, P, P]
         L.orc_update_cells_only.argtypes = [P, C.c_double, C.c_double]
         L.orc_update_cells_only.restype = C.c_int32
+        L.orc_update_cells_ears.argtypes = [P, C.c_double, C.c_double]
+        L.orc_update_cells_ears.restype = C.c_int32
         L.orc_refine_only.argtypes = [P]
         L.orc_refine_only.restype = C.c_int32
         L.orc_philox.argtypes = [C.c_uint32, C.c_uint32, P, P]
@@ -259,8 +261,9 @@ class Oracle:
         cdf = np.ascontiguousarray(cdf, np.float32)
         lib().orc_set_hist(self.h, pm.shape[0], _p(pm), _p(cdf))
 
-    def update_cells_only(self, V_I, C_I):
-        return lib().orc_update_cells_only(self.h, float(V_I), float(C_I))
+    def update_cells_only(self, V_I, C_I, ears=False):
+        f = lib().orc_update_cells_ears if ears else lib().orc_update_cells_only
+        return f(self.h, float(V_I), float(C_I))
 
     def refine_only(self):
         return lib().orc_refine_only(self.h)

@@ -16,7 +16,7 @@ MARS_OK, MARS_E_ARG, MARS_E_OOM, MARS_E_HIP, MARS_E_STATE, MARS_E_OVERFLOW, MARS
 STATUS_NAMES = {0: "MARS_OK", -1: "MARS_E_ARG", -2: "MARS_E_OOM", -3: "MARS_E_HIP",
                 -4: "MARS_E_STATE", -5: "MARS_E_OVERFLOW", -6: "MARS_E_NONFINITE", -7: "MARS_E_IO"}
 MODE_PT, MODE_PT_GUIDED, MODE_BDPT = 0, 1, 2
-ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_MLP = 0, 1, 2, 3
+ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_MLP, ALLOC_EARS = 0, 1, 2, 3, 4
 IMAGE_MEAN, IMAGE_IVW, IMAGE_LAST = 0, 1, 2
 SCENE_MLP = 1
 BATCH_UPDATE, BATCH_NO_GRAPH = 1, 2

@@ -8,7 +8,7 @@ import ctypes as C
 import numpy as np
 
 from . import _capi as capi
-from ._capi import (ALLOC_CLASSIC, ALLOC_FIXED, ALLOC_MARS, ALLOC_MLP, IMAGE_IVW,  # noqa: F401
+from ._capi import (ALLOC_CLASSIC, ALLOC_EARS, ALLOC_FIXED, ALLOC_MARS, ALLOC_MLP, IMAGE_IVW,  # noqa: F401
                     IMAGE_LAST, IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, SCENE_MLP, MarsError,
                     BATCH_NO_GRAPH, BATCH_UPDATE)
 

@@ -267,7 +267,7 @@ IterDev to_dev(const mars_iter_params* p) {
 void check_params(Scene* s, const mars_iter_params* p) {
   if (!p) throw Status(MARS_E_ARG, "null params");
   if (p->spp <= 0 || p->spp > 4096) throw Status(MARS_E_ARG, "spp out of range");
-  if (p->alloc < 0 || p->alloc > 3) throw Status(MARS_E_ARG, "bad alloc mode");
+  if (p->alloc < 0 || p->alloc > 4) throw Status(MARS_E_ARG, "bad alloc mode");
   if (p->alloc == MARS_ALLOC_FIXED && !s->fixed) throw Status(MARS_E_STATE, "no fixed counts set");
   if (p->alloc == MARS_ALLOC_MLP && !s->mlp_on)
     throw Status(MARS_E_ARG, "learned cache not enabled for scene");
@@ -814,7 +814,8 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   const int nb = s->n_cells;
   timed(c, KID_FIXED_POINT, [&] {
     k_fixed_point(s->cd, s->n_cells_dev, s->img.red, C_I, nullptr, 0.0, 1, 0.0,
-                  s->mode == MARS_MODE_PT_GUIDED, s->max_cells, &s->img, npx, spp, nullptr, st);
+                  s->mode == MARS_MODE_PT_GUIDED, s->max_cells, &s->img, npx, spp, nullptr, st,
+                  p && p->alloc == MARS_ALLOC_EARS ? s->mode : -1);
   });
   if (s->mlp_on) {
     IterDev itd = p ? to_dev(p) : IterDev{};
@@ -910,7 +911,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
     k_update_image(s->img, s->W, s->H, spp, s->img.red + 6, bdpt, stat_clamp, skip, st);
     k_fixed_point(s->cd, s->n_cells_dev, s->img.red, 0.0, s->cnt, (double)roots, 1, 0.0,
                   s->mode == MARS_MODE_PT_GUIDED, s->max_cells, &s->img, s->W * s->H, spp, skip,
-                  st);
+                  st, it.alloc == MARS_ALLOC_EARS ? s->mode : -1);
     k_refine(s->cd, s->n_cells_dev, s->n_cells_dev + 1, s->scratch, s->split_visits,
              s->max_tree_depth, s->max_cells, skip, st);
   }

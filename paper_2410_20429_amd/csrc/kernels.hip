@@ -738,6 +738,18 @@ void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, i
 // classic throughput RR: q = min(1, max T) from rr_start on (baseline and
 // warm-up of Sec. 4.1 / 5.2).
 // ---------------------------------------------------------------------------
+// EARS (the baseline the paper compares against, Sec. 5: the same number of
+// samples for every technique): beta_t = r_t lambda, with the classic
+// per-technique ratios r at q = 1.  Along that line the efficiency model of
+// Sec. 3.1 is optimal at lambda^2 = (C_I / V_I) sum_t (M_t / r_t) /
+// sum_t r_t C_t (M: per-sample second moment for RR, variance for
+// splitting), the fixed point restricted to the line; the update keeps these
+// shared factors in technique slot 0.
+__host__ __device__ inline void ears_ratios(int mode, double r[3]) {
+  if (mode == 1) { r[0] = 0.5; r[1] = 1.0; r[2] = 0.5; }
+  else if (mode == 2) { r[0] = 1.0; r[1] = 1.0; r[2] = 1.0; }
+  else { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; }
+}
 __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c, const IterDev& it,
                                           uint32_t cell, f3 T, const float* It, int depth,
                                           float beta[3]) {
@@ -748,6 +760,26 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
   else { cb[0] = q; cb[1] = 1.0f; cb[2] = 0.0f; }
   const bool en[3] = {true, sc.nee != 0 && sc.n_lights > 0, sc.mode != 0};
   const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
+  if (it.alloc == 4) {
+    // EARS: one shared count lambda from technique slot 0, beta_t = r_t lambda
+    const float* aRR = c.fac + (size_t)cell * 18;
+    const float* aS = c.fac + (size_t)cell * 18 + 9;
+    double r[3];
+    ears_ratios(sc.mode, r);
+    float lam = 0.0f;
+    if (!(aRR[0] < 0.0f)) {
+      const float sr = ((z0 * z0) * aRR[0] + (z1 * z1) * aRR[1]) + (z2 * z2) * aRR[2];
+      const float ss = ((z0 * z0) * aS[0] + (z1 * z1) * aS[1]) + (z2 * z2) * aS[2];
+      const float bRR = sqrtf(sr * (1.0f / 3.0f));
+      const float bS = sqrtf(ss * (1.0f / 3.0f));
+      lam = bRR < 1.0f ? bRR : (bS > 1.0f ? bS : 1.0f);
+      lam = fminf(fmaxf(lam, it.clamp_lo), it.clamp_hi);
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      beta[t] = !en[t] ? 0.0f : (aRR[0] < 0.0f ? cb[t] : (float)r[t] * lam);
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     if (!en[t]) { beta[t] = 0.0f; continue; }
@@ -2500,7 +2532,7 @@ __device__ __forceinline__ void ivw_at(ImageDev& img, int i, int spp, const doub
 __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const double* red,
                                    double C_I, const Counters* cnt, double roots, int use_dev,
                                    double V_host, int guided, ImageDev img, int npx, int spp,
-                                   int cell_blocks, const uint32_t* skip) {
+                                   int cell_blocks, const uint32_t* skip, int ears_mode) {
   SKIP_IF(skip);
   // V_I sums (red[3], red[4]) from vi's partials; workgroup 0 stores them
   // and advances the sample total (red[6]) by this iteration's spp
@@ -2542,6 +2574,36 @@ __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const
         c.fac[(size_t)cidx * 18 + (1 * 3 + t) * 3 + ch] = (float)(k * var);
       }
     }
+    if (ears_mode >= 0) {
+      // EARS iterations: the shared factors of the cell into technique slot 0
+      // (the fixed point restricted to beta_t = r_t lambda)
+      double r[3], num[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}}, den = 0.0;
+      ears_ratios(ears_mode, r);
+      bool any = false;
+      for (int t = 0; t < 3; ++t) {
+        const double* a = c.acc + ((size_t)cidx * 3 + t) * 8;
+        const double n = a[6];
+        if (!(r[t] > 0.0) || !(n > 0.0)) continue;
+        const double Ct = a[7] / n;
+        if (!(Ct > 0.0)) continue;
+        any = true;
+        den = den + r[t] * Ct;
+        for (int ch = 0; ch < 3; ++ch) {
+          const double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+          double var = E2 - E1 * E1;
+          if (var < 0.0) var = 0.0;
+          num[0][ch] = num[0][ch] + E2 / r[t];
+          num[1][ch] = num[1][ch] + var / r[t];
+        }
+      }
+      if (any) {
+        const double k = C_I / V_I;
+        for (int ch = 0; ch < 3; ++ch) {
+          c.fac[(size_t)cidx * 18 + (0 * 3 + 0) * 3 + ch] = (float)(k * (num[0][ch] / den));
+          c.fac[(size_t)cidx * 18 + (1 * 3 + 0) * 3 + ch] = (float)(k * (num[1][ch] / den));
+        }
+      }
+    }
   }
   if (!guided) return;
   // guided distribution of the next iteration: 0.9 learned + 0.1 uniform
@@ -2563,11 +2625,11 @@ __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const
 void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
                    const Counters* cnt, double roots, int use_device_vi, double V_I_host,
                    int guided, int max_cells, const ImageDev* img, int npx, int spp,
-                   const uint32_t* skip, hipStream_t s) {
+                   const uint32_t* skip, hipStream_t s, int ears_mode) {
   const int cb = (max_cells + 255) / 256, pb = img ? (npx + 255) / 256 : 0;
   fixed_point_kernel<<<cb + pb, 256, 0, s>>>(c, n_cells_dev, red, C_I, cnt, roots, use_device_vi,
                                               V_I_host, guided, img ? *img : ImageDev{},
-                                              img ? npx : 0, spp, cb, skip);
+                                              img ? npx : 0, spp, cb, skip, ears_mode);
 }
 
 // ---------------------------------------------------------------------------

@@ -219,10 +219,12 @@ void k_update_image(const ImageDev& img, int W, int H, int spp, const double* to
                     float stat_clamp, const uint32_t* skip, hipStream_t s);
 // C_I from rays / (pixels x spp): given on the host (cnt == null) or taken
 // from the iteration totals in `cnt` plus the camera rays `roots`
+// ears_mode: the scene mode when the update belongs to an EARS iteration
+// (shared factors into technique slot 0), else -1
 void k_fixed_point(const CacheDev& c, const int32_t* n_cells_dev, const double* red, double C_I,
                    const Counters* cnt, double roots, int use_device_vi, double V_I_host,
                    int guided, int max_cells, const ImageDev* img, int npx, int spp,
-                   const uint32_t* skip, hipStream_t s);
+                   const uint32_t* skip, hipStream_t s, int ears_mode = -1);
 void k_refine(const CacheDev& c, int32_t* n_cells_dev, int32_t* n_nodes_dev, uint32_t* scratch,
               int split_visits, int max_tree_depth, int max_cells, const uint32_t* skip,
               hipStream_t s);

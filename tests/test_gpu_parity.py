@@ -181,6 +181,42 @@ def test_guided_schedule_parity(ctx):
 
 
 # ---------------------------------------------------------------------------
+# EARS allocation (one shared count per vertex): the same schedule parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["pt", "guided"])
+def test_ears_schedule_parity(ctx, mode):
+    if mode == "pt":
+        sc, kw, warm = scenegen.make_cornell(48, 40), dict(max_depth=5), 1
+    else:
+        sc = scenegen.make_heightfield_scene(seed=2, width=40, height=33, grid=24, n_boxes=12)
+        kw, warm = dict(mode=orc.MODE_PT_GUIDED, max_depth=6), 2
+    g, o = _pair(ctx, sc, **kw)
+    for it in range(5):
+        say("EARS", mode, "iteration", it)
+        alloc = orc.ALLOC_CLASSIC if it < warm else orc.ALLOC_EARS
+        pg, po = _params(iteration=it, spp=2, alloc=alloc, debug_depth=kw["max_depth"])
+        g.render_iteration(pg)
+        o.render_iteration(po)
+        _cmp_radiance(g.sample_radiance(), o.sample_radiance())
+        dg, do = g.debug_vertices(), o.debug_vertices()
+        _cmp_vertices(dg, do)
+        if alloc == orc.ALLOC_EARS:
+            # one shared factor: BSDF and guided counts at half the NEE count
+            # (guided), the BSDF count equal to it (plain PT)
+            # (below the classic RR depth, where a cell without data falls
+            # back to counts of the same shape)
+            b = do["beta"]
+            half = np.float32(0.5) if mode == "guided" else np.float32(1.0)
+            on = (b[:, 1] > 0) & (do["depth"] < 5)
+            assert on.any() and np.array_equal(b[on, 0], half * b[on, 1])
+        g.update(pg)
+        o.update(po)
+        _cmp_cells(g, o)
+        assert np.array_equal(g.nodes(), o.nodes())
+    np.testing.assert_allclose(g.image(1), o.image(1), rtol=1e-5, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
 # update kernel and refinement on identical inputs: bit-identical
 # ---------------------------------------------------------------------------
 def test_fixed_point_update_bitexact(ctx):
