@@ -107,14 +107,16 @@ def reference_image(api, ctx, sc, spp=16, iters=256, seed_iter=100000, mode=None
     return acc / iters
 
 
-def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256)):
+def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256),
+                   ears=False):
     """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
     paper's evaluation: n_iter iterations of 1, 2, 4, ... spp, the first
     three with classic RR, then MARS (render + update each); the MARS image
     is the inverse-variance weighted combination of all iterations; classic
     RR renders the same sample counts (mean image).  relMSE against a
     classic reference of ref_spp[0] x ref_spp[1] spp, 0.01% brightest
-    outliers discarded."""
+    outliers discarded.  With ears, EARS (one shared count per vertex, the
+    paper's comparison method) runs the same schedule as MARS."""
     import numpy as np
     mode = api.MODE_PT_GUIDED if mode is None else mode
     kc = 0.0 if mode == api.MODE_BDPT else 50.0
@@ -130,7 +132,7 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
             alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
             p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=kc)
             rays += s.render_iteration(p).total_rays()
-            if alloc_after == api.ALLOC_MARS:
+            if alloc_after != api.ALLOC_CLASSIC:
                 s.update(p)
             else:
                 torch.cuda.synchronize()
@@ -140,21 +142,63 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
             spp_tot += 1 << i
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        img = s.image(api.IMAGE_IVW) if alloc_after == api.ALLOC_MARS else acc / spp_tot
+        img = s.image(api.IMAGE_IVW) if alloc_after != api.ALLOC_CLASSIC else acc / spp_tot
         s.release()
         return relmse(img, ref), dt, spp_tot, rays
 
     e_m, t_m, spp, r_m = run(api.ALLOC_MARS)
     e_c, t_c, _, r_c = run(api.ALLOC_CLASSIC)
     rs = ref_spp[0] * ref_spp[1]
-    return {"definition": "1/(relMSE*s); relMSE = mean (I-R)^2/(R^2+0.01), 0.01% outliers "
-                          f"discarded, vs a {rs} spp classic reference; iterations of 1,2,4.. spp",
-            "mars": 1.0 / (e_m * t_m), "classic": 1.0 / (e_c * t_c),
-            "gain_vs_classic": (e_c * t_c) / (e_m * t_m),
-            "relmse_mars": e_m, "relmse_classic": e_c, "seconds_mars": t_m,
-            "seconds_classic": t_c, "spp": spp, "iterations": n_iter, "reference_spp": rs,
-            "rays_mars": r_m, "rays_classic": r_c,
-            "ray_efficiency_gain_vs_classic": (e_c * r_c) / (e_m * r_m)}
+    out = {"definition": "1/(relMSE*s); relMSE = mean (I-R)^2/(R^2+0.01), 0.01% outliers "
+                         f"discarded, vs a {rs} spp classic reference; iterations of 1,2,4.. spp",
+           "mars": 1.0 / (e_m * t_m), "classic": 1.0 / (e_c * t_c),
+           "gain_vs_classic": (e_c * t_c) / (e_m * t_m),
+           "relmse_mars": e_m, "relmse_classic": e_c, "seconds_mars": t_m,
+           "seconds_classic": t_c, "spp": spp, "iterations": n_iter, "reference_spp": rs,
+           "rays_mars": r_m, "rays_classic": r_c,
+           "ray_efficiency_gain_vs_classic": (e_c * r_c) / (e_m * r_m)}
+    if ears:
+        e_e, t_e, _, r_e = run(api.ALLOC_EARS)
+        out.update({"ears": 1.0 / (e_e * t_e), "gain_vs_ears": (e_e * t_e) / (e_m * t_m),
+                    "relmse_ears": e_e, "seconds_ears": t_e, "rays_ears": r_e,
+                    "rays_mars_vs_ears": r_m / r_e - 1.0,
+                    "ray_efficiency_gain_vs_ears": (e_e * r_e) / (e_m * r_m)})
+    return out
+
+
+def run_ears(args, api, torch):
+    """MARS against EARS (one count shared by every technique of a vertex,
+    the paper's comparison method) and classic RR, by the efficiency
+    protocol above: the guided 512x512 heightfield (9 iterations of 1..256
+    spp, 4096 spp reference) and the bidirectional 1280x720 interior (7
+    iterations of 1..64 spp, 1024 spp reference).  value = MARS's efficiency
+    gain over EARS on the guided scene."""
+    import scenegen
+    ctx = api.Context(0)
+    sc = scenegen.make_heightfield_scene(seed=1)
+    print("[bench] ears: guided", file=sys.stderr, flush=True)
+    g = efficiency_leg(api, ctx, sc, torch, ears=True)
+    print("[bench] ears: bdpt", file=sys.stderr, flush=True)
+    scb = scenegen.make_interior(seed=1)
+    b = efficiency_leg(api, ctx, scb, torch, n_iter=7, mode=api.MODE_BDPT, depth=12,
+                       ref_spp=(16, 64), ears=True)
+    return {"metric": "efficiency 1/(relMSE*s): MARS vs EARS (classic RR beside them)",
+            "value": g["gain_vs_ears"], "unit": "ratio", "n_gpus": 1, "steps": g["iterations"],
+            "warmup": 3, "ms_per_step": g["seconds_mars"] * 1e3 / g["iterations"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "ears_vs_mars_guided512_bdpt720",
+                       "guided": {"width": sc["width"], "height": sc["height"],
+                                  "triangles": int(sc["V"].shape[0]), "max_depth": 10},
+                       "bdpt": {"width": scb["width"], "height": scb["height"],
+                                "triangles": int(scb["V"].shape[0]), "max_depth": 12}},
+            "guided": g, "bdpt": b,
+            "paper_context": {"guided_mars_vs_ears_plus_mixture_gd": 1.32,
+                              "guided_rays_vs_ears": -0.17, "bdpt_mars_vs_ears": 1.6,
+                              "bdpt_rays_vs_ears": -0.13,
+                              "note": "10 production scenes, 5 min equal time, CPU (Mitsuba); "
+                                      "the guided comparison there also differs in the guiding "
+                                      "method (gradient-descent mixtures)"}}
 
 
 def run_bdpt(args, api, torch):
@@ -425,9 +469,11 @@ def main():
                     help="(profiling runs) skip the instrumented iteration and the CPU leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="guided", choices=["guided", "batch", "bdpt", "mlp"],
+    ap.add_argument("--workload", default="guided",
+                    choices=["guided", "batch", "bdpt", "mlp", "ears"],
                     help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes; "
-                         "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree")
+                         "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree; "
+                         "ears: MARS vs EARS vs classic RR efficiency (guided and bidirectional)")
     ap.add_argument("--no-efficiency", action="store_true")
     ap.add_argument("--mlp-train-steps", type=int, default=32,
                     help="learned-cache workload: Adam steps of 8192 samples after each update")
@@ -443,7 +489,7 @@ def main():
     from paper_2410_20429_amd import api
 
     if args.workload != "guided":
-        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp}[args.workload]
+        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp, "ears": run_ears}[args.workload]
         print(json.dumps(run(args, api, torch)), flush=True)
         return
     sc = scenegen.make_heightfield_scene(seed=1)

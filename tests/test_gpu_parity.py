@@ -183,18 +183,22 @@ def test_guided_schedule_parity(ctx):
 # ---------------------------------------------------------------------------
 # EARS allocation (one shared count per vertex): the same schedule parity
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", ["pt", "guided"])
+@pytest.mark.parametrize("mode", ["pt", "guided", "bdpt"])
 def test_ears_schedule_parity(ctx, mode):
+    extra = {}
     if mode == "pt":
         sc, kw, warm = scenegen.make_cornell(48, 40), dict(max_depth=5), 1
-    else:
+    elif mode == "guided":
         sc = scenegen.make_heightfield_scene(seed=2, width=40, height=33, grid=24, n_boxes=12)
         kw, warm = dict(mode=orc.MODE_PT_GUIDED, max_depth=6), 2
+    else:
+        sc, kw, warm = scenegen.make_cornell(40, 36), dict(mode=orc.MODE_BDPT, max_depth=5), 2
+        extra = dict(stat_clamp=0.0)
     g, o = _pair(ctx, sc, **kw)
     for it in range(5):
         say("EARS", mode, "iteration", it)
         alloc = orc.ALLOC_CLASSIC if it < warm else orc.ALLOC_EARS
-        pg, po = _params(iteration=it, spp=2, alloc=alloc, debug_depth=kw["max_depth"])
+        pg, po = _params(iteration=it, spp=2, alloc=alloc, debug_depth=kw["max_depth"], **extra)
         g.render_iteration(pg)
         o.render_iteration(po)
         _cmp_radiance(g.sample_radiance(), o.sample_radiance())
@@ -209,6 +213,8 @@ def test_ears_schedule_parity(ctx, mode):
             half = np.float32(0.5) if mode == "guided" else np.float32(1.0)
             on = (b[:, 1] > 0) & (do["depth"] < 5)
             assert on.any() and np.array_equal(b[on, 0], half * b[on, 1])
+            if mode == "bdpt":
+                assert np.array_equal(b[on, 2], b[on, 1])
         g.update(pg)
         o.update(po)
         _cmp_cells(g, o)
