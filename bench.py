@@ -336,6 +336,78 @@ def run_mlp(args, api, torch, n_iter=14, seeds=(1, 2, 3)):
             "inv_vi_ci_ratio": float(np.exp(np.mean(np.log([r["inv_vi_ci_ratio"] for r in runs]))))}
 
 
+def run_convergence(args, api, torch, seeds=(1, 2, 3), n_iter=9):
+    """Convergence of the fixed point on the guided 512x512 heightfield:
+    for MARS and EARS, per iteration of the doubling schedule (1..256 spp,
+    the first three classic RR), the mean count per technique at the first
+    hit, the method's own 1/(V_I C_I), rays per camera sample and the
+    running efficiency 1/(relMSE s) of the inverse-variance weighted image
+    against a 4096 spp classic reference; each with several random-stream
+    seeds, whose spread is the stability check.  value = the mean over seeds
+    of MARS's final efficiency divided by classic RR's at the same spp."""
+    import numpy as np
+    import scenegen
+    ctx = api.Context(0)
+    sc = scenegen.make_heightfield_scene(seed=1)
+    ref = reference_image(api, ctx, sc, spp=16, iters=256)
+    print("[bench] convergence: reference done", file=sys.stderr, flush=True)
+
+    def run(alloc_after, seed):
+        s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget(),
+                      seed=seed)
+        rows, t, spp_tot, acc = [], 0.0, 0, np.zeros_like(ref)
+        for i in range(n_iter):
+            alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
+            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=50.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.render_iteration(p)
+            us = s.update(p) if alloc_after != api.ALLOC_CLASSIC else None
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            spp_tot += 1 << i
+            cm = s.count_map().reshape(-1, 3)
+            if alloc_after == api.ALLOC_CLASSIC:
+                acc += s.image(api.IMAGE_LAST) * (1 << i)
+                img = acc / spp_tot
+            else:
+                img = s.image(api.IMAGE_IVW)
+            e = relmse(img, ref)
+            rows.append({"iteration": i, "spp": 1 << i, "alloc": int(alloc),
+                         "mean_count_first_hit": [float(v) for v in cm.mean(0)],
+                         "inv_vi_ci": (1.0 / (us.V_I * us.C_I)) if us and us.V_I > 0 else None,
+                         "rays_per_sample": st.total_rays() / float(sc["width"] * sc["height"]
+                                                                    * (1 << i)),
+                         "relmse": e, "seconds": t, "efficiency": 1.0 / (e * t)})
+        s.release()
+        return rows
+
+    out_runs = {"mars": [], "ears": [], "classic": []}
+    for seed in seeds:
+        for name, alloc in (("mars", api.ALLOC_MARS), ("ears", api.ALLOC_EARS),
+                            ("classic", api.ALLOC_CLASSIC)):
+            out_runs[name].append({"seed": seed, "rows": run(alloc, seed)})
+        print(f"[bench] convergence: seed {seed} done", file=sys.stderr, flush=True)
+
+    def final(name):
+        return np.array([r["rows"][-1]["efficiency"] for r in out_runs[name]])
+    fm, fe, fc = final("mars"), final("ears"), final("classic")
+    stab = {n: {"final_efficiency_mean": float(f.mean()),
+                "final_efficiency_cv": float(f.std() / f.mean()),
+                "final_mean_counts": [[round(v, 4) for v in r["rows"][-1]["mean_count_first_hit"]]
+                                      for r in out_runs[n]]}
+            for n, f in (("mars", fm), ("ears", fe), ("classic", fc))}
+    return {"metric": "convergence: per-iteration counts and efficiency (MARS, EARS, classic RR)",
+            "value": float(np.mean(fm / fc)), "unit": "ratio", "n_gpus": 1, "steps": n_iter,
+            "warmup": 3, "ms_per_step": float(np.mean([r["rows"][-1]["seconds"]
+                                                       for r in out_runs["mars"]])) * 1e3 / n_iter,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "convergence_guided_512x512_heightfield132k_d10",
+                       "seeds": list(seeds), "iterations": n_iter, "reference_spp": 4096},
+            "mars_vs_ears_final": float(np.mean(fm / fe)), "stability": stab, "runs": out_runs}
+
+
 def cells_budget(mbytes=72.0):
     # bytes per cell: factors 72, accumulators 192, visits/leaf data 12,
     # directional pmf+cdf 512, training sums 512, octree node words 32
@@ -470,10 +542,11 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="guided",
-                    choices=["guided", "batch", "bdpt", "mlp", "ears"],
+                    choices=["guided", "batch", "bdpt", "mlp", "ears", "convergence"],
                     help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes; "
                          "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree; "
-                         "ears: MARS vs EARS vs classic RR efficiency (guided and bidirectional)")
+                         "ears: MARS vs EARS vs classic RR efficiency (guided and bidirectional); "
+                         "convergence: per-iteration counts and efficiency over several seeds")
     ap.add_argument("--no-efficiency", action="store_true")
     ap.add_argument("--mlp-train-steps", type=int, default=32,
                     help="learned-cache workload: Adam steps of 8192 samples after each update")
@@ -489,7 +562,8 @@ def main():
     from paper_2410_20429_amd import api
 
     if args.workload != "guided":
-        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp, "ears": run_ears}[args.workload]
+        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp, "ears": run_ears,
+               "convergence": run_convergence}[args.workload]
         print(json.dumps(run(args, api, torch)), flush=True)
         return
     sc = scenegen.make_heightfield_scene(seed=1)
