@@ -108,7 +108,7 @@ def reference_image(api, ctx, sc, spp=16, iters=256, seed_iter=100000, mode=None
 
 
 def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256),
-                   ears=False):
+                   ears=False, unaware=False):
     """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
     paper's evaluation: n_iter iterations of 1, 2, 4, ... spp, the first
     three with classic RR, then MARS (render + update each); the MARS image
@@ -116,13 +116,14 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
     RR renders the same sample counts (mean image).  relMSE against a
     classic reference of ref_spp[0] x ref_spp[1] spp, 0.01% brightest
     outliers discarded.  With ears, EARS (one shared count per vertex, the
-    paper's comparison method) runs the same schedule as MARS."""
+    paper's comparison method) runs the same schedule as MARS; with unaware,
+    so does MARS with the budget-unaware balance heuristic."""
     import numpy as np
     mode = api.MODE_PT_GUIDED if mode is None else mode
     kc = 0.0 if mode == api.MODE_BDPT else 50.0
     ref = reference_image(api, ctx, sc, spp=ref_spp[0], iters=ref_spp[1], mode=mode, depth=depth)
 
-    def run(alloc_after):
+    def run(alloc_after, aware=True):
         s = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget())
         acc = np.zeros_like(ref)
         spp_tot = rays = 0
@@ -130,7 +131,8 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
         t = time.perf_counter()
         for i in range(n_iter):
             alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
-            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=kc)
+            p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=kc,
+                                budget_aware=aware)
             rays += s.render_iteration(p).total_rays()
             if alloc_after != api.ALLOC_CLASSIC:
                 s.update(p)
@@ -163,12 +165,19 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
                     "relmse_ears": e_e, "seconds_ears": t_e, "rays_ears": r_e,
                     "rays_mars_vs_ears": r_m / r_e - 1.0,
                     "ray_efficiency_gain_vs_ears": (e_e * r_e) / (e_m * r_m)})
+    if unaware:
+        e_u, t_u, _, r_u = run(api.ALLOC_MARS, aware=False)
+        out.update({"mars_budget_unaware": 1.0 / (e_u * t_u),
+                    "gain_vs_budget_unaware": (e_u * t_u) / (e_m * t_m),
+                    "relmse_budget_unaware": e_u, "seconds_budget_unaware": t_u,
+                    "rays_budget_unaware": r_u})
     return out
 
 
 def run_ears(args, api, torch):
     """MARS against EARS (one count shared by every technique of a vertex,
-    the paper's comparison method) and classic RR, by the efficiency
+    the paper's comparison method), MARS with budget-unaware MIS weights,
+    and classic RR, by the efficiency
     protocol above: the guided 512x512 heightfield (9 iterations of 1..256
     spp, 4096 spp reference) and the bidirectional 1280x720 interior (7
     iterations of 1..64 spp, 1024 spp reference).  value = MARS's efficiency
@@ -177,11 +186,11 @@ def run_ears(args, api, torch):
     ctx = api.Context(0)
     sc = scenegen.make_heightfield_scene(seed=1)
     print("[bench] ears: guided", file=sys.stderr, flush=True)
-    g = efficiency_leg(api, ctx, sc, torch, ears=True)
+    g = efficiency_leg(api, ctx, sc, torch, ears=True, unaware=True)
     print("[bench] ears: bdpt", file=sys.stderr, flush=True)
     scb = scenegen.make_interior(seed=1)
     b = efficiency_leg(api, ctx, scb, torch, n_iter=7, mode=api.MODE_BDPT, depth=12,
-                       ref_spp=(16, 64), ears=True)
+                       ref_spp=(16, 64), ears=True, unaware=True)
     return {"metric": "efficiency 1/(relMSE*s): MARS vs EARS (classic RR beside them)",
             "value": g["gain_vs_ears"], "unit": "ratio", "n_gpus": 1, "steps": g["iterations"],
             "warmup": 3, "ms_per_step": g["seconds_mars"] * 1e3 / g["iterations"],
