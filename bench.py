@@ -52,7 +52,7 @@ def load_traffic(bytes_per_launch):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, n_pix=65536, seed=7):
+def cpu_baseline(sc, n_pix=262144, seed=7):
     """The oracle as it stands, on a bounded sample of the same workload:
     n_pix random pixels of the same 512 x 512 frame, one untimed classic
     iteration, then timed MARS iterations (render + update)."""
