@@ -55,9 +55,10 @@ def _twins(ctx, scenes, with_oracle=True, **kw):
     return G, E, O
 
 
-def _params(it, warm=2):
+def _params(it, warm=2, alloc=None):
     api = _api()
-    kw = dict(iteration=it, spp=2, alloc=orc.ALLOC_CLASSIC if it < warm else orc.ALLOC_MARS,
+    alloc = orc.ALLOC_MARS if alloc is None else alloc
+    kw = dict(iteration=it, spp=2, alloc=orc.ALLOC_CLASSIC if it < warm else alloc,
               stat_clamp=0.0, clamp_hi=8.0)
     return api.iter_params(**kw), orc.Oracle.params(**kw)
 
@@ -116,6 +117,25 @@ def test_batch_equals_eager_and_oracle(ctx, graph):
             u = ups[k]
             assert (u.V_I, u.C_I, u.n_cells_before, u.n_cells_after, u.n_excluded) == \
                    (ue.V_I, ue.C_I, ue.n_cells_before, ue.n_cells_after, ue.n_excluded), k
+            _cmp_twins(g, e)
+            _cmp_oracle(g, o)
+
+
+def test_batch_ears_equals_eager_and_oracle(ctx):
+    # the EARS count rule through the captured batch (its update writes the
+    # shared factors, signalled by the iteration's allocation mode)
+    api = _api()
+    scenes = _small_batch(seed=5)
+    G, E, O = _twins(ctx, scenes)
+    for it in range(4):
+        say("batch EARS iteration", it)
+        pg, po = _params(it, alloc=orc.ALLOC_EARS)
+        api.iterate_batch(G, pg, update=True, graph=True)
+        for g, e, o in zip(G, E, O):
+            e.render_iteration(pg)
+            e.update(pg)
+            o.render_iteration(po)
+            o.update(po)
             _cmp_twins(g, e)
             _cmp_oracle(g, o)
 
