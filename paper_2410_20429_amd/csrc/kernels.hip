@@ -500,24 +500,23 @@ __device__ __forceinline__ bool quad_any(bool b) {
 // flag, on which the others stop.  Each quad returns its own closest hit; the
 // caller reduces them in the (t, primitive) order.
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
+enum { kStepGo = 0, kStepEnd = 1, kStepFound = 2 };
+// One node of a quad's traversal.  State: bt, bp (the quad's closest hit so
+// far), sp and node (stack depth and the node to visit), split (while
+// splitting: levels still to split in bits 4.. and the digits of the path
+// below this level in bits 0..3, the next digit in bits 0..1).  Returns
+// kStepGo to go on, kStepEnd when the ray's traversal is over, kStepFound when
+// an any-hit ray found a hit (bt, bp then hold this lane's hit).
 template <bool kAny, int kSplit>
-__device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
-                                              int sub, int qcol, uint32_t qid, int g, lds_u32* sh,
-                                              float* bt_out, uint32_t* bp_out) {
-  const RayInv ri = ray_inv(o, d);
-  float bt = tmax;  // this quad's closest hit so far (and the culling distance)
-  uint32_t bp = kMiss;
-  int sp = 0;
-  int node = 0;
-  // while splitting: levels still to split (bits 4..) and the digits of the
-  // path below this level (bits 0..3, the next digit in bits 0..1)
-  uint32_t split = ((uint32_t)kSplit << 4) | (uint32_t)g;
-  while (true) {
+__device__ __forceinline__ int quad_step(const SceneDev& sc, const RayInv& ri, f3 o, f3 d, float tmax,
+                                         int* stk, int sub, int qcol, uint32_t qid, lds_u32* sh,
+                                         float& bt, uint32_t& bp, int& sp, int& node, uint32_t& split) {
+  {
     float cut = bt;
     if (kSplit > 0) {
       const uint32_t v = *(volatile lds_u32*)sh;
       if (kAny) {
-        if (v != 0u) break;
+        if (v != 0u) return kStepEnd;
       } else {
         cut = fminf(bt, __uint_as_float(v));
       }
@@ -572,9 +571,9 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       if (kAny) {
         if (quad_any(hit)) {
           if (kSplit > 0 && sub == 0) *(volatile lds_u32*)sh = 1u;
-          *bt_out = ht;
-          *bp_out = hp;
-          return true;
+          bt = ht;
+          bp = hp;
+          return kStepFound;
         }
       } else {
         quad_min_hit(ht, hp);
@@ -613,7 +612,7 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
       node = nearest;
       if (kSplit > 0 && split >= 16u) split = ((split - 16u) & ~15u) | ((split & 15u) >> 2);
     } else {
-      if (sp == 0) break;
+      if (sp == 0) return kStepEnd;
       --sp;
       // (the LDS read through an LDS-qualified pointer, so that it is not
       // merged with the spill read into one generic-address load)
@@ -622,9 +621,92 @@ __device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, fl
                  : sc.stack_spill[(size_t)(sp - kQuadStack) * sc.spill_threads + qid];
     }
   }
+  return kStepGo;
+}
+
+template <bool kAny, int kSplit>
+__device__ __forceinline__ bool traverse_quad(const SceneDev& sc, f3 o, f3 d, float tmax, int* stk,
+                                              int sub, int qcol, uint32_t qid, int g, lds_u32* sh,
+                                              float* bt_out, uint32_t* bp_out) {
+  const RayInv ri = ray_inv(o, d);
+  float bt = tmax;
+  uint32_t bp = kMiss;
+  int sp = 0, node = 0;
+  uint32_t split = ((uint32_t)kSplit << 4) | (uint32_t)g;
+  int r;
+  do {
+    r = quad_step<kAny, kSplit>(sc, ri, o, d, tmax, stk, sub, qcol, qid, sh, bt, bp, sp, node, split);
+  } while (r == kStepGo);
   *bt_out = bt;
   *bp_out = bp;
-  return bp != kMiss;
+  return r == kStepFound || bp != kMiss;
+}
+
+// One quad per ray, each quad taking the rays j, j + R, j + 2R, .. of one
+// kind below n and starting its next ray as soon as its current one is done,
+// so that a wave's quads do not wait for the wave's slowest ray after every
+// ray (only once, at the end of the stream).  Per ray the node order and the
+// result are those of traverse_quad.
+template <bool kAny>
+__device__ __forceinline__ void trace_stream(const SceneDev& sc, const QueuesDev& q, uint32_t j,
+                                             uint32_t n, uint32_t R, size_t L, int* stk, int sub,
+                                             int qcol, uint32_t qid) {
+  RayInv ri;
+  f3 o, d;
+  float tmax = INFINITY, bt = INFINITY;
+  uint32_t bp = kMiss, split = 0u;
+  int sp = 0, node = 0;
+  bool busy = false;
+  while (true) {
+    if (!busy) {
+      // the quad's next ray with work
+      float4 a, b;
+      for (; j < n; j += R) {
+        if (kAny) {
+          if (q.SH2[L + j].w != 0.0f) break;
+        } else {
+          a = q.R0[L + j];
+          if (a.w != 0.0f) break;
+          if (sub == 0) q.H[L + j] = make_uint2(ubits(INFINITY), kMiss);
+        }
+      }
+      if (j >= n) break;
+      if (kAny) {
+        a = q.SH0[L + j];
+        b = q.SH1[L + j];
+        tmax = a.w;
+      } else {
+        b = q.R1[L + j];
+      }
+      o = xyz(a);
+      d = xyz(b);
+      ri = ray_inv(o, d);
+      bt = tmax;
+      bp = kMiss;
+      sp = 0;
+      node = 0;
+      busy = true;
+    }
+    const int r = quad_step<kAny, 0>(sc, ri, o, d, tmax, stk, sub, qcol, qid, nullptr, bt, bp, sp, node, split);
+    if (r != kStepGo) {
+      if (sub == 0) {
+        if (kAny) {
+          if (r == kStepFound) {
+            // occluded: the contribution's colour cleared, its last word kept
+            float* c = (float*)&q.SH2[L + j];
+            c[0] = 0.0f;
+            c[1] = 0.0f;
+            c[2] = 0.0f;
+          }
+        } else {
+          // the quad's reduced closest hit (a miss leaves bt = inf, bp = kMiss)
+          q.H[L + j] = make_uint2(ubits(bt), bp);
+        }
+      }
+      busy = false;
+      j += R;
+    }
+  }
 }
 
 // LDS writes of some lanes of a wave made visible to reads by other lanes of
@@ -719,7 +801,15 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 
   const uint32_t n = nc + ns;
   if ((uint64_t)n * kSplitDiv16 <= Q) trace_rays<2>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
   else if ((uint64_t)n * kSplitDiv4 <= Q) trace_rays<1>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
-  else trace_rays<0>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
+  else {
+    // one quad per ray, the closest rays first; quad i takes ray j of the
+    // combined numbering (closest, then shadow) when j = i mod Q
+    const uint32_t qid = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int sub = threadIdx.x & 3, qcol = threadIdx.x >> 2;
+    trace_stream<false>(sc, q, qid, nc, Q, Lc, stk, sub, qcol, qid);
+    const uint32_t k0 = (qid + Q - nc % Q) % Q;
+    trace_stream<true>(sc, q, k0, ns, Q, Ls, stk, sub, qcol, qid);
+  }
 }
 
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
