@@ -1266,7 +1266,11 @@ void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Count
 //   v_s = B|cos|/p_N w_dir,N Le                   (NEE samples, 0 if occluded)
 // summed in the order NEE, BSDF, guided.  Every sample also feeds the cell's
 // moment and cost accumulators (Sec. 4.1 "Local estimates"); continuation
-// samples train the directional histogram of the guided technique.
+// samples train the directional histogram of the guided technique.  The
+// launches run from the deepest depth up; the launch of depth d computes the
+// value, cost and histogram training of each of its entries as a sample of
+// its parent, so that the parent's fold over its samples (in their order)
+// reads one record per sample.
 // ---------------------------------------------------------------------------
 // Cell statistics are first summed per vertex (all samples of a vertex fall
 // in its cell), then merged per workgroup in an LDS hash table keyed by
@@ -1361,31 +1365,14 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
         record(1, v, 1u);
       }
       for (uint32_t k = 0; k < v2.w; ++k) {
+        // the sample's value and cost, left by the launch of the next depth
         const size_t e = Ln + v2.z + k;
-        const float4 s1 = q.S1[e], s2 = q.S2[e];
+        const float4 sv = q.RO[e];
+        const float bt = q.S2[e].w;
         const uint32_t tech = q.S3[e].z >> 16;
-        f3 v = mk3(0.0f, 0.0f, 0.0f);
-        uint32_t sc_ = 1;
-        if (q.R0[e].w != 0.0f) {
-          const float4 cv = q.V0[e], cr = q.RO[e];
-          v = mk3(s1.x * (cv.x + s1.w * cr.x), s1.y * (cv.y + s1.w * cr.y),
-                  s1.z * (cv.z + s1.w * cr.z));
-          sc_ = 1u + ubits(cr.w);
-          if (guided && s2.y > 0.0f) {
-            f3 E = mk3(0.0f, 0.0f, 0.0f);
-            const uint2 h = q.H[e];
-            const f3 dir = xyz(q.R1[e]);
-            if (h.y != kMiss) {
-              const float* m = sc.mats + 8 * (size_t)sc.tri_mat[h.y];
-              const float cosl = -dot3(dir, xyz(sc.tri_ng[h.y]));
-              if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f))
-                E = mk3(m[5], m[6], m[7]);
-            }
-            const f3 Li = add3(E, xyz(cr));
-            atomicAdd(c.hacc + (size_t)cell * 64 + dir_bin(dir), (double)(lum(Li) / s2.y));
-          }
-        }
-        R = mk3(R.x + v.x / s2.w, R.y + v.y / s2.w, R.z + v.z / s2.w);
+        const f3 v = xyz(sv);
+        const uint32_t sc_ = ubits(sv.w);
+        R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
         cost += sc_;
         record(tech == 0 ? 0 : 2, v, sc_);
       }
@@ -1399,7 +1386,41 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
         agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
       }
     }
-    q.RO[L + j] = make_float4(R.x, R.y, R.z, fbits(cost));
+    if (d >= 2) {
+      // this entry as a continuation sample of its parent vertex (depth
+      // d - 1): v = B|cos|/p_t (w_dir,t E' + w_ind,t R') with the factors
+      // the parent stored, and its cost 1 + the cost of this subtree (1 for
+      // a sample whose direction was rejected).  The parent's pass reads
+      // the pair with one load.  A guided parent's directional histogram is
+      // trained here, with the incident radiance E + R' over the density of
+      // its continuation samples.
+      f3 v = mk3(0.0f, 0.0f, 0.0f);
+      uint32_t sc_ = 1u;
+      if (q.R0[L + j].w != 0.0f) {
+        const float4 s1 = q.S1[L + j];
+        v = mk3(s1.x * (v0.x + s1.w * R.x), s1.y * (v0.y + s1.w * R.y), s1.z * (v0.z + s1.w * R.z));
+        sc_ = 1u + cost;
+        if (guided) {
+          const float dsum = q.S2[L + j].y;
+          if (dsum > 0.0f) {
+            f3 E = mk3(0.0f, 0.0f, 0.0f);
+            const uint2 h = q.H[L + j];
+            const f3 dir = xyz(q.R1[L + j]);
+            if (h.y != kMiss) {
+              const float* m = sc.mats + 8 * (size_t)sc.tri_mat[h.y];
+              const float cosl = -dot3(dir, xyz(sc.tri_ng[h.y]));
+              if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f))
+                E = mk3(m[5], m[6], m[7]);
+            }
+            const f3 Li = add3(E, R);
+            const uint32_t pcell =
+                ubits(q.V0[(size_t)(d - 1) * q.cap + ubits(q.S0[L + j].w)].w);
+            atomicAdd(c.hacc + (size_t)pcell * 64 + dir_bin(dir), (double)(lum(Li) / dsum));
+          }
+        }
+      }
+      q.RO[L + j] = make_float4(v.x, v.y, v.z, fbits(sc_));
+    }
     if (d == 1) {
       const uint32_t root = q.S3[L + j].w;
       img.Ls[3 * (size_t)root] = v0.x + R.x;
