@@ -2252,17 +2252,13 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         record(1, v, 1u);
       }
       for (uint32_t k = 0; k < v2.w; ++k) {
+        // the sample's value and cost, left by the launch of the next depth
         const size_t e = Ln + v2.z + k;
-        const float4 s1 = q.S1[e], s2 = q.S2[e];
-        f3 v = mk3(0.0f, 0.0f, 0.0f);
-        uint32_t sc_ = 1;
-        if (q.R0[e].w != 0.0f) {
-          const float4 cv = q.V0[e], cr = q.RO[e];
-          v = mk3(s1.x * (cv.x + s1.w * cr.x), s1.y * (cv.y + s1.w * cr.y),
-                  s1.z * (cv.z + s1.w * cr.z));
-          sc_ = 1u + ubits(cr.w);
-        }
-        R = mk3(R.x + v.x / s2.w, R.y + v.y / s2.w, R.z + v.z / s2.w);
+        const float4 sv = q.RO[e];
+        const float bt = q.S2[e].w;
+        const f3 v = xyz(sv);
+        const uint32_t sc_ = ubits(sv.w);
+        R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
         cost += sc_;
         record(0, v, sc_);
       }
@@ -2298,7 +2294,19 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
       }
     }
-    q.RO[L + j] = make_float4(R.x, R.y, R.z, fbits(cost));
+    if (d >= 2) {
+      // this entry as a BSDF sample of its parent vertex (depth d - 1): its
+      // value with the factors the parent stored, and its cost (1 for a
+      // sample whose direction was rejected)
+      f3 v = mk3(0.0f, 0.0f, 0.0f);
+      uint32_t sc_ = 1u;
+      if (q.R0[L + j].w != 0.0f) {
+        const float4 s1 = q.S1[L + j];
+        v = mk3(s1.x * (v0.x + s1.w * R.x), s1.y * (v0.y + s1.w * R.y), s1.z * (v0.z + s1.w * R.z));
+        sc_ = 1u + cost;
+      }
+      q.RO[L + j] = make_float4(v.x, v.y, v.z, fbits(sc_));
+    }
     if (d == 1) {
       const uint32_t root = q.S3[L + j].w;
       img.Ls[3 * (size_t)root] = v0.x + R.x;

@@ -71,8 +71,7 @@ struct QueuesDev {
   float4* V0;   // weighted emission for the parent's direct term, cell (bits)
   float4* V1;   // beta_B, beta_N, beta_third, unused
   uint4* V2;    // NEE first, NEE count, continuation first, continuation count
-  float4* RO;   // PT: the entry's value as its parent's continuation sample, its cost (bits);
-               // BDPT: back-propagated secondary estimate, subtree cost (bits)
+  float4* RO;   // the entry's value as its parent's continuation sample, its cost (bits)
   // BDPT camera-vertex records for the full-path MIS weights (null otherwise):
   // W0 = (throughput of the camera prefix recomputed from positions, raw
   // BSDF count), W1 = (raw NEE count, raw LP count, pF here, pR two back)
