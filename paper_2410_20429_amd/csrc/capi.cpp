@@ -138,6 +138,10 @@ struct BatchGraph {
   double* summary = nullptr;  // device: [n][kSumWords]
 };
 
+constexpr size_t kPinnedBytes = 4096;
+static_assert(sizeof(Counters) <= kPinnedBytes && 8 * 8 + 4 * 4 + 4 <= kPinnedBytes,
+              "the pinned readback buffer holds the counters and the update's scalars");
+
 struct Ctx {
   int device = 0;
   uint64_t next_uid = 1;
@@ -150,6 +154,9 @@ struct Ctx {
   unsigned long long* tcount = nullptr;  // traversal counters (instrumented runs)
   bool counting = false;
   hipStream_t stream = nullptr;
+  // pinned host memory for the readbacks of every tile and update (a copy
+  // into pageable memory is staged through a host buffer by the runtime)
+  unsigned char* pinned = nullptr;
   mars_alloc_fn alloc = nullptr;
   mars_free_fn free_ = nullptr;
   void* user = nullptr;
@@ -357,10 +364,10 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
       timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st); });
     }
   }
-  Counters hc;
-  d2h(&hc, s->cnt, sizeof(Counters), st);
+  Counters* pc = (Counters*)c->pinned;
+  d2h(pc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));
-  return hc.rays_light;
+  return pc->rays_light;
 }
 
 // One wavefront tile: returns false on queue overflow.  The bottom-up pass is
@@ -401,8 +408,10 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
         k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
     });
   if (last) timed(c, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, spp, st); });
-  d2h(hc, s->cnt, sizeof(Counters), st);
+  Counters* pc = (Counters*)c->pinned;
+  d2h(pc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));
+  *hc = *pc;
   return hc->overflow == 0;
 }
 
@@ -830,10 +839,14 @@ void update_counts(Scene* s, const mars_iter_params* p, mars_update_stats* out) 
   double red[8];
   int32_t nc[4];
   uint32_t nrec = 0;
-  d2h(red, s->img.red, sizeof(red), st);
-  d2h(nc, s->n_cells_dev, sizeof(nc), st);
-  if (s->mlp_on) d2h(&nrec, s->mlp.n_rec, 4, st);
+  unsigned char* pb = c->pinned;
+  d2h(pb, s->img.red, sizeof(red), st);
+  d2h(pb + sizeof(red), s->n_cells_dev, sizeof(nc), st);
+  if (s->mlp_on) d2h(pb + sizeof(red) + sizeof(nc), s->mlp.n_rec, 4, st);
   HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(red, pb, sizeof(red));
+  std::memcpy(nc, pb + sizeof(red), sizeof(nc));
+  if (s->mlp_on) std::memcpy(&nrec, pb + sizeof(red) + sizeof(nc), 4);
   HIPCHK(hipGetLastError());
   c->prof.flush();
   s->n_cells = nc[0];
@@ -1342,6 +1355,10 @@ mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess &&
       cu > 0)
     c->cu = cu;
+  if (hipHostMalloc((void**)&c->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return MARS_E_OOM;
+  }
   c->batch_streams = kBatchStreams;
   if (const char* e = std::getenv("MARS_BATCH_STREAMS")) {
     const int k = std::atoi(e);
@@ -1360,6 +1377,7 @@ mars_status mars_destroy(mars_ctx* ctx) {
   for (auto e : ctx->pool_ev) (void)hipEventDestroy(e);
   for (auto& s : ctx->scenes) release_scene(s.get());
   if (ctx->tcount) ctx->dfree(ctx->tcount);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return MARS_OK;
 }
