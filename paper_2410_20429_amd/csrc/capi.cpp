@@ -206,6 +206,19 @@ void timed(Ctx* c, int kid, F&& launch) {
   c->prof.pending.push_back({kid, {a, b}});
 }
 
+// the same for a launch that stamps the two events itself (at its kernel's
+// start and end): launch(a, b), with null events when the kernel is not timed
+template <typename F>
+void timed_ext(Ctx* c, int kid, F&& launch) {
+  if (!((c->prof.mask >> kid) & 1u)) {
+    launch(nullptr, nullptr);
+    return;
+  }
+  hipEvent_t a = c->prof.get(), b = c->prof.get();
+  launch(a, b);
+  c->prof.pending.push_back({kid, {a, b}});
+}
+
 template <typename T>
 T* salloc(Scene* s, size_t n) {
   void* p = s->ctx->dalloc(n * sizeof(T));
@@ -353,7 +366,9 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
     const uint32_t n = (uint32_t)std::min<size_t>(s->cap, roots - r0);
     timed(c, KID_LIGHT, [&] { k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st); });
     for (int i = 1; i <= s->lt.lmax; ++i) {
-      timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc); });
+      timed_ext(c, KID_TRACE, [&](hipEvent_t a, hipEvent_t b) {
+        k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc, a, b);
+      });
       // learned-cache iterations: the network's counts at the new light
       // vertices, which the connections' MIS weights evaluate as if on the
       // camera side
@@ -385,7 +400,9 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   if (dbg0) h2d(&s->cnt->n_debug, &dbg0, 4, st);  // debug records accumulate across tiles
   timed(c, KID_RAYGEN, [&] { k_raygen(s->sd, s->qd, s->cnt, it, root0, n, st); });
-  timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc); });
+  timed_ext(c, KID_TRACE, [&](hipEvent_t a, hipEvent_t b) {
+    k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc, a, b);
+  });
   for (int d = 1; d <= s->max_depth; ++d) {
     if (it.alloc == MARS_ALLOC_MLP && d < s->max_depth)
       timed(c, KID_MLP, [&] { k_mlp_infer_queue(s->sd, s->qd, s->mlp, s->cnt, d, grid * 4, st); });
@@ -398,7 +415,9 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
     });
     // shadow rays of depth d with the continuation rays of depth d + 1
     const int dc = d < s->max_depth ? d + 1 : -1;
-    timed(c, KID_TRACE, [&] { k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc); });
+    timed_ext(c, KID_TRACE, [&](hipEvent_t a, hipEvent_t b) {
+      k_trace_pair(s->sd, s->qd, s->cnt, dc, d, grid_trace, st, tc, a, b);
+    });
   }
   for (int d = s->max_depth; d >= 1; --d)
     timed(c, KID_BACKPROP, [&] {

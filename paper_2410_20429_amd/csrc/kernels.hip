@@ -12,6 +12,7 @@
 // global atomic per wave), and the tree is reduced bottom-up afterwards by a
 // pull over each vertex's contiguous child range, so per-pixel radiance does
 // not depend on queue order.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_math.hpp"
@@ -813,11 +814,17 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 
 }
 
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
-                  int grid, hipStream_t s, unsigned long long* tc) {
+                  int grid, hipStream_t s, unsigned long long* tc, hipEvent_t ev0, hipEvent_t ev1) {
   // the spill area has one column per thread of the launch
   if (sc.stack_spill) grid = std::min(grid, (int)(sc.spill_threads / kTraceBlock));
   // instrumented runs count node visits per ray with the one-lane loop
-  if (tc) trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
+  if (tc) {
+    if (ev0) (void)hipEventRecord(ev0, s);
+    trace_pair_kernel<true><<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds, tc);
+    if (ev1) (void)hipEventRecord(ev1, s);
+  } else if (ev0)
+    hipExtLaunchKernelGGL(trace_quad_kernel, dim3(grid), dim3(kTraceBlock), 0, s, ev0, ev1, 0u, sc, q,
+                          cnt, dc, ds);
   else trace_quad_kernel<<<grid, kTraceBlock, 0, s>>>(sc, q, cnt, dc, ds);
 }
 

@@ -179,9 +179,12 @@ void k_raygen(const SceneDev& sc, const QueuesDev& q, Counters* cnt, const IterD
 // traverses the closest-hit queue of depth dc (-1 = none; 0 is the light
 // queue) and the shadow queue of depth ds (0 = none) in one launch.  tc (optional): traversal counters {rays,
 // nodes, triangles} of closest-hit rays at tc[0..2], shadow rays at tc[3..5]
-// stream: the streaming traversal (queues longer than the lanes resident)
+// stream: the streaming traversal (queues longer than the lanes resident).
+// ev0, ev1 (optional, timing runs): events stamped by the dispatch itself at
+// the kernel's start and end, with no marker packets around the launch
 void k_trace_pair(const SceneDev& sc, const QueuesDev& q, const Counters* cnt, int dc, int ds,
-                  int grid, hipStream_t s, unsigned long long* tc);
+                  int grid, hipStream_t s, unsigned long long* tc, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Counters* cnt,
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s);
