@@ -105,8 +105,11 @@ struct Profiler {
       pool.pop_back();
       return e;
     }
+    // timing events only: every host read waits on the stream after a copy,
+    // so the events need no system-scope fence (one costs a few
+    // microseconds between the launches an event brackets)
     hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
   }
   // call only after the stream has been synchronised
