@@ -228,6 +228,7 @@ struct oracle {
   float *pm, *cdf;/* [maxc][64] */
   double* hacc;   /* [maxc][64] */
   float* fixed_beta; int32_t nfixed;
+  int32_t rec_depth; /* tests: > 0 logs only the samples of vertices up to this depth */
   int32_t ears_update; /* the running update belongs to an EARS iteration */
   /* image */
   int32_t spp_last;
@@ -923,6 +924,13 @@ static v3 stat_clamp_v(const tctx* c, v3 v, v3 T) {
             fminf(v.z, (k * c->It[2]) / T.z));
 }
 
+/* sample records of a vertex at `depth` are logged unless a test limits
+ * them to shallower vertices */
+static void log_sample(const tctx* c, int depth, stat_rec s) {
+  if (c->o->rec_depth > 0 && depth > c->o->rec_depth) return;
+  log_push(c->L, s);
+}
+
 static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t strm, parent_mis pm) {
   const oracle* o = c->o;
   const orc_iter_params* p = c->p;
@@ -1017,7 +1025,7 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
     cost += 1;
     v3 vs = stat_clamp_v(c, v, T);
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_N, 0, {vs.x, vs.y, vs.z}, 1, 0};
-    log_push(c->L, s);
+    log_sample(c, depth, s);
   }
   /* continuation samples: BSDF (technique B) then guided (technique G) */
   for (int tech = 0; tech < 3; tech += 2) {
@@ -1075,7 +1083,7 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
       cost += scost;
       v3 vs = stat_clamp_v(c, v, T);
       stat_rec s = {REC_SAMPLE, cell, (uint32_t)tech, 0, {vs.x, vs.y, vs.z}, scost, 0};
-      log_push(c->L, s);
+      log_sample(c, depth, s);
     }
   }
   out.R = R;
@@ -1474,6 +1482,7 @@ void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n) {
 void orc_set_Itilde(oracle* o, const float* src) {
   memcpy(o->Itilde, src, sizeof(float) * 3 * o->W * o->H);
 }
+void orc_set_record_depth(oracle* o, int32_t depth) { o->rec_depth = depth; }
 void orc_set_fixed_beta(oracle* o, const float* beta, int32_t n) {
   free(o->fixed_beta);
   o->fixed_beta = malloc(sizeof(float) * 3 * (n > 0 ? n : 1));
@@ -1759,7 +1768,7 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
     R = mk(R.x + v.x / beta[1], R.y + v.y / beta[1], R.z + v.z / beta[1]);
     cost += 1;
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_N, 0, {v.x, v.y, v.z}, 1, 0};
-    log_push(c->L, s);
+    log_sample(c, depth, s);
   }
   /* BSDF continuation */
   for (uint32_t k = 0; k < gam[0]; ++k) {
@@ -1790,7 +1799,7 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
     R = mk(R.x + v.x / beta[0], R.y + v.y / beta[0], R.z + v.z / beta[0]);
     cost += scost;
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_B, 0, {v.x, v.y, v.z}, scost, 0};
-    log_push(c->L, s);
+    log_sample(c, depth, s);
   }
   /* light-path connections */
   uint32_t npool = (uint32_t)(o->W * o->H * p->spp);
@@ -1834,7 +1843,7 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
     R = mk(R.x + v.x / beta[2], R.y + v.y / beta[2], R.z + v.z / beta[2]);
     cost += scost;
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_G, 0, {v.x, v.y, v.z}, scost, 0};
-    log_push(c->L, s);
+    log_sample(c, depth, s);
   }
   out.R = R;
   out.cost = cost;

@@ -102,6 +102,8 @@ void orc_set_Itilde(oracle* o, const float* src);
 /* render only the listed pixels (NULL / 0: all); others get zero radiance */
 void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n);
 void orc_set_fixed_beta(oracle* o, const float* beta, int32_t n);
+/* tests: log sample statistics only for vertices up to `depth` (0: all) */
+void orc_set_record_depth(oracle* o, int32_t depth);
 void orc_set_hist(oracle* o, int32_t n, const float* pm, const float* cdf);
 int32_t orc_update_cells_only(oracle* o, double V_I, double C_I);
 /* the same update as an EARS iteration's: shared factors into slot 0 */

@@ -86,6 +86,7 @@ def lib():
         L.orc_set_Itilde.argtypes = [P, P]
         L.orc_set_pixel_subset.argtypes = [P, P, C.c_int32]
         L.orc_set_fixed_beta.argtypes = [P, P, C.c_int32]
+        L.orc_set_record_depth.argtypes = [P, C.c_int32]
         L.orc_set_hist.argtypes = [P, C.c_int32, P, P]
         L.orc_update_cells_only.argtypes = [P, C.c_double, C.c_double]
         L.orc_update_cells_only.restype = C.c_int32
@@ -255,6 +256,10 @@ class Oracle:
     def set_fixed_beta(self, beta):
         b = np.ascontiguousarray(beta, np.float32).reshape(-1, 3)
         lib().orc_set_fixed_beta(self.h, _p(b), b.shape[0])
+
+    def set_record_depth(self, depth):
+        """(tests) sample statistics only from vertices up to `depth`; 0: all"""
+        lib().orc_set_record_depth(self.h, int(depth))
 
     def set_hist(self, pm, cdf):
         pm = np.ascontiguousarray(pm, np.float32)
