@@ -108,7 +108,10 @@ typedef struct {
   float stat_clamp;         /* outlier clamp of statistics (50 in Sec. 4.1; 0 = off) */
   int32_t center_jitter;    /* 1: pixel-centre camera rays */
   int32_t debug_depth;      /* record per-vertex decisions up to this depth */
-  int32_t lp_stride;        /* BDPT: pool stride for extra light paths */
+  int32_t lp_stride;        /* BDPT: light-path sample j of a camera vertex connects to
+                               light subpath (b + j lp_stride) mod N of the iteration's N
+                               (one per camera sample), b a word of the vertex's random
+                               stream (Sec. 5: connections with light paths) */
 } mars_iter_params;
 
 typedef struct {
@@ -238,10 +241,14 @@ mars_status mars_update_cells_only(mars_ctx* ctx, int32_t scene_id, double V_I, 
 mars_status mars_refine_only(mars_ctx* ctx, int32_t scene_id, int32_t* n_split);
 
 /* ---- outputs ----------------------------------------------------------- */
-/* which = MARS_IMAGE_*; dst [H*W][3] */
+/* which = MARS_IMAGE_*; dst [H*W][3].  MEAN is the plain average of all
+ * iterations, IVW the inverse-variance weighted combination of Sec. 5.1
+ * (iteration i weighted by spp_i / V_I,i), LAST the last iteration alone. */
 mars_status mars_read_image(mars_ctx* ctx, int32_t scene_id, int32_t which, float* dst,
                             int32_t dst_is_device);
-/* dst [H*W][3]: mean count per technique at the first hit of the last iteration */
+/* dst [H*W][3]: mean count per technique at the first hit of the last
+ * iteration -- the allocation maps the paper shows beside its results
+ * (Sec. 4.2, Sec. 5.2: BSDF, NEE and the third technique per pixel) */
 mars_status mars_read_count_map(mars_ctx* ctx, int32_t scene_id, float* dst,
                                 int32_t dst_is_device);
 /* dst [H*W*spp][3]: radiance of every camera sample of the last iteration,
@@ -266,15 +273,27 @@ mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* pa
 mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* path);
 
 /* ---- learned cache (scenes uploaded with MARS_SCENE_MLP) -----------------
- * A network maps a vertex (position normalised to the octree box, shading
- * normal) to the log count of every technique relative to |T / I~|; render
- * iterations with alloc = MARS_ALLOC_MLP use beta_t = |T / I~| exp(y_t)
- * (clamped; the octree count where the output is not finite).  Training
- * data: a random subset of the iteration's vertices, recorded while shading;
- * mars_update_counts turns them into targets from the cells' updated
- * factors (log of the resolved octree count, weight min(n, 64)/64 for cells
- * with at least 4 samples of the technique).  The counts of the MIS weights
- * keep using the octree (a function of the path only).
+ * Not in the paper: its Sec. 6 ("Discontinuity artefacts") asks for sample
+ * counts that vary smoothly in space; a small network fitted online to the
+ * octree's estimates gives them.  The network maps a vertex (its position
+ * normalised to the octree's cube, and its geometric normal as stored, not
+ * turned toward the incoming ray, so that the same value can be evaluated at
+ * a light vertex) to one log count per technique relative to |T / I~| =
+ * sqrt((1/3) sum_ch (T_ch / I~_ch)^2).
+ * Render iterations with alloc = MARS_ALLOC_MLP pool the network's count
+ * |T / I~| exp(y_t) with the octree's count beta_t as their geometric mean
+ * sqrt(beta_t |T / I~| exp(y_t)), clamped like the octree's counts; where
+ * that is not finite the octree's count is used, and a technique the octree
+ * disables stays off.  Every MIS weight evaluates these pooled counts: the
+ * unidirectional records keep the counts each vertex drew with, and in
+ * bidirectional paths the camera-side records hold them and light vertices
+ * get network outputs too, so the weights of a path still sum to one.
+ * Training data: a random subset of the iteration's camera vertices,
+ * recorded while shading; mars_update_counts turns them into targets from
+ * the cells' updated factors: y*_t = log(beta^_t) - log|T / I~| with beta^_t
+ * the octree's resolved, unclamped count (Sec. 3.1, colour rule of
+ * Sec. 4.1), weight min(n_t, 64)/64 for cells with at least 4 samples of
+ * technique t in the iteration, else 0.
  * The network: sin/cos(2^k pi x), k < 6, of the 6 inputs (72 features,
  * padded to 80), 3 hidden layers of 64 ReLU units, 3 outputs; bfloat16
  * matrix-core products with binary32 accumulation; Adam (0.9, 0.99, 1e-8)
@@ -298,6 +317,21 @@ mars_status mars_mlp_grad(mars_ctx* ctx, int32_t scene_id, const float* x6, cons
                           const float* weight, int32_t n, float* grad, float* loss);
 /* one Adam step with the given gradient (host [num_params]) */
 mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* grad, float lr);
+
+/* The training set (tests).  mars_mlp_write_records replaces the recorded
+ * vertices: host pos, nrm, T [n][3] (binary32, finite) and pix [n] (< W*H);
+ * n at most the record capacity (2^18), else MARS_E_ARG.
+ * mars_mlp_targets_only recomputes inputs, targets and weights of the
+ * recorded vertices from the cells and I~ as they are (the step
+ * mars_update_counts runs after the fixed point, before refinement).
+ * mars_mlp_read_train copies up to cap entries (host x6 [n][6], target
+ * [n][3], weight [n][3]; any may be NULL) and the set's size into *n. */
+mars_status mars_mlp_write_records(mars_ctx* ctx, int32_t scene_id, const float* pos,
+                                   const float* nrm, const float* T, const uint32_t* pix,
+                                   int32_t n);
+mars_status mars_mlp_targets_only(mars_ctx* ctx, int32_t scene_id);
+mars_status mars_mlp_read_train(mars_ctx* ctx, int32_t scene_id, float* x6, float* target,
+                                float* weight, int32_t cap, int32_t* n);
 
 /* ---- measurement ------------------------------------------------------- */
 /* Per-kernel timing with HIP events recorded on the context's stream around

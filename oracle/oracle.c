@@ -1805,7 +1805,10 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
   uint32_t npool = (uint32_t)(o->W * o->H * p->spp);
   for (uint32_t k = 0; k < gam[2]; ++k) {
     c->L->samples++;
-    uint32_t lpi = (uint32_t)(((uint64_t)c->root + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
+    /* light subpath: pool entry (b + k stride) mod npool with b the first
+     * word of this vertex's stream, so the vertices of one path tree use
+     * unrelated light subpaths (their samples stay independent) */
+    uint32_t lpi = (uint32_t)(((uint64_t)strm.lo + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
     const lightpath* lp = &o->lpaths[lpi];
     v3 v = mk(0, 0, 0);
     /* cost of an LP sample: its connection rays (at least 1); the light

@@ -114,6 +114,9 @@ SIGNATURES = {
     "mars_mlp_forward": [P, I32, P, I32, P],
     "mars_mlp_grad": [P, I32, P, P, P, I32, P, P],
     "mars_mlp_apply_grad": [P, I32, P, C.c_float],
+    "mars_mlp_write_records": [P, I32, P, P, P, P, I32],
+    "mars_mlp_targets_only": [P, I32],
+    "mars_mlp_read_train": [P, I32, P, P, P, I32, PI32],
 }
 
 _lib = None
@@ -373,6 +376,20 @@ def mars_mlp_grad(ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr):
 
 def mars_mlp_apply_grad(ctx, sid, g_ptr, lr):
     _call("mars_mlp_apply_grad", ctx, sid, g_ptr, float(lr))
+
+
+def mars_mlp_write_records(ctx, sid, pos_ptr, nrm_ptr, t_ptr, pix_ptr, n):
+    _call("mars_mlp_write_records", ctx, sid, pos_ptr, nrm_ptr, t_ptr, pix_ptr, n)
+
+
+def mars_mlp_targets_only(ctx, sid):
+    _call("mars_mlp_targets_only", ctx, sid)
+
+
+def mars_mlp_read_train(ctx, sid, x_ptr, t_ptr, w_ptr, cap):
+    n = C.c_int32()
+    _call("mars_mlp_read_train", ctx, sid, x_ptr, t_ptr, w_ptr, cap, C.byref(n))
+    return n.value
 
 
 def mars_version():

@@ -246,6 +246,26 @@ class Scene:
         g = np.ascontiguousarray(grad, np.float32)
         capi.mars_mlp_apply_grad(self.ctx.h, self.id, _p(g), lr)
 
+    def mlp_write_records(self, pos, nrm, T, pix):
+        """(tests) replaces the training vertices of the learned cache"""
+        arrs = [np.ascontiguousarray(x, np.float32).reshape(-1, 3) for x in (pos, nrm, T)]
+        px = np.ascontiguousarray(pix, np.uint32).ravel()
+        capi.mars_mlp_write_records(self.ctx.h, self.id, *[_p(a) for a in arrs], _p(px),
+                                    px.shape[0])
+
+    def mlp_targets_only(self):
+        capi.mars_mlp_targets_only(self.ctx.h, self.id)
+
+    def mlp_train_set(self):
+        """inputs [n][6], targets [n][3] and weights [n][3] of the training set"""
+        n = capi.mars_mlp_read_train(self.ctx.h, self.id, None, None, None, 0)
+        x = np.zeros((n, 6), np.float32)
+        t = np.zeros((n, 3), np.float32)
+        w = np.zeros((n, 3), np.float32)
+        if n:
+            capi.mars_mlp_read_train(self.ctx.h, self.id, _p(x), _p(t), _p(w), n)
+        return x, t, w
+
     # ---- queue sizing ----
     def configure(self, queue_capacity=0, tile_roots=0):
         capi.mars_scene_configure(self.ctx.h, self.id, int(queue_capacity), int(tile_roots))

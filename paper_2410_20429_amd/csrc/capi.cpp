@@ -1965,6 +1965,63 @@ mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* gr
   });
 }
 
+mars_status mars_mlp_write_records(mars_ctx* ctx, int32_t scene_id, const float* pos,
+                                   const float* nrm, const float* T, const uint32_t* pix,
+                                   int32_t n) {
+  if (!ctx || !pos || !nrm || !T || !pix || n < 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    if ((uint32_t)n > s->mlp.rec_cap) throw Status(MARS_E_ARG, "more records than the capacity");
+    const uint32_t npx = (uint32_t)(s->W * s->H);
+    std::vector<float> rec(12 * (size_t)n);
+    for (int32_t r = 0; r < n; ++r) {
+      if (pix[r] >= npx) throw Status(MARS_E_ARG, "pixel index out of range");
+      for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(pos[3 * r + k]) || !std::isfinite(nrm[3 * r + k]) ||
+            !std::isfinite(T[3 * r + k]))
+          throw Status(MARS_E_NONFINITE, "non-finite record");
+        rec[12 * (size_t)r + k] = pos[3 * r + k];
+        rec[12 * (size_t)r + 4 + k] = nrm[3 * r + k];
+        rec[12 * (size_t)r + 8 + k] = T[3 * r + k];
+      }
+      std::memcpy(&rec[12 * (size_t)r + 3], &pix[r], 4);
+      rec[12 * (size_t)r + 7] = 0.0f;
+      rec[12 * (size_t)r + 11] = 0.0f;
+    }
+    const uint32_t nn = (uint32_t)n;
+    if (n) h2d(s->mlp.rec, rec.data(), 48 * (size_t)n, ctx->stream);
+    h2d(s->mlp.n_rec, &nn, 4, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    s->mlp_n_train = nn;
+  });
+}
+
+mars_status mars_mlp_targets_only(mars_ctx* ctx, int32_t scene_id) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    k_mlp_targets(s->sd, s->cd, s->mlp, s->img, IterDev{}, s->mlp.rec_cap, nullptr, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+mars_status mars_mlp_read_train(mars_ctx* ctx, int32_t scene_id, float* x6, float* target,
+                                float* weight, int32_t cap, int32_t* n) {
+  if (!ctx || cap < 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    const size_t m = std::min((size_t)s->mlp_n_train, (size_t)cap);
+    if (n) *n = (int32_t)s->mlp_n_train;
+    if (m) {
+      if (x6) d2h(x6, s->mlp.x6, 24 * m, ctx->stream);
+      if (target) d2h(target, s->mlp.tgt, 12 * m, ctx->stream);
+      if (weight) d2h(weight, s->mlp.wt, 12 * m, ctx->stream);
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 mars_status mars_probe(mars_ctx* ctx, int32_t kind, int32_t n, const void* in, void* out) {
   if (!ctx || !in || !out || n <= 0) return MARS_E_ARG;
   return guard(ctx, [&] {

@@ -1871,9 +1871,12 @@ __device__ __forceinline__ void camera_prefix(const SceneDev& sc, const QueuesDe
   }
 }
 
-__device__ __forceinline__ uint32_t lp_index(uint32_t root, uint32_t j, int32_t stride,
+// light subpath of LP sample j of a camera vertex: pool entry (b + j stride)
+// mod npool, b the first word of the vertex's own random stream, so that the
+// vertices of one path tree connect to unrelated light subpaths
+__device__ __forceinline__ uint32_t lp_index(uint32_t b, uint32_t j, int32_t stride,
                                              uint32_t npool) {
-  return (uint32_t)(((unsigned long long)root + (unsigned long long)j * (uint32_t)stride) % npool);
+  return (uint32_t)(((unsigned long long)b + (unsigned long long)j * (uint32_t)stride) % npool);
 }
 
 __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
@@ -1945,7 +1948,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           mlp_record(c, strm, x, pix, ng, T);
           const int imax0 = sc.max_depth - d - 1;
           for (uint32_t k = 0; k < gam[2]; ++k) {
-            const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+            const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
             nconn += (uint32_t)max(0, min(imax0, (int)lt.len[lpi].x));
           }
         }
@@ -2041,7 +2044,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
     uint32_t slot = sfirst + gam[1];
     const int imax0 = sc.max_depth - d - 1;
     for (uint32_t k = 0; k < gam[2]; ++k) {
-      const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+      const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
       const int imax = max(0, min(imax0, (int)lt.len[lpi].x));
       for (int i = 1; i <= imax; ++i, ++slot) {
         const size_t e = L + slot;
@@ -2272,7 +2275,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
       uint32_t slot = v2.x + nnee;
       const int imax0 = sc.max_depth - d - 1;
       for (uint32_t k = 0; k < glp; ++k) {
-        const uint32_t lpi = lp_index(root, k, it.lp_stride, npool);
+        const uint32_t lpi = lp_index(q.S3[L + j].x, k, it.lp_stride, npool);
         const uint2 ll = lt.len[lpi];
         const int imax = max(0, min(imax0, (int)ll.x));
         f3 v = mk3(0.0f, 0.0f, 0.0f);

@@ -1,7 +1,8 @@
 // Learned cache: a small MLP that predicts the log sample count of every
-// technique from a vertex's normalised position and shading normal
-// (sin/cos encoding with 6 frequencies -> 72 features, padded to 80; three
-// hidden layers of 64 ReLU units; 3 linear outputs).  Forward and backward
+// technique, relative to |T / I~|, from a vertex's position normalised to the
+// octree's cube and its geometric normal as stored (sin/cos encoding with 6
+// frequencies -> 72 features, padded to 80; three hidden layers of 64 ReLU
+// units; 3 linear outputs).  Forward and backward
 // run as bfloat16 matrix-core products with binary32 accumulation
 // (v_mfma_f32_16x16x16_bf16), one 16-sample tile per wave.  Master weights,
 // biases and Adam moments are binary32.

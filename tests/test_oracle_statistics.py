@@ -237,9 +237,11 @@ def test_vi_matches_independent_variance(mode):
 # Direct light only (D = 2) from a quad emitter above a floor, one cell,
 # fixed counts and a non-uniform starting distribution: the learned pmf
 # (0.9 learned + 0.1 uniform) must match a midpoint quadrature of the
-# emitter's solid angle per bin.  Catches: a sample weighted by its own
-# technique's density only, a bin taken from the outgoing direction, the
-# uniform share mixed in with the wrong weight.
+# emitter's solid angle per bin.  Catches: the luminance added without the
+# density of continuation samples, a bin taken from the outgoing direction,
+# the uniform share mixed in with the wrong weight.  (Dividing by each
+# technique's own density instead is also unbiased for the integral, up to
+# the factor beta_B + beta_G, and gives the same normalised distribution.)
 # ---------------------------------------------------------------------------
 def _floor_and_emitter(width, height, le=3.0):
     rect = (0.1, -0.4, 1.0, 1.0, 0.6)  # x0, y0, size x, size y, height
