@@ -1,17 +1,24 @@
 #!/usr/bin/env python
 """Benchmark of the MARS hot path on one MI355X.
 
-Workload: the guided path-tracing configuration -- 512 x 512 pixels, a seeded
-procedural scene of ~132k triangles (displaced 256 x 256 heightfield + 200
-boxes, GGX materials, 4 quad emitters), three techniques (BSDF, NEE, guided
-8 x 8 histogram per cell), max depth 10, octree cache (8 levels, split after
-32 visits, 72 MB budget).  One step = one MARS iteration: render at 1 sample
-per pixel (all depths, shadow rays, back-propagation, cell statistics) plus
-the update (image estimates, fixed-point factors, guided distribution,
-octree refinement).  The first warm-up steps are classic-RR iterations as in
-the paper's schedule; timed steps are MARS iterations.
+Default workload (the metric's configuration): the learned cache against the
+plain octree, bidirectional MARS at 1920 x 1080 on a seeded procedural
+interior of 2.08M triangles (4500 instanced furniture pieces, one small
+emitter hidden behind an occluder), max path length 12.  One step = one
+learned-cache MARS iteration at 2 samples per pixel: light subpaths, camera
+paths with per-vertex counts from the network pooled with the octree, all
+connections and shadow rays, back-propagation, cell statistics, the update
+(image estimates, fixed point, targets, refinement) and 32 Adam steps of
+the network.  Warm-up steps: 3 classic-RR iterations, then octree MARS
+iterations (the network trains from the first of them).  Beside the
+throughput: the efficiency 1/(relMSE s) of both methods at equal relMSE
+over the paper's growing-iteration schedule, the traversal kernel's
+roofline, and the CPU oracle's throughput on the same scene.
 
-Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
+Other workloads (--workload): guided (512 x 512 guided PT), bdpt
+(1280 x 720 bidirectional), batch (32 scenes), ears (MARS vs EARS vs
+classic RR) and convergence.  Prints one JSON line.  --gpus above 1 is not
+supported (one GPU per box).
 """
 import argparse
 import hashlib
@@ -39,47 +46,75 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(bytes_per_launch):
-    """HBM bytes per launch of the traversal kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "trace_guided512_traffic.json")
+def load_traffic(name, window):
+    """Measured HBM bytes per launch of the traversal kernel from the
+    committed rocprofv3 counter summary profiles/<name>, if it was taken on
+    the current kernel source and over the same window (workload, warm-up and
+    timed steps) as this run; else None."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("window") != window:
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
 
 
-def cpu_baseline(sc, n_pix=262144, seed=7):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    n_pix random pixels of the same 512 x 512 frame, one untimed classic
-    iteration, then timed MARS iterations (render + update)."""
-    import numpy as np
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
 
-    from oracle import oracle as orc
-    threads = orc.set_threads(0)
-    o = orc.Oracle(sc, mode=orc.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
-    rng = np.random.default_rng(seed)
-    o.set_pixel_subset(rng.choice(sc["width"] * sc["height"], n_pix, replace=False))
-    p = orc.Oracle.params(iteration=0, spp=1)
-    o.render_iteration(p)
-    o.update(p)
-    t0 = time.perf_counter()
-    n_iter = 0
-    while True:
-        p = orc.Oracle.params(iteration=1 + n_iter, spp=1, alloc=orc.ALLOC_MARS)
-        o.render_iteration(p)
-        o.update(p)
-        n_iter += 1
-        if time.perf_counter() - t0 > 10.0 or n_iter >= 8:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n_pix * n_iter / dt / 1e6, "unit": "Mpaths/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_pix} random pixels of the 512x512 frame, {n_iter} MARS iterations "
-                      f"(render+update) after one classic iteration, {dt:.1f} s"}
+
+def roofline(api, ctx, prof, step_counted, rays_closest, rays_shadow, traffic_name, window):
+    """The traversal kernel against the HBM roofline.  achieved = algorithmic
+    bytes per launch (per ray: I/O plus one 128 B node per visited node and
+    48 B per tested triangle, node and triangle counts from one instrumented
+    iteration) / the average launch time of the timed steps (HIP events the
+    dispatch stamps).  traffic = measured HBM bytes per launch (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy) over the same
+    window, when a summary of it is committed; measured_hbm_frac follows
+    from it."""
+    ctx.trace_counting(True)
+    step_counted()
+    tc = ctx.trace_counts()
+    ctx.trace_counting(False)
+    bpr_c = BYTES_RAY_IO + (BYTES_NODE * tc[1] + BYTES_TRI * tc[2]) / max(tc[0], 1)
+    bpr_s = BYTES_SHADOW_IO + (BYTES_NODE * tc[4] + BYTES_TRI * tc[5]) / max(tc[3], 1)
+    ms_tr, n_tr = prof["trace"]
+    avg_ms = ms_tr / max(n_tr, 1)
+    bytes_per_launch = (bpr_c * rays_closest + bpr_s * rays_shadow) / max(n_tr, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    t = load_traffic(traffic_name, window)
+    traffic = t["hbm_bytes_per_launch"] if t else None
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "trace",
+           "achieved_is": "algorithmic bytes (every visited node and tested triangle counted "
+                          "as fetched) / average launch time",
+           "avg_launch_ms": avg_ms, "launches_timed": n_tr,
+           "algorithmic_bytes_per_launch": bytes_per_launch,
+           "bytes_per_closest_ray": bpr_c, "bytes_per_shadow_ray": bpr_s,
+           "nodes_per_closest_ray": tc[1] / max(tc[0], 1),
+           "tris_per_closest_ray": tc[2] / max(tc[0], 1),
+           "nodes_per_shadow_ray": tc[4] / max(tc[3], 1),
+           "max_nodes_closest_ray": tc[6], "max_nodes_shadow_ray": tc[7],
+           "rays_over_64_nodes": [tc[8], tc[9]]}
+    if t:
+        out["measured_hbm_gbs"] = traffic / (avg_ms * 1e-3) / 1e9
+        out["measured_hbm_frac"] = out["measured_hbm_gbs"] / HBM_PEAK_GBS
+        out["traffic_source"] = "profiles/" + traffic_name
+        for k in ("occupancy_waves_per_simd", "vgprs", "scratch_bytes"):
+            if k in t:
+                out[k] = t[k]
+    return out
 
 
 def relmse(img, ref, eps=1e-2, drop=1e-4):
@@ -266,83 +301,268 @@ def run_bdpt(args, api, torch):
     return out
 
 
-def run_mlp(args, api, torch, n_iter=14, seeds=(1, 2, 3)):
-    train_steps = args.mlp_train_steps
-    """Learned-cache workload: 1920x1080 BDPT interior of 2.08M triangles,
-    max path length 12.  Octree MARS and learned-cache MARS run the same
-    schedule (3 classic iterations, MARS from the 4th, the network's counts
-    from the 9th; iterations of 2 spp; the network trained --mlp-train-steps
-    (32) Adam steps of 8192 samples after every update from the 4th iteration
-    on; queue and tile
-    sizes from the autotuner before the 4th).  Efficiency
-    1/(relMSE * s) of the IVW image of each against a 256 spp classic
-    reference, and the mean 1/(V_I C_I) of the last 6 iterations; each pair is
-    run with several random-stream seeds and the value is the geometric mean
-    of the per-seed efficiency ratios."""
-    import numpy as np
+LEARNED_WORKLOAD = "learned_vs_octree_bdpt_1920x1080_interior2m_d12"
+LEARNED_SPP = 2            # camera samples per pixel of a timed step
+LEARNED_TRAIN_STEPS = 32   # Adam steps of 8192 samples after every update
+
+
+def learned_scene():
     import scenegen
-    sc = scenegen.make_interior(seed=3, width=1920, height=1080, n_pieces=4500)
-    ctx = api.Context(0)
-    ref = reference_image(api, ctx, sc, spp=16, iters=16, mode=api.MODE_BDPT, depth=12)
-    print("[bench] mlp: reference done", file=sys.stderr, flush=True)
+    return scenegen.make_interior(seed=3, width=1920, height=1080, n_pieces=4500)
+
+
+def relmse_pair(img, r1, r2, eps=1e-2, drop=1e-4):
+    """relMSE against the mean of two independent half references, with the
+    reference's own noise removed: E[(I - (R1+R2)/2)^2] exceeds the error to
+    the expectation by Var(R)/2 per half, estimated per pixel as
+    (R1 - R2)^2 / 4.  Same outlier rule and epsilon as relmse()."""
+    import numpy as np
+    ref = 0.5 * (r1 + r2)
+    d = img.astype(np.float64) - ref
+    noise = 0.25 * (r1 - r2) ** 2
+    e = np.sort(np.mean((d * d - noise) / (ref * ref + eps), axis=-1).ravel())
+    keep = e.size - int(np.floor(drop * e.size))
+    return float(np.mean(e[:keep]))
+
+
+def time_to_relmse(curve, target):
+    """Seconds a (seconds, relMSE) curve needs to reach `target`,
+    interpolated log-log between the iterations around it; None if never."""
+    import math
+    prev = None
+    for t, e in curve:
+        if e <= target:
+            if prev is None or prev[1] <= e:
+                return t
+            a = (math.log(target) - math.log(prev[1])) / (math.log(e) - math.log(prev[1]))
+            return math.exp(math.log(prev[0]) + a * (math.log(t) - math.log(prev[0])))
+        prev = (t, e)
+    return None
+
+
+def learned_efficiency(api, ctx, sc, torch, seeds=(1, 2, 3), n_iter=11, ref_half_spp=512):
+    """Octree MARS and learned-cache MARS over the growing-iteration schedule
+    (spp_i = min(2^max(0, i - 3), 16): 3 classic-RR iterations, octree MARS
+    from the 4th, the network's counts from the 6th; the network trains 32
+    Adam steps after every update from the 4th; queue and tile sizes from the
+    autotuner before the 4th), each iteration's inverse-variance weighted
+    image scored against a reference of 2 x ref_half_spp spp of classic-RR
+    BDPT with its own noise removed.  Efficiency at equal relMSE: the target
+    is the larger of the two methods' final relMSE, each method's time to
+    reach it is interpolated on its curve, and efficiency = 1 / (target x
+    time).  Three random-stream seeds; the value is the geometric mean of
+    the per-seed ratios."""
+    import math
+
+    import numpy as np
+
+    def half(base):
+        r = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget())
+        acc = np.zeros((sc["height"], sc["width"], 3))
+        n = ref_half_spp // 16
+        for i in range(n):
+            r.render_iteration(api.iter_params(iteration=base + i, spp=16, stat_clamp=0.0))
+            acc += r.image(api.IMAGE_LAST)
+        r.release()
+        return acc / n
+    t0 = time.perf_counter()
+    r1, r2 = half(100000), half(200000)
+    t_ref = time.perf_counter() - t0
+    print(f"[bench] learned: reference {2 * ref_half_spp} spp in {t_ref:.1f} s", file=sys.stderr,
+          flush=True)
     runs = []
     for seed in seeds:
-        res = {}
-        for kind in ("octree", "mlp"):
+        res = {"seed": seed}
+        for kind in ("octree", "learned"):
             s = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget(),
-                          mlp=(kind == "mlp"), seed=seed)
-            vc = []
-            dt = 0.0
-            t_train = 0.0
+                          mlp=(kind == "learned"), seed=seed)
+            curve, t_cum, rays, spp_tot, t_train = [], 0.0, 0, 0, 0.0
             for i in range(n_iter):
+                spp = min(1 << max(0, i - 3), 16)
                 alloc = api.ALLOC_CLASSIC if i < 3 else api.ALLOC_MARS
-                if kind == "mlp" and i >= 8:
+                if kind == "learned" and i >= 5:
                     alloc = api.ALLOC_MLP
-                p = api.iter_params(iteration=i, spp=2, alloc=alloc, stat_clamp=0.0)
+                p = api.iter_params(iteration=i, spp=spp, alloc=alloc, stat_clamp=0.0)
                 if i == 3:
-                    # queue and tile sizes for the MARS iterations (untimed; the
-                    # two runs are identical up to here and get the same sizes)
                     api.autotune([s], p, mem_budget=96 << 30)
                     torch.cuda.empty_cache()
                 torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                s.render_iteration(p)
-                us = s.update(p)
-                if kind == "mlp" and i >= 3:
+                ta = time.perf_counter()
+                rays += s.render_iteration(p).total_rays()
+                s.update(p)
+                if kind == "learned" and i >= 3:
                     torch.cuda.synchronize()
                     tt = time.perf_counter()
-                    s.mlp_train(steps=train_steps, batch=8192, lr=2e-3)
+                    s.mlp_train(steps=LEARNED_TRAIN_STEPS, batch=8192, lr=2e-3)
                     torch.cuda.synchronize()
                     t_train += time.perf_counter() - tt
                 torch.cuda.synchronize()
-                dt += time.perf_counter() - t0
-                if i >= n_iter - 6:
-                    vc.append(1.0 / (us.V_I * us.C_I))
-            e = relmse(s.image(api.IMAGE_IVW), ref)
-            res[kind] = {"relmse": e, "seconds": dt, "efficiency": 1.0 / (e * dt),
-                         "inv_vi_ci_last6": float(np.mean(vc)), "train_seconds": t_train}
+                t_cum += time.perf_counter() - ta
+                spp_tot += spp
+                curve.append((t_cum, relmse_pair(s.image(api.IMAGE_IVW), r1, r2)))
             s.release()
-        res["seed"] = seed
-        res["ratio"] = res["mlp"]["efficiency"] / res["octree"]["efficiency"]
-        res["inv_vi_ci_ratio"] = res["mlp"]["inv_vi_ci_last6"] / res["octree"]["inv_vi_ci_last6"]
-        print(f"[bench] mlp: seed {seed} ratio {res['ratio']:.3f}", file=sys.stderr, flush=True)
+            res[kind] = {"curve": [[round(t, 4), e] for t, e in curve], "seconds": t_cum,
+                         "relmse": curve[-1][1], "rays": rays, "spp": spp_tot,
+                         "train_seconds": t_train,
+                         "efficiency_equal_iterations": 1.0 / (curve[-1][1] * t_cum)}
+        target = max(res["octree"]["relmse"], res["learned"]["relmse"])
+        for kind in ("octree", "learned"):
+            tk = time_to_relmse([tuple(c) for c in res[kind]["curve"]], target)
+            res[kind]["seconds_to_target"] = tk
+            res[kind]["efficiency"] = 1.0 / (target * tk)
+        res["target_relmse"] = target
+        res["ratio"] = res["learned"]["efficiency"] / res["octree"]["efficiency"]
+        print(f"[bench] learned: seed {seed} ratio {res['ratio']:.3f}", file=sys.stderr, flush=True)
         runs.append(res)
-    px = sc["width"] * sc["height"]
-    ratios = np.array([r["ratio"] for r in runs])
-    mlp_seconds = float(np.mean([r["mlp"]["seconds"] for r in runs]))
-    return {"metric": "efficiency 1/(relMSE*s): learned cache vs octree MARS",
-            "value": float(np.exp(np.mean(np.log(ratios)))),
-            "unit": "ratio", "n_gpus": 1, "steps": n_iter, "warmup": 3,
-            "ms_per_step": mlp_seconds * 1e3 / n_iter, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network, f32 radiance",
-            "data": "synthetic",
-            "config": {"workload": "mlp_bdpt_1920x1080_interior2m_d12", "width": sc["width"],
-                       "height": sc["height"], "triangles": int(sc["V"].shape[0]),
-                       "max_depth": 12, "spp_per_iteration": 2, "reference_spp": 256,
-                       "seeds": list(seeds), "train_steps": train_steps},
-            "per_seed": runs,
-            "paths_per_s_mlp": px * 2 * n_iter / mlp_seconds / 1e6,
-            "inv_vi_ci_ratio": float(np.exp(np.mean(np.log([r["inv_vi_ci_ratio"] for r in runs]))))}
+    ratios = [r["ratio"] for r in runs]
+    return {"definition": "1/(relMSE*s) at equal relMSE: the larger final relMSE of the two "
+                          "methods is the target, each method's time to reach it interpolated "
+                          "log-log on its per-iteration curve; relMSE = mean (I-R)^2/(R^2+0.01) "
+                          "minus the reference's own noise, 0.01% largest terms discarded",
+            "ratio_learned_vs_octree": float(math.exp(np.mean(np.log(ratios)))),
+            "ratio_per_seed": ratios,
+            "octree": float(np.mean([r["octree"]["efficiency"] for r in runs])),
+            "learned": float(np.mean([r["learned"]["efficiency"] for r in runs])),
+            "schedule_spp": [min(1 << max(0, i - 3), 16) for i in range(n_iter)],
+            "reference_spp": 2 * ref_half_spp, "reference_seconds": t_ref, "per_seed": runs}
+
+
+def cpu_baseline_learned(sc, warm, spp=LEARNED_SPP, frac=0.25, seed=7):
+    """The oracle as it stands (octree MARS: it has no learned cache) on the
+    same scene at 1/16 of the pixels (480 x 270), a random quarter of them
+    rendered: `warm` warm-up iterations (3 classic), then timed MARS
+    iterations of `spp` samples per pixel (render + update) on all host
+    threads, then one of 1 spp on a single thread."""
+    import numpy as np
+
+    import scenegen
+    from oracle import oracle as orc
+    small = scenegen.scaled(sc, 480, 270)
+    threads = orc.set_threads(0)
+    o = orc.Oracle(small, mode=orc.MODE_BDPT, max_depth=12, max_cells=cells_budget())
+    rng = np.random.default_rng(seed)
+    npx = small["width"] * small["height"]
+    sub = rng.choice(npx, int(frac * npx), replace=False)
+    o.set_pixel_subset(sub)
+    for i in range(warm):
+        alloc = orc.ALLOC_CLASSIC if i < 3 else orc.ALLOC_MARS
+        p = orc.Oracle.params(iteration=i, spp=1 if i < 3 else spp, alloc=alloc, stat_clamp=0.0)
+        o.render_iteration(p)
+        o.update(p)
+    t0 = time.perf_counter()
+    n_iter, rays = 0, 0
+    while True:
+        p = orc.Oracle.params(iteration=warm + n_iter, spp=spp, alloc=orc.ALLOC_MARS,
+                              stat_clamp=0.0)
+        rays += o.render_iteration(p).total_rays()
+        o.update(p)
+        n_iter += 1
+        if time.perf_counter() - t0 > 12.0 or n_iter >= 3:
+            break
+    dt = time.perf_counter() - t0
+    # one core: one more iteration of 1 spp on the same pixels (the light
+    # subpaths of every pixel are traced whatever the subset, so a smaller
+    # subset would not scale)
+    orc.set_threads(1)
+    p = orc.Oracle.params(iteration=warm + n_iter, spp=1, alloc=orc.ALLOC_MARS, stat_clamp=0.0)
+    t1 = time.perf_counter()
+    o.render_iteration(p)
+    o.update(p)
+    dt1 = time.perf_counter() - t1
+    orc.set_threads(0)
+    paths = len(sub) * spp * n_iter
+    return {"value": paths / dt / 1e6, "unit": "Mpaths/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_info(), "mrays_per_s": rays / dt / 1e6,
+            "one_core_mpaths_per_s": len(sub) / dt1 / 1e6,
+            "sample": f"the oracle's octree MARS (no learned cache) on the same scene at "
+                      f"480x270, {len(sub)} random pixels, {warm} warm-up iterations, "
+                      f"{n_iter} timed iterations of {spp} spp in {dt:.1f} s on {threads} "
+                      f"threads; the one-core figure from one more iteration of 1 spp on the "
+                      f"same pixels ({dt1:.1f} s)"}
+
+
+def run_learned(args, api, torch):
+    """The default workload: learned-cache MARS iterations on the 1920x1080
+    bidirectional interior (see the module docstring)."""
+    sc = learned_scene()
+    ctx = api.Context(0)
+    s = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget(), mlp=True,
+                  seed=1)
+    n_warm = max(args.warmup, 4)   # 3 classic + at least one octree MARS update to train on
+
+    def alloc_of(i):
+        if i < 3:
+            return api.ALLOC_CLASSIC
+        return api.ALLOC_MARS if i < n_warm else api.ALLOC_MLP
+
+    def step(i):
+        p = api.iter_params(iteration=i, spp=LEARNED_SPP, alloc=alloc_of(i), stat_clamp=0.0)
+        if i == 3:
+            api.autotune([s], p, mem_budget=96 << 30)
+            torch.cuda.empty_cache()
+        st = s.render_iteration(p)
+        us = s.update(p)
+        if i >= 3:
+            s.mlp_train(steps=LEARNED_TRAIN_STEPS, batch=8192, lr=2e-3)
+        return st, us
+
+    for i in range(n_warm):
+        step(i)
+        print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile(True, kernels=["trace"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rays = rays_closest = rays_shadow = 0
+    for k in range(args.steps):
+        st, _ = step(n_warm + k)
+        rays += st.total_rays()
+        rays_closest += st.rays_camera + st.rays_ext + st.rays_light
+        rays_shadow += st.rays_shadow + st.rays_conn
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    window = {"workload": LEARNED_WORKLOAD, "warmup": n_warm, "steps": args.steps}
+    paths = args.steps * sc["width"] * sc["height"] * LEARNED_SPP
+    out = {
+        "metric": "Mpaths/s of learned-cache MARS iterations; efficiency 1/(relMSE*s) of the "
+                  "learned cache vs octree MARS at equal relMSE beside it",
+        "value": paths / dt / 1e6, "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 radiance, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": LEARNED_WORKLOAD, "width": sc["width"], "height": sc["height"],
+                   "triangles": int(sc["V"].shape[0]), "max_depth": 12,
+                   "spp_per_step": LEARNED_SPP, "techniques": ["bsdf", "nee", "light_path"],
+                   "network": "6 inputs, 72 sin/cos features, 3 x 64 ReLU, 3 log counts",
+                   "train_steps_per_update": LEARNED_TRAIN_STEPS, "max_cells": cells_budget(),
+                   "warmup_iterations": n_warm},
+        "mrays_per_s": rays / dt / 1e6,
+        "trace_launches_timed": prof["trace"][1],
+    }
+    if args.profile_steps >= 0:
+        print(json.dumps(out), flush=True)
+        return None
+    n_brk = 2
+    ctx.profile(True)
+    for k in range(n_brk):
+        step(n_warm + args.steps + k)
+    brk = ctx.profile_read()
+    ctx.profile(False)
+    out["kernels_ms_per_step"] = {k: round(v[0] / n_brk, 3) for k, v in brk.items() if v[1]}
+    out["roofline"] = roofline(api, ctx, prof, lambda: step(n_warm + args.steps + n_brk),
+                               rays_closest, rays_shadow, "trace_learned1080_traffic.json",
+                               window)
+    s.release()
+    if not args.no_efficiency:
+        print("[bench] learned: efficiency", file=sys.stderr, flush=True)
+        out["efficiency"] = learned_efficiency(api, ctx, sc, torch)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_learned(sc, n_warm)
+    return out
 
 
 def run_convergence(args, api, torch, seeds=(1, 2, 3), n_iter=9):
@@ -540,41 +760,57 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
     return ctx_out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=-1,
-                    help="(profiling runs) skip the instrumented iteration and the CPU leg")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="guided",
-                    choices=["guided", "batch", "bdpt", "mlp", "ears", "convergence"],
-                    help="guided: the 512x512 guided-PT workload; batch: 32 mixed scenes; "
-                         "bdpt: 1280x720 bidirectional; mlp: 1920x1080 learned cache vs octree; "
-                         "ears: MARS vs EARS vs classic RR efficiency (guided and bidirectional); "
-                         "convergence: per-iteration counts and efficiency over several seeds")
-    ap.add_argument("--no-efficiency", action="store_true")
-    ap.add_argument("--mlp-train-steps", type=int, default=32,
-                    help="learned-cache workload: Adam steps of 8192 samples after each update")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
-                                   "--gpus must be 1"}))
-        sys.exit(2)
+def cpu_baseline_guided(sc, warm, n_pix=65536, seed=7):
+    """The oracle as it stands on the guided workload: n_pix random pixels of
+    the same 512 x 512 frame, the same `warm` warm-up iterations as the GPU
+    (the first three classic), then the MARS iterations the GPU times (render
+    + update, 1 spp) on all host threads, and one more on a single thread
+    over a sixteenth of the pixels."""
+    import numpy as np
 
-    import torch
+    from oracle import oracle as orc
+    threads = orc.set_threads(0)
+    o = orc.Oracle(sc, mode=orc.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
+    rng = np.random.default_rng(seed)
+    sub = rng.choice(sc["width"] * sc["height"], n_pix, replace=False)
+    o.set_pixel_subset(sub)
+    for i in range(warm):
+        p = orc.Oracle.params(iteration=i, spp=1,
+                              alloc=orc.ALLOC_CLASSIC if i < min(3, warm) else orc.ALLOC_MARS)
+        o.render_iteration(p)
+        o.update(p)
+    t0 = time.perf_counter()
+    n_iter = rays = 0
+    while True:
+        p = orc.Oracle.params(iteration=warm + n_iter, spp=1, alloc=orc.ALLOC_MARS)
+        rays += o.render_iteration(p).total_rays()
+        o.update(p)
+        n_iter += 1
+        if time.perf_counter() - t0 > 10.0 or n_iter >= 8:
+            break
+    dt = time.perf_counter() - t0
+    orc.set_threads(1)
+    o.set_pixel_subset(sub[: n_pix // 16])
+    p = orc.Oracle.params(iteration=warm + n_iter, spp=1, alloc=orc.ALLOC_MARS)
+    t1 = time.perf_counter()
+    o.render_iteration(p)
+    o.update(p)
+    dt1 = time.perf_counter() - t1
+    orc.set_threads(0)
+    return {"value": n_pix * n_iter / dt / 1e6, "unit": "Mpaths/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_info(), "mrays_per_s": rays / dt / 1e6,
+            "one_core_mpaths_per_s": (n_pix // 16) / dt1 / 1e6,
+            "sample": f"{n_pix} random pixels of the 512x512 frame, the GPU's {warm} warm-up "
+                      f"iterations, then {n_iter} MARS iterations (render+update, the GPU's "
+                      f"timed iterations {warm}..{warm + n_iter - 1}) in {dt:.1f} s on "
+                      f"{threads} threads; one core: one iteration on {n_pix // 16} pixels"}
 
+
+def run_guided(args, api, torch):
+    """Guided path tracing at 512 x 512 on the 132k-triangle heightfield:
+    one step = one MARS iteration at 1 spp (render + update) after classic
+    warm-up iterations; efficiency of MARS vs classic RR beside it."""
     import scenegen
-    from paper_2410_20429_amd import api
-
-    if args.workload != "guided":
-        run = {"batch": run_batch, "bdpt": run_bdpt, "mlp": run_mlp, "ears": run_ears,
-               "convergence": run_convergence}[args.workload]
-        print(json.dumps(run(args, api, torch)), flush=True)
-        return
     sc = scenegen.make_heightfield_scene(seed=1)
     ctx = api.Context(0)
     s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
@@ -587,21 +823,8 @@ def main():
         us = s.update(p)
         return st, us
 
-    if args.copy_calib:
-        # plain copy of known size: 1 GiB read + 1 GiB written
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        bcopy = torch.empty_like(a)
-        torch.cuda.synchronize()
-        bcopy.copy_(a)
-        torch.cuda.synchronize()
-        del a, bcopy
-    t_warm = 0.0
     for i in range(args.warmup):
-        torch.cuda.synchronize()
-        tw = time.perf_counter()
         step(i)
-        torch.cuda.synchronize()
-        t_warm += time.perf_counter() - tw
         print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     # HIP events around the launches of the roofline's kernel only, so that
@@ -620,64 +843,82 @@ def main():
     prof = ctx.profile_read()
     ctx.profile(False)
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
-    # per-kernel breakdown: two more steps with events around every launch
+    paths = args.steps * sc["width"] * sc["height"]
+    out = {
+        "metric": "Mpaths/s (guided MARS iterations; efficiency 1/(relMSE*s) beside it)",
+        "value": paths / dt / 1e6, "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "width": sc["width"], "height": sc["height"],
+                   "triangles": int(sc["V"].shape[0]), "max_depth": 10, "spp_per_step": 1,
+                   "techniques": ["bsdf", "nee", "guided"], "max_cells": cells_budget()},
+        "mrays_per_s": rays / dt / 1e6,
+        "trace_launches_timed": prof["trace"][1],
+    }
+    if args.profile_steps >= 0:
+        print(json.dumps(out), flush=True)
+        return None
     n_brk = 2
     ctx.profile(True)
     for k in range(n_brk):
         step(args.warmup + args.steps + k)
     brk = ctx.profile_read()
     ctx.profile(False)
-    paths = args.steps * sc["width"] * sc["height"]
-    out = {
-        "metric": "Mpaths/s (efficiency 1/(relMSE*s) reported beside it)",
-        "value": paths / dt / 1e6,
-        "unit": "Mpaths/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD, "width": sc["width"], "height": sc["height"],
-                   "triangles": int(sc["V"].shape[0]), "max_depth": 10, "spp_per_step": 1,
-                   "techniques": ["bsdf", "nee", "guided"], "max_cells": cells_budget()},
-        "mrays_per_s": rays / dt / 1e6,
-        "kernels_ms_per_step": {k: round(v[0] / n_brk, 3) for k, v in brk.items() if v[1]},
-    }
-    if args.profile_steps < 0:
-        if not args.no_efficiency:
-            print("[bench] efficiency", file=sys.stderr, flush=True)
-            out["efficiency"] = efficiency_leg(api, ctx, sc, torch)
-        # algorithmic bytes of the dominant kernel from one instrumented iteration
-        ctx.trace_counting(True)
-        st, _ = step(args.warmup + args.steps + n_brk)
-        tc = ctx.trace_counts()
-        ctx.trace_counting(False)
-        # per ray: I/O plus one 128 B node per visited node and 48 B per tested triangle
-        bpr_c = BYTES_RAY_IO + (BYTES_NODE * tc[1] + BYTES_TRI * tc[2]) / max(tc[0], 1)
-        bpr_s = BYTES_SHADOW_IO + (BYTES_NODE * tc[4] + BYTES_TRI * tc[5]) / max(tc[3], 1)
-        ms_tr, n_tr = prof["trace"]
-        avg_ms = ms_tr / max(n_tr, 1)
-        bytes_per_launch = (bpr_c * rays_closest + bpr_s * rays_shadow) / max(n_tr, 1)
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(bytes_per_launch)
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "trace", "avg_launch_ms": avg_ms,
-                           "algorithmic_bytes_per_launch": bytes_per_launch,
-                           "bytes_per_closest_ray": bpr_c, "bytes_per_shadow_ray": bpr_s,
-                           "nodes_per_closest_ray": tc[1] / max(tc[0], 1),
-                           "tris_per_closest_ray": tc[2] / max(tc[0], 1),
-                           "nodes_per_shadow_ray": tc[4] / max(tc[3], 1),
-                           "max_nodes_closest_ray": tc[6], "max_nodes_shadow_ray": tc[7],
-                           "rays_over_64_nodes": [tc[8], tc[9]]}
-        if not args.no_cpu_baseline:
-            print("[bench] cpu baseline", file=sys.stderr, flush=True)
-            out["cpu_baseline"] = cpu_baseline(sc)
-    print(json.dumps(out), flush=True)
+    out["kernels_ms_per_step"] = {k: round(v[0] / n_brk, 3) for k, v in brk.items() if v[1]}
+    window = {"workload": WORKLOAD, "warmup": args.warmup, "steps": args.steps}
+    out["roofline"] = roofline(api, ctx, prof, lambda: step(args.warmup + args.steps + n_brk),
+                               rays_closest, rays_shadow, "trace_guided512_traffic.json", window)
+    if not args.no_efficiency:
+        print("[bench] efficiency", file=sys.stderr, flush=True)
+        out["efficiency"] = efficiency_leg(api, ctx, sc, torch)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_guided(sc, args.warmup)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=-1,
+                    help="(profiling runs) stop after the timed steps: no breakdown, "
+                         "roofline, efficiency or CPU leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", default="learned",
+                    choices=["learned", "mlp", "guided", "batch", "bdpt", "ears", "convergence"],
+                    help="learned (default; mlp is the same): 1920x1080 bidirectional, learned "
+                         "cache vs octree; guided: the 512x512 guided-PT workload; batch: 32 "
+                         "mixed scenes; bdpt: 1280x720 bidirectional; ears: MARS vs EARS vs "
+                         "classic RR efficiency (guided and bidirectional); convergence: "
+                         "per-iteration counts and efficiency over several seeds")
+    ap.add_argument("--no-efficiency", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
+                                   "--gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2410_20429_amd import api
+
+    if args.copy_calib:
+        # plain copy of known size: 1 GiB read + 1 GiB written
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        torch.cuda.synchronize()
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
+    run = {"learned": run_learned, "mlp": run_learned, "guided": run_guided, "batch": run_batch,
+           "bdpt": run_bdpt, "ears": run_ears, "convergence": run_convergence}[args.workload]
+    out = run(args, api, torch)
+    if out is not None:
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

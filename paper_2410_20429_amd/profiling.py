@@ -2,7 +2,13 @@
 WRITE_SIZE counters) for the committed profile notes.
 
     python -m paper_2410_20429_amd.profiling stats <kernel_stats.csv> <command...>
-    python -m paper_2410_20429_amd.profiling traffic <fetch.csv> <write.csv> <kernel> <calls/step>
+    python -m paper_2410_20429_amd.profiling window <kernel_trace.csv> <kernel> <last_n>
+    python -m paper_2410_20429_amd.profiling traffic <fetch.csv> <write.csv> <kernel> <last_n> \
+        <workload> <warmup> <steps> [<occupancy.csv>]
+
+`last_n` selects the last n dispatches of the kernel: a profiling run of
+bench.py (--profile-steps) stops after its timed steps, which it reports as
+trace_launches_timed, so these are exactly the timed region's launches.
 
 HBM counters are calibrated with a plain device copy of known size run in the
 same process (1 GiB read + 1 GiB written): each counter is scaled by
@@ -37,11 +43,31 @@ def kernel_stats_md(path, command):
     return f"Command: `{command}`\n\n" + "\n".join(lines) + "\n"
 
 
-def _per_kernel(path):
+def _order(r):
+    for k in ("Dispatch_Id", "Correlation_Id", "Index"):
+        if k in r and r[k] not in (None, ""):
+            return int(r[k])
+    return 0
+
+
+def _per_kernel(path, counter=None):
+    """{kernel: [value per dispatch in dispatch order]} of one counter"""
+    rows = [r for r in csv.DictReader(open(path))
+            if counter is None or r.get("Counter_Name", counter) == counter]
+    rows.sort(key=_order)
     out = {}
-    for r in csv.DictReader(open(path)):
+    for r in rows:
         out.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
     return out
+
+
+def window_stats(trace_csv, kernel, last_n):
+    """average and total duration of the last `last_n` dispatches of a kernel"""
+    rows = [r for r in csv.DictReader(open(trace_csv)) if short_name(r["Kernel_Name"]) == kernel]
+    rows.sort(key=_order)
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows[-last_n:]]
+    return {"kernel": kernel, "launches": len(d), "avg_us": sum(d) / len(d) / 1e3,
+            "total_ms": sum(d) / 1e6, "all_launches": len(rows)}
 
 
 def kernel_source_hash():
@@ -52,7 +78,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic(fetch_csv, write_csv, kernel):
+def traffic(fetch_csv, write_csv, kernel, last_n=None, window=None, occupancy_csv=None):
+    """Measured HBM bytes per launch of `kernel` over its last `last_n`
+    dispatches, each counter scaled by known / counted bytes of the plain
+    1 GiB copy in the same process.  With an occupancy counter file
+    (SQ_WAVE_CYCLES and SQ_BUSY_CYCLES, or the derived MeanOccupancyPerCU),
+    the mean waves resident per SIMD over the same dispatches."""
     f, w = _per_kernel(fetch_csv), _per_kernel(write_csv)
     # the calibration copy is the largest copy dispatch
     cf = max(f.get("__amd_rocclr_copyBuffer", [0]))
@@ -60,17 +91,46 @@ def traffic(fetch_csv, write_csv, kernel):
     fs = COPY_BYTES / (cf * 1024.0) if cf > 0 else None
     ws = COPY_BYTES / (cw * 1024.0) if cw > 0 else None
     kf, kw = f.get(kernel, []), w.get(kernel, [])
+    if last_n:
+        kf, kw = kf[-last_n:], kw[-last_n:]
     if not kf or not kw or fs is None or ws is None:
         return None
     fetch = sum(kf) / len(kf) * 1024.0 * fs
     write = sum(kw) / len(kw) * 1024.0 * ws
-    return {"kernel": kernel, "launches": len(kf), "fetch_scale": fs, "write_scale": ws,
-            "hbm_fetch_bytes_per_launch": fetch, "hbm_write_bytes_per_launch": write,
-            "hbm_bytes_per_launch": fetch + write, "kernel_source_hash": kernel_source_hash()}
+    out = {"kernel": kernel, "launches": len(kf), "fetch_scale": fs, "write_scale": ws,
+           "hbm_fetch_bytes_per_launch": fetch, "hbm_write_bytes_per_launch": write,
+           "hbm_bytes_per_launch": fetch + write, "kernel_source_hash": kernel_source_hash()}
+    if window:
+        out["window"] = window
+    if occupancy_csv:
+        occ = _occupancy(occupancy_csv, kernel, last_n)
+        if occ is not None:
+            out["occupancy_waves_per_simd"] = occ
+    return out
+
+
+def _occupancy(path, kernel, last_n, simds=4 * 256):
+    """mean resident waves per SIMD: SQ_WAVE_CYCLES (wave-cycles summed over
+    the chip) / SQ_BUSY_CYCLES / SIMDs, or MeanOccupancyPerCU / 4"""
+    wc = _per_kernel(path, "SQ_WAVE_CYCLES").get(kernel, [])
+    bc = _per_kernel(path, "SQ_BUSY_CYCLES").get(kernel, [])
+    if wc and bc:
+        wc, bc = wc[-last_n:], bc[-last_n:]
+        return sum(wc) / max(sum(bc), 1.0) / simds
+    mo = _per_kernel(path, "MeanOccupancyPerCU").get(kernel, [])
+    if mo:
+        mo = mo[-last_n:]
+        return sum(mo) / len(mo) / 4.0
+    return None
 
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(kernel_stats_md(sys.argv[2], " ".join(sys.argv[3:])))
+    elif sys.argv[1] == "window":
+        print(json.dumps(window_stats(sys.argv[2], sys.argv[3], int(sys.argv[4])), indent=1))
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+        win = {"workload": sys.argv[6], "warmup": int(sys.argv[7]), "steps": int(sys.argv[8])}
+        occ = sys.argv[9] if len(sys.argv) > 9 else None
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), win, occ),
+                         indent=1))
