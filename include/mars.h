@@ -318,6 +318,21 @@ mars_status mars_mlp_grad(mars_ctx* ctx, int32_t scene_id, const float* x6, cons
 /* one Adam step with the given gradient (host [num_params]) */
 mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* grad, float lr);
 
+/* Allocation-free variant of mars_mlp_grad, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops): it calls no hipMalloc, hipFree or allocating routine.  x6 [n][6],
+ * target [n][3], weight [n][3] and grad [num_params + 1] (the gradient, then
+ * the loss) are DEVICE pointers on the context's device, owned by the
+ * caller.  The work is enqueued on the context's stream and not waited
+ * for; grad is complete when the stream reaches that point.  The
+ * per-workgroup partial gradients go to a fixed device array of 256 x
+ * (num_params + 1) binary32 words (14.9 MB), one per device, held until the
+ * process ends: n is limited to 262144 (MARS_E_ARG beyond), and calls that
+ * overlap on one device (on different streams or contexts) race on that
+ * array.  The result equals mars_mlp_grad's bit for bit. */
+mars_status mars_mlp_grad_noalloc(mars_ctx* ctx, int32_t scene_id, const float* x6,
+                                  const float* target, const float* weight, int32_t n,
+                                  float* grad);
 /* The training set (tests).  mars_mlp_write_records replaces the recorded
  * vertices: host pos, nrm, T [n][3] (binary32, finite) and pix [n] (< W*H);
  * n at most the record capacity (2^18), else MARS_E_ARG.

@@ -114,6 +114,7 @@ SIGNATURES = {
     "mars_mlp_forward": [P, I32, P, I32, P],
     "mars_mlp_grad": [P, I32, P, P, P, I32, P, P],
     "mars_mlp_apply_grad": [P, I32, P, C.c_float],
+    "mars_mlp_grad_noalloc": [P, I32, P, P, P, I32, P],
     "mars_mlp_write_records": [P, I32, P, P, P, P, I32],
     "mars_mlp_targets_only": [P, I32],
     "mars_mlp_read_train": [P, I32, P, P, P, I32, PI32],
@@ -376,6 +377,11 @@ def mars_mlp_grad(ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr):
 
 def mars_mlp_apply_grad(ctx, sid, g_ptr, lr):
     _call("mars_mlp_apply_grad", ctx, sid, g_ptr, float(lr))
+
+
+def mars_mlp_grad_noalloc(ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr):
+    """device pointers; enqueued on the context's stream, not waited for"""
+    _call("mars_mlp_grad_noalloc", ctx, sid, x_ptr, t_ptr, w_ptr, n, g_ptr)
 
 
 def mars_mlp_write_records(ctx, sid, pos_ptr, nrm_ptr, t_ptr, pix_ptr, n):

@@ -147,6 +147,8 @@ static_assert(sizeof(Counters) <= kPinnedBytes && 8 * 8 + 4 * 4 + 4 <= kPinnedBy
 
 struct Ctx {
   int device = 0;
+  float* noalloc_scratch = nullptr;  // device address of the fixed gradient array
+  std::string noalloc_error;
   uint64_t next_uid = 1;
   // batched iterations: a pool of default-priority streams and the graph cache
   std::vector<hipStream_t> pool;
@@ -1381,6 +1383,14 @@ mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
     delete c;
     return MARS_E_OOM;
   }
+  {
+    const hipError_t e = noalloc_scratch_address(desc->device, &c->noalloc_scratch);
+    if (e != hipSuccess) {
+      c->noalloc_scratch = nullptr;
+      c->noalloc_error = std::string("address of the fixed gradient array: ") +
+                         hipGetErrorString(e);
+    }
+  }
   c->batch_streams = kBatchStreams;
   if (const char* e = std::getenv("MARS_BATCH_STREAMS")) {
     const int k = std::atoi(e);
@@ -1962,6 +1972,25 @@ mars_status mars_mlp_apply_grad(mars_ctx* ctx, int32_t scene_id, const float* gr
       HIPCHK(hipStreamSynchronize(ctx->stream));
       HIPCHK(hipGetLastError());
     });
+  });
+}
+
+mars_status mars_mlp_grad_noalloc(mars_ctx* ctx, int32_t scene_id, const float* x6,
+                                  const float* target, const float* weight, int32_t n,
+                                  float* grad) {
+  if (!ctx || !x6 || !target || !weight || !grad || n <= 0) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = mlp_scene(ctx, scene_id);
+    if (n > kMlpMaxBlocks * 16 * 64)
+      throw Status(MARS_E_ARG, "batch larger than the fixed gradient array allows (262144)");
+    if (!ctx->noalloc_scratch) throw Status(MARS_E_STATE, ctx->noalloc_error);
+    MlpDev m = s->mlp;
+    m.partial = ctx->noalloc_scratch;
+    int nb = 0;
+    k_mlp_train_pass(m, x6, target, weight, n, 0, n, &nb, ctx->stream);
+    if (nb > kMlpMaxBlocks) throw Status(MARS_E_STATE, "gradient pass wider than its array");
+    k_mlp_sum_partials(m, nb, grad, grad + kMlpParams, ctx->stream);
+    HIPCHK(hipGetLastError());
   });
 }
 

@@ -151,6 +151,12 @@ constexpr int kBright = 10, kBrightChunk = 4096;
 constexpr int kMlpW1 = 0, kMlpB1 = 5120, kMlpW2 = 5184, kMlpB2 = 9280, kMlpW3 = 9344,
               kMlpB3 = 13440, kMlpW4 = 13504, kMlpB4 = 14528, kMlpParams = 14544;
 constexpr int kMlpMaxBlocks = 256;  // workgroups of one training pass
+// fixed device array of the allocation-free gradient pass: one partial
+// gradient (+ loss) per workgroup of a pass of at most kMlpMaxBlocks
+constexpr size_t kNoAllocScratchFloats = (size_t)kMlpMaxBlocks * (kMlpParams + 1);
+constexpr int kMaxDevices = 64;
+// device address of that array on `device`, which must be the current device
+hipError_t noalloc_scratch_address(int device, float** out);
 
 struct MlpDev {
   float* master;    // [kMlpParams]

@@ -13,6 +13,8 @@
 //   D (16 x 16, M x N): D[4 (l / 16) + r][l % 16]
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_math.hpp"
 #include "mars_internal.h"
 
@@ -465,6 +467,39 @@ void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, f
 }
 void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, hipStream_t s) {
   mlp_sum_partials_kernel<<<(kMlpParams + 256) / 256, 256, 0, s>>>(m, nblocks, grad, loss);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free gradient pass: the per-workgroup partial gradients of
+// mars_mlp_grad_noalloc live in this fixed array (one per device, kept until
+// the process ends) instead of scene memory.  Host code never passes the
+// array's name to a kernel: it is a host-side stand-in; the device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_address(int device, float** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (float*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 // bfloat16 copy of freshly written master weights
