@@ -1748,37 +1748,80 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
   q.W1[a] = make_float4(b[1], b[2], pF, pRg);
 }
 
+// The light side of a connection's path, read where it is used: vertex
+// idx = 0 .. m-1 of the path beyond the camera vertex (idx 0 next to it),
+// the emitter point last.  For a light-path connection to y_i these are
+// y_i, y_{i-1}, .., y_1, y_0 (PathSide, read from the light-vertex store on
+// demand); for NEE the emitter point alone (NeeSide).  No per-thread array
+// holds the path, so the weight's walk needs no private memory.
+struct NeeSide {
+  PV y;  // the emitter point
+  __device__ __forceinline__ PV at(int) const { return y; }
+  __device__ __forceinline__ uint32_t cell(int) const { return kNoCell; }
+};
+struct PathSide {
+  const float4* V0;         // light vertices: position, primitive
+  const float4* V2;         // light vertices: .z octree cell
+  const float4* Y0;         // emitter points: position, primitive
+  const float4* tri_ng;     // per primitive: geometric normal, emitter pdf
+  const uint32_t* tri_mat;  // per primitive: material
+  uint32_t base;            // first light vertex of the subpath, lpi * lmax
+  uint32_t lpi;             // light subpath
+  int i;                    // light vertex index connected to
+  __device__ __forceinline__ PV vertex(float4 v) const {
+    const uint32_t prim = ubits(v.w);
+    const float4 ng = tri_ng[prim];
+    return PV{xyz(v), xyz(ng), tri_mat[prim], ng.w};
+  }
+  __device__ __forceinline__ PV at(int idx) const {
+    return vertex(idx == i ? Y0[lpi] : V0[base + (uint32_t)(i - 1 - idx)]);
+  }
+  // octree cell of light vertex idx < i, found once when it was stored
+  __device__ __forceinline__ uint32_t cell(int idx) const {
+    return ubits(V2[base + (uint32_t)(i - 1 - idx)].z);
+  }
+};
+
+// pR(i) of the path, from the window z_i (C), z_{i+1} (D), z_{i+2} (E): the
+// density of reaching z_i from z_{i+1} (whose outgoing direction is towards
+// z_{i+2}) as area density at z_i; z_k's emitter pdf and z_{k-1}'s emission
+// density at the end of the path
+__device__ __forceinline__ float path_pR(const SceneDev& sc, int i, int k, const PV& C,
+                                         const PV& D, const PV& E) {
+  float d2;
+  if (i == k) return C.lpdf;
+  if (i == k - 1) {
+    const f3 w = dir_between(D.P, C.P, &d2);
+    const float cl = dot3(D.ng, w);
+    const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+    return (pe * fabsf(dot3(C.ng, w))) / d2;
+  }
+  const f3 wo = dir_between(D.P, E.P, &d2);
+  const f3 wi = dir_between(D.P, C.P, &d2);
+  f3 fc;
+  float p;
+  eval_facing(load_mat(sc.mats + 8 * (size_t)D.mat), D.ng, wo, wi, &fc, &p);
+  return (p * fabsf(dot3(C.ng, wi))) / d2;
+}
+
 // weight of strategy t = d + 1 for the path z_0..z_d (camera vertex j of
 // depth d: zc, its parent zp, the camera for d = 1) continued by the
-// light-side vertices Y[0..m-1] = z_{d+1}..z_k (z_k on the emitter)
+// light-side vertices Y.at(0..m-1) = z_{d+1}..z_k (z_k on the emitter)
 // ly: in learned-cache iterations, the network outputs of the light subpath's
 // vertices (light vertex i at ly[4 (i - 1)]), z_{d+1} being light vertex li0
-// ycell: the octree cells of Y[0..m-2] when known (else looked up here)
+// The walk keeps a window of five consecutive path vertices in registers.
+template <class Side>
 __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                                  const IterDev& it, int d, uint32_t j, const PV& zc, const PV& zp,
-                                 const PV* Y, int m, const float* It, const float* ly, int li0,
-                                 const uint32_t* ycell) {
+                                 const Side& Y, int m, const float* It, const float* ly,
+                                 int li0) {
   const int k = d + m, t = d + 1;
-  auto Z = [&](int i) -> const PV& { return i == d ? zc : (i == d - 1 ? zp : Y[i - d - 1]); };
-  // pR(i): the density of reaching z_i from z_{i+1} (whose outgoing
-  // direction is towards z_{i+2}) as area density at z_i; z_k's emitter pdf
-  // and z_{k-1}'s emission density at the end of the path
-  auto pR = [&](int i) -> float {
-    float d2;
-    if (i == k) return Z(k).lpdf;
-    if (i == k - 1) {
-      const f3 w = dir_between(Z(k).P, Z(k - 1).P, &d2);
-      const float cl = dot3(Z(k).ng, w);
-      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
-      return (pe * fabsf(dot3(Z(k - 1).ng, w))) / d2;
-    }
-    const f3 wo = dir_between(Z(i + 1).P, Z(i + 2).P, &d2);
-    const f3 wi = dir_between(Z(i + 1).P, Z(i).P, &d2);
-    f3 fc;
-    float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i + 1).mat), Z(i + 1).ng, wo, wi, &fc, &p);
-    return (p * fabsf(dot3(Z(i).ng, wi))) / d2;
-  };
+  // window A..E = z_{i-2} .. z_{i+2} for i = d + 1
+  PV A = zp, B = zc, C = Y.at(0);
+  PV D = m > 1 ? Y.at(1) : PV{}, E = m > 2 ? Y.at(2) : PV{};
+  // pR of the camera vertex and of its parent, for the camera-side sums
+  const float pR_d = d >= 2 ? path_pR(sc, d, k, B, C, D) : 0.0f;
+  const float pR_dm1 = d >= 3 ? path_pR(sc, d - 1, k, A, B, C) : 0.0f;
   // counts at z_d (its record); t's own technique count
   const VRec rd = load_rec(q, d, j);
   f3 T = rd.T;
@@ -1795,12 +1838,12 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
   float sum = 1.0f, rp = 1.0f, rb = 1.0f;
   for (int i = d + 1; i <= k; ++i) {
     float d2;
-    const f3 wo = dir_between(Z(i - 1).P, Z(i - 2).P, &d2);
-    const f3 wi = dir_between(Z(i - 1).P, Z(i).P, &d2);
+    const f3 wo = dir_between(B.P, A.P, &d2);
+    const f3 wi = dir_between(B.P, C.P, &d2);
     f3 fc;
     float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)Z(i - 1).mat), Z(i - 1).ng, wo, wi, &fc, &p);
-    const float pFi = (p * fabsf(dot3(Z(i).ng, wi))) / d2;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)B.mat), B.ng, wo, wi, &fc, &p);
+    const float pFi = (p * fabsf(dot3(C.ng, wi))) / d2;
     float tf = 1.0f;  // strategy k + 1
     float nB_i = 0.0f;
     if (i < k) {
@@ -1809,16 +1852,22 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
                 T.z * (((fc.z / p) * 1.0f) / b[0]));
       else
         T = mk3(0.0f, 0.0f, 0.0f);
-      const uint32_t cell = ycell ? ycell[i - d - 1] : cell_of(c.nodes, olo, sc.oct_inv, Z(i).P);
+      const uint32_t cy = Y.cell(i - d - 1);
+      const uint32_t cell = cy != kNoCell ? cy : cell_of(c.nodes, olo, sc.oct_inv, C.P);
       counts_at(sc, c, it, cell, T, It, i, b);
       if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
       nB_i = mis_count(it, b[0]);
       tf = i == k - 1 ? mis_count(it, b[1]) : mis_count(it, b[2]);
     }
-    rp = rp * (pFi / pR(i));
+    rp = rp * (pFi / path_pR(sc, i, k, C, D, E));
     rb = rb * nB_prev;
     sum = sum + (rp * rb) * (tf / tft);
     nB_prev = nB_i;
+    A = B;
+    B = C;
+    C = D;
+    D = E;
+    if (i + 3 <= k) E = Y.at(i + 2 - d);
   }
   // camera side, walking up the parent chain: pF of vertex tt, pR of vertex
   // tt + 2 (tt <= d - 2), counts of vertex tt - 1
@@ -1828,7 +1877,7 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
   uint32_t ecur = j;
   float prg1 = 0.0f, prg2 = 0.0f;
   for (int tt = d; tt >= 2; --tt) {
-    const float pRt = tt >= d - 1 ? pR(tt) : prg2;
+    const float pRt = tt == d ? pR_d : (tt == d - 1 ? pR_dm1 : prg2);
     const uint32_t epar = ubits(q.S0[(size_t)tt * q.cap + ecur].w);
     const VRec par = load_rec(q, tt - 1, epar);
     rp = rp * (pRt / cur.pF);
@@ -2068,8 +2117,6 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
   const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
   const size_t L = (size_t)d * q.cap;
   uint32_t my_sh = 0, my_conn = 0;
-  PV Y[kMaxDepth + 1];
-  uint32_t ycell[kMaxDepth + 1];
   // Each tile of blockDim.x entries is ranked by the length of its weight
   // walk (NEE first, then connections by light vertex index) with a
   // counting sort in LDS, and thread r takes the tile's r-th entry: a
@@ -2149,8 +2196,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
         const float pN = (lng.w * d2) / cl;
-        Y[0] = PV{y, xyz(lng), sc.tri_mat[li], lng.w};
-        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0, nullptr);
+        const NeeSide Y{PV{y, xyz(lng), sc.tri_mat[li], lng.w}};
+        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0);
         const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
         sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
@@ -2179,15 +2226,10 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
           (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
-        for (int jj = 1; jj <= i; ++jj) {
-          const float4 pv = lt.V0[(size_t)lpi * lt.lmax + (i - jj)];
-          Y[jj - 1] = prim_vertex(sc, xyz(pv), ubits(pv.w));
-          ycell[jj - 1] = ubits(lt.V2[(size_t)lpi * lt.lmax + (i - jj)].z);
-        }
-        const float4 y0r = lt.Y0[lpi];
-        Y[i] = prim_vertex(sc, xyz(y0r), ubits(y0r.w));
+        const PathSide Y{lt.V0, lt.V2, lt.Y0, sc.tri_ng, sc.tri_mat,
+                         lpi * (uint32_t)lt.lmax, lpi, i};
         const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
-        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i, ycell);
+        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i);
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;
