@@ -212,3 +212,69 @@ def rounding_noise_variance(beta, c, independent, n_u=20000):
         s += c[t] * g
         r = r + b[t] - g
     return float(s.var())
+
+
+# ---- rounding variants (supplement "Rounding": Fig. rounding) ----
+# A secondary estimator of one technique, built from a primary estimator with
+# mean mu and variance V, realises a real count beta by an integer number n
+# of samples.  Variants:
+#   stochastic, real count:    n = floor(beta) + [u < beta - floor(beta)],
+#                              estimate (1/beta) sum_n <I>          (the paper's)
+#   stochastic, rounded count: the same n, estimate (1/n) sum_n <I> when
+#                              beta > 1; (1/beta) sum for RR (beta < 1)
+#   nearest:                   n = floor(beta + 1/2) for beta >= 1, estimate
+#                              (1/n) sum_n <I>; RR as above for beta < 1
+#   simplified model:          the variance the fixed point optimises:
+#                              E2/beta - mu^2 for beta <= 1, V/beta above
+# Every variant's expected number of samples is its cost in units of one
+# sample; n is deterministic for nearest rounding.
+def rounding_variant_var_cost(beta, mu, var, variant):
+    b = np.asarray(beta, np.float64)
+    e2 = var + mu * mu
+    rr = e2 / b - mu * mu                      # Russian roulette, any variant
+    lo, hi = np.floor(b), np.ceil(b)
+    p_hi = b - lo
+    if variant == "stochastic":
+        v = var / b + rho(b) * mu * mu
+        c = b
+    elif variant == "rounded":
+        inv_n = np.where(hi > lo, p_hi / np.maximum(hi, 1) + (1 - p_hi) / np.maximum(lo, 1), 1 / b)
+        v = np.where(b < 1, rr, var * inv_n)
+        c = b
+    elif variant == "nearest":
+        n = np.maximum(np.floor(b + 0.5), 1.0)
+        v = np.where(b < 1, rr, var / n)
+        c = np.where(b < 1, b, n)
+    elif variant == "simplified":
+        v = simplified_variance(b, mu, e2)
+        c = b
+    else:
+        raise ValueError(variant)
+    return v, c
+
+
+def rounding_variant_efficiency(beta, mu, var, variant, v_delta=0.0, c_delta=1.0):
+    """1 / ((V_delta + V(beta)) (C_delta + cost(beta))): the efficiency of one
+    technique's secondary estimator beside a fixed rest of the estimator."""
+    v, c = rounding_variant_var_cost(beta, mu, var, variant)
+    return 1.0 / ((v_delta + v) * (c_delta + c))
+
+
+def rounding_variant_mc(beta, sampler, variant, n_trials, rng):
+    """Monte Carlo mean and variance of the variant's secondary estimate
+    (`sampler(rng, k)` draws k primary estimates) and its mean cost."""
+    lo = int(np.floor(beta))
+    fr = beta - lo
+    if variant == "nearest" and beta >= 1:
+        n = np.full(n_trials, int(np.floor(beta + 0.5)))
+    else:
+        n = lo + (rng.random(n_trials) < fr).astype(np.int64)
+    tot = np.zeros(n_trials)
+    mx = int(n.max()) if n_trials else 0
+    for k in range(mx):
+        tot += np.where(n > k, sampler(rng, n_trials), 0.0)
+    if variant in ("rounded", "nearest") and beta >= 1:
+        est = tot / np.maximum(n, 1)
+    else:
+        est = tot / beta
+    return float(est.mean()), float(est.var()), float(n.mean())
