@@ -637,6 +637,66 @@ def run_convergence(args, api, torch, seeds=(1, 2, 3), n_iter=9):
             "mars_vs_ears_final": float(np.mean(fm / fe)), "stability": stab, "runs": out_runs}
 
 
+def run_rounding(args, api, torch, n_alloc=9, n_rep=24, seed=1):
+    """Low-discrepancy rounding (supplement Alg. 1) against rounding each
+    count with its own uniform, in renders: the guided 512x512 heightfield
+    after a MARS schedule (the doubling schedule of 9 iterations), then the
+    allocation frozen (no further update) and n_rep render iterations of
+    4 spp with each rounding, alternating; the per-pixel variance of the
+    iteration images over the repetitions, relative to the squared mean
+    image (channel mean, pixels with a mean above 1e-3 of the image's), for
+    each scheme.  value = 1 - V(Alg. 1) / V(independent): the variance the
+    low-discrepancy rounding saves.  The same for the bidirectional 1280x720
+    interior beside it."""
+    import numpy as np
+    import scenegen
+    ctx = api.Context(0)
+    out = {}
+    for name, sc, mode, depth, kc in (
+            ("guided512", scenegen.make_heightfield_scene(seed=1), api.MODE_PT_GUIDED, 10, 50.0),
+            ("bdpt720", scenegen.make_interior(seed=1), api.MODE_BDPT, 12, 0.0)):
+        s = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget(), seed=seed)
+        for i in range(n_alloc):
+            p = api.iter_params(iteration=i, spp=min(1 << max(0, i - 3), 16), stat_clamp=kc,
+                                alloc=api.ALLOC_CLASSIC if i < 3 else api.ALLOC_MARS)
+            s.render_iteration(p)
+            s.update(p)
+        imgs = {0: [], 1: []}
+        rays = {0: 0, 1: 0}
+        for r in range(n_rep):
+            for rounding in (0, 1):
+                p = api.iter_params(iteration=1000 + r, spp=4, stat_clamp=kc,
+                                    alloc=api.ALLOC_MARS, rounding=rounding)
+                rays[rounding] += s.render_iteration(p).total_rays()
+                imgs[rounding].append(s.image(api.IMAGE_LAST).astype(np.float64))
+        s.release()
+        mean = 0.5 * (np.mean(imgs[0], 0) + np.mean(imgs[1], 0))
+        m = mean.mean(-1)
+        keep = m > 1e-3 * m.mean()
+        rel = {k: float(np.mean(np.var(np.array(v), 0, ddof=1).mean(-1)[keep] / m[keep] ** 2))
+               for k, v in imgs.items()}
+        # the spread of that ratio from halves of the repetitions
+        half = []
+        for a, b in ((slice(0, n_rep // 2), slice(n_rep // 2, n_rep)),):
+            for sl in (a, b):
+                r0 = np.mean(np.var(np.array(imgs[0][sl]), 0, ddof=1).mean(-1)[keep] / m[keep] ** 2)
+                r1 = np.mean(np.var(np.array(imgs[1][sl]), 0, ddof=1).mean(-1)[keep] / m[keep] ** 2)
+                half.append(1.0 - r0 / r1)
+        out[name] = {"rel_var_alg1": rel[0], "rel_var_independent": rel[1],
+                     "saving": 1.0 - rel[0] / rel[1], "saving_halves": half,
+                     "rays_alg1": rays[0], "rays_independent": rays[1],
+                     "pixels": int(keep.sum()), "repetitions": n_rep}
+        print(f"[bench] rounding {name}: saving {out[name]['saving']:.4f}", file=sys.stderr,
+              flush=True)
+    return {"metric": "variance saved by low-discrepancy rounding (Alg. 1) against rounding "
+                      "each count independently, frozen MARS allocation",
+            "value": out["guided512"]["saving"], "unit": "fraction", "n_gpus": 1,
+            "steps": n_rep, "warmup": n_alloc, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "rounding_guided512_bdpt720", "spp_per_repetition": 4},
+            "per_scene": out, "paper_context": {"saving": 0.02}}
+
+
 def cells_budget(mbytes=72.0):
     # bytes per cell: factors 72, accumulators 192, visits/leaf data 12,
     # directional pmf+cdf 512, training sums 512, octree node words 32
@@ -889,12 +949,14 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="learned",
-                    choices=["learned", "mlp", "guided", "batch", "bdpt", "ears", "convergence"],
+                    choices=["learned", "mlp", "guided", "batch", "bdpt", "ears", "convergence",
+                             "rounding"],
                     help="learned (default; mlp is the same): 1920x1080 bidirectional, learned "
                          "cache vs octree; guided: the 512x512 guided-PT workload; batch: 32 "
                          "mixed scenes; bdpt: 1280x720 bidirectional; ears: MARS vs EARS vs "
                          "classic RR efficiency (guided and bidirectional); convergence: "
-                         "per-iteration counts and efficiency over several seeds")
+                         "per-iteration counts and efficiency over several seeds; rounding: "
+                         "low-discrepancy against independent rounding in renders")
     ap.add_argument("--no-efficiency", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -915,7 +977,8 @@ def main():
         torch.cuda.synchronize()
         del a, bcopy
     run = {"learned": run_learned, "mlp": run_learned, "guided": run_guided, "batch": run_batch,
-           "bdpt": run_bdpt, "ears": run_ears, "convergence": run_convergence}[args.workload]
+           "bdpt": run_bdpt, "ears": run_ears, "convergence": run_convergence,
+           "rounding": run_rounding}[args.workload]
     out = run(args, api, torch)
     if out is not None:
         print(json.dumps(out), flush=True)

@@ -112,6 +112,9 @@ typedef struct {
                                light subpath (b + j lp_stride) mod N of the iteration's N
                                (one per camera sample), b a word of the vertex's random
                                stream (Sec. 5: connections with light paths) */
+  int32_t rounding;         /* 0: the low-discrepancy rounding of supplement Alg. 1 (one
+                               uniform for every technique of a vertex); 1: each count
+                               rounded with its own uniform (the naive scheme it replaces) */
 } mars_iter_params;
 
 typedef struct {

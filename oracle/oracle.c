@@ -144,6 +144,18 @@ static void alg1(const float beta[3], float u, uint32_t gamma[3]) {
   }
 }
 void orc_alg1(const float beta[3], float u, uint32_t gamma[3]) { alg1(beta, u, gamma); }
+/* the rounding of a vertex's counts: Alg. 1 with the first uniform of its
+ * draw block 0, or (the naive scheme Alg. 1 replaces) each count rounded
+ * with its own uniform, gamma_t = floor(beta_t + u_t), u_t the t-th uniform
+ * of that block */
+static void round_vertex(const orc_iter_params* p, const float beta[3], const float u[4],
+                         uint32_t gamma[3]) {
+  if (p->rounding) {
+    for (int t = 0; t < 3; ++t) gamma[t] = (uint32_t)floorf(beta[t] + u[t]);
+    return;
+  }
+  alg1(beta, u[0], gamma);
+}
 /* enumerate u = k / n for k = 0..n-1: mean counts, range of the total and of r */
 void orc_alg1_enumerate(const float beta[3], uint32_t n, double mean[3], uint32_t tot_minmax[2],
                         float r_minmax[2]) {
@@ -967,7 +979,7 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
   float ur[4];
   draw4(c->key, strm, 0, ur);
   uint32_t gam[3];
-  alg1(beta, ur[0], gam);
+  round_vertex(p, beta, ur, gam);
   c->L->vertices++;
   { stat_rec s = {REC_VISIT, cell, 0, 0, {0, 0, 0}, 0, 0}; log_push(c->L, s); }
   if (depth == 1) {
@@ -1715,7 +1727,7 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
   float ur[4];
   draw4(c->key, strm, 0, ur);
   uint32_t gam[3];
-  alg1(beta, ur[0], gam);
+  round_vertex(p, beta, ur, gam);
   c->L->vertices++;
   { stat_rec s = {REC_VISIT, cell, 0, 0, {0, 0, 0}, 0, 0}; log_push(c->L, s); }
   if (depth == 1) {

@@ -53,6 +53,7 @@ typedef struct {
   int32_t center_jitter; /* 1: pixel-centre rays */
   int32_t debug_depth;   /* record per-vertex decisions up to this depth */
   int32_t lp_stride;     /* BDPT: pool stride P for extra light paths */
+  int32_t rounding;      /* 0: Alg. 1; 1: each count rounded with its own uniform */
 } orc_iter_params;
 
 typedef struct {

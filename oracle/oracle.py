@@ -22,7 +22,8 @@ class IterParams(C.Structure):
     _fields_ = [("iteration", C.c_int32), ("spp", C.c_int32), ("alloc", C.c_int32),
                 ("budget_aware", C.c_int32), ("rr_start", C.c_int32), ("fixed_scale", C.c_int32),
                 ("clamp_lo", C.c_float), ("clamp_hi", C.c_float), ("stat_clamp", C.c_float),
-                ("center_jitter", C.c_int32), ("debug_depth", C.c_int32), ("lp_stride", C.c_int32)]
+                ("center_jitter", C.c_int32), ("debug_depth", C.c_int32), ("lp_stride", C.c_int32),
+                ("rounding", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -158,9 +159,10 @@ class Oracle:
     @staticmethod
     def params(iteration=0, spp=1, alloc=ALLOC_CLASSIC, budget_aware=True, rr_start=5,
                fixed_scale=False, clamp_lo=0.05, clamp_hi=20.0, stat_clamp=50.0,
-               center_jitter=False, debug_depth=0, lp_stride=7919):
+               center_jitter=False, debug_depth=0, lp_stride=7919, rounding=0):
         return IterParams(iteration, spp, alloc, int(budget_aware), rr_start, int(fixed_scale),
-                          clamp_lo, clamp_hi, stat_clamp, int(center_jitter), debug_depth, lp_stride)
+                          clamp_lo, clamp_hi, stat_clamp, int(center_jitter), debug_depth, lp_stride,
+                          int(rounding))
 
     def render_iteration(self, p):
         st = IterStats()

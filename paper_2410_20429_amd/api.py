@@ -90,10 +90,10 @@ class Context:
 
 def iter_params(iteration=0, spp=1, alloc=ALLOC_CLASSIC, budget_aware=True, rr_start=5,
                 fixed_scale=False, clamp_lo=0.05, clamp_hi=20.0, stat_clamp=50.0,
-                center_jitter=False, debug_depth=0, lp_stride=7919):
+                center_jitter=False, debug_depth=0, lp_stride=7919, rounding=0):
     return capi.mars_iter_params(iteration, spp, alloc, int(budget_aware), rr_start,
                                  int(fixed_scale), clamp_lo, clamp_hi, stat_clamp,
-                                 int(center_jitter), debug_depth, lp_stride)
+                                 int(center_jitter), debug_depth, lp_stride, int(rounding))
 
 
 class Scene:

@@ -286,6 +286,7 @@ IterDev to_dev(const mars_iter_params* p) {
   it.center_jitter = p->center_jitter;
   it.debug_depth = p->debug_depth;
   it.lp_stride = p->lp_stride;
+  it.rounding = p->rounding;
   return it;
 }
 
@@ -1016,7 +1017,8 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
                                (uint64_t)p->spp, (uint64_t)p->alloc, (uint64_t)p->budget_aware,
                                (uint64_t)p->rr_start, (uint64_t)p->fixed_scale,
                                fbits64(p->clamp_lo), fbits64(p->clamp_hi), fbits64(p->stat_clamp),
-                               (uint64_t)p->center_jitter, (uint64_t)p->lp_stride, (uint64_t)c->cu};
+                               (uint64_t)p->center_jitter, (uint64_t)p->lp_stride,
+                               (uint64_t)p->rounding, (uint64_t)c->cu};
   for (int i = 0; i < n; ++i) {
     key.push_back(sc[i]->uid);
     key.push_back(sc[i]->epoch);

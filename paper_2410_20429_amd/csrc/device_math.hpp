@@ -129,6 +129,16 @@ __device__ __forceinline__ void round_counts(const float beta[3], float u, uint3
   }
 }
 
+// each count rounded with its own uniform (the scheme Alg. 1 improves on):
+// gamma_t = floor(beta_t + u_t), which is ceil(beta_t) with probability
+// beta_t - floor(beta_t)
+__device__ __forceinline__ void round_counts_independent(const float beta[3], float4 u,
+                                                         uint32_t g[3]) {
+  g[0] = (uint32_t)floorf(beta[0] + u.x);
+  g[1] = (uint32_t)floorf(beta[1] + u.y);
+  g[2] = (uint32_t)floorf(beta[2] + u.z);
+}
+
 // ---------------------------------------------------------------------------
 // shading frame (Duff et al. 2017, branchless orthonormal basis)
 // ---------------------------------------------------------------------------

@@ -1074,7 +1074,8 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
           mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
-          round_counts(beta, u.x, gam);
+          if (it.rounding) round_counts_independent(beta, u, gam);
+          else round_counts(beta, u.x, gam);
           mlp_record(c, strm, x, pix, ng, T);
         }
       }
@@ -1993,7 +1994,8 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
-          round_counts(beta, u.x, gam);
+          if (it.rounding) round_counts_independent(beta, u, gam);
+          else round_counts(beta, u.x, gam);
           mlp_record(c, strm, x, pix, ng, T);
           const int imax0 = sc.max_depth - d - 1;
           for (uint32_t k = 0; k < gam[2]; ++k) {

@@ -110,7 +110,7 @@ struct LightDev {
 struct IterDev {
   int32_t iteration, spp, alloc, aware, rr_start, fixed_scale;
   float clamp_lo, clamp_hi, stat_clamp;
-  int32_t center_jitter, debug_depth, lp_stride;
+  int32_t center_jitter, debug_depth, lp_stride, rounding;
   const int32_t* iter_dev;  // if set, the iteration index is read here (graph replays)
 };
 __host__ __device__ inline int32_t iter_index(const IterDev& it) {

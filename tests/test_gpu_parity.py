@@ -548,3 +548,27 @@ def test_bdpt_full_size_sampled_pixels(ctx):
         dg = g.debug_vertices()
         dg = dg[np.isin(dg["root"], pix)]
         _cmp_vertices(dg, o.debug_vertices())
+
+
+# ---------------------------------------------------------------------------
+# independent rounding of each count (the scheme Alg. 1 replaces): the same
+# decisions and radiance as the oracle over MARS schedules
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [orc.MODE_PT, orc.MODE_PT_GUIDED, orc.MODE_BDPT])
+def test_independent_rounding_schedule_parity(ctx, mode):
+    sc = scenegen.make_cornell(40, 36)
+    g, o = _pair(ctx, sc, mode=mode, max_depth=4)
+    kc = 0.0 if mode == orc.MODE_BDPT else 50.0
+    for it in range(4):
+        say("independent rounding, mode", mode, "iteration", it)
+        alloc = orc.ALLOC_CLASSIC if it < 1 else orc.ALLOC_MARS
+        pg, po = _params(iteration=it, spp=2, alloc=alloc, stat_clamp=kc, debug_depth=4,
+                         rounding=1)
+        sg = g.render_iteration(pg)
+        so = o.render_iteration(po)
+        assert sg.total_rays() == so.total_rays()
+        _cmp_radiance(g.sample_radiance(), o.sample_radiance())
+        _cmp_vertices(g.debug_vertices(), o.debug_vertices())
+        g.update(pg)
+        o.update(po)
+        assert np.array_equal(g.nodes(), o.nodes())

@@ -432,3 +432,24 @@ def test_bdpt_unbiased_against_pt(aware):
         a, b = mref[:, ch], m[:, ch]
         z = (a.mean() - b.mean()) / math.sqrt(a.var() / len(a) + b.var() / len(b))
         assert abs(z) < 4.0, (ch, a.mean(), b.mean(), z)
+
+
+# ---------------------------------------------------------------------------
+# The naive rounding Alg. 1 replaces (each count rounded with its own
+# uniform) is unbiased too: MARS iterations in the furnace keep the closed
+# form, in the unidirectional and the bidirectional renderer.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [orc.MODE_PT, orc.MODE_BDPT])
+def test_furnace_independent_rounding(mode):
+    sc = scenegen.make_furnace(32, 32)
+    o = orc.Oracle(sc, mode=mode, max_depth=4)
+    L = []
+    for i in range(6):
+        p = orc.Oracle.params(iteration=i, spp=4, stat_clamp=0.0, rounding=1,
+                              alloc=orc.ALLOC_CLASSIC if i < 1 else orc.ALLOC_MARS)
+        o.render_iteration(p)
+        if i >= 1:
+            L.append(o.sample_radiance()[:, 0].copy())
+        o.update(p)
+    L = np.concatenate(L)
+    assert abs(_zscore(L, (1 - 0.5 ** 4) / 0.5)) < 4.0
