@@ -48,7 +48,9 @@ __host__ __device__ constexpr int qindex(int p) {
 }
 
 // features of one vertex: x = (q.xyz, n.xyz); f[(d*6+k)*2 + s] = sin/cos(2^k pi x_d).
-// Features k (even) and k + 1 are the sine and cosine of one angle.
+// Features k (even) and k + 1 are the sine and cosine of one angle; with k a
+// multiple of 4, features k + 2, k + 3 belong to the same input and twice
+// the angle.
 __device__ __forceinline__ void feature_pair(const float* x, int k, float* fs, float* fc) {
   if (k >= 72) {
     *fs = 0.0f;
@@ -60,23 +62,12 @@ __device__ __forceinline__ void feature_pair(const float* x, int k, float* fs, f
   sincospif(a, fs, fc);
 }
 
-// LDS written by some lanes of a wave and read by others of the same wave
-// (the workgroups using it hold several waves that do not meet): the wave's
-// own writes completed (workgroup-scope release), no code motion across it
-// (wave barrier), then the reads (acquire)
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Forward pass of one 16-sample tile by one wave.  x: this lane's sample
-// inputs (sample = lane % 16).  wq: the bfloat16 weights (global memory or a
-// copy in LDS).  Hidden activations go to hs[l][16][64] (bfloat16), features
-// to xs[16][80] when xs != nullptr.  Returns the output tile in D layout (rows
-// = samples, columns = outputs).  kGroupSync: one-wave workgroups meet at
-// workgroup barriers; otherwise only the wave's own order is kept.
-template <bool kGroupSync>
+// Forward pass of one 16-sample tile by one wave, keeping what the backward
+// pass needs.  x: this lane's sample inputs (sample = lane % 16).  wq: the
+// bfloat16 weights (global memory or a copy in LDS).  Hidden activations go
+// to hs[l][16][64] (bfloat16), features to xs[16][80] when xs != nullptr.
+// Returns the output tile in D layout (rows = samples, columns = outputs).
+// One-wave workgroups: the wave meets itself at workgroup barriers.
 __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master,
                                                 const uint16_t* __restrict__ wq, const float* x,
                                                 uint16_t (*hs)[16][64], uint16_t (*xs)[80]) {
@@ -87,19 +78,26 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
 #pragma unroll
   for (int ks = 0; ks < 5; ++ks) {
     v4s a;
+    // this lane's features k0 .. k0 + 3, k0 = 16 ks + 4 lg: the sine and
+    // cosine of one angle 2^kk pi x_d (kk even) and of its double, the
+    // latter from the double-angle identities
+    const int k0 = 16 * ks + 4 * lg;
+    float fs, fc, gs, gc;
+    feature_pair(x, k0, &fs, &fc);
+    if (k0 < 72) {
+      gs = 2.0f * (fs * fc);
+      gc = (fc - fs) * (fc + fs);
+    } else {
+      gs = 0.0f;
+      gc = 0.0f;
+    }
+    uint16_t h[4];
+    to_bf16x2(fs, fc, &h[0], &h[1]);
+    to_bf16x2(gs, gc, &h[2], &h[3]);
 #pragma unroll
-    for (int r = 0; r < 4; r += 2) {
-      const int k = 16 * ks + 4 * lg + r;
-      float fs, fc;
-      feature_pair(x, k, &fs, &fc);
-      uint16_t hs0, hc0;
-      to_bf16x2(fs, fc, &hs0, &hc0);
-      a[r] = (short)hs0;
-      a[r + 1] = (short)hc0;
-      if (xs) {
-        xs[lr][k] = hs0;
-        xs[lr][k + 1] = hc0;
-      }
+    for (int r = 0; r < 4; ++r) {
+      a[r] = (short)h[r];
+      if (xs) xs[lr][k0 + r] = h[r];
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -111,6 +109,7 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
   int boff[3] = {kMlpB1, kMlpB2, kMlpB3};
   int woff[3] = {qW2, qW3, qW4};
   for (int l = 0; l < 3; ++l) {
+    const int hb = l;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int j = 16 * nt + lr;
@@ -119,18 +118,17 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
       for (int r = 0; r < 4; r += 2) {
         uint16_t h0, h1;
         to_bf16x2(fmaxf(acc[nt][r] + bj, 0.0f), fmaxf(acc[nt][r + 1] + bj, 0.0f), &h0, &h1);
-        hs[l][4 * lg + r][j] = h0;
-        hs[l][4 * lg + r + 1][j] = h1;
+        hs[hb][4 * lg + r][j] = h0;
+        hs[hb][4 * lg + r + 1][j] = h1;
       }
     }
-    if (kGroupSync) __syncthreads();
-    else wave_lds_sync();
+    __syncthreads();
     const int ntn = l < 2 ? 4 : 1;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const uint16_t* hr = &hs[l][lr][16 * ks + 4 * lg];
+      const uint16_t* hr = &hs[hb][lr][16 * ks + 4 * lg];
       const v4s a = {(short)hr[0], (short)hr[1], (short)hr[2], (short)hr[3]};
       for (int nt = 0; nt < ntn; ++nt) {
         const uint16_t* w = wq + woff[l] + (16 * nt + lr) * 64 + 16 * ks + 4 * lg;
@@ -140,33 +138,175 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
     }
   }
   v4f y = acc[0];
+  const float b4 = master[kMlpB4 + lr];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) y[r] += master[kMlpB4 + lr];
+  for (int r = 0; r < 4; ++r) y[r] += b4;
   return y;
 }
 
-// inference over a list of vertices given as (q, n); 64-thread workgroups
-__global__ __launch_bounds__(64) void mlp_infer_inputs_kernel(MlpDev m, const float* x6, int n,
-                                                              float* y3) {
-  __shared__ uint16_t hs[3][16][64];
-  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
-  for (int tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
+// ---------------------------------------------------------------------------
+// Inference.  Every layer is computed transposed, Z^T = W H^T, with the
+// weights as the A operand and the activations as the B operand: the output
+// tile D[neuron 16 nt + 4 (l / 16) + r][sample l % 16] of output block nt is
+// then, after bias, ReLU and rounding, exactly the B operand of block
+// ks = nt of the next layer, so activations stay in registers.  (The same
+// products as mlp_forward_tile; only the order of each binary32 matrix-core
+// accumulation may differ.)
+//
+// The weights are staged in LDS in fragment order: the A operand of every
+// (layer, output block, k block) as 64 consecutive 8-byte lane fragments,
+// so that each operand is one conflict-free 512-byte read.  Blocks: layer 1
+// 5 nt + ks (nt < 4, ks < 5), layer 2 20 + 4 nt + ks, layer 3
+// 36 + 4 nt + ks, output layer 52 + ks (one output block); 28 KB in all.
+constexpr int kFragBlocks = 56;
+constexpr int kInferWaves = 8;            // waves per inference workgroup
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// (by the kInferWaves * 64 threads of a workgroup, each loading all of its
+// fragments before it writes any)
+__device__ __forceinline__ int fragment_source(int f) {
+  const int blk = f >> 6, ln = f & 63, lr = ln & 15, lg = ln >> 4;
+  int base, stride, nt, ks;
+  if (blk < 20) {
+    base = qW1; stride = 80; nt = blk / 5; ks = blk % 5;
+  } else if (blk < 52) {
+    const int b = (blk - 20) & 15;
+    base = blk < 36 ? qW2 : qW3; stride = 64; nt = b >> 2; ks = b & 3;
+  } else {
+    base = qW4; stride = 64; nt = 0; ks = blk - 52;
+  }
+  return base + (16 * nt + lr) * stride + 16 * ks + 4 * lg;
+}
+template <int kThreads>
+__device__ __forceinline__ void stage_fragments(const uint16_t* __restrict__ wq, uint2* wf) {
+  static_assert(kFragBlocks * 64 % kThreads == 0, "whole fragments per thread");
+  constexpr int kPer = kFragBlocks * 64 / kThreads;
+  uint2 v[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    v[j] = *reinterpret_cast<const uint2*>(wq + fragment_source(threadIdx.x + j * kThreads));
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) wf[threadIdx.x + j * kThreads] = v[j];
+}
+
+// the biases b1, b2, b3 (64 each) and b4 (16) as 52 float4 in LDS
+__device__ __forceinline__ void stage_biases(const float* __restrict__ master, float4* bl) {
+  float* b = reinterpret_cast<float*>(bl);
+  for (int k = threadIdx.x; k < 208; k += blockDim.x)
+    b[k] = k < 192 ? master[(k < 64 ? kMlpB1 : (k < 128 ? kMlpB2 : kMlpB3)) + (k & 63)]
+                   : master[kMlpB4 + (k - 192)];
+}
+
+__device__ __forceinline__ v4s frag(const uint2* wf, int blk, int lane) {
+  return __builtin_bit_cast(v4s, wf[blk * 64 + lane]);
+}
+
+// bias, ReLU and bfloat16 rounding of one output block: the next layer's B
+// operand (neurons 16 nt + 4 (l / 16) + r of sample l % 16)
+__device__ __forceinline__ v4s relu_bf16(const v4f& z, float4 b) {
+  uint16_t h[4];
+  to_bf16x2(fmaxf(z[0] + b.x, 0.0f), fmaxf(z[1] + b.y, 0.0f), &h[0], &h[1]);
+  to_bf16x2(fmaxf(z[2] + b.z, 0.0f), fmaxf(z[3] + b.w, 0.0f), &h[2], &h[3]);
+  return v4s{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+}
+
+// One 16-sample tile by one wave.  x: the inputs of sample l % 16 (the same
+// in the four lanes that hold it).  Returns D[output 4 (l / 16) + r][sample
+// l % 16]: the lanes l < 16 hold outputs 0..3 of sample l.
+__device__ __forceinline__ v4f mlp_infer_tile(const uint2* wf, const float4* bl, const float* x) {
+  const int lane = threadIdx.x & 63, lg = lane >> 4;
+  v4f acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 5; ++ks) {
+    // features k0 .. k0 + 3 of the sample, k0 = 16 ks + 4 lg: the sine and
+    // cosine of one angle 2^kk pi x_d (kk even) and of its double, the
+    // latter from the double-angle identities
+    const int k0 = 16 * ks + 4 * lg;
+    float fs, fc, gs, gc;
+    feature_pair(x, k0, &fs, &fc);
+    if (k0 < 72) {
+      gs = 2.0f * (fs * fc);
+      gc = (fc - fs) * (fc + fs);
+    } else {
+      gs = 0.0f;
+      gc = 0.0f;
+    }
+    uint16_t h[4];
+    to_bf16x2(fs, fc, &h[0], &h[1]);
+    to_bf16x2(gs, gc, &h[2], &h[3]);
+    const v4s b = {(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = mma(frag(wf, 5 * nt + ks, lane), b, acc[nt]);
+  }
+  v4s hb[4];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) hb[nt] = relu_bf16(acc[nt], bl[16 * l + 4 * nt + lg]);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        acc[nt] = mma(frag(wf, 20 + 16 * l + 4 * nt + ks, lane), hb[ks], acc[nt]);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) hb[nt] = relu_bf16(acc[nt], bl[32 + 4 * nt + lg]);
+  v4f y = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) y = mma(frag(wf, 52 + ks, lane), hb[ks], y);
+  const float4 b4 = bl[48 + lg];
+  y[0] += b4.x;
+  y[1] += b4.y;
+  y[2] += b4.z;
+  y[3] += b4.w;
+  return y;
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima, the gfx9
+// encoding): every vector memory operation issued so far has completed.  At
+// the top of a pipelined loop this costs nothing (what is outstanding was
+// issued a tile's computation earlier) and tells the compiler's wait
+// insertion that nothing is outstanding, which it cannot prove by itself
+// where loads are conditional and the first iteration's come from before the
+// loop; otherwise it waits, in the middle of the tile, for the stores and
+// loads the tile has just issued.
+__device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Inference kernels: the fragments and biases are staged once per
+// workgroup; each of its kInferWaves waves then runs 16-sample tiles (29 KB
+// of LDS per workgroup).  Every global access of a tile is issued a whole
+// tile's computation before it is needed: the records two tiles ahead, the
+// normals one tile ahead, and the outputs are stored one tile late.  (Vector
+// memory operations complete in the order they are issued, stores included,
+// so a wait for any of them is a wait for all that were issued before it.)
+
+// inference over a list of vertices given as (q, n)
+__global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_inputs_kernel(MlpDev m, const float* x6,
+                                                                            int n, float* y3) {
+  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ float4 bl[52];
+  stage_fragments<64 * kInferWaves>(m.wq, wf);
+  stage_biases(m.master, bl);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, lr = lane & 15, w = threadIdx.x >> 6;
+  for (int tile = blockIdx.x * kInferWaves + w; tile * 16 < n; tile += gridDim.x * kInferWaves) {
     const int s = tile * 16 + lr;
     float x[6] = {0, 0, 0, 0, 0, 0};
     if (s < n)
       for (int k = 0; k < 6; ++k) x[k] = x6[6 * (size_t)s + k];
-    const v4f y = mlp_forward_tile<true>(m.master, m.wq, x, hs, nullptr);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int si = tile * 16 + 4 * lg + r;
-      if (si < n && lr < 3) y3[3 * (size_t)si + lr] = y[r];
-    }
-    __syncthreads();
+    const v4f y = mlp_infer_tile(wf, bl, x);
+    if (s < n && lane < 16)
+      for (int t = 0; t < 3; ++t) y3[3 * (size_t)s + t] = y[t];
   }
 }
 void k_mlp_forward(const MlpDev& m, const float* x6, int n, float* y3, hipStream_t s) {
   const int tiles = (n + 15) / 16;
-  mlp_infer_inputs_kernel<<<std::min(tiles, 8192), 64, 0, s>>>(m, x6, n, y3);
+  const int blocks = std::max(1, std::min((tiles + kInferWaves - 1) / kInferWaves, 2048));
+  mlp_infer_inputs_kernel<<<blocks, 64 * kInferWaves, 0, s>>>(m, x6, n, y3);
 }
 
 // network inputs of a vertex: position normalised to the octree cube, and
@@ -180,52 +320,75 @@ __device__ __forceinline__ void mlp_input(const SceneDev& sc, f3 p, f3 ng, float
 
 // inference at the vertices of one depth's queue (hits with d < D): inputs
 // from the hit point and the geometric normal, outputs to m.y[d * cap + j].
-// The bfloat16 weights are copied once per workgroup into LDS; each of its
-// four waves then runs 16-sample tiles of the queue.
-constexpr int kInferWaves = 4;
+struct InferRec {
+  uint2 h;       // hit (t bits, primitive); primitive kMiss: no sample
+  float4 r0, r1;
+};
+
 __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_queue_kernel(SceneDev sc,
                                                                            QueuesDev q, MlpDev m,
                                                                            const Counters* cnt,
                                                                            int d) {
-  __shared__ uint4 wl4[kQW / 8];
-  __shared__ uint16_t hs[kInferWaves][3][16][64];
+  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ float4 bl[52];
   if (cnt->overflow) return;
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
   if ((size_t)blockIdx.x * kInferWaves * 16 >= n) return;  // no tile for this workgroup
-  for (int k = threadIdx.x; k < kQW / 8; k += blockDim.x)
-    wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
+  stage_fragments<64 * kInferWaves>(m.wq, wf);
+  stage_biases(m.master, bl);
   __syncthreads();
-  const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, lr = lane & 15, w = threadIdx.x >> 6;
   const size_t L = (size_t)d * q.cap;
-  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile * 16 < n;
-       tile += gridDim.x * kInferWaves) {
+  const uint32_t stride = gridDim.x * kInferWaves;
+  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  // this lane's sample (lr) of a tile
+  auto fetch = [&](uint32_t tile) {
+    InferRec r{make_uint2(0u, kMiss), zero4, zero4};
     const uint32_t s = tile * 16 + lr;
+    if (tile < kNoTile / 16 && s < n) {
+      r.h = q.H[L + s];
+      r.r0 = q.R0[L + s];
+      r.r1 = q.R1[L + s];
+    }
+    return r;
+  };
+  auto normal = [&](const InferRec& r) { return r.h.y != kMiss ? sc.tri_ng[r.h.y] : zero4; };
+  // outputs 0..3 of sample s (the fourth is padding) from the lanes < 16
+  auto store = [&](uint32_t tile, const v4f& y) {
+    const uint32_t s = tile * 16 + lr;
+    if (lane < 16 && s < n)
+      reinterpret_cast<float4*>(m.y)[L + s] = make_float4(y[0], y[1], y[2], y[3]);
+  };
+  uint32_t tile = blockIdx.x * kInferWaves + w;
+  InferRec cur = fetch(tile);
+  float4 ng = normal(cur);
+  InferRec nxt = fetch(tile + stride);
+  v4f yp = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t tp = kNoTile;  // the tile yp belongs to
+  for (; tile * 16 < n; tile += stride) {
+    wait_vector_memory();
+    if (tp != kNoTile) store(tp, yp);
     float x[6] = {0, 0, 0, 0, 0, 0};
-    if (s < n) {
-      const uint2 h = q.H[L + s];
-      if (h.y != kMiss) {
-        const float4 r0 = q.R0[L + s], r1 = q.R1[L + s];
-        const float t = __uint_as_float(h.x);
-        const f3 ng = xyz(sc.tri_ng[h.y]);
-        const f3 p = mk3(r0.x + t * r1.x, r0.y + t * r1.y, r0.z + t * r1.z);
-        mlp_input(sc, p, ng, x);
-      }
+    if (cur.h.y != kMiss) {
+      const float t = __uint_as_float(cur.h.x);
+      const f3 p = mk3(cur.r0.x + t * cur.r1.x, cur.r0.y + t * cur.r1.y, cur.r0.z + t * cur.r1.z);
+      mlp_input(sc, p, xyz(ng), x);
     }
-    const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t si = tile * 16 + 4 * lg + r;
-      if (si < n && lr < 3) m.y[(L + si) * 4 + lr] = y[r];
-    }
-    // the next tile rewrites hs[w] only after every lane has read it
-    wave_lds_sync();
+    const float4 ngn = normal(nxt);
+    const InferRec nn = fetch(tile + 2 * stride);
+    yp = mlp_infer_tile(wf, bl, x);
+    tp = tile;
+    cur = nxt;
+    ng = ngn;
+    nxt = nn;
   }
+  if (tp != kNoTile) store(tp, yp);
 }
 void k_mlp_infer_queue(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const Counters* cnt,
                        int d, int grid, hipStream_t s) {
-  // three workgroups (53 KB of LDS each) per CU; grid = 32 per CU
-  mlp_infer_queue_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, cnt, d);
+  // grid = 32 per CU.  At up to 128 VGPRs, four waves per SIMD: two
+  // eight-wave workgroups per CU, all resident at once
+  mlp_infer_queue_kernel<<<std::max(1, grid / 16), 64 * kInferWaves, 0, s>>>(sc, q, m, cnt, d);
 }
 
 // inference at the light vertices of bounce i (bidirectional learned-cache
@@ -238,48 +401,71 @@ __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_light_kernel(Scene
                                                                            MlpDev m, LightDev lt,
                                                                            const Counters* cnt,
                                                                            int i) {
-  __shared__ uint4 wl4[kQW / 8];
-  __shared__ uint16_t hs[kInferWaves][3][16][64];
+  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ float4 bl[52];
   const uint32_t n = min(cnt->n_ray[0], (uint32_t)q.cap);
   if ((size_t)blockIdx.x * kInferWaves * 16 >= n) return;
-  for (int k = threadIdx.x; k < kQW / 8; k += blockDim.x)
-    wl4[k] = reinterpret_cast<const uint4*>(m.wq)[k];
+  stage_fragments<64 * kInferWaves>(m.wq, wf);
+  stage_biases(m.master, bl);
   __syncthreads();
-  const uint16_t* wl = reinterpret_cast<const uint16_t*>(wl4);
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
-  for (uint32_t tile = blockIdx.x * kInferWaves + w; tile * 16 < n;
-       tile += gridDim.x * kInferWaves) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, w = threadIdx.x >> 6;
+  const uint32_t stride = gridDim.x * kInferWaves;
+  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  // the light ray and hit of this lane's sample (lr) of a tile; the same
+  // pipeline as the queue kernel's
+  auto fetch = [&](uint32_t tile) {
+    InferRec r{make_uint2(0u, kMiss), zero4, zero4};
     const uint32_t s = tile * 16 + lr;
+    if (tile < kNoTile / 16 && s < n) {
+      r.r0 = q.R0[s];
+      r.h = q.H[s];
+      r.r1 = q.R1[s];
+    }
+    return r;
+  };
+  auto is_hit = [](const InferRec& r) { return r.r0.w != 0.0f && r.h.y != kMiss; };
+  auto normal = [&](const InferRec& r) { return is_hit(r) ? sc.tri_ng[r.h.y] : zero4; };
+  uint32_t tile = blockIdx.x * kInferWaves + w;
+  InferRec cur = fetch(tile);
+  float4 ng = normal(cur);
+  InferRec nxt = fetch(tile + stride);
+  v4f yp = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t rootp = 0u;    // the root of this lane's sample of tile tp
+  uint32_t tp = kNoTile;  // the tile yp belongs to
+  // outputs 0..3 of the sample (the fourth is padding) from the lanes < 16
+  auto store = [&]() {
+    const uint32_t s = tp * 16 + lr;
+    if (lane < 16 && s < n)
+      reinterpret_cast<float4*>(lt.y)[(size_t)rootp * lt.lmax + (i - 1)] =
+          make_float4(yp[0], yp[1], yp[2], yp[3]);
+  };
+  for (; tile * 16 < n; tile += stride) {
+    wait_vector_memory();
+    if (tp != kNoTile) store();
+    tp = kNoTile;
+    const bool hit = is_hit(cur);
     float x[6] = {0, 0, 0, 0, 0, 0};
-    float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    uint2 h = make_uint2(0u, kMiss);
-    if (s < n) {
-      r0 = q.R0[s];
-      h = q.H[s];
-    }
-    const bool hit = r0.w != 0.0f && h.y != kMiss;
-    if (!__any(hit)) continue;  // no light vertex in the tile (wave-uniform)
     if (hit) {
-      const float4 r1 = q.R1[s];
-      const float t = __uint_as_float(h.x);
-      const f3 p = mk3(r0.x + t * r1.x, r0.y + t * r1.y, r0.z + t * r1.z);
-      mlp_input(sc, p, xyz(sc.tri_ng[h.y]), x);
+      const float t = __uint_as_float(cur.h.x);
+      const f3 p = mk3(cur.r0.x + t * cur.r1.x, cur.r0.y + t * cur.r1.y, cur.r0.z + t * cur.r1.z);
+      mlp_input(sc, p, xyz(ng), x);
     }
-    const v4f y = mlp_forward_tile<false>(m.master, wl, x, hs[w], nullptr);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t si = tile * 16 + 4 * lg + r;
-      if (si < n && lr < 3) {
-        const uint32_t root = __float_as_uint(q.R1[si].w);
-        lt.y[((size_t)root * lt.lmax + (i - 1)) * 4 + lr] = y[r];
-      }
+    const float4 ngn = normal(nxt);
+    const InferRec nn = fetch(tile + 2 * stride);
+    if (__any(hit)) {  // else no light vertex in the tile (wave-uniform)
+      yp = mlp_infer_tile(wf, bl, x);
+      rootp = __float_as_uint(cur.r1.w);
+      tp = tile;
     }
-    wave_lds_sync();
+    cur = nxt;
+    ng = ngn;
+    nxt = nn;
   }
+  if (tp != kNoTile) store();
 }
 void k_mlp_infer_light(const SceneDev& sc, const QueuesDev& q, const MlpDev& m, const LightDev& lt,
                        const Counters* cnt, int i, int grid, hipStream_t s) {
-  mlp_infer_light_kernel<<<std::max(1, grid * 3 / 32), 64 * kInferWaves, 0, s>>>(sc, q, m, lt, cnt, i);
+  mlp_infer_light_kernel<<<std::max(1, grid / 16), 64 * kInferWaves, 0, s>>>(sc, q, m, lt, cnt, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,7 +562,7 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
       const size_t s = (size_t)((offset + bi) % n_set);
       for (int k = 0; k < 6; ++k) x[k] = x6[6 * s + k];
     }
-    const v4f y = mlp_forward_tile<true>(m.master, wl, x, S.hs, S.xs);
+    const v4f y = mlp_forward_tile(m.master, wl, x, S.hs, S.xs);
     v4f dz[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -413,6 +599,23 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(MlpDev m, const float* x6
   if (lane == 0) out[kMlpParams] = lsum;
 }
 
+// sum over the workgroup partials of parameter p, in workgroup order; the
+// loads of eight partials are issued before their additions
+__device__ __forceinline__ float sum_partials(const float* __restrict__ partial, int nblocks,
+                                              int p) {
+  float g = 0.0f;
+  int b = 0;
+  for (; b + 8 <= nblocks; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(b + u) * (kMlpParams + 1) + p];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g += v[u];
+  }
+  for (; b < nblocks; ++b) g += partial[(size_t)b * (kMlpParams + 1) + p];
+  return g;
+}
+
 // Adam (binary32): the gradient is the sum of the workgroup partials in
 // workgroup order
 __global__ void mlp_adam_kernel(MlpDev m, int nblocks, const float* ext_grad, float lr, float bc1,
@@ -424,12 +627,7 @@ __global__ void mlp_adam_kernel(MlpDev m, int nblocks, const float* ext_grad, fl
     *loss_out = l;
   }
   if (p >= kMlpParams) return;
-  float g = 0.0f;
-  if (ext_grad) {
-    g = ext_grad[p];
-  } else {
-    for (int b = 0; b < nblocks; ++b) g += m.partial[(size_t)b * (kMlpParams + 1) + p];
-  }
+  const float g = ext_grad ? ext_grad[p] : sum_partials(m.partial, nblocks, p);
   const float b1 = 0.9f, b2 = 0.99f, c1 = (float)(1.0 - 0.9), c2 = (float)(1.0 - 0.99);
   const float mm = b1 * m.m[p] + c1 * g;
   const float vv = b2 * m.v[p] + c2 * g * g;
@@ -446,8 +644,7 @@ __global__ void mlp_adam_kernel(MlpDev m, int nblocks, const float* ext_grad, fl
 __global__ void mlp_sum_partials_kernel(MlpDev m, int nblocks, float* grad, float* loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kMlpParams) return;
-  float g = 0.0f;
-  for (int b = 0; b < nblocks; ++b) g += m.partial[(size_t)b * (kMlpParams + 1) + p];
+  const float g = sum_partials(m.partial, nblocks, p);
   if (p < kMlpParams) grad[p] = g;
   else *loss = g;
 }
@@ -462,11 +659,13 @@ void k_mlp_train_pass(const MlpDev& m, const float* x6, const float* tgt, const 
 }
 void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, float bc1, float bc2,
                 float* loss_out, hipStream_t s) {
-  mlp_adam_kernel<<<(kMlpParams + 255) / 256, 256, 0, s>>>(m, nblocks, ext_grad, lr, bc1, bc2,
-                                                           loss_out);
+  // one parameter per thread, 64-thread workgroups: 228 of them spread the
+  // partial sums over the whole chip
+  mlp_adam_kernel<<<(kMlpParams + 63) / 64, 64, 0, s>>>(m, nblocks, ext_grad, lr, bc1, bc2,
+                                                        loss_out);
 }
 void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, hipStream_t s) {
-  mlp_sum_partials_kernel<<<(kMlpParams + 256) / 256, 256, 0, s>>>(m, nblocks, grad, loss);
+  mlp_sum_partials_kernel<<<(kMlpParams + 64) / 64, 64, 0, s>>>(m, nblocks, grad, loss);
 }
 
 // ---------------------------------------------------------------------------
