@@ -9,8 +9,10 @@ learned-cache MARS iteration at 2 samples per pixel: light subpaths, camera
 paths with per-vertex counts from the network pooled with the octree, all
 connections and shadow rays, back-propagation, cell statistics, the update
 (image estimates, fixed point, targets, refinement) and 32 Adam steps of
-the network.  Warm-up steps: 3 classic-RR iterations, then octree MARS
-iterations (the network trains from the first of them).  Beside the
+the network.  The schedule: 3 classic-RR iterations, 2 octree MARS
+iterations (the network trains from the first of them), then learned-cache
+iterations; the default warm-up (10) ends after 5 of those, so that the
+timed steps see a network past its first updates.  Beside the
 throughput: the efficiency 1/(relMSE s) of both methods at equal relMSE
 over the paper's growing-iteration schedule, the traversal kernel's
 roofline, and the CPU oracle's throughput on the same scene.
@@ -304,6 +306,7 @@ def run_bdpt(args, api, torch):
 LEARNED_WORKLOAD = "learned_vs_octree_bdpt_1920x1080_interior2m_d12"
 LEARNED_SPP = 2            # camera samples per pixel of a timed step
 LEARNED_TRAIN_STEPS = 32   # Adam steps of 8192 samples after every update
+LEARNED_FIRST = 5          # the first learned-cache iteration (after 3 classic, 2 octree MARS)
 
 
 def learned_scene():
@@ -488,12 +491,14 @@ def run_learned(args, api, torch):
     ctx = api.Context(0)
     s = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, max_cells=cells_budget(), mlp=True,
                   seed=1)
-    n_warm = max(args.warmup, 4)   # 3 classic + at least one octree MARS update to train on
+    # 3 classic, 2 octree MARS (updates to train on), then learned-cache
+    # iterations; the timed steps are learned-cache iterations only
+    n_warm = max(args.warmup, LEARNED_FIRST)
 
     def alloc_of(i):
         if i < 3:
             return api.ALLOC_CLASSIC
-        return api.ALLOC_MARS if i < n_warm else api.ALLOC_MLP
+        return api.ALLOC_MARS if i < LEARNED_FIRST else api.ALLOC_MLP
 
     def step(i):
         p = api.iter_params(iteration=i, spp=LEARNED_SPP, alloc=alloc_of(i), stat_clamp=0.0)
@@ -561,7 +566,7 @@ def run_learned(args, api, torch):
         out["efficiency"] = learned_efficiency(api, ctx, sc, torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline_learned(sc, n_warm)
+        out["cpu_baseline"] = cpu_baseline_learned(sc, LEARNED_FIRST)
     return out
 
 
@@ -941,7 +946,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default: 10 for the learned workload, else 5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=-1,
                     help="(profiling runs) stop after the timed steps: no breakdown, "
@@ -959,6 +965,8 @@ def main():
                          "low-discrepancy against independent rounding in renders")
     ap.add_argument("--no-efficiency", action="store_true")
     args = ap.parse_args()
+    if args.warmup is None:
+        args.warmup = 10 if args.workload == "learned" else 5
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per box: this benchmark runs on a single MI355X; "
                                    "--gpus must be 1"}))
