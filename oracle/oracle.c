@@ -134,27 +134,28 @@ void orc_sincos2pi(float u, float* s_out, float* c_out) {
 /* gamma_t = floor(beta_t + r);  r <- r + beta_t - gamma_t                   */
 /* Pinned by exhaustive enumeration (E[gamma_t] = beta_t).                  */
 /* ------------------------------------------------------------------------ */
-static void alg1(const float beta[3], float u, uint32_t gamma[3]) {
+static void alg1n(const float* beta, int n, float u, uint32_t* gamma) {
   float r = u;
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < n; ++t) {
     float s = r + beta[t];
     float g = floorf(s);
     gamma[t] = (uint32_t)g;
     r = s - g;
   }
 }
+static void alg1(const float beta[3], float u, uint32_t gamma[3]) { alg1n(beta, 3, u, gamma); }
 void orc_alg1(const float beta[3], float u, uint32_t gamma[3]) { alg1(beta, u, gamma); }
 /* the rounding of a vertex's counts: Alg. 1 with the first uniform of its
  * draw block 0, or (the naive scheme Alg. 1 replaces) each count rounded
  * with its own uniform, gamma_t = floor(beta_t + u_t), u_t the t-th uniform
  * of that block */
-static void round_vertex(const orc_iter_params* p, const float beta[3], const float u[4],
-                         uint32_t gamma[3]) {
-  if (p->rounding) {
+static void round_vertex(const orc_iter_params* p, const float* beta, const float u[4],
+                         uint32_t* gamma, int n) {
+  if (p->rounding) {  /* three counts only (rejected with per-length light paths) */
     for (int t = 0; t < 3; ++t) gamma[t] = (uint32_t)floorf(beta[t] + u[t]);
     return;
   }
-  alg1(beta, u[0], gamma);
+  alg1n(beta, n, u[0], gamma);
 }
 /* enumerate u = k / n for k = 0..n-1: mean counts, range of the total and of r */
 void orc_alg1_enumerate(const float beta[3], uint32_t n, double mean[3], uint32_t tot_minmax[2],
@@ -237,6 +238,9 @@ struct oracle {
   uint32_t *leaf_node, *leaf_depth, *visits;
   float* fac;     /* [maxc][2][3][3] */
   double* acc;    /* [maxc][3][8] */
+  int32_t nlp;    /* light-path budgets per vertex: 1, or 3 (y_1, y_2, y_3+) */
+  float* fac_x;   /* nlp = 3: [maxc][2][2][3], techniques 3 and 4 */
+  double* acc_x;  /* nlp = 3: [maxc][2][8] */
   float *pm, *cdf;/* [maxc][64] */
   double* hacc;   /* [maxc][64] */
   float* fixed_beta; int32_t nfixed;
@@ -605,6 +609,8 @@ static void octree_reset(oracle* o) {
   for (int t = 0; t < 3; ++t)
     for (int k = 0; k < 2; ++k)
       for (int c = 0; c < 3; ++c) o->fac[((0 * 2 + k) * 3 + t) * 3 + c] = -1.0f;
+  if (o->fac_x)
+    for (int k = 0; k < 12; ++k) o->fac_x[k] = -1.0f;
   for (int b = 0; b < 64; ++b) {
     o->pm[b] = (float)(1.0 / 64.0);
     o->cdf[b] = (float)((double)(b + 1) / 64.0);
@@ -736,6 +742,11 @@ oracle* orc_create(const float* V, const uint32_t* tri_mat, int32_t ntri, const 
   o->pm = calloc((size_t)mc * 64, sizeof(float));
   o->cdf = calloc((size_t)mc * 64, sizeof(float));
   o->hacc = calloc((size_t)mc * 64, sizeof(double));
+  o->nlp = (cfg->mode == ORC_MODE_BDPT && cfg->lp_classes == 3) ? 3 : 1;
+  if (o->nlp == 3) {
+    o->fac_x = calloc((size_t)mc * 12, sizeof(float));
+    o->acc_x = calloc((size_t)mc * 16, sizeof(double));
+  }
   octree_reset(o);
   size_t npx = (size_t)width * height;
   o->iter_sum = calloc(npx * 3, sizeof(float));
@@ -755,6 +766,7 @@ void orc_destroy(oracle* o) {
   free(o->acc); free(o->pm); free(o->cdf); free(o->hacc); free(o->fixed_beta); free(o->Ls);
   free(o->iter_sum); free(o->accum); free(o->Itilde); free(o->ivw_acc); free(o->count_map);
   free(o->beta1); free(o->dbg); free(o->pix_mask); free(o->lpaths);
+  free(o->fac_x); free(o->acc_x);
   free(o);
 }
 
@@ -845,13 +857,32 @@ static void ears_ratios(int mode, double r[3]) {
   else { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; }
 }
 
-static void vertex_beta(const tctx* c, uint32_t cell, v3 T, int depth, float beta[3]) {
+/* resolve one technique's count from its cell factors (Sec. 3.1 fixed
+ * point, three cases; "Handling colors": L2 norm over the channels of the
+ * image-relative throughput z); classic count cb when the cell has no data */
+static float resolve_beta(const float* aRR, const float* aS, const float z[3], float cb) {
+  if (aRR[0] < 0.0f) return cb;
+  float sr = ((z[0] * z[0]) * aRR[0] + (z[1] * z[1]) * aRR[1]) + (z[2] * z[2]) * aRR[2];
+  float ss = ((z[0] * z[0]) * aS[0] + (z[1] * z[1]) * aS[1]) + (z[2] * z[2]) * aS[2];
+  float bRR = sqrtf(sr * (1.0f / 3.0f));
+  float bS = sqrtf(ss * (1.0f / 3.0f));
+  if (bRR < 1.0f) return bRR;
+  if (bS > 1.0f) return bS;
+  return 1.0f;
+}
+
+/* counts of a vertex: beta[0..2] (BSDF, NEE, guided or light path); with
+ * per-length light-path budgets also beta[3], beta[4] (light vertex y_2,
+ * y_3+; beta[2] then belongs to y_1).  beta has room for five. */
+static void vertex_beta(const tctx* c, uint32_t cell, v3 T, int depth, float beta[5]) {
   const oracle* o = c->o;
   const orc_iter_params* p = c->p;
   float cb[3];
   classic_beta(c, T, depth, cb);
   int enabled[3] = {1, o->cfg.nee_enabled && o->nlights > 0, o->cfg.mode != ORC_MODE_PT};
   float z[3] = {T.x / c->It[0], T.y / c->It[1], T.z / c->It[2]};
+  beta[3] = 0.0f;
+  beta[4] = 0.0f;
   if (p->alloc == ORC_ALLOC_EARS) {
     const float* aRR = o->fac + ((cell * 2 + 0) * 3 + 0) * 3;
     const float* aS = o->fac + ((cell * 2 + 1) * 3 + 0) * 3;
@@ -875,35 +906,29 @@ static void vertex_beta(const tctx* c, uint32_t cell, v3 T, int depth, float bet
     }
     return;
   }
-  for (int t = 0; t < 3; ++t) {
+  int ntech = o->nlp == 3 ? 5 : 3;
+  for (int t = 0; t < ntech; ++t) {
     float b;
-    if (!enabled[t]) { beta[t] = 0.0f; continue; }
+    int tc = t < 3 ? t : 2;   /* the light-path classes share the light-path rules */
+    if (!enabled[tc]) { beta[t] = 0.0f; continue; }
     if (p->alloc == ORC_ALLOC_CLASSIC) {
-      b = cb[t];
+      b = cb[tc];
       beta[t] = b;
       continue;
     }
     if (p->alloc == ORC_ALLOC_FIXED) {
       int32_t idx = o->nfixed > 1 ? (int32_t)cell : 0;
-      b = o->fixed_beta[idx * 3 + t];
+      b = o->fixed_beta[idx * 3 + tc];
       if (p->fixed_scale) {
         float s = ((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]) * (1.0f / 3.0f);
         b = b * sqrtf(s);
       }
+    } else if (t < 3) {
+      b = resolve_beta(o->fac + ((cell * 2 + 0) * 3 + t) * 3, o->fac + ((cell * 2 + 1) * 3 + t) * 3,
+                       z, cb[t]);
     } else {
-      const float* aRR = o->fac + ((cell * 2 + 0) * 3 + t) * 3;
-      const float* aS = o->fac + ((cell * 2 + 1) * 3 + t) * 3;
-      if (aRR[0] < 0.0f) {
-        b = cb[t];
-      } else {
-        float sr = ((z[0] * z[0]) * aRR[0] + (z[1] * z[1]) * aRR[1]) + (z[2] * z[2]) * aRR[2];
-        float ss = ((z[0] * z[0]) * aS[0] + (z[1] * z[1]) * aS[1]) + (z[2] * z[2]) * aS[2];
-        float bRR = sqrtf(sr * (1.0f / 3.0f));
-        float bS = sqrtf(ss * (1.0f / 3.0f));
-        if (bRR < 1.0f) b = bRR;
-        else if (bS > 1.0f) b = bS;
-        else b = 1.0f;
-      }
+      b = resolve_beta(o->fac_x + ((cell * 2 + 0) * 2 + (t - 3)) * 3,
+                       o->fac_x + ((cell * 2 + 1) * 2 + (t - 3)) * 3, z, cb[2]);
     }
     beta[t] = fminf(fmaxf(b, p->clamp_lo), p->clamp_hi);
   }
@@ -917,7 +942,9 @@ void orc_cell_beta(const oracle* o, const orc_iter_params* p, uint32_t cell, con
   memset(&c, 0, sizeof(c));
   c.o = o; c.p = p;
   c.It[0] = It[0]; c.It[1] = It[1]; c.It[2] = It[2];
-  vertex_beta(&c, cell, mk(T[0], T[1], T[2]), depth, beta);
+  float b5[5];
+  vertex_beta(&c, cell, mk(T[0], T[1], T[2]), depth, b5);
+  beta[0] = b5[0]; beta[1] = b5[1]; beta[2] = b5[2];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -974,12 +1001,12 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
   v3 ov = mk(x.x + n.x * o->eps, x.y + n.y * o->eps, x.z + n.z * o->eps);
   uint32_t cdepth;
   uint32_t cell = octree_lookup(o, x, &cdepth);
-  float beta[3];
+  float beta[5];
   vertex_beta(c, cell, T, depth, beta);
   float ur[4];
   draw4(c->key, strm, 0, ur);
   uint32_t gam[3];
-  round_vertex(p, beta, ur, gam);
+  round_vertex(p, beta, ur, gam, 3);
   c->L->vertices++;
   { stat_rec s = {REC_VISIT, cell, 0, 0, {0, 0, 0}, 0, 0}; log_push(c->L, s); }
   if (depth == 1) {
@@ -990,6 +1017,7 @@ static trace_out trace_pt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t str
     orc_vertex_rec d;
     d.root = c->root; d.depth = depth; d.stream_lo = strm.lo; d.stream_hi = strm.hi; d.cell = cell;
     for (int k = 0; k < 3; ++k) { d.beta[k] = beta[k]; d.gamma[k] = gam[k]; }
+    d.beta_x[0] = d.beta_x[1] = 0.0f; d.gamma_x[0] = d.gamma_x[1] = 0u;
     d.T[0] = T.x; d.T[1] = T.y; d.T[2] = T.z;
     dbg_push(c->L, d);
   }
@@ -1116,6 +1144,9 @@ static void build_light_paths(oracle* o, const orc_iter_params* p, key_t2 key, r
 int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats* st) {
   if (!o || !p || p->spp <= 0) return -1;
   if (p->alloc == ORC_ALLOC_FIXED && !o->fixed_beta) return -2;
+  /* per-length light-path budgets: Alg. 1 rounding over the five counts and
+   * per-technique fixed points only (no EARS line, no per-count uniforms) */
+  if (o->nlp == 3 && (p->alloc == ORC_ALLOC_EARS || p->rounding)) return -3;
   int32_t W = o->W, H = o->H, spp = p->spp;
   size_t nroots = (size_t)W * H * spp;
   if (o->spp_last != spp) {
@@ -1129,6 +1160,7 @@ int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats
   memset(o->Ls, 0, nroots * 3 * sizeof(float));
   memset(o->visits, 0, sizeof(uint32_t) * o->ncells);
   memset(o->acc, 0, sizeof(double) * 24 * o->ncells);
+  if (o->acc_x) memset(o->acc_x, 0, sizeof(double) * 16 * o->ncells);
   memset(o->hacc, 0, sizeof(double) * 64 * o->ncells);
   rowlog* logs = calloc(H, sizeof(rowlog));
   key_t2 key = {(uint32_t)o->cfg.seed, (uint32_t)(o->cfg.seed >> 32)};
@@ -1182,7 +1214,8 @@ int32_t orc_render_iteration(oracle* o, const orc_iter_params* p, orc_iter_stats
       if (r->kind == REC_VISIT) {
         o->visits[r->cell]++;
       } else if (r->kind == REC_SAMPLE) {
-        double* a = o->acc + ((size_t)r->cell * 3 + r->tech) * 8;
+        double* a = r->tech < 3 ? o->acc + ((size_t)r->cell * 3 + r->tech) * 8
+                                : o->acc_x + ((size_t)r->cell * 2 + (r->tech - 3)) * 8;
         for (int ch = 0; ch < 3; ++ch) {
           a[ch] += (double)r->v[ch];
           a[3 + ch] += (double)r->v[ch] * (double)r->v[ch];
@@ -1243,6 +1276,22 @@ int32_t orc_update_cells_only(oracle* o, double V_I, double C_I) {
         if (var < 0.0) var = 0.0;
         o->fac[((cidx * 2 + 0) * 3 + t) * 3 + ch] = (float)(k * E2);
         o->fac[((cidx * 2 + 1) * 3 + t) * 3 + ch] = (float)(k * var);
+      }
+    }
+    /* per-length light paths: techniques 3 and 4, the same update */
+    for (int x = 0; o->nlp == 3 && x < 2; ++x) {
+      const double* a = o->acc_x + ((size_t)cidx * 2 + x) * 8;
+      double n = a[6];
+      if (!(n > 0.0)) continue;
+      double Ct = a[7] / n;
+      if (!(Ct > 0.0)) continue;
+      double k = C_I / (Ct * V_I);
+      for (int ch = 0; ch < 3; ++ch) {
+        double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+        double var = E2 - E1 * E1;
+        if (var < 0.0) var = 0.0;
+        o->fac_x[((cidx * 2 + 0) * 2 + x) * 3 + ch] = (float)(k * E2);
+        o->fac_x[((cidx * 2 + 1) * 2 + x) * 3 + ch] = (float)(k * var);
       }
     }
     if (o->ears_update) {
@@ -1324,6 +1373,8 @@ int32_t orc_refine_only(oracle* o) {
       o->leaf_depth[id] = child_depth;
       if (ch) {
         memcpy(o->fac + 18 * (size_t)id, o->fac + 18 * (size_t)l, 18 * sizeof(float));
+        if (o->fac_x)
+          memcpy(o->fac_x + 12 * (size_t)id, o->fac_x + 12 * (size_t)l, 12 * sizeof(float));
         memcpy(o->pm + 64 * (size_t)id, o->pm + 64 * (size_t)l, 64 * sizeof(float));
         memcpy(o->cdf + 64 * (size_t)id, o->cdf + 64 * (size_t)l, 64 * sizeof(float));
       }
@@ -1491,6 +1542,18 @@ void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n) {
   for (int32_t i = 0; i < n; ++i)
     if (pix[i] >= 0 && pix[i] < o->W * o->H) o->pix_mask[pix[i]] = 1;
 }
+int32_t orc_lp_classes(const oracle* o) { return o->nlp; }
+void orc_read_cells_x(const oracle* o, float* factors_x, double* acc_x) {
+  if (!o->fac_x) return;
+  if (factors_x) memcpy(factors_x, o->fac_x, sizeof(float) * 12 * o->ncells);
+  if (acc_x) memcpy(acc_x, o->acc_x, sizeof(double) * 16 * o->ncells);
+}
+void orc_write_cells_x(oracle* o, int32_t n, const float* factors_x, const double* acc_x) {
+  if (!o->fac_x) return;
+  if (n > o->ncells) n = o->ncells;
+  if (factors_x) memcpy(o->fac_x, factors_x, sizeof(float) * 12 * n);
+  if (acc_x) memcpy(o->acc_x, acc_x, sizeof(double) * 16 * n);
+}
 void orc_set_Itilde(oracle* o, const float* src) {
   memcpy(o->Itilde, src, sizeof(float) * 3 * o->W * o->H);
 }
@@ -1550,8 +1613,8 @@ static void eval_facing(const float* m, v3 ng, v3 wo, v3 wi, v3* fc, float* pdf)
   bsdf_eval(m, n, wo, wi, fc, pdf);
 }
 
-/* counts of a vertex at depth `depth` used as camera vertex */
-static void counts_for(const tctx* c, v3 P, v3 T, int depth, float beta[3]) {
+/* counts of a vertex at depth `depth` used as camera vertex (room for five) */
+static void counts_for(const tctx* c, v3 P, v3 T, int depth, float beta[5]) {
   uint32_t cell = octree_lookup(c->o, P, NULL);
   vertex_beta(c, cell, T, depth, beta);
 }
@@ -1560,7 +1623,8 @@ static void counts_for(const tctx* c, v3 P, v3 T, int depth, float beta[3]) {
  * for the path z[0] (camera), z[1..k] (z[k] on an emitter). */
 static float bdpt_weight(const tctx* c, const pvert* z, int k, int t) {
   if (k <= 1) return 1.0f;
-  float pF[BD_MAXK + 2], pR[BD_MAXK + 2], nB[BD_MAXK + 2], nN[BD_MAXK + 2], nL[BD_MAXK + 2];
+  float pF[BD_MAXK + 2], pR[BD_MAXK + 2], nB[BD_MAXK + 2], nN[BD_MAXK + 2];
+  float nL[3][BD_MAXK + 2]; /* light-path counts; [1], [2] with per-length budgets */
   float d2;
   /* area densities of z_i sampled from the camera side (i >= 2) */
   for (int i = 2; i <= k; ++i) {
@@ -1591,11 +1655,14 @@ static float bdpt_weight(const tctx* c, const pvert* z, int k, int t) {
   v3 T = mk(1.0f, 1.0f, 1.0f);
   int aware = c->p->budget_aware;
   for (int i = 1; i <= k - 1; ++i) {
-    float b[3];
+    float b[5];
     counts_for(c, z[i].P, T, i, b);
     nB[i] = aware ? b[0] : (b[0] > 0.0f ? 1.0f : 0.0f);
     nN[i] = aware ? b[1] : (b[1] > 0.0f ? 1.0f : 0.0f);
-    nL[i] = aware ? b[2] : (b[2] > 0.0f ? 1.0f : 0.0f);
+    for (int x = 0; x < 3; ++x) {
+      float bl = b[x == 0 ? 2 : 2 + x];
+      nL[x][i] = aware ? bl : (bl > 0.0f ? 1.0f : 0.0f);
+    }
     if (i < k - 1) {
       v3 wo = dir_between(z[i].P, z[i - 1].P, &d2);
       v3 wi = dir_between(z[i].P, z[i + 1].P, &d2);
@@ -1609,7 +1676,11 @@ static float bdpt_weight(const tctx* c, const pvert* z, int k, int t) {
         T = mk(0.0f, 0.0f, 0.0f);
     }
   }
-#define TF(tt) ((tt) == k + 1 ? 1.0f : ((tt) == k ? nN[k - 1] : nL[(tt) - 1]))
+  /* strategy tt connects z_{tt-1} to z_tt = y_{k-tt}: the count of its
+   * light-vertex class (one class unless per-length budgets) */
+  const int nlp = c->o->nlp;
+#define LCLS(i) (nlp == 3 ? ((i) < 3 ? (i) - 1 : 2) : 0)
+#define TF(tt) ((tt) == k + 1 ? 1.0f : ((tt) == k ? nN[k - 1] : nL[LCLS(k - (tt))][(tt) - 1]))
   float tft = TF(t);
   if (!(tft > 0.0f)) return 0.0f;
   float sum = 1.0f, rp = 1.0f, rb = 1.0f;
@@ -1626,6 +1697,7 @@ static float bdpt_weight(const tctx* c, const pvert* z, int k, int t) {
     sum = sum + rp * (TF(tt) / (rb * tft));
   }
 #undef TF
+#undef LCLS
   if (!(sum < INFINITY)) return 0.0f; /* also NaN */
   return 1.0f / sum;
 }
@@ -1722,22 +1794,24 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
   v3 wo = mk(-dir.x, -dir.y, -dir.z);
   v3 ov = mk(x.x + n.x * o->eps, x.y + n.y * o->eps, x.z + n.z * o->eps);
   uint32_t cell = octree_lookup(o, x, NULL);
-  float beta[3];
+  float beta[5];
   vertex_beta(c, cell, T, depth, beta);
   float ur[4];
   draw4(c->key, strm, 0, ur);
-  uint32_t gam[3];
-  round_vertex(p, beta, ur, gam);
+  uint32_t gam[5] = {0, 0, 0, 0, 0};
+  round_vertex(p, beta, ur, gam, 2 + o->nlp);
   c->L->vertices++;
   { stat_rec s = {REC_VISIT, cell, 0, 0, {0, 0, 0}, 0, 0}; log_push(c->L, s); }
   if (depth == 1) {
     float* b1 = o->beta1 + 3 * (size_t)c->root;
-    b1[0] = beta[0]; b1[1] = beta[1]; b1[2] = beta[2];
+    /* per-length light paths: the light-path count is the sum over lengths */
+    b1[0] = beta[0]; b1[1] = beta[1]; b1[2] = o->nlp == 3 ? (beta[2] + beta[3]) + beta[4] : beta[2];
   }
   if (depth <= p->debug_depth) {
     orc_vertex_rec d;
     d.root = c->root; d.depth = depth; d.stream_lo = strm.lo; d.stream_hi = strm.hi; d.cell = cell;
     for (int k = 0; k < 3; ++k) { d.beta[k] = beta[k]; d.gamma[k] = gam[k]; }
+    d.beta_x[0] = beta[3]; d.beta_x[1] = beta[4]; d.gamma_x[0] = gam[3]; d.gamma_x[1] = gam[4];
     d.T[0] = T.x; d.T[1] = T.y; d.T[2] = T.z;
     dbg_push(c->L, d);
   }
@@ -1813,52 +1887,63 @@ static trace_out trace_bdpt(tctx* c, v3 org, v3 dir, v3 T, int depth, stream_t s
     stat_rec s = {REC_SAMPLE, cell, ORC_TECH_B, 0, {v.x, v.y, v.z}, scost, 0};
     log_sample(c, depth, s);
   }
-  /* light-path connections */
+  /* light-path connections: one budget for every light vertex, or with
+   * per-length budgets (Sec. 5, the variant named there as future work) a
+   * class per light-vertex index: technique 2 connects to y_1, 3 to y_2,
+   * 4 to y_3 and beyond.  Sample k of every class uses the same pool entry
+   * sequence, so with all class counts 1 the connections are those of one
+   * light-path sample. */
   uint32_t npool = (uint32_t)(o->W * o->H * p->spp);
-  for (uint32_t k = 0; k < gam[2]; ++k) {
-    c->L->samples++;
-    /* light subpath: pool entry (b + k stride) mod npool with b the first
-     * word of this vertex's stream, so the vertices of one path tree use
-     * unrelated light subpaths (their samples stay independent) */
-    uint32_t lpi = (uint32_t)(((uint64_t)strm.lo + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
-    const lightpath* lp = &o->lpaths[lpi];
-    v3 v = mk(0, 0, 0);
-    /* cost of an LP sample: its connection rays (at least 1); the light
-     * subpath is traced once per camera sample whatever the counts */
-    uint32_t scost = 0;
-    int imax = o->cfg.max_depth - depth - 1;
-    if (imax > lp->len) imax = lp->len;
-    for (int i = 1; i <= imax; ++i) {
-      const pvert* y = &lp->y[i - 1];
-      float d2;
-      v3 w = dir_between(x, y->P, &d2);
-      v3 fcC, fcL;
-      float pc, pl;
-      bsdf_eval(m, n, wo, w, &fcC, &pc);
-      eval_facing(y->m, y->ng, lp->wo[i - 1], mk(-w.x, -w.y, -w.z), &fcL, &pl);
-      if (!(fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f)) continue;
-      if (!(fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) continue;
-      /* the full path: z_1..z_depth, y_i, .., y_1, y_0 */
-      for (int j = 1; j <= i; ++j) z[depth + j] = lp->y[i - j];
-      z[depth + i + 1] = lp->y0;
-      float wc = bdpt_weight(c, z, depth + 1 + i, depth + 1);
-      v3 a = lp->alpha[i - 1];
-      v3 ny = vdot(y->ng, lp->wo[i - 1]) > 0.0f ? y->ng : mk(-y->ng.x, -y->ng.y, -y->ng.z);
-      v3 yo = mk(y->P.x + ny.x * o->eps, y->P.y + ny.y * o->eps, y->P.z + ny.z * o->eps);
-      float sd2;
-      v3 sw = dir_between(ov, yo, &sd2);
-      c->L->rays_conn++;
-      scost += 1;
-      if (!occluded(o, ov, sw, sqrtf(sd2) * (1.0f - 1e-3f))) {
-        v = mk(v.x + wc * (((a.x * fcL.x) * fcC.x) / d2), v.y + wc * (((a.y * fcL.y) * fcC.y) / d2),
-               v.z + wc * (((a.z * fcL.z) * fcC.z) / d2));
+  for (int cls = 0; cls < o->nlp; ++cls) {
+    const int tech = cls == 0 ? ORC_TECH_G : 2 + cls;
+    const int ilo = o->nlp == 1 ? 1 : cls + 1;
+    const int icap = (o->nlp == 1 || cls == 2) ? BD_MAXK : cls + 1;
+    for (uint32_t k = 0; k < gam[tech]; ++k) {
+      c->L->samples++;
+      /* light subpath: pool entry (b + k stride) mod npool with b the first
+       * word of this vertex's stream, so the vertices of one path tree use
+       * unrelated light subpaths (their samples stay independent) */
+      uint32_t lpi = (uint32_t)(((uint64_t)strm.lo + (uint64_t)k * (uint32_t)p->lp_stride) % npool);
+      const lightpath* lp = &o->lpaths[lpi];
+      v3 v = mk(0, 0, 0);
+      /* cost of an LP sample: its connection rays (at least 1); the light
+       * subpath is traced once per camera sample whatever the counts */
+      uint32_t scost = 0;
+      int imax = o->cfg.max_depth - depth - 1;
+      if (imax > lp->len) imax = lp->len;
+      if (imax > icap) imax = icap;
+      for (int i = ilo; i <= imax; ++i) {
+        const pvert* y = &lp->y[i - 1];
+        float d2;
+        v3 w = dir_between(x, y->P, &d2);
+        v3 fcC, fcL;
+        float pc, pl;
+        bsdf_eval(m, n, wo, w, &fcC, &pc);
+        eval_facing(y->m, y->ng, lp->wo[i - 1], mk(-w.x, -w.y, -w.z), &fcL, &pl);
+        if (!(fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f)) continue;
+        if (!(fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) continue;
+        /* the full path: z_1..z_depth, y_i, .., y_1, y_0 */
+        for (int j = 1; j <= i; ++j) z[depth + j] = lp->y[i - j];
+        z[depth + i + 1] = lp->y0;
+        float wc = bdpt_weight(c, z, depth + 1 + i, depth + 1);
+        v3 a = lp->alpha[i - 1];
+        v3 ny = vdot(y->ng, lp->wo[i - 1]) > 0.0f ? y->ng : mk(-y->ng.x, -y->ng.y, -y->ng.z);
+        v3 yo = mk(y->P.x + ny.x * o->eps, y->P.y + ny.y * o->eps, y->P.z + ny.z * o->eps);
+        float sd2;
+        v3 sw = dir_between(ov, yo, &sd2);
+        c->L->rays_conn++;
+        scost += 1;
+        if (!occluded(o, ov, sw, sqrtf(sd2) * (1.0f - 1e-3f))) {
+          v = mk(v.x + wc * (((a.x * fcL.x) * fcC.x) / d2), v.y + wc * (((a.y * fcL.y) * fcC.y) / d2),
+                 v.z + wc * (((a.z * fcL.z) * fcC.z) / d2));
+        }
       }
+      if (scost == 0) scost = 1;
+      R = mk(R.x + v.x / beta[tech], R.y + v.y / beta[tech], R.z + v.z / beta[tech]);
+      cost += scost;
+      stat_rec s = {REC_SAMPLE, cell, (uint32_t)tech, 0, {v.x, v.y, v.z}, scost, 0};
+      log_sample(c, depth, s);
     }
-    if (scost == 0) scost = 1;
-    R = mk(R.x + v.x / beta[2], R.y + v.y / beta[2], R.z + v.z / beta[2]);
-    cost += scost;
-    stat_rec s = {REC_SAMPLE, cell, ORC_TECH_G, 0, {v.x, v.y, v.z}, scost, 0};
-    log_sample(c, depth, s);
   }
   out.R = R;
   out.cost = cost;

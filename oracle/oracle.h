@@ -30,6 +30,10 @@ enum { ORC_MODE_PT = 0, ORC_MODE_PT_GUIDED = 1, ORC_MODE_BDPT = 2 };
  * classic per-technique ratios (value 3 is the GPU library's learned cache) */
 enum { ORC_ALLOC_CLASSIC = 0, ORC_ALLOC_MARS = 1, ORC_ALLOC_FIXED = 2, ORC_ALLOC_EARS = 4 };
 enum { ORC_TECH_B = 0, ORC_TECH_N = 1, ORC_TECH_G = 2 }; /* third = guided or light path */
+/* BDPT with separate light-path budgets per light-vertex index (Sec. 5,
+ * the variant left to future work there): technique 2 connects to y_1,
+ * technique 3 to y_2 and technique 4 to y_3 and beyond */
+enum { ORC_TECH_L2 = 3, ORC_TECH_L3 = 4 };
 
 typedef struct {
   int32_t mode;          /* ORC_MODE_* */
@@ -39,6 +43,8 @@ typedef struct {
   int32_t split_visits;  /* split a leaf after more than this many visits (32) */
   int32_t nee_enabled;   /* 1: NEE technique on (requires emitters) */
   uint64_t seed;
+  int32_t lp_classes;    /* BDPT: 3 = separate light-path budgets for y_1, y_2, y_3+;
+                            anything else = one budget for every light vertex */
 } orc_config;
 
 typedef struct {
@@ -71,6 +77,8 @@ typedef struct {
   float beta[3];
   uint32_t gamma[3];
   float T[3];
+  float beta_x[2];       /* counts of techniques 3 and 4 (per-length light paths) */
+  uint32_t gamma_x[2];
 } orc_vertex_rec;
 
 typedef struct oracle oracle;
@@ -99,6 +107,12 @@ int32_t orc_read_debug(const oracle* o, orc_vertex_rec* dst, int32_t cap);
 /* write-in for parity tests */
 void orc_write_cells(oracle* o, int32_t n, const float* factors, const double* acc,
                      const uint32_t* visits);
+/* per-length light-path budgets (lp_classes = 3): the factors [n][2][2][3]
+ * (RR/S, technique 3 or 4, ch) and accumulators [n][2][8] of techniques 3, 4;
+ * orc_lp_classes returns 3 when the scene has them, else 1 */
+int32_t orc_lp_classes(const oracle* o);
+void orc_read_cells_x(const oracle* o, float* factors_x, double* acc_x);
+void orc_write_cells_x(oracle* o, int32_t n, const float* factors_x, const double* acc_x);
 void orc_set_Itilde(oracle* o, const float* src);
 /* render only the listed pixels (NULL / 0: all); others get zero radiance */
 void orc_set_pixel_subset(oracle* o, const int32_t* pix, int32_t n);

@@ -15,7 +15,7 @@ ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_EARS = 0, 1, 2, 4
 class Config(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_depth", C.c_int32), ("max_cells", C.c_int32),
                 ("max_tree_depth", C.c_int32), ("split_visits", C.c_int32),
-                ("nee_enabled", C.c_int32), ("seed", C.c_uint64)]
+                ("nee_enabled", C.c_int32), ("seed", C.c_uint64), ("lp_classes", C.c_int32)]
 
 
 class IterParams(C.Structure):
@@ -46,12 +46,14 @@ class UpdateStats(C.Structure):
 class VertexRec(C.Structure):
     _fields_ = [("root", C.c_uint32), ("depth", C.c_uint32), ("stream_lo", C.c_uint32),
                 ("stream_hi", C.c_uint32), ("cell", C.c_uint32), ("beta", C.c_float * 3),
-                ("gamma", C.c_uint32 * 3), ("T", C.c_float * 3)]
+                ("gamma", C.c_uint32 * 3), ("T", C.c_float * 3), ("beta_x", C.c_float * 2),
+                ("gamma_x", C.c_uint32 * 2)]
 
 
 VERTEX_DTYPE = np.dtype([("root", "<u4"), ("depth", "<u4"), ("stream_lo", "<u4"),
                          ("stream_hi", "<u4"), ("cell", "<u4"), ("beta", "<f4", 3),
-                         ("gamma", "<u4", 3), ("T", "<f4", 3)])
+                         ("gamma", "<u4", 3), ("T", "<f4", 3), ("beta_x", "<f4", 2),
+                         ("gamma_x", "<u4", 2)])
 
 _lib = None
 
@@ -84,6 +86,10 @@ def lib():
         L.orc_read_debug.argtypes = [P, P, C.c_int32]
         L.orc_read_debug.restype = C.c_int32
         L.orc_write_cells.argtypes = [P, C.c_int32, P, P, P]
+        L.orc_lp_classes.argtypes = [P]
+        L.orc_lp_classes.restype = C.c_int32
+        L.orc_read_cells_x.argtypes = [P, P, P]
+        L.orc_write_cells_x.argtypes = [P, C.c_int32, P, P]
         L.orc_set_Itilde.argtypes = [P, P]
         L.orc_set_pixel_subset.argtypes = [P, P, C.c_int32]
         L.orc_set_fixed_beta.argtypes = [P, P, C.c_int32]
@@ -129,7 +135,7 @@ class Oracle:
     """Plain CPU implementation of the hot path, one scene per instance."""
 
     def __init__(self, scene, mode=MODE_PT, max_depth=5, max_cells=65536, max_tree_depth=8,
-                 split_visits=32, nee=True, seed=1):
+                 split_visits=32, nee=True, seed=1, lp_classes=1):
         L = lib()
         self.scene = scene
         self.V = np.ascontiguousarray(scene["V"], np.float32)
@@ -138,7 +144,7 @@ class Oracle:
         self.cam = np.ascontiguousarray(scene["camera"], np.float32)
         self.W, self.H = int(scene["width"]), int(scene["height"])
         self.cfg = Config(mode, max_depth, max_cells, max_tree_depth, split_visits, int(bool(nee)),
-                          seed)
+                          seed, int(lp_classes))
         self.h = L.orc_create(_p(self.V), _p(self.tm), self.V.shape[0], _p(self.mats),
                               self.mats.shape[0], _p(self.cam), self.W, self.H, C.byref(self.cfg))
         if not self.h:
@@ -220,6 +226,25 @@ class Oracle:
         dep = np.zeros(n, np.uint32)
         lib().orc_read_cells(self.h, _p(fac), _p(acc), _p(vis), _p(dep))
         return {"factors": fac, "acc": acc, "visits": vis, "depth": dep}
+
+    @property
+    def lp_classes(self):
+        return lib().orc_lp_classes(self.h)
+
+    def cells_x(self):
+        """Per-length light-path budgets: factors [n][2][2][3] and
+        accumulators [n][2][8] of techniques 3 (y_2) and 4 (y_3+)."""
+        n = self.ncells
+        fac = np.zeros((n, 2, 2, 3), np.float32)
+        acc = np.zeros((n, 2, 8), np.float64)
+        lib().orc_read_cells_x(self.h, _p(fac), _p(acc))
+        return {"factors": fac, "acc": acc}
+
+    def write_cells_x(self, factors=None, acc=None):
+        f = None if factors is None else np.ascontiguousarray(factors, np.float32)
+        a = None if acc is None else np.ascontiguousarray(acc, np.float64)
+        lib().orc_write_cells_x(self.h, self.ncells, None if f is None else _p(f),
+                                None if a is None else _p(a))
 
     def hist(self):
         n = self.ncells
