@@ -94,8 +94,16 @@ typedef struct {
 } mars_scene_desc;
 
 /* scene flags: MARS_SCENE_MLP allocates the learned cache (counts predicted
- * by a small network trained online on the octree's estimates) */
-enum { MARS_SCENE_MLP = 1 };
+ * by a small network trained online on the octree's estimates).
+ * MARS_SCENE_LP_LENGTHS (BDPT): separate light-path budgets per light-vertex
+ * index, the variant Sec. 5 leaves to future work.  A camera vertex then has
+ * five counts: BSDF, NEE, and connections to the light vertex y_1
+ * (technique 2), y_2 (technique 3) and y_3 and beyond (technique 4), each
+ * with its own moments, cost and fixed point; Alg. 1 rounds all five with
+ * one uniform, and sample k of every class connects to the same light
+ * subpath.  Not combined with MARS_SCENE_MLP, EARS iterations or
+ * independent rounding (MARS_E_ARG). */
+enum { MARS_SCENE_MLP = 1, MARS_SCENE_LP_LENGTHS = 2 };
 
 typedef struct {
   int32_t iteration;        /* keys the random streams */
@@ -137,6 +145,8 @@ typedef struct {
   float beta[3];
   uint32_t gamma[3];
   float T[3];
+  float beta_x[2];          /* MARS_SCENE_LP_LENGTHS: counts of techniques 3, 4, else 0 */
+  uint32_t gamma_x[2];
 } mars_vertex_rec;
 
 /* ---- lifetime ---------------------------------------------------------- */
@@ -264,6 +274,14 @@ mars_status mars_num_cells(mars_ctx* ctx, int32_t scene_id, int32_t* n_cells, in
 mars_status mars_read_cells(mars_ctx* ctx, int32_t scene_id, float* factors, double* acc,
                             uint32_t* visits, uint32_t* leaf_depth);
 mars_status mars_read_nodes(mars_ctx* ctx, int32_t scene_id, uint32_t* nodes);
+/* MARS_SCENE_LP_LENGTHS scenes: factors [n][2][2][3] (RR/S, technique 3 or 4,
+ * channel) and acc [n][2][8] of the two extra light-path classes, host arrays
+ * sized by mars_num_cells (either may be NULL; Sec. 3.1 "Optimization" per
+ * technique).  MARS_E_STATE for scenes without them. */
+mars_status mars_read_cells_x(mars_ctx* ctx, int32_t scene_id, float* factors_x, double* acc_x);
+/* the same arrays written in; n must equal the current number of cells */
+mars_status mars_write_cells_x(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* factors_x,
+                               const double* acc_x);
 mars_status mars_read_hist(mars_ctx* ctx, int32_t scene_id, float* pm, float* cdf);
 /* per-vertex decisions of the last iteration up to params.debug_depth;
  * writes at most cap records, returns the total in *n */

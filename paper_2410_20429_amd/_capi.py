@@ -19,6 +19,7 @@ MODE_PT, MODE_PT_GUIDED, MODE_BDPT = 0, 1, 2
 ALLOC_CLASSIC, ALLOC_MARS, ALLOC_FIXED, ALLOC_MLP, ALLOC_EARS = 0, 1, 2, 3, 4
 IMAGE_MEAN, IMAGE_IVW, IMAGE_LAST = 0, 1, 2
 SCENE_MLP = 1
+SCENE_LP_LENGTHS = 2
 BATCH_UPDATE, BATCH_NO_GRAPH = 1, 2
 
 alloc_fn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -68,7 +69,8 @@ class mars_update_stats(C.Structure):
 class mars_vertex_rec(C.Structure):
     _fields_ = [("root", C.c_uint32), ("depth", C.c_uint32), ("stream_lo", C.c_uint32),
                 ("stream_hi", C.c_uint32), ("cell", C.c_uint32), ("beta", C.c_float * 3),
-                ("gamma", C.c_uint32 * 3), ("T", C.c_float * 3)]
+                ("gamma", C.c_uint32 * 3), ("T", C.c_float * 3), ("beta_x", C.c_float * 2),
+                ("gamma_x", C.c_uint32 * 2)]
 
 
 P = C.c_void_p
@@ -98,6 +100,8 @@ SIGNATURES = {
     "mars_read_itilde": [P, I32, P, I32],
     "mars_num_cells": [P, I32, PI32, PI32],
     "mars_read_cells": [P, I32, P, P, P, P],
+    "mars_read_cells_x": [P, I32, P, P],
+    "mars_write_cells_x": [P, I32, I32, P, P],
     "mars_read_nodes": [P, I32, P],
     "mars_read_hist": [P, I32, P, P],
     "mars_debug_vertices": [P, I32, P, I32, PI32],
@@ -290,6 +294,14 @@ def mars_read_cells(ctx, sid, fac_ptr, acc_ptr, vis_ptr, dep_ptr):
 
 def mars_read_nodes(ctx, sid, ptr):
     _call("mars_read_nodes", ctx, sid, ptr)
+
+
+def mars_read_cells_x(ctx, sid, fac_ptr, acc_ptr):
+    _call("mars_read_cells_x", ctx, sid, fac_ptr, acc_ptr)
+
+
+def mars_write_cells_x(ctx, sid, n, fac_ptr, acc_ptr):
+    _call("mars_write_cells_x", ctx, sid, n, fac_ptr, acc_ptr)
 
 
 def mars_read_hist(ctx, sid, pm_ptr, cdf_ptr):

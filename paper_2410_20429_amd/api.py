@@ -10,11 +10,12 @@ import numpy as np
 from . import _capi as capi
 from ._capi import (ALLOC_CLASSIC, ALLOC_EARS, ALLOC_FIXED, ALLOC_MARS, ALLOC_MLP, IMAGE_IVW,  # noqa: F401
                     IMAGE_LAST, IMAGE_MEAN, MODE_BDPT, MODE_PT, MODE_PT_GUIDED, SCENE_MLP, MarsError,
-                    BATCH_NO_GRAPH, BATCH_UPDATE)
+                    BATCH_NO_GRAPH, BATCH_UPDATE, SCENE_LP_LENGTHS)
 
 VERTEX_DTYPE = np.dtype([("root", "<u4"), ("depth", "<u4"), ("stream_lo", "<u4"),
                          ("stream_hi", "<u4"), ("cell", "<u4"), ("beta", "<f4", 3),
-                         ("gamma", "<u4", 3), ("T", "<f4", 3)])
+                         ("gamma", "<u4", 3), ("T", "<f4", 3), ("beta_x", "<f4", 2),
+                         ("gamma_x", "<u4", 2)])
 
 
 def _p(a):
@@ -101,7 +102,7 @@ class Scene:
 
     def __init__(self, ctx: Context, scene: dict, mode=MODE_PT, max_depth=5, max_cells=65536,
                  max_tree_depth=8, split_visits=32, nee=True, seed=1, queue_capacity=0,
-                 tile_roots=0, mlp=False):
+                 tile_roots=0, mlp=False, lp_lengths=False):
         self.ctx = ctx
         self.V = np.ascontiguousarray(scene["V"], np.float32)
         self.tm = np.ascontiguousarray(scene["tri_mat"], np.uint32)
@@ -114,7 +115,7 @@ class Scene:
                                  self.V.shape[0], self.mats.shape[0], self.W, self.H, mode,
                                  max_depth, max_cells, max_tree_depth, split_visits, int(bool(nee)),
                                  seed, int(queue_capacity), int(tile_roots),
-                                 SCENE_MLP if mlp else 0)
+                                 (SCENE_MLP if mlp else 0) | (SCENE_LP_LENGTHS if lp_lengths else 0))
         self.id = capi.mars_scene_upload(ctx.h, d)
         self.spp = 0
         self._last = None
@@ -199,6 +200,21 @@ class Scene:
         dep = np.zeros(n, np.uint32)
         capi.mars_read_cells(self.ctx.h, self.id, _p(fac), _p(acc), _p(vis), _p(dep))
         return {"factors": fac, "acc": acc, "visits": vis, "depth": dep}
+
+    def cells_x(self):
+        """Per-length light-path budgets: factors [n][2][2][3] and
+        accumulators [n][2][8] of techniques 3 (y_2) and 4 (y_3+)."""
+        n = self.ncells
+        fac = np.zeros((n, 2, 2, 3), np.float32)
+        acc = np.zeros((n, 2, 8), np.float64)
+        capi.mars_read_cells_x(self.ctx.h, self.id, _p(fac), _p(acc))
+        return {"factors": fac, "acc": acc}
+
+    def write_cells_x(self, factors=None, acc=None):
+        arrs = [None if x is None else np.ascontiguousarray(x, dt)
+                for x, dt in ((factors, np.float32), (acc, np.float64))]
+        capi.mars_write_cells_x(self.ctx.h, self.id, self.ncells,
+                                *[None if a is None else _p(a) for a in arrs])
 
     def hist(self):
         n = self.ncells

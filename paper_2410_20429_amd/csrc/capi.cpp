@@ -297,6 +297,8 @@ void check_params(Scene* s, const mars_iter_params* p) {
   if (p->alloc == MARS_ALLOC_FIXED && !s->fixed) throw Status(MARS_E_STATE, "no fixed counts set");
   if (p->alloc == MARS_ALLOC_MLP && !s->mlp_on)
     throw Status(MARS_E_ARG, "learned cache not enabled for scene");
+  if (s->sd.lp_classes == 3 && (p->alloc == MARS_ALLOC_EARS || p->rounding))
+    throw Status(MARS_E_ARG, "per-length light-path budgets: no EARS iterations, Alg. 1 rounding only");
   if (!(p->clamp_lo > 0.0f) || !(p->clamp_hi >= p->clamp_lo) || !(p->clamp_hi <= 64.0f))
     throw Status(MARS_E_ARG, "count clamp must satisfy 0 < lo <= hi <= 64");
   if (!(p->stat_clamp >= 0.0f)) throw Status(MARS_E_ARG, "stat_clamp must be >= 0");
@@ -334,7 +336,8 @@ void alloc_queues(Scene* s, size_t cap) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     for (void* p : {(void*)q.R0, (void*)q.R1, (void*)q.S0, (void*)q.S1, (void*)q.S2, (void*)q.S3,
                     (void*)q.H, (void*)q.V0, (void*)q.V1, (void*)q.V2, (void*)q.RO, (void*)q.SH0,
-                    (void*)q.SH1, (void*)q.SH2, (void*)q.W0, (void*)q.W1, (void*)s->mlp.y})
+                    (void*)q.SH1, (void*)q.SH2, (void*)q.W0, (void*)q.W1, (void*)q.W2, (void*)q.V3,
+                    (void*)s->mlp.y})
       sfree(s, p);
     q = QueuesDev{};
     s->mlp.y = nullptr;
@@ -350,6 +353,10 @@ void alloc_queues(Scene* s, size_t cap) {
   if (s->mode == MARS_MODE_BDPT) {
     q.W0 = salloc<float4>(s, lv);
     q.W1 = salloc<float4>(s, lv);
+  }
+  if (s->sd.lp_classes == 3) {
+    q.W2 = salloc<float4>(s, lv);
+    q.V3 = salloc<float4>(s, lv);
   }
   q.cap = cap;
   if (s->mlp_on) s->mlp.y = salloc<float>(s, lv * 4);
@@ -574,6 +581,10 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
   if (d->max_cells < 8 || d->max_cells > (1 << 24)) throw Status(MARS_E_ARG, "max_cells out of range");
   if (d->max_tree_depth < 0 || d->max_tree_depth > 20) throw Status(MARS_E_ARG, "bad max_tree_depth");
   if ((int64_t)d->width * d->height > (1 << 26)) throw Status(MARS_E_ARG, "image too large");
+  if (d->flags & ~(MARS_SCENE_MLP | MARS_SCENE_LP_LENGTHS)) throw Status(MARS_E_ARG, "unknown scene flags");
+  if ((d->flags & MARS_SCENE_LP_LENGTHS) &&
+      (d->mode != MARS_MODE_BDPT || (d->flags & MARS_SCENE_MLP)))
+    throw Status(MARS_E_ARG, "per-length light-path budgets need a BDPT scene without the learned cache");
   const int nt = d->n_tris, nm = d->n_mats;
   for (size_t i = 0; i < (size_t)nt * 9; ++i)
     if (!std::isfinite(d->V[i])) throw Status(MARS_E_NONFINITE, "non-finite vertex");
@@ -733,6 +744,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     sd.mode = d->mode;
     sd.max_depth = d->max_depth;
     sd.nee = d->nee_enabled;
+    sd.lp_classes = (d->flags & MARS_SCENE_LP_LENGTHS) ? 3 : 1;
     sd.key0 = (uint32_t)d->seed;
     sd.key1 = (uint32_t)(d->seed >> 32);
     // cache: one root leaf, no data (classic counts), uniform distribution
@@ -747,6 +759,10 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
     cd.pm = salloc<float>(s, mc * 64);
     cd.cdf = salloc<float>(s, mc * 64);
     cd.hacc = salloc<double>(s, mc * 64);
+    if (sd.lp_classes == 3) {
+      cd.fac_x = salloc<float>(s, mc * 12);
+      cd.acc_x = salloc<double>(s, mc * 16);
+    }
     cd.fixed = nullptr;
     cd.n_fixed = 0;
     cd.max_cells = d->max_cells;
@@ -766,6 +782,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
       h2d(cd.leaf_node, &z, 4, st);
       h2d(cd.leaf_depth, &z, 4, st);
       h2d(cd.fac, f0.data(), 18 * 4, st);
+      if (cd.fac_x) h2d(cd.fac_x, f0.data(), 12 * 4, st);
       h2d(cd.pm, pm0.data(), 256, st);
       h2d(cd.cdf, cdf0.data(), 256, st);
       h2d(s->n_cells_dev, nc, 16, st);
@@ -1172,7 +1189,8 @@ size_t min_tile(size_t roots, double e) {
 
 size_t queue_bytes(const Scene* s, size_t cap) {
   return cap * (size_t)(s->max_depth + 2) *
-         (kQueueEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0));
+         (kQueueEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0) +
+          (s->sd.lp_classes == 3 ? 32 : 0));
 }
 
 std::string scene_class(const Scene* s, const mars_iter_params* p) {
@@ -1729,6 +1747,31 @@ mars_status mars_read_cells(mars_ctx* ctx, int32_t scene_id, float* factors, dou
   });
 }
 
+mars_status mars_read_cells_x(mars_ctx* ctx, int32_t scene_id, float* factors_x, double* acc_x) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (!s->cd.fac_x) throw Status(MARS_E_STATE, "scene has one light-path budget");
+    const size_t n = (size_t)s->n_cells;
+    if (factors_x) d2h(factors_x, s->cd.fac_x, 48 * n, ctx->stream);
+    if (acc_x) d2h(acc_x, s->cd.acc_x, 128 * n, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+mars_status mars_write_cells_x(mars_ctx* ctx, int32_t scene_id, int32_t n, const float* factors_x,
+                               const double* acc_x) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    Scene* s = ctx->scene(scene_id);
+    if (!s->cd.fac_x) throw Status(MARS_E_STATE, "scene has one light-path budget");
+    if (n != s->n_cells) throw Status(MARS_E_ARG, "n must equal the number of cells");
+    if (factors_x) h2d(s->cd.fac_x, factors_x, 48 * (size_t)n, ctx->stream);
+    if (acc_x) h2d(s->cd.acc_x, acc_x, 128 * (size_t)n, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 mars_status mars_read_nodes(mars_ctx* ctx, int32_t scene_id, uint32_t* nodes) {
   if (!ctx || !nodes) return MARS_E_ARG;
   return guard(ctx, [&] {
@@ -1783,6 +1826,8 @@ mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* pa
     d2h(it.data(), s->img.itilde, px * 12, st);
     d2h(ivw.data(), s->img.ivw_acc, px * 24, st);
     d2h(red.data(), s->img.red, 64, st);
+    std::vector<float> facx(s->cd.fac_x ? nc * 12 : 0);
+    if (s->cd.fac_x) d2h(facx.data(), s->cd.fac_x, nc * 48, st);
     HIPCHK(hipStreamSynchronize(st));
     CkptHeader h{};
     std::memcpy(h.magic, "MARSCKP1", 8);
@@ -1796,6 +1841,7 @@ mars_status mars_checkpoint_save(mars_ctx* ctx, int32_t scene_id, const char* pa
     w(nodes.data(), nn * 4); w(lnode.data(), nc * 4); w(ldep.data(), nc * 4);
     w(fac.data(), nc * 72); w(pm.data(), nc * 256); w(cdf.data(), nc * 256);
     w(accum.data(), px * 12); w(it.data(), px * 12); w(ivw.data(), px * 24);
+    w(facx.data(), facx.size() * 4);  // per-length light-path scenes only
     ok = (std::fclose(f) == 0) && ok;
     if (!ok) throw Status(MARS_E_IO, "checkpoint write failed");
   });
@@ -1827,6 +1873,8 @@ mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* pa
     r(nodes.data(), nn * 4); r(lnode.data(), nc * 4); r(ldep.data(), nc * 4);
     r(fac.data(), nc * 72); r(pm.data(), nc * 256); r(cdf.data(), nc * 256);
     r(accum.data(), px * 12); r(it.data(), px * 12); r(ivw.data(), px * 24);
+    std::vector<float> facx(s->cd.fac_x ? nc * 12 : 0);
+    r(facx.data(), facx.size() * 4);  // per-length light-path scenes only
     std::fclose(f);
     if (!ok) throw Status(MARS_E_IO, "truncated checkpoint");
     // structural validation: every reference stays inside the arrays
@@ -1845,6 +1893,7 @@ mars_status mars_checkpoint_load(mars_ctx* ctx, int32_t scene_id, const char* pa
     h2d(s->cd.leaf_node, lnode.data(), nc * 4, st);
     h2d(s->cd.leaf_depth, ldep.data(), nc * 4, st);
     h2d(s->cd.fac, fac.data(), nc * 72, st);
+    if (s->cd.fac_x) h2d(s->cd.fac_x, facx.data(), nc * 48, st);
     h2d(s->cd.pm, pm.data(), nc * 256, st);
     h2d(s->cd.cdf, cdf.data(), nc * 256, st);
     h2d(s->img.accum, accum.data(), px * 12, st);

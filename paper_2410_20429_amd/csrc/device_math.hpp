@@ -118,15 +118,19 @@ __device__ __forceinline__ void sincos_turns(float u, float* s_out, float* c_out
 // techniques; each technique takes floor(beta + r) samples and passes the
 // fractional remainder on (supplement, Alg. 1)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void round_counts(const float beta[3], float u, uint32_t g[3]) {
+template <int N>
+__device__ __forceinline__ void round_counts_n(const float* beta, float u, uint32_t* g) {
   float r = u;
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < N; ++t) {
     const float s = r + beta[t];
     const float f = floorf(s);
     g[t] = (uint32_t)f;
     r = s - f;
   }
+}
+__device__ __forceinline__ void round_counts(const float beta[3], float u, uint32_t g[3]) {
+  round_counts_n<3>(beta, u, g);
 }
 
 // each count rounded with its own uniform (the scheme Alg. 1 improves on):

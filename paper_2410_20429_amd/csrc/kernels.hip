@@ -138,13 +138,15 @@ void k_fill_f64(double* p, double v, size_t n, hipStream_t s) {
 __global__ void clear_iteration_kernel(CacheDev c, const int32_t* n_cells_dev, int guided,
                                        float* beta1, size_t n_beta) {
   const size_t n = (size_t)*n_cells_dev;
-  const size_t na = n * 24, nh = guided ? n * 64 : 0, nv = n;
-  const size_t total = na + nh + nv + n_beta;
+  const size_t na = n * 24, nx = c.acc_x ? n * 16 : 0, nh = guided ? n * 64 : 0, nv = n;
+  const size_t total = na + nx + nh + nv + n_beta;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
     size_t k = i;
     if (k < na) { c.acc[k] = 0.0; continue; }
     k -= na;
+    if (k < nx) { c.acc_x[k] = 0.0; continue; }
+    k -= nx;
     if (k < nh) { c.hacc[k] = 0.0; continue; }
     k -= nh;
     if (k < nv) { c.visits[k] = 0u; continue; }
@@ -906,6 +908,49 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
   }
 }
 
+// counts of the light-path classes y_2 and y_3+ (techniques 3 and 4) of a
+// bidirectional scene with per-length budgets: the light-path rules of
+// counts_at (classic count 1, the fixed count of the light-path slot, the
+// fixed point of Sec. 3.1 with the class's own factors and the same colour
+// rule and clamp)
+__device__ __forceinline__ void counts_at_x(const CacheDev& c, const IterDev& it, uint32_t cell,
+                                            f3 T, const float* It, float bx[2]) {
+  const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    if (it.alloc == 0) { bx[x] = 1.0f; continue; }
+    float b;
+    if (it.alloc == 2) {
+      const int idx = c.n_fixed > 1 ? (int)cell : 0;
+      b = c.fixed[idx * 3 + 2];
+      if (it.fixed_scale) {
+        const float s = ((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f);
+        b = b * sqrtf(s);
+      }
+    } else {
+      const float* aRR = c.fac_x + (size_t)cell * 12 + (0 * 2 + x) * 3;
+      const float* aS = c.fac_x + (size_t)cell * 12 + (1 * 2 + x) * 3;
+      if (aRR[0] < 0.0f) {
+        b = 1.0f;
+      } else {
+        const float sr = ((z0 * z0) * aRR[0] + (z1 * z1) * aRR[1]) + (z2 * z2) * aRR[2];
+        const float ss = ((z0 * z0) * aS[0] + (z1 * z1) * aS[1]) + (z2 * z2) * aS[2];
+        const float bRR = sqrtf(sr * (1.0f / 3.0f));
+        const float bS = sqrtf(ss * (1.0f / 3.0f));
+        b = bRR < 1.0f ? bRR : (bS > 1.0f ? bS : 1.0f);
+      }
+    }
+    bx[x] = fminf(fmaxf(b, it.clamp_lo), it.clamp_hi);
+  }
+}
+
+// the count of the light-path class of light vertex y_i (i >= 1): one class
+// unless per-length budgets, then b2 for y_1, b3 for y_2, b4 for y_3+
+__device__ __forceinline__ float lp_class_count(const SceneDev& sc, float b2, float b3, float b4,
+                                                int i) {
+  return sc.lp_classes == 3 ? (i == 1 ? b2 : (i == 2 ? b3 : b4)) : b2;
+}
+
 // learned cache (alloc mode 3): from the network's outputs y at a vertex,
 // its count |T / I~| exp(y_t) (colour rule's norm) is pooled with the
 // octree's count beta_t as their geometric mean, then clamped; the octree
@@ -1295,9 +1340,11 @@ struct AggTable {
   double val[kAggSlots][kAggVals];
 };
 
+// key = cell << 3 | technique; techniques 3 and 4 (per-length light paths)
+// live in acc_x
 __device__ __forceinline__ void global_add_stats(const CacheDev& c, uint32_t key, const double* v) {
-  const uint32_t cell = key >> 2, t = key & 3u;
-  double* a = c.acc + ((size_t)cell * 3 + t) * 8;
+  const uint32_t cell = key >> 3, t = key & 7u;
+  double* a = t < 3u ? c.acc + ((size_t)cell * 3 + t) * 8 : c.acc_x + ((size_t)cell * 2 + (t - 3u)) * 8;
 #pragma unroll
   for (int i = 0; i < 8; ++i)
     if (v[i] != 0.0) atomicAdd(a + i, v[i]);
@@ -1391,7 +1438,7 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
 #pragma unroll
         for (int i = 0; i < 8; ++i) vals[i] = st[t][i];
         vals[8] = t == 0 ? 1.0 : 0.0;
-        agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
+        agg_add(A, c, (cell << 3) | (uint32_t)t, vals);
       }
     }
     if (d >= 2) {
@@ -1490,11 +1537,13 @@ __device__ __forceinline__ PV prim_vertex(const SceneDev& sc, f3 P, uint32_t pri
 struct VRec {
   f3 T;
   float b0, b1, b2, pF, pRg;
+  float b3, b4;  // per-length light paths: the y_2 and y_3+ classes (else unused)
 };
 __device__ __forceinline__ VRec load_rec(const QueuesDev& q, int l, uint32_t e) {
   const size_t a = (size_t)l * q.cap + e;
   const float4 w0 = q.W0[a], w1 = q.W1[a];
-  return VRec{xyz(w0), w0.w, w1.x, w1.y, w1.z, w1.w};
+  const float4 w2 = q.W2 ? q.W2[a] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  return VRec{xyz(w0), w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y};
 }
 __device__ __forceinline__ float mis_count(const IterDev& it, float b) {
   return it.aware ? b : (b > 0.0f ? 1.0f : 0.0f);
@@ -1534,9 +1583,12 @@ __device__ float bdpt_weight(const SceneDev& sc, const QueuesDev& q, const IterD
     eval_facing(load_mat(sc.mats + 8 * (size_t)z[i + 1].mat), z[i + 1].ng, wo, wi, &fc, &p);
     return (p * fabsf(dot3(z[i].ng, wi))) / d2;
   };
-  // strategy tt's own technique count, from the record of z_{tt-1}
+  // strategy tt's own technique count, from the record of z_{tt-1} (it
+  // connects z_{tt-1} to the light vertex y_{k-tt})
   auto tf = [&](int tt, const VRec& r) -> float {
-    return tt == k + 1 ? 1.0f : (tt == k ? mis_count(it, r.b1) : mis_count(it, r.b2));
+    return tt == k + 1 ? 1.0f
+                       : (tt == k ? mis_count(it, r.b1)
+                                  : mis_count(it, lp_class_count(sc, r.b2, r.b3, r.b4, k - tt)));
   };
   const float tft = t == k + 1 ? 1.0f : tf(t, load_rec(q, t - 1, ez[t - 1]));
   if (!(tft > 0.0f)) return 0.0f;
@@ -1747,6 +1799,11 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
   if (mlp_active(c, it)) mlp_apply(it, T, It, c.mlp_y + a * 4, b);
   q.W0[a] = make_float4(T.x, T.y, T.z, b[0]);
   q.W1[a] = make_float4(b[1], b[2], pF, pRg);
+  if (q.W2) {
+    float bx[2];
+    counts_at_x(c, it, cell, T, It, bx);
+    q.W2[a] = make_float4(bx[0], bx[1], 0.0f, 0.0f);
+  }
 }
 
 // The light side of a connection's path, read where it is used: vertex
@@ -1827,9 +1884,11 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
   const VRec rd = load_rec(q, d, j);
   f3 T = rd.T;
   float b[3] = {rd.b0, rd.b1, rd.b2};
+  float bx[2] = {rd.b3, rd.b4};
   const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
   float nB_prev = mis_count(it, b[0]);
-  const float tft = t == k ? mis_count(it, b[1]) : mis_count(it, b[2]);
+  const float tft = t == k ? mis_count(it, b[1])
+                           : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], k - t));
   if (!(tft > 0.0f)) return 0.0f;
   // the strategies tt = t + 1 .. k + 1, in that order, walking the light
   // side one vertex z_i = z_{tt-1} at a time: the BSDF at z_{i-1} gives both
@@ -1857,8 +1916,11 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
       const uint32_t cell = cy != kNoCell ? cy : cell_of(c.nodes, olo, sc.oct_inv, C.P);
       counts_at(sc, c, it, cell, T, It, i, b);
       if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
+      if (sc.lp_classes == 3) counts_at_x(c, it, cell, T, It, bx);
       nB_i = mis_count(it, b[0]);
-      tf = i == k - 1 ? mis_count(it, b[1]) : mis_count(it, b[2]);
+      // strategy i + 1 connects z_i to the light vertex y_{k-i-1}
+      tf = i == k - 1 ? mis_count(it, b[1])
+                      : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], k - i - 1));
     }
     rp = rp * (pFi / path_pR(sc, i, k, C, D, E));
     rb = rb * nB_prev;
@@ -1883,7 +1945,8 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
     const VRec par = load_rec(q, tt - 1, epar);
     rp = rp * (pRt / cur.pF);
     rb = rb * mis_count(it, par.b0);
-    sum = sum + rp * (mis_count(it, par.b2) / (rb * tft));
+    // strategy tt connects z_{tt-1} (par) to the light vertex y_{k-tt}
+    sum = sum + rp * (mis_count(it, lp_class_count(sc, par.b2, par.b3, par.b4, k - tt)) / (rb * tft));
     prg2 = prg1;
     prg1 = cur.pRg;
     cur = par;
@@ -1929,6 +1992,20 @@ __device__ __forceinline__ uint32_t lp_index(uint32_t b, uint32_t j, int32_t str
   return (uint32_t)(((unsigned long long)b + (unsigned long long)j * (uint32_t)stride) % npool);
 }
 
+// light vertices y_lo..y_hi a light-path sample of class cls connects to,
+// of the imax its subpath offers within the path-length limit: every one
+// with one light-path budget; with per-length budgets y_1, y_2 or y_3+
+__device__ __forceinline__ void lp_class_range(const SceneDev& sc, int cls, int imax, int* lo,
+                                               int* hi) {
+  if (sc.lp_classes != 3) {
+    *lo = 1;
+    *hi = imax;
+  } else {
+    *lo = cls + 1;
+    *hi = cls == 2 ? imax : min(cls + 1, imax);
+  }
+}
+
 __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                          LightDev lt, Counters* cnt, IterDev it,
                                                          ImageDev img, DebugRec* dbg,
@@ -1948,8 +2025,9 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
     bool vert = false;
     f3 Ew = mk3(0.0f, 0.0f, 0.0f);
     uint32_t cell = kNoCell;
-    float beta[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t gam[3] = {0u, 0u, 0u};
+    // BSDF, NEE, light path (with per-length budgets: y_1, then y_2, y_3+)
+    float beta[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    uint32_t gam[5] = {0u, 0u, 0u, 0u, 0u};
     f3 x = mk3(0, 0, 0), n_s = mk3(0, 0, 0), wo = mk3(0, 0, 0), T = mk3(0, 0, 0),
        ov = mk3(0, 0, 0);
     uint32_t prim = kMiss, pix = 0, root = 0, nconn = 0;
@@ -1990,17 +2068,23 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           cell = cell_of(c.nodes, mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]), sc.oct_inv, x);
           T = xyz(q.S0[L + j]);
           counts_at(sc, c, it, cell, T, It, d, beta);
+          if (sc.lp_classes == 3) counts_at_x(c, it, cell, T, It, beta + 3);
           bdpt_record(sc, c, q, it, d, j, x, ng, cell, It);
           mlp_counts(c, it, L + j, T, It, beta);
           strm = make_uint2(s3.x, s3.y);
           const float4 u = draw4(key, strm, 0);
           if (it.rounding) round_counts_independent(beta, u, gam);
+          else if (sc.lp_classes == 3) round_counts_n<5>(beta, u.x, gam);
           else round_counts(beta, u.x, gam);
           mlp_record(c, strm, x, pix, ng, T);
           const int imax0 = sc.max_depth - d - 1;
-          for (uint32_t k = 0; k < gam[2]; ++k) {
-            const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
-            nconn += (uint32_t)max(0, min(imax0, (int)lt.len[lpi].x));
+          for (int cls = 0; cls < sc.lp_classes; ++cls) {
+            for (uint32_t k = 0; k < gam[cls == 0 ? 2 : 2 + cls]; ++k) {
+              const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
+              int lo, hi;
+              lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
+              nconn += (uint32_t)max(0, hi - lo + 1);
+            }
           }
         }
       }
@@ -2018,16 +2102,19 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
     if (!active) continue;
     q.V0[L + j] = make_float4(Ew.x, Ew.y, Ew.z, fbits(cell));
     q.V1[L + j] = make_float4(beta[0], beta[1], beta[2], fbits(vert ? gam[2] : 0u));
+    if (q.V3)
+      q.V3[L + j] = make_float4(beta[3], beta[4], fbits(vert ? gam[3] : 0u), fbits(vert ? gam[4] : 0u));
     q.V2[L + j] = ovf ? make_uint4(0, 0, 0, 0)
                       : make_uint4(sfirst, (vert ? gam[1] : 0u) | (nconn << 16), cfirst, ncont);
     if (d == 1) {
       img.beta1[3 * (size_t)root] = beta[0];
       img.beta1[3 * (size_t)root + 1] = beta[1];
-      img.beta1[3 * (size_t)root + 2] = beta[2];
+      // per-length light paths: the light-path count is the sum over lengths
+      img.beta1[3 * (size_t)root + 2] = sc.lp_classes == 3 ? (beta[2] + beta[3]) + beta[4] : beta[2];
     }
     if (!vert || ovf) continue;
     ++my_vert;
-    my_samp += gam[0] + gam[1] + gam[2];
+    my_samp += gam[0] + gam[1] + gam[2] + gam[3] + gam[4];
     if (d <= it.debug_depth && dbg) {
       const uint32_t k = atomicAdd(&cnt->n_debug, 1u);
       if (k < dbg_cap) {
@@ -2035,6 +2122,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
         r.root = root; r.depth = (uint32_t)d; r.stream_lo = strm.x; r.stream_hi = strm.y;
         r.cell = cell;
         for (int t = 0; t < 3; ++t) { r.beta[t] = beta[t]; r.gamma[t] = gam[t]; }
+        r.beta_x[0] = beta[3]; r.beta_x[1] = beta[4]; r.gamma_x[0] = gam[3]; r.gamma_x[1] = gam[4];
         r.T[0] = T.x; r.T[1] = T.y; r.T[2] = T.z;
         dbg[k] = r;
       }
@@ -2091,16 +2179,20 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
       q.S2[e] = make_float4(0.0f, 0.0f, 0.0f, beta[0]);
       q.S3[e] = make_uint4(ss.x, ss.y, k, root);
     }
-    // light-path connections: one shadow entry per (sample, light vertex)
+    // light-path connections: one shadow entry per (sample, light vertex),
+    // the classes in order (sample k of every class on the same subpath)
     uint32_t slot = sfirst + gam[1];
     const int imax0 = sc.max_depth - d - 1;
-    for (uint32_t k = 0; k < gam[2]; ++k) {
-      const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
-      const int imax = max(0, min(imax0, (int)lt.len[lpi].x));
-      for (int i = 1; i <= imax; ++i, ++slot) {
-        const size_t e = L + slot;
-        q.SH0[e] = make_float4(fbits(lpi), fbits((uint32_t)i), 0.0f, 0.0f);
-        q.SH1[e] = make_float4(fbits(kConnLight), 0.0f, 0.0f, fbits(j));
+    for (int cls = 0; cls < sc.lp_classes; ++cls) {
+      for (uint32_t k = 0; k < gam[cls == 0 ? 2 : 2 + cls]; ++k) {
+        const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
+        int lo, hi;
+        lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
+        for (int i = lo; i <= hi; ++i, ++slot) {
+          const size_t e = L + slot;
+          q.SH0[e] = make_float4(fbits(lpi), fbits((uint32_t)i), 0.0f, 0.0f);
+          q.SH1[e] = make_float4(fbits(kConnLight), 0.0f, 0.0f, fbits(j));
+        }
       }
     }
   }
@@ -2263,6 +2355,10 @@ void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, con
 }
 
 // back-propagation for BDPT: NEE, BSDF and LP samples in that order
+// (kLpLengths: per-length light-path budgets, the classes y_1, y_2, y_3+;
+// an instantiation of its own so that the single-budget kernel keeps its
+// registers)
+template <bool kLpLengths>
 __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDev c, QueuesDev q,
                                                             LightDev lt, const Counters* cnt,
                                                             IterDev it, ImageDev img, int d,
@@ -2318,25 +2414,49 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
       }
       uint32_t slot = v2.x + nnee;
       const int imax0 = sc.max_depth - d - 1;
-      for (uint32_t k = 0; k < glp; ++k) {
-        const uint32_t lpi = lp_index(q.S3[L + j].x, k, it.lp_stride, npool);
-        const uint2 ll = lt.len[lpi];
-        const int imax = max(0, min(imax0, (int)ll.x));
-        f3 v = mk3(0.0f, 0.0f, 0.0f);
-        // an LP sample costs its connection rays (at least 1): the light
-        // subpath is traced once per camera sample whatever the counts
-        uint32_t sc_ = 0;
-        for (int i = 1; i <= imax; ++i, ++slot) {
-          const float4 r = q.SH2[L + slot];
-          if (r.w != 0.0f) {
-            sc_ += 1;
-            v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
+      const float4 v3 = kLpLengths ? q.V3[L + j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int cls = 0; cls < (kLpLengths ? 3 : 1); ++cls) {
+        // the class's count and rounded count: y_1 (or every light vertex)
+        // in V1, the y_2 and y_3+ classes in V3, whose statistics are summed
+        // apart and merged when the class is done
+        const float bt = cls == 0 ? b.z : (cls == 1 ? v3.x : v3.y);
+        const uint32_t g = cls == 0 ? glp : ubits(cls == 1 ? v3.z : v3.w);
+        double sx[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (uint32_t k = 0; k < g; ++k) {
+          const uint32_t lpi = lp_index(q.S3[L + j].x, k, it.lp_stride, npool);
+          const uint2 ll = lt.len[lpi];
+          int lo, hi;
+          lp_class_range(sc, cls, max(0, min(imax0, (int)ll.x)), &lo, &hi);
+          f3 v = mk3(0.0f, 0.0f, 0.0f);
+          // an LP sample costs its connection rays (at least 1): the light
+          // subpath is traced once per camera sample whatever the counts
+          uint32_t sc_ = 0;
+          for (int i = lo; i <= hi; ++i, ++slot) {
+            const float4 r = q.SH2[L + slot];
+            if (r.w != 0.0f) {
+              sc_ += 1;
+              v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
+            }
+          }
+          sc_ = max(sc_, 1u);
+          R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
+          cost += sc_;
+          if (!kLpLengths || cls == 0) {
+            record(2, v, sc_);
+          } else {
+            const double x0 = (double)v.x, x1 = (double)v.y, x2 = (double)v.z;
+            sx[0] += x0; sx[1] += x1; sx[2] += x2;
+            sx[3] += x0 * x0; sx[4] += x1 * x1; sx[5] += x2 * x2;
+            sx[6] += 1.0; sx[7] += (double)sc_;
           }
         }
-        sc_ = max(sc_, 1u);
-        R = mk3(R.x + v.x / b.z, R.y + v.y / b.z, R.z + v.z / b.z);
-        cost += sc_;
-        record(2, v, sc_);
+        if (kLpLengths && cls > 0 && sx[6] != 0.0) {
+          double vals[kAggVals];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) vals[i] = sx[i];
+          vals[8] = 0.0;
+          agg_add(A, c, (cell << 3) | (uint32_t)(2 + cls), vals);
+        }
       }
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
@@ -2345,7 +2465,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
 #pragma unroll
         for (int i = 0; i < 8; ++i) vals[i] = st[t][i];
         vals[8] = t == 0 ? 1.0 : 0.0;
-        agg_add(A, c, (cell << 2) | (uint32_t)t, vals);
+        agg_add(A, c, (cell << 3) | (uint32_t)t, vals);
       }
     }
     if (d >= 2) {
@@ -2379,7 +2499,10 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s) {
-  backprop_bdpt_kernel<<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
+  if (sc.lp_classes == 3)
+    backprop_bdpt_kernel<true><<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
+  else
+    backprop_bdpt_kernel<false><<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
 }
 
 // ---------------------------------------------------------------------------
@@ -2747,6 +2870,22 @@ __global__ void fixed_point_kernel(CacheDev c, const int32_t* n_cells_dev, const
         c.fac[(size_t)cidx * 18 + (1 * 3 + t) * 3 + ch] = (float)(k * var);
       }
     }
+    // per-length light paths: techniques 3 and 4, the same update
+    for (int x = 0; c.acc_x && x < 2; ++x) {
+      const double* a = c.acc_x + ((size_t)cidx * 2 + x) * 8;
+      const double n = a[6];
+      if (!(n > 0.0)) continue;
+      const double Ct = a[7] / n;
+      if (!(Ct > 0.0)) continue;
+      const double k = C_I / (Ct * V_I);
+      for (int ch = 0; ch < 3; ++ch) {
+        const double E1 = a[ch] / n, E2 = a[3 + ch] / n;
+        double var = E2 - E1 * E1;
+        if (var < 0.0) var = 0.0;
+        c.fac_x[(size_t)cidx * 12 + (0 * 2 + x) * 3 + ch] = (float)(k * E2);
+        c.fac_x[(size_t)cidx * 12 + (1 * 2 + x) * 3 + ch] = (float)(k * var);
+      }
+    }
     if (ears_mode >= 0) {
       // EARS iterations: the shared factors of the cell into technique slot 0
       // (the fixed point restricted to beta_t = r_t lambda)
@@ -2918,6 +3057,11 @@ __global__ __launch_bounds__(256) void apply_split_kernel(CacheDev c, const uint
   }
   for (int k = lane; k < 7 * 18; k += 64)
     c.fac[(size_t)(first + k / 18) * 18 + k % 18] = c.fac[(size_t)l * 18 + k % 18];
+  if (c.fac_x) {
+    for (int k = lane; k < 7 * 12; k += 64)
+      c.fac_x[(size_t)(first + k / 12) * 12 + k % 12] = c.fac_x[(size_t)l * 12 + k % 12];
+    for (int k = lane; k < 7 * 16; k += 64) c.acc_x[(size_t)(first + k / 16) * 16 + k % 16] = 0.0;
+  }
   for (int k = lane; k < 7 * 64; k += 64) {
     const size_t dst = (size_t)(first + k / 64) * 64 + k % 64, src = (size_t)l * 64 + k % 64;
     c.pm[dst] = c.pm[src];

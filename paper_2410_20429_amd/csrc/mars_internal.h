@@ -32,6 +32,9 @@ struct SceneDev {
   float oct_lo[3];
   float oct_inv;
   int32_t mode, max_depth, nee;
+  // BDPT light-path budgets per camera vertex: 1, or 3 (connections to the
+  // light vertex y_1, y_2 and y_3+ each with its own count, techniques 2-4)
+  int32_t lp_classes;
   uint32_t key0, key1;
   // traversal stack entries beyond the LDS part, [depth][spill_threads]
   // (null when the tree's stack bound fits in LDS)
@@ -47,6 +50,8 @@ struct CacheDev {
   uint32_t* visits;      // [max_cells]
   float* fac;            // [max_cells][2][3][3]  a^RR, a^S per technique and channel
   double* acc;           // [max_cells][3][8]     sum v (3), sum v^2 (3), n, cost
+  float* fac_x;          // lp_classes 3: [max_cells][2][2][3] factors of techniques 3, 4
+  double* acc_x;         // lp_classes 3: [max_cells][2][8]
   float* pm;             // [max_cells][64]       directional pmf (guided)
   float* cdf;            // [max_cells][64]
   double* hacc;          // [max_cells][64]       directional training sums
@@ -77,6 +82,10 @@ struct QueuesDev {
   // BSDF count), W1 = (raw NEE count, raw LP count, pF here, pR two back)
   float4* W0;
   float4* W1;
+  // lp_classes 3 only: W2 = (raw count of the y_2 class, of the y_3+ class,
+  // -, -); V3 = (beta of those classes, their rounded counts (bits))
+  float4* W2;
+  float4* V3;
   float4* SH0;  // shadow origin, tmax
   float4* SH1;  // shadow direction, parent vertex (bits)
   float4* SH2;  // unoccluded NEE sample value, flags (1 = traced)
@@ -122,6 +131,8 @@ struct DebugRec {
   float beta[3];
   uint32_t gamma[3];
   float T[3];
+  float beta_x[2];     // techniques 3, 4 (per-length light paths), else 0
+  uint32_t gamma_x[2];
 };
 
 // per-iteration image buffers
