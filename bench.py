@@ -19,8 +19,10 @@ roofline, and the CPU oracle's throughput on the same scene.
 
 Other workloads (--workload): guided (512 x 512 guided PT), bdpt
 (1280 x 720 bidirectional), batch (32 scenes), ears (MARS vs EARS vs
-classic RR) and convergence.  Prints one JSON line.  --gpus above 1 is not
-supported (one GPU per box).
+classic RR), convergence, rounding (Alg. 1 against independent rounding)
+and lp_lengths (separate light-path budgets per light-vertex index against
+one budget).  Prints one JSON line.  --gpus above 1 is not supported (one
+GPU per box).
 """
 import argparse
 import hashlib
@@ -145,7 +147,7 @@ def reference_image(api, ctx, sc, spp=16, iters=256, seed_iter=100000, mode=None
 
 
 def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256),
-                   ears=False, unaware=False):
+                   ears=False, unaware=False, lp_lengths=False):
     """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
     paper's evaluation: n_iter iterations of 1, 2, 4, ... spp, the first
     three with classic RR, then MARS (render + update each); the MARS image
@@ -154,14 +156,17 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
     classic reference of ref_spp[0] x ref_spp[1] spp, 0.01% brightest
     outliers discarded.  With ears, EARS (one shared count per vertex, the
     paper's comparison method) runs the same schedule as MARS; with unaware,
-    so does MARS with the budget-unaware balance heuristic."""
+    so does MARS with the budget-unaware balance heuristic; with lp_lengths,
+    MARS with separate light-path budgets per light-vertex index (y_1, y_2,
+    y_3+; bidirectional scenes), with both MIS forms."""
     import numpy as np
     mode = api.MODE_PT_GUIDED if mode is None else mode
     kc = 0.0 if mode == api.MODE_BDPT else 50.0
     ref = reference_image(api, ctx, sc, spp=ref_spp[0], iters=ref_spp[1], mode=mode, depth=depth)
 
-    def run(alloc_after, aware=True):
-        s = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget())
+    def run(alloc_after, aware=True, per_length=False):
+        s = api.Scene(ctx, sc, mode=mode, max_depth=depth, max_cells=cells_budget(),
+                      lp_lengths=per_length)
         acc = np.zeros_like(ref)
         spp_tot = rays = 0
         torch.cuda.synchronize()
@@ -202,6 +207,13 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
                     "relmse_ears": e_e, "seconds_ears": t_e, "rays_ears": r_e,
                     "rays_mars_vs_ears": r_m / r_e - 1.0,
                     "ray_efficiency_gain_vs_ears": (e_e * r_e) / (e_m * r_m)})
+    if lp_lengths:
+        for aw, tag in ((True, "per_length"), (False, "per_length_budget_unaware")):
+            e_l, t_l, _, r_l = run(api.ALLOC_MARS, aware=aw, per_length=True)
+            out.update({tag: 1.0 / (e_l * t_l), f"relmse_{tag}": e_l, f"seconds_{tag}": t_l,
+                        f"rays_{tag}": r_l})
+        out["gain_per_length_vs_one_budget"] = (e_m * t_m) / (out["relmse_per_length"] *
+                                                             out["seconds_per_length"])
     if unaware:
         e_u, t_u, _, r_u = run(api.ALLOC_MARS, aware=False)
         out.update({"mars_budget_unaware": 1.0 / (e_u * t_u),
@@ -245,6 +257,32 @@ def run_ears(args, api, torch):
                               "note": "10 production scenes, 5 min equal time, CPU (Mitsuba); "
                                       "the guided comparison there also differs in the guiding "
                                       "method (gradient-descent mixtures)"}}
+
+
+def run_lp_lengths(args, api, torch):
+    """Separate light-path budgets per light-vertex index (y_1, y_2, y_3+;
+    the variant Sec. 5 leaves to future work) against one light-path budget,
+    classic RR beside them, by the efficiency protocol on the bidirectional
+    1280x720 interior (7 iterations of 1..64 spp against 1024 spp), with
+    the budget-aware and the budget-unaware balance heuristic.  value =
+    per-length MARS's 1/(relMSE s) over one-budget MARS's."""
+    import scenegen
+    ctx = api.Context(0)
+    scb = scenegen.make_interior(seed=1)
+    print("[bench] lp_lengths: bdpt", file=sys.stderr, flush=True)
+    b = efficiency_leg(api, ctx, scb, torch, n_iter=7, mode=api.MODE_BDPT, depth=12,
+                       ref_spp=(16, 64), unaware=True, lp_lengths=True)
+    return {"metric": "efficiency 1/(relMSE*s): per-length light-path budgets vs one budget "
+                      "(MARS, bidirectional)",
+            "value": b["gain_per_length_vs_one_budget"], "unit": "ratio", "n_gpus": 1,
+            "steps": b["iterations"], "warmup": 3,
+            "ms_per_step": b["seconds_per_length"] * 1e3 / b["iterations"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "lp_lengths_bdpt720", "width": scb["width"],
+                       "height": scb["height"], "triangles": int(scb["V"].shape[0]),
+                       "max_depth": 12, "classes": ["y_1", "y_2", "y_3+"]},
+            "bdpt": b}
 
 
 def run_bdpt(args, api, torch):
@@ -956,6 +994,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="learned",
                     choices=["learned", "mlp", "guided", "batch", "bdpt", "ears", "convergence",
+                             "lp_lengths",
                              "rounding"],
                     help="learned (default; mlp is the same): 1920x1080 bidirectional, learned "
                          "cache vs octree; guided: the 512x512 guided-PT workload; batch: 32 "
@@ -985,6 +1024,7 @@ def main():
         torch.cuda.synchronize()
         del a, bcopy
     run = {"learned": run_learned, "mlp": run_learned, "guided": run_guided, "batch": run_batch,
+           "lp_lengths": run_lp_lengths,
            "bdpt": run_bdpt, "ears": run_ears, "convergence": run_convergence,
            "rounding": run_rounding}[args.workload]
     out = run(args, api, torch)
