@@ -1,9 +1,11 @@
 """Separate light-path budgets per light-vertex index (y_1, y_2, y_3+) in the
 bidirectional HIP path, through the C ABI, against the oracle: a schedule of
 classic and MARS iterations with every vertex's five counts, rounded counts
-and radiance, the cells and the per-class cells after every update; the
-single-budget path unchanged; and the argument checks.  Bars as in
-test_gpu_parity.py."""
+and radiance, the cells and the per-class cells after every update; random
+written class factors; the argument checks; checkpoint resume and batched
+iterations (graph and stream pool) against per-scene calls, bit for bit but
+for the order of binary64 atomic sums.
+Bars as in test_gpu_parity.py."""
 import numpy as np
 import pytest
 
@@ -128,3 +130,57 @@ def test_lp_lengths_argument_checks(ctx):
     with pytest.raises(api.MarsError):
         one.cells_x()
     one.release()
+
+
+def test_lp_lengths_checkpoint_resume_identical(ctx, tmp_path):
+    """The class factors travel with the checkpoint: a resumed scene renders
+    the next MARS iteration bit for bit like the uninterrupted one."""
+    from paper_2410_20429_amd import api
+    sc = scenegen.make_cornell(32, 32)
+    a = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=5, lp_lengths=True)
+    b = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=5, lp_lengths=True)
+    for it in range(4):
+        p = api.iter_params(iteration=it, spp=2, stat_clamp=0.0,
+                            alloc=api.ALLOC_CLASSIC if it == 0 else api.ALLOC_MARS)
+        a.render_iteration(p)
+        a.update(p)
+    assert np.any(a.cells_x()["factors"] >= 0)
+    path = tmp_path / "ck_lp.bin"
+    a.checkpoint_save(path)
+    b.checkpoint_load(path)
+    assert np.array_equal(a.cells_x()["factors"].view(np.uint32),
+                          b.cells_x()["factors"].view(np.uint32))
+    p = api.iter_params(iteration=4, spp=2, alloc=api.ALLOC_MARS, stat_clamp=0.0)
+    a.render_iteration(p)
+    b.render_iteration(p)
+    assert np.array_equal(a.sample_radiance().view(np.uint32), b.sample_radiance().view(np.uint32))
+    a.release()
+    b.release()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_lp_lengths_batch_equals_eager(ctx, graph):
+    """Per-length scenes in a batch (captured graphs or the stream pool)
+    equal their per-scene twins bit for bit after every iteration."""
+    from paper_2410_20429_amd import api
+    scenes = [scenegen.make_cornell(20, 18), scenegen.make_interior(seed=4, n_pieces=30, tess=1,
+                                                                    width=24, height=16)]
+    G = [api.Scene(ctx, s, mode=api.MODE_BDPT, max_depth=6, lp_lengths=True) for s in scenes]
+    E = [api.Scene(ctx, s, mode=api.MODE_BDPT, max_depth=6, lp_lengths=True) for s in scenes]
+    for it in range(4):
+        say("per-length batch iteration", it, "graph", graph)
+        p = api.iter_params(iteration=it, spp=2, stat_clamp=0.0,
+                            alloc=api.ALLOC_CLASSIC if it < 2 else api.ALLOC_MARS)
+        api.iterate_batch(G, p, update=True, graph=graph)
+        for g, e in zip(G, E):
+            e.render_iteration(p)
+            e.update(p)
+            assert np.array_equal(g.sample_radiance().view(np.uint32),
+                                  e.sample_radiance().view(np.uint32))
+            assert np.array_equal(g.nodes(), e.nodes())
+            xg, xe = g.cells_x(), e.cells_x()
+            assert np.array_equal(xg["factors"].view(np.uint32), xe["factors"].view(np.uint32))
+            # binary64 atomics add in either order
+            assert np.allclose(xg["acc"], xe["acc"], rtol=1e-12, atol=0)
+    for s in G + E:
+        s.release()
