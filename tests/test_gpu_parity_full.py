@@ -4,10 +4,11 @@
     schedule of 3 classic and 3 MARS iterations at 1 spp over every pixel,
     the octree, visits, accumulators, factors and directional distributions
     after every update and the radiance of every camera sample;
-  - bidirectional 1280 x 720 interior (1.04M triangles) and the learned-cache
-    workload's 1920 x 1080 interior (2.08M triangles), max path length 12:
-    the octree grown by both sides over two classic iterations over every
-    pixel, then a MARS iteration on it, compared on sampled pixels;
+  - bidirectional 1280 x 720 interior (1.04M triangles; with one light-path
+    budget and with per-length budgets) and the learned-cache workload's
+    1920 x 1080 interior (2.08M triangles), max path length 12: the octree
+    grown by both sides over two classic iterations over every pixel, then a
+    MARS iteration on it, compared on sampled pixels;
   - the Cornell box's MARS schedule: its image mean within 3 sigma of a
     65,536 spp render of the oracle (tests/golden/cornell64_d5_mean.json).
 Bars as in test_gpu_parity.py."""
@@ -103,13 +104,14 @@ def test_guided_full_schedule(ctx):
     g.release()
 
 
-def _grown_then_sampled(ctx, sc, n_pix, seed):
+def _grown_then_sampled(ctx, sc, n_pix, seed, lp_lengths=False):
     """Two classic iterations over every pixel on both sides (the octree and
     the factors grow from their statistics), then a MARS iteration compared
-    on n_pix sampled pixels."""
+    on n_pix sampled pixels (with per-length light-path budgets: the class
+    cells too)."""
     from paper_2410_20429_amd import api
-    g = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12)
-    o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=12)
+    g = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=12, lp_lengths=lp_lengths)
+    o = orc.Oracle(sc, mode=orc.MODE_BDPT, max_depth=12, lp_classes=3 if lp_lengths else 1)
     for it in range(2):
         pg, po = _params(iteration=it, spp=1, stat_clamp=0.0)
         say("grow octree, classic iteration", it)
@@ -120,6 +122,10 @@ def _grown_then_sampled(ctx, sc, n_pix, seed):
         ug, uo = g.update(pg), o.update(po)
         assert abs(ug.V_I - uo.V_I) <= 1e-9 * uo.V_I
         _cmp_cache(g, o)
+        if lp_lengths:
+            xg, xo = g.cells_x(), o.cells_x()
+            assert np.allclose(xg["acc"], xo["acc"], rtol=1e-9, atol=1e-12)
+            assert np.allclose(xg["factors"], xo["factors"], rtol=1e-6, atol=0)
     assert g.ncells >= 64
     rng = np.random.default_rng(seed)
     pix = rng.choice(sc["width"] * sc["height"], n_pix, replace=False)
@@ -131,8 +137,14 @@ def _grown_then_sampled(ctx, sc, n_pix, seed):
     _cmp_radiance(g.sample_radiance()[pix], o.sample_radiance()[pix], "MARS iteration")
     dg = g.debug_vertices()
     dg = dg[np.isin(dg["root"], pix)]
-    _cmp_vertices(dg, o.debug_vertices())
+    do = o.debug_vertices()
+    _cmp_vertices(dg, do)
     assert np.any(dg["gamma"][:, 2] > 1)  # splitting of light-path samples happened
+    if lp_lengths:
+        kg = np.sort(dg, order=["root", "depth", "stream_lo", "stream_hi"])
+        ko = np.sort(do, order=["root", "depth", "stream_lo", "stream_hi"])
+        assert np.array_equal(kg["gamma_x"], ko["gamma_x"])
+        assert np.array_equal(kg["beta_x"].view(np.uint32), ko["beta_x"].view(np.uint32))
     g.release()
 
 
@@ -140,6 +152,12 @@ def test_bdpt_grown_octree_sampled(ctx):
     sc = scenegen.make_interior(seed=1)
     say("bidirectional interior", sc["width"], "x", sc["height"], sc["V"].shape[0], "tris")
     _grown_then_sampled(ctx, sc, 1024, 29)
+
+
+def test_bdpt_lp_lengths_grown_octree_sampled(ctx):
+    sc = scenegen.make_interior(seed=1)
+    say("bidirectional interior, per-length light paths", sc["width"], "x", sc["height"])
+    _grown_then_sampled(ctx, sc, 512, 37, lp_lengths=True)
 
 
 def test_learned_scene_grown_octree_sampled(ctx):
