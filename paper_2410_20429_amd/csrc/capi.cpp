@@ -309,7 +309,8 @@ void ensure_roots(Scene* s, size_t roots) {
   if (s->roots_cap) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     for (void* p : {(void*)s->img.Ls, (void*)s->img.beta1, (void*)s->lt.V0, (void*)s->lt.V1,
-                    (void*)s->lt.V2, (void*)s->lt.Y0, (void*)s->lt.len, (void*)s->lt.y})
+                    (void*)s->lt.V2, (void*)s->lt.V3, (void*)s->lt.Y0, (void*)s->lt.len,
+                    (void*)s->lt.y})
       sfree(s, p);
   }
   s->img.Ls = salloc<float>(s, roots * 3);
@@ -319,6 +320,7 @@ void ensure_roots(Scene* s, size_t roots) {
     s->lt.V0 = salloc<float4>(s, roots * lm);
     s->lt.V1 = salloc<float4>(s, roots * lm);
     s->lt.V2 = salloc<float4>(s, roots * lm);
+    s->lt.V3 = salloc<float4>(s, roots * lm);
     s->lt.Y0 = salloc<float4>(s, roots);
     s->lt.len = salloc<uint2>(s, roots);
     // learned cache: network outputs at the light vertices (MIS weights)
@@ -392,6 +394,7 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
       timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st); });
     }
   }
+  timed(c, KID_LIGHT, [&] { k_light_walk(s->sd, s->lt, (uint32_t)roots, st); });
   Counters* pc = (Counters*)c->pinned;
   d2h(pc, s->cnt, sizeof(Counters), st);
   HIPCHK(hipStreamSynchronize(st));
@@ -938,6 +941,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
         k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st);
       }
     }
+    k_light_walk(s->sd, s->lt, (uint32_t)roots, st);
   }
   const size_t tile = std::max<size_t>(1, std::min<size_t>(s->tile_roots, s->cap));
   for (size_t r0 = 0; r0 < roots; r0 += tile) {

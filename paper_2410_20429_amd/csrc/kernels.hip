@@ -849,9 +849,10 @@ __host__ __device__ inline void ears_ratios(int mode, double r[3]) {
   else if (mode == 2) { r[0] = 1.0; r[1] = 1.0; r[2] = 1.0; }
   else { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; }
 }
+// (mask: the techniques whose counts are wanted; the others are left as they are)
 __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c, const IterDev& it,
                                           uint32_t cell, f3 T, const float* It, int depth,
-                                          float beta[3]) {
+                                          float beta[3], uint32_t mask = 7u) {
   const float q = (depth >= it.rr_start) ? fminf(1.0f, fmaxf(fmaxf(T.x, T.y), T.z)) : 1.0f;
   float cb[3];
   if (sc.mode == 1) { cb[0] = q * 0.5f; cb[1] = 1.0f; cb[2] = q * 0.5f; }
@@ -876,11 +877,12 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-      beta[t] = !en[t] ? 0.0f : (aRR[0] < 0.0f ? cb[t] : (float)r[t] * lam);
+      if ((mask >> t) & 1u) beta[t] = !en[t] ? 0.0f : (aRR[0] < 0.0f ? cb[t] : (float)r[t] * lam);
     return;
   }
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
+    if (!((mask >> t) & 1u)) continue;
     if (!en[t]) { beta[t] = 0.0f; continue; }
     if (it.alloc == 0) { beta[t] = cb[t]; continue; }
     float b;
@@ -914,10 +916,12 @@ __device__ __forceinline__ void counts_at(const SceneDev& sc, const CacheDev& c,
 // fixed point of Sec. 3.1 with the class's own factors and the same colour
 // rule and clamp)
 __device__ __forceinline__ void counts_at_x(const CacheDev& c, const IterDev& it, uint32_t cell,
-                                            f3 T, const float* It, float bx[2]) {
+                                            f3 T, const float* It, float bx[2],
+                                            uint32_t mask = 3u) {
   const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
 #pragma unroll
   for (int x = 0; x < 2; ++x) {
+    if (!((mask >> x) & 1u)) continue;
     if (it.alloc == 0) { bx[x] = 1.0f; continue; }
     float b;
     if (it.alloc == 2) {
@@ -959,12 +963,12 @@ __device__ __forceinline__ float lp_class_count(const SceneDev& sc, float b2, fl
 // (not turned toward the incoming ray), so that the same counts can be
 // evaluated at a light vertex for the MIS weights of bidirectional paths.
 __device__ __forceinline__ void mlp_apply(const IterDev& it, f3 T, const float* It, const float* y,
-                                          float beta[3]) {
+                                          float beta[3], uint32_t mask = 7u) {
   const float z0 = T.x / It[0], z1 = T.y / It[1], z2 = T.z / It[2];
   const float sm = sqrtf(((z0 * z0 + z1 * z1) + z2 * z2) * (1.0f / 3.0f));
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
-    if (!(beta[t] > 0.0f)) continue;
+    if (!((mask >> t) & 1u) || !(beta[t] > 0.0f)) continue;
     const float b = sqrtf(beta[t] * (sm * expf(y[t])));
     if (isfinite(b)) beta[t] = fminf(fmaxf(b, it.clamp_lo), it.clamp_hi);
   }
@@ -1806,39 +1810,19 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
   }
 }
 
-// The light side of a connection's path, read where it is used: vertex
-// idx = 0 .. m-1 of the path beyond the camera vertex (idx 0 next to it),
-// the emitter point last.  For a light-path connection to y_i these are
-// y_i, y_{i-1}, .., y_1, y_0 (PathSide, read from the light-vertex store on
-// demand); for NEE the emitter point alone (NeeSide).  No per-thread array
-// holds the path, so the weight's walk needs no private memory.
+// The emitter point of a NEE sample: the light side of its path, for the
+// weight's walk (one vertex).
 struct NeeSide {
   PV y;  // the emitter point
   __device__ __forceinline__ PV at(int) const { return y; }
   __device__ __forceinline__ uint32_t cell(int) const { return kNoCell; }
 };
-struct PathSide {
-  const float4* V0;         // light vertices: position, primitive
-  const float4* V2;         // light vertices: .z octree cell
-  const float4* Y0;         // emitter points: position, primitive
-  const float4* tri_ng;     // per primitive: geometric normal, emitter pdf
-  const uint32_t* tri_mat;  // per primitive: material
-  uint32_t base;            // first light vertex of the subpath, lpi * lmax
-  uint32_t lpi;             // light subpath
-  int i;                    // light vertex index connected to
-  __device__ __forceinline__ PV vertex(float4 v) const {
-    const uint32_t prim = ubits(v.w);
-    const float4 ng = tri_ng[prim];
-    return PV{xyz(v), xyz(ng), tri_mat[prim], ng.w};
-  }
-  __device__ __forceinline__ PV at(int idx) const {
-    return vertex(idx == i ? Y0[lpi] : V0[base + (uint32_t)(i - 1 - idx)]);
-  }
-  // octree cell of light vertex idx < i, found once when it was stored
-  __device__ __forceinline__ uint32_t cell(int idx) const {
-    return ubits(V2[base + (uint32_t)(i - 1 - idx)].z);
-  }
-};
+// a light vertex (or emitter point) as stored: position, primitive (bits)
+__device__ __forceinline__ PV light_vertex(const SceneDev& sc, float4 v) {
+  const uint32_t prim = ubits(v.w);
+  const float4 ng = sc.tri_ng[prim];
+  return PV{xyz(v), xyz(ng), sc.tri_mat[prim], ng.w};
+}
 
 // pR(i) of the path, from the window z_i (C), z_{i+1} (D), z_{i+2} (E): the
 // density of reaching z_i from z_{i+1} (whose outgoing direction is towards
@@ -1862,9 +1846,97 @@ __device__ __forceinline__ float path_pR(const SceneDev& sc, int i, int k, const
   return (p * fabsf(dot3(C.ng, wi))) / d2;
 }
 
+// The terms of a connection's weight that involve light vertices only, once
+// per light vertex after the subpaths are traced (Sec. 5: the full-path
+// weight sums over every strategy of the connected path; along its light
+// side the densities and throughput factors below do not depend on the
+// camera vertex).  For y_i of subpath r (y_0 its emitter point):
+//   V2.w: the density of reaching y_i from y_{i-1} (incoming from y_{i-2}),
+//         as area density at y_i; for y_1 the emission density of y_0;
+//   V3:   for i < length, the BSDF at y_i towards y_{i-1} for a path arriving
+//         from y_{i+1}: f cos / p per channel (-1 if p = 0) and the density
+//         of reaching y_{i-1} (area density there).
+// Both are evaluated by the same operations as the weight's walk would,
+// so the weights do not change.
+__global__ __launch_bounds__(256) void light_walk_kernel(SceneDev sc, LightDev lt, uint32_t roots) {
+  const uint32_t lm = (uint32_t)lt.lmax;
+  const uint32_t total = roots * lm;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const uint32_t r = e / lm;
+    const int i = (int)(e - r * lm) + 1;
+    const int len = (int)lt.len[r].x;
+    if (i > len) continue;
+    const PV C = light_vertex(sc, lt.V0[e]);
+    const PV D = light_vertex(sc, i >= 2 ? lt.V0[e - 1] : lt.Y0[r]);
+    float d2;
+    float pR;
+    if (i == 1) {
+      const f3 w = dir_between(D.P, C.P, &d2);
+      const float cl = dot3(D.ng, w);
+      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+      pR = (pe * fabsf(dot3(C.ng, w))) / d2;
+    } else {
+      const PV E = light_vertex(sc, i >= 3 ? lt.V0[e - 2] : lt.Y0[r]);
+      const f3 wo = dir_between(D.P, E.P, &d2);
+      const f3 wi = dir_between(D.P, C.P, &d2);
+      f3 fc;
+      float p;
+      eval_facing(load_mat(sc.mats + 8 * (size_t)D.mat), D.ng, wo, wi, &fc, &p);
+      pR = (p * fabsf(dot3(C.ng, wi))) / d2;
+    }
+    const float4 v2 = lt.V2[e];
+    lt.V2[e] = make_float4(v2.x, v2.y, v2.z, pR);
+    if (i < len) {
+      const PV A = light_vertex(sc, lt.V0[e + 1]);
+      const f3 wo = dir_between(C.P, A.P, &d2);
+      const f3 wi = dir_between(C.P, D.P, &d2);
+      f3 fc;
+      float p;
+      eval_facing(load_mat(sc.mats + 8 * (size_t)C.mat), C.ng, wo, wi, &fc, &p);
+      const float pF = (p * fabsf(dot3(D.ng, wi))) / d2;
+      lt.V3[e] = p > 0.0f ? make_float4(fc.x / p, fc.y / p, fc.z / p, pF)
+                          : make_float4(-1.0f, -1.0f, -1.0f, pF);
+    }
+  }
+}
+void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStream_t s) {
+  const uint32_t total = roots * (uint32_t)lt.lmax;
+  if (!total) return;
+  light_walk_kernel<<<std::min<uint32_t>((total + 255) / 256, 8192), 256, 0, s>>>(sc, lt, roots);
+}
+
+// the strategies tt = d .. 2 of a connection or NEE sample at the camera
+// vertex j of depth d, walking up the parent chain: pF of vertex tt, pR of
+// vertex tt + 2 (tt <= d - 2) from the records, the counts of vertex tt - 1;
+// pR_d and pR_dm1 involve the light side and are passed in
+__device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const QueuesDev& q,
+                                                 const IterDev& it, int d, int k, uint32_t j,
+                                                 const VRec& rd, float pR_d, float pR_dm1,
+                                                 float tft, float sum) {
+  float rp = 1.0f, rb = 1.0f;
+  VRec cur = rd;
+  uint32_t ecur = j;
+  float prg1 = 0.0f, prg2 = 0.0f;
+  for (int tt = d; tt >= 2; --tt) {
+    const float pRt = tt == d ? pR_d : (tt == d - 1 ? pR_dm1 : prg2);
+    const uint32_t epar = ubits(q.S0[(size_t)tt * q.cap + ecur].w);
+    const VRec par = load_rec(q, tt - 1, epar);
+    rp = rp * (pRt / cur.pF);
+    rb = rb * mis_count(it, par.b0);
+    // strategy tt connects z_{tt-1} (par) to the light vertex y_{k-tt}
+    sum = sum + rp * (mis_count(it, lp_class_count(sc, par.b2, par.b3, par.b4, k - tt)) / (rb * tft));
+    prg2 = prg1;
+    prg1 = cur.pRg;
+    cur = par;
+    ecur = epar;
+  }
+  return sum;
+}
+
 // weight of strategy t = d + 1 for the path z_0..z_d (camera vertex j of
 // depth d: zc, its parent zp, the camera for d = 1) continued by the
-// light-side vertices Y.at(0..m-1) = z_{d+1}..z_k (z_k on the emitter)
+// light-side vertices Y.at(0..m-1) = z_{d+1}..z_k (z_k on the emitter); NEE
+// samples use it with m = 1
 // ly: in learned-cache iterations, the network outputs of the light subpath's
 // vertices (light vertex i at ly[4 (i - 1)]), z_{d+1} being light vertex li0
 // The walk keeps a window of five consecutive path vertices in registers.
@@ -1932,26 +2004,100 @@ __device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const Qu
     D = E;
     if (i + 3 <= k) E = Y.at(i + 2 - d);
   }
-  // camera side, walking up the parent chain: pF of vertex tt, pR of vertex
-  // tt + 2 (tt <= d - 2), counts of vertex tt - 1
-  rp = 1.0f;
-  rb = 1.0f;
-  VRec cur = rd;
-  uint32_t ecur = j;
-  float prg1 = 0.0f, prg2 = 0.0f;
-  for (int tt = d; tt >= 2; --tt) {
-    const float pRt = tt == d ? pR_d : (tt == d - 1 ? pR_dm1 : prg2);
-    const uint32_t epar = ubits(q.S0[(size_t)tt * q.cap + ecur].w);
-    const VRec par = load_rec(q, tt - 1, epar);
-    rp = rp * (pRt / cur.pF);
-    rb = rb * mis_count(it, par.b0);
-    // strategy tt connects z_{tt-1} (par) to the light vertex y_{k-tt}
-    sum = sum + rp * (mis_count(it, lp_class_count(sc, par.b2, par.b3, par.b4, k - tt)) / (rb * tft));
-    prg2 = prg1;
-    prg1 = cur.pRg;
-    cur = par;
-    ecur = epar;
+  sum = camera_side_sum(sc, q, it, d, k, j, rd, pR_d, pR_dm1, tft, sum);
+  if (!(sum < INFINITY)) return 0.0f;
+  return 1.0f / sum;
+}
+
+// weight of the light-path connection of camera vertex j (depth d: zc, its
+// parent zp, the camera for d = 1) to the light vertex y_i (yi) of subpath
+// r, strategy t = d + 1 of the path z_0..z_k, k = d + i + 1, whose light side
+// z_{d+1}..z_k is y_i, .., y_1, y_0.  The same sums as bdpt_weight_rec in the
+// same order; the terms that involve light vertices only are read from the
+// light walk (V2.w, V3) instead of evaluated.  ly: in learned-cache
+// iterations, the network outputs at the subpath's vertices (y_h at
+// ly[4 (h - 1)]).
+__device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
+                                const LightDev& lt, const IterDev& it, int d, uint32_t j,
+                                const PV& zc, const PV& zp, const PV& yi, uint32_t r, int i,
+                                const float* It, const float* ly) {
+  const int k = d + i + 1, t = d + 1;
+  const uint32_t base = r * (uint32_t)lt.lmax;  // y_h at base + h - 1
+  const PV y0 = light_vertex(sc, lt.Y0[r]);
+  const PV yn = i >= 2 ? light_vertex(sc, lt.V0[base + (uint32_t)(i - 2)]) : y0;  // y_{i-1}
+  // pR of the camera vertex and of its parent, for the camera-side sums
+  const float pR_d = d >= 2 ? path_pR(sc, d, k, zc, yi, yn) : 0.0f;
+  const float pR_dm1 = d >= 3 ? path_pR(sc, d - 1, k, zp, zc, yi) : 0.0f;
+  // counts at z_d (its record); t's own technique count
+  const VRec rd = load_rec(q, d, j);
+  f3 T = rd.T;
+  float b[3] = {rd.b0, rd.b1, rd.b2};
+  float bx[2] = {rd.b3, rd.b4};
+  float nB_prev = mis_count(it, b[0]);
+  const float tft = mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], k - t));
+  if (!(tft > 0.0f)) return 0.0f;
+  // the strategies u + 1 = t + 1 .. k + 1 along the light side, z_u = y_h:
+  // pF(u) from the BSDF at z_{u-1} (evaluated for u <= d + 2, whose window
+  // holds a camera vertex; read from V3 of y_{h+1} beyond), pR(u) of y_h
+  // from V2.w (y_0: its emitter pdf), the counts at y_h along the
+  // camera-prefix throughput continued through the light side
+  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
+  for (int u = d + 1; u <= k; ++u) {
+    const int h = k - u;
+    f3 fcp;
+    bool pos;
+    float pFu;
+    if (u <= d + 2) {
+      const PV& B = u == d + 1 ? zc : yi;
+      const PV& A = u == d + 1 ? zp : zc;
+      const PV& C = u == d + 1 ? yi : yn;
+      float d2;
+      const f3 wo = dir_between(B.P, A.P, &d2);
+      const f3 wi = dir_between(B.P, C.P, &d2);
+      f3 fc;
+      float p;
+      eval_facing(load_mat(sc.mats + 8 * (size_t)B.mat), B.ng, wo, wi, &fc, &p);
+      pFu = (p * fabsf(dot3(C.ng, wi))) / d2;
+      pos = p > 0.0f;
+      fcp = pos ? mk3(fc.x / p, fc.y / p, fc.z / p) : mk3(0.0f, 0.0f, 0.0f);
+    } else {
+      const float4 w3 = lt.V3[base + (uint32_t)h];  // of y_{h+1}
+      fcp = xyz(w3);
+      pFu = w3.w;
+      pos = !(w3.x < 0.0f);
+    }
+    float tf = 1.0f;  // strategy k + 1
+    float nB_u = 0.0f;
+    float pRu;
+    if (u < k) {
+      const float4 v2 = lt.V2[base + (uint32_t)(h - 1)];
+      pRu = v2.w;
+      if (pos && b[0] > 0.0f)
+        T = mk3(T.x * ((fcp.x * 1.0f) / b[0]), T.y * ((fcp.y * 1.0f) / b[0]),
+                T.z * ((fcp.z * 1.0f) / b[0]));
+      else
+        T = mk3(0.0f, 0.0f, 0.0f);
+      const uint32_t cell = ubits(v2.z);
+      // only the counts this walk reads: the BSDF count and the count of
+      // strategy u + 1's technique (NEE, or the class of y_{h-1})
+      const bool cls_x = sc.lp_classes == 3 && h - 1 >= 2;
+      const uint32_t mask = 1u | (u == k - 1 ? 2u : (cls_x ? 0u : 4u));
+      counts_at(sc, c, it, cell, T, It, u, b, mask);
+      if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (h - 1), b, mask);
+      if (cls_x && u != k - 1) counts_at_x(c, it, cell, T, It, bx, h - 1 == 2 ? 1u : 2u);
+      nB_u = mis_count(it, b[0]);
+      // strategy u + 1 connects z_u to the light vertex y_{h-1}
+      tf = u == k - 1 ? mis_count(it, b[1])
+                      : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], h - 1));
+    } else {
+      pRu = y0.lpdf;
+    }
+    rp = rp * (pFu / pRu);
+    rb = rb * nB_prev;
+    sum = sum + (rp * rb) * (tf / tft);
+    nB_prev = nB_u;
   }
+  sum = camera_side_sum(sc, q, it, d, k, j, rd, pR_d, pR_dm1, tft, sum);
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
 }
@@ -2320,10 +2466,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
           (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
-        const PathSide Y{lt.V0, lt.V2, lt.Y0, sc.tri_ng, sc.tri_mat,
-                         lpi * (uint32_t)lt.lmax, lpi, i};
         const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
-        const float wc = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, i + 1, It, ly, i);
+        const float wc = bdpt_weight_lp(sc, c, q, lt, it, d, j, zc, zp, yv, lpi, i, It, ly);
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;

@@ -109,7 +109,12 @@ constexpr int kTileWords = 2 * (kMaxDepth + 2) + 1;
 struct LightDev {
   float4* V0;     // [root][lmax]: position y_i, primitive (bits)
   float4* V1;     // [root][lmax]: direction towards y_{i-1}, alpha.r
-  float4* V2;     // [root][lmax]: alpha.g, alpha.b, octree cell of y_i (bits), -
+  float4* V2;     // [root][lmax]: alpha.g, alpha.b, octree cell of y_i (bits), and the
+                  // area density of reaching y_i from y_{i-1} (y_0: emission density)
+  // [root][lmax]: the BSDF at y_i towards y_{i-1} when the path arrives from
+  // y_{i+1}: f cos / p per channel (-1 where p = 0) and the area density at
+  // y_{i-1}; set for i < the subpath's length
+  float4* V3;
   float4* Y0;     // [root]: point on the emitter, emitter primitive (bits)
   uint2* len;     // [root]: vertices stored, rays traced
   float* y;       // [root][lmax][4]: learned-cache outputs at the light vertices (null if none)
@@ -211,6 +216,7 @@ void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, C
                    const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s);
 void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                    Counters* cnt, const IterDev& it, int bounce, int grid, hipStream_t s);
+void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStream_t s);
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s);
