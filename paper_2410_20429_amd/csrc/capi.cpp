@@ -1415,6 +1415,8 @@ mars_status mars_create(const mars_ctx_desc* desc, mars_ctx** out) {
                          hipGetErrorString(e);
     }
   }
+  // launch grids sized by occupancy, queried now rather than under a capture
+  k_init_launch_grids();
   c->batch_streams = kBatchStreams;
   if (const char* e = std::getenv("MARS_BATCH_STREAMS")) {
     const int k = std::atoi(e);

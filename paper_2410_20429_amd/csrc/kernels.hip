@@ -15,6 +15,10 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "device_math.hpp"
 #include "mars_internal.h"
 
@@ -39,14 +43,35 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // shading kernels: 1024-thread groups (one queue allocation per group); the
-// connection kernel (statistics atomics only, 78 VGPRs): 512-thread groups,
-// three per CU
+// connection kernel (statistics atomics only): 512-thread groups
 constexpr int kShadeBlock = 1024, kConnectBlock = 512;
+
+// Launch grid of a kernel whose workgroups loop over equal shares of the
+// work: exactly the groups the device holds at once (CUs x resident groups
+// per CU at the kernel's register and LDS use), so that no group starts
+// after the first ones finish and leaves the CUs half empty for its share.
+template <class K>
+int resident_grid(K* kernel, int block) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const std::pair<const void*, int> key{(const void*)kernel, dev};
+  std::lock_guard<std::mutex> lk(mu);
+  auto f = cache.find(key);
+  if (f != cache.end()) return f->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return cache[key] = per_cu * cus;
+}
 // unidirectional shading: 256-thread groups held to 80 VGPRs (6 waves per
 // SIMD) to hide its dependent loads (octree walk, distribution search)
 constexpr int kShadePtBlock = 256;
-// launch grid for the shading kernels: the thread count of `grid` groups of 256
-inline int shade_grid(int grid) { return grid * 256 / kShadeBlock > 0 ? grid * 256 / kShadeBlock : 1; }
 
 // the overflow flag read once per workgroup, so that every thread of the
 // group takes the same exit (the kernels below use workgroup barriers)
@@ -1497,7 +1522,8 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
 }
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
                    const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s) {
-  backprop_pt_kernel<<<grid, 256, 0, s>>>(sc, c, q, cnt, it, img, d);
+  (void)grid;
+  backprop_pt_kernel<<<resident_grid(backprop_pt_kernel, 256), 256, 0, s>>>(sc, c, q, cnt, it, img, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -2491,11 +2517,12 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s) {
-  shade_bdpt_kernel<<<shade_grid(grid), kShadeBlock, 0, s>>>(sc, c, q, lt, cnt, it, img, dbg, dbg_cap,
-                                                               d, npool);
+  (void)grid;
+  shade_bdpt_kernel<<<resident_grid(shade_bdpt_kernel, kShadeBlock), kShadeBlock, 0, s>>>(
+      sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
   if (d < sc.max_depth)
-    connect_bdpt_kernel<<<std::max(1, grid * 3 / 8), kConnectBlock, 0, s>>>(sc, c, q, lt, cnt, it,
-                                                                           img, d);
+    connect_bdpt_kernel<<<resident_grid(connect_bdpt_kernel, kConnectBlock), kConnectBlock, 0, s>>>(
+        sc, c, q, lt, cnt, it, img, d);
 }
 
 // back-propagation for BDPT: NEE, BSDF and LP samples in that order
@@ -2640,13 +2667,24 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
     global_add_stats(c, A.key[k], vals);
   }
 }
+void k_init_launch_grids() {
+  (void)resident_grid(shade_bdpt_kernel, kShadeBlock);
+  (void)resident_grid(connect_bdpt_kernel, kConnectBlock);
+  (void)resident_grid(backprop_bdpt_kernel<true>, 256);
+  (void)resident_grid(backprop_bdpt_kernel<false>, 256);
+  (void)resident_grid(backprop_pt_kernel, 256);
+}
+
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s) {
+  (void)grid;
   if (sc.lp_classes == 3)
-    backprop_bdpt_kernel<true><<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
+    backprop_bdpt_kernel<true><<<resident_grid(backprop_bdpt_kernel<true>, 256), 256, 0, s>>>(
+        sc, c, q, lt, cnt, it, img, d, npool);
   else
-    backprop_bdpt_kernel<false><<<grid, 256, 0, s>>>(sc, c, q, lt, cnt, it, img, d, npool);
+    backprop_bdpt_kernel<false><<<resident_grid(backprop_bdpt_kernel<false>, 256), 256, 0, s>>>(
+        sc, c, q, lt, cnt, it, img, d, npool);
 }
 
 // ---------------------------------------------------------------------------
