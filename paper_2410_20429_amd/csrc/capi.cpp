@@ -87,11 +87,11 @@ struct Scene {
 // inverse-variance weighted image)
 enum KernelId {
   KID_RAYGEN, KID_TRACE, KID_SHADE, KID_BACKPROP, KID_PIXEL_SUMS, KID_UPDATE_IMAGE,
-  KID_FIXED_POINT, KID_REFINE, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_BATCH, KID_COUNT
+  KID_FIXED_POINT, KID_REFINE, KID_LIGHT, KID_MLP, KID_MLP_TRAIN, KID_BATCH, KID_CONNECT, KID_COUNT
 };
 const char* kKernelNames[KID_COUNT] = {
     "raygen", "trace", "shade", "backprop", "pixel_sums", "update_image",
-    "fixed_point", "refine", "light", "mlp_infer", "mlp_train", "batch"};
+    "fixed_point", "refine", "light", "mlp_infer", "mlp_train", "batch", "connect"};
 
 struct Profiler {
   uint64_t mask = 0;  // bit k: kernel k is timed
@@ -429,6 +429,10 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
       else
         k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
     });
+    if (bdpt)
+      timed(c, KID_CONNECT, [&] {
+        k_connect_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, st);
+      });
     // shadow rays of depth d with the continuation rays of depth d + 1
     const int dc = d < s->max_depth ? d + 1 : -1;
     timed_ext(c, KID_TRACE, [&](hipEvent_t a, hipEvent_t b) {
@@ -950,11 +954,13 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
     k_raygen(s->sd, s->qd, s->cnt, it, (uint32_t)r0, n, st);
       k_trace_pair(s->sd, s->qd, s->cnt, 1, 0, grid_trace, st, tc);
     for (int d = 1; d <= s->max_depth; ++d) {
-      if (bdpt)
+      if (bdpt) {
         k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, nullptr, 0, d, (uint32_t)roots,
                      grid, st);
-      else
+        k_connect_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, st);
+      } else {
         k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, nullptr, 0, d, grid, st);
+      }
       k_trace_pair(s->sd, s->qd, s->cnt, d < s->max_depth ? d + 1 : -1, d, grid_trace, st, tc);
     }
     for (int d = s->max_depth; d >= 1; --d) {

@@ -42,9 +42,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// shading kernels: 1024-thread groups (one queue allocation per group); the
-// connection kernel (statistics atomics only): 512-thread groups
-constexpr int kShadeBlock = 1024, kConnectBlock = 512;
+// bidirectional vertex and connection kernels: 256-thread groups (one queue
+// allocation per group; a connection group sorts one tile by walk length).
+// A group's barriers wait for its slowest wave, so small groups keep the
+// SIMDs busy: at four waves per SIMD a 1024-thread group held a whole CU.
+constexpr int kShadeBlock = 256, kConnectBlock = 256;
 
 // Launch grid of a kernel whose workgroups loop over equal shares of the
 // work: exactly the groups the device holds at once (CUs x resident groups
@@ -1836,13 +1838,6 @@ __device__ __forceinline__ void bdpt_record(const SceneDev& sc, const CacheDev& 
   }
 }
 
-// The emitter point of a NEE sample: the light side of its path, for the
-// weight's walk (one vertex).
-struct NeeSide {
-  PV y;  // the emitter point
-  __device__ __forceinline__ PV at(int) const { return y; }
-  __device__ __forceinline__ uint32_t cell(int) const { return kNoCell; }
-};
 // a light vertex (or emitter point) as stored: position, primitive (bits)
 __device__ __forceinline__ PV light_vertex(const SceneDev& sc, float4 v) {
   const uint32_t prim = ubits(v.w);
@@ -1937,10 +1932,9 @@ void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStr
 // pR_d and pR_dm1 involve the light side and are passed in
 __device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const QueuesDev& q,
                                                  const IterDev& it, int d, int k, uint32_t j,
-                                                 const VRec& rd, float pR_d, float pR_dm1,
-                                                 float tft, float sum) {
+                                                 float pR_d, float pR_dm1, float tft, float sum) {
   float rp = 1.0f, rb = 1.0f;
-  VRec cur = rd;
+  VRec cur = load_rec(q, d, j);
   uint32_t ecur = j;
   float prg1 = 0.0f, prg2 = 0.0f;
   for (int tt = d; tt >= 2; --tt) {
@@ -1959,78 +1953,31 @@ __device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const Queue
   return sum;
 }
 
-// weight of strategy t = d + 1 for the path z_0..z_d (camera vertex j of
-// depth d: zc, its parent zp, the camera for d = 1) continued by the
-// light-side vertices Y.at(0..m-1) = z_{d+1}..z_k (z_k on the emitter); NEE
-// samples use it with m = 1
-// ly: in learned-cache iterations, the network outputs of the light subpath's
-// vertices (light vertex i at ly[4 (i - 1)]), z_{d+1} being light vertex li0
-// The walk keeps a window of five consecutive path vertices in registers.
-template <class Side>
-__device__ float bdpt_weight_rec(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
-                                 const IterDev& it, int d, uint32_t j, const PV& zc, const PV& zp,
-                                 const Side& Y, int m, const float* It, const float* ly,
-                                 int li0) {
-  const int k = d + m, t = d + 1;
-  // window A..E = z_{i-2} .. z_{i+2} for i = d + 1
-  PV A = zp, B = zc, C = Y.at(0);
-  PV D = m > 1 ? Y.at(1) : PV{}, E = m > 2 ? Y.at(2) : PV{};
-  // pR of the camera vertex and of its parent, for the camera-side sums
-  const float pR_d = d >= 2 ? path_pR(sc, d, k, B, C, D) : 0.0f;
-  const float pR_dm1 = d >= 3 ? path_pR(sc, d - 1, k, A, B, C) : 0.0f;
-  // counts at z_d (its record); t's own technique count
+// weight of the NEE sample of camera vertex j (depth d: zc, its parent zp,
+// the camera for d = 1) on the emitter point y: strategy t = d + 1 of the
+// path z_0..z_k, k = d + 1 (the same sums as bdpt_weight for t = k)
+__device__ float bdpt_weight_nee(const SceneDev& sc, const QueuesDev& q, const IterDev& it, int d,
+                                 uint32_t j, const PV& zc, const PV& zp, const PV& y) {
+  const int k = d + 1;
+  // pR of the camera vertex (y's emission density) and of its parent
+  const float pR_d = d >= 2 ? path_pR(sc, d, k, zc, y, y) : 0.0f;
+  const float pR_dm1 = d >= 3 ? path_pR(sc, d - 1, k, zp, zc, y) : 0.0f;
+  // the NEE count at z_d (its record)
   const VRec rd = load_rec(q, d, j);
-  f3 T = rd.T;
-  float b[3] = {rd.b0, rd.b1, rd.b2};
-  float bx[2] = {rd.b3, rd.b4};
-  const f3 olo = mk3(sc.oct_lo[0], sc.oct_lo[1], sc.oct_lo[2]);
-  float nB_prev = mis_count(it, b[0]);
-  const float tft = t == k ? mis_count(it, b[1])
-                           : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], k - t));
+  const float tft = mis_count(it, rd.b1);
   if (!(tft > 0.0f)) return 0.0f;
-  // the strategies tt = t + 1 .. k + 1, in that order, walking the light
-  // side one vertex z_i = z_{tt-1} at a time: the BSDF at z_{i-1} gives both
-  // pF(i) and the throughput factor into z_i, and the counts at z_i (a light
-  // vertex in the role of a camera vertex: the count function of the
-  // sampling, along the camera-prefix throughput) give tt's count products
-  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
-  for (int i = d + 1; i <= k; ++i) {
-    float d2;
-    const f3 wo = dir_between(B.P, A.P, &d2);
-    const f3 wi = dir_between(B.P, C.P, &d2);
-    f3 fc;
-    float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)B.mat), B.ng, wo, wi, &fc, &p);
-    const float pFi = (p * fabsf(dot3(C.ng, wi))) / d2;
-    float tf = 1.0f;  // strategy k + 1
-    float nB_i = 0.0f;
-    if (i < k) {
-      if (p > 0.0f && b[0] > 0.0f)
-        T = mk3(T.x * (((fc.x / p) * 1.0f) / b[0]), T.y * (((fc.y / p) * 1.0f) / b[0]),
-                T.z * (((fc.z / p) * 1.0f) / b[0]));
-      else
-        T = mk3(0.0f, 0.0f, 0.0f);
-      const uint32_t cy = Y.cell(i - d - 1);
-      const uint32_t cell = cy != kNoCell ? cy : cell_of(c.nodes, olo, sc.oct_inv, C.P);
-      counts_at(sc, c, it, cell, T, It, i, b);
-      if (ly && mlp_active(c, it)) mlp_apply(it, T, It, ly + 4 * (li0 - (i - d - 1) - 1), b);
-      if (sc.lp_classes == 3) counts_at_x(c, it, cell, T, It, bx);
-      nB_i = mis_count(it, b[0]);
-      // strategy i + 1 connects z_i to the light vertex y_{k-i-1}
-      tf = i == k - 1 ? mis_count(it, b[1])
-                      : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], k - i - 1));
-    }
-    rp = rp * (pFi / path_pR(sc, i, k, C, D, E));
-    rb = rb * nB_prev;
-    sum = sum + (rp * rb) * (tf / tft);
-    nB_prev = nB_i;
-    A = B;
-    B = C;
-    C = D;
-    D = E;
-    if (i + 3 <= k) E = Y.at(i + 2 - d);
-  }
-  sum = camera_side_sum(sc, q, it, d, k, j, rd, pR_d, pR_dm1, tft, sum);
+  // strategy k + 1: the BSDF sample at z_d reaching y
+  float d2;
+  const f3 wo = dir_between(zc.P, zp.P, &d2);
+  const f3 wi = dir_between(zc.P, y.P, &d2);
+  f3 fc;
+  float p;
+  eval_facing(load_mat(sc.mats + 8 * (size_t)zc.mat), zc.ng, wo, wi, &fc, &p);
+  const float pFk = (p * fabsf(dot3(y.ng, wi))) / d2;
+  const float rp = 1.0f * (pFk / y.lpdf);
+  const float rb = 1.0f * mis_count(it, rd.b0);
+  float sum = 1.0f + (rp * rb) * (1.0f / tft);
+  sum = camera_side_sum(sc, q, it, d, k, j, pR_d, pR_dm1, tft, sum);
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
 }
@@ -2068,30 +2015,11 @@ __device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const Que
   // from V2.w (y_0: its emitter pdf), the counts at y_h along the
   // camera-prefix throughput continued through the light side
   float sum = 1.0f, rp = 1.0f, rb = 1.0f;
-  for (int u = d + 1; u <= k; ++u) {
+  const float lpdf0 = y0.lpdf;
+  // one strategy u + 1 past z_u = y_h: pF(u) and the BSDF factor into z_u
+  // (fcp; pos: p > 0), the counts at y_h along the continued throughput
+  auto advance = [&](int u, bool pos, f3 fcp, float pFu) {
     const int h = k - u;
-    f3 fcp;
-    bool pos;
-    float pFu;
-    if (u <= d + 2) {
-      const PV& B = u == d + 1 ? zc : yi;
-      const PV& A = u == d + 1 ? zp : zc;
-      const PV& C = u == d + 1 ? yi : yn;
-      float d2;
-      const f3 wo = dir_between(B.P, A.P, &d2);
-      const f3 wi = dir_between(B.P, C.P, &d2);
-      f3 fc;
-      float p;
-      eval_facing(load_mat(sc.mats + 8 * (size_t)B.mat), B.ng, wo, wi, &fc, &p);
-      pFu = (p * fabsf(dot3(C.ng, wi))) / d2;
-      pos = p > 0.0f;
-      fcp = pos ? mk3(fc.x / p, fc.y / p, fc.z / p) : mk3(0.0f, 0.0f, 0.0f);
-    } else {
-      const float4 w3 = lt.V3[base + (uint32_t)h];  // of y_{h+1}
-      fcp = xyz(w3);
-      pFu = w3.w;
-      pos = !(w3.x < 0.0f);
-    }
     float tf = 1.0f;  // strategy k + 1
     float nB_u = 0.0f;
     float pRu;
@@ -2116,14 +2044,37 @@ __device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const Que
       tf = u == k - 1 ? mis_count(it, b[1])
                       : mis_count(it, lp_class_count(sc, b[2], bx[0], bx[1], h - 1));
     } else {
-      pRu = y0.lpdf;
+      pRu = lpdf0;
     }
     rp = rp * (pFu / pRu);
     rb = rb * nB_prev;
     sum = sum + (rp * rb) * (tf / tft);
     nB_prev = nB_u;
+  };
+  // u = d + 1 and d + 2: the BSDFs at the camera vertex and at y_i, whose
+  // directions involve the camera vertex
+  for (int u = d + 1; u <= d + 2; ++u) {
+    const PV& B = u == d + 1 ? zc : yi;
+    const PV& A = u == d + 1 ? zp : zc;
+    const PV& C = u == d + 1 ? yi : yn;
+    float d2;
+    const f3 wo = dir_between(B.P, A.P, &d2);
+    const f3 wi = dir_between(B.P, C.P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(load_mat(sc.mats + 8 * (size_t)B.mat), B.ng, wo, wi, &fc, &p);
+    const bool pos = p > 0.0f;
+    advance(u, pos, pos ? mk3(fc.x / p, fc.y / p, fc.z / p) : mk3(0.0f, 0.0f, 0.0f),
+            (p * fabsf(dot3(C.ng, wi))) / d2);
   }
-  sum = camera_side_sum(sc, q, it, d, k, j, rd, pR_d, pR_dm1, tft, sum);
+  // u >= d + 3: pF(u) and the factor from V3 of y_{h+1}, loaded a step ahead
+  float4 w3 = d + 3 <= k ? lt.V3[base + (uint32_t)(k - d - 3)] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int u = d + 3; u <= k; ++u) {
+    const float4 w3c = w3;
+    if (u + 1 <= k) w3 = lt.V3[base + (uint32_t)(k - u - 1)];
+    advance(u, !(w3c.x < 0.0f), xyz(w3c), w3c.w);
+  }
+  sum = camera_side_sum(sc, q, it, d, k, j, pR_d, pR_dm1, tft, sum);
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
 }
@@ -2460,17 +2411,16 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float pB;
       eval_bsdf(mat, n_s, wo, w, &fc, &pB);
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
-        const float pN = (lng.w * d2) / cl;
-        const NeeSide Y{PV{y, xyz(lng), sc.tri_mat[li], lng.w}};
-        const float wN = bdpt_weight_rec(sc, c, q, it, d, j, zc, zp, Y, 1, It, nullptr, 0);
-        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
-        sh2 = make_float4((fc.x / pN) * (wN * Le[0]), (fc.y / pN) * (wN * Le[1]),
-                          (fc.z / pN) * (wN * Le[2]), 1.0f);
-        ++my_sh;
-      }
       q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
       q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
+        const float pN = (lng.w * d2) / cl;
+        const f3 fp = mk3(fc.x / pN, fc.y / pN, fc.z / pN);
+        const float wN = bdpt_weight_nee(sc, q, it, d, j, zc, zp, PV{y, xyz(lng), sc.tri_mat[li], lng.w});
+        const float* Le = sc.mats + 8 * (size_t)sc.tri_mat[li] + 5;
+        sh2 = make_float4(fp.x * (wN * Le[0]), fp.y * (wN * Le[1]), fp.z * (wN * Le[2]), 1.0f);
+        ++my_sh;
+      }
       q.SH2[e] = sh2;
     } else {
       const uint32_t lpi = ubits(s0.x);
@@ -2488,25 +2438,28 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       const Mat ym = load_mat(sc.mats + 8 * (size_t)yv.mat);
       const f3 ywo = xyz(y1v);
       eval_facing(ym, yv.ng, ywo, mk3(-w.x, -w.y, -w.z), &fcL, &pl);
-      float4 sh0 = make_float4(ov.x, ov.y, ov.z, 0.0f), sh1 = make_float4(w.x, w.y, w.z, fbits(j));
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if ((fcC.x > 0.0f || fcC.y > 0.0f || fcC.z > 0.0f) &&
           (fcL.x > 0.0f || fcL.y > 0.0f || fcL.z > 0.0f)) {
-        const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
-        const float wc = bdpt_weight_lp(sc, c, q, lt, it, d, j, zc, zp, yv, lpi, i, It, ly);
+        // the shadow ray and the unweighted contribution first, so that
+        // only the contribution stays live across the weight's walk
         const f3 ny = dot3(yv.ng, ywo) > 0.0f ? yv.ng : mk3(-yv.ng.x, -yv.ng.y, -yv.ng.z);
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;
         const f3 sw = dir_between(ov, yo, &sd2);
+        q.SH0[e] = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
+        q.SH1[e] = make_float4(sw.x, sw.y, sw.z, fbits(j));
         const f3 al = mk3(y1v.w, y2v.x, y2v.y);
-        sh0 = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
-        sh1 = make_float4(sw.x, sw.y, sw.z, fbits(j));
-        sh2 = make_float4(wc * (((al.x * fcL.x) * fcC.x) / d2), wc * (((al.y * fcL.y) * fcC.y) / d2),
-                          wc * (((al.z * fcL.z) * fcC.z) / d2), 1.0f);
+        const f3 cv = mk3(((al.x * fcL.x) * fcC.x) / d2, ((al.y * fcL.y) * fcC.y) / d2,
+                          ((al.z * fcL.z) * fcC.z) / d2);
+        const float* ly = lt.y ? lt.y + (size_t)lpi * lt.lmax * 4 : nullptr;
+        const float wc = bdpt_weight_lp(sc, c, q, lt, it, d, j, zc, zp, yv, lpi, i, It, ly);
+        sh2 = make_float4(wc * cv.x, wc * cv.y, wc * cv.z, 1.0f);
         ++my_conn;
+      } else {
+        q.SH0[e] = make_float4(ov.x, ov.y, ov.z, 0.0f);
+        q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
       }
-      q.SH0[e] = sh0;
-      q.SH1[e] = sh1;
       q.SH2[e] = sh2;
     }
   }
@@ -2520,6 +2473,9 @@ void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, con
   (void)grid;
   shade_bdpt_kernel<<<resident_grid(shade_bdpt_kernel, kShadeBlock), kShadeBlock, 0, s>>>(
       sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
+}
+void k_connect_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                    Counters* cnt, const IterDev& it, const ImageDev& img, int d, hipStream_t s) {
   if (d < sc.max_depth)
     connect_bdpt_kernel<<<resident_grid(connect_bdpt_kernel, kConnectBlock), kConnectBlock, 0, s>>>(
         sc, c, q, lt, cnt, it, img, d);

@@ -223,6 +223,10 @@ void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStr
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
                   uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s);
+// the NEE samples' and light-path connections' weights and contributions of
+// the camera vertices of depth d (after k_shade_bdpt)
+void k_connect_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
+                    Counters* cnt, const IterDev& it, const ImageDev& img, int d, hipStream_t s);
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
                      const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s);
