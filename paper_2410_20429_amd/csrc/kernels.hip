@@ -1580,68 +1580,6 @@ __device__ __forceinline__ VRec load_rec(const QueuesDev& q, int l, uint32_t e) 
 __device__ __forceinline__ float mis_count(const IterDev& it, float b) {
   return it.aware ? b : (b > 0.0f ? 1.0f : 0.0f);
 }
-// full-path weight of strategy t for the path z_0..z_k whose camera
-// vertices z_1..z_{k-1} are the queue entries ez[1..k-1] (their counts are
-// read from their records, the counts their samples were drawn with)
-__device__ float bdpt_weight(const SceneDev& sc, const QueuesDev& q, const IterDev& it,
-                             const PV* z, const uint32_t* ez, int k, int t) {
-  if (k <= 1) return 1.0f;
-  // pF(i): the density of reaching z_i from z_{i-1} (incoming from z_{i-2});
-  // pR(i): of reaching z_i from z_{i+1} (incoming from z_{i+2}), z_k's
-  // emitter pdf and z_{k-1}'s emission density at the end; both as area
-  // densities at z_i, evaluated where the sums below need them
-  auto pF = [&](int i) -> float {
-    float d2;
-    const f3 wo = dir_between(z[i - 1].P, z[i - 2].P, &d2);
-    const f3 wi = dir_between(z[i - 1].P, z[i].P, &d2);
-    f3 fc;
-    float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)z[i - 1].mat), z[i - 1].ng, wo, wi, &fc, &p);
-    return (p * fabsf(dot3(z[i].ng, wi))) / d2;
-  };
-  auto pR = [&](int i) -> float {
-    float d2;
-    if (i == k) return z[k].lpdf;
-    if (i == k - 1) {
-      const f3 w = dir_between(z[k].P, z[k - 1].P, &d2);
-      const float cl = dot3(z[k].ng, w);
-      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
-      return (pe * fabsf(dot3(z[k - 1].ng, w))) / d2;
-    }
-    const f3 wo = dir_between(z[i + 1].P, z[i + 2].P, &d2);
-    const f3 wi = dir_between(z[i + 1].P, z[i].P, &d2);
-    f3 fc;
-    float p;
-    eval_facing(load_mat(sc.mats + 8 * (size_t)z[i + 1].mat), z[i + 1].ng, wo, wi, &fc, &p);
-    return (p * fabsf(dot3(z[i].ng, wi))) / d2;
-  };
-  // strategy tt's own technique count, from the record of z_{tt-1} (it
-  // connects z_{tt-1} to the light vertex y_{k-tt})
-  auto tf = [&](int tt, const VRec& r) -> float {
-    return tt == k + 1 ? 1.0f
-                       : (tt == k ? mis_count(it, r.b1)
-                                  : mis_count(it, lp_class_count(sc, r.b2, r.b3, r.b4, k - tt)));
-  };
-  const float tft = t == k + 1 ? 1.0f : tf(t, load_rec(q, t - 1, ez[t - 1]));
-  if (!(tft > 0.0f)) return 0.0f;
-  float sum = 1.0f, rp = 1.0f, rb = 1.0f;
-  for (int tt = t + 1; tt <= k + 1; ++tt) {
-    rp = rp * (pF(tt - 1) / pR(tt - 1));
-    rb = rb * mis_count(it, load_rec(q, tt - 2, ez[tt - 2]).b0);
-    const float f = tt == k + 1 ? 1.0f : tf(tt, load_rec(q, tt - 1, ez[tt - 1]));
-    sum = sum + (rp * rb) * (f / tft);
-  }
-  rp = 1.0f;
-  rb = 1.0f;
-  for (int tt = t - 1; tt >= 2; --tt) {
-    const VRec r = load_rec(q, tt - 1, ez[tt - 1]);
-    rp = rp * (pR(tt) / pF(tt));
-    rb = rb * mis_count(it, r.b0);
-    sum = sum + rp * (tf(tt, r) / (rb * tft));
-  }
-  if (!(sum < INFINITY)) return 0.0f;
-  return 1.0f / sum;
-}
 
 // light subpaths: emission point by power, cosine direction; the light
 // queue lives at depth 0 of the queues: R0 origin/flag, R1 direction/root,
@@ -1764,13 +1702,18 @@ void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, co
 }
 
 // ---------------------------------------------------------------------------
-// Full-path MIS weights from per-vertex records.  Every term of the weight
-// that depends on camera vertices only (pF, pR, counts along the
+// Full-path MIS weights (Sec. 5) from per-vertex records.  The weight of
+// strategy t of a path z_0..z_k is 1 / sum_s (beta_s p_s) / (beta_t p_t),
+// summed as ratios in a fixed order: 1 for s = t, then s = t + 1 .. k + 1
+// outward along the light side (each step multiplying pF / pR and the BSDF
+// count of the vertex passed), then s = t - 1 .. 2 up the camera side.
+// Every term that depends on camera vertices only (pF, pR, counts along the
 // position-derived throughput) is computed once, when the vertex is shaded,
-// and stored with it; a NEE sample or connection then evaluates only the
-// terms that involve its light-side vertices and reads the rest walking up
-// the parent chain.  Each value is computed by the same operations and the
-// sums run in the same order as in bdpt_weight, so the weight is the same.
+// and stored with it; terms that depend on light vertices only once per
+// light vertex (light_walk_kernel); a NEE sample or connection evaluates
+// only the terms that involve both sides.  Each term is computed by the same
+// operations wherever it is evaluated, so the weight does not depend on
+// where its terms come from.
 // ---------------------------------------------------------------------------
 // the hit vertex of queue entry e at level l
 __device__ __forceinline__ PV hit_vertex(const SceneDev& sc, const QueuesDev& q, int l, uint32_t e) {
@@ -1926,15 +1869,16 @@ void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStr
   light_walk_kernel<<<std::min<uint32_t>((total + 255) / 256, 8192), 256, 0, s>>>(sc, lt, roots);
 }
 
-// the strategies tt = d .. 2 of a connection or NEE sample at the camera
-// vertex j of depth d, walking up the parent chain: pF of vertex tt, pR of
-// vertex tt + 2 (tt <= d - 2) from the records, the counts of vertex tt - 1;
-// pR_d and pR_dm1 involve the light side and are passed in
+// the strategies tt = d .. 2 of a path z_0..z_k through the camera vertex j
+// of depth d (k > d: a connection or NEE sample there; k = d: z_d on an
+// emitter), walking up the parent chain: pF of vertex tt and pR of vertex
+// tt + 2 (tt <= d - 2) from the records (cur: those of z_d), the counts of
+// vertex tt - 1; pR_d and pR_dm1 involve z_{d+1} and are passed in
 __device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const QueuesDev& q,
                                                  const IterDev& it, int d, int k, uint32_t j,
-                                                 float pR_d, float pR_dm1, float tft, float sum) {
+                                                 VRec cur, float pR_d, float pR_dm1, float tft,
+                                                 float sum) {
   float rp = 1.0f, rb = 1.0f;
-  VRec cur = load_rec(q, d, j);
   uint32_t ecur = j;
   float prg1 = 0.0f, prg2 = 0.0f;
   for (int tt = d; tt >= 2; --tt) {
@@ -1943,8 +1887,11 @@ __device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const Queue
     const VRec par = load_rec(q, tt - 1, epar);
     rp = rp * (pRt / cur.pF);
     rb = rb * mis_count(it, par.b0);
-    // strategy tt connects z_{tt-1} (par) to the light vertex y_{k-tt}
-    sum = sum + rp * (mis_count(it, lp_class_count(sc, par.b2, par.b3, par.b4, k - tt)) / (rb * tft));
+    // strategy tt: NEE at z_{k-1} (tt = k), else z_{tt-1} (par) connected to
+    // the light vertex y_{k-tt}
+    const float f = tt == k ? mis_count(it, par.b1)
+                            : mis_count(it, lp_class_count(sc, par.b2, par.b3, par.b4, k - tt));
+    sum = sum + rp * (f / (rb * tft));
     prg2 = prg1;
     prg1 = cur.pRg;
     cur = par;
@@ -1955,7 +1902,7 @@ __device__ __forceinline__ float camera_side_sum(const SceneDev& sc, const Queue
 
 // weight of the NEE sample of camera vertex j (depth d: zc, its parent zp,
 // the camera for d = 1) on the emitter point y: strategy t = d + 1 of the
-// path z_0..z_k, k = d + 1 (the same sums as bdpt_weight for t = k)
+// path z_0..z_k, k = d + 1 (the sums above for t = k)
 __device__ float bdpt_weight_nee(const SceneDev& sc, const QueuesDev& q, const IterDev& it, int d,
                                  uint32_t j, const PV& zc, const PV& zp, const PV& y) {
   const int k = d + 1;
@@ -1977,7 +1924,47 @@ __device__ float bdpt_weight_nee(const SceneDev& sc, const QueuesDev& q, const I
   const float rp = 1.0f * (pFk / y.lpdf);
   const float rb = 1.0f * mis_count(it, rd.b0);
   float sum = 1.0f + (rp * rb) * (1.0f / tft);
-  sum = camera_side_sum(sc, q, it, d, k, j, pR_d, pR_dm1, tft, sum);
+  sum = camera_side_sum(sc, q, it, d, k, j, load_rec(q, d, j), pR_d, pR_dm1, tft, sum);
+  if (!(sum < INFINITY)) return 0.0f;
+  return 1.0f / sum;
+}
+
+// weight of the camera path z_0..z_k whose vertex z_k (queue entry j of
+// depth k >= 2, zk) lies on an emitter: strategy k + 1, BSDF sampling at
+// z_{k-1} (the sums above for t = k + 1).  pF(k) and pR(k - 2)
+// involve z_k and are evaluated here; the rest comes from the records.
+__device__ float bdpt_weight_hit(const SceneDev& sc, const QueuesDev& q, const IterDev& it, int k,
+                                 uint32_t j, const PV& zk) {
+  const uint32_t e1 = ubits(q.S0[(size_t)k * q.cap + j].w);
+  const PV z1 = hit_vertex(sc, q, k - 1, e1);  // z_{k-1}
+  PV z2{};                                      // z_{k-2} (the camera: position only)
+  if (k == 2) z2.P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
+  else z2 = hit_vertex(sc, q, k - 2, ubits(q.S0[(size_t)(k - 1) * q.cap + e1].w));
+  const Mat m1 = load_mat(sc.mats + 8 * (size_t)z1.mat);
+  float d2;
+  VRec cur{};
+  {
+    const f3 wo = dir_between(z1.P, z2.P, &d2);
+    const f3 wi = dir_between(z1.P, zk.P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(m1, z1.ng, wo, wi, &fc, &p);
+    cur.pF = (p * fabsf(dot3(zk.ng, wi))) / d2;
+  }
+  if (k >= 3) {
+    const f3 wo = dir_between(z1.P, zk.P, &d2);
+    const f3 wi = dir_between(z1.P, z2.P, &d2);
+    f3 fc;
+    float p;
+    eval_facing(m1, z1.ng, wo, wi, &fc, &p);
+    cur.pRg = (p * fabsf(dot3(z2.ng, wi))) / d2;
+  }
+  // pR(k - 1): the emission density of z_k towards z_{k-1}
+  const f3 w = dir_between(zk.P, z1.P, &d2);
+  const float cl = dot3(zk.ng, w);
+  const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+  const float pR_km1 = (pe * fabsf(dot3(z1.ng, w))) / d2;
+  const float sum = camera_side_sum(sc, q, it, k, k, j, cur, zk.lpdf, pR_km1, 1.0f, 1.0f);
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
 }
@@ -2074,7 +2061,7 @@ __device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const Que
     if (u + 1 <= k) w3 = lt.V3[base + (uint32_t)(k - u - 1)];
     advance(u, !(w3c.x < 0.0f), xyz(w3c), w3c.w);
   }
-  sum = camera_side_sum(sc, q, it, d, k, j, pR_d, pR_dm1, tft, sum);
+  sum = camera_side_sum(sc, q, it, d, k, j, load_rec(q, d, j), pR_d, pR_dm1, tft, sum);
   if (!(sum < INFINITY)) return 0.0f;
   return 1.0f / sum;
 }
@@ -2083,29 +2070,6 @@ __device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const Que
 // camera vertex in SH1.w; NEE: emitter point and triangle in SH0; light
 // path: subpath index and light vertex index in SH0.xy
 constexpr uint32_t kConnNee = 1u, kConnLight = 2u;
-
-// camera prefix z_0..z_d of the camera vertex j of depth d (hit point x on
-// primitive prim, reached along dir) from the parent chain
-__device__ __forceinline__ void camera_prefix(const SceneDev& sc, const QueuesDev& q, int d,
-                                              uint32_t j, f3 x, f3 ng, uint32_t prim, f3 dir,
-                                              PV* z, uint32_t* ez) {
-  z[0].P = mk3(sc.cam_o[0], sc.cam_o[1], sc.cam_o[2]);
-  z[0].ng = dir;
-  z[0].mat = 0;
-  z[0].lpdf = 0.0f;
-  z[d] = PV{x, ng, sc.tri_mat[prim], sc.tri_ng[prim].w};
-  ez[d] = j;
-  uint32_t e = ubits(q.S0[(size_t)d * q.cap + j].w);
-  for (int l = d - 1; l >= 1; --l) {
-    ez[l] = e;
-    const size_t ee = (size_t)l * q.cap + e;
-    const float4 a0 = q.R0[ee], a1 = q.R1[ee];
-    const uint2 ah = q.H[ee];
-    const float at = fbits(ah.x);
-    z[l] = prim_vertex(sc, mk3(a0.x + at * a1.x, a0.y + at * a1.y, a0.z + at * a1.z), ah.y);
-    e = ubits(q.S0[ee].w);
-  }
-}
 
 // light subpath of LP sample j of a camera vertex: pool entry (b + j stride)
 // mod npool, b the first word of the vertex's own random stream, so that the
@@ -2140,8 +2104,6 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
   const int lane = threadIdx.x & 63;
   const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
   uint32_t my_vert = 0, my_samp = 0, my_ext = 0;
-  PV z[2 * kMaxDepth + 4];
-  uint32_t ez[kMaxDepth + 2];
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t j = base + threadIdx.x;
     const bool active = j < n;
@@ -2176,11 +2138,8 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
         It[2] = img.itilde[3 * (size_t)pix + 2];
         const float cosl = -dot3(dir, ng);
         if (cosl > 0.0f && (m[5] > 0.0f || m[6] > 0.0f || m[7] > 0.0f)) {
-          float w = 1.0f;
-          if (d > 1) {
-            camera_prefix(sc, q, d, j, x, ng, prim, dir, z, ez);
-            w = bdpt_weight(sc, q, it, z, ez, d, d + 1);
-          }
+          const float w = d > 1 ? bdpt_weight_hit(sc, q, it, d, j, PV{x, ng, sc.tri_mat[prim], ngl.w})
+                                : 1.0f;
           Ew = mk3(w * m[5], w * m[6], w * m[7]);
         }
         if (d < sc.max_depth) {
