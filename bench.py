@@ -331,7 +331,8 @@ def run_bdpt(args, api, torch):
            "config": {"workload": "bdpt_1280x720_interior1m_d12", "width": sc["width"],
                       "height": sc["height"], "triangles": int(sc["V"].shape[0]), "max_depth": 12,
                       "spp_per_step": 1, "techniques": ["bsdf", "nee", "light_path"],
-                      "queue_capacity": tuned[0][0], "tile_roots": tuned[0][1]},
+                      "queue_capacity": tuned[0][0], "shadow_queue_capacity": tuned[0][3],
+                      "tile_roots": tuned[0][1]},
            "mrays_per_s": rays / dt / 1e6,
            "kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
     if not args.no_efficiency:
@@ -785,8 +786,8 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
     # tuned on a MARS iteration: splitting sets the queue peaks
     t1 = time.perf_counter()
     tuned = api.autotune(S, params(warm), mem_budget=budget)
-    for e, (cap, tile, _) in zip(E, tuned):
-        e.configure(queue_capacity=cap, tile_roots=tile)
+    for e, (cap, tile, _, scap, _) in zip(E, tuned):
+        e.configure(queue_capacity=cap, tile_roots=tile, shadow_capacity=scap)
     torch.cuda.empty_cache()  # queue buffers replaced while tuning
     print(f"[bench] batch: autotuned in {time.perf_counter() - t1:.1f} s", file=sys.stderr,
           flush=True)

@@ -204,32 +204,51 @@ mars_status mars_iterate_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t 
                                const mars_iter_params* p, int32_t flags,
                                mars_iter_stats* iter_stats, mars_update_stats* upd_stats);
 
-/* Re-sizes a scene's path queues: queue_capacity entries per depth level,
- * camera samples per wavefront tile (<= queue_capacity; 0 = keep).  Queue
- * memory is about 216 bytes x (max_depth + 2) x queue_capacity. */
+/* Re-sizes a scene's path queues.  A scene holds per depth level (levels
+ * 0 .. max_depth + 1) ray queues (camera, continuation and light rays with
+ * their vertices) and shadow queues (NEE samples and light-path
+ * connections, which splitting and connections can make far longer).
+ * mars_scene_configure_queues: ray_capacity and shadow_capacity entries per
+ * level, camera samples per wavefront tile (<= ray_capacity); 0 keeps a
+ * value.  Queue memory is about (max_depth + 2) x (168 B x ray_capacity +
+ * 48 B x shadow_capacity), plus per ray entry 32 B for BDPT, 32 B more with
+ * per-length light-path budgets and 16 B with the learned cache.
+ * mars_scene_configure: both capacities queue_capacity. */
+mars_status mars_scene_configure_queues(mars_ctx* ctx, int32_t scene_id, int64_t ray_capacity,
+                                        int64_t shadow_capacity, int32_t tile_roots);
 mars_status mars_scene_configure(mars_ctx* ctx, int32_t scene_id, int64_t queue_capacity,
                                  int32_t tile_roots);
-/* queue size and tile size of a scene, the peak queue occupancy per camera
- * sample seen by the last eager render iteration */
+/* ray-queue capacity and tile size of a scene, the peak queue occupancy
+ * per camera sample (the larger of the two queues) seen by the last eager
+ * render iteration */
 mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_capacity,
                              int32_t* tile_roots, double* peak_per_root);
+/* both capacities and both peaks (entries per camera sample at the fullest
+ * level) of the last eager render iteration; any pointer may be null */
+mars_status mars_scene_query_queues(mars_ctx* ctx, int32_t scene_id, int64_t* ray_capacity,
+                                    int64_t* shadow_capacity, double* peak_ray,
+                                    double* peak_shadow);
 
 /* Autotuner of queue and tile sizes.  For each scene: one probe render
  * iteration with p (no update; the last-iteration image and sample radiance
- * then hold the probe's) measures the peak queue occupancy per camera sample
- * e; tiles of up to all camera samples are planned under mem_budget bytes of
- * queue memory for the n scenes together (capacity = tile x e x 1.25,
- * largest scenes halved first, no tile below min(all samples, max(4096,
- * 2^18 / e)) rounded up to 64); then up to three tile sizes (plan, plan/2,
- * plan/4, same floor) are timed with one render iteration each and the
- * fastest kept.  cache_path (optional): a text file of lines
- * "<class> <capacity> <tile> <e> <ms>" keyed by the scene class (resolution,
- * spp, mode, depth, triangles, allocation mode); classes found there are
- * applied without probing and new ones appended.  out (optional, n entries
- * each): chosen capacity, tile, measured e. */
+ * then hold the probe's) measures the peak occupancy per camera sample of
+ * the ray queues e and of the shadow queues e_s (each at least 1); tiles of
+ * up to all camera samples are planned under mem_budget bytes of queue
+ * memory for the n scenes together (capacities tile x e x 1.25 and
+ * tile x e_s x 1.25, rounded up to 4096; largest scenes halved first, no
+ * tile below min(all samples, max(4096, 2^18 / max(e, e_s))) rounded up to
+ * 64); then up to three tile sizes (plan, plan/2, plan/4, same floor) are
+ * timed with one render iteration each and the fastest kept.  cache_path
+ * (optional): a text file of lines
+ * "<class> <capacity> <shadow capacity> <tile> <e> <e_s> <ms>" keyed by the
+ * scene class (resolution, spp, mode, depth, triangles, allocation mode);
+ * classes found there are applied without probing and new ones appended
+ * (lines of another form are ignored).  out (optional, n entries each):
+ * chosen ray capacity, tile, e, shadow capacity, e_s. */
 mars_status mars_autotune(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
                           const mars_iter_params* p, int64_t mem_budget, const char* cache_path,
-                          int64_t* out_capacity, int32_t* out_tile, double* out_peak);
+                          int64_t* out_capacity, int32_t* out_tile, double* out_peak,
+                          int64_t* out_shadow_capacity, double* out_shadow_peak);
 /* Image estimates (I~, V_I, C_I), the fixed-point update of every cell's
  * factors, the directional distribution of the guided technique, octree
  * refinement and the inverse-variance weighted image (Sec. 4.1, 5.1). */

@@ -85,8 +85,12 @@ SIGNATURES = {
     "mars_render_batch": [P, P, I32, C.POINTER(mars_iter_params), C.POINTER(mars_iter_stats)],
     "mars_iterate_batch": [P, P, I32, C.POINTER(mars_iter_params), I32, P, P],
     "mars_scene_configure": [P, I32, C.c_int64, I32],
+    "mars_scene_configure_queues": [P, I32, C.c_int64, C.c_int64, I32],
     "mars_scene_query": [P, I32, C.POINTER(C.c_int64), PI32, C.POINTER(C.c_double)],
-    "mars_autotune": [P, P, I32, C.POINTER(mars_iter_params), C.c_int64, C.c_char_p, P, P, P],
+    "mars_scene_query_queues": [P, I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "mars_autotune": [P, P, I32, C.POINTER(mars_iter_params), C.c_int64, C.c_char_p, P, P, P, P,
+                      P],
     "mars_update_counts": [P, I32, C.POINTER(mars_iter_params), C.POINTER(mars_update_stats)],
     "mars_set_fixed_counts": [P, I32, P, I32],
     "mars_set_itilde": [P, I32, P],
@@ -217,20 +221,33 @@ def mars_scene_configure(ctx, sid, queue_capacity=0, tile_roots=0):
     _call("mars_scene_configure", ctx, sid, queue_capacity, tile_roots)
 
 
+def mars_scene_configure_queues(ctx, sid, ray_capacity=0, shadow_capacity=0, tile_roots=0):
+    _call("mars_scene_configure_queues", ctx, sid, ray_capacity, shadow_capacity, tile_roots)
+
+
 def mars_scene_query(ctx, sid):
     cap, tile, peak = C.c_int64(), C.c_int32(), C.c_double()
     _call("mars_scene_query", ctx, sid, C.byref(cap), C.byref(tile), C.byref(peak))
     return cap.value, tile.value, peak.value
 
 
+def mars_scene_query_queues(ctx, sid):
+    cap, scap, pr, ps = C.c_int64(), C.c_int64(), C.c_double(), C.c_double()
+    _call("mars_scene_query_queues", ctx, sid, C.byref(cap), C.byref(scap), C.byref(pr),
+          C.byref(ps))
+    return cap.value, scap.value, pr.value, ps.value
+
+
 def mars_autotune(ctx, sids, params, mem_budget=0, cache_path=None):
     n = len(sids)
     arr = (C.c_int32 * n)(*sids)
     cap, tile, peak = (C.c_int64 * n)(), (C.c_int32 * n)(), (C.c_double * n)()
+    scap, speak = (C.c_int64 * n)(), (C.c_double * n)()
     _call("mars_autotune", ctx, C.cast(arr, C.c_void_p), n, C.byref(params), mem_budget,
           cache_path.encode() if cache_path else None, C.cast(cap, C.c_void_p),
-          C.cast(tile, C.c_void_p), C.cast(peak, C.c_void_p))
-    return list(cap), list(tile), list(peak)
+          C.cast(tile, C.c_void_p), C.cast(peak, C.c_void_p), C.cast(scap, C.c_void_p),
+          C.cast(speak, C.c_void_p))
+    return list(cap), list(tile), list(peak), list(scap), list(speak)
 
 
 def mars_update_counts(ctx, sid, params):

@@ -283,13 +283,24 @@ class Scene:
         return x, t, w
 
     # ---- queue sizing ----
-    def configure(self, queue_capacity=0, tile_roots=0):
-        capi.mars_scene_configure(self.ctx.h, self.id, int(queue_capacity), int(tile_roots))
+    def configure(self, queue_capacity=0, tile_roots=0, shadow_capacity=None):
+        """Queue sizes: queue_capacity entries per level of the ray queues and
+        shadow_capacity of the shadow queues (None: queue_capacity); 0 keeps."""
+        if shadow_capacity is None:
+            capi.mars_scene_configure(self.ctx.h, self.id, int(queue_capacity), int(tile_roots))
+        else:
+            capi.mars_scene_configure_queues(self.ctx.h, self.id, int(queue_capacity),
+                                             int(shadow_capacity), int(tile_roots))
 
     def query(self):
-        """(queue capacity, tile size, peak queue level per camera sample of
-        the last eager iteration)"""
+        """(ray-queue capacity, tile size, peak queue level per camera sample
+        of the last eager iteration)"""
         return capi.mars_scene_query(self.ctx.h, self.id)
+
+    def query_queues(self):
+        """(ray-queue capacity, shadow-queue capacity, peak ray and shadow
+        entries per camera sample of the last eager iteration)"""
+        return capi.mars_scene_query_queues(self.ctx.h, self.id)
 
     def checkpoint_save(self, path):
         capi.mars_checkpoint_save(self.ctx.h, self.id, str(path))
@@ -317,10 +328,11 @@ def iterate_batch(scenes, params, update=True, graph=True):
 
 
 def autotune(scenes, params, mem_budget=0, cache_path=None):
-    """Queue capacity and tile size per scene: [(capacity, tile, peak per sample)]."""
-    cap, tile, peak = capi.mars_autotune(scenes[0].ctx.h, [s.id for s in scenes], params,
-                                         int(mem_budget), cache_path)
-    return list(zip(cap, tile, peak))
+    """Queue and tile sizes per scene: [(ray capacity, tile, peak rays per
+    sample, shadow capacity, peak shadow entries per sample)]."""
+    r = capi.mars_autotune(scenes[0].ctx.h, [s.id for s in scenes], params, int(mem_budget),
+                           cache_path)
+    return list(zip(*r))
 
 
 def run_schedule(scene: Scene, n_iter, warmup=1, spp=1, budget_aware=True, stat_clamp=None,

@@ -78,8 +78,10 @@ struct Scene {
   uint32_t mlp_n_train = 0;
   int mlp_step = 0;
   uint64_t vertices_last = 0;
-  // largest queue level per camera sample over the tiles of the last eager iteration
-  double peak_per_root = 0.0;
+  // largest queue level per camera sample over the tiles of the last eager
+  // iteration: of the ray queues, of the shadow queues, and the larger
+  double peak_ray = 0.0, peak_shadow = 0.0, peak_per_root = 0.0;
+  size_t scap = 0;  // shadow-queue entries per level (cap: ray-queue entries)
 };
 
 // per-kernel HIP-event timing on the context's stream
@@ -330,9 +332,12 @@ void ensure_roots(Scene* s, size_t roots) {
   s->epoch++;
 }
 
-// per-depth path queues of `cap` entries per level (levels 0 .. max_depth + 1)
-void alloc_queues(Scene* s, size_t cap) {
-  if (cap == 0 || cap > 0xFFFF0000ull) throw Status(MARS_E_ARG, "queue capacity out of range");
+// per-depth path queues (levels 0 .. max_depth + 1): `cap` entries per level
+// of the ray queues, `scap` of the shadow queues (NEE samples and light-path
+// connections, which can far outnumber the rays)
+void alloc_queues(Scene* s, size_t cap, size_t scap) {
+  if (cap == 0 || cap > 0xFFFF0000ull || scap == 0 || scap > 0xFFFF0000ull)
+    throw Status(MARS_E_ARG, "queue capacity out of range");
   QueuesDev& q = s->qd;
   if (q.R0) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
@@ -351,7 +356,8 @@ void alloc_queues(Scene* s, size_t cap) {
   q.H = salloc<uint2>(s, lv);
   q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
   q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
-  q.SH0 = salloc<float4>(s, lv); q.SH1 = salloc<float4>(s, lv); q.SH2 = salloc<float4>(s, lv);
+  const size_t lvs = (size_t)(s->max_depth + 2) * scap;
+  q.SH0 = salloc<float4>(s, lvs); q.SH1 = salloc<float4>(s, lvs); q.SH2 = salloc<float4>(s, lvs);
   if (s->mode == MARS_MODE_BDPT) {
     q.W0 = salloc<float4>(s, lv);
     q.W1 = salloc<float4>(s, lv);
@@ -361,13 +367,15 @@ void alloc_queues(Scene* s, size_t cap) {
     q.V3 = salloc<float4>(s, lv);
   }
   q.cap = cap;
+  q.scap = scap;
   if (s->mlp_on) s->mlp.y = salloc<float>(s, lv * 4);
   s->cap = cap;
+  s->scap = scap;
   s->epoch++;
 }
 
-// bytes of queue memory per entry of one level
-constexpr size_t kQueueEntryBytes = 13 * 16 + 8;
+// bytes of queue memory per entry of one level: ray queues, shadow queues
+constexpr size_t kRayEntryBytes = 10 * 16 + 8, kShadowEntryBytes = 3 * 16;
 
 // BDPT: one light subpath per camera sample of the iteration, before any
 // camera tile (connections may use any sample's subpath)
@@ -498,7 +506,7 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     work.emplace_back((uint32_t)r, n);  // processed back to front: ascending roots
   }
   uint32_t dbg_total = 0;
-  double peak = 0.0;
+  double peak_r = 0.0, peak_s = 0.0;
   uint32_t ok_tile = 0;  // largest tile that fit after an overflow
   bool overflowed = false;
   while (!work.empty()) {
@@ -507,8 +515,10 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
     Counters hc;
     const bool ok = run_tile(s, it, r0, n, dbg_total, (uint32_t)roots, work.empty(), p->spp, &hc);
     S.tiles++;
-    for (int d = 1; d <= s->max_depth + 1; ++d)
-      peak = std::max(peak, (double)std::max(hc.n_ray[d], hc.n_shadow[d]) / (double)n);
+    for (int d = 1; d <= s->max_depth + 1; ++d) {
+      peak_r = std::max(peak_r, (double)hc.n_ray[d] / (double)n);
+      peak_s = std::max(peak_s, (double)hc.n_shadow[d] / (double)n);
+    }
     if (!ok) {
       if (n == 1) throw Status(MARS_E_OVERFLOW, "a single path tree exceeds the queue capacity");
       S.overflow_retries++;
@@ -532,7 +542,9 @@ void render_iteration(Scene* s, const mars_iter_params* p, mars_iter_stats* out)
   s->vertices_last = S.vertices;
   s->rays_last = S.rays_camera + S.rays_ext + S.rays_shadow + S.rays_light + S.rays_conn;
   s->dbg_last = dbg_total;
-  s->peak_per_root = peak;
+  s->peak_ray = peak_r;
+  s->peak_shadow = peak_s;
+  s->peak_per_root = std::max(peak_r, peak_s);
   // later iterations start from a tile that fitted (tiles do not change results)
   if (overflowed && ok_tile > 0 && (int)ok_tile < s->tile_roots) s->tile_roots = (int)ok_tile;
   S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -802,7 +814,7 @@ int upload_scene(Ctx* c, const mars_scene_desc* d) {
                                        : std::max<size_t>(65536, 4 * (size_t)s->tile_roots);
     if (cap > 0xFFFF0000ull) cap = 0xFFFF0000ull;
     s->mlp_on = (d->flags & MARS_SCENE_MLP) != 0;
-    alloc_queues(s, cap);
+    alloc_queues(s, cap, cap);
     s->cnt = salloc<Counters>(s, 1);
     s->lt.lmax = d->max_depth - 2;
     s->dbg_cap = 0;  // allocated on the first iteration that asks for records
@@ -1002,8 +1014,9 @@ uint64_t fbits64(float f) {
   return u;
 }
 
-void configure(Scene* s, size_t cap, int tile) {
-  if (cap && cap != s->cap) alloc_queues(s, cap);
+void configure(Scene* s, size_t cap, size_t scap, int tile) {
+  if ((cap && cap != s->cap) || (scap && scap != s->scap))
+    alloc_queues(s, cap ? cap : s->cap, scap ? scap : s->scap);
   if (tile > 0) s->tile_roots = tile;  // part of the graph key, no new epoch needed
 }
 
@@ -1052,6 +1065,7 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
     key.push_back((uint64_t)lane[i]);
     key.push_back((uint64_t)sc[i]->tile_roots);
     key.push_back((uint64_t)sc[i]->cap);
+    key.push_back((uint64_t)sc[i]->scap);
   }
   BatchGraph* g = nullptr;
   for (auto& e : c->graphs)
@@ -1190,17 +1204,19 @@ size_t tuned_capacity(size_t tile, double e) {
 }
 
 // smallest tile worth a launch sequence: about 2^18 queue entries at the
-// peak level (enough rays to fill the chip), at least 4096 camera samples
+// peak level of either queue (enough rays to fill the chip), at least 4096
+// camera samples
 constexpr double kTuneMinEntries = 262144.0;
 size_t min_tile(size_t roots, double e) {
   const size_t t = (size_t)std::ceil(kTuneMinEntries / std::max(1.0, e));
   return std::min(roots, (std::max<size_t>(t, 4096) + 63) / 64 * 64);
 }
 
-size_t queue_bytes(const Scene* s, size_t cap) {
-  return cap * (size_t)(s->max_depth + 2) *
-         (kQueueEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0) +
-          (s->sd.lp_classes == 3 ? 32 : 0));
+size_t queue_bytes(const Scene* s, size_t cap, size_t scap) {
+  return (size_t)(s->max_depth + 2) *
+         (cap * (kRayEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0) +
+                 (s->sd.lp_classes == 3 ? 32 : 0)) +
+          scap * kShadowEntryBytes);
 }
 
 std::string scene_class(const Scene* s, const mars_iter_params* p) {
@@ -1211,13 +1227,14 @@ std::string scene_class(const Scene* s, const mars_iter_params* p) {
 }
 
 struct TuneEntry {
-  size_t cap = 0;
+  size_t cap = 0, scap = 0;  // ray-queue and shadow-queue entries per level
   int tile = 0;
-  double e = 0.0, ms = 0.0;
+  double e = 0.0, es = 0.0, ms = 0.0;  // peak ray / shadow entries per camera sample
 };
 
 void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int64_t budget,
-              const char* path, int64_t* ocap, int32_t* otile, double* opeak) {
+              const char* path, int64_t* ocap, int32_t* otile, double* opeak, int64_t* oscap,
+              double* ospeak) {
   if (!ids || n <= 0 || !p) throw Status(MARS_E_ARG, "empty batch or null params");
   if (budget <= 0) {
     size_t fr = 0, tot = 0;
@@ -1232,13 +1249,16 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
   std::vector<std::pair<std::string, TuneEntry>> cache;
   if (path) {
     if (FILE* f = std::fopen(path, "r")) {
-      char cls[192];
-      unsigned long long cap;
+      char line[512], cls[192];
+      unsigned long long cap, scap;
       int tile;
-      double e, ms;
-      while (std::fscanf(f, "%191s %llu %d %lf %lf", cls, &cap, &tile, &e, &ms) == 5)
-        if (cap > 0 && cap <= 0xFFFF0000ull && tile > 0 && (size_t)tile <= cap)
-          cache.push_back({cls, TuneEntry{(size_t)cap, tile, e, ms}});
+      double e, es, ms;
+      while (std::fgets(line, sizeof(line), f))
+        if (std::sscanf(line, "%191s %llu %llu %d %lf %lf %lf", cls, &cap, &scap, &tile, &e, &es,
+                        &ms) == 7 &&
+            cap > 0 && cap <= 0xFFFF0000ull && scap > 0 && scap <= 0xFFFF0000ull && tile > 0 &&
+            (size_t)tile <= cap)
+          cache.push_back({cls, TuneEntry{(size_t)cap, (size_t)scap, tile, e, es, ms}});
       std::fclose(f);
     }
   }
@@ -1251,42 +1271,47 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
   std::vector<int> todo;
   for (int i = 0; i < n; ++i) {
     if (TuneEntry* t = find(scene_class(sc[i], p))) {
-      configure(sc[i], t->cap, t->tile);
+      configure(sc[i], t->cap, t->scap, t->tile);
       res[i] = *t;
     } else {
       todo.push_back(i);
     }
   }
-  // probe: peak queue level per camera sample at the current sizes
+  // probe: peak queue levels per camera sample at the current sizes
   for (int i : todo) {
     render_iteration(sc[i], p, nullptr);
-    res[i].e = std::max(1.0, sc[i]->peak_per_root);
+    res[i].e = std::max(1.0, sc[i]->peak_ray);
+    res[i].es = std::max(1.0, sc[i]->peak_shadow);
   }
+  auto bytes_at = [&](int i, size_t t) {
+    return queue_bytes(sc[i], tuned_capacity(t, res[i].e), tuned_capacity(t, res[i].es));
+  };
+  auto floor_of = [&](int i) {
+    return min_tile(roots_of(sc[i], p->spp), std::max(res[i].e, res[i].es));
+  };
   // plan: whole-iteration tiles, the largest scenes halved until the queues fit
   std::vector<size_t> T(n);
   double used = 0.0;
   for (int i = 0; i < n; ++i) {
     const bool tuned = std::find(todo.begin(), todo.end(), i) != todo.end();
     T[i] = tuned ? roots_of(sc[i], p->spp) : (size_t)res[i].tile;
-    used += (double)queue_bytes(sc[i], tuned ? tuned_capacity(T[i], res[i].e) : res[i].cap);
+    used += (double)(tuned ? bytes_at(i, T[i]) : queue_bytes(sc[i], res[i].cap, res[i].scap));
   }
   while (used > (double)budget) {
     int best = -1;
     size_t bytes = 0;
     for (int i : todo) {
-      const size_t floor_t = min_tile(roots_of(sc[i], p->spp), res[i].e);
-      const size_t b = queue_bytes(sc[i], tuned_capacity(T[i], res[i].e));
-      if (T[i] > floor_t && b > bytes) { best = i; bytes = b; }
+      const size_t b = bytes_at(i, T[i]);
+      if (T[i] > floor_of(i) && b > bytes) { best = i; bytes = b; }
     }
     if (best < 0) throw Status(MARS_E_OOM, "queue memory budget too small for the batch");
-    const size_t floor_t = min_tile(roots_of(sc[best], p->spp), res[best].e);
-    T[best] = std::max(floor_t, (T[best] + 1) / 2);
-    used += (double)queue_bytes(sc[best], tuned_capacity(T[best], res[best].e)) - (double)bytes;
+    T[best] = std::max(floor_of(best), (T[best] + 1) / 2);
+    used += (double)bytes_at(best, T[best]) - (double)bytes;
   }
   // measure: the planned tile and two smaller ones, one timed iteration each
   for (int i : todo) {
     Scene* s = sc[i];
-    const size_t floor_t = min_tile(roots_of(s, p->spp), res[i].e);
+    const size_t floor_t = floor_of(i);
     std::vector<size_t> cand;
     for (size_t t = T[i]; cand.size() < 3; t /= 2) {
       const size_t tt = std::max(floor_t, t);
@@ -1296,7 +1321,8 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
     double best_ms = INFINITY;
     size_t best_t = cand[0];
     for (size_t k = 0; k < cand.size(); ++k) {
-      configure(s, tuned_capacity(cand[k], res[i].e), (int)std::min<size_t>(cand[k], 0x7FFFFFFF));
+      configure(s, tuned_capacity(cand[k], res[i].e), tuned_capacity(cand[k], res[i].es),
+                (int)std::min<size_t>(cand[k], 0x7FFFFFFF));
       if (k == 0) render_iteration(s, p, nullptr);  // first use of the new buffers
       mars_iter_stats S{};
       render_iteration(s, p, &S);
@@ -1304,8 +1330,9 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
     }
     res[i].tile = (int)std::min<size_t>(best_t, 0x7FFFFFFF);
     res[i].cap = tuned_capacity(best_t, res[i].e);
+    res[i].scap = tuned_capacity(best_t, res[i].es);
     res[i].ms = best_ms;
-    configure(s, res[i].cap, res[i].tile);
+    configure(s, res[i].cap, res[i].scap, res[i].tile);
     const std::string k = scene_class(s, p);
     if (TuneEntry* t = find(k)) *t = res[i];
     else cache.push_back({k, res[i]});
@@ -1314,14 +1341,17 @@ void autotune(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p, int6
     FILE* f = std::fopen(path, "w");
     if (!f) throw Status(MARS_E_IO, "cannot write the autotuner cache");
     for (auto& e : cache)
-      std::fprintf(f, "%s %llu %d %.6g %.6g\n", e.first.c_str(), (unsigned long long)e.second.cap,
-                   e.second.tile, e.second.e, e.second.ms);
+      std::fprintf(f, "%s %llu %llu %d %.6g %.6g %.6g\n", e.first.c_str(),
+                   (unsigned long long)e.second.cap, (unsigned long long)e.second.scap,
+                   e.second.tile, e.second.e, e.second.es, e.second.ms);
     if (std::fclose(f) != 0) throw Status(MARS_E_IO, "cannot write the autotuner cache");
   }
   for (int i = 0; i < n; ++i) {
     if (ocap) ocap[i] = (int64_t)sc[i]->cap;
     if (otile) otile[i] = sc[i]->tile_roots;
     if (opeak) opeak[i] = res[i].e;
+    if (oscap) oscap[i] = (int64_t)sc[i]->scap;
+    if (ospeak) ospeak[i] = res[i].es;
   }
 }
 
@@ -1557,18 +1587,25 @@ mars_status mars_iterate_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t 
   return guard(ctx, [&] { batch_iterate(ctx, scene_ids, n, p, flags, iter_stats, upd_stats); });
 }
 
-mars_status mars_scene_configure(mars_ctx* ctx, int32_t scene_id, int64_t queue_capacity,
-                                 int32_t tile_roots) {
+mars_status mars_scene_configure_queues(mars_ctx* ctx, int32_t scene_id, int64_t ray_capacity,
+                                        int64_t shadow_capacity, int32_t tile_roots) {
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
     Scene* s = ctx->scene(scene_id);
-    if (queue_capacity < 0 || queue_capacity > (int64_t)0xFFFF0000ull || tile_roots < 0)
+    if (ray_capacity < 0 || ray_capacity > (int64_t)0xFFFF0000ull || shadow_capacity < 0 ||
+        shadow_capacity > (int64_t)0xFFFF0000ull || tile_roots < 0)
       throw Status(MARS_E_ARG, "bad queue capacity or tile size");
-    const size_t cap = queue_capacity > 0 ? (size_t)queue_capacity : s->cap;
+    const size_t cap = ray_capacity > 0 ? (size_t)ray_capacity : s->cap;
+    const size_t scap = shadow_capacity > 0 ? (size_t)shadow_capacity : s->scap;
     const size_t tile = tile_roots > 0 ? (size_t)tile_roots : (size_t)s->tile_roots;
     if (tile > cap) throw Status(MARS_E_ARG, "tile larger than the queue capacity");
-    configure(s, cap, (int)tile);
+    configure(s, cap, scap, (int)tile);
   });
+}
+
+mars_status mars_scene_configure(mars_ctx* ctx, int32_t scene_id, int64_t queue_capacity,
+                                 int32_t tile_roots) {
+  return mars_scene_configure_queues(ctx, scene_id, queue_capacity, queue_capacity, tile_roots);
 }
 
 mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_capacity,
@@ -1582,12 +1619,27 @@ mars_status mars_scene_query(mars_ctx* ctx, int32_t scene_id, int64_t* queue_cap
   });
 }
 
-mars_status mars_autotune(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
-                          const mars_iter_params* p, int64_t mem_budget, const char* cache_path,
-                          int64_t* out_capacity, int32_t* out_tile, double* out_peak) {
+mars_status mars_scene_query_queues(mars_ctx* ctx, int32_t scene_id, int64_t* ray_capacity,
+                                    int64_t* shadow_capacity, double* peak_ray,
+                                    double* peak_shadow) {
   if (!ctx) return MARS_E_ARG;
   return guard(ctx, [&] {
-    autotune(ctx, scene_ids, n, p, mem_budget, cache_path, out_capacity, out_tile, out_peak);
+    Scene* s = ctx->scene(scene_id);
+    if (ray_capacity) *ray_capacity = (int64_t)s->cap;
+    if (shadow_capacity) *shadow_capacity = (int64_t)s->scap;
+    if (peak_ray) *peak_ray = s->peak_ray;
+    if (peak_shadow) *peak_shadow = s->peak_shadow;
+  });
+}
+
+mars_status mars_autotune(mars_ctx* ctx, const int32_t* scene_ids, int32_t n,
+                          const mars_iter_params* p, int64_t mem_budget, const char* cache_path,
+                          int64_t* out_capacity, int32_t* out_tile, double* out_peak,
+                          int64_t* out_shadow_capacity, double* out_shadow_peak) {
+  if (!ctx) return MARS_E_ARG;
+  return guard(ctx, [&] {
+    autotune(ctx, scene_ids, n, p, mem_budget, cache_path, out_capacity, out_tile, out_peak,
+             out_shadow_capacity, out_shadow_peak);
   });
 }
 

@@ -411,8 +411,8 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
   __shared__ int stk[kStackDepth * kTraceBlock];
   if (cnt->overflow) return;
   const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
-  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
-  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.scap) : 0u;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.scap;
   uint32_t cr = 0, cn = 0, ct = 0, sr = 0, sn = 0, st = 0;
   uint32_t cmax = 0, smax = 0, clong = 0, slong = 0;  // per-ray node visits: max, rays > 64
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nc + ns;
@@ -825,8 +825,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(8, 
   __shared__ uint2 res[kQuadsPerBlock];
   if (cnt->overflow) return;
   const uint32_t nc = dc >= 0 ? min(cnt->n_ray[dc], (uint32_t)q.cap) : 0u;
-  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.cap) : 0u;
-  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.cap;
+  const uint32_t ns = ds > 0 ? min(cnt->n_shadow[ds], (uint32_t)q.scap) : 0u;
+  const size_t Lc = (size_t)(dc >= 0 ? dc : 0) * q.cap, Ls = (size_t)ds * q.scap;
   const uint32_t Q = gridDim.x * (blockDim.x >> 2);
   const uint32_t n = nc + ns;
   if ((uint64_t)n * kSplitDiv16 <= Q) trace_rays<2>(sc, q, nc, ns, Lc, Ls, stk, shared_t, res);
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
     group_alloc<kShadePtBlock>(ncont, nnee, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
                              alloc_lds);
     bool ovf = false;
-    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.cap)) {
+    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nnee > q.scap)) {
       ovf = true;
       atomicMax(&cnt->overflow, 1u);
       atomicMax(&cnt->overflow_any, 1u);
@@ -1256,7 +1256,7 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
         ++my_sh;
       }
-      const size_t e = L + sv.sfirst[v] + k;
+      const size_t e = (size_t)d * q.scap + sv.sfirst[v] + k;
       q.SH0[e] = make_float4(vo.x, vo.y, vo.z, dist * (1.0f - 1e-3f));
       q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(sv.j[v]));
       q.SH2[e] = sh2;
@@ -1445,7 +1445,7 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
         st[t][6] += 1.0; st[t][7] += (double)cst;
       };
       for (uint32_t k = 0; k < v2.y; ++k) {
-        const f3 v = xyz(q.SH2[L + v2.x + k]);
+        const f3 v = xyz(q.SH2[(size_t)d * q.scap + v2.x + k]);
         R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
         cost += 1;
         record(1, v, 1u);
@@ -2176,7 +2176,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
     group_alloc<kShadeBlock>(ncont, nsh, &cnt->n_ray[d + 1], &cnt->n_shadow[d], &cfirst, &sfirst,
                              alloc_lds);
     bool ovf = false;
-    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nsh > q.cap)) {
+    if (vert && ((size_t)cfirst + ncont > q.cap || (size_t)sfirst + nsh > q.scap)) {
       ovf = true;
       atomicMax(&cnt->overflow, 1u);
       atomicMax(&cnt->overflow_any, 1u);
@@ -2227,7 +2227,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
       const float a = su * (1.0f - u.z), b = su * u.z;
       const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
                        (v0.z + a * e1.z) + b * e2.z);
-      const size_t e = L + sfirst + k;
+      const size_t e = (size_t)d * q.scap + sfirst + k;
       q.SH0[e] = make_float4(y.x, y.y, y.z, fbits((uint32_t)li));
       q.SH1[e] = make_float4(fbits(kConnNee), 0.0f, 0.0f, fbits(j));
     }
@@ -2271,7 +2271,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
         int lo, hi;
         lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
         for (int i = lo; i <= hi; ++i, ++slot) {
-          const size_t e = L + slot;
+          const size_t e = (size_t)d * q.scap + slot;
           q.SH0[e] = make_float4(fbits(lpi), fbits((uint32_t)i), 0.0f, 0.0f);
           q.SH1[e] = make_float4(fbits(kConnLight), 0.0f, 0.0f, fbits(j));
         }
@@ -2290,8 +2290,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
                                                            LightDev lt, Counters* cnt, IterDev it,
                                                            ImageDev img, int d) {
   if (group_overflowed(cnt)) return;
-  const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.cap);
-  const size_t L = (size_t)d * q.cap;
+  const uint32_t n = min(cnt->n_shadow[d], (uint32_t)q.scap);
+  const size_t L = (size_t)d * q.cap, Ls = (size_t)d * q.scap;
   uint32_t my_sh = 0, my_conn = 0;
   // Each tile of blockDim.x entries is ranked by the length of its weight
   // walk (NEE first, then connections by light vertex index) with a
@@ -2306,7 +2306,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       const uint32_t sr = base + threadIdx.x;
       uint32_t key = 0;
       if (sr < n) {
-        const size_t er = L + sr;
+        const size_t er = Ls + sr;
         if (ubits(q.SH1[er].x) != kConnNee) key = min(ubits(q.SH0[er].y), (uint32_t)kMaxDepth) + 1u;
       }
       if (threadIdx.x < kKeys) key_count[threadIdx.x] = 0u;
@@ -2328,7 +2328,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
     const uint32_t ntile = min(n - base, (uint32_t)blockDim.x);
     const uint32_t s = base + ((uint32_t)threadIdx.x < ntile ? (uint32_t)tile_order[threadIdx.x] : 0u);
     if ((uint32_t)threadIdx.x >= ntile) continue;
-    const size_t e = L + s;
+    const size_t e = Ls + s;
     const float4 s0 = q.SH0[e], s1 = q.SH1[e];
     const uint32_t kind = ubits(s1.x), j = ubits(s1.w);
     // the camera vertex
@@ -2457,7 +2457,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
   }
   __syncthreads();
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
-  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap;
+  const size_t L = (size_t)d * q.cap, Ln = (size_t)(d + 1) * q.cap, Ls = (size_t)d * q.scap;
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint32_t j0 = blockIdx.x * chunk, j1 = min(n, j0 + chunk);
   for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -2482,7 +2482,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         st[t][6] += 1.0; st[t][7] += (double)cst;
       };
       for (uint32_t k = 0; k < nnee; ++k) {
-        const f3 v = xyz(q.SH2[L + v2.x + k]);
+        const f3 v = xyz(q.SH2[Ls + v2.x + k]);
         R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
         cost += 1;
         record(1, v, 1u);
@@ -2518,7 +2518,7 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
           // subpath is traced once per camera sample whatever the counts
           uint32_t sc_ = 0;
           for (int i = lo; i <= hi; ++i, ++slot) {
-            const float4 r = q.SH2[L + slot];
+            const float4 r = q.SH2[Ls + slot];
             if (r.w != 0.0f) {
               sc_ += 1;
               v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);

@@ -89,7 +89,8 @@ struct QueuesDev {
   float4* SH0;  // shadow origin, tmax
   float4* SH1;  // shadow direction, parent vertex (bits)
   float4* SH2;  // unoccluded NEE sample value, flags (1 = traced)
-  size_t cap;   // entries per depth (rays and shadow rays each)
+  size_t cap;   // entries per depth level of the ray queues
+  size_t scap;  // entries per depth level of the shadow queues (SH0..SH2)
 };
 
 // queue counters of a tile (the first kTileWords words, reset per tile) and

@@ -203,10 +203,11 @@ def _floor(roots, e):
     return min(roots, (max(t, 4096) + 63) // 64 * 64)
 
 
-def _qbytes(scene, cap):
-    # 216 B per queue entry and level; BDPT adds the 32 B camera-vertex record
-    per = 216 + (32 if scene.mode == orc.MODE_BDPT else 0)
-    return cap * (scene.max_depth + 2) * per
+def _qbytes(scene, cap, scap):
+    # per level: 168 B per ray-queue entry (BDPT adds the 32 B camera-vertex
+    # record), 48 B per shadow-queue entry
+    per = 168 + (32 if scene.mode == orc.MODE_BDPT else 0)
+    return (scene.max_depth + 2) * (cap * per + scap * 48)
 
 
 def test_autotune_and_cache(ctx, tmp_path):
@@ -223,30 +224,32 @@ def test_autotune_and_cache(ctx, tmp_path):
     res = api.autotune(G, p0, mem_budget=4 << 30, cache_path=cache)
     lines = [ln for ln in open(cache).read().split("\n") if ln.strip()]
     assert len(lines) == len(G)
-    for g, r, (cap, tile, e) in zip(G, roots, res):
+    for g, r, (cap, tile, e, scap, es) in zip(G, roots, res):
         assert g.query()[:2] == (cap, tile)
-        assert e >= 1.0 and _floor(r, e) <= tile <= r and cap == _cap(tile, e)
+        assert g.query_queues()[:2] == (cap, scap)
+        assert e >= 1.0 and es >= 1.0 and _floor(r, max(e, es)) <= tile <= r
+        assert cap == _cap(tile, e) and scap == _cap(tile, es)
     # a budget that only fits the large scene at its smallest tile
-    es = [e for _, _, e in res]
-    fl = _floor(roots[-1], es[-1])
+    pk = [(e, es) for _, _, e, _, es in res]
+    fl = _floor(roots[-1], max(pk[-1]))
     assert fl < roots[-1]
-    need = _qbytes(G[-1], _cap(fl, es[-1])) + sum(
-        _qbytes(g, _cap(r, e)) for g, r, e in zip(G[:-1], roots[:-1], es[:-1]))
+    need = _qbytes(G[-1], _cap(fl, pk[-1][0]), _cap(fl, pk[-1][1])) + sum(
+        _qbytes(g, _cap(r, e), _cap(r, es)) for g, r, (e, es) in zip(G[:-1], roots[:-1], pk[:-1]))
     # probe again at whole-iteration tiles so the measured peaks repeat
-    for g, r, e in zip(G, roots, es):
-        g.configure(queue_capacity=_cap(r, e), tile_roots=r)
+    for g, r, (e, es) in zip(G, roots, pk):
+        g.configure(queue_capacity=_cap(r, e), tile_roots=r, shadow_capacity=_cap(r, es))
     say("autotune, tight budget", need)
     res_t = api.autotune(G, p0, mem_budget=need + (1 << 20))
     assert res_t[-1][1] == fl
-    assert sum(_qbytes(g, c) for g, (c, _, _) in zip(G, res_t)) <= need + (1 << 20)
+    assert sum(_qbytes(g, c, sc_) for g, (c, _, _, sc_, _) in zip(G, res_t)) <= need + (1 << 20)
     with pytest.raises(api.MarsError) as err:
         api.autotune(G, p0, mem_budget=1 << 20)
     assert err.value.code == -2
     # cached classes are applied without probing
     res2 = api.autotune(E, p0, mem_budget=4 << 30, cache_path=cache)
-    assert [(c, t) for c, t, _ in res2] == [(c, t) for c, t, _ in res]
-    for g, (c, t, _) in zip(G, res):
-        g.configure(queue_capacity=c, tile_roots=t)
+    assert [(c, t, sc_) for c, t, _, sc_, _ in res2] == [(c, t, sc_) for c, t, _, sc_, _ in res]
+    for g, (c, t, _, sc_, _) in zip(G, res):
+        g.configure(queue_capacity=c, tile_roots=t, shadow_capacity=sc_)
     # tuned batches still equal their eager twins
     for it in range(1, 4):
         say("tuned batch iteration", it)

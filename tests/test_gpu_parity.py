@@ -333,6 +333,35 @@ def test_overflow_rerun_gives_identical_results(ctx):
     assert retries > 0 and b.query()[1] < 512
 
 
+def test_shadow_queue_overflow_rerun_gives_identical_results(ctx):
+    """Ray queues roomy, shadow queues (NEE samples and connections) small:
+    the shadow queues overflow, the tile halves and the bidirectional
+    results equal those of roomy queues bit for bit."""
+    api = _api()
+    sc = scenegen.make_interior(seed=3, n_pieces=12, tess=1, width=32, height=24)
+    a = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=6)
+    b = api.Scene(ctx, sc, mode=api.MODE_BDPT, max_depth=6)
+    b.configure(queue_capacity=1 << 16, tile_roots=768, shadow_capacity=2048)
+    assert b.query_queues()[:2] == (1 << 16, 2048)
+    retries = 0
+    for it in range(3):
+        say("shadow overflow iteration", it)
+        p = api.iter_params(iteration=it, spp=2, stat_clamp=0.0,
+                            alloc=api.ALLOC_CLASSIC if it == 0 else api.ALLOC_MARS)
+        sa = a.render_iteration(p)
+        sb = b.render_iteration(p)
+        retries += sb.overflow_retries
+        assert sa.total_rays() == sb.total_rays()
+        assert np.array_equal(a.sample_radiance().view(np.uint32), b.sample_radiance().view(np.uint32))
+        a.update(p)
+        b.update(p)
+        assert np.array_equal(a.nodes(), b.nodes())
+    assert retries > 0 and b.query()[1] < 768
+    # the peaks per camera sample of the two queues
+    _, _, pr, ps = b.query_queues()
+    assert ps > pr > 0.0
+
+
 def test_single_tree_overflow_is_reported(ctx):
     api = _api()
     sc = scenegen.make_cornell(8, 8)
