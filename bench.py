@@ -285,6 +285,11 @@ def run_lp_lengths(args, api, torch):
             "bdpt": b}
 
 
+# queue memory of the bidirectional workload (of the 288 GB of HBM): half
+# the frame's camera samples per tile
+BDPT_QUEUE_GIB = 160
+
+
 def run_bdpt(args, api, torch):
     """Bidirectional workload: 1280x720 interior, 1,040,714 triangles, max
     path length 12.  One step = one MARS iteration at 1 spp (render + update)
@@ -307,7 +312,7 @@ def run_bdpt(args, api, torch):
     # queue and tile sizes from the autotuner on a MARS iteration (connections
     # multiply the shadow queues), then one untimed iteration at those sizes
     tuned = api.autotune([s], api.iter_params(iteration=warm, spp=1, alloc=api.ALLOC_MARS,
-                                              stat_clamp=0.0), mem_budget=96 << 30)
+                                              stat_clamp=0.0), mem_budget=BDPT_QUEUE_GIB << 30)
     torch.cuda.empty_cache()
     step(warm)
     warm += 1

@@ -618,26 +618,53 @@ __device__ __forceinline__ float sum_partials(const float* __restrict__ partial,
 
 // Adam (binary32): the gradient is the sum of the workgroup partials in
 // workgroup order
-__global__ void mlp_adam_kernel(MlpDev m, int nblocks, const float* ext_grad, float lr, float bc1,
-                                float bc2, float* loss_out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && loss_out) {
-    float l = 0.0f;
-    for (int b = 0; b < nblocks; ++b) l += m.partial[(size_t)b * (kMlpParams + 1) + kMlpParams];
-    *loss_out = l;
+// Adam over the summed workgroup partials: a workgroup of kAdamWaves waves
+// takes 64 parameters (index kMlpParams: the loss), wave w summing the
+// partials of workgroups w, w + kAdamWaves, ... and the waves' sums then
+// added in wave order, so that the gradient does not depend on scheduling
+constexpr int kAdamWaves = 8;
+__global__ __launch_bounds__(64 * kAdamWaves) void mlp_adam_kernel(MlpDev m, int nblocks,
+                                                                  const float* ext_grad, float lr,
+                                                                  float bc1, float bc2,
+                                                                  float* loss_out) {
+  __shared__ float part[kAdamWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  float g = 0.0f;
+  if (p <= kMlpParams && (!ext_grad || p == kMlpParams)) {
+    const float* __restrict__ src = m.partial + p;
+    constexpr size_t kRow = (size_t)kMlpParams + 1;
+    int b = w;
+    for (; b + 7 * kAdamWaves < nblocks; b += 8 * kAdamWaves) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(b + u * kAdamWaves) * kRow];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) g += v[u];
+    }
+    for (; b < nblocks; b += kAdamWaves) g += src[(size_t)b * kRow];
   }
-  if (p >= kMlpParams) return;
-  const float g = ext_grad ? ext_grad[p] : sum_partials(m.partial, nblocks, p);
+  part[w][lane] = g;
+  __syncthreads();
+  if (w != 0 || p > kMlpParams) return;
+  float gs = part[0][lane];
+#pragma unroll
+  for (int k = 1; k < kAdamWaves; ++k) gs += part[k][lane];
+  if (p == kMlpParams) {
+    if (loss_out) *loss_out = gs;
+    return;
+  }
+  if (ext_grad) gs = ext_grad[p];
   const float b1 = 0.9f, b2 = 0.99f, c1 = (float)(1.0 - 0.9), c2 = (float)(1.0 - 0.99);
-  const float mm = b1 * m.m[p] + c1 * g;
-  const float vv = b2 * m.v[p] + c2 * g * g;
+  const float mm = b1 * m.m[p] + c1 * gs;
+  const float vv = b2 * m.v[p] + c2 * gs * gs;
   m.m[p] = mm;
   m.v[p] = vv;
   const float mh = mm / bc1, vh = vv / bc2;
-  const float w = m.master[p] - (lr * mh) / (sqrtf(vh) + 1e-8f);
-  m.master[p] = w;
+  const float wn = m.master[p] - (lr * mh) / (sqrtf(vh) + 1e-8f);
+  m.master[p] = wn;
   const int qi = qindex(p);
-  if (qi >= 0) m.wq[qi] = to_bf16(w);
+  if (qi >= 0) m.wq[qi] = to_bf16(wn);
 }
 
 // gradient only (tests): the partials summed in workgroup order
@@ -659,10 +686,9 @@ void k_mlp_train_pass(const MlpDev& m, const float* x6, const float* tgt, const 
 }
 void k_mlp_adam(const MlpDev& m, int nblocks, const float* ext_grad, float lr, float bc1, float bc2,
                 float* loss_out, hipStream_t s) {
-  // one parameter per thread, 64-thread workgroups: 228 of them spread the
-  // partial sums over the whole chip
-  mlp_adam_kernel<<<(kMlpParams + 63) / 64, 64, 0, s>>>(m, nblocks, ext_grad, lr, bc1, bc2,
-                                                        loss_out);
+  // 64 parameters (and the loss) per workgroup: 228 of them
+  mlp_adam_kernel<<<(kMlpParams + 1 + 63) / 64, 64 * kAdamWaves, 0, s>>>(m, nblocks, ext_grad, lr,
+                                                                         bc1, bc2, loss_out);
 }
 void k_mlp_sum_partials(const MlpDev& m, int nblocks, float* grad, float* loss, hipStream_t s) {
   mlp_sum_partials_kernel<<<(kMlpParams + 64) / 64, 64, 0, s>>>(m, nblocks, grad, loss);
