@@ -2481,22 +2481,41 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         st[t][3] += x0 * x0; st[t][4] += x1 * x1; st[t][5] += x2 * x2;
         st[t][6] += 1.0; st[t][7] += (double)cst;
       };
-      for (uint32_t k = 0; k < nnee; ++k) {
-        const f3 v = xyz(q.SH2[Ls + v2.x + k]);
-        R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
-        cost += 1;
-        record(1, v, 1u);
+      // loads issued four at a time, the sums taken in sample order
+      for (uint32_t k0 = 0; k0 < nnee; k0 += 4) {
+        float4 r4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          r4[u] = k0 + u < nnee ? q.SH2[Ls + v2.x + k0 + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (k0 + u >= nnee) break;
+          const f3 v = xyz(r4[u]);
+          R = mk3(R.x + v.x / b.y, R.y + v.y / b.y, R.z + v.z / b.y);
+          cost += 1;
+          record(1, v, 1u);
+        }
       }
-      for (uint32_t k = 0; k < v2.w; ++k) {
-        // the sample's value and cost, left by the launch of the next depth
-        const size_t e = Ln + v2.z + k;
-        const float4 sv = q.RO[e];
-        const float bt = q.S2[e].w;
-        const f3 v = xyz(sv);
-        const uint32_t sc_ = ubits(sv.w);
-        R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
-        cost += sc_;
-        record(0, v, sc_);
+      for (uint32_t k0 = 0; k0 < v2.w; k0 += 2) {
+        // the samples' values and costs, left by the launch of the next depth
+        float4 sv2[2];
+        float bt2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const size_t e = Ln + v2.z + k0 + u;
+          sv2[u] = k0 + u < v2.w ? q.RO[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          bt2[u] = k0 + u < v2.w ? q.S2[e].w : 1.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (k0 + u >= v2.w) break;
+          const f3 v = xyz(sv2[u]);
+          const float bt = bt2[u];
+          const uint32_t sc_ = ubits(sv2[u].w);
+          R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
+          cost += sc_;
+          record(0, v, sc_);
+        }
       }
       uint32_t slot = v2.x + nnee;
       const int imax0 = sc.max_depth - d - 1;
@@ -2517,13 +2536,22 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
           // an LP sample costs its connection rays (at least 1): the light
           // subpath is traced once per camera sample whatever the counts
           uint32_t sc_ = 0;
-          for (int i = lo; i <= hi; ++i, ++slot) {
-            const float4 r = q.SH2[Ls + slot];
-            if (r.w != 0.0f) {
-              sc_ += 1;
-              v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
+          for (int i0 = lo; i0 <= hi; i0 += 4) {
+            float4 r4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              r4[u] = i0 + u <= hi ? q.SH2[Ls + slot + (uint32_t)(i0 - lo + u)]
+                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const float4 r = r4[u];
+              if (i0 + u <= hi && r.w != 0.0f) {
+                sc_ += 1;
+                v = mk3(v.x + r.x, v.y + r.y, v.z + r.z);
+              }
             }
           }
+          slot += (uint32_t)max(0, hi - lo + 1);
           sc_ = max(sc_, 1u);
           R = mk3(R.x + v.x / bt, R.y + v.y / bt, R.z + v.z / bt);
           cost += sc_;
