@@ -573,6 +573,7 @@ def run_learned(args, api, torch):
     prof = ctx.profile_read()
     ctx.profile(False)
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    qq = s.query_queues()
     window = {"workload": LEARNED_WORKLOAD, "warmup": n_warm, "steps": args.steps}
     paths = args.steps * sc["width"] * sc["height"] * LEARNED_SPP
     out = {
@@ -587,7 +588,8 @@ def run_learned(args, api, torch):
                    "spp_per_step": LEARNED_SPP, "techniques": ["bsdf", "nee", "light_path"],
                    "network": "6 inputs, 72 sin/cos features, 3 x 64 ReLU, 3 log counts",
                    "train_steps_per_update": LEARNED_TRAIN_STEPS, "max_cells": cells_budget(),
-                   "warmup_iterations": n_warm},
+                   "warmup_iterations": n_warm, "queue_capacity": qq[0],
+                   "shadow_queue_capacity": qq[1], "tile_roots": s.query()[1]},
         "mrays_per_s": rays / dt / 1e6,
         "trace_launches_timed": prof["trace"][1],
     }
