@@ -211,8 +211,10 @@ mars_status mars_iterate_batch(mars_ctx* ctx, const int32_t* scene_ids, int32_t 
  * mars_scene_configure_queues: ray_capacity and shadow_capacity entries per
  * level, camera samples per wavefront tile (<= ray_capacity); 0 keeps a
  * value.  Queue memory is about (max_depth + 2) x (168 B x ray_capacity +
- * 48 B x shadow_capacity), plus per ray entry 32 B for BDPT, 32 B more with
- * per-length light-path budgets and 16 B with the learned cache.
+ * 16 B x shadow_capacity) + 32 B x shadow_capacity (the shadow rays hold one
+ * level, reused by every depth; their values stay per level), plus per ray
+ * entry and level 32 B for BDPT, 32 B more with per-length light-path
+ * budgets and 16 B with the learned cache.
  * mars_scene_configure: both capacities queue_capacity. */
 mars_status mars_scene_configure_queues(mars_ctx* ctx, int32_t scene_id, int64_t ray_capacity,
                                         int64_t shadow_capacity, int32_t tile_roots);

@@ -356,8 +356,11 @@ void alloc_queues(Scene* s, size_t cap, size_t scap) {
   q.H = salloc<uint2>(s, lv);
   q.V0 = salloc<float4>(s, lv); q.V1 = salloc<float4>(s, lv);
   q.V2 = salloc<uint4>(s, lv); q.RO = salloc<float4>(s, lv);
+  // shadow rays (SH0, SH1) live from the vertex kernel of their depth to the
+  // traversal of that depth: one level serves every depth; the values (SH2)
+  // stay until back-propagation
   const size_t lvs = (size_t)(s->max_depth + 2) * scap;
-  q.SH0 = salloc<float4>(s, lvs); q.SH1 = salloc<float4>(s, lvs); q.SH2 = salloc<float4>(s, lvs);
+  q.SH0 = salloc<float4>(s, scap); q.SH1 = salloc<float4>(s, scap); q.SH2 = salloc<float4>(s, lvs);
   if (s->mode == MARS_MODE_BDPT) {
     q.W0 = salloc<float4>(s, lv);
     q.W1 = salloc<float4>(s, lv);
@@ -374,8 +377,9 @@ void alloc_queues(Scene* s, size_t cap, size_t scap) {
   s->epoch++;
 }
 
-// bytes of queue memory per entry of one level: ray queues, shadow queues
-constexpr size_t kRayEntryBytes = 10 * 16 + 8, kShadowEntryBytes = 3 * 16;
+// bytes of queue memory per entry: ray queues (per level), shadow values (per
+// level) and shadow rays (one level for all depths)
+constexpr size_t kRayEntryBytes = 10 * 16 + 8, kShadowValueBytes = 16, kShadowRayBytes = 32;
 
 // BDPT: one light subpath per camera sample of the iteration, before any
 // camera tile (connections may use any sample's subpath)
@@ -1214,9 +1218,10 @@ size_t min_tile(size_t roots, double e) {
 
 size_t queue_bytes(const Scene* s, size_t cap, size_t scap) {
   return (size_t)(s->max_depth + 2) *
-         (cap * (kRayEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0) +
-                 (s->sd.lp_classes == 3 ? 32 : 0)) +
-          scap * kShadowEntryBytes);
+             (cap * (kRayEntryBytes + (s->mlp_on ? 16 : 0) + (s->mode == MARS_MODE_BDPT ? 32 : 0) +
+                     (s->sd.lp_classes == 3 ? 32 : 0)) +
+              scap * kShadowValueBytes) +
+         scap * kShadowRayBytes;
 }
 
 std::string scene_class(const Scene* s, const mars_iter_params* p) {

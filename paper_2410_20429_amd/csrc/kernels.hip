@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_pair_kernel(SceneDev sc, Qu
       const uint32_t k = j - nc;
       const float4 v = q.SH2[Ls + k];
       if (v.w == 0.0f) continue;
-      const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
+      const float4 a = q.SH0[k], b = q.SH1[k];
       if (kCount) ++sr;
       const uint32_t sn0 = sn;
       if (traverse<true, kCount>(sc, xyz(a), xyz(b), a.w, stk, &t, &p, &sn, &st))
@@ -702,8 +702,8 @@ __device__ __forceinline__ void trace_stream(const SceneDev& sc, const QueuesDev
       }
       if (j >= n) break;
       if (kAny) {
-        a = q.SH0[L + j];
-        b = q.SH1[L + j];
+        a = q.SH0[j];
+        b = q.SH1[j];
         tmax = a.w;
       } else {
         b = q.R1[L + j];
@@ -797,7 +797,7 @@ __device__ __forceinline__ void trace_rays(const SceneDev& sc, const QueuesDev& 
       const uint32_t k = j - nc;
       const float4 v = q.SH2[Ls + k];
       if (v.w == 0.0f) continue;
-      const float4 a = q.SH0[Ls + k], b = q.SH1[Ls + k];
+      const float4 a = q.SH0[k], b = q.SH1[k];
       if (kSplit > 0) {
         if (lead) *sh = 0u;
         wave_lds_fence();
@@ -1256,10 +1256,10 @@ __global__ __launch_bounds__(kShadePtBlock) __attribute__((amdgpu_waves_per_eu(6
                           (fc.z / pN) * (wN * Le[2]), 1.0f);
         ++my_sh;
       }
-      const size_t e = (size_t)d * q.scap + sv.sfirst[v] + k;
+      const size_t e = sv.sfirst[v] + k;
       q.SH0[e] = make_float4(vo.x, vo.y, vo.z, dist * (1.0f - 1e-3f));
       q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(sv.j[v]));
-      q.SH2[e] = sh2;
+      q.SH2[(size_t)d * q.scap + e] = sh2;
     }
     // continuation: BSDF samples (slots 0..) then guided samples (after the
     // vertex's BSDF samples)
@@ -2227,7 +2227,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
       const float a = su * (1.0f - u.z), b = su * u.z;
       const f3 y = mk3((v0.x + a * e1.x) + b * e2.x, (v0.y + a * e1.y) + b * e2.y,
                        (v0.z + a * e1.z) + b * e2.z);
-      const size_t e = (size_t)d * q.scap + sfirst + k;
+      const size_t e = sfirst + k;
       q.SH0[e] = make_float4(y.x, y.y, y.z, fbits((uint32_t)li));
       q.SH1[e] = make_float4(fbits(kConnNee), 0.0f, 0.0f, fbits(j));
     }
@@ -2271,7 +2271,7 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
         int lo, hi;
         lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
         for (int i = lo; i <= hi; ++i, ++slot) {
-          const size_t e = (size_t)d * q.scap + slot;
+          const size_t e = slot;
           q.SH0[e] = make_float4(fbits(lpi), fbits((uint32_t)i), 0.0f, 0.0f);
           q.SH1[e] = make_float4(fbits(kConnLight), 0.0f, 0.0f, fbits(j));
         }
@@ -2306,8 +2306,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       const uint32_t sr = base + threadIdx.x;
       uint32_t key = 0;
       if (sr < n) {
-        const size_t er = Ls + sr;
-        if (ubits(q.SH1[er].x) != kConnNee) key = min(ubits(q.SH0[er].y), (uint32_t)kMaxDepth) + 1u;
+        if (ubits(q.SH1[sr].x) != kConnNee) key = min(ubits(q.SH0[sr].y), (uint32_t)kMaxDepth) + 1u;
       }
       if (threadIdx.x < kKeys) key_count[threadIdx.x] = 0u;
       __syncthreads();
@@ -2328,8 +2327,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
     const uint32_t ntile = min(n - base, (uint32_t)blockDim.x);
     const uint32_t s = base + ((uint32_t)threadIdx.x < ntile ? (uint32_t)tile_order[threadIdx.x] : 0u);
     if ((uint32_t)threadIdx.x >= ntile) continue;
-    const size_t e = Ls + s;
-    const float4 s0 = q.SH0[e], s1 = q.SH1[e];
+    const size_t e = Ls + s;  // SH2; SH0 and SH1 hold one level, at s
+    const float4 s0 = q.SH0[s], s1 = q.SH1[s];
     const uint32_t kind = ubits(s1.x), j = ubits(s1.w);
     // the camera vertex
     const uint2 h = q.H[L + j];
@@ -2370,8 +2369,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
       float pB;
       eval_bsdf(mat, n_s, wo, w, &fc, &pB);
       float4 sh2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      q.SH0[e] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
-      q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+      q.SH0[s] = make_float4(ov.x, ov.y, ov.z, dist * (1.0f - 1e-3f));
+      q.SH1[s] = make_float4(w.x, w.y, w.z, fbits(j));
       if (cl > 0.0f && (fc.x > 0.0f || fc.y > 0.0f || fc.z > 0.0f)) {
         const float pN = (lng.w * d2) / cl;
         const f3 fp = mk3(fc.x / pN, fc.y / pN, fc.z / pN);
@@ -2406,8 +2405,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
         const f3 yo = mk3(yP.x + ny.x * sc.eps, yP.y + ny.y * sc.eps, yP.z + ny.z * sc.eps);
         float sd2;
         const f3 sw = dir_between(ov, yo, &sd2);
-        q.SH0[e] = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
-        q.SH1[e] = make_float4(sw.x, sw.y, sw.z, fbits(j));
+        q.SH0[s] = make_float4(ov.x, ov.y, ov.z, sqrtf(sd2) * (1.0f - 1e-3f));
+        q.SH1[s] = make_float4(sw.x, sw.y, sw.z, fbits(j));
         const f3 al = mk3(y1v.w, y2v.x, y2v.y);
         const f3 cv = mk3(((al.x * fcL.x) * fcC.x) / d2, ((al.y * fcL.y) * fcC.y) / d2,
                           ((al.z * fcL.z) * fcC.z) / d2);
@@ -2416,8 +2415,8 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
         sh2 = make_float4(wc * cv.x, wc * cv.y, wc * cv.z, 1.0f);
         ++my_conn;
       } else {
-        q.SH0[e] = make_float4(ov.x, ov.y, ov.z, 0.0f);
-        q.SH1[e] = make_float4(w.x, w.y, w.z, fbits(j));
+        q.SH0[s] = make_float4(ov.x, ov.y, ov.z, 0.0f);
+        q.SH1[s] = make_float4(w.x, w.y, w.z, fbits(j));
       }
       q.SH2[e] = sh2;
     }

@@ -86,9 +86,9 @@ struct QueuesDev {
   // -, -); V3 = (beta of those classes, their rounded counts (bits))
   float4* W2;
   float4* V3;
-  float4* SH0;  // shadow origin, tmax
-  float4* SH1;  // shadow direction, parent vertex (bits)
-  float4* SH2;  // unoccluded NEE sample value, flags (1 = traced)
+  float4* SH0;  // shadow origin, tmax (one level of scap entries, reused by every depth)
+  float4* SH1;  // shadow direction, parent vertex (bits) (one level, as SH0)
+  float4* SH2;  // unoccluded sample value, flags (1 = traced); one level per depth
   size_t cap;   // entries per depth level of the ray queues
   size_t scap;  // entries per depth level of the shadow queues (SH0..SH2)
 };

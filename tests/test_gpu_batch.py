@@ -205,9 +205,9 @@ def _floor(roots, e):
 
 def _qbytes(scene, cap, scap):
     # per level: 168 B per ray-queue entry (BDPT adds the 32 B camera-vertex
-    # record), 48 B per shadow-queue entry
+    # record), 16 B per shadow value; the 32 B shadow rays hold one level
     per = 168 + (32 if scene.mode == orc.MODE_BDPT else 0)
-    return (scene.max_depth + 2) * (cap * per + scap * 48)
+    return (scene.max_depth + 2) * (cap * per + scap * 16) + scap * 32
 
 
 def test_autotune_and_cache(ctx, tmp_path):
