@@ -146,15 +146,20 @@ def reference_image(api, ctx, sc, spp=16, iters=256, seed_iter=100000, mode=None
     return acc / iters
 
 
+# queue memory of each method's scene in the efficiency protocols
+EFFICIENCY_QUEUE_GIB = 96
+
+
 def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(16, 256),
                    ears=False, unaware=False, lp_lengths=False):
     """Efficiency 1/(relMSE * seconds) of MARS and of classic RR, as in the
     paper's evaluation: n_iter iterations of 1, 2, 4, ... spp, the first
     three with classic RR, then MARS (render + update each); the MARS image
     is the inverse-variance weighted combination of all iterations; classic
-    RR renders the same sample counts (mean image).  relMSE against a
-    classic reference of ref_spp[0] x ref_spp[1] spp, 0.01% brightest
-    outliers discarded.  With ears, EARS (one shared count per vertex, the
+    RR renders the same sample counts (mean image).  Each method's queue and
+    tile sizes come from the autotuner before its 4th iteration (outside the
+    timed region).  relMSE against a classic reference of ref_spp[0] x
+    ref_spp[1] spp, 0.01% brightest outliers discarded.  With ears, EARS (one shared count per vertex, the
     paper's comparison method) runs the same schedule as MARS; with unaware,
     so does MARS with the budget-unaware balance heuristic; with lp_lengths,
     MARS with separate light-path budgets per light-vertex index (y_1, y_2,
@@ -175,6 +180,16 @@ def efficiency_leg(api, ctx, sc, torch, n_iter=9, mode=None, depth=10, ref_spp=(
             alloc = api.ALLOC_CLASSIC if i < 3 else alloc_after
             p = api.iter_params(iteration=i, spp=1 << i, alloc=alloc, stat_clamp=kc,
                                 budget_aware=aware)
+            if i == 3:
+                # queue and tile sizes for this method's own queue peaks (a
+                # MARS iteration draws many more connections than a classic
+                # one), outside the timed region
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                api.autotune([s], p, mem_budget=EFFICIENCY_QUEUE_GIB << 30)
+                torch.cuda.empty_cache()
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t_pause
             rays += s.render_iteration(p).total_rays()
             if alloc_after != api.ALLOC_CLASSIC:
                 s.update(p)
@@ -387,7 +402,7 @@ def time_to_relmse(curve, target):
     return None
 
 
-def learned_efficiency(api, ctx, sc, torch, seeds=(1, 2, 3), n_iter=11, ref_half_spp=512):
+def learned_efficiency(api, ctx, sc, torch, seeds=(1, 2, 3, 4, 5), n_iter=11, ref_half_spp=512):
     """Octree MARS and learned-cache MARS over the growing-iteration schedule
     (spp_i = min(2^max(0, i - 3), 16): 3 classic-RR iterations, octree MARS
     from the 4th, the network's counts from the 6th; the network trains 32
@@ -397,7 +412,7 @@ def learned_efficiency(api, ctx, sc, torch, seeds=(1, 2, 3), n_iter=11, ref_half
     BDPT with its own noise removed.  Efficiency at equal relMSE: the target
     is the larger of the two methods' final relMSE, each method's time to
     reach it is interpolated on its curve, and efficiency = 1 / (target x
-    time).  Three random-stream seeds; the value is the geometric mean of
+    time).  Five random-stream seeds; the value is the geometric mean of
     the per-seed ratios."""
     import math
 
@@ -757,6 +772,14 @@ def cells_budget(mbytes=72.0):
 BATCH_WORKLOAD = "batch32_mixed_guided_bdpt"
 
 
+def queue_bytes(scene, cap, scap):
+    """The library's queue memory model: per level 168 B per ray-queue entry
+    (+32 B for BDPT) and 16 B per shadow value, the 32 B shadow rays in one
+    level (no learned cache or per-length budgets in the batch)."""
+    per = 168 + (32 if scene.mode == 2 else 0)
+    return (scene.max_depth + 2) * (cap * per + scap * 16) + scap * 32
+
+
 def run_batch(args, api, torch, seed=1, budget=64 << 30):
     """The batched workload: 32 independent scenes (resolution uniform over
     64^2 .. 1024^2, 1k-500k triangles log-uniform, half guided PT and half
@@ -860,7 +883,7 @@ def run_batch(args, api, torch, seed=1, budget=64 << 30):
                    "triangles": tris, "spp_per_step": 1, "clamp_hi": 8.0,
                    "guided": sum(sc["mode"] == "guided" for sc in scenes),
                    "bdpt": sum(sc["mode"] == "bdpt" for sc in scenes),
-                   "queue_bytes": sum(c * (s.max_depth + 2) * 216 for s, (c, _, _) in zip(S, tuned))},
+                   "queue_bytes": sum(queue_bytes(s, c, sc_) for s, (c, _, _, sc_, _) in zip(S, tuned))},
         "eager_ms_per_step": dt_eager * 1e3 / args.steps,
         "stream_pool_ms_per_step": dt_pool * 1e3 / args.steps,
         "graph_speedup_vs_eager": dt_eager / dt,
