@@ -1362,7 +1362,7 @@ void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Count
 // table slot.  A workgroup walks a contiguous range of the queue, so
 // neighbouring vertices (often in the same cell) share slots; keys that find
 // no slot within a few probes go straight to global memory.
-constexpr int kAggSlots = 128;
+constexpr int kAggSlots = 256;
 constexpr int kAggVals = 9;  // sum v (3), sum v^2 (3), n, cost, visits
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
 
@@ -1384,7 +1384,7 @@ __device__ __forceinline__ void global_add_stats(const CacheDev& c, uint32_t key
 
 __device__ __forceinline__ void agg_add(AggTable& A, const CacheDev& c, uint32_t key,
                                         const double* v) {
-  uint32_t h = (key * 2654435761u) >> 25;  // 7 bits
+  uint32_t h = (key * 2654435761u) >> 24;  // 8 bits
 #pragma unroll 1
   for (int probe = 0; probe < 8; ++probe) {
     const uint32_t prev = atomicCAS(&A.key[h], kAggEmpty, key);
