@@ -191,6 +191,33 @@ def test_batch_overflow_reruns_scene(ctx):
     assert G[0].query()[1] == 1024 and E[0].query()[1] < 1024
 
 
+def test_batch_full_size_equals_eager(ctx):
+    """A batch at full configuration sizes (the 512x512 guided heightfield
+    of 132k triangles, depth 10, and the 1280x720 bidirectional interior of
+    1.04M triangles, depth 12) equals its per-scene twins bit for bit over a
+    classic and two MARS iterations, through the captured graphs."""
+    api = _api()
+    hf = scenegen.make_heightfield_scene(seed=1)
+    hf["mode"], hf["max_depth"] = "guided", 10
+    it_ = scenegen.make_interior(seed=1)
+    it_["mode"], it_["max_depth"] = "bdpt", 12
+    G, E, _ = _twins(ctx, [hf, it_], with_oracle=False)
+    for x in (G[1], E[1]):
+        x.configure(queue_capacity=4 << 20, tile_roots=230400, shadow_capacity=64 << 20)
+    for it in range(3):
+        say("full-size batch iteration", it)
+        p = api.iter_params(iteration=it, spp=1, stat_clamp=0.0,
+                            alloc=api.ALLOC_CLASSIC if it == 0 else api.ALLOC_MARS)
+        its, _ = api.iterate_batch(G, p, update=True)
+        for k, (g, e) in enumerate(zip(G, E)):
+            se = e.render_iteration(p)
+            e.update(p)
+            assert its[k].total_rays() == se.total_rays(), k
+            _cmp_twins(g, e)
+    for s_ in G + E:
+        s_.release()
+
+
 def _cap(tile, e):
     """Queue capacity the autotuner derives from a tile and the measured peak."""
     c = int(np.ceil(tile * max(1.0, e) * 1.25))
