@@ -2071,13 +2071,22 @@ __device__ float bdpt_weight_lp(const SceneDev& sc, const CacheDev& c, const Que
 // path: subpath index and light vertex index in SH0.xy
 constexpr uint32_t kConnNee = 1u, kConnLight = 2u;
 
-// light subpath of LP sample j of a camera vertex: pool entry (b + j stride)
-// mod npool, b the first word of the vertex's own random stream, so that the
-// vertices of one path tree connect to unrelated light subpaths
-__device__ __forceinline__ uint32_t lp_index(uint32_t b, uint32_t j, int32_t stride,
-                                             uint32_t npool) {
-  return (uint32_t)(((unsigned long long)b + (unsigned long long)j * (uint32_t)stride) % npool);
-}
+// the light subpaths of the LP samples j = 0, 1, .. of a camera vertex, in
+// turn: pool entry (b + j stride) mod npool, b the first word of the
+// vertex's own random stream, so that the vertices of one path tree connect
+// to unrelated light subpaths; walked by steps of stride mod npool (the same
+// integers, without a 64-bit remainder per sample)
+struct LpWalk {
+  uint32_t idx, step, n;
+  __device__ __forceinline__ LpWalk(uint32_t b, int32_t stride, uint32_t npool)
+      : idx(b % npool), step((uint32_t)stride % npool), n(npool) {}
+  __device__ __forceinline__ uint32_t next() {
+    const uint32_t r = idx;
+    const uint32_t t = idx + step;  // < 2 npool
+    idx = t >= n ? t - n : t;
+    return r;
+  }
+};
 
 // light vertices y_lo..y_hi a light-path sample of class cls connects to,
 // of the imax its subpath offers within the path-length limit: every one
@@ -2161,8 +2170,9 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
           mlp_record(c, strm, x, pix, ng, T);
           const int imax0 = sc.max_depth - d - 1;
           for (int cls = 0; cls < sc.lp_classes; ++cls) {
+            LpWalk lw(strm.x, it.lp_stride, npool);
             for (uint32_t k = 0; k < gam[cls == 0 ? 2 : 2 + cls]; ++k) {
-              const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
+              const uint32_t lpi = lw.next();
               int lo, hi;
               lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
               nconn += (uint32_t)max(0, hi - lo + 1);
@@ -2266,8 +2276,9 @@ __global__ __launch_bounds__(kShadeBlock) void shade_bdpt_kernel(SceneDev sc, Ca
     uint32_t slot = sfirst + gam[1];
     const int imax0 = sc.max_depth - d - 1;
     for (int cls = 0; cls < sc.lp_classes; ++cls) {
+      LpWalk lw(strm.x, it.lp_stride, npool);
       for (uint32_t k = 0; k < gam[cls == 0 ? 2 : 2 + cls]; ++k) {
-        const uint32_t lpi = lp_index(strm.x, k, it.lp_stride, npool);
+        const uint32_t lpi = lw.next();
         int lo, hi;
         lp_class_range(sc, cls, max(0, min(imax0, (int)lt.len[lpi].x)), &lo, &hi);
         for (int i = lo; i <= hi; ++i, ++slot) {
@@ -2526,8 +2537,9 @@ __global__ __launch_bounds__(256) void backprop_bdpt_kernel(SceneDev sc, CacheDe
         const float bt = cls == 0 ? b.z : (cls == 1 ? v3.x : v3.y);
         const uint32_t g = cls == 0 ? glp : ubits(cls == 1 ? v3.z : v3.w);
         double sx[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        LpWalk lw(q.S3[L + j].x, it.lp_stride, npool);
         for (uint32_t k = 0; k < g; ++k) {
-          const uint32_t lpi = lp_index(q.S3[L + j].x, k, it.lp_stride, npool);
+          const uint32_t lpi = lw.next();
           const uint2 ll = lt.len[lpi];
           int lo, hi;
           lp_class_range(sc, cls, max(0, min(imax0, (int)ll.x)), &lo, &hi);
