@@ -577,10 +577,11 @@ def run_learned(args, api, torch):
     ctx.profile(True, kernels=["trace"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rays = rays_closest = rays_shadow = 0
+    rays = rays_closest = rays_shadow = retries = 0
     for k in range(args.steps):
         st, _ = step(n_warm + k)
         rays += st.total_rays()
+        retries += st.overflow_retries
         rays_closest += st.rays_camera + st.rays_ext + st.rays_light
         rays_shadow += st.rays_shadow + st.rays_conn
     torch.cuda.synchronize()
@@ -604,7 +605,8 @@ def run_learned(args, api, torch):
                    "network": "6 inputs, 72 sin/cos features, 3 x 64 ReLU, 3 log counts",
                    "train_steps_per_update": LEARNED_TRAIN_STEPS, "max_cells": cells_budget(),
                    "warmup_iterations": n_warm, "queue_capacity": qq[0],
-                   "shadow_queue_capacity": qq[1], "tile_roots": s.query()[1]},
+                   "shadow_queue_capacity": qq[1], "tile_roots": s.query()[1],
+                   "overflow_reruns_timed": retries},
         "mrays_per_s": rays / dt / 1e6,
         "trace_launches_timed": prof["trace"][1],
     }

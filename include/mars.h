@@ -240,7 +240,8 @@ mars_status mars_scene_query_queues(mars_ctx* ctx, int32_t scene_id, int64_t* ra
  * tile x e_s x 1.25, rounded up to 4096; largest scenes halved first, no
  * tile below min(all samples, max(4096, 2^18 / max(e, e_s))) rounded up to
  * 64); then up to three tile sizes (plan, plan/2, plan/4, same floor) are
- * timed with one render iteration each and the fastest kept.  cache_path
+ * timed (the better of two render iterations each) and the fastest kept, a
+ * smaller tile only when at least 3% faster than the best larger one.  cache_path
  * (optional): a text file of lines
  * "<class> <capacity> <shadow capacity> <tile> <e> <e_s> <ms>" keyed by the
  * scene class (resolution, spp, mode, depth, triangles, allocation mode);
