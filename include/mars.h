@@ -236,8 +236,8 @@ mars_status mars_scene_query_queues(mars_ctx* ctx, int32_t scene_id, int64_t* ra
  * then hold the probe's) measures the peak occupancy per camera sample of
  * the ray queues e and of the shadow queues e_s (each at least 1); tiles of
  * up to all camera samples are planned under mem_budget bytes of queue
- * memory for the n scenes together (capacities tile x e x 1.25 and
- * tile x e_s x 1.25, rounded up to 4096; largest scenes halved first, no
+ * memory for the n scenes together (capacities tile x e x 1.5 and
+ * tile x e_s x 1.5, rounded up to 4096; largest scenes halved first, no
  * tile below min(all samples, max(4096, 2^18 / max(e, e_s))) rounded up to
  * 64); then up to three tile sizes (plan, plan/2, plan/4, same floor) are
  * timed (the better of two render iterations each) and the fastest kept, a

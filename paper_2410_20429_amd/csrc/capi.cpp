@@ -1200,8 +1200,10 @@ void batch_iterate(Ctx* c, const int32_t* ids, int n, const mars_iter_params* p,
 // ---------------------------------------------------------------------------
 // queue / tile autotuner
 // ---------------------------------------------------------------------------
+// the probe's peak per camera sample with half again as much room: later
+// iterations' peaks move with the counts, and an overflow re-runs a tile
 size_t tuned_capacity(size_t tile, double e) {
-  const double want = std::ceil((double)tile * std::max(1.0, e) * 1.25);
+  const double want = std::ceil((double)tile * std::max(1.0, e) * 1.5);
   size_t cap = (size_t)want;
   cap = (cap + 4095) / 4096 * 4096;
   return std::min<size_t>(std::max<size_t>(cap, 4096), 0xFFFF0000ull);

@@ -220,7 +220,7 @@ def test_batch_full_size_equals_eager(ctx):
 
 def _cap(tile, e):
     """Queue capacity the autotuner derives from a tile and the measured peak."""
-    c = int(np.ceil(tile * max(1.0, e) * 1.25))
+    c = int(np.ceil(tile * max(1.0, e) * 1.5))
     return min(max((c + 4095) // 4096 * 4096, 4096), 0xFFFF0000)
 
 
