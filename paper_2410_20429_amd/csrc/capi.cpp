@@ -437,7 +437,7 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
     timed(c, KID_SHADE, [&] {
       if (bdpt)
         k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, npool,
-                     grid, st);
+                     st);
       else
         k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, s->dbg, s->dbg_cap, d, grid, st);
     });
@@ -454,9 +454,9 @@ bool run_tile(Scene* s, const IterDev& it, uint32_t root0, uint32_t n, uint32_t 
   for (int d = s->max_depth; d >= 1; --d)
     timed(c, KID_BACKPROP, [&] {
       if (bdpt)
-        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, npool, grid, st);
+        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, npool, st);
       else
-        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
+        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, st);
     });
   if (last) timed(c, KID_PIXEL_SUMS, [&] { k_pixel_sums(s->img, s->W * s->H, spp, st); });
   Counters* pc = (Counters*)c->pinned;
@@ -972,7 +972,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
     for (int d = 1; d <= s->max_depth; ++d) {
       if (bdpt) {
         k_shade_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, nullptr, 0, d, (uint32_t)roots,
-                     grid, st);
+                     st);
         k_connect_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, st);
       } else {
         k_shade_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, nullptr, 0, d, grid, st);
@@ -981,9 +981,9 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
     }
     for (int d = s->max_depth; d >= 1; --d) {
       if (bdpt)
-        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, (uint32_t)roots, grid, st);
+        k_backprop_bdpt(s->sd, s->cd, s->qd, s->lt, s->cnt, it, s->img, d, (uint32_t)roots, st);
       else
-        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, grid, st);
+        k_backprop_pt(s->sd, s->cd, s->qd, s->cnt, it, s->img, d, st);
     }
   }
   k_pixel_sums(s->img, s->W * s->H, spp, st);

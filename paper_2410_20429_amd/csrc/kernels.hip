@@ -1523,8 +1523,7 @@ __global__ __launch_bounds__(256) void backprop_pt_kernel(SceneDev sc, CacheDev 
   }
 }
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
-                   const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s) {
-  (void)grid;
+                   const IterDev& it, const ImageDev& img, int d, hipStream_t s) {
   backprop_pt_kernel<<<resident_grid(backprop_pt_kernel, 256), 256, 0, s>>>(sc, c, q, cnt, it, img, d);
 }
 
@@ -1972,8 +1971,8 @@ __device__ float bdpt_weight_hit(const SceneDev& sc, const QueuesDev& q, const I
 // weight of the light-path connection of camera vertex j (depth d: zc, its
 // parent zp, the camera for d = 1) to the light vertex y_i (yi) of subpath
 // r, strategy t = d + 1 of the path z_0..z_k, k = d + i + 1, whose light side
-// z_{d+1}..z_k is y_i, .., y_1, y_0.  The same sums as bdpt_weight_rec in the
-// same order; the terms that involve light vertices only are read from the
+// z_{d+1}..z_k is y_i, .., y_1, y_0.  The sums above, in the order they
+// state; the terms that involve light vertices only are read from the
 // light walk (V2.w, V3) instead of evaluated.  ly: in learned-cache
 // iterations, the network outputs at the subpath's vertices (y_h at
 // ly[4 (h - 1)]).
@@ -2079,7 +2078,7 @@ constexpr uint32_t kConnNee = 1u, kConnLight = 2u;
 struct LpWalk {
   uint32_t idx, step, n;
   __device__ __forceinline__ LpWalk(uint32_t b, int32_t stride, uint32_t npool)
-      : idx(b % npool), step((uint32_t)stride % npool), n(npool) {}
+      : idx(npool ? b % npool : 0u), step(npool ? (uint32_t)stride % npool : 0u), n(npool) {}
   __device__ __forceinline__ uint32_t next() {
     const uint32_t r = idx;
     const uint32_t t = idx + step;  // < 2 npool
@@ -2438,8 +2437,7 @@ __global__ __launch_bounds__(kConnectBlock) void connect_bdpt_kernel(SceneDev sc
 
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
-                  uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s) {
-  (void)grid;
+                  uint32_t dbg_cap, int d, uint32_t npool, hipStream_t s) {
   shade_bdpt_kernel<<<resident_grid(shade_bdpt_kernel, kShadeBlock), kShadeBlock, 0, s>>>(
       sc, c, q, lt, cnt, it, img, dbg, dbg_cap, d, npool);
 }
@@ -2631,8 +2629,7 @@ void k_init_launch_grids() {
 
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
-                     const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s) {
-  (void)grid;
+                     const ImageDev& img, int d, uint32_t npool, hipStream_t s) {
   if (sc.lp_classes == 3)
     backprop_bdpt_kernel<true><<<resident_grid(backprop_bdpt_kernel<true>, 256), 256, 0, s>>>(
         sc, c, q, lt, cnt, it, img, d, npool);

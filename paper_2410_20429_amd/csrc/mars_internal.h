@@ -212,7 +212,7 @@ void k_shade_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, Count
                 const IterDev& it, const ImageDev& img, DebugRec* dbg, uint32_t dbg_cap, int d,
                 int grid, hipStream_t s);
 void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const Counters* cnt,
-                   const IterDev& it, const ImageDev& img, int d, int grid, hipStream_t s);
+                   const IterDev& it, const ImageDev& img, int d, hipStream_t s);
 void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
                    const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s);
 void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
@@ -223,14 +223,14 @@ void k_init_launch_grids();
 void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStream_t s);
 void k_shade_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                   Counters* cnt, const IterDev& it, const ImageDev& img, DebugRec* dbg,
-                  uint32_t dbg_cap, int d, uint32_t npool, int grid, hipStream_t s);
+                  uint32_t dbg_cap, int d, uint32_t npool, hipStream_t s);
 // the NEE samples' and light-path connections' weights and contributions of
 // the camera vertices of depth d (after k_shade_bdpt)
 void k_connect_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
                     Counters* cnt, const IterDev& it, const ImageDev& img, int d, hipStream_t s);
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,
                      const LightDev& lt, const Counters* cnt, const IterDev& it,
-                     const ImageDev& img, int d, uint32_t npool, int grid, hipStream_t s);
+                     const ImageDev& img, int d, uint32_t npool, hipStream_t s);
 void k_mlp_targets(const SceneDev& sc, const CacheDev& c, const MlpDev& m, const ImageDev& img,
                    const IterDev& it, uint32_t n, const uint32_t* skip, hipStream_t s);
 // ---- launchers (mlp.hip) ----
