@@ -578,8 +578,10 @@ def run_learned(args, api, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rays = rays_closest = rays_shadow = retries = 0
+    t_steps = []  # host time at the end of each step (each step ends with host waits)
     for k in range(args.steps):
         st, _ = step(n_warm + k)
+        t_steps.append(time.perf_counter())
         rays += st.total_rays()
         retries += st.overflow_retries
         rays_closest += st.rays_camera + st.rays_ext + st.rays_light
@@ -609,6 +611,7 @@ def run_learned(args, api, torch):
                    "overflow_reruns_timed": retries},
         "mrays_per_s": rays / dt / 1e6,
         "trace_launches_timed": prof["trace"][1],
+        "step_ms": [round((b - a) * 1e3, 2) for a, b in zip([t0] + t_steps[:-1], t_steps)],
     }
     if args.profile_steps >= 0:
         print(json.dumps(out), flush=True)
