@@ -20,7 +20,11 @@ def _gather(o, params_list):
 
 
 def _zscore(x, expected):
-    return (x.mean() - expected) / (x.std() / math.sqrt(len(x)))
+    se = x.std() / math.sqrt(len(x))
+    if se == 0.0:
+        # noiseless estimates (one segment): exact or infinitely far
+        return 0.0 if abs(x.mean() - expected) < 1e-5 else math.inf
+    return (x.mean() - expected) / se
 
 
 # ---------------------------------------------------------------------------
