@@ -115,7 +115,8 @@ def roofline(api, ctx, prof, step_counted, rays_closest, rays_shadow, traffic_na
         out["measured_hbm_gbs"] = traffic / (avg_ms * 1e-3) / 1e9
         out["measured_hbm_frac"] = out["measured_hbm_gbs"] / HBM_PEAK_GBS
         out["traffic_source"] = "profiles/" + traffic_name
-        for k in ("occupancy_waves_per_simd", "vgprs", "scratch_bytes"):
+        for k in ("occupancy_waves_per_simd", "occupancy_waves_per_simd_time_weighted", "vgprs",
+                  "scratch_bytes"):
             if k in t:
                 out[k] = t[k]
     return out

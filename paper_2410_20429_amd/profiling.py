@@ -106,7 +106,24 @@ def traffic(fetch_csv, write_csv, kernel, last_n=None, window=None, occupancy_cs
         occ = _occupancy(occupancy_csv, kernel, last_n)
         if occ is not None:
             out["occupancy_waves_per_simd"] = occ
+        occ_t = _occupancy_time_weighted(occupancy_csv, kernel, last_n)
+        if occ_t is not None:
+            out["occupancy_waves_per_simd_time_weighted"] = occ_t
     return out
+
+
+def _occupancy_time_weighted(path, kernel, last_n):
+    """MeanOccupancyPerCU / 4 over the last `last_n` dispatches, each weighted
+    by its duration in the counter run (the plain mean weighs the short
+    launches of the deep bounces as much as the long ones)"""
+    rows = [r for r in csv.DictReader(open(path))
+            if r.get("Counter_Name") == "MeanOccupancyPerCU" and short_name(r["Kernel_Name"]) == kernel]
+    rows.sort(key=_order)
+    rows = rows[-last_n:] if last_n else rows
+    w = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+    if not rows or sum(w) <= 0:
+        return None
+    return sum(float(r["Counter_Value"]) * d for r, d in zip(rows, w)) / sum(w) / 4.0
 
 
 def _occupancy(path, kernel, last_n, simds=4 * 256):
