@@ -1010,11 +1010,19 @@ __device__ __forceinline__ void mlp_counts(const CacheDev& c, const IterDev& it,
   mlp_apply(it, T, It, c.mlp_y + e * 4, beta);
 }
 
-// training vertices for the learned cache: a seeded random subset
+// training vertices for the learned cache: a seeded random subset.  The
+// wave's recording lanes take their slots with one atomic: the first adds
+// their number, each lane counts the recording lanes below it.
 __device__ __forceinline__ void mlp_record(const CacheDev& c, uint2 strm, f3 x, uint32_t pix, f3 n,
                                            f3 T) {
   if (!c.mlp_rec || (strm.x >> 8) >= c.mlp_keep) return;
-  const uint32_t k = atomicAdd(c.mlp_n_rec, 1u);
+  const uint64_t m = __ballot(1);
+  const uint32_t first = (uint32_t)__builtin_ctzll(m);
+  uint32_t base = 0u;
+  if (__lane_id() == first) base = atomicAdd(c.mlp_n_rec, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)first);
+  const uint32_t k =
+      base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   if (k >= c.mlp_rec_cap) return;
   c.mlp_rec[3 * (size_t)k] = make_float4(x.x, x.y, x.z, __uint_as_float(pix));
   c.mlp_rec[3 * (size_t)k + 1] = make_float4(n.x, n.y, n.z, 0.0f);

@@ -3,11 +3,13 @@
 // octree's cube and its geometric normal as stored (sin/cos encoding with 6
 // frequencies -> 72 features, padded to 80; three hidden layers of 64 ReLU
 // units; 3 linear outputs).  Forward and backward
-// run as bfloat16 matrix-core products with binary32 accumulation
-// (v_mfma_f32_16x16x16_bf16), one 16-sample tile per wave.  Master weights,
-// biases and Adam moments are binary32.
+// run as bfloat16 matrix-core products with binary32 accumulation, one
+// 16-sample tile per wave: training on v_mfma_f32_16x16x16_bf16, inference
+// on gfx950's v_mfma_f32_16x16x32_bf16 (half the products per tile).  Master
+// weights, biases and Adam moments are binary32.
 //
-// MFMA 16x16x16 operand layout (lane l = 0..63, element r = 0..3):
+// MFMA 16x16x16 operand layout (lane l = 0..63, element r = 0..3; the
+// inference's 16x16x32 form is described with its kernels):
 //   A (16 x 16, M x K): A[l % 16][4 (l / 16) + r]
 //   B (16 x 16, K x N): B[4 (l / 16) + r][l % 16]
 //   D (16 x 16, M x N): D[4 (l / 16) + r][l % 16]
@@ -146,47 +148,72 @@ __device__ __forceinline__ v4f mlp_forward_tile(const float* __restrict__ master
 
 // ---------------------------------------------------------------------------
 // Inference.  Every layer is computed transposed, Z^T = W H^T, with the
-// weights as the A operand and the activations as the B operand: the output
-// tile D[neuron 16 nt + 4 (l / 16) + r][sample l % 16] of output block nt is
-// then, after bias, ReLU and rounding, exactly the B operand of block
-// ks = nt of the next layer, so activations stay in registers.  (The same
+// weights as the A operand and the activations as the B operand, on gfx950's
+// 16x16x32 bfloat16 matrix-core product (v_mfma_f32_16x16x32_bf16): lane l
+// holds elements e = 0..7 of row l % 16 of A and of column l % 16 of B in
+// the K positions of its lane group l / 16, the same positions for A and B.
+// Which of the 32 products a position stands for is the caller's choice as
+// long as A and B agree: here element e of lane group g in chunk c stands for
+// input 16 (2c + e / 4) + 4g + e % 4.  The output tile D[neuron 16 nt +
+// 4 (l / 16) + r][sample l % 16] of output block nt is, after bias, ReLU and
+// rounding, elements 4 (nt % 2) .. 4 (nt % 2) + 3 of the B operand of chunk
+// nt / 2 of the next layer, so activations stay in registers.  (The same
 // products as mlp_forward_tile; only the order of each binary32 matrix-core
 // accumulation may differ.)
 //
 // The weights are staged in LDS in fragment order: the A operand of every
-// (layer, output block, k block) as 64 consecutive 8-byte lane fragments,
-// so that each operand is one conflict-free 512-byte read.  Blocks: layer 1
-// 5 nt + ks (nt < 4, ks < 5), layer 2 20 + 4 nt + ks, layer 3
-// 36 + 4 nt + ks, output layer 52 + ks (one output block); 28 KB in all.
-constexpr int kFragBlocks = 56;
+// (layer, output block, chunk) as 64 consecutive 16-byte lane fragments,
+// so that each operand is one conflict-free 1 KB read.  Blocks: layer 1
+// 3 nt + c (nt < 4, c < 3; inputs 80 .. 95 are zero), layer 2 12 + 2 nt + c,
+// layer 3 20 + 2 nt + c, output layer 28 + c (one output block); 30 KB.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v4f mma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ v8s cat8(v4s lo, v4s hi) {
+  return v8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+constexpr int kFragBlocks = 30;
 constexpr int kInferWaves = 8;            // waves per inference workgroup
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 
-// (by the kInferWaves * 64 threads of a workgroup, each loading all of its
-// fragments before it writes any)
-__device__ __forceinline__ int fragment_source(int f) {
-  const int blk = f >> 6, ln = f & 63, lr = ln & 15, lg = ln >> 4;
-  int base, stride, nt, ks;
-  if (blk < 20) {
-    base = qW1; stride = 80; nt = blk / 5; ks = blk % 5;
-  } else if (blk < 52) {
-    const int b = (blk - 20) & 15;
-    base = blk < 36 ? qW2 : qW3; stride = 64; nt = b >> 2; ks = b & 3;
-  } else {
-    base = qW4; stride = 64; nt = 0; ks = blk - 52;
-  }
-  return base + (16 * nt + lr) * stride + 16 * ks + 4 * lg;
-}
+// Stages the fragments: fragment f (block f / 64, lane f % 64) is two runs of
+// four consecutive weights, inputs 16 (2c) + 4g .. + 3 and 16 (2c + 1) + 4g
+// .. + 3 of output row 16 nt + l % 16 (a run past input 79 of layer 1 is
+// zero).  Every thread loads all of its fragments before it writes any.
 template <int kThreads>
-__device__ __forceinline__ void stage_fragments(const uint16_t* __restrict__ wq, uint2* wf) {
-  static_assert(kFragBlocks * 64 % kThreads == 0, "whole fragments per thread");
-  constexpr int kPer = kFragBlocks * 64 / kThreads;
-  uint2 v[kPer];
+__device__ __forceinline__ void stage_fragments(const uint16_t* __restrict__ wq, uint4* wf) {
+  constexpr int kN = kFragBlocks * 64, kPer = (kN + kThreads - 1) / kThreads;
+  uint4 v[kPer];
 #pragma unroll
-  for (int j = 0; j < kPer; ++j)
-    v[j] = *reinterpret_cast<const uint2*>(wq + fragment_source(threadIdx.x + j * kThreads));
+  for (int j = 0; j < kPer; ++j) {
+    const int f = threadIdx.x + j * kThreads;
+    v[j] = make_uint4(0u, 0u, 0u, 0u);
+    if (f < kN) {
+      const int blk = f >> 6, ln = f & 63, lr = ln & 15, lg = ln >> 4;
+      int base, stride, nt, c, nin;
+      if (blk < 12) {
+        base = qW1; stride = 80; nin = 80; nt = blk / 3; c = blk % 3;
+      } else if (blk < 28) {
+        const int b = (blk - 12) & 7;
+        base = blk < 20 ? qW2 : qW3; stride = 64; nin = 64; nt = b >> 1; c = b & 1;
+      } else {
+        base = qW4; stride = 64; nin = 64; nt = 0; c = blk - 28;
+      }
+      const int row = base + (16 * nt + lr) * stride, k0 = 32 * c + 4 * lg, k1 = k0 + 16;
+      const uint2 lo = *reinterpret_cast<const uint2*>(wq + row + k0);
+      const uint2 hi = k1 < nin ? *reinterpret_cast<const uint2*>(wq + row + k1) : make_uint2(0u, 0u);
+      v[j] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    }
+  }
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) wf[threadIdx.x + j * kThreads] = v[j];
+  for (int j = 0; j < kPer; ++j) {
+    const int f = threadIdx.x + j * kThreads;
+    if (f < kN) wf[f] = v[j];
+  }
 }
 
 // the biases b1, b2, b3 (64 each) and b4 (16) as 52 float4 in LDS
@@ -197,12 +224,12 @@ __device__ __forceinline__ void stage_biases(const float* __restrict__ master, f
                    : master[kMlpB4 + (k - 192)];
 }
 
-__device__ __forceinline__ v4s frag(const uint2* wf, int blk, int lane) {
-  return __builtin_bit_cast(v4s, wf[blk * 64 + lane]);
+__device__ __forceinline__ v8s frag(const uint4* wf, int blk, int lane) {
+  return __builtin_bit_cast(v8s, wf[blk * 64 + lane]);
 }
 
-// bias, ReLU and bfloat16 rounding of one output block: the next layer's B
-// operand (neurons 16 nt + 4 (l / 16) + r of sample l % 16)
+// bias, ReLU and bfloat16 rounding of one output block (neurons 16 nt +
+// 4 (l / 16) + r of sample l % 16): half of the next layer's B operand
 __device__ __forceinline__ v4s relu_bf16(const v4f& z, float4 b) {
   uint16_t h[4];
   to_bf16x2(fmaxf(z[0] + b.x, 0.0f), fmaxf(z[1] + b.y, 0.0f), &h[0], &h[1]);
@@ -210,35 +237,38 @@ __device__ __forceinline__ v4s relu_bf16(const v4f& z, float4 b) {
   return v4s{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
 }
 
+// features k0 .. k0 + 3 of a sample, k0 a multiple of 4: the sine and cosine
+// of one angle 2^kk pi x_d (kk even) and of its double, the latter from the
+// double-angle identities (zero past feature 71)
+__device__ __forceinline__ v4s feature_quad(const float* x, int k0) {
+  float fs, fc, gs, gc;
+  feature_pair(x, k0, &fs, &fc);
+  if (k0 < 72) {
+    gs = 2.0f * (fs * fc);
+    gc = (fc - fs) * (fc + fs);
+  } else {
+    gs = 0.0f;
+    gc = 0.0f;
+  }
+  uint16_t h[4];
+  to_bf16x2(fs, fc, &h[0], &h[1]);
+  to_bf16x2(gs, gc, &h[2], &h[3]);
+  return v4s{(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+}
+
 // One 16-sample tile by one wave.  x: the inputs of sample l % 16 (the same
 // in the four lanes that hold it).  Returns D[output 4 (l / 16) + r][sample
 // l % 16]: the lanes l < 16 hold outputs 0..3 of sample l.
-__device__ __forceinline__ v4f mlp_infer_tile(const uint2* wf, const float4* bl, const float* x) {
+__device__ __forceinline__ v4f mlp_infer_tile(const uint4* wf, const float4* bl, const float* x) {
   const int lane = threadIdx.x & 63, lg = lane >> 4;
   v4f acc[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int ks = 0; ks < 5; ++ks) {
-    // features k0 .. k0 + 3 of the sample, k0 = 16 ks + 4 lg: the sine and
-    // cosine of one angle 2^kk pi x_d (kk even) and of its double, the
-    // latter from the double-angle identities
-    const int k0 = 16 * ks + 4 * lg;
-    float fs, fc, gs, gc;
-    feature_pair(x, k0, &fs, &fc);
-    if (k0 < 72) {
-      gs = 2.0f * (fs * fc);
-      gc = (fc - fs) * (fc + fs);
-    } else {
-      gs = 0.0f;
-      gc = 0.0f;
-    }
-    uint16_t h[4];
-    to_bf16x2(fs, fc, &h[0], &h[1]);
-    to_bf16x2(gs, gc, &h[2], &h[3]);
-    const v4s b = {(short)h[0], (short)h[1], (short)h[2], (short)h[3]};
+  for (int c = 0; c < 3; ++c) {
+    const v8s b = cat8(feature_quad(x, 32 * c + 4 * lg), feature_quad(x, 32 * c + 16 + 4 * lg));
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = mma(frag(wf, 5 * nt + ks, lane), b, acc[nt]);
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = mma32(frag(wf, 3 * nt + c, lane), b, acc[nt]);
   }
   v4s hb[4];
 #pragma unroll
@@ -248,16 +278,18 @@ __device__ __forceinline__ v4f mlp_infer_tile(const uint2* wf, const float4* bl,
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+    for (int c = 0; c < 2; ++c) {
+      const v8s b = cat8(hb[2 * c], hb[2 * c + 1]);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
-        acc[nt] = mma(frag(wf, 20 + 16 * l + 4 * nt + ks, lane), hb[ks], acc[nt]);
+        acc[nt] = mma32(frag(wf, 12 + 8 * l + 2 * nt + c, lane), b, acc[nt]);
+    }
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) hb[nt] = relu_bf16(acc[nt], bl[32 + 4 * nt + lg]);
   v4f y = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) y = mma(frag(wf, 52 + ks, lane), hb[ks], y);
+  for (int c = 0; c < 2; ++c) y = mma32(frag(wf, 28 + c, lane), cat8(hb[2 * c], hb[2 * c + 1]), y);
   const float4 b4 = bl[48 + lg];
   y[0] += b4.x;
   y[1] += b4.y;
@@ -277,7 +309,7 @@ __device__ __forceinline__ v4f mlp_infer_tile(const uint2* wf, const float4* bl,
 __device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Inference kernels: the fragments and biases are staged once per
-// workgroup; each of its kInferWaves waves then runs 16-sample tiles (29 KB
+// workgroup; each of its kInferWaves waves then runs 16-sample tiles (31 KB
 // of LDS per workgroup).  Every global access of a tile is issued a whole
 // tile's computation before it is needed: the records two tiles ahead, the
 // normals one tile ahead, and the outputs are stored one tile late.  (Vector
@@ -287,7 +319,7 @@ __device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcn
 // inference over a list of vertices given as (q, n)
 __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_inputs_kernel(MlpDev m, const float* x6,
                                                                             int n, float* y3) {
-  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ uint4 wf[kFragBlocks * 64];
   __shared__ float4 bl[52];
   stage_fragments<64 * kInferWaves>(m.wq, wf);
   stage_biases(m.master, bl);
@@ -329,7 +361,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_queue_kernel(Scene
                                                                            QueuesDev q, MlpDev m,
                                                                            const Counters* cnt,
                                                                            int d) {
-  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ uint4 wf[kFragBlocks * 64];
   __shared__ float4 bl[52];
   if (cnt->overflow) return;
   const uint32_t n = min(cnt->n_ray[d], (uint32_t)q.cap);
@@ -401,7 +433,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void mlp_infer_light_kernel(Scene
                                                                            MlpDev m, LightDev lt,
                                                                            const Counters* cnt,
                                                                            int i) {
-  __shared__ uint2 wf[kFragBlocks * 64];
+  __shared__ uint4 wf[kFragBlocks * 64];
   __shared__ float4 bl[52];
   const uint32_t n = min(cnt->n_ray[0], (uint32_t)q.cap);
   if ((size_t)blockIdx.x * kInferWaves * 16 >= n) return;
