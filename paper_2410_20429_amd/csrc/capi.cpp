@@ -386,7 +386,7 @@ constexpr size_t kRayEntryBytes = 10 * 16 + 8, kShadowValueBytes = 16, kShadowRa
 uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
   hipStream_t st = s->ctx->stream;
   Ctx* c = s->ctx;
-  const int grid_trace = c->cu * kTraceBlocksPerCU, grid = c->cu * 8;
+  const int grid_trace = c->cu * kTraceBlocksPerCU;
   unsigned long long* tc = c->counting ? c->tcount : nullptr;
   k_fill_u32((uint32_t*)s->cnt, 0u, sizeof(Counters) / 4, st);
   for (size_t r0 = 0; r0 < roots; r0 += s->cap) {
@@ -403,7 +403,7 @@ uint64_t trace_light_paths(Scene* s, const IterDev& it, size_t roots) {
         timed(c, KID_MLP, [&] {
           k_mlp_infer_light(s->sd, s->qd, s->mlp, s->lt, s->cnt, i, c->cu * 32, st);
         });
-      timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st); });
+      timed(c, KID_LIGHT, [&] { k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, st); });
     }
   }
   timed(c, KID_LIGHT, [&] { k_light_walk(s->sd, s->lt, (uint32_t)roots, st); });
@@ -958,7 +958,7 @@ void enqueue_iteration(Scene* s, const IterDev& it, int spp, bool with_update, f
       k_light_start(s->sd, s->qd, s->lt, s->cnt, it, (uint32_t)r0, n, st);
       for (int i = 1; i <= s->lt.lmax; ++i) {
         k_trace_pair(s->sd, s->qd, s->cnt, 0, 0, grid_trace, st, tc);
-        k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, grid, st);
+        k_light_shade(s->sd, s->cd, s->qd, s->lt, s->cnt, it, i, st);
       }
     }
     k_light_walk(s->sd, s->lt, (uint32_t)roots, st);

@@ -1704,8 +1704,9 @@ __global__ void light_shade_kernel(SceneDev sc, const uint32_t* __restrict__ oct
   if ((threadIdx.x & 63) == 0 && sr) atomicAdd(&cnt->rays_light, (unsigned long long)sr);
 }
 void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
-                   Counters* cnt, const IterDev& it, int bounce, int grid, hipStream_t s) {
-  light_shade_kernel<<<grid, 256, 0, s>>>(sc, c.nodes, q, lt, cnt, it, bounce);
+                   Counters* cnt, const IterDev& it, int bounce, hipStream_t s) {
+  light_shade_kernel<<<resident_grid(light_shade_kernel, 256), 256, 0, s>>>(sc, c.nodes, q, lt, cnt,
+                                                                            it, bounce);
 }
 
 // ---------------------------------------------------------------------------
@@ -1829,51 +1830,58 @@ __device__ __forceinline__ float path_pR(const SceneDev& sc, int i, int k, const
 //         of reaching y_{i-1} (area density there).
 // Both are evaluated by the same operations as the weight's walk would,
 // so the weights do not change.
+// One thread per subpath, walking it from y_1 with a window of four
+// vertices (E = y_{i-2}, D = y_{i-1}, C = y_i, A = y_{i+1}), so that each
+// vertex is fetched and decoded once.
 __global__ __launch_bounds__(256) void light_walk_kernel(SceneDev sc, LightDev lt, uint32_t roots) {
   const uint32_t lm = (uint32_t)lt.lmax;
-  const uint32_t total = roots * lm;
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const uint32_t r = e / lm;
-    const int i = (int)(e - r * lm) + 1;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < roots; r += gridDim.x * blockDim.x) {
     const int len = (int)lt.len[r].x;
-    if (i > len) continue;
-    const PV C = light_vertex(sc, lt.V0[e]);
-    const PV D = light_vertex(sc, i >= 2 ? lt.V0[e - 1] : lt.Y0[r]);
-    float d2;
-    float pR;
-    if (i == 1) {
-      const f3 w = dir_between(D.P, C.P, &d2);
-      const float cl = dot3(D.ng, w);
-      const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
-      pR = (pe * fabsf(dot3(C.ng, w))) / d2;
-    } else {
-      const PV E = light_vertex(sc, i >= 3 ? lt.V0[e - 2] : lt.Y0[r]);
-      const f3 wo = dir_between(D.P, E.P, &d2);
-      const f3 wi = dir_between(D.P, C.P, &d2);
-      f3 fc;
-      float p;
-      eval_facing(load_mat(sc.mats + 8 * (size_t)D.mat), D.ng, wo, wi, &fc, &p);
-      pR = (p * fabsf(dot3(C.ng, wi))) / d2;
-    }
-    const float4 v2 = lt.V2[e];
-    lt.V2[e] = make_float4(v2.x, v2.y, v2.z, pR);
-    if (i < len) {
+    if (len < 1) continue;
+    const size_t b = (size_t)r * lm;  // y_i at b + i - 1
+    PV E{};
+    PV D = light_vertex(sc, lt.Y0[r]);
+    PV C = light_vertex(sc, lt.V0[b]);
+    for (int i = 1; i <= len; ++i) {
+      const size_t e = b + (size_t)(i - 1);
+      float d2;
+      float pR;
+      if (i == 1) {
+        const f3 w = dir_between(D.P, C.P, &d2);
+        const float cl = dot3(D.ng, w);
+        const float pe = cl > 0.0f ? cl * kInvPi : 0.0f;
+        pR = (pe * fabsf(dot3(C.ng, w))) / d2;
+      } else {
+        const f3 wo = dir_between(D.P, E.P, &d2);
+        const f3 wi = dir_between(D.P, C.P, &d2);
+        f3 fc;
+        float p;
+        eval_facing(load_mat(sc.mats + 8 * (size_t)D.mat), D.ng, wo, wi, &fc, &p);
+        pR = (p * fabsf(dot3(C.ng, wi))) / d2;
+      }
+      const float4 v2 = lt.V2[e];
+      lt.V2[e] = make_float4(v2.x, v2.y, v2.z, pR);
+      if (i == len) break;
       const PV A = light_vertex(sc, lt.V0[e + 1]);
-      const f3 wo = dir_between(C.P, A.P, &d2);
-      const f3 wi = dir_between(C.P, D.P, &d2);
-      f3 fc;
-      float p;
-      eval_facing(load_mat(sc.mats + 8 * (size_t)C.mat), C.ng, wo, wi, &fc, &p);
-      const float pF = (p * fabsf(dot3(D.ng, wi))) / d2;
-      lt.V3[e] = p > 0.0f ? make_float4(fc.x / p, fc.y / p, fc.z / p, pF)
-                          : make_float4(-1.0f, -1.0f, -1.0f, pF);
+      {
+        const f3 wo = dir_between(C.P, A.P, &d2);
+        const f3 wi = dir_between(C.P, D.P, &d2);
+        f3 fc;
+        float p;
+        eval_facing(load_mat(sc.mats + 8 * (size_t)C.mat), C.ng, wo, wi, &fc, &p);
+        const float pF = (p * fabsf(dot3(D.ng, wi))) / d2;
+        lt.V3[e] = p > 0.0f ? make_float4(fc.x / p, fc.y / p, fc.z / p, pF)
+                            : make_float4(-1.0f, -1.0f, -1.0f, pF);
+      }
+      E = D;
+      D = C;
+      C = A;
     }
   }
 }
 void k_light_walk(const SceneDev& sc, const LightDev& lt, uint32_t roots, hipStream_t s) {
-  const uint32_t total = roots * (uint32_t)lt.lmax;
-  if (!total) return;
-  light_walk_kernel<<<std::min<uint32_t>((total + 255) / 256, 8192), 256, 0, s>>>(sc, lt, roots);
+  if (!roots || lt.lmax < 1) return;
+  light_walk_kernel<<<(roots + 255) / 256, 256, 0, s>>>(sc, lt, roots);
 }
 
 // the strategies tt = d .. 2 of a path z_0..z_k through the camera vertex j
@@ -2633,6 +2641,7 @@ void k_init_launch_grids() {
   (void)resident_grid(backprop_bdpt_kernel<true>, 256);
   (void)resident_grid(backprop_bdpt_kernel<false>, 256);
   (void)resident_grid(backprop_pt_kernel, 256);
+  (void)resident_grid(light_shade_kernel, 256);
 }
 
 void k_backprop_bdpt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q,

@@ -216,7 +216,7 @@ void k_backprop_pt(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, co
 void k_light_start(const SceneDev& sc, const QueuesDev& q, const LightDev& lt, Counters* cnt,
                    const IterDev& it, uint32_t root0, uint32_t n, hipStream_t s);
 void k_light_shade(const SceneDev& sc, const CacheDev& c, const QueuesDev& q, const LightDev& lt,
-                   Counters* cnt, const IterDev& it, int bounce, int grid, hipStream_t s);
+                   Counters* cnt, const IterDev& it, int bounce, hipStream_t s);
 // resident-group grids of the kernels that loop over equal shares of their
 // work, for the current device (cached; launches query them otherwise)
 void k_init_launch_grids();
