@@ -34,6 +34,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2410_20429_amd import iterlog  # noqa: E402  (host-side JSON lines, no GPU)
+
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "guided_pt_512x512_heightfield132k_d10"
 BYTES_RAY_IO = 48.0      # ray 32 B in (origin, direction) + hit 16 B out
@@ -560,15 +562,21 @@ def run_learned(args, api, torch):
             return api.ALLOC_CLASSIC
         return api.ALLOC_MARS if i < LEARNED_FIRST else api.ALLOC_MLP
 
+    log = iterlog_open(args)
+
     def step(i):
         p = api.iter_params(iteration=i, spp=LEARNED_SPP, alloc=alloc_of(i), stat_clamp=0.0)
         if i == 3:
             api.autotune([s], p, mem_budget=96 << 30)
             torch.cuda.empty_cache()
+        t = time.perf_counter()
         st = s.render_iteration(p)
         us = s.update(p)
         if i >= 3:
             s.mlp_train(steps=LEARNED_TRAIN_STEPS, batch=8192, lr=2e-3)
+        if log:
+            log.write(iterlog.record(i, p, st, us, time.perf_counter() - t, sc["width"],
+                                     sc["height"], s.count_map()))
         return st, us
 
     for i in range(n_warm):
@@ -769,6 +777,13 @@ def run_rounding(args, api, torch, n_alloc=9, n_rep=24, seed=1):
             "per_scene": out, "paper_context": {"saving": 0.02}}
 
 
+def iterlog_open(args):
+    """The per-iteration JSON-lines log of --log-jsonl, or None.  Logging
+    reads the count map back after every step (a few ms at 1920x1080), so a
+    logged run's timing is not the benchmark's."""
+    return iterlog.IterationLog(args.log_jsonl) if args.log_jsonl else None
+
+
 def cells_budget(mbytes=72.0):
     # bytes per cell: factors 72, accumulators 192, visits/leaf data 12,
     # directional pmf+cdf 512, training sums 512, octree node words 32
@@ -956,11 +971,17 @@ def run_guided(args, api, torch):
     s = api.Scene(ctx, sc, mode=api.MODE_PT_GUIDED, max_depth=10, max_cells=cells_budget())
     n_classic = min(3, args.warmup)
 
+    log = iterlog_open(args)
+
     def step(i):
         alloc = api.ALLOC_CLASSIC if i < n_classic else api.ALLOC_MARS
         p = api.iter_params(iteration=i, spp=1, alloc=alloc, stat_clamp=50.0)
+        t = time.perf_counter()
         st = s.render_iteration(p)
         us = s.update(p)
+        if log:
+            log.write(iterlog.record(i, p, st, us, time.perf_counter() - t, sc["width"],
+                                     sc["height"], s.count_map()))
         return st, us
 
     for i in range(args.warmup):
@@ -1040,6 +1061,10 @@ def main():
                          "per-iteration counts and efficiency over several seeds; rounding: "
                          "low-discrepancy against independent rounding in renders")
     ap.add_argument("--no-efficiency", action="store_true")
+    ap.add_argument("--log-jsonl", default=None,
+                    help="(learned and guided workloads) append one JSON line per iteration "
+                         "(rays, Mrays/s, Mpaths/s, V_I, C_I, 1/(V_I C_I), mean first-hit "
+                         "counts) to this file")
     args = ap.parse_args()
     if args.warmup is None:
         args.warmup = 10 if args.workload == "learned" else 5

@@ -122,3 +122,30 @@ def test_committed_traffic_summaries_match_kernel_source(bench, name):
     assert t["hbm_bytes_per_launch"] == pytest.approx(
         t["hbm_fetch_bytes_per_launch"] + t["hbm_write_bytes_per_launch"])
     assert math.isfinite(t["occupancy_waves_per_simd_time_weighted"])
+
+
+def test_iteration_log_lines(tmp_path):
+    """One JSON object per iteration with the rays, rates, V_I, C_I, the
+    proxy 1/(V_I C_I) and the mean first-hit counts."""
+    from types import SimpleNamespace as NS
+
+    from paper_2410_20429_amd import iterlog
+    p = NS(spp=2, alloc=1)
+    st = NS(rays_camera=100, rays_ext=50, rays_shadow=30, rays_light=20, rays_conn=0, tiles=3,
+            overflow_retries=1)
+    us = NS(V_I=0.5, C_I=4.0)
+    cm = np.zeros((2, 5, 3), np.float32)
+    cm[..., 0], cm[..., 1], cm[..., 2] = 1.0, 2.0, 0.5
+    cm[0, 0, 0] = 11.0  # mean over 10 pixels: 2.0
+    path = tmp_path / "log.jsonl"
+    log = iterlog.IterationLog(path)
+    log.write(iterlog.record(7, p, st, us, 0.5, 5, 2, cm))
+    log.write(iterlog.record(8, p, st, NS(V_I=0.0, C_I=4.0), 0.5, 5, 2))
+    log.close()
+    a, b = [json.loads(x) for x in open(path).read().splitlines()]
+    assert a["iteration"] == 7 and a["rays"] == 200 and a["tiles"] == 3
+    assert a["mrays_per_s"] == pytest.approx(200 / 0.5 / 1e6)
+    assert a["mpaths_per_s"] == pytest.approx(5 * 2 * 2 / 0.5 / 1e6)
+    assert a["proxy_efficiency"] == pytest.approx(0.5)
+    assert a["mean_first_hit_counts"] == pytest.approx([2.0, 2.0, 0.5])
+    assert b["proxy_efficiency"] is None and "mean_first_hit_counts" not in b
